@@ -1,0 +1,241 @@
+"""FP64 CPU oracle for discounted CFR on hold'em public subgames.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library never loads it, and it imports nothing from the product package.
+
+The arithmetic lives in ``oracle.c`` (plain per-history CFR, written from the
+paper's definitions in Sec. 3 and the seven-stage description of Sec. 4);
+this module only loads the shared object and marshals arguments.
+
+Parity status of each function (what pins it) is recorded in the tests under
+``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+NCOMBO = 1326
+
+T_DEC, T_FOLD, T_SHOW, T_CHANCE, T_LEAF, T_ALLIN = range(6)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (OpenMP, -O2)."""
+    src = os.path.join(_HERE, "oracle.c")
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                           "-o", tmp, src, "-lm"])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        sig = {
+            "ora_eval5": (I, [P]),
+            "ora_eval7": (I, [P]),
+            "ora_category_counts": (None, [I, P]),
+            "ora_distinct5": (I, []),
+            "ora_eval7_batch": (None, [P, I64, P]),
+            "ora_build_tree": (P, [I, P, I64, I64, I64, I, P, I, I, I]),
+            "ora_build_kuhn": (P, []),
+            "ora_tree_free": (None, [P]),
+            "ora_tree_info": (None, [P, P]),
+            "ora_tree_export": (None, [P] * 10),
+            "ora_solver_create": (P, [P, P, D, D, D, I]),
+            "ora_solver_free": (None, [P]),
+            "ora_iterate": (None, [P, I, I]),
+            "ora_iteration": (I64, [P]),
+            "ora_get_strategy": (I, [P, I, I, P]),
+            "ora_get_rows": (None, [P, I, P]),
+            "ora_set_rows": (None, [P, P, P, I64]),
+            "ora_root_cfv_current": (None, [P, P]),
+            "ora_root_cfv_avg": (None, [P, P]),
+            "ora_pair_mass": (D, [P]),
+            "ora_exploitability": (D, [P, P]),
+            "ora_set_leaf_table": (None, [P, P]),
+            "ora_num_leaves": (I, [P]),
+            "ora_reach_current": (None, [P, P]),
+            "ora_equity_table": (I, [P, I, P]),
+            "ora_node_board": (I, [P, I, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def eval5(cards) -> int:
+    a = np.ascontiguousarray(cards, dtype=np.int32)
+    return int(lib().ora_eval5(_p(a)))
+
+
+def eval7(cards) -> int:
+    a = np.ascontiguousarray(cards, dtype=np.int32)
+    return int(lib().ora_eval7(_p(a)))
+
+
+def eval7_batch(cards: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(cards, dtype=np.int32).reshape(-1, 7)
+    out = np.empty(a.shape[0], dtype=np.int32)
+    lib().ora_eval7_batch(_p(a), a.shape[0], _p(out))
+    return out
+
+
+def category_counts(n: int) -> np.ndarray:
+    out = np.zeros(9, dtype=np.int64)
+    lib().ora_category_counts(n, _p(out))
+    return out
+
+
+def distinct5() -> int:
+    return int(lib().ora_distinct5())
+
+
+class Tree:
+    """A public tree built by the oracle's own builder (breadth-first ids)."""
+
+    def __init__(self, handle, kuhn=False):
+        self._h = handle
+        self.kuhn = kuhn
+        info = np.zeros(9, dtype=np.int64)
+        lib().ora_tree_info(self._h, _p(info))
+        (self.n_nodes, self.n_decision, self.n_fold, self.n_showdown, self.n_chance,
+         self.n_leaf, self.n_allin, self.n_levels, self.n_rows) = (int(x) for x in info)
+        self.nh = 3 if kuhn else NCOMBO
+
+    @classmethod
+    def holdem(cls, board, pot, stacks, sizes, allin=True, max_raises=2, depth_limit=0):
+        b = np.asarray(board, dtype=np.int32)
+        s = np.asarray(sizes, dtype=np.int32)
+        h = lib().ora_build_tree(len(b), _p(b), int(pot), int(stacks[0]), int(stacks[1]),
+                                 len(s), _p(s), int(allin), int(max_raises), int(depth_limit))
+        if not h:
+            raise ValueError("oracle rejected the tree spec")
+        t = cls(h)
+        t._keep = (b, s)
+        return t
+
+    @classmethod
+    def kuhn_poker(cls):
+        return cls(lib().ora_build_kuhn(), kuhn=True)
+
+    def export(self) -> dict:
+        n = self.n_nodes
+        out = {k: np.zeros(n, dtype=np.int32) for k in
+               ("type", "player", "parent", "action", "depth", "chance_card", "first_child", "n_child")}
+        out["contrib"] = np.zeros((n, 2), dtype=np.int64)
+        lib().ora_tree_export(self._h, _p(out["type"]), _p(out["player"]), _p(out["parent"]),
+                              _p(out["action"]), _p(out["depth"]), _p(out["contrib"]),
+                              _p(out["chance_card"]), _p(out["first_child"]), _p(out["n_child"]))
+        return out
+
+    def node_board(self, node: int) -> list:
+        b = np.zeros(5, dtype=np.int32)
+        nb = lib().ora_node_board(self._h, int(node), _p(b))
+        return [int(x) for x in b[:nb]]
+
+    def equity_table(self, node: int) -> np.ndarray:
+        out = np.zeros((self.nh, self.nh), dtype=np.float64)
+        if lib().ora_equity_table(self._h, int(node), _p(out)) != 0:
+            raise ValueError("node has no board table")
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().ora_tree_free(self._h)
+            self._h = None
+
+
+class Solver:
+    """Per-history DCFR with simultaneous updates, in FP64."""
+
+    def __init__(self, tree: Tree, ranges, alpha=1.5, beta=0.0, gamma=2.0, support_only=False):
+        self.tree = tree
+        r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, tree.nh)
+        self._r = r
+        self._h = lib().ora_solver_create(tree._h, _p(r), alpha, beta, gamma, int(support_only))
+
+    def iterate(self, n: int, threads: int = 0):
+        lib().ora_iterate(self._h, int(n), int(threads))
+
+    @property
+    def t(self) -> int:
+        return int(lib().ora_iteration(self._h))
+
+    def strategy(self, node: int, which: str = "avg") -> np.ndarray:
+        A = int(self.tree.export()["n_child"][node]) if not hasattr(self, "_nchild") else int(self._nchild[node])
+        out = np.zeros((A, self.tree.nh), dtype=np.float64)
+        if lib().ora_get_strategy(self._h, int(node), 0 if which == "avg" else 1, _p(out)) != 0:
+            raise ValueError("not a decision node")
+        return out
+
+    def cache_shape(self):
+        self._nchild = self.tree.export()["n_child"]
+        return self
+
+    def rows(self, which: str) -> np.ndarray:
+        out = np.zeros((self.tree.n_rows, self.tree.nh), dtype=np.float64)
+        lib().ora_get_rows(self._h, 0 if which == "R" else 1, _p(out))
+        return out
+
+    def set_rows(self, R, S, t):
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        lib().ora_set_rows(self._h, _p(R), _p(S), int(t))
+
+    def root_cfv(self, which: str = "current") -> np.ndarray:
+        out = np.zeros((2, self.tree.nh), dtype=np.float64)
+        if which == "current":
+            lib().ora_root_cfv_current(self._h, _p(out))
+        else:
+            lib().ora_root_cfv_avg(self._h, _p(out))
+        return out
+
+    def pair_mass(self) -> float:
+        return float(lib().ora_pair_mass(self._h))
+
+    def exploitability(self):
+        br = np.zeros(2, dtype=np.float64)
+        e = lib().ora_exploitability(self._h, _p(br))
+        return float(e), br
+
+    def num_leaves(self) -> int:
+        return int(lib().ora_num_leaves(self._h))
+
+    def set_leaf_table(self, ev: np.ndarray):
+        ev = np.ascontiguousarray(ev, dtype=np.float64)
+        assert ev.size == self.num_leaves() * 2 * 52 * self.tree.nh
+        self._ev = ev
+        lib().ora_set_leaf_table(self._h, _p(ev))
+
+    def reach_current(self) -> np.ndarray:
+        out = np.zeros((self.tree.n_nodes, 2, self.tree.nh), dtype=np.float64)
+        lib().ora_reach_current(self._h, _p(out))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().ora_solver_free(self._h)
+            self._h = None

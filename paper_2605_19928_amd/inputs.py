@@ -1,0 +1,112 @@
+"""Seeded synthetic inputs: boards, private-hand ranges, pots and stacks.
+
+This module holds no arithmetic of the solver.  It only draws random public
+boards and range vectors with numpy's ``default_rng`` so that the GPU library
+and the CPU oracle can be fed identical inputs.  Both sides import it; it
+imports neither.
+
+Conventions: card = 4*rank + suit (rank 0..12 = 2..A); a two-card combo
+{a > b} has index a(a-1)/2 + b in [0, 1326).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NCOMBO = 1326
+
+
+def combo_cards() -> np.ndarray:
+    """(1326, 2) array of (a, b) with a > b, row = combo index."""
+    out = np.zeros((NCOMBO, 2), dtype=np.int32)
+    for a in range(1, 52):
+        for b in range(a):
+            out[a * (a - 1) // 2 + b] = (a, b)
+    return out
+
+
+_CC = combo_cards()
+
+
+def blocked_mask(board) -> np.ndarray:
+    """Boolean (1326,) mask of combos that share a card with the board."""
+    bset = np.zeros(52, dtype=bool)
+    bset[np.asarray(board, dtype=np.int64)] = True
+    return bset[_CC[:, 0]] | bset[_CC[:, 1]]
+
+
+def draw_board(rng: np.random.Generator, n: int) -> list:
+    return [int(c) for c in rng.choice(52, n, replace=False)]
+
+
+def dirichlet_range(rng: np.random.Generator, board, alpha: float = 1.0, support: int | None = None) -> np.ndarray:
+    """Symmetric Dirichlet(alpha) over the board-compatible combos.
+
+    With ``support=k`` only k compatible combos, picked uniformly, get mass
+    (the sparse-support ranges the per-history oracle can afford on big trees).
+    """
+    ok = np.flatnonzero(~blocked_mask(board))
+    if support is not None:
+        ok = np.sort(rng.choice(ok, size=min(support, ok.size), replace=False))
+    w = rng.dirichlet(np.full(ok.size, alpha))
+    r = np.zeros(NCOMBO, dtype=np.float64)
+    r[ok] = w
+    return r
+
+
+def draw_pot_stack(rng: np.random.Generator, spr_lo: float = 1.0, spr_hi: float = 8.0,
+                   pot_lo: float = 20.0, pot_hi: float = 400.0, log_spr: bool = False):
+    """Pot log-uniform in [pot_lo, pot_hi] rounded to an even chip count; stack = round(SPR * pot)."""
+    pot = math.exp(rng.uniform(math.log(pot_lo), math.log(pot_hi)))
+    pot = max(2, 2 * int(round(pot / 2)))
+    if log_spr:
+        spr = math.exp(rng.uniform(math.log(spr_lo), math.log(spr_hi)))
+    else:
+        spr = rng.uniform(spr_lo, spr_hi)
+    stack = int(round(spr * pot))
+    return pot, stack
+
+
+def river_config(seed: int, support: int | None = None):
+    """River subgame: 5-card board, Dirichlet(1) ranges, pot 100, stacks 400,
+    sizes {50, 100}% + all-in, max 2 bets/raises per street."""
+    rng = np.random.default_rng(seed)
+    board = draw_board(rng, 5)
+    r0 = dirichlet_range(rng, board, 1.0, support)
+    r1 = dirichlet_range(rng, board, 1.0, support)
+    spec = dict(board=board, pot=100, stacks=(400, 400), sizes=[50, 100], allin=True,
+                max_raises=2, depth_limit=0)
+    return spec, np.stack([r0, r1])
+
+
+def turn_config(seed: int, support: int | None = None, spr: float | None = None, pot: int | None = None,
+                sizes=(33, 75, 150), max_raises: int = 3):
+    """Turn subgame solved to showdown: 4-card board, Dirichlet(1) ranges,
+    pot log-uniform in [20, 400], SPR uniform in [1, 8] unless given,
+    sizes {33, 75, 150}% + all-in, max 3 bets/raises per street."""
+    rng = np.random.default_rng(seed)
+    board = draw_board(rng, 4)
+    r0 = dirichlet_range(rng, board, 1.0, support)
+    r1 = dirichlet_range(rng, board, 1.0, support)
+    p, st = draw_pot_stack(rng)
+    if pot is not None:
+        p = pot
+    if spr is not None:
+        st = int(round(spr * p))
+    spec = dict(board=board, pot=p, stacks=(st, st), sizes=list(sizes), allin=True,
+                max_raises=max_raises, depth_limit=0)
+    return spec, np.stack([r0, r1])
+
+
+def flop_config(seed: int, support: int | None = None, pot: int = 100, stack: int = 400,
+                sizes=(33, 75), max_raises: int = 3):
+    """Depth-limited flop subgame: 3-card board, Dirichlet(1) ranges, leaves at
+    the turn card; pot 100, stack 400, sizes {33, 75}% + all-in, max 3."""
+    rng = np.random.default_rng(seed)
+    board = draw_board(rng, 3)
+    r0 = dirichlet_range(rng, board, 1.0, support)
+    r1 = dirichlet_range(rng, board, 1.0, support)
+    spec = dict(board=board, pot=pot, stacks=(stack, stack), sizes=list(sizes), allin=True,
+                max_raises=max_raises, depth_limit=1)
+    return spec, np.stack([r0, r1])
