@@ -1,0 +1,193 @@
+/*
+ * pcfr.h -- C ABI of the MI355X (gfx950) discounted-CFR library for heads-up
+ * no-limit hold'em public subgames.
+ *
+ * The operation is one CFR iteration over a public tree whose every node
+ * carries a range vector per player over the 1326 hole-card combos (Li &
+ * Huang, "Real-Time Parallel Counterfactual Regret Minimization", Sec. 4:
+ * the seven stages of Table 1 -- forward reach, aggregation, opponent reach,
+ * showdown, leaf evaluation, backward counterfactual values, regret update).
+ * Every stage runs in HIP kernels on the GPU; the host only builds the tree
+ * and its lookup tables once.
+ *
+ * Conventions shared with callers:
+ *   card  = 4*rank + suit, rank 0..12 = 2..A, suit 0..3;
+ *   combo = a(a-1)/2 + b for cards a > b, 0 <= combo < 1326;
+ *   chips are integers; each player has put pot/2 in at the root.
+ *
+ * Errors: every call returns an int32 status.  Out-parameters are written
+ * only on PCFR_OK.  pcfr_last_error() returns a message for the calling
+ * thread's most recent failure.  No C++ exception crosses this boundary.
+ *
+ * Threading: a handle is not thread-safe; distinct handles are independent.
+ * Device work of a solver is ordered on the stream given at creation.
+ */
+#ifndef PCFR_H
+#define PCFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCFR_ABI_VERSION 1
+#define PCFR_NCOMBO 1326
+
+enum {
+    PCFR_OK = 0,
+    PCFR_E_INVALID_ARG = 1,   /* bad pointer, size, card, range, node or enum */
+    PCFR_E_OUT_OF_MEMORY = 2, /* host allocation failed or workspace too small */
+    PCFR_E_DEVICE = 3,        /* a HIP runtime call failed */
+    PCFR_E_STATE = 4,         /* call not valid in the handle's current state */
+    PCFR_E_UNSUPPORTED = 5,   /* option not implemented */
+    PCFR_E_NUMERIC = 6,       /* non-finite value detected */
+    PCFR_E_TOO_LARGE = 7      /* tree exceeds an internal limit */
+};
+
+enum { PCFR_F32 = 0, PCFR_F64 = 1 };             /* solver arithmetic */
+enum { PCFR_AVG = 0, PCFR_CURRENT = 1 };         /* which strategy / values */
+enum { PCFR_DCFR = 0, PCFR_CFRPLUS = 1, PCFR_PCFRPLUS = 2 }; /* Stage-7 rule */
+
+/* Node types in exported trees. */
+enum {
+    PCFR_NODE_DECISION = 0,
+    PCFR_NODE_FOLD = 1,
+    PCFR_NODE_SHOWDOWN = 2,
+    PCFR_NODE_CHANCE = 3,
+    PCFR_NODE_LEAF = 4,       /* depth-limit leaf, valued by the leaf model */
+    PCFR_NODE_ALLIN_LEAF = 5  /* depth-limit leaf with a player all in: exact runout equity */
+};
+
+/* Betting abstraction of a subgame (Sec. 5 "Game": fixed action
+ * abstraction, stack-to-pot ratio, number of raise sizes).
+ *   n_board      3, 4 or 5 public cards in board[0..n_board)
+ *   pot          chips in the pot at the root; even, > 0
+ *   stack[2]     chips behind per player; the smaller one caps every bet
+ *   size_pct     n_sizes (<= 8) bet sizes as integer percent of the pot after
+ *                calling; a bet puts in to_call + floor((pct*pot' + 50)/100)
+ *   allin        1 adds an all-in action wherever bets are allowed
+ *   max_raises   bets + raises allowed per street, the opening bet included
+ *   depth_limit  0: play to showdown; 1: stop at the end of the root street
+ *                with depth-limit leaves.
+ * Player 0 acts first on every street. */
+typedef struct pcfr_tree_spec {
+    int32_t n_board;
+    int32_t board[5];
+    int64_t pot;
+    int64_t stack[2];
+    int32_t n_sizes;
+    int32_t size_pct[8];
+    int32_t allin;
+    int32_t max_raises;
+    int32_t depth_limit;
+} pcfr_tree_spec;
+
+/* Solver options.  DCFR discounting (the paper's default CFR variant,
+ * Sec. 5 "Baselines", after Brown & Sandholm 2019): after adding the
+ * iteration-t regret, a positive cumulative regret is scaled by
+ * t^alpha/(t^alpha+1), a non-positive one by t^beta/(t^beta+1), and the
+ * average-strategy sum by (t/(t+1))^gamma.  Updates are simultaneous for
+ * both players (alternating must be 0). */
+typedef struct pcfr_solver_cfg {
+    int32_t dtype;        /* PCFR_F32 or PCFR_F64 */
+    int32_t variant;      /* PCFR_DCFR */
+    double alpha, beta, gamma;
+    int32_t alternating;  /* must be 0 */
+} pcfr_solver_cfg;
+
+typedef struct pcfr_tree pcfr_tree;
+typedef struct pcfr_solver pcfr_solver;
+
+int32_t pcfr_abi_version(void);
+const char* pcfr_last_error(void);
+
+/* ---------------------------------------------------------------- tree
+ * Build the public tree of a subgame on the host (Sec. 3, depth-limited
+ * solving: the tree ends at showdown or at the depth limit).  Node ids are
+ * breadth-first from the root; children follow action order (fold, call or
+ * check, then bets ascending) and chance children ascend by card.  The
+ * library owns *out; release with pcfr_tree_free. */
+int32_t pcfr_build_tree(const pcfr_tree_spec* spec, pcfr_tree** out);
+int32_t pcfr_tree_free(pcfr_tree* tree);
+
+/* out[16]: nodes, decision, fold, showdown, chance, leaf, allin-leaf,
+ * levels, action rows (sum of actions over decision nodes), hands
+ * (board-compatible combos), padded hands, then zeros. */
+int32_t pcfr_tree_info(const pcfr_tree* tree, int64_t* out);
+
+/* Node arrays, each of length nodes (contrib: 2 per node), caller-owned
+ * host buffers.  player: actor of a decision, folder of a fold, else -1.
+ * parent/action: -1 at the root.  chance_card: card dealt on the edge into
+ * the node, else -1.  first_child: -1 for nodes without children. */
+int32_t pcfr_tree_export(const pcfr_tree* tree, int32_t* type, int32_t* player, int32_t* parent,
+                         int32_t* action, int32_t* depth, int64_t* contrib, int32_t* chance_card,
+                         int32_t* first_child, int32_t* n_child);
+
+/* Seven-card hand values, host side (used to order hands at showdown,
+ * Sec. 4.3 Stage 4).  cards: n*7 card ids; out: n values.  Value layout:
+ * category (0 high card .. 8 straight flush) in bits 20..23 and the
+ * tie-breaking ranks in bits 16..19 down to 0..3. */
+int32_t pcfr_eval7_batch(const int32_t* cards, int64_t n, int32_t* out);
+
+/* ---------------------------------------------------------------- solver
+ * Device memory is the caller's: ask for the size, allocate it, keep it alive
+ * until pcfr_solver_free.  The solver copies the tree, so the tree may be
+ * freed after creation. */
+int32_t pcfr_solver_workspace_bytes(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, size_t* bytes);
+
+/* ranges: host [2][1326] reach of each player's hands at the root; finite,
+ * >= 0, zero on combos that share a card with the board, and some compatible
+ * pair of hands must carry mass.  workspace: device pointer of at least
+ * pcfr_solver_workspace_bytes bytes, 256-byte aligned.  stream: a hipStream_t
+ * (NULL = default stream).  The solver starts at iteration 0 with zero
+ * regrets and zero average-strategy sums. */
+int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, const double* ranges,
+                           void* workspace, size_t workspace_bytes, void* stream, pcfr_solver** out);
+int32_t pcfr_solver_free(pcfr_solver* s);
+
+/* Enqueue n >= 0 DCFR iterations on the solver's stream (asynchronous).
+ * The per-iteration launch sequence is captured once in a HIP graph and
+ * replayed; the iteration counter lives on the device. */
+int32_t pcfr_cfr_iterate(pcfr_solver* s, int32_t n);
+int32_t pcfr_synchronize(pcfr_solver* s);
+
+/* Run n iterations like pcfr_cfr_iterate, but launch by launch with HIP
+ * events around every kernel on the solver's stream, and return the summed
+ * device time and launch count per kernel class: [0] iteration bookkeeping,
+ * [1] forward reach sweep, [2] terminal evaluation, [3] backward value and
+ * regret sweep.  ms and launches are host arrays of 4.  Synchronises. */
+int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* launches);
+int32_t pcfr_iteration(pcfr_solver* s, int64_t* t);   /* synchronises */
+
+/* Strategy at a decision node: PCFR_AVG = average strategy (sum of
+ * reach-weighted strategies, normalised; uniform where the sum is 0),
+ * PCFR_CURRENT = regret matching of the cumulative regrets (eq. rm; uniform
+ * where no regret is positive).  out: host [A][1326] doubles, A = the node's
+ * action count; combos blocked by the board get 0.  Synchronises. */
+int32_t pcfr_get_strategy(pcfr_solver* s, int32_t node, int32_t which, double* out);
+
+/* Root counterfactual values in chips (eq. cfv: each hand's value summed over
+ * compatible opponent hands weighted by their reach).  PCFR_CURRENT: from the
+ * last iteration, under the strategy it used; PCFR_AVG: under the average
+ * strategies of both players.  out: host [2][1326]; blocked combos get 0. */
+int32_t pcfr_get_root_cfv(pcfr_solver* s, int32_t which, double* out);
+
+/* Exploitability of the average strategy in chips per hand:
+ * (BR_0 + BR_1) / 2, BR_i = best-response value of player i against the
+ * other's average strategy, per unit of joint mass of compatible hand pairs.
+ * br may be NULL.  Synchronises. */
+int32_t pcfr_exploitability(pcfr_solver* s, double* chips_per_hand, double* br);
+
+/* Checkpoint: iteration counter, cumulative regrets and average-strategy
+ * sums in the solver's dtype.  pcfr_state_bytes gives the buffer size; buf is
+ * host memory. */
+int32_t pcfr_state_bytes(pcfr_solver* s, size_t* bytes);
+int32_t pcfr_save_state(pcfr_solver* s, void* buf, size_t bytes);
+int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCFR_H */

@@ -73,6 +73,8 @@ def lib():
             "ora_reach_current": (None, [P, P]),
             "ora_equity_table": (I, [P, I, P]),
             "ora_node_board": (I, [P, I, P]),
+            "ora_set_traverser_hands": (None, [P, P]),
+            "ora_max_threads": (I, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -107,6 +109,11 @@ def category_counts(n: int) -> np.ndarray:
     out = np.zeros(9, dtype=np.int64)
     lib().ora_category_counts(n, _p(out))
     return out
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().ora_max_threads())
 
 
 def distinct5() -> int:
@@ -229,6 +236,10 @@ class Solver:
         assert ev.size == self.num_leaves() * 2 * 52 * self.tree.nh
         self._ev = ev
         lib().ora_set_leaf_table(self._h, _p(ev))
+
+    def set_traverser_hands(self, mask):
+        m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(2, self.tree.nh)
+        lib().ora_set_traverser_hands(self._h, _p(m))
 
     def reach_current(self) -> np.ndarray:
         out = np.zeros((self.tree.n_nodes, 2, self.tree.nh), dtype=np.float64)

@@ -546,6 +546,7 @@ typedef struct {
     double cfv[2][NCOMBO];
     int64_t t;
     int support_only;
+    unsigned char* tmask;  /* optional [2][nh]: traverser hands to evaluate (NULL = all) */
     int leaf_kind;
     double* leaf_ev;      /* LEAF_TABLE: [leaf node][player][card][nh] expected value per pot */
     int* leaf_slot;       /* node -> leaf slot */
@@ -577,7 +578,17 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
 void ora_solver_free(osolver* s) {
     if (!s) return;
     free(s->R); free(s->S); free(s->sig); free(s->rinst); free(s->sadd);
-    free(s->leaf_ev); free(s->leaf_slot); free(s);
+    free(s->leaf_ev); free(s->leaf_slot); free(s->tmask); free(s);
+}
+
+/* Restrict the traverser's hands whose values and regrets are computed (the
+ * opponent's range is always used in full).  Regrets of the skipped hands
+ * stay zero, so this is only meaningful for a single iteration from the
+ * initial state or for hands whose rows are compared alone. */
+void ora_set_traverser_hands(osolver* s, const unsigned char* mask) {
+    size_t n = (size_t)2 * s->g->nh;
+    if (!s->tmask) s->tmask = malloc(n);
+    memcpy(s->tmask, mask, n);
 }
 
 /* Regret matching (eq. rm): positive part normalised, uniform if none. */
@@ -739,6 +750,7 @@ static void iterate_once(osolver* s) {
             s->cfv[i][hi] = 0;
             if (!g->hvalid[hi]) continue;
             if (s->support_only && !(s->rng[i][hi] > 0)) continue;
+            if (s->tmask && !s->tmask[i * nh + hi]) continue;
             double acc = 0;
             for (int k = 0; k < no; k++) {
                 int ho = olist[k];
@@ -762,6 +774,8 @@ static void iterate_once(osolver* s) {
         s->S[k] = (s->S[k] + s->sadd[k]) * davg;
     }
 }
+
+int ora_max_threads(void) { return omp_get_max_threads(); }
 
 void ora_iterate(osolver* s, int n_iter, int nthreads) {
     if (nthreads > 0) omp_set_num_threads(nthreads);

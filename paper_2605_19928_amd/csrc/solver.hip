@@ -1,0 +1,1087 @@
+// Discounted CFR over a hold'em public tree on gfx950: device kernels, the
+// solver runtime around them, and the solver half of the C ABI.
+//
+// Data layout (all in the caller's workspace):
+//   every public node n owns a reach slot [2][Hp] and a value slot [2][Hp]
+//   (player-major, hands contiguous, Hp = board-compatible hands padded to a
+//   multiple of 64); decision node n owns rows rs..rs+A-1 of the regret
+//   table R and the average-strategy table S, each row [Hp].  Hands are the
+//   root-compatible combos in ascending combo order; padding lanes carry zero
+//   reach and have no cards.
+//
+// One iteration (Sec. 4, Table 1), simultaneous for both players:
+//   forward, level by level from the root (Stages 1-2): regret matching
+//     (eq. rm) of each decision node, child reach = parent reach times the
+//     actor's action probability, the other player's reach copied, chance
+//     children masked by the dealt card; the average-strategy sum gets the
+//     reach-weighted strategy and its DCFR discount in the same pass;
+//   terminals, one workgroup per node (Stages 2-4): per-card and total
+//     opponent reach, compatible mass by inclusion-exclusion over the two
+//     cards of a hand, fold values; showdown values by a scan over hands
+//     sorted by strength with per-card corrections;
+//   backward, level by level to the root (Stages 6-7): eq. backward at the
+//     actor's nodes, plain sums at the opponent's, 1/K-weighted sums at
+//     chance nodes, and the regret update with DCFR discounting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+
+namespace pcfr {
+
+enum { MODE_ITER = 0, MODE_BR = 1, MODE_EV = 2 };
+
+struct __align__(16) DNode {
+    int32_t type, player, first_child, n_child;
+    int32_t rs, aux, card, sub;   // aux: showdown board table, or chance divisor K
+    int32_t dead, pad0;           // cards dealt since the root, packed c1 | c2 << 8 (0xff = none)
+    double pay;                   // fold: folder's contribution; showdown: each contribution
+};
+
+struct IterState {
+    int64_t t;
+    int64_t pad;
+    double dpos, dneg, davg, pad2;
+};
+
+constexpr int kBlock = 256;
+constexpr int kSdHeader = 64;     // card-list offsets per board table (53 used)
+
+// ------------------------------------------------------------ vector I/O
+template <typename T> struct V4 { T e[4]; };
+
+__device__ __forceinline__ V4<float> ld4(const float* p) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    return V4<float>{{v.x, v.y, v.z, v.w}};
+}
+__device__ __forceinline__ V4<double> ld4(const double* p) {
+    double2 a = *reinterpret_cast<const double2*>(p);
+    double2 b = *reinterpret_cast<const double2*>(p + 2);
+    return V4<double>{{a.x, a.y, b.x, b.y}};
+}
+__device__ __forceinline__ void st4(float* p, const V4<float>& v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v.e[0], v.e[1], v.e[2], v.e[3]);
+}
+__device__ __forceinline__ void st4(double* p, const V4<double>& v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v.e[0], v.e[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v.e[2], v.e[3]);
+}
+
+// ------------------------------------------------------------ iteration state
+__global__ void k_begin_iter(IterState* st, double alpha, double beta, double gamma) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t t = st->t + 1;
+    st->t = t;
+    double td = (double)t;
+    double ta = pow(td, alpha), tb = pow(td, beta);
+    st->dpos = ta / (ta + 1.0);
+    st->dneg = tb / (tb + 1.0);
+    st->davg = pow(td / (td + 1.0), gamma);
+}
+
+// ------------------------------------------------------------ forward
+// Strategy of a row group for 4 hands: regret matching of R (MODE_ITER) or
+// the normalised average-strategy sum S (other modes); uniform when the
+// denominator vanishes.
+template <typename T, int MODE>
+__device__ __forceinline__ T strat(T x, T den, T inv_a) {
+    if (MODE == MODE_ITER) return den > T(0) ? (x > T(0) ? x / den : T(0)) : inv_a;
+    return den > T(0) ? x / den : inv_a;
+}
+
+template <typename T, int MODE, int A>
+__device__ __forceinline__ void fwd_decision(const DNode& nd, int64_t n, int h, int Hp, const T* __restrict__ R,
+                                             const T* __restrict__ S, T* __restrict__ reach) {
+    const int p = nd.player, o = 1 - p;
+    const T* rn = reach + n * 2 * Hp;
+    const V4<T> rp = ld4(rn + (int64_t)p * Hp + h);
+    const V4<T> ro = ld4(rn + (int64_t)o * Hp + h);
+    const T* src = (MODE == MODE_ITER ? R : S) + (int64_t)nd.rs * Hp + h;
+    V4<T> x[A];
+#pragma unroll
+    for (int a = 0; a < A; a++) x[a] = ld4(src + (int64_t)a * Hp);
+    T den[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < A; a++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
+    const T inv_a = T(1) / T(A);
+#pragma unroll
+    for (int a = 0; a < A; a++) {
+        V4<T> q;
+#pragma unroll
+        for (int j = 0; j < 4; j++) q.e[j] = rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a);
+        T* rc = reach + (int64_t)(nd.first_child + a) * 2 * Hp;
+        st4(rc + (int64_t)p * Hp + h, q);
+        st4(rc + (int64_t)o * Hp + h, ro);
+    }
+}
+
+__device__ __forceinline__ bool has_card(uint32_t hc, int c) {
+    return (int)(hc & 0xffu) == c || (int)(hc >> 8) == c;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
+                                                    int count, int Hp, const T* __restrict__ R, const T* __restrict__ S,
+                                                    T* __restrict__ reach, const uint16_t* __restrict__ hcards) {
+    const int groups = Hp >> 2;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k = gid / groups;
+    if (k >= count) return;
+    const int h = (int)(gid - k * groups) * 4;
+    const int64_t n = list[k];
+    const DNode nd = nodes[n];
+    if (nd.type == PCFR_NODE_CHANCE) {
+        const T* rn = reach + n * 2 * Hp;
+        const V4<T> r0 = ld4(rn + h), r1 = ld4(rn + Hp + h);
+        const uint16_t* hc = hcards + (int64_t)nd.sub * Hp + h;
+        uint32_t c4[4] = {hc[0], hc[1], hc[2], hc[3]};
+        for (int c = 0; c < nd.n_child; c++) {
+            const int64_t ch = nd.first_child + c;
+            const int card = nodes[ch].card;
+            V4<T> m0 = r0, m1 = r1;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (has_card(c4[j], card)) { m0.e[j] = T(0); m1.e[j] = T(0); }
+            T* rc = reach + ch * 2 * Hp;
+            st4(rc + h, m0);
+            st4(rc + Hp + h, m1);
+        }
+        return;
+    }
+    switch (nd.n_child) {
+#define PCFR_FWD_CASE(A) case A: fwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, reach); break;
+        PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
+        PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
+#undef PCFR_FWD_CASE
+        default: break;
+    }
+}
+
+// ------------------------------------------------------------ backward
+template <typename T, int MODE, int A>
+__device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
+                                             T* __restrict__ S, const T* __restrict__ reach, T* __restrict__ cfv,
+                                             const IterState* st) {
+    const int p = nd.player, o = 1 - p;
+    V4<T> x[A];
+    T den[4] = {T(0), T(0), T(0), T(0)};
+    const T inv_a = T(1) / T(A);
+    if (MODE != MODE_BR) {
+        const T* src = (MODE == MODE_ITER ? (const T*)R : S) + (int64_t)nd.rs * Hp + h;
+#pragma unroll
+        for (int a = 0; a < A; a++) x[a] = ld4(src + (int64_t)a * Hp);
+#pragma unroll
+        for (int a = 0; a < A; a++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
+    }
+    V4<T> vp = {{T(0), T(0), T(0), T(0)}}, vo = {{T(0), T(0), T(0), T(0)}};
+#pragma unroll
+    for (int a = 0; a < A; a++) {
+        const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
+        const V4<T> c = ld4(cc + (int64_t)p * Hp + h);
+        const V4<T> d = ld4(cc + (int64_t)o * Hp + h);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            vo.e[j] += d.e[j];
+            if (MODE == MODE_BR) vp.e[j] = (a == 0 || c.e[j] > vp.e[j]) ? c.e[j] : vp.e[j];
+            else vp.e[j] += strat<T, MODE>(x[a].e[j], den[j], inv_a) * c.e[j];
+        }
+    }
+    T* me = cfv + n * 2 * Hp;
+    st4(me + (int64_t)p * Hp + h, vp);
+    st4(me + (int64_t)o * Hp + h, vo);
+    if (MODE == MODE_ITER) {
+        // Stage 7: regret update, and the reach-weighted strategy added to the
+        // average-strategy sum (Stage 1's accumulation, done here so that one
+        // pass reads and writes both tables), each with its DCFR discount.
+        const T dpos = (T)st->dpos, dneg = (T)st->dneg, davg = (T)st->davg;
+        const V4<T> rp = ld4(reach + n * 2 * Hp + (int64_t)p * Hp + h);
+#pragma unroll
+        for (int a = 0; a < A; a++) {
+            const V4<T> c = ld4(cfv + (int64_t)(nd.first_child + a) * 2 * Hp + (int64_t)p * Hp + h);
+            T* sp = S + (int64_t)(nd.rs + a) * Hp + h;
+            V4<T> sv = ld4(sp);
+            V4<T> y;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                T r = x[a].e[j] + (c.e[j] - vp.e[j]);
+                y.e[j] = r * (r > T(0) ? dpos : dneg);
+                sv.e[j] = (sv.e[j] + rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a)) * davg;
+            }
+            st4(R + (int64_t)(nd.rs + a) * Hp + h, y);
+            st4(sp, sv);
+        }
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
+                                                     int count, int Hp, T* __restrict__ R, T* __restrict__ S,
+                                                     const T* __restrict__ reach, T* __restrict__ cfv,
+                                                     const IterState* __restrict__ st) {
+    const int groups = Hp >> 2;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k = gid / groups;
+    if (k >= count) return;
+    const int h = (int)(gid - k * groups) * 4;
+    const int64_t n = list[k];
+    const DNode nd = nodes[n];
+    if (nd.type == PCFR_NODE_CHANCE) {
+        V4<T> a0 = {{T(0), T(0), T(0), T(0)}}, a1 = a0;
+        for (int c = 0; c < nd.n_child; c++) {
+            const T* cc = cfv + (int64_t)(nd.first_child + c) * 2 * Hp;
+            const V4<T> u = ld4(cc + h), w = ld4(cc + Hp + h);
+#pragma unroll
+            for (int j = 0; j < 4; j++) { a0.e[j] += u.e[j]; a1.e[j] += w.e[j]; }
+        }
+        const T inv_k = T(1) / T(nd.aux);
+#pragma unroll
+        for (int j = 0; j < 4; j++) { a0.e[j] *= inv_k; a1.e[j] *= inv_k; }
+        T* me = cfv + n * 2 * Hp;
+        st4(me + h, a0);
+        st4(me + Hp + h, a1);
+        return;
+    }
+    switch (nd.n_child) {
+#define PCFR_BWD_CASE(A) case A: bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, reach, cfv, st); break;
+        PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
+        PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
+#undef PCFR_BWD_CASE
+        default: break;
+    }
+}
+
+// ------------------------------------------------------------ terminals
+// Fold: v_i(h) = -+ c_f * M_{-i}(h) where M(h) is the opponent reach over
+// hands sharing no card with h: total - per-card(a) - per-card(b) + r(h)
+// (the hand itself was removed twice).
+template <typename T>
+__device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
+                          const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
+                          const int16_t* __restrict__ chands, T* lds) {
+    T* pc = lds;              // [2][52]
+    T* red = lds + 104;       // [2][kBlock]
+    const T* r0 = reach + n * 2 * Hp;
+    const T* r1 = r0 + Hp;
+    const int tid = threadIdx.x;
+    if (tid < 104) {
+        const int p = tid / 52, c = tid - p * 52;
+        const T* r = p ? r1 : r0;
+        T s = T(0);
+        for (int j = coff[c]; j < coff[c + 1]; j++) s += r[chands[j]];
+        pc[tid] = s;
+    }
+    T s0 = T(0), s1 = T(0);
+    for (int h = tid; h < Hp; h += kBlock) { s0 += r0[h]; s1 += r1[h]; }
+    red[tid] = s0;
+    red[kBlock + tid] = s1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) { red[tid] += red[tid + w]; red[kBlock + tid] += red[kBlock + tid + w]; }
+        __syncthreads();
+    }
+    const T tot0 = red[0], tot1 = red[kBlock];
+    const int f = nd.player;
+    const T pay = (T)nd.pay;
+    const int d1 = nd.dead & 0xff, d2 = (nd.dead >> 8) & 0xff;
+    T* v0 = cfv + n * 2 * Hp;
+    T* v1 = v0 + Hp;
+    for (int h = tid; h < Hp; h += kBlock) {
+        const uint32_t c = hc[h];
+        const int a = c & 0xff, b = c >> 8;
+        const bool alive = a != 0xff && a != d1 && a != d2 && b != d1 && b != d2;
+        T m0 = T(0), m1 = T(0);
+        if (alive) {
+            m0 = tot0 - pc[a] - pc[b] + r0[h];
+            m1 = tot1 - pc[52 + a] - pc[52 + b] + r1[h];
+        }
+        v0[h] = (f == 0 ? -pay : pay) * m1;
+        v1[h] = (f == 1 ? -pay : pay) * m0;
+    }
+}
+
+// Showdown on a five-card board: hands sorted by value ascending (perm),
+// with tie groups [glo, ghi) in sorted positions; every card has the list of
+// sorted positions of hands holding it, ascending, followed by one slot for
+// the list total; [alo, ahi) and [blo, bhi) are the tie group of a hand inside
+// the lists of its two cards.  W = opponent reach of compatible weaker hands,
+// L = of compatible stronger ones; ties pay nothing.
+template <typename T>
+__device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
+                              const uint16_t* __restrict__ hc, const int16_t* __restrict__ tb, int Hb, T* lds) {
+    const int QN = 2 * Hp + kSdHeader;
+    T* xs0 = lds;                 // [Hp + 1]: sorted reach, then its exclusive prefix
+    T* xs1 = xs0 + (Hp + 1);
+    T* q0 = xs1 + (Hp + 1);       // [QN]: card-list exclusive prefixes
+    T* q1 = q0 + QN;
+    T* part = q1 + QN;            // [2][kBlock]
+    const int16_t* perm = tb;
+    const int16_t* glo = tb + Hp;
+    const int16_t* ghi = tb + 2 * Hp;
+    const int16_t* alo = tb + 3 * Hp;
+    const int16_t* ahi = tb + 4 * Hp;
+    const int16_t* blo = tb + 5 * Hp;
+    const int16_t* bhi = tb + 6 * Hp;
+    const int16_t* coff = tb + 7 * Hp;
+    const int16_t* clist = coff + kSdHeader;
+    const T* r0 = reach + n * 2 * Hp;
+    const T* r1 = r0 + Hp;
+    const int tid = threadIdx.x;
+
+    for (int s = tid; s < Hb; s += kBlock) {
+        const int h = perm[s];
+        xs0[s] = r0[h];
+        xs1[s] = r1[h];
+    }
+    __syncthreads();
+    if (tid < 104) {
+        const int p = tid / 52, c = tid - p * 52;
+        const T* xs = p ? xs1 : xs0;
+        T* q = p ? q1 : q0;
+        const int lo = coff[c], hi = coff[c + 1] - 1;
+        T acc = T(0);
+        for (int j = lo; j < hi; j++) { q[j] = acc; acc += xs[clist[j]]; }
+        q[hi] = acc;
+    }
+    // block-wide exclusive scan of xs0 / xs1 over [0, Hb), total at [Hb]
+    constexpr int kMaxChunk = 8;
+    const int chunk = (Hb + kBlock - 1) / kBlock;
+    const int beg = tid * chunk;
+    T l0[kMaxChunk], l1[kMaxChunk];
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int i = 0; i < kMaxChunk; i++) {
+        const int s = beg + i;
+        const bool in = i < chunk && s < Hb;
+        l0[i] = in ? xs0[s] : T(0);
+        l1[i] = in ? xs1[s] : T(0);
+        s0 += l0[i];
+        s1 += l1[i];
+    }
+    part[tid] = s0;
+    part[kBlock + tid] = s1;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        T a0 = tid >= off ? part[tid - off] : T(0);
+        T a1 = tid >= off ? part[kBlock + tid - off] : T(0);
+        __syncthreads();
+        part[tid] += a0;
+        part[kBlock + tid] += a1;
+        __syncthreads();
+    }
+    T e0 = part[tid] - s0, e1 = part[kBlock + tid] - s1;   // exclusive offset of this chunk
+#pragma unroll
+    for (int i = 0; i < kMaxChunk; i++) {
+        const int s = beg + i;
+        if (i < chunk && s < Hb) {
+            xs0[s] = e0;
+            xs1[s] = e1;
+            e0 += l0[i];
+            e1 += l1[i];
+        }
+    }
+    if (tid == kBlock - 1) {
+        xs0[Hb] = part[kBlock - 1];
+        xs1[Hb] = part[2 * kBlock - 1];
+    }
+    __syncthreads();
+
+    const T pay = (T)nd.pay;
+    T* v0 = cfv + n * 2 * Hp;
+    T* v1 = v0 + Hp;
+    const T tot0 = xs0[Hb], tot1 = xs1[Hb];
+    for (int s = tid; s < Hp; s += kBlock) {
+        const int h = perm[s];
+        if (s >= Hb) { v0[h] = T(0); v1[h] = T(0); continue; }
+        const uint32_t c = hc[h];
+        const int a = c & 0xff, b = c >> 8;
+        const int ae = coff[a + 1] - 1, be = coff[b + 1] - 1;
+        const int gl = glo[s], gh = ghi[s], al = alo[s], ah = ahi[s], bl = blo[s], bh = bhi[s];
+        // against player 1's reach (value of player 0)
+        const T w1 = xs1[gl] - q1[al] - q1[bl];
+        const T lo1 = (tot1 - xs1[gh]) - (q1[ae] - q1[ah]) - (q1[be] - q1[bh]);
+        const T w0 = xs0[gl] - q0[al] - q0[bl];
+        const T lo0 = (tot0 - xs0[gh]) - (q0[ae] - q0[ah]) - (q0[be] - q0[bh]);
+        v0[h] = pay * (w1 - lo1);
+        v1[h] = pay * (w0 - lo0);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
+                                                     int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
+                                                     const uint16_t* __restrict__ hcards, const int32_t* __restrict__ coff,
+                                                     const int16_t* __restrict__ chands, int chand_stride,
+                                                     const int16_t* __restrict__ sd, int64_t sd_stride,
+                                                     const int32_t* __restrict__ sd_n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    const int64_t n = list[blockIdx.x];
+    const DNode nd = nodes[n];
+    const uint16_t* hc = hcards + (int64_t)nd.sub * Hp;
+    if (nd.type == PCFR_NODE_FOLD)
+        term_fold<T>(nd, n, Hp, reach, cfv, hc, coff + nd.sub * 53, chands + (int64_t)nd.sub * chand_stride, lds);
+    else
+        term_showdown<T>(nd, n, Hp, reach, cfv, hc, sd + (int64_t)nd.aux * sd_stride, sd_n[nd.aux], lds);
+}
+
+// ------------------------------------------------------------ small kernels
+template <typename T>
+__global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// Strategy of one decision node for every hand: which 0 = average, 1 = current.
+template <typename T>
+__global__ void k_strategy(const T* __restrict__ src, int rs, int A, int Hp, int which, T* __restrict__ out) {
+    int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= Hp) return;
+    T den = T(0);
+    for (int a = 0; a < A; a++) {
+        T x = src[(int64_t)(rs + a) * Hp + h];
+        den += which ? (x > T(0) ? x : T(0)) : x;
+    }
+    for (int a = 0; a < A; a++) {
+        T x = src[(int64_t)(rs + a) * Hp + h];
+        out[(int64_t)a * Hp + h] = den > T(0) ? ((which && !(x > T(0))) ? T(0) : x / den) : T(1) / T(A);
+    }
+}
+
+// ------------------------------------------------------------ host runtime
+static int32_t hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PCFR_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return PCFR_E_DEVICE;
+}
+#define HIPCHK(call)                                             \
+    do {                                                         \
+        int32_t _rc = hip_check((call), #call);                  \
+        if (_rc != PCFR_OK) return _rc;                          \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+    int64_t N, rows, Hp, H, n_boards, term, fwd, chand_stride, sd_stride;
+    size_t esz;
+    size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
+        off_R, off_S, off_reach, off_cfv, off_root, off_stage, total;
+    size_t lds_bytes;
+};
+
+struct Prepared {
+    std::vector<DNode> nodes;
+    std::vector<int32_t> fwd, term;
+    std::vector<int64_t> fwd_off;         // per level start into fwd (size levels+1)
+    std::vector<uint16_t> hcards;         // [Hp]
+    std::vector<int32_t> coff;            // [53]
+    std::vector<int16_t> chands;
+    std::vector<int16_t> sd;              // [boards][sd_stride]
+    std::vector<int32_t> sdn;
+    std::vector<int32_t> hand_combo;      // [H]
+    std::vector<int32_t> combo_hand;      // [1326], -1 if blocked
+    int64_t Hp = 0, H = 0, sd_stride = 0;
+    int32_t levels = 0, max_a = 0;
+};
+
+// Host preprocessing: node records, level work lists, hand cards, per-card
+// hand lists, and one strength-sorted table per showdown board.
+static int32_t prepare(const Tree& t, Prepared& P) {
+    const ComboTable& cc = combos();
+    P.combo_hand.assign(kCombos, -1);
+    for (int k = 0; k < kCombos; k++) {
+        if ((t.root_mask >> cc.hi[k] & 1ull) || (t.root_mask >> cc.lo[k] & 1ull)) continue;
+        P.combo_hand[k] = (int32_t)P.hand_combo.size();
+        P.hand_combo.push_back(k);
+    }
+    P.H = (int64_t)P.hand_combo.size();
+    P.Hp = (P.H + 63) / 64 * 64;
+    const int64_t Hp = P.Hp;
+    P.hcards.assign(Hp, 0xffff);
+    for (int64_t h = 0; h < P.H; h++) {
+        int k = P.hand_combo[h];
+        P.hcards[h] = (uint16_t)(cc.hi[k] | (cc.lo[k] << 8));
+    }
+    // per-card hand lists
+    P.coff.assign(53, 0);
+    {
+        std::vector<std::vector<int16_t>> lists(52);
+        for (int64_t h = 0; h < P.H; h++) {
+            int k = P.hand_combo[h];
+            lists[cc.hi[k]].push_back((int16_t)h);
+            lists[cc.lo[k]].push_back((int16_t)h);
+        }
+        for (int c = 0; c < 52; c++) {
+            P.coff[c] = (int32_t)P.chands.size();
+            for (auto x : lists[c]) P.chands.push_back(x);
+        }
+        P.coff[52] = (int32_t)P.chands.size();
+    }
+    // showdown boards
+    P.sd_stride = (7 * Hp + kSdHeader + 2 * Hp + kSdHeader + 63) / 64 * 64;
+    std::map<uint64_t, int32_t> board_id;
+    const int64_t N = (int64_t)t.nodes.size();
+    P.nodes.resize(N);
+    P.levels = t.n_levels;
+    std::vector<std::vector<int32_t>> per_level(t.n_levels);
+    for (int64_t i = 0; i < N; i++) {
+        const Node& s = t.nodes[i];
+        DNode d{};
+        d.type = s.type; d.player = s.player; d.first_child = s.first_child; d.n_child = s.n_child;
+        d.rs = -1; d.aux = 0; d.card = s.chance_card; d.sub = 0; d.pay = 0.0;
+        // cards dealt since the root
+        uint64_t extra = s.board_mask & ~t.root_mask;
+        int dd[2] = {0xff, 0xff}, nd = 0;
+        for (int c = 0; c < 52 && nd < 2; c++) if (extra >> c & 1ull) dd[nd++] = c;
+        d.dead = dd[0] | (dd[1] << 8);
+        P.nodes[i] = d;
+    }
+    int64_t rows = 0;
+    for (int64_t i = 0; i < N; i++) {
+        const Node& s = t.nodes[i];
+        DNode& d = P.nodes[i];
+        if (s.type == PCFR_NODE_DECISION) {
+            d.rs = (int32_t)rows;
+            rows += s.n_child;
+            if (s.n_child > kMaxActions || s.n_child < 1) { set_error("unsupported action count"); return PCFR_E_TOO_LARGE; }
+            P.max_a = std::max(P.max_a, s.n_child);
+            per_level[s.depth].push_back((int32_t)i);
+        } else if (s.type == PCFR_NODE_CHANCE) {
+            int nb = __builtin_popcountll(s.board_mask);
+            d.aux = 52 - nb - 4;
+            per_level[s.depth].push_back((int32_t)i);
+        } else if (s.type == PCFR_NODE_FOLD) {
+            d.pay = (double)s.contrib[s.player];
+            P.term.push_back((int32_t)i);
+        } else if (s.type == PCFR_NODE_SHOWDOWN) {
+            d.pay = (double)s.contrib[0];
+            auto it = board_id.find(s.board_mask);
+            if (it == board_id.end()) it = board_id.emplace(s.board_mask, (int32_t)board_id.size()).first;
+            d.aux = it->second;
+            P.term.push_back((int32_t)i);
+        } else {
+            set_error("depth-limit leaves need a leaf model, which this solver does not take");
+            return PCFR_E_UNSUPPORTED;
+        }
+    }
+    P.fwd_off.assign(t.n_levels + 1, 0);
+    for (int l = 0; l < t.n_levels; l++) {
+        P.fwd_off[l] = (int64_t)P.fwd.size();
+        for (auto x : per_level[l]) P.fwd.push_back(x);
+    }
+    P.fwd_off[t.n_levels] = (int64_t)P.fwd.size();
+    // strength tables
+    const int64_t nbds = (int64_t)board_id.size();
+    P.sd.assign((size_t)std::max<int64_t>(nbds, 1) * P.sd_stride, 0);
+    P.sdn.assign(std::max<int64_t>(nbds, 1), 0);
+    for (auto& kv : board_id) {
+        const uint64_t bm = kv.first;
+        int16_t* tb = P.sd.data() + (size_t)kv.second * P.sd_stride;
+        std::vector<std::pair<uint32_t, int32_t>> alive;
+        std::vector<char> is_alive(Hp, 0);
+        for (int64_t h = 0; h < P.H; h++) {
+            int k = P.hand_combo[h];
+            uint64_t hm = (1ull << cc.hi[k]) | (1ull << cc.lo[k]);
+            if (hm & bm) continue;
+            alive.push_back({eval7_mask(hm | bm), (int32_t)h});
+            is_alive[h] = 1;
+        }
+        std::sort(alive.begin(), alive.end());
+        const int Hb = (int)alive.size();
+        P.sdn[kv.second] = Hb;
+        int16_t *perm = tb, *glo = tb + Hp, *ghi = tb + 2 * Hp, *alo = tb + 3 * Hp, *ahi = tb + 4 * Hp,
+                *blo = tb + 5 * Hp, *bhi = tb + 6 * Hp, *coff = tb + 7 * Hp, *clist = coff + kSdHeader;
+        int s = 0;
+        for (auto& x : alive) perm[s++] = (int16_t)x.second;
+        for (int64_t h = 0; h < Hp; h++) if (!is_alive[h]) perm[s++] = (int16_t)h;
+        for (int i = 0; i < Hb;) {
+            int j = i;
+            while (j < Hb && alive[j].first == alive[i].first) j++;
+            for (int q = i; q < j; q++) { glo[q] = (int16_t)i; ghi[q] = (int16_t)j; }
+            i = j;
+        }
+        // per-card lists of sorted positions, each followed by a total slot
+        std::vector<std::vector<int>> lists(52);
+        for (int q = 0; q < Hb; q++) {
+            int k = P.hand_combo[alive[q].second];
+            lists[cc.hi[k]].push_back(q);
+            lists[cc.lo[k]].push_back(q);
+        }
+        int pos = 0;
+        std::vector<int> where_hi(Hb), where_lo(Hb);
+        for (int c = 0; c < 52; c++) {
+            coff[c] = (int16_t)pos;
+            for (int q : lists[c]) {
+                int k = P.hand_combo[alive[q].second];
+                if (cc.hi[k] == c) where_hi[q] = pos; else where_lo[q] = pos;
+                clist[pos++] = (int16_t)q;
+            }
+            clist[pos++] = -1;
+        }
+        coff[52] = (int16_t)pos;
+        auto group = [&](int c, int at, int16_t& lo, int16_t& hi) {
+            uint32_t v = alive[clist[at]].first;
+            int a = at, b = at;
+            while (a > coff[c] && alive[clist[a - 1]].first == v) a--;
+            while (b + 1 < coff[c + 1] - 1 && alive[clist[b + 1]].first == v) b++;
+            lo = (int16_t)a;
+            hi = (int16_t)(b + 1);
+        };
+        for (int q = 0; q < Hb; q++) {
+            int k = P.hand_combo[alive[q].second];
+            group(cc.hi[k], where_hi[q], alo[q], ahi[q]);
+            group(cc.lo[k], where_lo[q], blo[q], bhi[q]);
+        }
+    }
+    return PCFR_OK;
+}
+
+static void make_plan(const Prepared& P, const Tree& t, int dtype, Plan& L) {
+    L.N = (int64_t)P.nodes.size();
+    L.rows = t.rows;
+    L.Hp = P.Hp;
+    L.H = P.H;
+    L.n_boards = (int64_t)P.sdn.size();
+    L.term = (int64_t)P.term.size();
+    L.fwd = (int64_t)P.fwd.size();
+    L.chand_stride = (int64_t)P.chands.size();
+    L.sd_stride = P.sd_stride;
+    L.esz = dtype == PCFR_F64 ? 8 : 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.off_nodes = take(sizeof(DNode) * L.N);
+    L.off_fwd = take(sizeof(int32_t) * std::max<int64_t>(L.fwd, 1));
+    L.off_term = take(sizeof(int32_t) * std::max<int64_t>(L.term, 1));
+    L.off_hc = take(sizeof(uint16_t) * L.Hp);
+    L.off_coff = take(sizeof(int32_t) * 53);
+    L.off_chands = take(sizeof(int16_t) * std::max<int64_t>(L.chand_stride, 1));
+    L.off_sd = take(sizeof(int16_t) * L.n_boards * L.sd_stride);
+    L.off_sdn = take(sizeof(int32_t) * L.n_boards);
+    L.off_state = take(sizeof(IterState));
+    L.off_R = take(L.esz * L.rows * L.Hp);
+    L.off_S = take(L.esz * L.rows * L.Hp);
+    L.off_reach = take(L.esz * L.N * 2 * L.Hp);
+    L.off_cfv = take(L.esz * L.N * 2 * L.Hp);
+    L.off_root = take(L.esz * 2 * L.Hp);
+    L.off_stage = take(L.esz * kMaxActions * L.Hp);
+    L.total = o;
+    const size_t qn = 2 * L.Hp + kSdHeader;
+    L.lds_bytes = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock);
+}
+
+}  // namespace pcfr
+
+using namespace pcfr;
+
+struct pcfr_solver {
+    Tree tree;
+    pcfr_solver_cfg cfg;
+    Prepared P;
+    Plan L;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    double ranges[2][kCombos];
+    double pair_mass = 0;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    int64_t t_host = 0;     // iterations enqueued
+    template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace pcfr {
+
+// Optional per-launch timing: events recorded around every launch, tagged
+// with a kernel class (0 small kernels, 1 forward, 2 terminal, 3 backward).
+struct LaunchTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> cls;
+    hipStream_t stream;
+    void before(int c) {
+        hipEvent_t a;
+        (void)hipEventCreate(&a);
+        (void)hipEventRecord(a, stream);
+        ev.push_back(a);
+        cls.push_back(c);
+    }
+    void after() {
+        hipEvent_t b;
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(b, stream);
+        ev.push_back(b);
+    }
+};
+
+template <typename T, int MODE>
+static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm = nullptr) {
+    const Plan& L = s->L;
+    const Prepared& P = s->P;
+    const int Hp = (int)L.Hp;
+    const int groups = Hp / 4;
+    DNode* nodes = s->at<DNode>(L.off_nodes);
+    int32_t* fwd = s->at<int32_t>(L.off_fwd);
+    T* R = s->at<T>(L.off_R);
+    T* S = s->at<T>(L.off_S);
+    T* reach = s->at<T>(L.off_reach);
+    T* cfv = s->at<T>(L.off_cfv);
+    IterState* st = s->at<IterState>(L.off_state);
+    if (MODE == MODE_ITER) {
+        if (tm) tm->before(0);
+        hipLaunchKernelGGL(k_begin_iter, dim3(1), dim3(64), 0, stream, st, s->cfg.alpha, s->cfg.beta, s->cfg.gamma);
+        if (tm) tm->after();
+    }
+    for (int l = 0; l < P.levels; l++) {
+        int64_t cnt = P.fwd_off[l + 1] - P.fwd_off[l];
+        if (!cnt) continue;
+        int64_t threads = cnt * groups;
+        dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
+        if (tm) tm->before(1);
+        hipLaunchKernelGGL((k_forward<T, MODE>), grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l],
+                           (int)cnt, Hp, R, S, reach, s->at<uint16_t>(L.off_hc));
+        if (tm) tm->after();
+    }
+    if (L.term) {
+        if (tm) tm->before(2);
+        hipLaunchKernelGGL((k_terminal<T>), dim3((unsigned)L.term), dim3(kBlock), L.lds_bytes, stream, nodes,
+                           s->at<int32_t>(L.off_term), Hp, reach, cfv, s->at<uint16_t>(L.off_hc),
+                           s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands), (int)L.chand_stride,
+                           s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn));
+        if (tm) tm->after();
+    }
+    for (int l = P.levels - 1; l >= 0; l--) {
+        int64_t cnt = P.fwd_off[l + 1] - P.fwd_off[l];
+        if (!cnt) continue;
+        int64_t threads = cnt * groups;
+        dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
+        if (tm) tm->before(3);
+        hipLaunchKernelGGL((k_backward<T, MODE>), grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l],
+                           (int)cnt, Hp, R, S, reach, cfv, st);
+        if (tm) tm->after();
+    }
+    if (MODE == MODE_ITER) {
+        int64_t n = 2 * L.Hp;
+        if (tm) tm->before(0);
+        hipLaunchKernelGGL((k_copy<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, cfv,
+                           s->at<T>(L.off_root), n);
+        if (tm) tm->after();
+    }
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
+template <int MODE>
+static int32_t sweep(pcfr_solver* s, hipStream_t stream) {
+    return s->cfg.dtype == PCFR_F64 ? enqueue_sweep<double, MODE>(s, stream) : enqueue_sweep<float, MODE>(s, stream);
+}
+template <int MODE>
+static int32_t sweep(pcfr_solver* s) { return sweep<MODE>(s, s->stream); }
+
+// One iteration's launch sequence, captured once on a private stream (the
+// caller's may be the legacy default stream, which cannot be captured) and
+// replayed on the caller's stream.
+static int32_t build_graph(pcfr_solver* s) {
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { (void)hipStreamDestroy(cs); return hip_check(e, "hipStreamBeginCapture"); }
+    int32_t rc = sweep<MODE_ITER>(s, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc != PCFR_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    HIPCHK(e);
+    s->graph_def = g;
+    HIPCHK(hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0));
+    return PCFR_OK;
+}
+
+// Copy a [rows][Hp] device block (solver dtype) into host doubles [rows][1326].
+static int32_t fetch_hands(pcfr_solver* s, const void* dev, int rows, double* out) {
+    const Plan& L = s->L;
+    std::vector<char> buf(L.esz * rows * L.Hp);
+    HIPCHK(hipMemcpyAsync(buf.data(), dev, buf.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int r = 0; r < rows; r++)
+        for (int k = 0; k < kCombos; k++) {
+            int h = s->P.combo_hand[k];
+            double v = 0;
+            if (h >= 0) {
+                size_t i = (size_t)r * L.Hp + h;
+                v = L.esz == 8 ? reinterpret_cast<double*>(buf.data())[i] : (double)reinterpret_cast<float*>(buf.data())[i];
+            }
+            out[(size_t)r * kCombos + k] = v;
+        }
+    return PCFR_OK;
+}
+
+}  // namespace pcfr
+
+extern "C" {
+
+int32_t pcfr_solver_workspace_bytes(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, size_t* bytes) {
+    if (!tree || !cfg || !bytes) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (cfg->dtype != PCFR_F32 && cfg->dtype != PCFR_F64) { set_error("dtype must be PCFR_F32 or PCFR_F64"); return PCFR_E_INVALID_ARG; }
+    Prepared P;
+    int32_t rc;
+    try { rc = prepare(tree->t, P); } catch (const std::bad_alloc&) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
+    if (rc != PCFR_OK) return rc;
+    Plan L;
+    make_plan(P, tree->t, cfg->dtype, L);
+    *bytes = L.total;
+    return PCFR_OK;
+}
+
+int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, const double* ranges, void* workspace,
+                           size_t workspace_bytes, void* stream, pcfr_solver** out) {
+    if (!tree || !cfg || !ranges || !workspace || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (cfg->dtype != PCFR_F32 && cfg->dtype != PCFR_F64) { set_error("dtype must be PCFR_F32 or PCFR_F64"); return PCFR_E_INVALID_ARG; }
+    if (cfg->variant != PCFR_DCFR) { set_error("only the DCFR update is implemented"); return PCFR_E_UNSUPPORTED; }
+    if (cfg->alternating != 0) { set_error("only simultaneous updates are implemented"); return PCFR_E_UNSUPPORTED; }
+    if (!std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta) || !std::isfinite(cfg->gamma)) {
+        set_error("alpha, beta, gamma must be finite");
+        return PCFR_E_INVALID_ARG;
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) { set_error("workspace must be 256-byte aligned"); return PCFR_E_INVALID_ARG; }
+    pcfr_solver* s = new (std::nothrow) pcfr_solver;
+    if (!s) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
+    std::unique_ptr<pcfr_solver> guard(s);
+    try {
+        s->tree = tree->t;
+        int32_t rc = prepare(s->tree, s->P);
+        if (rc != PCFR_OK) return rc;
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return PCFR_E_OUT_OF_MEMORY;
+    }
+    s->cfg = *cfg;
+    make_plan(s->P, s->tree, cfg->dtype, s->L);
+    const Plan& L = s->L;
+    if (workspace_bytes < L.total) { set_error("workspace smaller than pcfr_solver_workspace_bytes"); return PCFR_E_OUT_OF_MEMORY; }
+    if (L.lds_bytes > 65536) { set_error("hand count too large for the showdown kernel"); return PCFR_E_TOO_LARGE; }
+    // ranges
+    const ComboTable& cc = combos();
+    double mass[2] = {0, 0};
+    for (int p = 0; p < 2; p++)
+        for (int k = 0; k < kCombos; k++) {
+            double v = ranges[p * kCombos + k];
+            if (!std::isfinite(v) || v < 0) { set_error("ranges must be finite and >= 0"); return PCFR_E_INVALID_ARG; }
+            if (s->P.combo_hand[k] < 0 && v != 0) { set_error("range mass on a combo blocked by the board"); return PCFR_E_INVALID_ARG; }
+            s->ranges[p][k] = v;
+            mass[p] += v;
+        }
+    // joint mass of compatible pairs: r0 . (total1 - per-card sums + r1)
+    {
+        double card1[52] = {0};
+        for (int k = 0; k < kCombos; k++) { card1[cc.hi[k]] += s->ranges[1][k]; card1[cc.lo[k]] += s->ranges[1][k]; }
+        double z = 0;
+        for (int k = 0; k < kCombos; k++) {
+            if (s->ranges[0][k] == 0) continue;
+            z += s->ranges[0][k] * (mass[1] - card1[cc.hi[k]] - card1[cc.lo[k]] + s->ranges[1][k]);
+        }
+        s->pair_mass = z;
+        if (!(z > 0)) { set_error("no compatible pair of hands carries mass"); return PCFR_E_INVALID_ARG; }
+    }
+    s->stream = reinterpret_cast<hipStream_t>(stream);
+    s->ws = reinterpret_cast<char*>(workspace);
+    const Prepared& P = s->P;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> int32_t {
+        if (!bytes) return PCFR_OK;
+        return hip_check(hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream), "upload");
+    };
+    int32_t rc;
+    if ((rc = up(L.off_nodes, P.nodes.data(), sizeof(DNode) * P.nodes.size()))) return rc;
+    if ((rc = up(L.off_fwd, P.fwd.data(), sizeof(int32_t) * P.fwd.size()))) return rc;
+    if ((rc = up(L.off_term, P.term.data(), sizeof(int32_t) * P.term.size()))) return rc;
+    if ((rc = up(L.off_hc, P.hcards.data(), sizeof(uint16_t) * P.hcards.size()))) return rc;
+    if ((rc = up(L.off_coff, P.coff.data(), sizeof(int32_t) * P.coff.size()))) return rc;
+    if ((rc = up(L.off_chands, P.chands.data(), sizeof(int16_t) * P.chands.size()))) return rc;
+    if ((rc = up(L.off_sd, P.sd.data(), sizeof(int16_t) * L.n_boards * L.sd_stride))) return rc;
+    if ((rc = up(L.off_sdn, P.sdn.data(), sizeof(int32_t) * L.n_boards))) return rc;
+    HIPCHK(hipMemsetAsync(s->ws + L.off_state, 0, sizeof(IterState), s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_R, 0, L.esz * L.rows * L.Hp, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_S, 0, L.esz * L.rows * L.Hp, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_reach, 0, L.esz * L.N * 2 * L.Hp, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_cfv, 0, L.esz * L.N * 2 * L.Hp, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_root, 0, L.esz * 2 * L.Hp, s->stream));
+    // root reach = ranges in hand order (node 0's reach slot, never written again)
+    {
+        std::vector<char> rr(L.esz * 2 * L.Hp, 0);
+        for (int p = 0; p < 2; p++)
+            for (int64_t h = 0; h < P.H; h++) {
+                double v = s->ranges[p][P.hand_combo[h]];
+                size_t i = (size_t)p * L.Hp + h;
+                if (L.esz == 8) reinterpret_cast<double*>(rr.data())[i] = v;
+                else reinterpret_cast<float*>(rr.data())[i] = (float)v;
+            }
+        if ((rc = up(L.off_reach, rr.data(), rr.size()))) return rc;
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    if ((rc = build_graph(s))) return rc;
+    *out = guard.release();
+    return PCFR_OK;
+}
+
+int32_t pcfr_solver_free(pcfr_solver* s) {
+    if (!s) return PCFR_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    if (s->graph_def) (void)hipGraphDestroy(s->graph_def);
+    delete s;
+    return PCFR_OK;
+}
+
+int32_t pcfr_cfr_iterate(pcfr_solver* s, int32_t n) {
+    if (!s || n < 0) { set_error("null solver or negative count"); return PCFR_E_INVALID_ARG; }
+    for (int32_t i = 0; i < n; i++) HIPCHK(hipGraphLaunch(s->graph, s->stream));
+    s->t_host += n;
+    return PCFR_OK;
+}
+
+int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* launches) {
+    if (!s || n < 0 || !ms || !launches) { set_error("null argument or negative count"); return PCFR_E_INVALID_ARG; }
+    for (int k = 0; k < 4; k++) { ms[k] = 0; launches[k] = 0; }
+    for (int32_t i = 0; i < n; i++) {
+        LaunchTimer tm;
+        tm.stream = s->stream;
+        int32_t rc = s->cfg.dtype == PCFR_F64 ? enqueue_sweep<double, MODE_ITER>(s, s->stream, &tm)
+                                              : enqueue_sweep<float, MODE_ITER>(s, s->stream, &tm);
+        hipError_t e = hipStreamSynchronize(s->stream);
+        for (size_t k = 0; k < tm.cls.size(); k++) {
+            float t = 0;
+            if (e == hipSuccess && rc == PCFR_OK) (void)hipEventElapsedTime(&t, tm.ev[2 * k], tm.ev[2 * k + 1]);
+            ms[tm.cls[k]] += t;
+            launches[tm.cls[k]]++;
+        }
+        for (auto ev : tm.ev) (void)hipEventDestroy(ev);
+        if (rc) return rc;
+        HIPCHK(e);
+    }
+    s->t_host += n;
+    return PCFR_OK;
+}
+
+int32_t pcfr_synchronize(pcfr_solver* s) {
+    if (!s) { set_error("null solver"); return PCFR_E_INVALID_ARG; }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return PCFR_OK;
+}
+
+int32_t pcfr_iteration(pcfr_solver* s, int64_t* t) {
+    if (!s || !t) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    IterState st;
+    HIPCHK(hipMemcpyAsync(&st, s->ws + s->L.off_state, sizeof(st), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    *t = st.t;
+    return PCFR_OK;
+}
+
+int32_t pcfr_get_strategy(pcfr_solver* s, int32_t node, int32_t which, double* out) {
+    if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (which != PCFR_AVG && which != PCFR_CURRENT) { set_error("which must be PCFR_AVG or PCFR_CURRENT"); return PCFR_E_INVALID_ARG; }
+    if (node < 0 || node >= (int32_t)s->P.nodes.size() || s->P.nodes[node].type != PCFR_NODE_DECISION) {
+        set_error("node is not a decision node");
+        return PCFR_E_INVALID_ARG;
+    }
+    const DNode& d = s->P.nodes[node];
+    const Plan& L = s->L;
+    void* stage = s->ws + L.off_stage;
+    dim3 grid((unsigned)((L.Hp + 255) / 256));
+    if (L.esz == 8)
+        hipLaunchKernelGGL((k_strategy<double>), grid, dim3(256), 0, s->stream,
+                           s->at<double>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
+                           which == PCFR_CURRENT ? 1 : 0, (double*)stage);
+    else
+        hipLaunchKernelGGL((k_strategy<float>), grid, dim3(256), 0, s->stream,
+                           s->at<float>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
+                           which == PCFR_CURRENT ? 1 : 0, (float*)stage);
+    HIPCHK(hipGetLastError());
+    int32_t rc = fetch_hands(s, stage, d.n_child, out);
+    if (rc) return rc;
+    for (int a = 0; a < d.n_child; a++)
+        for (int k = 0; k < kCombos; k++)
+            if (s->P.combo_hand[k] < 0) out[(size_t)a * kCombos + k] = 0;
+    return PCFR_OK;
+}
+
+int32_t pcfr_get_root_cfv(pcfr_solver* s, int32_t which, double* out) {
+    if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (which == PCFR_CURRENT) return fetch_hands(s, s->ws + s->L.off_root, 2, out);
+    if (which != PCFR_AVG) { set_error("which must be PCFR_AVG or PCFR_CURRENT"); return PCFR_E_INVALID_ARG; }
+    int32_t rc = sweep<MODE_EV>(s);
+    if (rc) return rc;
+    return fetch_hands(s, s->ws + s->L.off_cfv, 2, out);
+}
+
+int32_t pcfr_exploitability(pcfr_solver* s, double* chips_per_hand, double* br) {
+    if (!s || !chips_per_hand) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    int32_t rc = sweep<MODE_BR>(s);
+    if (rc) return rc;
+    std::vector<double> v(2 * kCombos);
+    if ((rc = fetch_hands(s, s->ws + s->L.off_cfv, 2, v.data()))) return rc;
+    double b[2] = {0, 0};
+    for (int p = 0; p < 2; p++)
+        for (int k = 0; k < kCombos; k++) b[p] += s->ranges[p][k] * v[(size_t)p * kCombos + k];
+    b[0] /= s->pair_mass;
+    b[1] /= s->pair_mass;
+    if (!std::isfinite(b[0]) || !std::isfinite(b[1])) { set_error("non-finite best-response value"); return PCFR_E_NUMERIC; }
+    *chips_per_hand = 0.5 * (b[0] + b[1]);
+    if (br) { br[0] = b[0]; br[1] = b[1]; }
+    return PCFR_OK;
+}
+
+int32_t pcfr_state_bytes(pcfr_solver* s, size_t* bytes) {
+    if (!s || !bytes) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    *bytes = 16 + 2 * s->L.esz * s->L.rows * s->L.Hp;
+    return PCFR_OK;
+}
+
+int32_t pcfr_save_state(pcfr_solver* s, void* buf, size_t bytes) {
+    size_t need;
+    if (!s || !buf) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    pcfr_state_bytes(s, &need);
+    if (bytes < need) { set_error("state buffer too small"); return PCFR_E_INVALID_ARG; }
+    const Plan& L = s->L;
+    IterState st;
+    char* b = reinterpret_cast<char*>(buf);
+    size_t rb = L.esz * L.rows * L.Hp;
+    HIPCHK(hipMemcpyAsync(&st, s->ws + L.off_state, sizeof(st), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(b + 16, s->ws + L.off_R, rb, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(b + 16 + rb, s->ws + L.off_S, rb, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    int64_t hdr[2] = {st.t, (int64_t)L.esz};
+    std::memcpy(b, hdr, 16);
+    return PCFR_OK;
+}
+
+int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes) {
+    size_t need;
+    if (!s || !buf) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    pcfr_state_bytes(s, &need);
+    if (bytes < need) { set_error("state buffer too small"); return PCFR_E_INVALID_ARG; }
+    const Plan& L = s->L;
+    const char* b = reinterpret_cast<const char*>(buf);
+    int64_t hdr[2];
+    std::memcpy(hdr, b, 16);
+    if (hdr[1] != (int64_t)L.esz || hdr[0] < 0) { set_error("state was saved with another dtype"); return PCFR_E_INVALID_ARG; }
+    size_t rb = L.esz * L.rows * L.Hp;
+    IterState st{};
+    st.t = hdr[0];
+    HIPCHK(hipMemcpyAsync(s->ws + L.off_state, &st, sizeof(st), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->ws + L.off_R, b + 16, rb, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->ws + L.off_S, b + 16 + rb, rb, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return PCFR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+"""Python binding of ``libpcfr.so`` (argument marshalling only).
+
+Every step of a CFR iteration runs in the library's HIP kernels; this module
+only converts arguments, owns the device workspace as a torch tensor, and
+passes torch's current stream.  If the built library is missing, importing
+the binding raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcfr.so")
+NCOMBO = 1326
+
+OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_DEVICE, E_STATE, E_UNSUPPORTED, E_NUMERIC, E_TOO_LARGE = range(8)
+F32, F64 = 0, 1
+AVG, CURRENT = 0, 1
+DCFR, CFRPLUS, PCFRPLUS = 0, 1, 2
+NODE_DECISION, NODE_FOLD, NODE_SHOWDOWN, NODE_CHANCE, NODE_LEAF, NODE_ALLIN_LEAF = range(6)
+
+
+class PcfrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pcfr error {code}: {msg}")
+        self.code = code
+
+
+class TreeSpec(C.Structure):
+    _fields_ = [("n_board", C.c_int32), ("board", C.c_int32 * 5), ("pot", C.c_int64),
+                ("stack", C.c_int64 * 2), ("n_sizes", C.c_int32), ("size_pct", C.c_int32 * 8),
+                ("allin", C.c_int32), ("max_raises", C.c_int32), ("depth_limit", C.c_int32)]
+
+
+class SolverCfg(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("variant", C.c_int32), ("alpha", C.c_double),
+                ("beta", C.c_double), ("gamma", C.c_double), ("alternating", C.c_int32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "pcfr_abi_version": (C.c_int32, []),
+    "pcfr_last_error": (C.c_char_p, []),
+    "pcfr_build_tree": (C.c_int32, [C.POINTER(TreeSpec), C.POINTER(C.c_void_p)]),
+    "pcfr_tree_free": (C.c_int32, [C.c_void_p]),
+    "pcfr_tree_info": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_tree_export": (C.c_int32, [C.c_void_p] * 10),
+    "pcfr_eval7_batch": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "pcfr_solver_workspace_bytes": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.POINTER(C.c_size_t)]),
+    "pcfr_solver_create": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.c_void_p, C.c_void_p, C.c_size_t,
+                                       C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pcfr_solver_free": (C.c_int32, [C.c_void_p]),
+    "pcfr_cfr_iterate": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "pcfr_synchronize": (C.c_int32, [C.c_void_p]),
+    "pcfr_profile_iterations": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "pcfr_iteration": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "pcfr_get_strategy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "pcfr_get_root_cfv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "pcfr_exploitability": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "pcfr_state_bytes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "pcfr_save_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "pcfr_load_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+}
+
+
+def lib():
+    """Load the built library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_19928_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise PcfrError(rc, lib().pcfr_last_error().decode(errors="replace"))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def eval7_batch(cards) -> np.ndarray:
+    a = np.ascontiguousarray(cards, dtype=np.int32).reshape(-1, 7)
+    out = np.empty(a.shape[0], dtype=np.int32)
+    _check(lib().pcfr_eval7_batch(_p(a), a.shape[0], _p(out)))
+    return out
+
+
+class Tree:
+    """Public tree of a subgame, built on the host by the library."""
+
+    def __init__(self, board, pot, stacks, sizes, allin=True, max_raises=2, depth_limit=0):
+        sp = TreeSpec()
+        sp.n_board = len(board)
+        for i, c in enumerate(board):
+            sp.board[i] = int(c)
+        sp.pot = int(pot)
+        sp.stack[0], sp.stack[1] = int(stacks[0]), int(stacks[1])
+        if len(sizes) > 8:
+            raise ValueError("at most 8 bet sizes")
+        sp.n_sizes = len(sizes)
+        for i, s in enumerate(sizes):
+            sp.size_pct[i] = int(s)
+        sp.allin, sp.max_raises, sp.depth_limit = int(allin), int(max_raises), int(depth_limit)
+        h = C.c_void_p()
+        _check(lib().pcfr_build_tree(C.byref(sp), C.byref(h)))
+        self._h = h
+        self.spec = dict(board=list(board), pot=pot, stacks=tuple(stacks), sizes=list(sizes), allin=allin,
+                         max_raises=max_raises, depth_limit=depth_limit)
+        info = np.zeros(16, dtype=np.int64)
+        _check(lib().pcfr_tree_info(self._h, _p(info)))
+        (self.n_nodes, self.n_decision, self.n_fold, self.n_showdown, self.n_chance, self.n_leaf,
+         self.n_allin, self.n_levels, self.n_rows, self.n_hands, self.n_hands_padded) = (int(x) for x in info[:11])
+
+    def export(self) -> dict:
+        n = self.n_nodes
+        out = {k: np.zeros(n, dtype=np.int32) for k in
+               ("type", "player", "parent", "action", "depth", "chance_card", "first_child", "n_child")}
+        out["contrib"] = np.zeros((n, 2), dtype=np.int64)
+        _check(lib().pcfr_tree_export(self._h, _p(out["type"]), _p(out["player"]), _p(out["parent"]),
+                                      _p(out["action"]), _p(out["depth"]), _p(out["contrib"]),
+                                      _p(out["chance_card"]), _p(out["first_child"]), _p(out["n_child"])))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pcfr_tree_free(h)
+            self._h = None
+
+
+@dataclass
+class SolverConfig:
+    dtype: str = "f32"
+    alpha: float = 1.5
+    beta: float = 0.0
+    gamma: float = 2.0
+    variant: int = DCFR
+    alternating: int = 0
+
+    def to_c(self) -> SolverCfg:
+        c = SolverCfg()
+        c.dtype = F64 if self.dtype == "f64" else F32
+        c.variant, c.alpha, c.beta, c.gamma, c.alternating = (self.variant, self.alpha, self.beta, self.gamma,
+                                                             self.alternating)
+        return c
+
+
+class Solver:
+    """DCFR solver on the GPU.  The workspace is a torch uint8 tensor on
+    ``device``; work is enqueued on torch's current stream of that device."""
+
+    def __init__(self, tree: Tree, ranges, cfg: SolverConfig | None = None, device="cuda"):
+        import torch
+
+        self.tree = tree
+        self.cfg = cfg or SolverConfig()
+        c = self.cfg.to_c()
+        self._cfg_c = c
+        nbytes = C.c_size_t()
+        _check(lib().pcfr_solver_workspace_bytes(tree._h, C.byref(c), C.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self.ws.data_ptr()
+        ptr = (ptr + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, NCOMBO)
+        self._ranges = r
+        h = C.c_void_p()
+        _check(lib().pcfr_solver_create(tree._h, C.byref(c), _p(r), C.c_void_p(ptr),
+                                        self.workspace_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self._nchild = tree.export()["n_child"]
+
+    def iterate(self, n: int):
+        _check(lib().pcfr_cfr_iterate(self._h, int(n)))
+
+    def profile(self, n: int):
+        """Run n iterations with per-launch event timing; returns (ms[4], launches[4])
+        for the classes bookkeeping, forward, terminal, backward."""
+        ms = np.zeros(4, dtype=np.float64)
+        cnt = np.zeros(4, dtype=np.int64)
+        _check(lib().pcfr_profile_iterations(self._h, int(n), _p(ms), _p(cnt)))
+        return ms, cnt
+
+    def synchronize(self):
+        _check(lib().pcfr_synchronize(self._h))
+
+    @property
+    def t(self) -> int:
+        v = C.c_int64()
+        _check(lib().pcfr_iteration(self._h, C.byref(v)))
+        return int(v.value)
+
+    def strategy(self, node: int, which: str = "avg") -> np.ndarray:
+        A = int(self._nchild[node])
+        out = np.zeros((max(A, 1), NCOMBO), dtype=np.float64)
+        _check(lib().pcfr_get_strategy(self._h, int(node), AVG if which == "avg" else CURRENT, _p(out)))
+        return out
+
+    def root_cfv(self, which: str = "current") -> np.ndarray:
+        out = np.zeros((2, NCOMBO), dtype=np.float64)
+        _check(lib().pcfr_get_root_cfv(self._h, CURRENT if which == "current" else AVG, _p(out)))
+        return out
+
+    def exploitability(self):
+        e = C.c_double()
+        br = np.zeros(2, dtype=np.float64)
+        _check(lib().pcfr_exploitability(self._h, C.byref(e), _p(br)))
+        return float(e.value), br
+
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().pcfr_state_bytes(self._h, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        _check(lib().pcfr_save_state(self._h, buf, n.value))
+        return bytes(buf)
+
+    def load_state(self, blob: bytes):
+        buf = (C.c_char * len(blob)).from_buffer_copy(blob)
+        _check(lib().pcfr_load_state(self._h, buf, len(blob)))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pcfr_solver_free(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,233 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+Tolerances (values in pot units, i.e. chips / root pot):
+* FP64 solver: 1e-9 on root counterfactual values, average and current
+  strategies, and exploitability.
+* FP32 solver: 1e-4 on root counterfactual values and exploitability, and on
+  average strategies where the hand's own average-strategy mass at the node is
+  at least 1e-3 of the node's largest (elsewhere the strategy of a hand that
+  never reaches the node is decided by float rounding near regret-matching
+  ties); the ungated maximum is printed.
+Each case prints its name, seed and shape before running on the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_19928_amd import inputs as I
+from paper_2605_19928_amd import pcfr as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_oracle(spec, r, T, support_only=False):
+    t = O.Tree.holdem(**spec)
+    s = O.Solver(t, r, support_only=support_only)
+    s.iterate(T)
+    return t, s
+
+
+def run_gpu(spec, r, T, dtype):
+    t = P.Tree(**spec)
+    s = P.Solver(t, r, P.SolverConfig(dtype=dtype))
+    s.iterate(T)
+    s.synchronize()
+    return t, s
+
+
+def decision_nodes(tree):
+    e = tree.export()
+    return [int(n) for n in np.flatnonzero(e["type"] == P.NODE_DECISION)]
+
+
+def compare(spec, r, T, dtype, support_only=False, check_current=None):
+    pot = spec["pot"]
+    say(f"case: board={spec['board']} pot={pot} stacks={spec['stacks']} sizes={spec['sizes']} "
+        f"T={T} dtype={dtype} support_only={support_only}")
+    ot, os_ = run_oracle(spec, r, T, support_only)
+    gt, gs = run_gpu(spec, r, T, dtype)
+    assert gs.t == T
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    mask = (r > 0) if support_only else np.ones_like(r, dtype=bool)
+    mask &= ~I.blocked_mask(spec["board"])[None, :]
+    # root counterfactual values of the last iteration
+    dv = np.abs(gs.root_cfv("current") - os_.root_cfv("current"))[mask] / pot
+    say(f"  root cfv (current) max |d| = {dv.max():.3e} pot")
+    assert dv.max() <= tol
+    # strategies at every decision node
+    worst_gated, worst = 0.0, 0.0
+    S = os_.rows("S")
+    e = ot.export()
+    rs = np.concatenate([[0], np.cumsum(np.where(e["type"] == O.T_DEC, e["n_child"], 0))])
+    for n in decision_nodes(gt):
+        g, o = gs.strategy(n, "avg"), os_.strategy(n, "avg")
+        pl = int(e["player"][n])
+        own = mask[pl]
+        d = np.abs(g - o)[:, own]
+        worst = max(worst, float(d.max()))
+        mass = S[rs[n]:rs[n] + e["n_child"][n]].sum(axis=0)[own]
+        gate = mass >= 1e-3 * max(mass.max(), 1e-300)
+        if gate.any():
+            worst_gated = max(worst_gated, float(d[:, gate].max()))
+        if dtype == "f64":
+            assert d.max() <= tol, (n, d.max())
+            c = np.abs(gs.strategy(n, "current") - os_.strategy(n, "current"))[:, own]
+            assert c.max() <= tol, (n, c.max())
+    say(f"  avg strategy max |d| = {worst:.3e} (reach-gated {worst_gated:.3e})")
+    assert worst_gated <= tol
+    if not support_only:
+        eg, brg = gs.exploitability()
+        eo, bro = os_.exploitability()
+        say(f"  exploitability gpu={eg:.9f} oracle={eo:.9f} chips")
+        assert abs(eg - eo) / pot <= tol
+        np.testing.assert_allclose(brg / pot, bro / pot, atol=tol)
+        av = np.abs(gs.root_cfv("avg") - os_.root_cfv("avg"))[mask] / pot
+        say(f"  root cfv (avg) max |d| = {av.max():.3e} pot")
+        assert av.max() <= tol
+    return gs, os_
+
+
+# ---------------------------------------------------------------- river
+def test_river_full_ranges_f64():
+    spec, r = I.river_config(0)
+    compare(spec, r, 24, "f64")
+
+
+def test_river_full_ranges_f32():
+    spec, r = I.river_config(0)
+    compare(spec, r, 24, "f32")
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_river_sparse_200_iterations(seed):
+    spec, r = I.river_config(seed, support=150)
+    compare(spec, r, 200, "f64")
+    compare(spec, r, 200, "f32")
+
+
+def test_river_single_hands_and_no_bets():
+    rng = np.random.default_rng(5)
+    board = I.draw_board(rng, 5)
+    ok = np.flatnonzero(~I.blocked_mask(board))
+    r = np.zeros((2, 1326))
+    r[0, ok[0]] = 1.0
+    r[1, ok[-1]] = 1.0
+    spec = dict(board=board, pot=20, stacks=(0, 0), sizes=[], allin=False, max_raises=0, depth_limit=0)
+    compare(spec, r, 5, "f64")
+    spec = dict(board=board, pot=20, stacks=(90, 90), sizes=[100], allin=True, max_raises=3, depth_limit=0)
+    compare(spec, r, 30, "f64")
+
+
+# ---------------------------------------------------------------- turn
+@pytest.mark.parametrize("seed,spr,support", [(1, 1, 64), (2, 2, 48)])
+def test_turn_sparse_support(seed, spr, support):
+    spec, r = I.turn_config(seed, support=support, spr=spr)
+    compare(spec, r, 40, "f64", support_only=True)
+    compare(spec, r, 40, "f32", support_only=True)
+
+
+def test_turn_full_size_first_iteration_sampled_hands():
+    """The benchmark's turn workload at full size, checked on sampled hands
+    after one iteration from the initial state (the oracle evaluates those
+    hands history by history against the full opponent range)."""
+    spec, r = I.turn_config(0)
+    say(f"case: full-size turn {spec}")
+    gt, gs = run_gpu(spec, r, 1, "f32")
+    ot = O.Tree.holdem(**spec)
+    os_ = O.Solver(ot, r)
+    rng = np.random.default_rng(0)
+    ok = np.flatnonzero(~I.blocked_mask(spec["board"]))
+    pick = np.sort(rng.choice(ok, 6, replace=False))
+    m = np.zeros((2, 1326), dtype=np.uint8)
+    m[:, pick] = 1
+    os_.set_traverser_hands(m)
+    os_.iterate(1)
+    g = gs.root_cfv("current")[:, pick]
+    o = os_.root_cfv("current")[:, pick]
+    d = np.abs(g - o).max() / spec["pot"]
+    say(f"  sampled root cfv max |d| = {d:.3e} pot")
+    assert d <= 1e-4
+
+
+def test_turn_full_size_invariants():
+    spec, r = I.turn_config(0)
+    say(f"case: full-size turn invariants {spec}")
+    gt, gs = run_gpu(spec, r, 0, "f32")
+    prev = None
+    for T in (1, 5, 20):
+        gs.iterate(T - gs.t)
+        v = gs.root_cfv("current")
+        total = (r[0] * v[0]).sum() + (r[1] * v[1]).sum()
+        scale = np.abs(r[0] * v[0]).sum() + np.abs(r[1] * v[1]).sum()
+        assert abs(total) <= 1e-5 * scale
+        e, br = gs.exploitability()
+        av = gs.root_cfv("avg")
+        gv = (r[0] * av[0]).sum() / sum_pairs(r)
+        assert br[0] >= gv - 1e-4 * spec["pot"] and br[1] >= -gv - 1e-4 * spec["pot"]
+        if prev is not None:
+            assert e < prev
+        prev = e
+        for n in (0, 1, 7):
+            s = gs.strategy(n, "avg")
+            ok = ~I.blocked_mask(spec["board"])
+            np.testing.assert_allclose(s.sum(axis=0)[ok], 1.0, atol=1e-5)
+
+
+def sum_pairs(r):
+    cc = I.combo_cards()
+    card = np.zeros((2, 52))
+    for p in range(2):
+        np.add.at(card[p], cc[:, 0], r[p])
+        np.add.at(card[p], cc[:, 1], r[p])
+    m1 = r[1].sum() - card[1][cc[:, 0]] - card[1][cc[:, 1]] + r[1]
+    return float((r[0] * m1).sum())
+
+
+# ---------------------------------------------------------------- runtime
+def test_checkpoint_resume_is_bitwise():
+    spec, r = I.turn_config(2, spr=1)
+    t = P.Tree(**spec)
+    a = P.Solver(t, r)
+    a.iterate(10)
+    blob = a.save_state()
+    a.iterate(10)
+    b = P.Solver(t, r)
+    b.load_state(blob)
+    assert b.t == 10
+    b.iterate(10)
+    assert a.t == b.t == 20
+    np.testing.assert_array_equal(a.strategy(0, "avg"), b.strategy(0, "avg"))
+    np.testing.assert_array_equal(a.strategy(5, "current"), b.strategy(5, "current"))
+    assert a.save_state() == b.save_state()
+
+
+def test_run_to_run_deterministic():
+    spec, r = I.river_config(3)
+    out = []
+    for _ in range(2):
+        t = P.Tree(**spec)
+        s = P.Solver(t, r)
+        s.iterate(15)
+        out.append((s.save_state(), s.root_cfv("current").tobytes()))
+    assert out[0] == out[1]
+
+
+def test_invalid_inputs_on_device():
+    spec, r = I.river_config(0)
+    t = P.Tree(**spec)
+    bad = r.copy()
+    bad[0, np.flatnonzero(I.blocked_mask(spec["board"]))[0]] = 0.1
+    with pytest.raises(P.PcfrError) as e:
+        P.Solver(t, bad)
+    assert e.value.code == P.E_INVALID_ARG
+    bad = r.copy()
+    bad[1, 5] = np.nan
+    with pytest.raises(P.PcfrError):
+        P.Solver(t, bad)
+    s = P.Solver(t, r)
+    with pytest.raises(P.PcfrError):
+        s.strategy(int(np.flatnonzero(t.export()["type"] == P.NODE_FOLD)[0]))
