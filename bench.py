@@ -1,16 +1,27 @@
 #!/usr/bin/env python3
 """DCFR iterations per second on one MI355X.
 
-A step is one full DCFR iteration of the solver (regret matching, forward
-reach, fold and showdown terminals, chance averaging, backward values, regret
-and average-strategy update) over one subgame whose regret and
-average-strategy tables live in HBM.
+A step is one full DCFR iteration of the solver over one subgame, with every
+stage on the GPU: regret matching and forward reach, fold terminals, exact
+all-in leaves, the batched leaf-network evaluation (input build, bf16 MFMA
+GEMMs, chance-weighted combine), backward values, regret and
+average-strategy updates.
 
-Default workload: a turn subgame solved to showdown -- seeded 4-card board,
-Dirichlet(1) ranges over the 1128 compatible combos, pot log-uniform in
-[20, 400] and stack-to-pot ratio uniform in [1, 8] (seed 0 draws pot 166,
-stacks 1006), bet sizes {33, 75, 150}% of the pot plus all-in, at most 3
-bets/raises per street, FP32.
+Default workload (``--workload flop``): the depth-limited flop subgame --
+seeded 3-card board, Dirichlet(1) ranges over the 1176 compatible combos, pot
+100, stacks 400, bet sizes {33, 75}% of the pot plus all-in, at most 3
+bets/raises, leaves at the turn card: 36 decision nodes, 21 network leaves x
+49 turn cards = 1029 network rows per iteration, 14 exact all-in leaves.
+Leaf network 2705 -> 4 x 1536 -> 2652 (ReLU), bf16 weights, FP32 accumulate;
+random He-initialised weights (no trained weights ship with the benchmark).
+Tree arithmetic FP32.
+
+Secondary workload (``--workload turn``, and reported inside the flop line
+as ``tree_sweep``): a turn subgame solved to showdown -- seeded 4-card board,
+Dirichlet(1) ranges, pot 166, stacks 1006 (seed 0 of pot log-uniform in
+[20, 400] and stack-to-pot uniform in [1, 8]), sizes {33, 75, 150}% +
+all-in, at most 3 per street: 77,529 nodes, 74,312 action rows, FP32.  Its
+685 MB of regret and average-strategy state is the HBM-bound part.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the solver runs on one
 GPU.
@@ -19,13 +30,14 @@ from __future__ import annotations
 
 import argparse
 import json
-import os
 import sys
 import time
 
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+CLASSES = ["bookkeeping", "forward", "terminal", "backward", "leaves", "leaf_gemm"]
 
 
 def parse():
@@ -34,29 +46,36 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", default="flop", choices=["flop", "turn"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--profile-iters", type=int, default=5)
+    ap.add_argument("--no-secondary", action="store_true", help="skip the turn tree-sweep measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
+
+
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
 
 
 def pair_count(r0, r1, cc):
     """Number of (hand, opponent hand) pairs with mass on both sides that share no card."""
     a = np.flatnonzero(r0 > 0)
     b = np.flatnonzero(r1 > 0)
-    ca = cc[a]
-    cb = cc[b]
+    ca, cb = cc[a], cc[b]
     clash = ((ca[:, 0:1] == cb[None, :, 0]) | (ca[:, 0:1] == cb[None, :, 1]) |
              (ca[:, 1:2] == cb[None, :, 0]) | (ca[:, 1:2] == cb[None, :, 1]))
     return int((~clash).sum())
 
 
-def cpu_baseline(spec, r, budget_s):
+def cpu_baseline(spec, r, budget_s, leaf_params=None):
     """Time the FP64 oracle on the same tree with sparse-support ranges at two
     support sizes, fit time = fixed + per_pair * pairs, and extrapolate to the
-    full ranges' pair count."""
+    full ranges' pair count.  With a leaf network, each oracle iteration also
+    builds the leaf inputs and runs the FP64 network (its cost is in `fixed`)."""
     import oracle as O
+    from oracle import mlp
     from paper_2605_19928_amd import inputs as I
 
     cc = I.combo_cards()
@@ -64,6 +83,9 @@ def cpu_baseline(spec, r, budget_s):
     full_pairs = 2 * pair_count(r[0], r[1], cc)
     rng = np.random.default_rng(1234)
     ok = np.flatnonzero(~I.blocked_mask(spec["board"]))
+    e = t.export()
+    leaves = np.flatnonzero(e["type"] == O.T_LEAF)
+    eff = min(spec["stacks"])
     pts = []
     for k in (8, 24):
         pick = np.sort(rng.choice(ok, k, replace=False))
@@ -72,6 +94,17 @@ def cpu_baseline(spec, r, budget_s):
         s = O.Solver(t, rs, support_only=True)
         n, t0 = 0, time.perf_counter()
         while True:
+            if leaf_params is not None and len(leaves):
+                reach = s.reach_current()
+                ev = np.zeros((len(leaves), 2, 52, 1326))
+                for li, node in enumerate(leaves):
+                    c = e["contrib"][node][0]
+                    cards, X = mlp.leaf_inputs(reach[node], spec["board"], 2 * c, spec["pot"] // 2 + eff - c, 2705)
+                    Y = mlp.forward(leaf_params, X, emulate_bf16=True)
+                    for kk, card in enumerate(cards):
+                        ev[li, 0, card] = Y[kk, :1326]
+                        ev[li, 1, card] = Y[kk, 1326:]
+                s.set_leaf_table(ev)
             s.iterate(1)
             n += 1
             el = time.perf_counter() - t0
@@ -89,9 +122,70 @@ def cpu_baseline(spec, r, budget_s):
         "cores": O.max_threads(),
         "kind": "oracle",
         "sample": (f"oracle on the same tree with random 8- and 24-combo supports per player "
-                   f"({pts[0][1]:.3f} and {pts[1][1]:.3f} s/iter over {pts[0][0]} and {pts[1][0]} hand pairs); "
-                   f"time = fixed + per-pair cost fitted and extrapolated to the full ranges' {full_pairs} pairs"),
+                   f"({pts[0][1]:.3f} and {pts[1][1]:.3f} s/iter over {pts[0][0]} and {pts[1][0]} hand pairs"
+                   + (", FP64 leaf network included" if leaf_params is not None else "")
+                   + f"); time = fixed + per-pair cost fitted and extrapolated to the full ranges' "
+                     f"{full_pairs} pairs"),
     }
+
+
+def he_params(shapes, seed):
+    rng = np.random.default_rng(seed)
+    return [((rng.standard_normal((o, i)) * np.sqrt(2.0 / i)).astype(np.float32), np.zeros(o, np.float32))
+            for o, i in shapes]
+
+
+def timed(solver, steps, warmup):
+    import torch
+
+    solver.iterate(warmup)
+    solver.synchronize()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(solver.stream)
+    solver.iterate(steps)
+    ev1.record(solver.stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def tree_sweep(args, seed, steps, warmup):
+    """Turn subgame to showdown: ms/iter and the backward kernel's HBM roofline."""
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+
+    spec, r = I.turn_config(seed)
+    log(f"building turn subgame seed={seed} {spec}")
+    tree = P.Tree(**spec)
+    solver = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
+    esz = 8 if args.dtype == "f64" else 4
+    alg_bytes = 4 * esz * tree.n_rows * tree.n_hands   # R and S, each read and written once
+    ms = timed(solver, steps, warmup)
+    pms, pl = solver.profile(args.profile_iters)
+    pms, pl = pms / args.profile_iters, pl // args.profile_iters
+    achieved = alg_bytes / (pms[3] * 1e-3) / 1e9
+    expl, _ = solver.exploitability()
+    out = {
+        "workload": f"turn subgame to showdown, seed {seed}",
+        "board": spec["board"], "pot": spec["pot"], "stacks": list(spec["stacks"]),
+        "nodes": tree.n_nodes, "decision_nodes": tree.n_decision, "chance_nodes": tree.n_chance,
+        "action_rows": tree.n_rows, "hands": tree.n_hands, "levels": tree.n_levels,
+        "state_bytes_R_S": 2 * esz * tree.n_rows * tree.n_hands_padded,
+        "ms_per_iter": ms, "iters_per_s": 1000.0 / ms,
+        "iteration_hbm_frac": (alg_bytes / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
+        "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
+        "exploitability_mbb_per_hand": expl * 100.0,
+        "roofline": {
+            "kernel": "k_backward<float,0> (values, DCFR regret and average-strategy update)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_us": 1e3 * pms[3] / max(pl[3], 1), "launches_per_iter": int(pl[3]),
+            "alg_bytes_per_iter": alg_bytes,
+        },
+    }
+    log(f"turn: {ms:.4f} ms/iter, kernels {out['kernel_ms_per_iter']}")
+    return out, spec, r
 
 
 def main():
@@ -99,47 +193,44 @@ def main():
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
-    import torch
-
     from paper_2605_19928_amd import inputs as I
     from paper_2605_19928_amd import pcfr as P
 
-    spec, r = I.turn_config(args.seed)
-    print(f"bench: building turn subgame seed={args.seed} {spec}", file=sys.stderr, flush=True)
+    if args.workload == "turn":
+        sweep, spec, r = tree_sweep(args, args.seed, args.steps, args.warmup)
+        result = {
+            "metric": "DCFR ms/iter & iters/sec, flop depth-limited subgame; exploitability mbb/hand",
+            "value": sweep["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": sweep["ms_per_iter"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+            "config": {k: v for k, v in sweep.items() if k not in ("roofline", "kernel_ms_per_iter")},
+            "roofline": sweep["roofline"],
+        }
+        if not args.no_cpu_baseline:
+            log("timing the CPU oracle on a bounded sample")
+            result["cpu_baseline"] = cpu_baseline(spec, r, args.cpu_seconds)
+        print(json.dumps(result), flush=True)
+        return
+
+    spec, r = I.flop_config(args.seed)
+    log(f"building depth-limited flop subgame seed={args.seed} {spec}")
     tree = P.Tree(**spec)
     solver = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
-    H = tree.n_hands
-    units = tree.n_rows * H                       # (action row, hand) pairs
-    esz = 8 if args.dtype == "f64" else 4
-    alg_bytes = 4 * esz * units                   # R and S, each read and written once
-
-    solver.iterate(args.warmup)
-    solver.synchronize()
-    stream = solver.stream
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    solver.iterate(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    ms = total_ms / args.steps
-    print(f"bench: {args.steps} steps in {total_ms:.2f} ms", file=sys.stderr, flush=True)
-
-    # per-kernel-class device time, launch by launch with HIP events
-    pms, plaunch = solver.profile(args.profile_iters)
-    pms = pms / args.profile_iters
-    plaunch = plaunch // args.profile_iters
-    names = ["bookkeeping", "forward", "terminal", "backward"]
-    dom = int(np.argmax(pms))
-    bwd_ms = pms[3]
-    bwd_avg_us = 1e3 * bwd_ms / max(plaunch[3], 1)
-    achieved = alg_bytes / (bwd_ms * 1e-3) / 1e9
-    expl, br = solver.exploitability()
-    print(f"bench: per-iteration kernel ms {dict(zip(names, np.round(pms, 4)))} launches {plaunch.tolist()}",
-          file=sys.stderr, flush=True)
-
+    n_leaves, n_next = solver.leaf_rows()
+    rows = n_leaves * n_next
+    net = P.LeafNet(P.LEAF_D_IN, 1536, 4, P.LEAF_D_OUT, max_batch=rows)
+    params = he_params(net.layer_shapes(), 7)
+    net.set_params(params)
+    solver.attach_leafnet(net)
+    flops_alg = 2.0 * rows * sum(o * i for o, i in net.layer_shapes())
+    ms = timed(solver, args.steps, args.warmup)
+    log(f"{args.steps} steps: {ms:.4f} ms/iter")
+    pms, pl = solver.profile(args.profile_iters)
+    pms, pl = pms / args.profile_iters, pl // args.profile_iters
+    gemm_ms = pms[5]
+    achieved = flops_alg / (gemm_ms * 1e-3) / 1e12
+    expl, _ = solver.exploitability()
+    log(f"kernel ms/iter {dict(zip(CLASSES, np.round(pms[:6], 4)))} launches {pl[:6].tolist()}")
     result = {
         "metric": "DCFR ms/iter & iters/sec, flop depth-limited subgame; exploitability mbb/hand",
         "value": 1000.0 / ms,
@@ -154,35 +245,38 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {
-            "workload": f"turn subgame to showdown, seed {args.seed}",
+            "workload": f"depth-limited flop subgame with leaf network, seed {args.seed}",
             "board": spec["board"], "pot": spec["pot"], "stacks": list(spec["stacks"]),
-            "spr": round(spec["stacks"][0] / spec["pot"], 3),
             "bet_sizes_pct": spec["sizes"], "allin": True, "max_raises_per_street": spec["max_raises"],
-            "nodes": tree.n_nodes, "decision_nodes": tree.n_decision, "chance_nodes": tree.n_chance,
-            "action_rows": tree.n_rows, "hands": H, "levels": tree.n_levels,
-            "state_bytes_R_S": 2 * esz * tree.n_rows * tree.n_hands_padded,
+            "nodes": tree.n_nodes, "decision_nodes": tree.n_decision, "network_leaves": n_leaves,
+            "allin_leaves": tree.n_allin, "next_cards": n_next, "network_rows": rows, "hands": tree.n_hands,
+            "leaf_network": "2705 -> 4 x 1536 -> 2652 ReLU MLP, bf16 weights, fp32 accumulate, He init",
+            "leaf_network_params": net.n_params,
+            "leaf_flops_per_iter": flops_alg,
         },
         "exploitability_mbb_per_hand": expl * 100.0,
-        "exploitability_after_iters": args.warmup + args.steps + args.profile_iters,
-        "iteration_hbm_frac": (alg_bytes / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
-        "kernel_ms_per_iter": dict(zip(names, [float(x) for x in pms])),
+        "exploitability_note": "of the average strategy within the depth-limited game, leaves valued by the network",
+        "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
         "roofline": {
-            "kernel": "k_backward (value + regret + average-strategy sweep)",
-            "dominant_kernel": names[dom],
-            "bound": "hbm",
+            "kernel": "k_gemm_nt (leaf network layers, bf16 MFMA 32x32x16)",
+            "bound": "mfma",
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "peak": BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / BF16_PEAK_TFLOPS,
             "traffic": None,
-            "avg_launch_us": bwd_avg_us,
-            "launches_per_iter": int(plaunch[3]),
-            "alg_bytes_per_iter": alg_bytes,
+            "avg_launch_us": 1e3 * gemm_ms / max(pl[5], 1),
+            "launches_per_iter": int(pl[5]),
+            "alg_flops_per_iter": flops_alg,
         },
     }
+    del solver, net
+    if not args.no_secondary:
+        sweep, _, _ = tree_sweep(args, 0, max(20, args.steps // 4), 5)
+        result["tree_sweep"] = sweep
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(spec, r, args.cpu_seconds)
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(spec, r, args.cpu_seconds, leaf_params=params)
     print(json.dumps(result), flush=True)
 
 

@@ -131,6 +131,14 @@ int32_t pcfr_tree_export(const pcfr_tree* tree, int32_t* type, int32_t* player, 
  * tie-breaking ranks in bits 16..19 down to 0..3. */
 int32_t pcfr_eval7_batch(const int32_t* cards, int64_t n, int32_t* out);
 
+/* Pairwise check-down equity on the tree's root board (3 or 4 cards): out
+ * [1326][1326] host doubles, out[h][o] = mean over every completion of the
+ * board by cards neither hand holds of sign(value(h) - value(o)); 0 for
+ * pairs sharing a card or touching the board.  This is the exact value per
+ * chip of contribution of an all-in depth-limit leaf (Sec. 3, depth-limited
+ * solving: leaves where nothing is left to decide are valued exactly). */
+int32_t pcfr_equity_table(const pcfr_tree* tree, double* out);
+
 /* ---------------------------------------------------------------- solver
  * Device memory is the caller's: ask for the size, allocate it, keep it alive
  * until pcfr_solver_free.  The solver copies the tree, so the tree may be
@@ -156,8 +164,10 @@ int32_t pcfr_synchronize(pcfr_solver* s);
 /* Run n iterations like pcfr_cfr_iterate, but launch by launch with HIP
  * events around every kernel on the solver's stream, and return the summed
  * device time and launch count per kernel class: [0] iteration bookkeeping,
- * [1] forward reach sweep, [2] terminal evaluation, [3] backward value and
- * regret sweep.  ms and launches are host arrays of 4.  Synchronises. */
+ * [1] forward reach sweep, [2] fold/showdown terminals, [3] backward value
+ * and regret sweep, [4] depth-limit leaves (exact equity, network input and
+ * combine), [5] leaf-network GEMMs, [6..7] unused.  ms and launches are host
+ * arrays of 8.  Synchronises. */
 int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* launches);
 int32_t pcfr_iteration(pcfr_solver* s, int64_t* t);   /* synchronises */
 
@@ -186,6 +196,50 @@ int32_t pcfr_exploitability(pcfr_solver* s, double* chips_per_hand, double* br);
 int32_t pcfr_state_bytes(pcfr_solver* s, size_t* bytes);
 int32_t pcfr_save_state(pcfr_solver* s, void* buf, size_t bytes);
 int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes);
+
+/* ---------------------------------------------------------------- leaf network
+ * The value network f_theta of depth-limited solving (Sec. 3): a ReLU MLP
+ * d_in -> width x depth -> d_out evaluated for all leaves of an iteration in
+ * one batch (Sec. 4.3, Stage 5) with bfloat16 MFMA GEMMs accumulating in
+ * FP32.  FP32 master parameters; host layout for set/get: for each layer l
+ * in order, W_l [out][in] row-major, then b_l [out].  Device memory is the
+ * caller's workspace (256-byte aligned), work is ordered on `stream`.
+ * max_batch bounds the rows of forward/train calls.  Parameters start at 0. */
+typedef struct pcfr_leafnet pcfr_leafnet;
+
+int32_t pcfr_leafnet_workspace_bytes(int32_t d_in, int32_t width, int32_t depth, int32_t d_out,
+                                     int32_t max_batch, size_t* bytes);
+int32_t pcfr_leafnet_create(int32_t d_in, int32_t width, int32_t depth, int32_t d_out, int32_t max_batch,
+                            void* workspace, size_t workspace_bytes, void* stream, pcfr_leafnet** out);
+int32_t pcfr_leafnet_free(pcfr_leafnet* net);
+int32_t pcfr_leafnet_num_params(const pcfr_leafnet* net, int64_t* count);
+/* Host FP32 parameters in, all finite; resets the Adam state.  Synchronises. */
+int32_t pcfr_leafnet_set_params(pcfr_leafnet* net, const float* host);
+int32_t pcfr_leafnet_get_params(pcfr_leafnet* net, float* host);
+/* Gradients of the last train step, same layout.  Synchronises. */
+int32_t pcfr_leafnet_get_grads(pcfr_leafnet* net, float* host);
+
+/* y[m][d_out] = f(x[m][d_in]); x and y device FP32 (x is rounded to bf16
+ * on the device).  Asynchronous. */
+int32_t pcfr_leafnet_forward(pcfr_leafnet* net, const float* x, int32_t m, float* y);
+
+/* One Adam step (beta 0.9/0.999, eps 1e-8, learning rate lr) on the Huber
+ * loss (delta 1) between f(x) and target over entries where mask != 0,
+ * averaged over the mask's sum.  x [m][d_in], target and mask [m][d_out]
+ * device FP32.  loss (host, may be NULL) receives the batch loss before the
+ * step, which synchronises. */
+int32_t pcfr_leafnet_train_step(pcfr_leafnet* net, const float* x, const float* target, const float* mask,
+                                int32_t m, float lr, float* loss);
+
+/* Value the solver's depth-limit leaves with net (NULL: exact check-down
+ * equity, the stub model).  The net must map 2*1326 + 53 inputs (both
+ * normalised ranges after each next card, the board one-hot, the
+ * stack-to-pot ratio) to 2*1326 outputs (each hand's value per pot unit and
+ * per unit of compatible opponent reach) and hold leaves x next-cards rows.
+ * All-in leaves stay exact.  The net must outlive the attachment. */
+int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net);
+/* Network leaves and next cards per leaf (rows = product). */
+int32_t pcfr_leaf_rows(pcfr_solver* s, int32_t* n_leaves, int32_t* n_next);
 
 #ifdef __cplusplus
 }

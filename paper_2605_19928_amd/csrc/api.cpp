@@ -2,6 +2,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "host.hpp"
 
@@ -71,6 +72,28 @@ int32_t pcfr_tree_export(const pcfr_tree* tree, int32_t* type, int32_t* player, 
         depth[i] = n.depth; contrib[2 * i] = n.contrib[0]; contrib[2 * i + 1] = n.contrib[1];
         chance_card[i] = n.chance_card; first_child[i] = n.first_child; n_child[i] = n.n_child;
     }
+    return PCFR_OK;
+}
+
+int32_t pcfr_equity_table(const pcfr_tree* tree, double* out) {
+    if (!tree || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    const Tree& t = tree->t;
+    if (__builtin_popcountll(t.root_mask) == 5) { set_error("the root board is complete"); return PCFR_E_INVALID_ARG; }
+    const ComboTable& cc = combos();
+    std::vector<int32_t> hands;
+    for (int k = 0; k < kCombos; k++)
+        if (!((t.root_mask >> cc.hi[k] & 1ull) || (t.root_mask >> cc.lo[k] & 1ull))) hands.push_back(k);
+    std::vector<double> E;
+    try {
+        equity_matrix(t.root_mask, hands, E);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return PCFR_E_OUT_OF_MEMORY;
+    }
+    std::memset(out, 0, sizeof(double) * kCombos * kCombos);
+    const size_t H = hands.size();
+    for (size_t i = 0; i < H; i++)
+        for (size_t j = 0; j < H; j++) out[(size_t)hands[i] * kCombos + hands[j]] = E[i * H + j];
     return PCFR_OK;
 }
 

@@ -48,6 +48,9 @@ struct Tree {
 
 int32_t build_tree(const pcfr_tree_spec& spec, Tree& out);
 
+// Pairwise check-down equity E[h][o] over a hand list on a partial board.
+void equity_matrix(uint64_t board, const std::vector<int32_t>& hand_combo, std::vector<double>& E);
+
 }  // namespace pcfr
 
 struct pcfr_tree {

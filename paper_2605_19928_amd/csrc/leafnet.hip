@@ -1,0 +1,594 @@
+// Leaf value network on gfx950: a ReLU MLP evaluated and trained with
+// bfloat16 MFMA GEMMs that accumulate in FP32 (v_mfma_f32_32x32x16_bf16).
+//
+// The paper evaluates every depth-limit leaf of an iteration in one batched
+// forward pass (Sec. 4.3, Stage 5) of a network of the players' normalised
+// reach probabilities and the public state (Sec. 3, the depth-limited solving
+// equation); it trains that network as prior work does (Sec. 2) without
+// giving an architecture.  Here: d_in -> width x depth (ReLU) -> d_out,
+// weights kept as FP32 masters with bfloat16 copies for the GEMMs, trained
+// with a Huber loss and Adam.
+//
+// Every GEMM has the form C[M,N] = A[M,K] * B[N,K]^T with both operands
+// K-contiguous; the backward pass forms the transposed operands it needs with
+// a tiled transpose kernel.  All dimensions are padded to multiples of 64 and
+// padding entries are zero.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+#include "leafnet.hpp"
+
+namespace pcfr {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 v8bf;
+typedef __attribute__((ext_vector_type(16))) float v16f;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ------------------------------------------------------------------ GEMM
+// Workgroup tile BM x BN, 4 waves in a 2 x 2 grid, each wave (BM/2) x (BN/2)
+// made of 32 x 32 MFMA tiles; K staged through LDS 64 at a time, double
+// buffered, rows padded by 8 elements against bank conflicts.
+//   EPI_BIAS_F32      C = A B^T + bias           (float out)
+//   EPI_BIAS_RELU_BF  C = relu(A B^T + bias)     (bf16 out)
+//   EPI_F32           C = A B^T                  (float out)
+//   EPI_MASK_BF       C = (A B^T) * [mask > 0]   (bf16 out, mask bf16 [M][ldc])
+enum { EPI_BIAS_F32 = 0, EPI_BIAS_RELU_BF = 1, EPI_F32 = 2, EPI_MASK_BF = 3 };
+
+template <int BM, int BN, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
+                                                 const uint16_t* __restrict__ B, int ldb, int K,
+                                                 const float* __restrict__ bias, void* __restrict__ Cout, int ldc,
+                                                 const uint16_t* __restrict__ mask) {
+    constexpr int BK = 64, LDK = BK + 8;
+    constexpr int TM = BM / 64, TN = BN / 64;
+    constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;
+    __shared__ __align__(16) uint16_t sA[2][BM * LDK];
+    __shared__ __align__(16) uint16_t sB[2][BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    uint4 ra[CA], rb[CB];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < CA; i++) {
+            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
+            ra[i] = *reinterpret_cast<const uint4*>(A + (m0 + row) * lda + k0 + col);
+        }
+#pragma unroll
+        for (int i = 0; i < CB; i++) {
+            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
+            rb[i] = *reinterpret_cast<const uint4*>(B + (n0 + row) * ldb + k0 + col);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < CA; i++) {
+            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
+            *reinterpret_cast<uint4*>(&sA[buf][row * LDK + col]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < CB; i++) {
+            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
+            *reinterpret_cast<uint4*>(&sB[buf][row * LDK + col]) = rb[i];
+        }
+    };
+    v16f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    const int kh = 8 * (lane >> 5), l32 = lane & 31;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const int buf = (k0 / BK) & 1;
+        const bool more = k0 + BK < K;
+        if (more) gload(k0 + BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            v8bf a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; i++)
+                a[i] = *reinterpret_cast<const v8bf*>(&sA[buf][(wm * (BM / 2) + i * 32 + l32) * LDK + ks + kh]);
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+                b[j] = *reinterpret_cast<const v8bf*>(&sB[buf][(wn * (BN / 2) + j * 32 + l32) * LDK + ks + kh]);
+#pragma unroll
+            for (int i = 0; i < TM; i++)
+#pragma unroll
+                for (int j = 0; j < TN; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) sstore(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++) {
+            const int64_t col = n0 + wn * (BN / 2) + j * 32 + l32;
+            const float bv = (EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_RELU_BF) ? bias[col] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int64_t row = m0 + wm * (BM / 2) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                float v = acc[i][j][r] + bv;
+                if (EPI == EPI_BIAS_F32 || EPI == EPI_F32) {
+                    reinterpret_cast<float*>(Cout)[row * ldc + col] = v;
+                } else if (EPI == EPI_BIAS_RELU_BF) {
+                    reinterpret_cast<uint16_t*>(Cout)[row * ldc + col] = f2bf(v > 0.f ? v : 0.f);
+                } else {
+                    const bool on = bf2f(mask[row * ldc + col]) > 0.f;
+                    reinterpret_cast<uint16_t*>(Cout)[row * ldc + col] = f2bf(on ? v : 0.f);
+                }
+            }
+        }
+}
+
+// bf16 transpose: out[c][r] = in[r][c], both dims multiples of 64.
+__global__ __launch_bounds__(256) void k_transpose_bf16(const uint16_t* __restrict__ in, int ldin,
+                                                        uint16_t* __restrict__ out, int ldout) {
+    __shared__ uint16_t t[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) t[r][tx] = in[(r0 + r) * ldin + c0 + tx];
+    __syncthreads();
+    for (int c = ty; c < 64; c += 4) out[(c0 + c) * ldout + r0 + tx] = t[tx][c];
+}
+
+// fp32 -> bf16 copy of n elements
+__global__ void k_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = f2bf(in[i]);
+}
+
+// Rows [0, m) of a [rows][ld] fp32 matrix with `cols` valid columns -> bf16
+// [rows][ldo]; rows >= m and columns >= cols become zero.
+__global__ void k_rows_to_bf16(const float* __restrict__ in, int64_t m, int cols, uint16_t* __restrict__ out,
+                               int ldo, int64_t rows) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * ldo) return;
+    int64_t r = i / ldo;
+    int c = (int)(i - r * ldo);
+    out[i] = (r < m && c < cols) ? f2bf(in[r * cols + c]) : (uint16_t)0;
+}
+
+// Valid block of an fp32 [rows][ld] matrix -> dense [m][cols]
+__global__ void k_unpad_f32(const float* __restrict__ in, int ld, int64_t m, int cols, float* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m * cols) return;
+    int64_t r = i / cols;
+    int c = (int)(i - r * cols);
+    out[i] = in[r * ld + c];
+}
+
+// Sum of a mask -> 1 / max(sum, 1) in *inv (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void k_mask_inv(const float* __restrict__ mask, int64_t n, float* __restrict__ inv) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s += mask[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) inv[0] = (float)(1.0 / (red[0] > 1.0 ? red[0] : 1.0));
+}
+
+// Huber loss (delta = 1) averaged over masked entries, its gradient as bf16
+// [rows][ld] (zero outside the valid block), and per-block partial sums of
+// the loss for a deterministic final reduction.
+__global__ __launch_bounds__(256) void k_huber(const float* __restrict__ y, int ld, const float* __restrict__ t,
+                                               const float* __restrict__ mask, int64_t m, int cols,
+                                               const float* __restrict__ inv_n_p, uint16_t* __restrict__ g,
+                                               int64_t rows, double* __restrict__ part) {
+    __shared__ double red[256];
+    const float inv_n = inv_n_p[0];
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double l = 0.0;
+    if (i < rows * ld) {
+        int64_t r = i / ld;
+        int c = (int)(i - r * ld);
+        float gv = 0.f;
+        if (r < m && c < cols) {
+            int64_t k = r * cols + c;
+            float mk = mask[k];
+            float d = (y[i] - t[k]) * mk;
+            float a = fabsf(d);
+            l = a <= 1.f ? 0.5 * (double)d * d : (double)a - 0.5;
+            gv = (a <= 1.f ? d : copysignf(1.f, d)) * inv_n;
+        }
+        g[i] = f2bf(gv);
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Column sums of a bf16 [rows][ld] matrix -> fp32 [ld] (bias gradients).
+__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t* __restrict__ g, int ld, int64_t rows,
+                                                     float* __restrict__ out) {
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= ld) return;
+    float s = 0.f;
+    for (int64_t r = 0; r < rows; r++) s += bf2f(g[r * ld + c]);
+    out[c] = s;
+}
+
+// Adam (Kingma & Ba) on FP32 masters, refreshing the bf16 copy; `live`
+// marks entries that are real parameters (padding stays zero).
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ pb, const uint8_t* __restrict__ live, int64_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !live[i]) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+}
+
+// ------------------------------------------------------------------ host
+static int32_t hipchk(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PCFR_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return PCFR_E_DEVICE;
+}
+#define LN_CHK(call)                                        \
+    do {                                                    \
+        int32_t _rc = hipchk((call), #call);                \
+        if (_rc != PCFR_OK) return _rc;                     \
+    } while (0)
+
+static int64_t r64(int64_t x) { return (x + 63) / 64 * 64; }
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M,
+                    int64_t N, int64_t K, const float* bias, void* C, int ldc, const uint16_t* mask) {
+    if (M % 64 || N % 64 || K % 64 || M <= 0 || N <= 0 || K <= 0) {
+        set_error("GEMM dims must be positive multiples of 64");
+        return PCFR_E_INVALID_ARG;
+    }
+    // 128 x 128 tiles when they still give at least one workgroup per CU
+    const bool big = (M % 128 == 0) && (N % 128 == 0) && (M / 128) * (N / 128) >= 256;
+    dim3 blk(256);
+#define LN_GEMM(BMv, BNv, E)                                                                                      \
+    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E>), dim3((unsigned)(N / BNv), (unsigned)(M / BMv)), blk, 0, st, A, \
+                       lda, B, ldb, (int)K, bias, C, ldc, mask)
+    if (big) {
+        switch (epi) {
+            case EPI_BIAS_F32: LN_GEMM(128, 128, EPI_BIAS_F32); break;
+            case EPI_BIAS_RELU_BF: LN_GEMM(128, 128, EPI_BIAS_RELU_BF); break;
+            case EPI_F32: LN_GEMM(128, 128, EPI_F32); break;
+            default: LN_GEMM(128, 128, EPI_MASK_BF); break;
+        }
+    } else {
+        switch (epi) {
+            case EPI_BIAS_F32: LN_GEMM(64, 64, EPI_BIAS_F32); break;
+            case EPI_BIAS_RELU_BF: LN_GEMM(64, 64, EPI_BIAS_RELU_BF); break;
+            case EPI_F32: LN_GEMM(64, 64, EPI_F32); break;
+            default: LN_GEMM(64, 64, EPI_MASK_BF); break;
+        }
+    }
+#undef LN_GEMM
+    return hipchk(hipGetLastError(), "gemm launch");
+}
+
+static int32_t transpose(hipStream_t st, const uint16_t* in, int64_t rows, int64_t cols, uint16_t* out) {
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)(cols / 64), (unsigned)(rows / 64)), dim3(256), 0, st, in,
+                       (int)cols, out, (int)rows);
+    return hipchk(hipGetLastError(), "transpose launch");
+}
+
+void LeafNetPlan::make(int d_in_, int width_, int depth_, int d_out_, int max_batch_) {
+    d_in = d_in_; width = width_; depth = depth_; d_out = d_out_;
+    Mp = r64(max_batch_);
+    L = depth + 1;
+    dims.assign(L + 1, 0);
+    pdims.assign(L + 1, 0);
+    dims[0] = d_in;
+    for (int i = 1; i < L; i++) dims[i] = width;
+    dims[L] = d_out;
+    for (int i = 0; i <= L; i++) pdims[i] = r64(dims[i]);
+    woff.assign(L, 0);
+    boff.assign(L, 0);
+    int64_t o = 0;
+    for (int l = 0; l < L; l++) {
+        woff[l] = o;
+        o += pdims[l + 1] * pdims[l];
+        boff[l] = o;
+        o += pdims[l + 1];
+    }
+    n_padded = o;
+    n_params = 0;
+    for (int l = 0; l < L; l++) n_params += (int64_t)dims[l + 1] * dims[l] + dims[l + 1];
+    maxw = 0;
+    for (int i = 0; i <= L; i++) maxw = std::max<int64_t>(maxw, pdims[i]);
+    size_t s = 0;
+    auto take = [&](size_t b) { size_t at = s; s = a256(s + b); return at; };
+    off_p = take(4 * n_padded);
+    off_pb = take(2 * n_padded);
+    off_g = take(4 * n_padded);
+    off_m = take(4 * n_padded);
+    off_v = take(4 * n_padded);
+    off_live = take(n_padded);
+    off_wt = take(2 * (size_t)maxw * maxw);
+    off_x = take(2 * (size_t)Mp * pdims[0]);
+    off_h.assign(L, 0);
+    for (int l = 1; l < L; l++) off_h[l] = take(2 * (size_t)Mp * pdims[l]);
+    off_y = take(4 * (size_t)Mp * pdims[L]);
+    off_dz = take(2 * (size_t)Mp * maxw);
+    off_dz2 = take(2 * (size_t)Mp * maxw);
+    off_t1 = take(2 * (size_t)Mp * maxw);
+    off_t2 = take(2 * (size_t)Mp * maxw);
+    off_part = take(8 * (size_t)((Mp * pdims[L] + 255) / 256));
+    off_cnt = take(16);
+    total = s;
+}
+
+}  // namespace pcfr
+
+using namespace pcfr;
+
+extern "C" {
+
+int32_t pcfr_leafnet_workspace_bytes(int32_t d_in, int32_t width, int32_t depth, int32_t d_out, int32_t max_batch,
+                                     size_t* bytes) {
+    if (!bytes || d_in <= 0 || width <= 0 || depth < 1 || depth > 16 || d_out <= 0 || max_batch <= 0) {
+        set_error("invalid network shape");
+        return PCFR_E_INVALID_ARG;
+    }
+    LeafNetPlan p;
+    p.make(d_in, width, depth, d_out, max_batch);
+    *bytes = p.total;
+    return PCFR_OK;
+}
+
+int32_t pcfr_leafnet_create(int32_t d_in, int32_t width, int32_t depth, int32_t d_out, int32_t max_batch,
+                            void* workspace, size_t bytes, void* stream, pcfr_leafnet** out) {
+    size_t need;
+    int32_t rc = pcfr_leafnet_workspace_bytes(d_in, width, depth, d_out, max_batch, &need);
+    if (rc) return rc;
+    if (!workspace || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) { set_error("workspace must be 256-byte aligned"); return PCFR_E_INVALID_ARG; }
+    if (bytes < need) { set_error("workspace smaller than pcfr_leafnet_workspace_bytes"); return PCFR_E_OUT_OF_MEMORY; }
+    pcfr_leafnet* n = new (std::nothrow) pcfr_leafnet;
+    if (!n) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
+    n->P.make(d_in, width, depth, d_out, max_batch);
+    n->ws = reinterpret_cast<char*>(workspace);
+    n->stream = reinterpret_cast<hipStream_t>(stream);
+    const LeafNetPlan& P = n->P;
+    rc = hipchk(hipMemsetAsync(n->ws, 0, P.total, n->stream), "workspace clear");
+    if (rc) { delete n; return rc; }
+    std::vector<uint8_t> live(P.n_padded, 0);
+    for (int l = 0; l < P.L; l++) {
+        for (int o = 0; o < P.dims[l + 1]; o++) {
+            for (int i = 0; i < P.dims[l]; i++) live[P.woff[l] + (int64_t)o * P.pdims[l] + i] = 1;
+            live[P.boff[l] + o] = 1;
+        }
+    }
+    rc = hipchk(hipMemcpyAsync(n->ws + P.off_live, live.data(), live.size(), hipMemcpyHostToDevice, n->stream), "upload");
+    if (!rc) rc = hipchk(hipStreamSynchronize(n->stream), "sync");
+    if (rc) { delete n; return rc; }
+    *out = n;
+    return PCFR_OK;
+}
+
+int32_t pcfr_leafnet_free(pcfr_leafnet* n) {
+    if (!n) return PCFR_OK;
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    delete n;
+    return PCFR_OK;
+}
+
+int32_t pcfr_leafnet_num_params(const pcfr_leafnet* n, int64_t* count) {
+    if (!n || !count) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    *count = n->P.n_params;
+    return PCFR_OK;
+}
+
+// Host parameter layout: for each layer l, W_l [out][in] row-major, then b_l [out].
+int32_t pcfr_leafnet_set_params(pcfr_leafnet* n, const float* host) {
+    if (!n || !host) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    const LeafNetPlan& P = n->P;
+    std::vector<float> pad(P.n_padded, 0.f);
+    int64_t k = 0;
+    for (int l = 0; l < P.L; l++) {
+        for (int o = 0; o < P.dims[l + 1]; o++)
+            for (int i = 0; i < P.dims[l]; i++) {
+                float v = host[k++];
+                if (!std::isfinite(v)) { set_error("non-finite parameter"); return PCFR_E_INVALID_ARG; }
+                pad[P.woff[l] + (int64_t)o * P.pdims[l] + i] = v;
+            }
+        for (int o = 0; o < P.dims[l + 1]; o++) {
+            float v = host[k++];
+            if (!std::isfinite(v)) { set_error("non-finite parameter"); return PCFR_E_INVALID_ARG; }
+            pad[P.boff[l] + o] = v;
+        }
+    }
+    LN_CHK(hipMemcpyAsync(n->ws + P.off_p, pad.data(), 4 * P.n_padded, hipMemcpyHostToDevice, n->stream));
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((P.n_padded + 255) / 256)), dim3(256), 0, n->stream,
+                       reinterpret_cast<float*>(n->ws + P.off_p), reinterpret_cast<uint16_t*>(n->ws + P.off_pb),
+                       P.n_padded);
+    LN_CHK(hipGetLastError());
+    LN_CHK(hipMemsetAsync(n->ws + P.off_m, 0, 4 * P.n_padded, n->stream));
+    LN_CHK(hipMemsetAsync(n->ws + P.off_v, 0, 4 * P.n_padded, n->stream));
+    n->adam_t = 0;
+    LN_CHK(hipStreamSynchronize(n->stream));
+    return PCFR_OK;
+}
+
+static int32_t get_padded(pcfr_leafnet* n, size_t off, float* host) {
+    const LeafNetPlan& P = n->P;
+    std::vector<float> pad(P.n_padded);
+    LN_CHK(hipMemcpyAsync(pad.data(), n->ws + off, 4 * P.n_padded, hipMemcpyDeviceToHost, n->stream));
+    LN_CHK(hipStreamSynchronize(n->stream));
+    int64_t k = 0;
+    for (int l = 0; l < P.L; l++) {
+        for (int o = 0; o < P.dims[l + 1]; o++)
+            for (int i = 0; i < P.dims[l]; i++) host[k++] = pad[P.woff[l] + (int64_t)o * P.pdims[l] + i];
+        for (int o = 0; o < P.dims[l + 1]; o++) host[k++] = pad[P.boff[l] + o];
+    }
+    return PCFR_OK;
+}
+
+int32_t pcfr_leafnet_get_params(pcfr_leafnet* n, float* host) {
+    if (!n || !host) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    return get_padded(n, n->P.off_p, host);
+}
+
+int32_t pcfr_leafnet_get_grads(pcfr_leafnet* n, float* host) {
+    if (!n || !host) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    return get_padded(n, n->P.off_g, host);
+}
+
+}  // extern "C"
+
+namespace pcfr {
+
+// Forward over the rows already staged in the bf16 input buffer; M = padded rows.
+int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st) {
+    const LeafNetPlan& P = n->P;
+    const uint16_t* in = reinterpret_cast<const uint16_t*>(n->ws + P.off_x);
+    for (int l = 0; l < P.L; l++) {
+        const uint16_t* W = reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l];
+        const float* b = reinterpret_cast<const float*>(n->ws + P.off_p) + P.boff[l];
+        int32_t rc;
+        if (l + 1 < P.L) {
+            uint16_t* h = reinterpret_cast<uint16_t*>(n->ws + P.off_h[l + 1]);
+            rc = launch_gemm(st, EPI_BIAS_RELU_BF, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
+                             P.pdims[l], b, h, (int)P.pdims[l + 1], nullptr);
+            in = h;
+        } else {
+            rc = launch_gemm(st, EPI_BIAS_F32, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
+                             P.pdims[l], b, n->ws + P.off_y, (int)P.pdims[l + 1], nullptr);
+        }
+        if (rc) return rc;
+    }
+    return PCFR_OK;
+}
+
+}  // namespace pcfr
+
+extern "C" {
+
+int32_t pcfr_leafnet_forward(pcfr_leafnet* n, const float* x, int32_t m, float* y) {
+    if (!n || !x || !y || m <= 0) { set_error("null argument or empty batch"); return PCFR_E_INVALID_ARG; }
+    const LeafNetPlan& P = n->P;
+    if (m > P.Mp) { set_error("batch larger than max_batch"); return PCFR_E_INVALID_ARG; }
+    const int64_t M = r64(m);
+    const int64_t tot = M * P.pdims[0];
+    hipLaunchKernelGGL(k_rows_to_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, n->stream, x, (int64_t)m,
+                       P.dims[0], reinterpret_cast<uint16_t*>(n->ws + P.off_x), (int)P.pdims[0], M);
+    LN_CHK(hipGetLastError());
+    int32_t rc = leafnet_forward_staged(n, M, n->stream);
+    if (rc) return rc;
+    const int64_t ny = (int64_t)m * P.dims[P.L];
+    hipLaunchKernelGGL(k_unpad_f32, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, n->stream,
+                       reinterpret_cast<const float*>(n->ws + P.off_y), (int)P.pdims[P.L], (int64_t)m, P.dims[P.L], y);
+    LN_CHK(hipGetLastError());
+    return PCFR_OK;
+}
+
+// One Adam step on the Huber loss of a batch: forward, loss gradient,
+// backward GEMMs (dW = dZ^T H, dH = dZ W masked by the ReLU), bias sums,
+// Adam.  x [m][d_in], target and mask [m][d_out] are device fp32.
+int32_t pcfr_leafnet_train_step(pcfr_leafnet* n, const float* x, const float* target, const float* mask, int32_t m,
+                                float lr, float* loss) {
+    if (!n || !x || !target || !mask || m <= 0) { set_error("null argument or empty batch"); return PCFR_E_INVALID_ARG; }
+    const LeafNetPlan& P = n->P;
+    if (m > P.Mp) { set_error("batch larger than max_batch"); return PCFR_E_INVALID_ARG; }
+    hipStream_t st = n->stream;
+    const int64_t M = r64(m);
+    {
+        const int64_t tot = M * P.pdims[0];
+        hipLaunchKernelGGL(k_rows_to_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, x, (int64_t)m,
+                           P.dims[0], reinterpret_cast<uint16_t*>(n->ws + P.off_x), (int)P.pdims[0], M);
+        LN_CHK(hipGetLastError());
+    }
+    int32_t rc = leafnet_forward_staged(n, M, st);
+    if (rc) return rc;
+    const int64_t ny = (int64_t)m * P.dims[P.L];
+    float* inv_n = reinterpret_cast<float*>(n->ws + P.off_cnt);
+    hipLaunchKernelGGL(k_mask_inv, dim3(1), dim3(1024), 0, st, mask, ny, inv_n);
+    LN_CHK(hipGetLastError());
+    const int64_t Ny = P.pdims[P.L];
+    const int64_t nel = M * Ny;
+    const unsigned nblk = (unsigned)((nel + 255) / 256);
+    uint16_t* dz = reinterpret_cast<uint16_t*>(n->ws + P.off_dz);
+    uint16_t* dz2 = reinterpret_cast<uint16_t*>(n->ws + P.off_dz2);
+    uint16_t* t1 = reinterpret_cast<uint16_t*>(n->ws + P.off_t1);
+    uint16_t* t2 = reinterpret_cast<uint16_t*>(n->ws + P.off_t2);
+    uint16_t* wt = reinterpret_cast<uint16_t*>(n->ws + P.off_wt);
+    float* g = reinterpret_cast<float*>(n->ws + P.off_g);
+    double* part = reinterpret_cast<double*>(n->ws + P.off_part);
+    hipLaunchKernelGGL(k_huber, dim3(nblk), dim3(256), 0, st, reinterpret_cast<const float*>(n->ws + P.off_y),
+                       (int)Ny, target, mask, (int64_t)m, P.dims[P.L], inv_n, dz, M, part);
+    LN_CHK(hipGetLastError());
+    for (int l = P.L - 1; l >= 0; l--) {
+        const int64_t in = P.pdims[l], outd = P.pdims[l + 1];
+        const uint16_t* H = l == 0 ? reinterpret_cast<const uint16_t*>(n->ws + P.off_x)
+                                   : reinterpret_cast<const uint16_t*>(n->ws + P.off_h[l]);
+        // dW_l = dZ^T H: A' = dZ^T [out][M], B' = H^T [in][M]
+        if ((rc = transpose(st, dz, M, outd, t1))) return rc;
+        if ((rc = transpose(st, H, M, in, t2))) return rc;
+        if ((rc = launch_gemm(st, EPI_F32, t1, (int)M, t2, (int)M, outd, in, M, nullptr, g + P.woff[l], (int)in,
+                              nullptr)))
+            return rc;
+        hipLaunchKernelGGL(k_colsum_bf16, dim3((unsigned)((outd + 255) / 256)), dim3(256), 0, st, dz, (int)outd, M,
+                           g + P.boff[l]);
+        LN_CHK(hipGetLastError());
+        if (l > 0) {
+            // dZ_{l-1} = (dZ_l W_l) * [H_l > 0]: B' = W_l^T [in][out]
+            const uint16_t* W = reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l];
+            if ((rc = transpose(st, W, outd, in, wt))) return rc;
+            if ((rc = launch_gemm(st, EPI_MASK_BF, dz, (int)outd, wt, (int)outd, M, in, outd, nullptr, dz2, (int)in,
+                                  H)))
+                return rc;
+            std::swap(dz, dz2);
+        }
+    }
+    n->adam_t++;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)n->adam_t), c2 = 1.f - powf(b2, (float)n->adam_t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((P.n_padded + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<float*>(n->ws + P.off_p), g, reinterpret_cast<float*>(n->ws + P.off_m),
+                       reinterpret_cast<float*>(n->ws + P.off_v), reinterpret_cast<uint16_t*>(n->ws + P.off_pb),
+                       reinterpret_cast<const uint8_t*>(n->ws + P.off_live), P.n_padded, lr, b1, b2, eps, c1, c2);
+    LN_CHK(hipGetLastError());
+    if (loss) {
+        std::vector<double> hp(nblk);
+        float iv = 1.f;
+        LN_CHK(hipMemcpyAsync(hp.data(), part, 8 * nblk, hipMemcpyDeviceToHost, st));
+        LN_CHK(hipMemcpyAsync(&iv, inv_n, 4, hipMemcpyDeviceToHost, st));
+        LN_CHK(hipStreamSynchronize(st));
+        double s = 0;
+        for (double v : hp) s += v;
+        *loss = (float)(s * iv);
+    }
+    return PCFR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// Leaf network: workspace plan and handle (shared by the solver's leaf stage).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/pcfr.h"
+
+namespace pcfr {
+
+struct LeafNetPlan {
+    int d_in = 0, width = 0, depth = 0, d_out = 0, L = 0;
+    int64_t Mp = 0;                       // max batch rows, padded to 64
+    std::vector<int> dims;                // layer widths, unpadded (L + 1)
+    std::vector<int64_t> pdims;           // padded to 64
+    std::vector<int64_t> woff, boff;      // parameter offsets (elements) in the padded layout
+    int64_t n_padded = 0, n_params = 0, maxw = 0;
+    size_t off_p = 0, off_pb = 0, off_g = 0, off_m = 0, off_v = 0, off_live = 0, off_wt = 0, off_x = 0;
+    std::vector<size_t> off_h;            // hidden activations (bf16), index 1..L-1
+    size_t off_y = 0, off_dz = 0, off_dz2 = 0, off_t1 = 0, off_t2 = 0, off_part = 0, off_cnt = 0, total = 0;
+    void make(int d_in, int width, int depth, int d_out, int max_batch);
+};
+
+int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M,
+                    int64_t N, int64_t K, const float* bias, void* C, int ldc, const uint16_t* mask);
+
+}  // namespace pcfr
+
+struct pcfr_leafnet {
+    pcfr::LeafNetPlan P;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t adam_t = 0;
+};
+
+namespace pcfr {
+int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st);
+}

@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "host.hpp"
+#include "leafnet.hpp"
 
 namespace pcfr {
 
@@ -437,6 +438,173 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
         term_showdown<T>(nd, n, Hp, reach, cfv, hc, sd + (int64_t)nd.aux * sd_stride, sd_n[nd.aux], lds);
 }
 
+// ------------------------------------------------------------ depth-limit leaves
+// Exact leaf values from pairwise check-down equity (all-in leaves, and every
+// leaf when no network is attached): v_i(h) = c * sum_o E(h,o) r_{-i}(o).
+// Et is stored transposed, [o][h], so consecutive threads read consecutive h;
+// each workgroup serves J leaves whose reach vectors sit in LDS.
+template <typename T, int J>
+__global__ __launch_bounds__(kBlock) void k_equity_leaf(const int32_t* __restrict__ leaves,
+                                                        const double* __restrict__ pay, int n_leaves, int Hp,
+                                                        const T* __restrict__ Et, const T* __restrict__ reach,
+                                                        T* __restrict__ cfv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* rr = reinterpret_cast<T*>(smem);   // [J][2][Hp]
+    const int j0 = blockIdx.y * J;
+    const int nj = min(J, n_leaves - j0);
+    for (int i = threadIdx.x; i < nj * 2 * Hp; i += kBlock) {
+        const int j = i / (2 * Hp);
+        rr[i] = reach[(int64_t)leaves[j0 + j] * 2 * Hp + (i - j * 2 * Hp)];
+    }
+    __syncthreads();
+    const int h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= Hp) return;
+    T acc[J][2];
+#pragma unroll
+    for (int j = 0; j < J; j++) { acc[j][0] = T(0); acc[j][1] = T(0); }
+    for (int o = 0; o < Hp; o++) {
+        const T e = Et[(int64_t)o * Hp + h];
+#pragma unroll
+        for (int j = 0; j < J; j++) {
+            acc[j][0] += e * rr[(j * 2 + 1) * Hp + o];   // player 0 against player 1's reach
+            acc[j][1] += e * rr[(j * 2) * Hp + o];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        if (j >= nj) break;
+        const int64_t n = leaves[j0 + j];
+        const T c = (T)pay[j0 + j];
+        cfv[n * 2 * Hp + h] = c * acc[j][0];
+        cfv[n * 2 * Hp + Hp + h] = c * acc[j][1];
+    }
+}
+
+__device__ __forceinline__ int combo_index(int a, int b) {
+    const int hi = a > b ? a : b, lo = a > b ? b : a;
+    return hi * (hi - 1) / 2 + lo;
+}
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Stage 2's batched leaf input (Sec. 4.2): one row per (leaf, next card c):
+// each player's reach with the hands holding c removed, normalised to sum 1,
+// over the 1326 combos; then the board after c as 52 one-hot entries; then
+// the stack-to-pot ratio at the leaf; bf16, zero padded to ldx.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_leaf_input(const int32_t* __restrict__ leaves, const float* __restrict__ spr,
+                                                       int n_next, const int8_t* __restrict__ next_cards, int Hp, int H,
+                                                       const T* __restrict__ reach, const uint16_t* __restrict__ hcards,
+                                                       const int16_t* __restrict__ combo_hand,
+                                                       const uint8_t* __restrict__ board_hot, uint16_t* __restrict__ X,
+                                                       int ldx) {
+    __shared__ double red[2][kBlock];
+    const int q = blockIdx.x;
+    const int li = q / n_next, k = q - li * n_next;
+    const int c = next_cards[k];
+    const int64_t n = leaves[li];
+    const T* r0 = reach + n * 2 * Hp;
+    const T* r1 = r0 + Hp;
+    const int tid = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (int h = tid; h < H; h += kBlock)
+        if (!has_card(hcards[h], c)) { s0 += (double)r0[h]; s1 += (double)r1[h]; }
+    red[0][tid] = s0;
+    red[1][tid] = s1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
+        __syncthreads();
+    }
+    const double S0 = red[0][0], S1 = red[1][0];
+    uint16_t* row = X + (int64_t)q * ldx;
+    for (int col = tid; col < ldx; col += kBlock) {
+        float v = 0.f;
+        if (col < 2 * kCombos) {
+            const int p = col >= kCombos;
+            const int h = combo_hand[col - p * kCombos];
+            const double S = p ? S1 : S0;
+            if (h >= 0 && S > 0.0 && !has_card(hcards[h], c)) v = (float)((double)(p ? r1[h] : r0[h]) / S);
+        } else if (col < 2 * kCombos + 52) {
+            const int card = col - 2 * kCombos;
+            v = (board_hot[card] || card == c) ? 1.f : 0.f;
+        } else if (col == 2 * kCombos + 52) {
+            v = spr[li];
+        }
+        row[col] = to_bf16(v);
+    }
+}
+
+// Leaf counterfactual values from the network's per-card outputs (Sec. 4.4:
+// leaf predictions weighted by the opponent's counterfactual reach and the
+// chance probability): v_i(h) = pot/K * sum_{c not in h} EV_i(h | c) *
+// M_{-i}(h | c), where M(h | c) is the opponent reach over hands sharing no
+// card with h or c:  T - C[a] - C[b] - C[c] + r(ab) + r(ac) + r(bc).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restrict__ leaves,
+                                                         const double* __restrict__ pot_over_k, int n_next,
+                                                         const int8_t* __restrict__ next_cards, int Hp, int H,
+                                                         const T* __restrict__ reach, T* __restrict__ cfv,
+                                                         const uint16_t* __restrict__ hcards,
+                                                         const int16_t* __restrict__ hand_combo,
+                                                         const int16_t* __restrict__ combo_hand,
+                                                         const int32_t* __restrict__ coff,
+                                                         const int16_t* __restrict__ chands,
+                                                         const float* __restrict__ Y, int ldy) {
+    __shared__ T cs[2][52];
+    __shared__ T red[2][kBlock];
+    const int li = blockIdx.x;
+    const int64_t n = leaves[li];
+    const T* r0 = reach + n * 2 * Hp;
+    const T* r1 = r0 + Hp;
+    const int tid = threadIdx.x;
+    if (tid < 104) {
+        const int p = tid / 52, c = tid - p * 52;
+        const T* r = p ? r1 : r0;
+        T s = T(0);
+        for (int j = coff[c]; j < coff[c + 1]; j++) s += r[chands[j]];
+        cs[p][c] = s;
+    }
+    T s0 = T(0), s1 = T(0);
+    for (int h = tid; h < Hp; h += kBlock) { s0 += r0[h]; s1 += r1[h]; }
+    red[0][tid] = s0;
+    red[1][tid] = s1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
+        __syncthreads();
+    }
+    const T t0 = red[0][0], t1 = red[1][0];
+    const T scale = (T)pot_over_k[li];
+    T* v0 = cfv + n * 2 * Hp;
+    T* v1 = v0 + Hp;
+    for (int h = tid; h < Hp; h += kBlock) {
+        if (h >= H) { v0[h] = T(0); v1[h] = T(0); continue; }
+        const uint32_t hc = hcards[h];
+        const int a = hc & 0xff, b = hc >> 8;
+        const int combo = hand_combo[h];
+        T acc0 = T(0), acc1 = T(0);
+        for (int k = 0; k < n_next; k++) {
+            const int c = next_cards[k];
+            if (c == a || c == b) continue;
+            const int ha = combo_hand[combo_index(a, c)], hb = combo_hand[combo_index(b, c)];
+            const T m1 = t1 - cs[1][a] - cs[1][b] - cs[1][c] + r1[h] + (ha >= 0 ? r1[ha] : T(0)) +
+                         (hb >= 0 ? r1[hb] : T(0));
+            const T m0 = t0 - cs[0][a] - cs[0][b] - cs[0][c] + r0[h] + (ha >= 0 ? r0[ha] : T(0)) +
+                         (hb >= 0 ? r0[hb] : T(0));
+            const float* y = Y + (int64_t)(li * n_next + k) * ldy;
+            acc0 += (T)y[combo] * m1;
+            acc1 += (T)y[kCombos + combo] * m0;
+        }
+        v0[h] = scale * acc0;
+        v1[h] = scale * acc1;
+    }
+}
+
 // ------------------------------------------------------------ small kernels
 template <typename T>
 __global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, int64_t n) {
@@ -475,10 +643,11 @@ static int32_t hip_check(hipError_t e, const char* what) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
-    int64_t N, rows, Hp, H, n_boards, term, fwd, chand_stride, sd_stride;
+    int64_t N, rows, Hp, H, n_boards, term, fwd, chand_stride, sd_stride, n_eq, n_net, n_next;
     size_t esz;
     size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
-        off_R, off_S, off_reach, off_cfv, off_root, off_stage, total;
+        off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
+        off_potk, off_next, off_hot, off_c2h, off_h2c, total;
     size_t lds_bytes;
 };
 
@@ -495,6 +664,16 @@ struct Prepared {
     std::vector<int32_t> combo_hand;      // [1326], -1 if blocked
     int64_t Hp = 0, H = 0, sd_stride = 0;
     int32_t levels = 0, max_a = 0;
+    // depth-limit leaves: all-in leaves first, then network leaves (so the
+    // all-in prefix is what stays exact when a network is attached)
+    std::vector<int32_t> eq_leaves;
+    std::vector<double> eq_pay;
+    int64_t n_allin = 0;
+    std::vector<int32_t> net_leaves;
+    std::vector<float> net_spr;
+    std::vector<double> net_potk;
+    std::vector<int8_t> next_cards;
+    std::vector<uint8_t> board_hot;
 };
 
 // Host preprocessing: node records, level work lists, hand cards, per-card
@@ -572,9 +751,34 @@ static int32_t prepare(const Tree& t, Prepared& P) {
             if (it == board_id.end()) it = board_id.emplace(s.board_mask, (int32_t)board_id.size()).first;
             d.aux = it->second;
             P.term.push_back((int32_t)i);
+        } else if (s.type == PCFR_NODE_ALLIN_LEAF || s.type == PCFR_NODE_LEAF) {
+            if (s.contrib[0] != s.contrib[1]) { set_error("leaf with unequal contributions"); return PCFR_E_INVALID_ARG; }
         } else {
-            set_error("depth-limit leaves need a leaf model, which this solver does not take");
-            return PCFR_E_UNSUPPORTED;
+            set_error("unknown node type");
+            return PCFR_E_INVALID_ARG;
+        }
+    }
+    {
+        const int64_t eff = std::min(t.spec.stack[0], t.spec.stack[1]);
+        const int64_t cap = t.spec.pot / 2 + eff;
+        for (int pass = 0; pass < 2; pass++)
+            for (int64_t i = 0; i < N; i++) {
+                const Node& s = t.nodes[i];
+                if (s.type != (pass == 0 ? PCFR_NODE_ALLIN_LEAF : PCFR_NODE_LEAF)) continue;
+                P.eq_leaves.push_back((int32_t)i);
+                P.eq_pay.push_back((double)s.contrib[0]);
+                if (pass == 1) {
+                    const int nb = __builtin_popcountll(s.board_mask);
+                    P.net_leaves.push_back((int32_t)i);
+                    P.net_spr.push_back((float)((double)(cap - s.contrib[0]) / (double)(2 * s.contrib[0])));
+                    P.net_potk.push_back((double)(2 * s.contrib[0]) / (double)(52 - nb - 4));
+                }
+            }
+        P.n_allin = (int64_t)t.count[PCFR_NODE_ALLIN_LEAF];
+        P.board_hot.assign(52, 0);
+        for (int c = 0; c < 52; c++) {
+            if (t.root_mask >> c & 1ull) P.board_hot[c] = 1;
+            else P.next_cards.push_back((int8_t)c);
         }
     }
     P.fwd_off.assign(t.n_levels + 1, 0);
@@ -677,6 +881,19 @@ static void make_plan(const Prepared& P, const Tree& t, int dtype, Plan& L) {
     L.off_cfv = take(L.esz * L.N * 2 * L.Hp);
     L.off_root = take(L.esz * 2 * L.Hp);
     L.off_stage = take(L.esz * kMaxActions * L.Hp);
+    L.n_eq = (int64_t)P.eq_leaves.size();
+    L.n_net = (int64_t)P.net_leaves.size();
+    L.n_next = (int64_t)P.next_cards.size();
+    L.off_et = take(L.n_eq ? L.esz * L.Hp * L.Hp : 0);
+    L.off_eq = take(sizeof(int32_t) * std::max<int64_t>(L.n_eq, 1));
+    L.off_eqpay = take(sizeof(double) * std::max<int64_t>(L.n_eq, 1));
+    L.off_net = take(sizeof(int32_t) * std::max<int64_t>(L.n_net, 1));
+    L.off_spr = take(sizeof(float) * std::max<int64_t>(L.n_net, 1));
+    L.off_potk = take(sizeof(double) * std::max<int64_t>(L.n_net, 1));
+    L.off_next = take(64);
+    L.off_hot = take(64);
+    L.off_c2h = take(sizeof(int16_t) * kCombos);
+    L.off_h2c = take(sizeof(int16_t) * L.Hp);
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
     L.lds_bytes = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock);
@@ -697,6 +914,7 @@ struct pcfr_solver {
     double pair_mass = 0;
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
+    pcfr_leafnet* net = nullptr;
     int64_t t_host = 0;     // iterations enqueued
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
 };
@@ -758,6 +976,39 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->at<int32_t>(L.off_term), Hp, reach, cfv, s->at<uint16_t>(L.off_hc),
                            s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands), (int)L.chand_stride,
                            s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn));
+        if (tm) tm->after();
+    }
+    // depth-limit leaves: exact equity for all-in leaves (and for every leaf
+    // without a network), the network for the others
+    const int64_t n_eq_active = s->net ? P.n_allin : L.n_eq;
+    if (n_eq_active) {
+        constexpr int J = sizeof(T) == 8 ? 2 : 4;
+        dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)((n_eq_active + J - 1) / J));
+        const size_t lds = (size_t)J * 2 * Hp * sizeof(T);
+        if (tm) tm->before(4);
+        hipLaunchKernelGGL((k_equity_leaf<T, J>), grid, dim3(kBlock), lds, stream, s->at<int32_t>(L.off_eq),
+                           s->at<double>(L.off_eqpay), (int)n_eq_active, Hp, s->at<T>(L.off_et), reach, cfv);
+        if (tm) tm->after();
+    }
+    if (s->net && L.n_net) {
+        pcfr_leafnet* net = s->net;
+        const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
+        if (tm) tm->before(4);
+        hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, s->at<int32_t>(L.off_net),
+                           s->at<float>(L.off_spr), (int)L.n_next, s->at<int8_t>(L.off_next), Hp, (int)L.H, reach,
+                           s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_c2h), s->at<uint8_t>(L.off_hot),
+                           reinterpret_cast<uint16_t*>(net->ws + net->P.off_x), (int)net->P.pdims[0]);
+        if (tm) { tm->after(); tm->before(5); }
+        int32_t rc = leafnet_forward_staged(net, Mp, stream);
+        if (tm) tm->after();
+        if (rc) return rc;
+        if (tm) tm->before(4);
+        hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream,
+                           s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), (int)L.n_next,
+                           s->at<int8_t>(L.off_next), Hp, (int)L.H, reach, cfv, s->at<uint16_t>(L.off_hc),
+                           s->at<int16_t>(L.off_h2c), s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff),
+                           s->at<int16_t>(L.off_chands), reinterpret_cast<const float*>(net->ws + net->P.off_y),
+                           (int)net->P.pdims[net->P.L]);
         if (tm) tm->after();
     }
     for (int l = P.levels - 1; l >= 0; l--) {
@@ -908,6 +1159,39 @@ int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, co
     if ((rc = up(L.off_chands, P.chands.data(), sizeof(int16_t) * P.chands.size()))) return rc;
     if ((rc = up(L.off_sd, P.sd.data(), sizeof(int16_t) * L.n_boards * L.sd_stride))) return rc;
     if ((rc = up(L.off_sdn, P.sdn.data(), sizeof(int32_t) * L.n_boards))) return rc;
+    {
+        std::vector<int16_t> c2h(kCombos), h2c(L.Hp, -1);
+        for (int k = 0; k < kCombos; k++) c2h[k] = (int16_t)P.combo_hand[k];
+        for (int64_t h = 0; h < P.H; h++) h2c[h] = (int16_t)P.hand_combo[h];
+        if ((rc = up(L.off_c2h, c2h.data(), sizeof(int16_t) * kCombos))) return rc;
+        if ((rc = up(L.off_h2c, h2c.data(), sizeof(int16_t) * L.Hp))) return rc;
+        if ((rc = up(L.off_next, P.next_cards.data(), P.next_cards.size()))) return rc;
+        if ((rc = up(L.off_hot, P.board_hot.data(), 52))) return rc;
+        if ((rc = up(L.off_eq, P.eq_leaves.data(), sizeof(int32_t) * P.eq_leaves.size()))) return rc;
+        if ((rc = up(L.off_eqpay, P.eq_pay.data(), sizeof(double) * P.eq_pay.size()))) return rc;
+        if ((rc = up(L.off_net, P.net_leaves.data(), sizeof(int32_t) * P.net_leaves.size()))) return rc;
+        if ((rc = up(L.off_spr, P.net_spr.data(), sizeof(float) * P.net_spr.size()))) return rc;
+        if ((rc = up(L.off_potk, P.net_potk.data(), sizeof(double) * P.net_potk.size()))) return rc;
+        if (L.n_eq) {
+            std::vector<double> E;
+            try {
+                equity_matrix(s->tree.root_mask, P.hand_combo, E);
+            } catch (const std::bad_alloc&) {
+                set_error("out of host memory for the equity table");
+                return PCFR_E_OUT_OF_MEMORY;
+            }
+            std::vector<char> et(L.esz * L.Hp * L.Hp, 0);
+            for (int64_t h = 0; h < P.H; h++)
+                for (int64_t o = 0; o < P.H; o++) {
+                    const double v = E[(size_t)h * P.H + o];
+                    const size_t i = (size_t)o * L.Hp + h;   // transposed
+                    if (L.esz == 8) reinterpret_cast<double*>(et.data())[i] = v;
+                    else reinterpret_cast<float*>(et.data())[i] = (float)v;
+                }
+            if ((rc = up(L.off_et, et.data(), et.size()))) return rc;
+            HIPCHK(hipStreamSynchronize(s->stream));
+        }
+    }
     HIPCHK(hipMemsetAsync(s->ws + L.off_state, 0, sizeof(IterState), s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_R, 0, L.esz * L.rows * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_S, 0, L.esz * L.rows * L.Hp, s->stream));
@@ -932,6 +1216,30 @@ int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, co
     return PCFR_OK;
 }
 
+int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net) {
+    if (!s) { set_error("null solver"); return PCFR_E_INVALID_ARG; }
+    if (net) {
+        const LeafNetPlan& N = net->P;
+        if (N.dims[0] != 2 * kCombos + 53 || N.dims[N.L] != 2 * kCombos) {
+            set_error("leaf network must map 2*1326 + 53 inputs to 2*1326 outputs");
+            return PCFR_E_INVALID_ARG;
+        }
+        if (s->L.n_net * s->L.n_next > N.Mp) { set_error("leaf network max_batch below leaves x next cards"); return PCFR_E_INVALID_ARG; }
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->net = net;
+    if (s->graph) { (void)hipGraphExecDestroy(s->graph); s->graph = nullptr; }
+    if (s->graph_def) { (void)hipGraphDestroy(s->graph_def); s->graph_def = nullptr; }
+    return build_graph(s);
+}
+
+int32_t pcfr_leaf_rows(pcfr_solver* s, int32_t* n_leaves, int32_t* n_next) {
+    if (!s || !n_leaves || !n_next) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    *n_leaves = (int32_t)s->L.n_net;
+    *n_next = (int32_t)s->L.n_next;
+    return PCFR_OK;
+}
+
 int32_t pcfr_solver_free(pcfr_solver* s) {
     if (!s) return PCFR_OK;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
@@ -950,7 +1258,7 @@ int32_t pcfr_cfr_iterate(pcfr_solver* s, int32_t n) {
 
 int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* launches) {
     if (!s || n < 0 || !ms || !launches) { set_error("null argument or negative count"); return PCFR_E_INVALID_ARG; }
-    for (int k = 0; k < 4; k++) { ms[k] = 0; launches[k] = 0; }
+    for (int k = 0; k < 8; k++) { ms[k] = 0; launches[k] = 0; }
     for (int32_t i = 0; i < n; i++) {
         LaunchTimer tm;
         tm.stream = s->stream;

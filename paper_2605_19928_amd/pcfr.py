@@ -52,6 +52,20 @@ _SIGS = {
     "pcfr_tree_info": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pcfr_tree_export": (C.c_int32, [C.c_void_p] * 10),
     "pcfr_eval7_batch": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "pcfr_equity_table": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_leafnet_workspace_bytes": (C.c_int32, [C.c_int32] * 5 + [C.POINTER(C.c_size_t)]),
+    "pcfr_leafnet_create": (C.c_int32, [C.c_int32] * 5 + [C.c_void_p, C.c_size_t, C.c_void_p,
+                                                          C.POINTER(C.c_void_p)]),
+    "pcfr_leafnet_free": (C.c_int32, [C.c_void_p]),
+    "pcfr_leafnet_num_params": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "pcfr_leafnet_set_params": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_leafnet_get_params": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_leafnet_get_grads": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_leafnet_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "pcfr_leafnet_train_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                            C.c_float, C.POINTER(C.c_float)]),
+    "pcfr_solver_attach_leafnet": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_leaf_rows": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pcfr_solver_workspace_bytes": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.POINTER(C.c_size_t)]),
     "pcfr_solver_create": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.c_void_p, C.c_void_p, C.c_size_t,
                                        C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -130,6 +144,11 @@ class Tree:
         (self.n_nodes, self.n_decision, self.n_fold, self.n_showdown, self.n_chance, self.n_leaf,
          self.n_allin, self.n_levels, self.n_rows, self.n_hands, self.n_hands_padded) = (int(x) for x in info[:11])
 
+    def equity_table(self) -> np.ndarray:
+        out = np.zeros((NCOMBO, NCOMBO), dtype=np.float64)
+        _check(lib().pcfr_equity_table(self._h, _p(out)))
+        return out
+
     def export(self) -> dict:
         n = self.n_nodes
         out = {k: np.zeros(n, dtype=np.int32) for k in
@@ -195,10 +214,10 @@ class Solver:
         _check(lib().pcfr_cfr_iterate(self._h, int(n)))
 
     def profile(self, n: int):
-        """Run n iterations with per-launch event timing; returns (ms[4], launches[4])
-        for the classes bookkeeping, forward, terminal, backward."""
-        ms = np.zeros(4, dtype=np.float64)
-        cnt = np.zeros(4, dtype=np.int64)
+        """Run n iterations with per-launch event timing; returns (ms[8], launches[8])
+        for the classes bookkeeping, forward, terminal, backward, leaves, leaf GEMMs."""
+        ms = np.zeros(8, dtype=np.float64)
+        cnt = np.zeros(8, dtype=np.int64)
         _check(lib().pcfr_profile_iterations(self._h, int(n), _p(ms), _p(cnt)))
         return ms, cnt
 
@@ -239,10 +258,104 @@ class Solver:
         buf = (C.c_char * len(blob)).from_buffer_copy(blob)
         _check(lib().pcfr_load_state(self._h, buf, len(blob)))
 
+    def attach_leafnet(self, net: "LeafNet | None"):
+        _check(lib().pcfr_solver_attach_leafnet(self._h, net._h if net is not None else None))
+        self._net = net
+
+    def leaf_rows(self):
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().pcfr_leaf_rows(self._h, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
     def close(self):
         h = getattr(self, "_h", None)
         if h and _lib is not None:
             _lib.pcfr_solver_free(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+LEAF_D_IN = 2 * NCOMBO + 53
+LEAF_D_OUT = 2 * NCOMBO
+
+
+class LeafNet:
+    """ReLU MLP on the GPU (bf16 MFMA GEMMs, FP32 masters, Adam)."""
+
+    def __init__(self, d_in=LEAF_D_IN, width=1536, depth=4, d_out=LEAF_D_OUT, max_batch=2048, device="cuda"):
+        import torch
+
+        self.shape = (d_in, width, depth, d_out)
+        nbytes = C.c_size_t()
+        _check(lib().pcfr_leafnet_workspace_bytes(d_in, width, depth, d_out, max_batch, C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().pcfr_leafnet_create(d_in, width, depth, d_out, max_batch, C.c_void_p(ptr), int(nbytes.value),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        n = C.c_int64()
+        _check(lib().pcfr_leafnet_num_params(self._h, C.byref(n)))
+        self.n_params = int(n.value)
+
+    def layer_shapes(self):
+        d_in, width, depth, d_out = self.shape
+        dims = [d_in] + [width] * depth + [d_out]
+        return [(dims[i + 1], dims[i]) for i in range(len(dims) - 1)]
+
+    def set_params(self, layers):
+        """layers: list of (W [out, in], b [out]) arrays."""
+        flat = np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                               for W, b in layers]).astype(np.float32)
+        assert flat.size == self.n_params
+        _check(lib().pcfr_leafnet_set_params(self._h, _p(flat)))
+
+    def _unflat(self, flat):
+        out, k = [], 0
+        for o, i in self.layer_shapes():
+            W = flat[k:k + o * i].reshape(o, i)
+            k += o * i
+            b = flat[k:k + o]
+            k += o
+            out.append((W, b))
+        return out
+
+    def get_params(self):
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().pcfr_leafnet_get_params(self._h, _p(flat)))
+        return self._unflat(flat)
+
+    def get_grads(self):
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().pcfr_leafnet_get_grads(self._h, _p(flat)))
+        return self._unflat(flat)
+
+    def forward(self, x):
+        """x: torch float32 [m, d_in] on the device -> torch float32 [m, d_out]."""
+        import torch
+
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], self.shape[3]), dtype=torch.float32, device=self.device)
+        _check(lib().pcfr_leafnet_forward(self._h, C.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                          C.c_void_p(y.data_ptr())))
+        return y
+
+    def train_step(self, x, target, mask, lr: float, want_loss: bool = True):
+        loss = C.c_float()
+        _check(lib().pcfr_leafnet_train_step(self._h, C.c_void_p(x.contiguous().data_ptr()),
+                                             C.c_void_p(target.contiguous().data_ptr()),
+                                             C.c_void_p(mask.contiguous().data_ptr()), int(x.shape[0]), float(lr),
+                                             C.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pcfr_leafnet_free(h)
             self._h = None
 
     def __del__(self):

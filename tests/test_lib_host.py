@@ -31,7 +31,7 @@ def header_functions():
 def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(P.LIB_PATH)
     names = header_functions()
-    assert len(names) >= 19
+    assert len(names) >= 30
     for n in names:
         assert hasattr(L, n), n
     assert L.pcfr_abi_version() == 1
@@ -102,3 +102,14 @@ def test_invalid_specs_rejected(bad):
     with pytest.raises(P.PcfrError) as e:
         P.Tree(**bad)
     assert e.value.code == P.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("nb", [4, 3])
+def test_equity_table_matches_oracle(nb):
+    rng = np.random.default_rng(20 + nb)
+    board = I.draw_board(rng, nb)
+    spec = dict(board=board, pot=100, stacks=(400, 400), sizes=[75], allin=True, max_raises=1, depth_limit=1)
+    lib_t = P.Tree(**spec)
+    ora_t = O.Tree.holdem(**spec)
+    leaf = int(np.flatnonzero(ora_t.export()["type"] == O.T_LEAF)[0])
+    np.testing.assert_array_equal(lib_t.equity_table(), ora_t.equity_table(leaf))
