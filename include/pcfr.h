@@ -197,6 +197,25 @@ int32_t pcfr_state_bytes(pcfr_solver* s, size_t* bytes);
 int32_t pcfr_save_state(pcfr_solver* s, void* buf, size_t bytes);
 int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent subgames (river and turn, uneven sizes) solved together:
+ * their trees form one forest whose levels are swept by the same launches,
+ * so one graph replay advances every subgame by one iteration.  The handle is
+ * a pcfr_solver; the single-subgame calls act on subgame 0, the batch calls
+ * take a subgame index.  ranges: host [n][2][1326].  Depth-limited trees
+ * cannot be batched (PCFR_E_UNSUPPORTED).  Results are bitwise identical to
+ * solving each subgame alone. */
+int32_t pcfr_batch_workspace_bytes(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg,
+                                   size_t* bytes);
+int32_t pcfr_batch_create(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg,
+                          const double* ranges, void* workspace, size_t workspace_bytes, void* stream,
+                          pcfr_solver** out);
+int32_t pcfr_batch_size(const pcfr_solver* s, int32_t* n);
+int32_t pcfr_batch_get_strategy(pcfr_solver* s, int32_t sub, int32_t node, int32_t which, double* out);
+int32_t pcfr_batch_get_root_cfv(pcfr_solver* s, int32_t sub, int32_t which, double* out);
+/* chips_per_hand: host [n]; br: host [n][2] or NULL.  Synchronises. */
+int32_t pcfr_batch_exploitability(pcfr_solver* s, double* chips_per_hand, double* br);
+
 /* ---------------------------------------------------------------- leaf network
  * The value network f_theta of depth-limited solving (Sec. 3): a ReLU MLP
  * d_in -> width x depth -> d_out evaluated for all leaves of an iteration in

@@ -606,10 +606,15 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
 }
 
 // ------------------------------------------------------------ small kernels
+// Root values of every subgame -> a slot that later sweeps do not overwrite.
 template <typename T>
-__global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, int64_t n) {
+__global__ void k_gather_roots(const T* __restrict__ cfv, const int32_t* __restrict__ roots, int n_sub, int Hp,
+                               T* __restrict__ dst) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
+    const int64_t per = 2 * (int64_t)Hp;
+    if (i >= per * n_sub) return;
+    const int64_t g = i / per;
+    dst[i] = cfv[(int64_t)roots[g] * per + (i - g * per)];
 }
 
 // Strategy of one decision node for every hand: which 0 = average, 1 = current.
@@ -647,25 +652,32 @@ struct Plan {
     size_t esz;
     size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_next, off_hot, off_c2h, off_h2c, total;
+        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, total;
     size_t lds_bytes;
 };
 
 struct Prepared {
+    // forest of subgames: node ids are global, subgame k's nodes start at node_base[k]
+    int32_t n_sub = 0;
+    std::vector<int64_t> node_base, root_node;
     std::vector<DNode> nodes;
     std::vector<int32_t> fwd, term;
     std::vector<int64_t> fwd_off;         // per level start into fwd (size levels+1)
-    std::vector<uint16_t> hcards;         // [Hp]
-    std::vector<int32_t> coff;            // [53]
-    std::vector<int16_t> chands;
+    std::vector<uint16_t> hcards;         // [n_sub][Hp]
+    std::vector<int32_t> coff;            // [n_sub][53]
+    std::vector<int16_t> chands;          // [n_sub][chand_stride]
+    int64_t chand_stride = 0;
     std::vector<int16_t> sd;              // [boards][sd_stride]
     std::vector<int32_t> sdn;
-    std::vector<int32_t> hand_combo;      // [H]
-    std::vector<int32_t> combo_hand;      // [1326], -1 if blocked
-    int64_t Hp = 0, H = 0, sd_stride = 0;
+    std::vector<std::vector<int32_t>> hand_combo;   // per subgame [H_k]
+    std::vector<std::vector<int32_t>> combo_hand;   // per subgame [1326], -1 if blocked
+    std::vector<int64_t> Hs;              // hands per subgame
+    std::vector<uint64_t> root_mask;
+    int64_t Hp = 0, H = 0, sd_stride = 0;  // H: hands of subgame 0
     int32_t levels = 0, max_a = 0;
-    // depth-limit leaves: all-in leaves first, then network leaves (so the
-    // all-in prefix is what stays exact when a network is attached)
+    // depth-limit leaves (single subgame only): all-in leaves first, then
+    // network leaves (so the all-in prefix is what stays exact when a
+    // network is attached)
     std::vector<int32_t> eq_leaves;
     std::vector<double> eq_pay;
     int64_t n_allin = 0;
@@ -676,93 +688,120 @@ struct Prepared {
     std::vector<uint8_t> board_hot;
 };
 
-// Host preprocessing: node records, level work lists, hand cards, per-card
-// hand lists, and one strength-sorted table per showdown board.
-static int32_t prepare(const Tree& t, Prepared& P) {
+// Host preprocessing of a forest of subgames: node records, merged level work
+// lists, hand cards, per-card hand lists, and one strength-sorted table per
+// (subgame, showdown board).
+static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
     const ComboTable& cc = combos();
-    P.combo_hand.assign(kCombos, -1);
-    for (int k = 0; k < kCombos; k++) {
-        if ((t.root_mask >> cc.hi[k] & 1ull) || (t.root_mask >> cc.lo[k] & 1ull)) continue;
-        P.combo_hand[k] = (int32_t)P.hand_combo.size();
-        P.hand_combo.push_back(k);
+    const int32_t K = (int32_t)trees.size();
+    P.n_sub = K;
+    P.hand_combo.assign(K, {});
+    P.combo_hand.assign(K, std::vector<int32_t>(kCombos, -1));
+    P.Hs.assign(K, 0);
+    P.root_mask.assign(K, 0);
+    int64_t Hmax = 0;
+    for (int32_t g = 0; g < K; g++) {
+        const uint64_t rm = trees[g]->root_mask;
+        P.root_mask[g] = rm;
+        for (int k = 0; k < kCombos; k++) {
+            if ((rm >> cc.hi[k] & 1ull) || (rm >> cc.lo[k] & 1ull)) continue;
+            P.combo_hand[g][k] = (int32_t)P.hand_combo[g].size();
+            P.hand_combo[g].push_back(k);
+        }
+        P.Hs[g] = (int64_t)P.hand_combo[g].size();
+        Hmax = std::max(Hmax, P.Hs[g]);
     }
-    P.H = (int64_t)P.hand_combo.size();
-    P.Hp = (P.H + 63) / 64 * 64;
+    P.H = P.Hs[0];
+    P.Hp = (Hmax + 63) / 64 * 64;
     const int64_t Hp = P.Hp;
-    P.hcards.assign(Hp, 0xffff);
-    for (int64_t h = 0; h < P.H; h++) {
-        int k = P.hand_combo[h];
-        P.hcards[h] = (uint16_t)(cc.hi[k] | (cc.lo[k] << 8));
-    }
-    // per-card hand lists
-    P.coff.assign(53, 0);
-    {
+    P.hcards.assign((size_t)K * Hp, 0xffff);
+    P.coff.assign((size_t)K * 53, 0);
+    P.chand_stride = 2 * Hmax;
+    P.chands.assign((size_t)K * P.chand_stride, 0);
+    for (int32_t g = 0; g < K; g++) {
+        for (int64_t h = 0; h < P.Hs[g]; h++) {
+            int k = P.hand_combo[g][h];
+            P.hcards[(size_t)g * Hp + h] = (uint16_t)(cc.hi[k] | (cc.lo[k] << 8));
+        }
         std::vector<std::vector<int16_t>> lists(52);
-        for (int64_t h = 0; h < P.H; h++) {
-            int k = P.hand_combo[h];
+        for (int64_t h = 0; h < P.Hs[g]; h++) {
+            int k = P.hand_combo[g][h];
             lists[cc.hi[k]].push_back((int16_t)h);
             lists[cc.lo[k]].push_back((int16_t)h);
         }
+        int32_t pos = 0;
         for (int c = 0; c < 52; c++) {
-            P.coff[c] = (int32_t)P.chands.size();
-            for (auto x : lists[c]) P.chands.push_back(x);
+            P.coff[(size_t)g * 53 + c] = pos;
+            for (auto x : lists[c]) P.chands[(size_t)g * P.chand_stride + pos++] = x;
         }
-        P.coff[52] = (int32_t)P.chands.size();
+        P.coff[(size_t)g * 53 + 52] = pos;
     }
-    // showdown boards
     P.sd_stride = (7 * Hp + kSdHeader + 2 * Hp + kSdHeader + 63) / 64 * 64;
-    std::map<uint64_t, int32_t> board_id;
-    const int64_t N = (int64_t)t.nodes.size();
+    std::map<std::pair<int32_t, uint64_t>, int32_t> board_id;
+    int64_t N = 0;
+    P.node_base.assign(K, 0);
+    P.root_node.assign(K, 0);
+    P.levels = 0;
+    for (int32_t g = 0; g < K; g++) {
+        P.node_base[g] = N;
+        P.root_node[g] = N;
+        N += (int64_t)trees[g]->nodes.size();
+        P.levels = std::max(P.levels, trees[g]->n_levels);
+    }
     P.nodes.resize(N);
-    P.levels = t.n_levels;
-    std::vector<std::vector<int32_t>> per_level(t.n_levels);
-    for (int64_t i = 0; i < N; i++) {
-        const Node& s = t.nodes[i];
-        DNode d{};
-        d.type = s.type; d.player = s.player; d.first_child = s.first_child; d.n_child = s.n_child;
-        d.rs = -1; d.aux = 0; d.card = s.chance_card; d.sub = 0; d.pay = 0.0;
-        // cards dealt since the root
-        uint64_t extra = s.board_mask & ~t.root_mask;
-        int dd[2] = {0xff, 0xff}, nd = 0;
-        for (int c = 0; c < 52 && nd < 2; c++) if (extra >> c & 1ull) dd[nd++] = c;
-        d.dead = dd[0] | (dd[1] << 8);
-        P.nodes[i] = d;
-    }
+    std::vector<std::vector<int32_t>> per_level(P.levels);
     int64_t rows = 0;
-    for (int64_t i = 0; i < N; i++) {
-        const Node& s = t.nodes[i];
-        DNode& d = P.nodes[i];
-        if (s.type == PCFR_NODE_DECISION) {
-            d.rs = (int32_t)rows;
-            rows += s.n_child;
-            if (s.n_child > kMaxActions || s.n_child < 1) { set_error("unsupported action count"); return PCFR_E_TOO_LARGE; }
-            P.max_a = std::max(P.max_a, s.n_child);
-            per_level[s.depth].push_back((int32_t)i);
-        } else if (s.type == PCFR_NODE_CHANCE) {
-            int nb = __builtin_popcountll(s.board_mask);
-            d.aux = 52 - nb - 4;
-            per_level[s.depth].push_back((int32_t)i);
-        } else if (s.type == PCFR_NODE_FOLD) {
-            d.pay = (double)s.contrib[s.player];
-            P.term.push_back((int32_t)i);
-        } else if (s.type == PCFR_NODE_SHOWDOWN) {
-            d.pay = (double)s.contrib[0];
-            auto it = board_id.find(s.board_mask);
-            if (it == board_id.end()) it = board_id.emplace(s.board_mask, (int32_t)board_id.size()).first;
-            d.aux = it->second;
-            P.term.push_back((int32_t)i);
-        } else if (s.type == PCFR_NODE_ALLIN_LEAF || s.type == PCFR_NODE_LEAF) {
-            if (s.contrib[0] != s.contrib[1]) { set_error("leaf with unequal contributions"); return PCFR_E_INVALID_ARG; }
-        } else {
-            set_error("unknown node type");
-            return PCFR_E_INVALID_ARG;
+    for (int32_t g = 0; g < K; g++) {
+        const Tree& t = *trees[g];
+        const int64_t base = P.node_base[g];
+        for (size_t i = 0; i < t.nodes.size(); i++) {
+            const Node& s = t.nodes[i];
+            const int64_t gi = base + (int64_t)i;
+            DNode d{};
+            d.type = s.type; d.player = s.player; d.n_child = s.n_child;
+            d.first_child = s.first_child < 0 ? -1 : (int32_t)(base + s.first_child);
+            d.rs = -1; d.aux = 0; d.card = s.chance_card; d.sub = g; d.pay = 0.0;
+            uint64_t extra = s.board_mask & ~t.root_mask;
+            int dd[2] = {0xff, 0xff}, nd = 0;
+            for (int c = 0; c < 52 && nd < 2; c++) if (extra >> c & 1ull) dd[nd++] = c;
+            d.dead = dd[0] | (dd[1] << 8);
+            if (s.type == PCFR_NODE_DECISION) {
+                d.rs = (int32_t)rows;
+                rows += s.n_child;
+                if (s.n_child > kMaxActions || s.n_child < 1) { set_error("unsupported action count"); return PCFR_E_TOO_LARGE; }
+                P.max_a = std::max(P.max_a, s.n_child);
+                per_level[s.depth].push_back((int32_t)gi);
+            } else if (s.type == PCFR_NODE_CHANCE) {
+                d.aux = 52 - __builtin_popcountll(s.board_mask) - 4;
+                per_level[s.depth].push_back((int32_t)gi);
+            } else if (s.type == PCFR_NODE_FOLD) {
+                d.pay = (double)s.contrib[s.player];
+                P.term.push_back((int32_t)gi);
+            } else if (s.type == PCFR_NODE_SHOWDOWN) {
+                d.pay = (double)s.contrib[0];
+                auto key = std::make_pair(g, s.board_mask);
+                auto it = board_id.find(key);
+                if (it == board_id.end()) it = board_id.emplace(key, (int32_t)board_id.size()).first;
+                d.aux = it->second;
+                P.term.push_back((int32_t)gi);
+            } else if (s.type == PCFR_NODE_ALLIN_LEAF || s.type == PCFR_NODE_LEAF) {
+                if (K > 1) { set_error("depth-limited subgames cannot be batched"); return PCFR_E_UNSUPPORTED; }
+                if (s.contrib[0] != s.contrib[1]) { set_error("leaf with unequal contributions"); return PCFR_E_INVALID_ARG; }
+            } else {
+                set_error("unknown node type");
+                return PCFR_E_INVALID_ARG;
+            }
+            P.nodes[gi] = d;
         }
+        if (rows > (int64_t)INT32_MAX) { set_error("too many action rows"); return PCFR_E_TOO_LARGE; }
     }
-    {
+    if (N > (int64_t)INT32_MAX) { set_error("too many nodes"); return PCFR_E_TOO_LARGE; }
+    if (K == 1) {
+        const Tree& t = *trees[0];
         const int64_t eff = std::min(t.spec.stack[0], t.spec.stack[1]);
         const int64_t cap = t.spec.pot / 2 + eff;
         for (int pass = 0; pass < 2; pass++)
-            for (int64_t i = 0; i < N; i++) {
+            for (size_t i = 0; i < t.nodes.size(); i++) {
                 const Node& s = t.nodes[i];
                 if (s.type != (pass == 0 ? PCFR_NODE_ALLIN_LEAF : PCFR_NODE_LEAF)) continue;
                 P.eq_leaves.push_back((int32_t)i);
@@ -775,29 +814,31 @@ static int32_t prepare(const Tree& t, Prepared& P) {
                 }
             }
         P.n_allin = (int64_t)t.count[PCFR_NODE_ALLIN_LEAF];
-        P.board_hot.assign(52, 0);
-        for (int c = 0; c < 52; c++) {
-            if (t.root_mask >> c & 1ull) P.board_hot[c] = 1;
-            else P.next_cards.push_back((int8_t)c);
-        }
     }
-    P.fwd_off.assign(t.n_levels + 1, 0);
-    for (int l = 0; l < t.n_levels; l++) {
+    P.board_hot.assign(52, 0);
+    for (int c = 0; c < 52; c++) {
+        if (P.root_mask[0] >> c & 1ull) P.board_hot[c] = 1;
+        else P.next_cards.push_back((int8_t)c);
+    }
+    P.fwd_off.assign(P.levels + 1, 0);
+    for (int l = 0; l < P.levels; l++) {
         P.fwd_off[l] = (int64_t)P.fwd.size();
         for (auto x : per_level[l]) P.fwd.push_back(x);
     }
-    P.fwd_off[t.n_levels] = (int64_t)P.fwd.size();
+    P.fwd_off[P.levels] = (int64_t)P.fwd.size();
     // strength tables
     const int64_t nbds = (int64_t)board_id.size();
     P.sd.assign((size_t)std::max<int64_t>(nbds, 1) * P.sd_stride, 0);
     P.sdn.assign(std::max<int64_t>(nbds, 1), 0);
     for (auto& kv : board_id) {
-        const uint64_t bm = kv.first;
+        const int32_t g = kv.first.first;
+        const uint64_t bm = kv.first.second;
+        const std::vector<int32_t>& hcmb = P.hand_combo[g];
         int16_t* tb = P.sd.data() + (size_t)kv.second * P.sd_stride;
         std::vector<std::pair<uint32_t, int32_t>> alive;
         std::vector<char> is_alive(Hp, 0);
-        for (int64_t h = 0; h < P.H; h++) {
-            int k = P.hand_combo[h];
+        for (int64_t h = 0; h < P.Hs[g]; h++) {
+            int k = hcmb[h];
             uint64_t hm = (1ull << cc.hi[k]) | (1ull << cc.lo[k]);
             if (hm & bm) continue;
             alive.push_back({eval7_mask(hm | bm), (int32_t)h});
@@ -820,7 +861,7 @@ static int32_t prepare(const Tree& t, Prepared& P) {
         // per-card lists of sorted positions, each followed by a total slot
         std::vector<std::vector<int>> lists(52);
         for (int q = 0; q < Hb; q++) {
-            int k = P.hand_combo[alive[q].second];
+            int k = hcmb[alive[q].second];
             lists[cc.hi[k]].push_back(q);
             lists[cc.lo[k]].push_back(q);
         }
@@ -829,7 +870,7 @@ static int32_t prepare(const Tree& t, Prepared& P) {
         for (int c = 0; c < 52; c++) {
             coff[c] = (int16_t)pos;
             for (int q : lists[c]) {
-                int k = P.hand_combo[alive[q].second];
+                int k = hcmb[alive[q].second];
                 if (cc.hi[k] == c) where_hi[q] = pos; else where_lo[q] = pos;
                 clist[pos++] = (int16_t)q;
             }
@@ -845,7 +886,7 @@ static int32_t prepare(const Tree& t, Prepared& P) {
             hi = (int16_t)(b + 1);
         };
         for (int q = 0; q < Hb; q++) {
-            int k = P.hand_combo[alive[q].second];
+            int k = hcmb[alive[q].second];
             group(cc.hi[k], where_hi[q], alo[q], ahi[q]);
             group(cc.lo[k], where_lo[q], blo[q], bhi[q]);
         }
@@ -853,15 +894,15 @@ static int32_t prepare(const Tree& t, Prepared& P) {
     return PCFR_OK;
 }
 
-static void make_plan(const Prepared& P, const Tree& t, int dtype, Plan& L) {
+static void make_plan(const Prepared& P, int64_t rows, int dtype, Plan& L) {
     L.N = (int64_t)P.nodes.size();
-    L.rows = t.rows;
+    L.rows = rows;
     L.Hp = P.Hp;
     L.H = P.H;
     L.n_boards = (int64_t)P.sdn.size();
     L.term = (int64_t)P.term.size();
     L.fwd = (int64_t)P.fwd.size();
-    L.chand_stride = (int64_t)P.chands.size();
+    L.chand_stride = P.chand_stride;
     L.sd_stride = P.sd_stride;
     L.esz = dtype == PCFR_F64 ? 8 : 4;
     size_t o = 0;
@@ -869,9 +910,9 @@ static void make_plan(const Prepared& P, const Tree& t, int dtype, Plan& L) {
     L.off_nodes = take(sizeof(DNode) * L.N);
     L.off_fwd = take(sizeof(int32_t) * std::max<int64_t>(L.fwd, 1));
     L.off_term = take(sizeof(int32_t) * std::max<int64_t>(L.term, 1));
-    L.off_hc = take(sizeof(uint16_t) * L.Hp);
-    L.off_coff = take(sizeof(int32_t) * 53);
-    L.off_chands = take(sizeof(int16_t) * std::max<int64_t>(L.chand_stride, 1));
+    L.off_hc = take(sizeof(uint16_t) * L.Hp * P.n_sub);
+    L.off_coff = take(sizeof(int32_t) * 53 * P.n_sub);
+    L.off_chands = take(sizeof(int16_t) * std::max<int64_t>(L.chand_stride, 1) * P.n_sub);
     L.off_sd = take(sizeof(int16_t) * L.n_boards * L.sd_stride);
     L.off_sdn = take(sizeof(int32_t) * L.n_boards);
     L.off_state = take(sizeof(IterState));
@@ -879,7 +920,7 @@ static void make_plan(const Prepared& P, const Tree& t, int dtype, Plan& L) {
     L.off_S = take(L.esz * L.rows * L.Hp);
     L.off_reach = take(L.esz * L.N * 2 * L.Hp);
     L.off_cfv = take(L.esz * L.N * 2 * L.Hp);
-    L.off_root = take(L.esz * 2 * L.Hp);
+    L.off_root = take(L.esz * 2 * L.Hp * P.n_sub);
     L.off_stage = take(L.esz * kMaxActions * L.Hp);
     L.n_eq = (int64_t)P.eq_leaves.size();
     L.n_net = (int64_t)P.net_leaves.size();
@@ -894,6 +935,7 @@ static void make_plan(const Prepared& P, const Tree& t, int dtype, Plan& L) {
     L.off_hot = take(64);
     L.off_c2h = take(sizeof(int16_t) * kCombos);
     L.off_h2c = take(sizeof(int16_t) * L.Hp);
+    L.off_roots = take(sizeof(int32_t) * P.n_sub);
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
     L.lds_bytes = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock);
@@ -904,14 +946,14 @@ static void make_plan(const Prepared& P, const Tree& t, int dtype, Plan& L) {
 using namespace pcfr;
 
 struct pcfr_solver {
-    Tree tree;
+    std::vector<Tree> trees;
     pcfr_solver_cfg cfg;
     Prepared P;
     Plan L;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
-    double ranges[2][kCombos];
-    double pair_mass = 0;
+    std::vector<double> ranges;       // [n_sub][2][1326]
+    std::vector<double> pair_mass;    // [n_sub]
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
     pcfr_leafnet* net = nullptr;
@@ -1022,10 +1064,10 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (tm) tm->after();
     }
     if (MODE == MODE_ITER) {
-        int64_t n = 2 * L.Hp;
+        int64_t n = 2 * L.Hp * P.n_sub;
         if (tm) tm->before(0);
-        hipLaunchKernelGGL((k_copy<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, cfv,
-                           s->at<T>(L.off_root), n);
+        hipLaunchKernelGGL((k_gather_roots<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, cfv,
+                           s->at<int32_t>(L.off_roots), P.n_sub, Hp, s->at<T>(L.off_root));
         if (tm) tm->after();
     }
     return hip_check(hipGetLastError(), "kernel launch");
@@ -1057,15 +1099,15 @@ static int32_t build_graph(pcfr_solver* s) {
     return PCFR_OK;
 }
 
-// Copy a [rows][Hp] device block (solver dtype) into host doubles [rows][1326].
-static int32_t fetch_hands(pcfr_solver* s, const void* dev, int rows, double* out) {
+// Copy a [rows][Hp] device block (solver dtype) of subgame g into host doubles [rows][1326].
+static int32_t fetch_hands(pcfr_solver* s, const void* dev, int rows, double* out, int32_t g = 0) {
     const Plan& L = s->L;
     std::vector<char> buf(L.esz * rows * L.Hp);
     HIPCHK(hipMemcpyAsync(buf.data(), dev, buf.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     for (int r = 0; r < rows; r++)
         for (int k = 0; k < kCombos; k++) {
-            int h = s->P.combo_hand[k];
+            int h = s->P.combo_hand[g][k];
             double v = 0;
             if (h >= 0) {
                 size_t i = (size_t)r * L.Hp + h;
@@ -1078,24 +1120,9 @@ static int32_t fetch_hands(pcfr_solver* s, const void* dev, int rows, double* ou
 
 }  // namespace pcfr
 
-extern "C" {
+namespace pcfr {
 
-int32_t pcfr_solver_workspace_bytes(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, size_t* bytes) {
-    if (!tree || !cfg || !bytes) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
-    if (cfg->dtype != PCFR_F32 && cfg->dtype != PCFR_F64) { set_error("dtype must be PCFR_F32 or PCFR_F64"); return PCFR_E_INVALID_ARG; }
-    Prepared P;
-    int32_t rc;
-    try { rc = prepare(tree->t, P); } catch (const std::bad_alloc&) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
-    if (rc != PCFR_OK) return rc;
-    Plan L;
-    make_plan(P, tree->t, cfg->dtype, L);
-    *bytes = L.total;
-    return PCFR_OK;
-}
-
-int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, const double* ranges, void* workspace,
-                           size_t workspace_bytes, void* stream, pcfr_solver** out) {
-    if (!tree || !cfg || !ranges || !workspace || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+static int32_t check_cfg(const pcfr_solver_cfg* cfg) {
     if (cfg->dtype != PCFR_F32 && cfg->dtype != PCFR_F64) { set_error("dtype must be PCFR_F32 or PCFR_F64"); return PCFR_E_INVALID_ARG; }
     if (cfg->variant != PCFR_DCFR) { set_error("only the DCFR update is implemented"); return PCFR_E_UNSUPPORTED; }
     if (cfg->alternating != 0) { set_error("only simultaneous updates are implemented"); return PCFR_E_UNSUPPORTED; }
@@ -1103,54 +1130,90 @@ int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, co
         set_error("alpha, beta, gamma must be finite");
         return PCFR_E_INVALID_ARG;
     }
+    return PCFR_OK;
+}
+
+static int32_t workspace_for(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg, size_t* bytes) {
+    if (!trees || n < 1 || !cfg || !bytes) { set_error("null argument or empty batch"); return PCFR_E_INVALID_ARG; }
+    int32_t rc = check_cfg(cfg);
+    if (rc) return rc;
+    std::vector<const Tree*> tv;
+    int64_t rows = 0;
+    for (int32_t i = 0; i < n; i++) {
+        if (!trees[i]) { set_error("null tree"); return PCFR_E_INVALID_ARG; }
+        tv.push_back(&trees[i]->t);
+        rows += trees[i]->t.rows;
+    }
+    Prepared P;
+    try { rc = prepare(tv, P); } catch (const std::bad_alloc&) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
+    if (rc != PCFR_OK) return rc;
+    Plan L;
+    make_plan(P, rows, cfg->dtype, L);
+    *bytes = L.total;
+    return PCFR_OK;
+}
+
+static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg, const double* ranges,
+                           void* workspace, size_t workspace_bytes, void* stream, pcfr_solver** out) {
+    if (!trees || n < 1 || !cfg || !ranges || !workspace || !out) { set_error("null argument or empty batch"); return PCFR_E_INVALID_ARG; }
+    int32_t rc = check_cfg(cfg);
+    if (rc) return rc;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) { set_error("workspace must be 256-byte aligned"); return PCFR_E_INVALID_ARG; }
     pcfr_solver* s = new (std::nothrow) pcfr_solver;
     if (!s) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
     std::unique_ptr<pcfr_solver> guard(s);
+    int64_t rows = 0;
     try {
-        s->tree = tree->t;
-        int32_t rc = prepare(s->tree, s->P);
+        for (int32_t i = 0; i < n; i++) {
+            if (!trees[i]) { set_error("null tree"); return PCFR_E_INVALID_ARG; }
+            s->trees.push_back(trees[i]->t);
+            rows += trees[i]->t.rows;
+        }
+        std::vector<const Tree*> tv;
+        for (auto& t : s->trees) tv.push_back(&t);
+        rc = prepare(tv, s->P);
         if (rc != PCFR_OK) return rc;
     } catch (const std::bad_alloc&) {
         set_error("out of host memory");
         return PCFR_E_OUT_OF_MEMORY;
     }
     s->cfg = *cfg;
-    make_plan(s->P, s->tree, cfg->dtype, s->L);
+    make_plan(s->P, rows, cfg->dtype, s->L);
     const Plan& L = s->L;
-    if (workspace_bytes < L.total) { set_error("workspace smaller than pcfr_solver_workspace_bytes"); return PCFR_E_OUT_OF_MEMORY; }
+    const Prepared& P = s->P;
+    if (workspace_bytes < L.total) { set_error("workspace smaller than the size the library asked for"); return PCFR_E_OUT_OF_MEMORY; }
     if (L.lds_bytes > 65536) { set_error("hand count too large for the showdown kernel"); return PCFR_E_TOO_LARGE; }
-    // ranges
+    // ranges and the joint mass of compatible pairs: r0 . (total1 - per-card sums + r1)
     const ComboTable& cc = combos();
-    double mass[2] = {0, 0};
-    for (int p = 0; p < 2; p++)
-        for (int k = 0; k < kCombos; k++) {
-            double v = ranges[p * kCombos + k];
-            if (!std::isfinite(v) || v < 0) { set_error("ranges must be finite and >= 0"); return PCFR_E_INVALID_ARG; }
-            if (s->P.combo_hand[k] < 0 && v != 0) { set_error("range mass on a combo blocked by the board"); return PCFR_E_INVALID_ARG; }
-            s->ranges[p][k] = v;
-            mass[p] += v;
-        }
-    // joint mass of compatible pairs: r0 . (total1 - per-card sums + r1)
-    {
+    s->ranges.assign((size_t)n * 2 * kCombos, 0.0);
+    s->pair_mass.assign(n, 0.0);
+    for (int32_t g = 0; g < n; g++) {
+        double mass[2] = {0, 0};
+        double* rg = &s->ranges[(size_t)g * 2 * kCombos];
+        for (int p = 0; p < 2; p++)
+            for (int k = 0; k < kCombos; k++) {
+                double v = ranges[((size_t)g * 2 + p) * kCombos + k];
+                if (!std::isfinite(v) || v < 0) { set_error("ranges must be finite and >= 0"); return PCFR_E_INVALID_ARG; }
+                if (P.combo_hand[g][k] < 0 && v != 0) { set_error("range mass on a combo blocked by the board"); return PCFR_E_INVALID_ARG; }
+                rg[p * kCombos + k] = v;
+                mass[p] += v;
+            }
         double card1[52] = {0};
-        for (int k = 0; k < kCombos; k++) { card1[cc.hi[k]] += s->ranges[1][k]; card1[cc.lo[k]] += s->ranges[1][k]; }
+        for (int k = 0; k < kCombos; k++) { card1[cc.hi[k]] += rg[kCombos + k]; card1[cc.lo[k]] += rg[kCombos + k]; }
         double z = 0;
         for (int k = 0; k < kCombos; k++) {
-            if (s->ranges[0][k] == 0) continue;
-            z += s->ranges[0][k] * (mass[1] - card1[cc.hi[k]] - card1[cc.lo[k]] + s->ranges[1][k]);
+            if (rg[k] == 0) continue;
+            z += rg[k] * (mass[1] - card1[cc.hi[k]] - card1[cc.lo[k]] + rg[kCombos + k]);
         }
-        s->pair_mass = z;
+        s->pair_mass[g] = z;
         if (!(z > 0)) { set_error("no compatible pair of hands carries mass"); return PCFR_E_INVALID_ARG; }
     }
     s->stream = reinterpret_cast<hipStream_t>(stream);
     s->ws = reinterpret_cast<char*>(workspace);
-    const Prepared& P = s->P;
     auto up = [&](size_t off, const void* src, size_t bytes) -> int32_t {
         if (!bytes) return PCFR_OK;
         return hip_check(hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream), "upload");
     };
-    int32_t rc;
     if ((rc = up(L.off_nodes, P.nodes.data(), sizeof(DNode) * P.nodes.size()))) return rc;
     if ((rc = up(L.off_fwd, P.fwd.data(), sizeof(int32_t) * P.fwd.size()))) return rc;
     if ((rc = up(L.off_term, P.term.data(), sizeof(int32_t) * P.term.size()))) return rc;
@@ -1159,10 +1222,13 @@ int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, co
     if ((rc = up(L.off_chands, P.chands.data(), sizeof(int16_t) * P.chands.size()))) return rc;
     if ((rc = up(L.off_sd, P.sd.data(), sizeof(int16_t) * L.n_boards * L.sd_stride))) return rc;
     if ((rc = up(L.off_sdn, P.sdn.data(), sizeof(int32_t) * L.n_boards))) return rc;
+    std::vector<int32_t> roots(n);
+    for (int32_t g = 0; g < n; g++) roots[g] = (int32_t)P.root_node[g];
+    if ((rc = up(L.off_roots, roots.data(), sizeof(int32_t) * n))) return rc;
     {
         std::vector<int16_t> c2h(kCombos), h2c(L.Hp, -1);
-        for (int k = 0; k < kCombos; k++) c2h[k] = (int16_t)P.combo_hand[k];
-        for (int64_t h = 0; h < P.H; h++) h2c[h] = (int16_t)P.hand_combo[h];
+        for (int k = 0; k < kCombos; k++) c2h[k] = (int16_t)P.combo_hand[0][k];
+        for (int64_t h = 0; h < P.H; h++) h2c[h] = (int16_t)P.hand_combo[0][h];
         if ((rc = up(L.off_c2h, c2h.data(), sizeof(int16_t) * kCombos))) return rc;
         if ((rc = up(L.off_h2c, h2c.data(), sizeof(int16_t) * L.Hp))) return rc;
         if ((rc = up(L.off_next, P.next_cards.data(), P.next_cards.size()))) return rc;
@@ -1175,7 +1241,7 @@ int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, co
         if (L.n_eq) {
             std::vector<double> E;
             try {
-                equity_matrix(s->tree.root_mask, P.hand_combo, E);
+                equity_matrix(P.root_mask[0], P.hand_combo[0], E);
             } catch (const std::bad_alloc&) {
                 set_error("out of host memory for the equity table");
                 return PCFR_E_OUT_OF_MEMORY;
@@ -1197,22 +1263,120 @@ int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, co
     HIPCHK(hipMemsetAsync(s->ws + L.off_S, 0, L.esz * L.rows * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_reach, 0, L.esz * L.N * 2 * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_cfv, 0, L.esz * L.N * 2 * L.Hp, s->stream));
-    HIPCHK(hipMemsetAsync(s->ws + L.off_root, 0, L.esz * 2 * L.Hp, s->stream));
-    // root reach = ranges in hand order (node 0's reach slot, never written again)
+    HIPCHK(hipMemsetAsync(s->ws + L.off_root, 0, L.esz * 2 * L.Hp * n, s->stream));
+    // root reach = ranges in hand order (the roots' reach slots are never written again)
     {
         std::vector<char> rr(L.esz * 2 * L.Hp, 0);
-        for (int p = 0; p < 2; p++)
-            for (int64_t h = 0; h < P.H; h++) {
-                double v = s->ranges[p][P.hand_combo[h]];
-                size_t i = (size_t)p * L.Hp + h;
-                if (L.esz == 8) reinterpret_cast<double*>(rr.data())[i] = v;
-                else reinterpret_cast<float*>(rr.data())[i] = (float)v;
-            }
-        if ((rc = up(L.off_reach, rr.data(), rr.size()))) return rc;
-        HIPCHK(hipStreamSynchronize(s->stream));
+        for (int32_t g = 0; g < n; g++) {
+            std::fill(rr.begin(), rr.end(), 0);
+            for (int p = 0; p < 2; p++)
+                for (int64_t h = 0; h < P.Hs[g]; h++) {
+                    double v = s->ranges[((size_t)g * 2 + p) * kCombos + P.hand_combo[g][h]];
+                    size_t i = (size_t)p * L.Hp + h;
+                    if (L.esz == 8) reinterpret_cast<double*>(rr.data())[i] = v;
+                    else reinterpret_cast<float*>(rr.data())[i] = (float)v;
+                }
+            if ((rc = up(L.off_reach + L.esz * (size_t)P.root_node[g] * 2 * L.Hp, rr.data(), rr.size()))) return rc;
+            HIPCHK(hipStreamSynchronize(s->stream));
+        }
     }
     if ((rc = build_graph(s))) return rc;
     *out = guard.release();
+    return PCFR_OK;
+}
+
+static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t which, double* out) {
+    if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (which != PCFR_AVG && which != PCFR_CURRENT) { set_error("which must be PCFR_AVG or PCFR_CURRENT"); return PCFR_E_INVALID_ARG; }
+    if (g < 0 || g >= s->P.n_sub) { set_error("subgame index out of range"); return PCFR_E_INVALID_ARG; }
+    const int64_t nn = (int64_t)s->trees[g].nodes.size();
+    if (node < 0 || node >= nn || s->trees[g].nodes[node].type != PCFR_NODE_DECISION) {
+        set_error("node is not a decision node");
+        return PCFR_E_INVALID_ARG;
+    }
+    const DNode& d = s->P.nodes[s->P.node_base[g] + node];
+    const Plan& L = s->L;
+    void* stage = s->ws + L.off_stage;
+    dim3 grid((unsigned)((L.Hp + 255) / 256));
+    if (L.esz == 8)
+        hipLaunchKernelGGL((k_strategy<double>), grid, dim3(256), 0, s->stream,
+                           s->at<double>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
+                           which == PCFR_CURRENT ? 1 : 0, (double*)stage);
+    else
+        hipLaunchKernelGGL((k_strategy<float>), grid, dim3(256), 0, s->stream,
+                           s->at<float>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
+                           which == PCFR_CURRENT ? 1 : 0, (float*)stage);
+    HIPCHK(hipGetLastError());
+    int32_t rc = fetch_hands(s, stage, d.n_child, out, g);
+    if (rc) return rc;
+    for (int a = 0; a < d.n_child; a++)
+        for (int k = 0; k < kCombos; k++)
+            if (s->P.combo_hand[g][k] < 0) out[(size_t)a * kCombos + k] = 0;
+    return PCFR_OK;
+}
+
+static int32_t root_cfv_impl(pcfr_solver* s, int32_t g, int32_t which, double* out, bool sweep_first) {
+    if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (g < 0 || g >= s->P.n_sub) { set_error("subgame index out of range"); return PCFR_E_INVALID_ARG; }
+    const Plan& L = s->L;
+    if (which == PCFR_CURRENT) return fetch_hands(s, s->ws + L.off_root + L.esz * 2 * L.Hp * (size_t)g, 2, out, g);
+    if (which != PCFR_AVG) { set_error("which must be PCFR_AVG or PCFR_CURRENT"); return PCFR_E_INVALID_ARG; }
+    if (sweep_first) {
+        int32_t rc = sweep<MODE_EV>(s);
+        if (rc) return rc;
+    }
+    return fetch_hands(s, s->ws + L.off_cfv + L.esz * 2 * L.Hp * (size_t)s->P.root_node[g], 2, out, g);
+}
+
+// Best-response sweep for every subgame, then per subgame
+// (BR_0 + BR_1) / 2 per unit of joint pair mass.
+static int32_t exploitability_impl(pcfr_solver* s, double* chips, double* br) {
+    int32_t rc = sweep<MODE_BR>(s);
+    if (rc) return rc;
+    const int32_t n = s->P.n_sub;
+    std::vector<double> v(2 * kCombos);
+    for (int32_t g = 0; g < n; g++) {
+        if ((rc = root_cfv_impl(s, g, PCFR_AVG, v.data(), false))) return rc;
+        const double* rg = &s->ranges[(size_t)g * 2 * kCombos];
+        double b[2] = {0, 0};
+        for (int p = 0; p < 2; p++)
+            for (int k = 0; k < kCombos; k++) b[p] += rg[p * kCombos + k] * v[(size_t)p * kCombos + k];
+        b[0] /= s->pair_mass[g];
+        b[1] /= s->pair_mass[g];
+        if (!std::isfinite(b[0]) || !std::isfinite(b[1])) { set_error("non-finite best-response value"); return PCFR_E_NUMERIC; }
+        chips[g] = 0.5 * (b[0] + b[1]);
+        if (br) { br[2 * g] = b[0]; br[2 * g + 1] = b[1]; }
+    }
+    return PCFR_OK;
+}
+
+}  // namespace pcfr
+
+extern "C" {
+
+int32_t pcfr_solver_workspace_bytes(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, size_t* bytes) {
+    const pcfr_tree* t[1] = {tree};
+    return workspace_for(t, 1, cfg, bytes);
+}
+
+int32_t pcfr_solver_create(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, const double* ranges, void* workspace,
+                           size_t workspace_bytes, void* stream, pcfr_solver** out) {
+    const pcfr_tree* t[1] = {tree};
+    return create_impl(t, 1, cfg, ranges, workspace, workspace_bytes, stream, out);
+}
+
+int32_t pcfr_batch_workspace_bytes(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg, size_t* bytes) {
+    return workspace_for(trees, n, cfg, bytes);
+}
+
+int32_t pcfr_batch_create(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg, const double* ranges,
+                          void* workspace, size_t workspace_bytes, void* stream, pcfr_solver** out) {
+    return create_impl(trees, n, cfg, ranges, workspace, workspace_bytes, stream, out);
+}
+
+int32_t pcfr_batch_size(const pcfr_solver* s, int32_t* n) {
+    if (!s || !n) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    *n = s->P.n_sub;
     return PCFR_OK;
 }
 
@@ -1295,57 +1459,32 @@ int32_t pcfr_iteration(pcfr_solver* s, int64_t* t) {
 }
 
 int32_t pcfr_get_strategy(pcfr_solver* s, int32_t node, int32_t which, double* out) {
-    if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
-    if (which != PCFR_AVG && which != PCFR_CURRENT) { set_error("which must be PCFR_AVG or PCFR_CURRENT"); return PCFR_E_INVALID_ARG; }
-    if (node < 0 || node >= (int32_t)s->P.nodes.size() || s->P.nodes[node].type != PCFR_NODE_DECISION) {
-        set_error("node is not a decision node");
-        return PCFR_E_INVALID_ARG;
-    }
-    const DNode& d = s->P.nodes[node];
-    const Plan& L = s->L;
-    void* stage = s->ws + L.off_stage;
-    dim3 grid((unsigned)((L.Hp + 255) / 256));
-    if (L.esz == 8)
-        hipLaunchKernelGGL((k_strategy<double>), grid, dim3(256), 0, s->stream,
-                           s->at<double>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
-                           which == PCFR_CURRENT ? 1 : 0, (double*)stage);
-    else
-        hipLaunchKernelGGL((k_strategy<float>), grid, dim3(256), 0, s->stream,
-                           s->at<float>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
-                           which == PCFR_CURRENT ? 1 : 0, (float*)stage);
-    HIPCHK(hipGetLastError());
-    int32_t rc = fetch_hands(s, stage, d.n_child, out);
-    if (rc) return rc;
-    for (int a = 0; a < d.n_child; a++)
-        for (int k = 0; k < kCombos; k++)
-            if (s->P.combo_hand[k] < 0) out[(size_t)a * kCombos + k] = 0;
-    return PCFR_OK;
+    return strategy_impl(s, 0, node, which, out);
 }
 
-int32_t pcfr_get_root_cfv(pcfr_solver* s, int32_t which, double* out) {
-    if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
-    if (which == PCFR_CURRENT) return fetch_hands(s, s->ws + s->L.off_root, 2, out);
-    if (which != PCFR_AVG) { set_error("which must be PCFR_AVG or PCFR_CURRENT"); return PCFR_E_INVALID_ARG; }
-    int32_t rc = sweep<MODE_EV>(s);
-    if (rc) return rc;
-    return fetch_hands(s, s->ws + s->L.off_cfv, 2, out);
+int32_t pcfr_batch_get_strategy(pcfr_solver* s, int32_t sub, int32_t node, int32_t which, double* out) {
+    return strategy_impl(s, sub, node, which, out);
+}
+
+int32_t pcfr_get_root_cfv(pcfr_solver* s, int32_t which, double* out) { return root_cfv_impl(s, 0, which, out, true); }
+
+int32_t pcfr_batch_get_root_cfv(pcfr_solver* s, int32_t sub, int32_t which, double* out) {
+    return root_cfv_impl(s, sub, which, out, true);
 }
 
 int32_t pcfr_exploitability(pcfr_solver* s, double* chips_per_hand, double* br) {
     if (!s || !chips_per_hand) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
-    int32_t rc = sweep<MODE_BR>(s);
+    std::vector<double> e(s->P.n_sub), b(2 * s->P.n_sub);
+    int32_t rc = exploitability_impl(s, e.data(), b.data());
     if (rc) return rc;
-    std::vector<double> v(2 * kCombos);
-    if ((rc = fetch_hands(s, s->ws + s->L.off_cfv, 2, v.data()))) return rc;
-    double b[2] = {0, 0};
-    for (int p = 0; p < 2; p++)
-        for (int k = 0; k < kCombos; k++) b[p] += s->ranges[p][k] * v[(size_t)p * kCombos + k];
-    b[0] /= s->pair_mass;
-    b[1] /= s->pair_mass;
-    if (!std::isfinite(b[0]) || !std::isfinite(b[1])) { set_error("non-finite best-response value"); return PCFR_E_NUMERIC; }
-    *chips_per_hand = 0.5 * (b[0] + b[1]);
+    *chips_per_hand = e[0];
     if (br) { br[0] = b[0]; br[1] = b[1]; }
     return PCFR_OK;
+}
+
+int32_t pcfr_batch_exploitability(pcfr_solver* s, double* chips_per_hand, double* br) {
+    if (!s || !chips_per_hand) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    return exploitability_impl(s, chips_per_hand, br);
 }
 
 int32_t pcfr_state_bytes(pcfr_solver* s, size_t* bytes) {

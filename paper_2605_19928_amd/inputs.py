@@ -110,3 +110,37 @@ def flop_config(seed: int, support: int | None = None, pot: int = 100, stack: in
     spec = dict(board=board, pot=pot, stacks=(stack, stack), sizes=list(sizes), allin=True,
                 max_raises=max_raises, depth_limit=1)
     return spec, np.stack([r0, r1])
+
+
+def batch_config(seed: int, count_nodes, n: int = 256, river_share: float = 0.7,
+                 lo: int = 10, hi: int = 2000, sizes_pool=(33, 50, 75, 100, 150)):
+    """Many independent river/turn subgames of uneven size.
+
+    The first round(river_share * n) subgames are rivers, the rest turns.
+    Each gets its own board, Dirichlet(1) ranges, pot (log-uniform [20, 400])
+    and stack-to-pot ratio (uniform [1, 8]) and its own bet abstraction: 1-4
+    sizes drawn from sizes_pool plus all-in, and 1-3 bets/raises per street.
+    A draw is kept when count_nodes(spec), supplied by the caller, lies in
+    [lo, hi]; otherwise the abstraction, pot and stack are drawn again.
+    """
+    rng = np.random.default_rng(seed)
+    n_river = int(round(river_share * n))
+    out = []
+    for i in range(n):
+        nb = 5 if i < n_river else 4
+        board = draw_board(rng, nb)
+        r0 = dirichlet_range(rng, board, 1.0)
+        r1 = dirichlet_range(rng, board, 1.0)
+        for _ in range(1000):
+            k = int(rng.integers(1, 5))
+            sizes = sorted(int(x) for x in rng.choice(sizes_pool, k, replace=False))
+            cap = int(rng.integers(1, 4))
+            pot, stack = draw_pot_stack(rng)
+            spec = dict(board=board, pot=pot, stacks=(stack, stack), sizes=sizes, allin=True,
+                        max_raises=cap, depth_limit=0)
+            if lo <= count_nodes(spec) <= hi:
+                break
+        else:
+            raise RuntimeError("no abstraction met the node-count window")
+        out.append((spec, np.stack([r0, r1])))
+    return out

@@ -65,6 +65,13 @@ _SIGS = {
     "pcfr_leafnet_train_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                             C.c_float, C.POINTER(C.c_float)]),
     "pcfr_solver_attach_leafnet": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_batch_workspace_bytes": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SolverCfg), C.POINTER(C.c_size_t)]),
+    "pcfr_batch_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SolverCfg), C.c_void_p, C.c_void_p,
+                                      C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pcfr_batch_size": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "pcfr_batch_get_strategy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "pcfr_batch_get_root_cfv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "pcfr_batch_exploitability": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pcfr_leaf_rows": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pcfr_solver_workspace_bytes": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.POINTER(C.c_size_t)]),
     "pcfr_solver_create": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.c_void_p, C.c_void_p, C.c_size_t,
@@ -275,6 +282,56 @@ class Solver:
 
     def __del__(self):
         self.close()
+
+
+class Batch(Solver):
+    """Many subgames advanced together by the same launches (one forest)."""
+
+    def __init__(self, trees, ranges, cfg: SolverConfig | None = None, device="cuda"):
+        import torch
+
+        self.trees = list(trees)
+        self.tree = self.trees[0]
+        self.cfg = cfg or SolverConfig()
+        c = self.cfg.to_c()
+        self._cfg_c = c
+        n = len(self.trees)
+        arr = (C.c_void_p * n)(*[t._h.value for t in self.trees])
+        self._arr = arr
+        nbytes = C.c_size_t()
+        _check(lib().pcfr_batch_workspace_bytes(arr, n, C.byref(c), C.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(n, 2, NCOMBO)
+        self._ranges = r
+        h = C.c_void_p()
+        _check(lib().pcfr_batch_create(arr, n, C.byref(c), _p(r), C.c_void_p(ptr), self.workspace_bytes,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self._nchildren = [t.export()["n_child"] for t in self.trees]
+        self._nchild = self._nchildren[0]
+        self.n = n
+
+    def strategy_of(self, sub: int, node: int, which: str = "avg") -> np.ndarray:
+        A = int(self._nchildren[sub][node])
+        out = np.zeros((max(A, 1), NCOMBO), dtype=np.float64)
+        _check(lib().pcfr_batch_get_strategy(self._h, int(sub), int(node), AVG if which == "avg" else CURRENT,
+                                             _p(out)))
+        return out
+
+    def root_cfv_of(self, sub: int, which: str = "current") -> np.ndarray:
+        out = np.zeros((2, NCOMBO), dtype=np.float64)
+        _check(lib().pcfr_batch_get_root_cfv(self._h, int(sub), CURRENT if which == "current" else AVG, _p(out)))
+        return out
+
+    def exploitability_all(self):
+        e = np.zeros(self.n, dtype=np.float64)
+        br = np.zeros((self.n, 2), dtype=np.float64)
+        _check(lib().pcfr_batch_exploitability(self._h, _p(e), _p(br)))
+        return e, br
 
 
 LEAF_D_IN = 2 * NCOMBO + 53

@@ -1,9 +1,12 @@
 """Leaf network and depth-limited solving on the GPU vs the FP64 references.
 
 * Forward GEMM chain (bf16 MFMA, FP32 accumulate) vs oracle/mlp.py with the
-  same bf16 roundings: relative error <= 1e-3 of the output scale and cosine
-  similarity > 0.9999, on ragged shapes and on the full leaf architecture
-  (2705 -> 4 x 1536 -> 2652) at 1029 rows.
+  same bf16 roundings: relative error in Frobenius norm <= 1e-3, cosine
+  similarity > 0.9999, and every entry within 5e-3 of the output scale, on
+  ragged shapes and on the full leaf architecture (2705 -> 4 x 1536 -> 2652)
+  at 1029 rows.  (A hidden activation whose FP32 and FP64 sums straddle a
+  bf16 rounding boundary rounds one bf16 ulp apart, ~0.4%, so single
+  entries of a deep network move more than the norm does.)
 * One training step: gradients vs the FP64 backward with bf16 emulation
   (same bounds); the Adam update vs the closed form of Adam's first step.
 * Depth-limited flop with exact check-down leaves, FP64: 1e-9 pot vs the
@@ -36,9 +39,10 @@ def close(g, o, name):
     g = np.asarray(g, np.float64).ravel()
     o = np.asarray(o, np.float64).ravel()
     rel = np.abs(g - o).max() / max(np.abs(o).max(), 1e-30)
+    fro = np.linalg.norm(g - o) / max(np.linalg.norm(o), 1e-300)
     cos = float(g @ o / (np.linalg.norm(g) * np.linalg.norm(o) + 1e-300))
-    say(f"  {name}: max rel err {rel:.2e}, cosine {cos:.8f}")
-    assert rel <= 1e-3 and cos > 0.9999
+    say(f"  {name}: max rel err {rel:.2e}, frobenius rel err {fro:.2e}, cosine {cos:.8f}")
+    assert fro <= 1e-3 and cos > 0.9999 and rel <= 5e-3
 
 
 @pytest.mark.parametrize("d_in,width,depth,d_out,m", [(300, 256, 2, 200, 130), (2705, 1536, 4, 2652, 1029)])
