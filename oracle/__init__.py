@@ -75,6 +75,7 @@ def lib():
             "ora_node_board": (I, [P, I, P]),
             "ora_set_traverser_hands": (None, [P, P]),
             "ora_max_threads": (I, []),
+            "ora_set_variant": (None, [P, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -178,11 +179,14 @@ class Tree:
 class Solver:
     """Per-history DCFR with simultaneous updates, in FP64."""
 
-    def __init__(self, tree: Tree, ranges, alpha=1.5, beta=0.0, gamma=2.0, support_only=False):
+    VARIANTS = {"dcfr": 0, "cfr+": 1, "pcfr+": 2}
+
+    def __init__(self, tree: Tree, ranges, alpha=1.5, beta=0.0, gamma=2.0, support_only=False, variant="dcfr"):
         self.tree = tree
         r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, tree.nh)
         self._r = r
         self._h = lib().ora_solver_create(tree._h, _p(r), alpha, beta, gamma, int(support_only))
+        lib().ora_set_variant(self._h, self.VARIANTS[variant])
 
     def iterate(self, n: int, threads: int = 0):
         lib().ora_iterate(self._h, int(n), int(threads))

@@ -538,11 +538,23 @@ void ora_tree_export(const ogame* g, int32_t* type, int32_t* player, int32_t* pa
 /* ------------------------------------------------------------- solver */
 enum { LEAF_EQUITY = 0, LEAF_TABLE = 1 };
 
+/* Stage-7 update rules (Sec. 4.4: the CFR variant only changes Stage 7).
+ *   DCFR  (Brown & Sandholm 2019): discounted regrets and average, see
+ *         iterate_once.
+ *   CFR+  (Tammelin 2014): cumulative regrets floored at zero after every
+ *         update; the average strategy weights iteration t by t.
+ *   PCFR+ (Farina, Kroer & Sandholm 2021): predictive regret matching -- the
+ *         strategy of iteration t matches [R^{t-1} + m^t]^+ with the
+ *         prediction m^t = r^{t-1}, the last instantaneous regret; regrets
+ *         floored at zero; the average weights iteration t by t^2. */
+enum { V_DCFR = 0, V_CFRPLUS = 1, V_PCFRPLUS = 2 };
+
 typedef struct {
     ogame* g;
     double alpha, beta, gamma;
+    int variant;
     double rng[2][NCOMBO];
-    double *R, *S, *sig, *rinst, *sadd;
+    double *R, *S, *sig, *rinst, *sadd, *pred;
     double cfv[2][NCOMBO];
     int64_t t;
     int support_only;
@@ -566,6 +578,7 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
     s->R = calloc(n, sizeof(double)); s->S = calloc(n, sizeof(double));
     s->sig = calloc(n, sizeof(double)); s->rinst = calloc(n, sizeof(double));
     s->sadd = calloc(n, sizeof(double));
+    s->pred = calloc(n, sizeof(double));
     s->leaf_slot = malloc(sizeof(int) * g->n);
     for (int i = 0; i < g->n; i++) {
         s->leaf_slot[i] = -1;
@@ -577,7 +590,7 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
 
 void ora_solver_free(osolver* s) {
     if (!s) return;
-    free(s->R); free(s->S); free(s->sig); free(s->rinst); free(s->sadd);
+    free(s->R); free(s->S); free(s->sig); free(s->rinst); free(s->sadd); free(s->pred);
     free(s->leaf_ev); free(s->leaf_slot); free(s->tmask); free(s);
 }
 
@@ -727,7 +740,17 @@ static void own_reach(osolver* s, int n, int p, int h, double pi) {
     }
 }
 
-/* One DCFR iteration with simultaneous updates of both players. */
+void ora_set_variant(osolver* s, int variant) { s->variant = variant; }
+
+/* Regrets the next strategy is matched on: R, or R + m for PCFR+. */
+static const double* matched_regrets(const osolver* s, double* tmp) {
+    if (s->variant != V_PCFRPLUS) return s->R;
+    size_t n = (size_t)s->g->nrows * s->g->nh;
+    for (size_t k = 0; k < n; k++) tmp[k] = s->R[k] + s->pred[k];
+    return tmp;
+}
+
+/* One iteration with simultaneous updates of both players. */
 static void iterate_once(osolver* s) {
     ogame* g = s->g;
     int nh = g->nh;
@@ -737,7 +760,7 @@ static void iterate_once(osolver* s) {
     double dpos = ta / (ta + 1.0), dneg = tb / (tb + 1.0);
     double davg = pow(t / (t + 1.0), s->gamma);
     size_t n = (size_t)g->nrows * nh;
-    strategy_rows(g, s->R, s->sig, 0);
+    strategy_rows(g, matched_regrets(s, s->rinst), s->sig, 0);
     memset(s->rinst, 0, n * sizeof(double));
     memset(s->sadd, 0, n * sizeof(double));
     for (int i = 0; i < 2; i++) {
@@ -770,8 +793,14 @@ static void iterate_once(osolver* s) {
     #pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; k++) {
         double r = s->R[k] + s->rinst[k];
-        s->R[k] = r * (r > 0 ? dpos : dneg);
-        s->S[k] = (s->S[k] + s->sadd[k]) * davg;
+        if (s->variant == V_DCFR) {
+            s->R[k] = r * (r > 0 ? dpos : dneg);
+            s->S[k] = (s->S[k] + s->sadd[k]) * davg;
+        } else {
+            s->R[k] = r > 0 ? r : 0.0;
+            s->S[k] += (s->variant == V_CFRPLUS ? t : t * t) * s->sadd[k];
+            s->pred[k] = s->rinst[k];
+        }
     }
 }
 
@@ -791,10 +820,18 @@ int ora_get_strategy(const osolver* s, int node, int which, double* out) {
     if (node < 0 || node >= g->n || g->nd[node].type != T_DEC) return 1;
     const onode* o = &g->nd[node];
     int A = o->n_child, nh = g->nh;
+    double cur[64];
     const double* src = (which == 0 ? s->S : s->R) + (size_t)o->rs * nh;
     for (int h = 0; h < nh; h++) {
         if (!g->hvalid[h]) { for (int a = 0; a < A; a++) out[(size_t)a * nh + h] = 0; continue; }
-        if (which == 1) { regret_match(src, out, A, nh, h); continue; }
+        if (which == 1) {
+            for (int a = 0; a < A; a++)
+                cur[a] = src[(size_t)a * nh + h] + (s->variant == V_PCFRPLUS ? s->pred[((size_t)o->rs + a) * nh + h] : 0.0);
+            double sg[64];
+            regret_match(cur, sg, A, 1, 0);
+            for (int a = 0; a < A; a++) out[(size_t)a * nh + h] = sg[a];
+            continue;
+        }
         double den = 0;
         for (int a = 0; a < A; a++) den += src[(size_t)a * nh + h];
         for (int a = 0; a < A; a++) out[(size_t)a * nh + h] = den > 0 ? src[(size_t)a * nh + h] / den : 1.0 / A;

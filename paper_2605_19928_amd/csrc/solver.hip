@@ -47,10 +47,16 @@ struct __align__(16) DNode {
     double pay;                   // fold: folder's contribution; showdown: each contribution
 };
 
+// Per-iteration Stage-7 coefficients, computed on the device from t:
+//   R <- (R + r) * (R + r > 0 ? dpos : dneg);   S <- (S + wadd * pi * sigma) * wmul
+// DCFR: dpos = t^a/(t^a+1), dneg = t^b/(t^b+1), wadd = 1, wmul = (t/(t+1))^g.
+// CFR+: dpos = 1, dneg = 0 (regrets floored at zero), wadd = t, wmul = 1.
+// PCFR+: as CFR+ with wadd = t^2; the strategy matches on R + m, m the last
+// instantaneous regret.
 struct IterState {
     int64_t t;
-    int64_t pad;
-    double dpos, dneg, davg, pad2;
+    int32_t variant, pad;
+    double dpos, dneg, wadd, wmul;
 };
 
 constexpr int kBlock = 256;
@@ -77,15 +83,23 @@ __device__ __forceinline__ void st4(double* p, const V4<double>& v) {
 }
 
 // ------------------------------------------------------------ iteration state
-__global__ void k_begin_iter(IterState* st, double alpha, double beta, double gamma) {
+__global__ void k_begin_iter(IterState* st, int variant, double alpha, double beta, double gamma) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int64_t t = st->t + 1;
     st->t = t;
     double td = (double)t;
-    double ta = pow(td, alpha), tb = pow(td, beta);
-    st->dpos = ta / (ta + 1.0);
-    st->dneg = tb / (tb + 1.0);
-    st->davg = pow(td / (td + 1.0), gamma);
+    if (variant == PCFR_DCFR) {
+        double ta = pow(td, alpha), tb = pow(td, beta);
+        st->dpos = ta / (ta + 1.0);
+        st->dneg = tb / (tb + 1.0);
+        st->wadd = 1.0;
+        st->wmul = pow(td / (td + 1.0), gamma);
+    } else {
+        st->dpos = 1.0;
+        st->dneg = 0.0;
+        st->wadd = variant == PCFR_CFRPLUS ? td : td * td;
+        st->wmul = 1.0;
+    }
 }
 
 // ------------------------------------------------------------ forward
@@ -100,7 +114,8 @@ __device__ __forceinline__ T strat(T x, T den, T inv_a) {
 
 template <typename T, int MODE, int A>
 __device__ __forceinline__ void fwd_decision(const DNode& nd, int64_t n, int h, int Hp, const T* __restrict__ R,
-                                             const T* __restrict__ S, T* __restrict__ reach) {
+                                             const T* __restrict__ S, const T* __restrict__ Mp,
+                                             T* __restrict__ reach) {
     const int p = nd.player, o = 1 - p;
     const T* rn = reach + n * 2 * Hp;
     const V4<T> rp = ld4(rn + (int64_t)p * Hp + h);
@@ -109,6 +124,14 @@ __device__ __forceinline__ void fwd_decision(const DNode& nd, int64_t n, int h, 
     V4<T> x[A];
 #pragma unroll
     for (int a = 0; a < A; a++) x[a] = ld4(src + (int64_t)a * Hp);
+    if (MODE == MODE_ITER && Mp) {
+#pragma unroll
+        for (int a = 0; a < A; a++) {
+            const V4<T> m = ld4(Mp + (int64_t)(nd.rs + a) * Hp + h);
+#pragma unroll
+            for (int j = 0; j < 4; j++) x[a].e[j] += m.e[j];
+        }
+    }
     T den[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < A; a++)
@@ -133,7 +156,8 @@ __device__ __forceinline__ bool has_card(uint32_t hc, int c) {
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                     int count, int Hp, const T* __restrict__ R, const T* __restrict__ S,
-                                                    T* __restrict__ reach, const uint16_t* __restrict__ hcards) {
+                                                    const T* __restrict__ Mp, T* __restrict__ reach,
+                                                    const uint16_t* __restrict__ hcards) {
     const int groups = Hp >> 2;
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t k = gid / groups;
@@ -160,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ no
         return;
     }
     switch (nd.n_child) {
-#define PCFR_FWD_CASE(A) case A: fwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, reach); break;
+#define PCFR_FWD_CASE(A) case A: fwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach); break;
         PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
         PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
 #undef PCFR_FWD_CASE
@@ -171,8 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ no
 // ------------------------------------------------------------ backward
 template <typename T, int MODE, int A>
 __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
-                                             T* __restrict__ S, const T* __restrict__ reach, T* __restrict__ cfv,
-                                             const IterState* st) {
+                                             T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
+                                             T* __restrict__ cfv, const IterState* st) {
     const int p = nd.player, o = 1 - p;
     V4<T> x[A];
     T den[4] = {T(0), T(0), T(0), T(0)};
@@ -181,6 +205,15 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         const T* src = (MODE == MODE_ITER ? (const T*)R : S) + (int64_t)nd.rs * Hp + h;
 #pragma unroll
         for (int a = 0; a < A; a++) x[a] = ld4(src + (int64_t)a * Hp);
+        if (MODE == MODE_ITER && Mp) {
+            // the strategy of this iteration matched R + m; R itself is read again below
+#pragma unroll
+            for (int a = 0; a < A; a++) {
+                const V4<T> m = ld4(Mp + (int64_t)(nd.rs + a) * Hp + h);
+#pragma unroll
+                for (int j = 0; j < 4; j++) x[a].e[j] += m.e[j];
+            }
+        }
 #pragma unroll
         for (int a = 0; a < A; a++)
 #pragma unroll
@@ -207,22 +240,26 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         // Stage 7: regret update, and the reach-weighted strategy added to the
         // average-strategy sum (Stage 1's accumulation, done here so that one
         // pass reads and writes both tables), each with its DCFR discount.
-        const T dpos = (T)st->dpos, dneg = (T)st->dneg, davg = (T)st->davg;
+        const T dpos = (T)st->dpos, dneg = (T)st->dneg, wadd = (T)st->wadd, wmul = (T)st->wmul;
         const V4<T> rp = ld4(reach + n * 2 * Hp + (int64_t)p * Hp + h);
 #pragma unroll
         for (int a = 0; a < A; a++) {
             const V4<T> c = ld4(cfv + (int64_t)(nd.first_child + a) * 2 * Hp + (int64_t)p * Hp + h);
             T* sp = S + (int64_t)(nd.rs + a) * Hp + h;
+            T* rptr = R + (int64_t)(nd.rs + a) * Hp + h;
             V4<T> sv = ld4(sp);
-            V4<T> y;
+            const V4<T> r0 = Mp ? ld4(rptr) : x[a];
+            V4<T> y, inst;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                T r = x[a].e[j] + (c.e[j] - vp.e[j]);
+                inst.e[j] = c.e[j] - vp.e[j];
+                T r = r0.e[j] + inst.e[j];
                 y.e[j] = r * (r > T(0) ? dpos : dneg);
-                sv.e[j] = (sv.e[j] + rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a)) * davg;
+                sv.e[j] = (sv.e[j] + wadd * (rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a))) * wmul;
             }
-            st4(R + (int64_t)(nd.rs + a) * Hp + h, y);
+            st4(rptr, y);
             st4(sp, sv);
+            if (Mp) st4(Mp + (int64_t)(nd.rs + a) * Hp + h, inst);
         }
     }
 }
@@ -230,8 +267,8 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                      int count, int Hp, T* __restrict__ R, T* __restrict__ S,
-                                                     const T* __restrict__ reach, T* __restrict__ cfv,
-                                                     const IterState* __restrict__ st) {
+                                                     T* __restrict__ Mp, const T* __restrict__ reach,
+                                                     T* __restrict__ cfv, const IterState* __restrict__ st) {
     const int groups = Hp >> 2;
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t k = gid / groups;
@@ -256,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ n
         return;
     }
     switch (nd.n_child) {
-#define PCFR_BWD_CASE(A) case A: bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, reach, cfv, st); break;
+#define PCFR_BWD_CASE(A) case A: bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach, cfv, st); break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
 #undef PCFR_BWD_CASE
@@ -582,7 +619,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
     const T scale = (T)pot_over_k[li];
     T* v0 = cfv + n * 2 * Hp;
     T* v1 = v0 + Hp;
-    for (int h = tid; h < Hp; h += kBlock) {
+    // blockIdx.y picks a tile of kBlock hands; the sums above are per leaf
+    for (int h = blockIdx.y * kBlock + tid; h < min(Hp, (int)(blockIdx.y + 1) * kBlock); h += kBlock) {
         if (h >= H) { v0[h] = T(0); v1[h] = T(0); continue; }
         const uint32_t hc = hcards[h];
         const int a = hc & 0xff, b = hc >> 8;
@@ -619,16 +657,17 @@ __global__ void k_gather_roots(const T* __restrict__ cfv, const int32_t* __restr
 
 // Strategy of one decision node for every hand: which 0 = average, 1 = current.
 template <typename T>
-__global__ void k_strategy(const T* __restrict__ src, int rs, int A, int Hp, int which, T* __restrict__ out) {
+__global__ void k_strategy(const T* __restrict__ src, const T* __restrict__ pred, int rs, int A, int Hp, int which,
+                           T* __restrict__ out) {
     int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= Hp) return;
     T den = T(0);
     for (int a = 0; a < A; a++) {
-        T x = src[(int64_t)(rs + a) * Hp + h];
+        T x = src[(int64_t)(rs + a) * Hp + h] + (pred ? pred[(int64_t)(rs + a) * Hp + h] : T(0));
         den += which ? (x > T(0) ? x : T(0)) : x;
     }
     for (int a = 0; a < A; a++) {
-        T x = src[(int64_t)(rs + a) * Hp + h];
+        T x = src[(int64_t)(rs + a) * Hp + h] + (pred ? pred[(int64_t)(rs + a) * Hp + h] : T(0));
         out[(int64_t)a * Hp + h] = den > T(0) ? ((which && !(x > T(0))) ? T(0) : x / den) : T(1) / T(A);
     }
 }
@@ -652,7 +691,7 @@ struct Plan {
     size_t esz;
     size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, total;
+        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, total;
     size_t lds_bytes;
 };
 
@@ -894,7 +933,7 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
     return PCFR_OK;
 }
 
-static void make_plan(const Prepared& P, int64_t rows, int dtype, Plan& L) {
+static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, Plan& L) {
     L.N = (int64_t)P.nodes.size();
     L.rows = rows;
     L.Hp = P.Hp;
@@ -936,6 +975,7 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, Plan& L) {
     L.off_c2h = take(sizeof(int16_t) * kCombos);
     L.off_h2c = take(sizeof(int16_t) * L.Hp);
     L.off_roots = take(sizeof(int32_t) * P.n_sub);
+    L.off_M = take(variant == PCFR_PCFRPLUS ? L.esz * L.rows * L.Hp : 0);
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
     L.lds_bytes = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock);
@@ -996,10 +1036,12 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     T* S = s->at<T>(L.off_S);
     T* reach = s->at<T>(L.off_reach);
     T* cfv = s->at<T>(L.off_cfv);
+    T* Mp = s->cfg.variant == PCFR_PCFRPLUS ? s->at<T>(L.off_M) : nullptr;
     IterState* st = s->at<IterState>(L.off_state);
     if (MODE == MODE_ITER) {
         if (tm) tm->before(0);
-        hipLaunchKernelGGL(k_begin_iter, dim3(1), dim3(64), 0, stream, st, s->cfg.alpha, s->cfg.beta, s->cfg.gamma);
+        hipLaunchKernelGGL(k_begin_iter, dim3(1), dim3(64), 0, stream, st, (int)s->cfg.variant, s->cfg.alpha,
+                           s->cfg.beta, s->cfg.gamma);
         if (tm) tm->after();
     }
     for (int l = 0; l < P.levels; l++) {
@@ -1009,7 +1051,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
         if (tm) tm->before(1);
         hipLaunchKernelGGL((k_forward<T, MODE>), grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l],
-                           (int)cnt, Hp, R, S, reach, s->at<uint16_t>(L.off_hc));
+                           (int)cnt, Hp, R, S, Mp, reach, s->at<uint16_t>(L.off_hc));
         if (tm) tm->after();
     }
     if (L.term) {
@@ -1045,7 +1087,8 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (tm) tm->after();
         if (rc) return rc;
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream,
+        hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)((Hp + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, stream,
                            s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), (int)L.n_next,
                            s->at<int8_t>(L.off_next), Hp, (int)L.H, reach, cfv, s->at<uint16_t>(L.off_hc),
                            s->at<int16_t>(L.off_h2c), s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff),
@@ -1060,7 +1103,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
         if (tm) tm->before(3);
         hipLaunchKernelGGL((k_backward<T, MODE>), grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l],
-                           (int)cnt, Hp, R, S, reach, cfv, st);
+                           (int)cnt, Hp, R, S, Mp, reach, cfv, st);
         if (tm) tm->after();
     }
     if (MODE == MODE_ITER) {
@@ -1124,7 +1167,10 @@ namespace pcfr {
 
 static int32_t check_cfg(const pcfr_solver_cfg* cfg) {
     if (cfg->dtype != PCFR_F32 && cfg->dtype != PCFR_F64) { set_error("dtype must be PCFR_F32 or PCFR_F64"); return PCFR_E_INVALID_ARG; }
-    if (cfg->variant != PCFR_DCFR) { set_error("only the DCFR update is implemented"); return PCFR_E_UNSUPPORTED; }
+    if (cfg->variant != PCFR_DCFR && cfg->variant != PCFR_CFRPLUS && cfg->variant != PCFR_PCFRPLUS) {
+        set_error("variant must be PCFR_DCFR, PCFR_CFRPLUS or PCFR_PCFRPLUS");
+        return PCFR_E_INVALID_ARG;
+    }
     if (cfg->alternating != 0) { set_error("only simultaneous updates are implemented"); return PCFR_E_UNSUPPORTED; }
     if (!std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta) || !std::isfinite(cfg->gamma)) {
         set_error("alpha, beta, gamma must be finite");
@@ -1148,7 +1194,7 @@ static int32_t workspace_for(const pcfr_tree* const* trees, int32_t n, const pcf
     try { rc = prepare(tv, P); } catch (const std::bad_alloc&) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
     if (rc != PCFR_OK) return rc;
     Plan L;
-    make_plan(P, rows, cfg->dtype, L);
+    make_plan(P, rows, cfg->dtype, cfg->variant, L);
     *bytes = L.total;
     return PCFR_OK;
 }
@@ -1178,7 +1224,7 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         return PCFR_E_OUT_OF_MEMORY;
     }
     s->cfg = *cfg;
-    make_plan(s->P, rows, cfg->dtype, s->L);
+    make_plan(s->P, rows, cfg->dtype, cfg->variant, s->L);
     const Plan& L = s->L;
     const Prepared& P = s->P;
     if (workspace_bytes < L.total) { set_error("workspace smaller than the size the library asked for"); return PCFR_E_OUT_OF_MEMORY; }
@@ -1261,6 +1307,7 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     HIPCHK(hipMemsetAsync(s->ws + L.off_state, 0, sizeof(IterState), s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_R, 0, L.esz * L.rows * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_S, 0, L.esz * L.rows * L.Hp, s->stream));
+    if (cfg->variant == PCFR_PCFRPLUS) HIPCHK(hipMemsetAsync(s->ws + L.off_M, 0, L.esz * L.rows * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_reach, 0, L.esz * L.N * 2 * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_cfv, 0, L.esz * L.N * 2 * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_root, 0, L.esz * 2 * L.Hp * n, s->stream));
@@ -1300,11 +1347,15 @@ static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t wh
     dim3 grid((unsigned)((L.Hp + 255) / 256));
     if (L.esz == 8)
         hipLaunchKernelGGL((k_strategy<double>), grid, dim3(256), 0, s->stream,
-                           s->at<double>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
+                           s->at<double>(which == PCFR_AVG ? L.off_S : L.off_R),
+                           (which == PCFR_CURRENT && s->cfg.variant == PCFR_PCFRPLUS) ? s->at<double>(L.off_M) : nullptr,
+                           d.rs, d.n_child, (int)L.Hp,
                            which == PCFR_CURRENT ? 1 : 0, (double*)stage);
     else
         hipLaunchKernelGGL((k_strategy<float>), grid, dim3(256), 0, s->stream,
-                           s->at<float>(which == PCFR_AVG ? L.off_S : L.off_R), d.rs, d.n_child, (int)L.Hp,
+                           s->at<float>(which == PCFR_AVG ? L.off_S : L.off_R),
+                           (which == PCFR_CURRENT && s->cfg.variant == PCFR_PCFRPLUS) ? s->at<float>(L.off_M) : nullptr,
+                           d.rs, d.n_child, (int)L.Hp,
                            which == PCFR_CURRENT ? 1 : 0, (float*)stage);
     HIPCHK(hipGetLastError());
     int32_t rc = fetch_hands(s, stage, d.n_child, out, g);
@@ -1489,7 +1540,7 @@ int32_t pcfr_batch_exploitability(pcfr_solver* s, double* chips_per_hand, double
 
 int32_t pcfr_state_bytes(pcfr_solver* s, size_t* bytes) {
     if (!s || !bytes) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
-    *bytes = 16 + 2 * s->L.esz * s->L.rows * s->L.Hp;
+    *bytes = 16 + (s->cfg.variant == PCFR_PCFRPLUS ? 3 : 2) * s->L.esz * s->L.rows * s->L.Hp;
     return PCFR_OK;
 }
 
@@ -1505,8 +1556,10 @@ int32_t pcfr_save_state(pcfr_solver* s, void* buf, size_t bytes) {
     HIPCHK(hipMemcpyAsync(&st, s->ws + L.off_state, sizeof(st), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(b + 16, s->ws + L.off_R, rb, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(b + 16 + rb, s->ws + L.off_S, rb, hipMemcpyDeviceToHost, s->stream));
+    if (s->cfg.variant == PCFR_PCFRPLUS)
+        HIPCHK(hipMemcpyAsync(b + 16 + 2 * rb, s->ws + L.off_M, rb, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    int64_t hdr[2] = {st.t, (int64_t)L.esz};
+    int64_t hdr[2] = {st.t, (int64_t)L.esz + 16 * s->cfg.variant};
     std::memcpy(b, hdr, 16);
     return PCFR_OK;
 }
@@ -1520,11 +1573,16 @@ int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes) {
     const char* b = reinterpret_cast<const char*>(buf);
     int64_t hdr[2];
     std::memcpy(hdr, b, 16);
-    if (hdr[1] != (int64_t)L.esz || hdr[0] < 0) { set_error("state was saved with another dtype"); return PCFR_E_INVALID_ARG; }
+    if (hdr[1] != (int64_t)L.esz + 16 * s->cfg.variant || hdr[0] < 0) {
+        set_error("state was saved with another dtype or variant");
+        return PCFR_E_INVALID_ARG;
+    }
     size_t rb = L.esz * L.rows * L.Hp;
     IterState st{};
     st.t = hdr[0];
     HIPCHK(hipMemcpyAsync(s->ws + L.off_state, &st, sizeof(st), hipMemcpyHostToDevice, s->stream));
+    if (s->cfg.variant == PCFR_PCFRPLUS)
+        HIPCHK(hipMemcpyAsync(s->ws + L.off_M, b + 16 + 2 * rb, rb, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->ws + L.off_R, b + 16, rb, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->ws + L.off_S, b + 16 + rb, rb, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));

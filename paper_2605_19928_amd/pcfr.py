@@ -173,19 +173,23 @@ class Tree:
             self._h = None
 
 
+VARIANTS = {"dcfr": DCFR, "cfr+": CFRPLUS, "pcfr+": PCFRPLUS}
+
+
 @dataclass
 class SolverConfig:
     dtype: str = "f32"
     alpha: float = 1.5
     beta: float = 0.0
     gamma: float = 2.0
-    variant: int = DCFR
+    variant: str = "dcfr"
     alternating: int = 0
 
     def to_c(self) -> SolverCfg:
         c = SolverCfg()
         c.dtype = F64 if self.dtype == "f64" else F32
-        c.variant, c.alpha, c.beta, c.gamma, c.alternating = (self.variant, self.alpha, self.beta, self.gamma,
+        v = VARIANTS[self.variant] if isinstance(self.variant, str) else int(self.variant)
+        c.variant, c.alpha, c.beta, c.gamma, c.alternating = (v, self.alpha, self.beta, self.gamma,
                                                              self.alternating)
         return c
 

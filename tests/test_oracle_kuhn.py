@@ -142,3 +142,44 @@ def test_first_two_dcfr_iterations_match_brute_force(kuhn):
             np.testing.assert_allclose(So[row:row + 2, c], S[(h, c)], atol=1e-14)
     # iteration 2 exercised both discount branches
     assert any((v > 0).any() for v in R.values()) and any((v < 0).any() for v in R.values())
+
+
+@pytest.mark.parametrize("variant,bound", [("cfr+", 2e-3), ("pcfr+", 1e-5)])
+def test_variants_reach_the_game_value(kuhn, variant, bound):
+    s = O.Solver(kuhn, np.ones((2, 3)), variant=variant)
+    s.iterate(5000)
+    e, _ = s.exploitability()
+    v = s.root_cfv("avg")
+    assert 0 <= e < bound
+    assert abs(v[0].sum() / s.pair_mass() + 1 / 18) < max(bound, 1e-6)
+
+
+@pytest.mark.parametrize("variant", ["cfr+", "pcfr+"])
+def test_variant_first_iterations_match_brute_force(kuhn, variant):
+    """CFR+ floors regrets at 0 and weights the average by t; PCFR+ also
+    matches on R + m with m the previous instantaneous regret and weights the
+    average by t^2 (Tammelin 2014; Farina, Kroer & Sandholm 2021)."""
+    s = O.Solver(kuhn, np.ones((2, 3)), variant=variant)
+    R = {k: np.zeros(2) for k in ((h, c) for h in INFOSETS for c in range(3))}
+    S = {k: np.zeros(2) for k in R}
+    M = {k: np.zeros(2) for k in R}
+    rows_of = {0: 0, 1: 2, 2: 4, 4: 6}
+    for t in (1, 2, 3):
+        sig = {k: rm(R[k] + (M[k] if variant == "pcfr+" else 0)) for k in R}
+        reg, sadd = brute_iteration(sig)
+        for k in R:
+            R[k] = np.maximum(R[k] + reg[k], 0.0)
+            S[k] = S[k] + (t if variant == "cfr+" else t * t) * sadd[k]
+            M[k] = reg[k]
+        s.iterate(1)
+        Ro, So = s.rows("R"), s.rows("S")
+        for (h, c), v in R.items():
+            row = rows_of[NODE_OF[h]]
+            np.testing.assert_allclose(Ro[row:row + 2, c], v, atol=1e-14)
+            np.testing.assert_allclose(So[row:row + 2, c], S[(h, c)], atol=1e-14)
+        for node in (0, 1, 2, 4):
+            cur = s.strategy(node, "current")
+            for c in range(3):
+                key = next(h for h in INFOSETS if NODE_OF[h] == node)
+                want = rm(R[(key, c)] + (M[(key, c)] if variant == "pcfr+" else 0))
+                np.testing.assert_allclose(cur[:, c], want, atol=1e-14)
