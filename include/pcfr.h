@@ -257,6 +257,17 @@ int32_t pcfr_leafnet_train_step(pcfr_leafnet* net, const float* x, const float* 
  * per unit of compatible opponent reach) and hold leaves x next-cards rows.
  * All-in leaves stay exact.  The net must outlive the attachment. */
 int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net);
+/* Training samples for the leaf network from a solved batch (the survey of
+ * the paper's depth-limited method: the network is trained on subgames the
+ * solver itself solves).  Row g of x (device fp32 [n][ldx], ldx >= 2705):
+ * subgame g's root ranges normalised to sum 1 over the 1326 combos, its board
+ * one-hot, its stack-to-pot ratio.  Row g of y and mask (device fp32
+ * [n][ldy], ldy >= 2652): each hand's root value under both average
+ * strategies divided by (pot * the opponent's root reach compatible with the
+ * hand), mask 1 where that reach is positive, else 0.  Runs one value sweep
+ * under the average strategies.  Synchronises. */
+int32_t pcfr_batch_leaf_samples(pcfr_solver* s, float* x, int32_t ldx, float* y, float* mask, int32_t ldy);
+
 /* Network leaves and next cards per leaf (rows = product). */
 int32_t pcfr_leaf_rows(pcfr_solver* s, int32_t* n_leaves, int32_t* n_next);
 

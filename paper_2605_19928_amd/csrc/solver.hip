@@ -643,6 +643,91 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
     }
 }
 
+// ------------------------------------------------------------ leaf-network samples
+// One training sample per subgame of a solved batch, in the leaf network's
+// input/output layout: x = both root ranges normalised to sum 1 over the 1326
+// combos, the board one-hot (52), the stack-to-pot ratio; y = each hand's
+// root value under the average strategies per unit of pot and of compatible
+// opponent reach, v_i(h) / (pot * M_{-i}(h)); mask = 1 where M > 0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_samples(const int32_t* __restrict__ roots, const float* __restrict__ pot_spr,
+                                                    const uint8_t* __restrict__ boards, int Hp,
+                                                    const T* __restrict__ reach, const T* __restrict__ cfv,
+                                                    const uint16_t* __restrict__ hcards,
+                                                    const int16_t* __restrict__ combo_hand /* [n_sub][1326] */,
+                                                    const int32_t* __restrict__ coff, const int16_t* __restrict__ chands,
+                                                    int chand_stride, float* __restrict__ x, int ldx,
+                                                    float* __restrict__ y, float* __restrict__ mask, int ldy) {
+    __shared__ T cs[2][52];
+    __shared__ double red[2][kBlock];
+    const int g = blockIdx.x, tid = threadIdx.x;
+    const int64_t n = roots[g];
+    const T* r0 = reach + n * 2 * Hp;
+    const T* r1 = r0 + Hp;
+    const T* v0 = cfv + n * 2 * Hp;
+    const T* v1 = v0 + Hp;
+    const uint16_t* hc = hcards + (int64_t)g * Hp;
+    const int16_t* c2h = combo_hand + (int64_t)g * kCombos;
+    if (tid < 104) {
+        const int p = tid / 52, c = tid - p * 52;
+        const T* r = p ? r1 : r0;
+        const int32_t* co = coff + g * 53;
+        const int16_t* ch = chands + (int64_t)g * chand_stride;
+        T acc = T(0);
+        for (int j = co[c]; j < co[c + 1]; j++) acc += r[ch[j]];
+        cs[p][c] = acc;
+    }
+    double s0 = 0.0, s1 = 0.0;
+    for (int h = tid; h < Hp; h += kBlock) { s0 += (double)r0[h]; s1 += (double)r1[h]; }
+    red[0][tid] = s0;
+    red[1][tid] = s1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
+        __syncthreads();
+    }
+    const double S0 = red[0][0], S1 = red[1][0];
+    const float pot = pot_spr[2 * g], spr = pot_spr[2 * g + 1];
+    float* xr = x + (int64_t)g * ldx;
+    float* yr = y + (int64_t)g * ldy;
+    float* mr = mask + (int64_t)g * ldy;
+    for (int col = tid; col < ldx; col += kBlock) {
+        float v = 0.f;
+        if (col < 2 * kCombos) {
+            const int p = col >= kCombos;
+            const int h = c2h[col - p * kCombos];
+            const double S = p ? S1 : S0;
+            if (h >= 0 && S > 0.0) v = (float)((double)(p ? r1[h] : r0[h]) / S);
+        } else if (col < 2 * kCombos + 52) {
+            v = boards[(int64_t)g * 52 + (col - 2 * kCombos)] ? 1.f : 0.f;
+        } else if (col == 2 * kCombos + 52) {
+            v = spr;
+        }
+        xr[col] = v;
+    }
+    for (int col = tid; col < ldy; col += kBlock) {
+        float t = 0.f, m = 0.f;
+        if (col < 2 * kCombos) {
+            const int p = col >= kCombos;
+            const int h = c2h[col - p * kCombos];
+            if (h >= 0) {
+                const uint32_t c = hc[h];
+                const int a = c & 0xff, b = c >> 8;
+                const int o = 1 - p;
+                const T* ro = o ? r1 : r0;
+                const T tot = (T)(o ? S1 : S0);
+                const T M = tot - cs[o][a] - cs[o][b] + ro[h];
+                if (M > T(0)) {
+                    t = (float)((p ? v1[h] : v0[h]) / ((T)pot * M));
+                    m = 1.f;
+                }
+            }
+        }
+        yr[col] = t;
+        mr[col] = m;
+    }
+}
+
 // ------------------------------------------------------------ small kernels
 // Root values of every subgame -> a slot that later sweeps do not overwrite.
 template <typename T>
@@ -691,7 +776,7 @@ struct Plan {
     size_t esz;
     size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, total;
+        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, total;
     size_t lds_bytes;
 };
 
@@ -976,6 +1061,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_h2c = take(sizeof(int16_t) * L.Hp);
     L.off_roots = take(sizeof(int32_t) * P.n_sub);
     L.off_M = take(variant == PCFR_PCFRPLUS ? L.esz * L.rows * L.Hp : 0);
+    L.off_samp = take(align256(sizeof(float) * 2 * P.n_sub) + align256((size_t)P.n_sub * 52) +
+                      align256(sizeof(int16_t) * (size_t)P.n_sub * kCombos));
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
     L.lds_bytes = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock);
@@ -1271,6 +1358,25 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     std::vector<int32_t> roots(n);
     for (int32_t g = 0; g < n; g++) roots[g] = (int32_t)P.root_node[g];
     if ((rc = up(L.off_roots, roots.data(), sizeof(int32_t) * n))) return rc;
+    {
+        // per-subgame tables of the leaf-network sample builder
+        std::vector<float> ps(2 * n);
+        std::vector<uint8_t> boards((size_t)n * 52, 0);
+        std::vector<int16_t> c2h((size_t)n * kCombos);
+        for (int32_t g = 0; g < n; g++) {
+            const pcfr_tree_spec& sp = s->trees[g].spec;
+            const int64_t eff = std::min(sp.stack[0], sp.stack[1]);
+            ps[2 * g] = (float)sp.pot;
+            ps[2 * g + 1] = (float)((double)eff / (double)sp.pot);
+            for (int c = 0; c < 52; c++) boards[(size_t)g * 52 + c] = (P.root_mask[g] >> c & 1ull) ? 1 : 0;
+            for (int k = 0; k < kCombos; k++) c2h[(size_t)g * kCombos + k] = (int16_t)P.combo_hand[g][k];
+        }
+        const size_t o1 = align256(sizeof(float) * 2 * n), o2 = o1 + align256((size_t)n * 52);
+        if ((rc = up(L.off_samp, ps.data(), sizeof(float) * ps.size()))) return rc;
+        if ((rc = up(L.off_samp + o1, boards.data(), boards.size()))) return rc;
+        if ((rc = up(L.off_samp + o2, c2h.data(), sizeof(int16_t) * c2h.size()))) return rc;
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
     {
         std::vector<int16_t> c2h(kCombos), h2c(L.Hp, -1);
         for (int k = 0; k < kCombos; k++) c2h[k] = (int16_t)P.combo_hand[0][k];
@@ -1585,6 +1691,31 @@ int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes) {
         HIPCHK(hipMemcpyAsync(s->ws + L.off_M, b + 16 + 2 * rb, rb, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->ws + L.off_R, b + 16, rb, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->ws + L.off_S, b + 16 + rb, rb, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return PCFR_OK;
+}
+
+int32_t pcfr_batch_leaf_samples(pcfr_solver* s, float* x, int32_t ldx, float* y, float* mask, int32_t ldy) {
+    if (!s || !x || !y || !mask) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (ldx < 2 * kCombos + 53 || ldy < 2 * kCombos) { set_error("row strides too small"); return PCFR_E_INVALID_ARG; }
+    const Plan& L = s->L;
+    const int32_t n = s->P.n_sub;
+    const float* dps = s->at<float>(L.off_samp);
+    const uint8_t* dboards = s->at<uint8_t>(L.off_samp + align256(sizeof(float) * 2 * n));
+    const int16_t* dc2h = s->at<int16_t>(L.off_samp + align256(sizeof(float) * 2 * n) + align256((size_t)n * 52));
+    int32_t rc = sweep<MODE_EV>(s);
+    if (rc) return rc;
+    if (L.esz == 8)
+        hipLaunchKernelGGL((k_samples<double>), dim3(n), dim3(kBlock), 0, s->stream, s->at<int32_t>(L.off_roots), dps,
+                           dboards, (int)L.Hp, s->at<double>(L.off_reach), s->at<double>(L.off_cfv),
+                           s->at<uint16_t>(L.off_hc), dc2h, s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
+                           (int)L.chand_stride, x, ldx, y, mask, ldy);
+    else
+        hipLaunchKernelGGL((k_samples<float>), dim3(n), dim3(kBlock), 0, s->stream, s->at<int32_t>(L.off_roots), dps,
+                           dboards, (int)L.Hp, s->at<float>(L.off_reach), s->at<float>(L.off_cfv),
+                           s->at<uint16_t>(L.off_hc), dc2h, s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
+                           (int)L.chand_stride, x, ldx, y, mask, ldy);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return PCFR_OK;
 }

@@ -144,3 +144,24 @@ def batch_config(seed: int, count_nodes, n: int = 256, river_share: float = 0.7,
             raise RuntimeError("no abstraction met the node-count window")
         out.append((spec, np.stack([r0, r1])))
     return out
+
+
+def leaf_training_config(seed: int, index: int, sizes=(75,), max_raises: int = 2,
+                         spr_lo: float = 0.1, spr_hi: float = 8.0):
+    """One random turn subgame for leaf-network training data.
+
+    Seeded by (seed, index): 4-card board; each player's range
+    Dirichlet(alpha_p) over the compatible combos with alpha_p ~ U[0.5, 2];
+    pot log-uniform in [20, 400] (even chips); stack-to-pot ratio
+    log-uniform in [spr_lo, spr_hi] (the depth-limit leaves of a flop
+    subgame sit at ratios from about 0.1 to 4); continuation abstraction
+    {75}% + all-in, at most 2 bets/raises per street."""
+    rng = np.random.default_rng([seed, index])
+    board = draw_board(rng, 4)
+    a0, a1 = rng.uniform(0.5, 2.0, size=2)
+    r0 = dirichlet_range(rng, board, a0)
+    r1 = dirichlet_range(rng, board, a1)
+    pot, stack = draw_pot_stack(rng, spr_lo=spr_lo, spr_hi=spr_hi, log_spr=True)
+    spec = dict(board=board, pot=pot, stacks=(stack, stack), sizes=list(sizes), allin=True,
+                max_raises=max_raises, depth_limit=0)
+    return spec, np.stack([r0, r1])

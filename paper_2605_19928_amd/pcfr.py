@@ -72,6 +72,7 @@ _SIGS = {
     "pcfr_batch_get_strategy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     "pcfr_batch_get_root_cfv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "pcfr_batch_exploitability": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pcfr_batch_leaf_samples": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     "pcfr_leaf_rows": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pcfr_solver_workspace_bytes": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.POINTER(C.c_size_t)]),
     "pcfr_solver_create": (C.c_int32, [C.c_void_p, C.POINTER(SolverCfg), C.c_void_p, C.c_void_p, C.c_size_t,
@@ -91,9 +92,16 @@ _SIGS = {
 
 
 def lib():
-    """Load the built library; raises if it was not built."""
+    """Load the built library; raises if it was not built.
+
+    torch is imported first: its wheel carries its own HIP runtime under the
+    same soname, and the device memory and streams this binding passes come
+    from torch, so the library must bind to that runtime rather than load a
+    second one."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (loads torch's HIP runtime before libpcfr.so)
+
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_19928_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -330,6 +338,14 @@ class Batch(Solver):
         out = np.zeros((2, NCOMBO), dtype=np.float64)
         _check(lib().pcfr_batch_get_root_cfv(self._h, int(sub), CURRENT if which == "current" else AVG, _p(out)))
         return out
+
+    def leaf_samples(self, X, Y, Mk):
+        """Fill rows of device tensors X [n, >=2705], Y and Mk [n, >=2652] (fp32) with one
+        leaf-network sample per subgame (values under the average strategies)."""
+        for t in (X, Y, Mk):
+            assert t.is_contiguous() and t.shape[0] >= self.n
+        _check(lib().pcfr_batch_leaf_samples(self._h, C.c_void_p(X.data_ptr()), int(X.shape[1]),
+                                             C.c_void_p(Y.data_ptr()), C.c_void_p(Mk.data_ptr()), int(Y.shape[1])))
 
     def exploitability_all(self):
         e = np.zeros(self.n, dtype=np.float64)
