@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the turn tree-sweep measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-mb", type=int, default=0,
+                    help="first run a plain elementwise kernel over this many MiB (reads it once, writes it "
+                         "once) so hardware byte counters can be scaled against a known size")
     return ap.parse_args()
 
 
@@ -195,6 +198,16 @@ def main():
         sys.exit(2)
     from paper_2605_19928_amd import inputs as I
     from paper_2605_19928_amd import pcfr as P
+
+    if args.calibrate_mb:
+        import torch
+
+        x = torch.ones(args.calibrate_mb * (1 << 18), dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log(f"calibration kernel: read {args.calibrate_mb} MiB, wrote {args.calibrate_mb} MiB")
+        del x, y
 
     if args.workload == "turn":
         sweep, spec, r = tree_sweep(args, args.seed, args.steps, args.warmup)

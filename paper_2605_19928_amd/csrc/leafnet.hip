@@ -84,13 +84,18 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
             *reinterpret_cast<uint4*>(&sB[buf][row * LDK + col]) = rb[i];
         }
     };
-    v16f acc[TM][TN];
+    // KACC independent accumulator chains per output tile, so consecutive
+    // MFMAs of a wave do not wait on each other's results; summed at the end
+    constexpr int KACC = (TM * TN >= 4) ? 1 : 4 / (TM * TN);
+    v16f acc[KACC][TM][TN];
 #pragma unroll
-    for (int i = 0; i < TM; i++)
+    for (int q = 0; q < KACC; q++)
 #pragma unroll
-        for (int j = 0; j < TN; j++)
+        for (int i = 0; i < TM; i++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+            for (int j = 0; j < TN; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) acc[q][i][j][r] = 0.f;
     gload(0);
     sstore(0);
     __syncthreads();
@@ -99,23 +104,38 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
         const int buf = (k0 / BK) & 1;
         const bool more = k0 + BK < K;
         if (more) gload(k0 + BK);
+        // all fragments of this stage first, then the MFMAs
+        v8bf a[BK / 16][TM], b[BK / 16][TN];
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 16) {
-            v8bf a[TM], b[TN];
+        for (int kk = 0; kk < BK / 16; kk++) {
 #pragma unroll
             for (int i = 0; i < TM; i++)
-                a[i] = *reinterpret_cast<const v8bf*>(&sA[buf][(wm * (BM / 2) + i * 32 + l32) * LDK + ks + kh]);
+                a[kk][i] = *reinterpret_cast<const v8bf*>(
+                    &sA[buf][(wm * (BM / 2) + i * 32 + l32) * LDK + kk * 16 + kh]);
 #pragma unroll
             for (int j = 0; j < TN; j++)
-                b[j] = *reinterpret_cast<const v8bf*>(&sB[buf][(wn * (BN / 2) + j * 32 + l32) * LDK + ks + kh]);
+                b[kk][j] = *reinterpret_cast<const v8bf*>(
+                    &sB[buf][(wn * (BN / 2) + j * 32 + l32) * LDK + kk * 16 + kh]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < BK / 16; kk++)
 #pragma unroll
             for (int i = 0; i < TM; i++)
 #pragma unroll
-                for (int j = 0; j < TN; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
+                for (int j = 0; j < TN; j++)
+                    acc[kk % KACC][i][j] =
+                        __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kk][i], b[kk][j], acc[kk % KACC][i][j], 0, 0, 0);
         if (more) sstore(buf ^ 1);
         __syncthreads();
     }
+#pragma unroll
+    for (int q = 1; q < KACC; q++)
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) acc[0][i][j][r] += acc[q][i][j][r];
 #pragma unroll
     for (int i = 0; i < TM; i++)
 #pragma unroll
@@ -125,7 +145,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int64_t row = m0 + wm * (BM / 2) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                float v = acc[i][j][r] + bv;
+                float v = acc[0][i][j][r] + bv;
                 if (EPI == EPI_BIAS_F32 || EPI == EPI_F32) {
                     reinterpret_cast<float*>(Cout)[row * ldc + col] = v;
                 } else if (EPI == EPI_BIAS_RELU_BF) {

@@ -304,28 +304,40 @@ __global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ n
 // ------------------------------------------------------------ terminals
 // Fold: v_i(h) = -+ c_f * M_{-i}(h) where M(h) is the opponent reach over
 // hands sharing no card with h: total - per-card(a) - per-card(b) + r(h)
-// (the hand itself was removed twice).
+// (the hand itself was removed twice).  Both reach vectors and the per-card
+// hand lists are staged in LDS first, so the 104 per-card sums read LDS only.
 template <typename T>
 __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                           const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
                           const int16_t* __restrict__ chands, T* lds) {
-    T* pc = lds;              // [2][52]
-    T* red = lds + 104;       // [2][kBlock]
+    T* x0 = lds;                  // [Hp]
+    T* x1 = x0 + Hp;              // [Hp]
+    T* pc = x1 + Hp;              // [2][52]
+    T* red = pc + 104;            // [2][kBlock]
+    int16_t* lst = reinterpret_cast<int16_t*>(red + 2 * kBlock);   // [2 * Hp]
     const T* r0 = reach + n * 2 * Hp;
     const T* r1 = r0 + Hp;
     const int tid = threadIdx.x;
-    if (tid < 104) {
-        const int p = tid / 52, c = tid - p * 52;
-        const T* r = p ? r1 : r0;
-        T s = T(0);
-        for (int j = coff[c]; j < coff[c + 1]; j++) s += r[chands[j]];
-        pc[tid] = s;
-    }
+    const int nl = coff[52];
     T s0 = T(0), s1 = T(0);
-    for (int h = tid; h < Hp; h += kBlock) { s0 += r0[h]; s1 += r1[h]; }
+    for (int h = tid; h < Hp; h += kBlock) {
+        const T a = r0[h], b = r1[h];
+        x0[h] = a;
+        x1[h] = b;
+        s0 += a;
+        s1 += b;
+    }
+    for (int j = tid; j < nl; j += kBlock) lst[j] = chands[j];
     red[tid] = s0;
     red[kBlock + tid] = s1;
     __syncthreads();
+    if (tid < 104) {
+        const int p = tid / 52, c = tid - p * 52;
+        const T* x = p ? x1 : x0;
+        T acc = T(0);
+        for (int j = coff[c]; j < coff[c + 1]; j++) acc += x[lst[j]];
+        pc[tid] = acc;
+    }
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (tid < w) { red[tid] += red[tid + w]; red[kBlock + tid] += red[kBlock + tid + w]; }
         __syncthreads();
@@ -342,8 +354,8 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
         const bool alive = a != 0xff && a != d1 && a != d2 && b != d1 && b != d2;
         T m0 = T(0), m1 = T(0);
         if (alive) {
-            m0 = tot0 - pc[a] - pc[b] + r0[h];
-            m1 = tot1 - pc[52 + a] - pc[52 + b] + r1[h];
+            m0 = tot0 - pc[a] - pc[b] + x0[h];
+            m1 = tot1 - pc[52 + a] - pc[52 + b] + x1[h];
         }
         v0[h] = (f == 0 ? -pay : pay) * m1;
         v1[h] = (f == 1 ? -pay : pay) * m0;
@@ -372,8 +384,10 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     const int16_t* ahi = tb + 4 * Hp;
     const int16_t* blo = tb + 5 * Hp;
     const int16_t* bhi = tb + 6 * Hp;
-    const int16_t* coff = tb + 7 * Hp;
-    const int16_t* clist = coff + kSdHeader;
+    const int16_t* gcoff = tb + 7 * Hp;
+    const int16_t* gclist = gcoff + kSdHeader;
+    int16_t* coff = reinterpret_cast<int16_t*>(part + 2 * kBlock);    // [kSdHeader], LDS copy
+    int16_t* clist = coff + kSdHeader;                                // [QN - kSdHeader], LDS copy
     const T* r0 = reach + n * 2 * Hp;
     const T* r1 = r0 + Hp;
     const int tid = threadIdx.x;
@@ -383,6 +397,8 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         xs0[s] = r0[h];
         xs1[s] = r1[h];
     }
+    if (tid < kSdHeader) coff[tid] = gcoff[tid];
+    for (int j = tid; j < QN - kSdHeader; j += kBlock) clist[j] = gclist[j];
     __syncthreads();
     if (tid < 104) {
         const int p = tid / 52, c = tid - p * 52;
@@ -478,20 +494,26 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
 // ------------------------------------------------------------ depth-limit leaves
 // Exact leaf values from pairwise check-down equity (all-in leaves, and every
 // leaf when no network is attached): v_i(h) = c * sum_o E(h,o) r_{-i}(o).
-// Et is stored transposed, [o][h], so consecutive threads read consecutive h;
-// each workgroup serves J leaves whose reach vectors sit in LDS.
+// Et is stored transposed, [o][h], so consecutive threads read consecutive h.
+// The sum over o is split into kEqSplit slices, each slice of J leaves one
+// workgroup with the slice of their reach vectors in LDS; a second kernel adds
+// the slices in a fixed order (deterministic) and applies the contribution.
+constexpr int kEqSplit = 8;
+constexpr int kMaxHp = 1216;    // flop: 1176 compatible combos padded to 64
+
 template <typename T, int J>
-__global__ __launch_bounds__(kBlock) void k_equity_leaf(const int32_t* __restrict__ leaves,
-                                                        const double* __restrict__ pay, int n_leaves, int Hp,
-                                                        const T* __restrict__ Et, const T* __restrict__ reach,
-                                                        T* __restrict__ cfv) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    T* rr = reinterpret_cast<T*>(smem);   // [J][2][Hp]
+__global__ __launch_bounds__(kBlock) void k_equity_partial(const int32_t* __restrict__ leaves, int n_leaves, int Hp,
+                                                           const T* __restrict__ Et, const T* __restrict__ reach,
+                                                           T* __restrict__ part) {
+    constexpr int kChunk = (kMaxHp + kEqSplit - 1) / kEqSplit;
+    __shared__ T rr[J][2][kChunk];
     const int j0 = blockIdx.y * J;
     const int nj = min(J, n_leaves - j0);
-    for (int i = threadIdx.x; i < nj * 2 * Hp; i += kBlock) {
-        const int j = i / (2 * Hp);
-        rr[i] = reach[(int64_t)leaves[j0 + j] * 2 * Hp + (i - j * 2 * Hp)];
+    const int chunk = (Hp + kEqSplit - 1) / kEqSplit;
+    const int o0 = blockIdx.z * chunk, o1 = min(Hp, o0 + chunk);
+    for (int i = threadIdx.x; i < nj * 2 * chunk; i += kBlock) {
+        const int j = i / (2 * chunk), rest = i - j * 2 * chunk, p = rest / chunk, o = o0 + rest - p * chunk;
+        rr[j][p][o - o0] = o < o1 ? reach[(int64_t)leaves[j0 + j] * 2 * Hp + (int64_t)p * Hp + o] : T(0);
     }
     __syncthreads();
     const int h = blockIdx.x * kBlock + threadIdx.x;
@@ -499,22 +521,34 @@ __global__ __launch_bounds__(kBlock) void k_equity_leaf(const int32_t* __restric
     T acc[J][2];
 #pragma unroll
     for (int j = 0; j < J; j++) { acc[j][0] = T(0); acc[j][1] = T(0); }
-    for (int o = 0; o < Hp; o++) {
+    for (int o = o0; o < o1; o++) {
         const T e = Et[(int64_t)o * Hp + h];
 #pragma unroll
         for (int j = 0; j < J; j++) {
-            acc[j][0] += e * rr[(j * 2 + 1) * Hp + o];   // player 0 against player 1's reach
-            acc[j][1] += e * rr[(j * 2) * Hp + o];
+            acc[j][0] += e * rr[j][1][o - o0];   // player 0 against player 1's reach
+            acc[j][1] += e * rr[j][0][o - o0];
         }
     }
 #pragma unroll
     for (int j = 0; j < J; j++) {
         if (j >= nj) break;
-        const int64_t n = leaves[j0 + j];
-        const T c = (T)pay[j0 + j];
-        cfv[n * 2 * Hp + h] = c * acc[j][0];
-        cfv[n * 2 * Hp + Hp + h] = c * acc[j][1];
+        T* dst = part + (((int64_t)blockIdx.z * n_leaves + j0 + j) * 2) * Hp + h;
+        dst[0] = acc[j][0];
+        dst[Hp] = acc[j][1];
     }
+}
+
+template <typename T>
+__global__ void k_equity_reduce(const int32_t* __restrict__ leaves, const double* __restrict__ pay, int n_leaves,
+                                int Hp, const T* __restrict__ part, T* __restrict__ cfv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = 2 * (int64_t)Hp;
+    if (i >= per * n_leaves) return;
+    const int64_t j = i / per, rest = i - j * per;
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < kEqSplit; k++) acc += part[((int64_t)k * n_leaves + j) * per + rest];
+    cfv[(int64_t)leaves[j] * per + rest] = (T)pay[j] * acc;
 }
 
 __device__ __forceinline__ int combo_index(int a, int b) {
@@ -592,6 +626,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
                                                          const int32_t* __restrict__ coff,
                                                          const int16_t* __restrict__ chands,
                                                          const float* __restrict__ Y, int ldy) {
+    __shared__ T x[2][kMaxHp];
+    __shared__ int16_t c2h[kCombos];
+    __shared__ int8_t nxt[52];
     __shared__ T cs[2][52];
     __shared__ T red[2][kBlock];
     const int li = blockIdx.x;
@@ -599,18 +636,25 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
     const T* r0 = reach + n * 2 * Hp;
     const T* r1 = r0 + Hp;
     const int tid = threadIdx.x;
-    if (tid < 104) {
-        const int p = tid / 52, c = tid - p * 52;
-        const T* r = p ? r1 : r0;
-        T s = T(0);
-        for (int j = coff[c]; j < coff[c + 1]; j++) s += r[chands[j]];
-        cs[p][c] = s;
-    }
     T s0 = T(0), s1 = T(0);
-    for (int h = tid; h < Hp; h += kBlock) { s0 += r0[h]; s1 += r1[h]; }
+    for (int h = tid; h < Hp; h += kBlock) {
+        const T a = r0[h], b = r1[h];
+        x[0][h] = a;
+        x[1][h] = b;
+        s0 += a;
+        s1 += b;
+    }
+    for (int k = tid; k < kCombos; k += kBlock) c2h[k] = combo_hand[k];
+    if (tid < n_next) nxt[tid] = next_cards[tid];
     red[0][tid] = s0;
     red[1][tid] = s1;
     __syncthreads();
+    if (tid < 104) {
+        const int p = tid / 52, c = tid - p * 52;
+        T acc = T(0);
+        for (int j = coff[c]; j < coff[c + 1]; j++) acc += x[p][chands[j]];
+        cs[p][c] = acc;
+    }
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
         __syncthreads();
@@ -620,27 +664,27 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
     T* v0 = cfv + n * 2 * Hp;
     T* v1 = v0 + Hp;
     // blockIdx.y picks a tile of kBlock hands; the sums above are per leaf
-    for (int h = blockIdx.y * kBlock + tid; h < min(Hp, (int)(blockIdx.y + 1) * kBlock); h += kBlock) {
-        if (h >= H) { v0[h] = T(0); v1[h] = T(0); continue; }
-        const uint32_t hc = hcards[h];
-        const int a = hc & 0xff, b = hc >> 8;
-        const int combo = hand_combo[h];
-        T acc0 = T(0), acc1 = T(0);
-        for (int k = 0; k < n_next; k++) {
-            const int c = next_cards[k];
-            if (c == a || c == b) continue;
-            const int ha = combo_hand[combo_index(a, c)], hb = combo_hand[combo_index(b, c)];
-            const T m1 = t1 - cs[1][a] - cs[1][b] - cs[1][c] + r1[h] + (ha >= 0 ? r1[ha] : T(0)) +
-                         (hb >= 0 ? r1[hb] : T(0));
-            const T m0 = t0 - cs[0][a] - cs[0][b] - cs[0][c] + r0[h] + (ha >= 0 ? r0[ha] : T(0)) +
-                         (hb >= 0 ? r0[hb] : T(0));
-            const float* y = Y + (int64_t)(li * n_next + k) * ldy;
-            acc0 += (T)y[combo] * m1;
-            acc1 += (T)y[kCombos + combo] * m0;
-        }
-        v0[h] = scale * acc0;
-        v1[h] = scale * acc1;
+    const int h = blockIdx.y * kBlock + tid;
+    if (h >= Hp) return;
+    if (h >= H) { v0[h] = T(0); v1[h] = T(0); return; }
+    const uint32_t hc = hcards[h];
+    const int a = hc & 0xff, b = hc >> 8;
+    const int combo = hand_combo[h];
+    const T base0 = t0 - cs[0][a] - cs[0][b] + x[0][h];
+    const T base1 = t1 - cs[1][a] - cs[1][b] + x[1][h];
+    const float* y = Y + (int64_t)li * n_next * ldy;
+    T acc0 = T(0), acc1 = T(0);
+    for (int k = 0; k < n_next; k++) {
+        const int c = nxt[k];
+        if (c == a || c == b) continue;
+        const int ha = c2h[combo_index(a, c)], hb = c2h[combo_index(b, c)];
+        const T m1 = base1 - cs[1][c] + (ha >= 0 ? x[1][ha] : T(0)) + (hb >= 0 ? x[1][hb] : T(0));
+        const T m0 = base0 - cs[0][c] + (ha >= 0 ? x[0][ha] : T(0)) + (hb >= 0 ? x[0][hb] : T(0));
+        acc0 += (T)y[(int64_t)k * ldy + combo] * m1;
+        acc1 += (T)y[(int64_t)k * ldy + kCombos + combo] * m0;
     }
+    v0[h] = scale * acc0;
+    v1[h] = scale * acc1;
 }
 
 // ------------------------------------------------------------ leaf-network samples
@@ -776,7 +820,7 @@ struct Plan {
     size_t esz;
     size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, total;
+        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
     size_t lds_bytes;
 };
 
@@ -1063,9 +1107,12 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_M = take(variant == PCFR_PCFRPLUS ? L.esz * L.rows * L.Hp : 0);
     L.off_samp = take(align256(sizeof(float) * 2 * P.n_sub) + align256((size_t)P.n_sub * 52) +
                       align256(sizeof(int16_t) * (size_t)P.n_sub * kCombos));
+    L.off_eqpart = take(L.esz * kEqSplit * L.n_eq * 2 * L.Hp);
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
-    L.lds_bytes = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock);
+    const size_t sd_lds = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * qn;
+    const size_t fold_lds = L.esz * (2 * L.Hp + 104 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp;
+    L.lds_bytes = std::max(sd_lds, fold_lds);
 }
 
 }  // namespace pcfr
@@ -1154,11 +1201,14 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     const int64_t n_eq_active = s->net ? P.n_allin : L.n_eq;
     if (n_eq_active) {
         constexpr int J = sizeof(T) == 8 ? 2 : 4;
-        dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)((n_eq_active + J - 1) / J));
-        const size_t lds = (size_t)J * 2 * Hp * sizeof(T);
+        dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)((n_eq_active + J - 1) / J), kEqSplit);
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_equity_leaf<T, J>), grid, dim3(kBlock), lds, stream, s->at<int32_t>(L.off_eq),
-                           s->at<double>(L.off_eqpay), (int)n_eq_active, Hp, s->at<T>(L.off_et), reach, cfv);
+        hipLaunchKernelGGL((k_equity_partial<T, J>), grid, dim3(kBlock), 0, stream, s->at<int32_t>(L.off_eq),
+                           (int)n_eq_active, Hp, s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
+        const int64_t tot = n_eq_active * 2 * (int64_t)Hp;
+        hipLaunchKernelGGL((k_equity_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream,
+                           s->at<int32_t>(L.off_eq), s->at<double>(L.off_eqpay), (int)n_eq_active, Hp,
+                           s->at<T>(L.off_eqpart), cfv);
         if (tm) tm->after();
     }
     if (s->net && L.n_net) {
@@ -1315,7 +1365,16 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     const Plan& L = s->L;
     const Prepared& P = s->P;
     if (workspace_bytes < L.total) { set_error("workspace smaller than the size the library asked for"); return PCFR_E_OUT_OF_MEMORY; }
-    if (L.lds_bytes > 65536) { set_error("hand count too large for the showdown kernel"); return PCFR_E_TOO_LARGE; }
+    if (L.lds_bytes > 160 * 1024) { set_error("hand count too large for the terminal kernel's LDS"); return PCFR_E_TOO_LARGE; }
+    if (L.lds_bytes > 65536) {
+        // gfx950 gives a workgroup up to 160 KB of LDS; dynamic sizes above 64 KB must be declared
+        hipError_t e = cfg->dtype == PCFR_F64
+                           ? hipFuncSetAttribute(reinterpret_cast<const void*>(&k_terminal<double>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes)
+                           : hipFuncSetAttribute(reinterpret_cast<const void*>(&k_terminal<float>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+        if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+    }
     // ranges and the joint mass of compatible pairs: r0 . (total1 - per-card sums + r1)
     const ComboTable& cc = combos();
     s->ranges.assign((size_t)n * 2 * kCombos, 0.0);
