@@ -387,7 +387,7 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     const int16_t* gcoff = tb + 7 * Hp;
     const int16_t* gclist = gcoff + kSdHeader;
     int16_t* coff = reinterpret_cast<int16_t*>(part + 2 * kBlock);    // [kSdHeader], LDS copy
-    int16_t* clist = coff + kSdHeader;                                // [QN - kSdHeader], LDS copy
+    int16_t* clist = coff + kSdHeader;                                // [QN]: lists + total slots, LDS copy
     const T* r0 = reach + n * 2 * Hp;
     const T* r1 = r0 + Hp;
     const int tid = threadIdx.x;
@@ -398,7 +398,8 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         xs1[s] = r1[h];
     }
     if (tid < kSdHeader) coff[tid] = gcoff[tid];
-    for (int j = tid; j < QN - kSdHeader; j += kBlock) clist[j] = gclist[j];
+    // the lists hold 2 * Hb + 52 entries (one total slot per card) <= QN
+    for (int j = tid; j < QN; j += kBlock) clist[j] = gclist[j];
     __syncthreads();
     if (tid < 104) {
         const int p = tid / 52, c = tid - p * 52;
@@ -1110,7 +1111,7 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_eqpart = take(L.esz * kEqSplit * L.n_eq * 2 * L.Hp);
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
-    const size_t sd_lds = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * qn;
+    const size_t sd_lds = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn);
     const size_t fold_lds = L.esz * (2 * L.Hp + 104 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp;
     L.lds_bytes = std::max(sd_lds, fold_lds);
 }
