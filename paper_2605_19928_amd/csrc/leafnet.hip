@@ -29,6 +29,7 @@ namespace pcfr {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 v8bf;
 typedef __attribute__((ext_vector_type(16))) float v16f;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;   // 16-byte copies kept in registers
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -59,31 +60,31 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
     __shared__ __align__(16) uint16_t sB[2][BN * LDK];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
     const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
-    uint4 ra[CA], rb[CB];
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < CA; i++) {
-            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
-            ra[i] = *reinterpret_cast<const uint4*>(A + (m0 + row) * lda + k0 + col);
-        }
-#pragma unroll
-        for (int i = 0; i < CB; i++) {
-            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
-            rb[i] = *reinterpret_cast<const uint4*>(B + (n0 + row) * ldb + k0 + col);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < CA; i++) {
-            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
-            *reinterpret_cast<uint4*>(&sA[buf][row * LDK + col]) = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < CB; i++) {
-            int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;
-            *reinterpret_cast<uint4*>(&sB[buf][row * LDK + col]) = rb[i];
-        }
-    };
+    // global -> register staging of the next K tile (no lambdas: the
+    // staging registers must not have their address taken)
+    u32x4 ra[CA], rb[CB];
+#define LN_GLOAD(k0)                                                                               \
+    do {                                                                                           \
+        _Pragma("unroll") for (int i = 0; i < CA; i++) {                                           \
+            const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
+            ra[i] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + (k0) + col);            \
+        }                                                                                          \
+        _Pragma("unroll") for (int i = 0; i < CB; i++) {                                           \
+            const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
+            rb[i] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + (k0) + col);            \
+        }                                                                                          \
+    } while (0)
+#define LN_SSTORE(buf)                                                                             \
+    do {                                                                                           \
+        _Pragma("unroll") for (int i = 0; i < CA; i++) {                                           \
+            const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
+            *reinterpret_cast<u32x4*>(&sA[buf][row * LDK + col]) = ra[i];                          \
+        }                                                                                          \
+        _Pragma("unroll") for (int i = 0; i < CB; i++) {                                           \
+            const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
+            *reinterpret_cast<u32x4*>(&sB[buf][row * LDK + col]) = rb[i];                          \
+        }                                                                                          \
+    } while (0)
     // KACC independent accumulator chains per output tile, so consecutive
     // MFMAs of a wave do not wait on each other's results; summed at the end
     constexpr int KACC = (TM * TN >= 4) ? 1 : 4 / (TM * TN);
@@ -96,14 +97,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
             for (int j = 0; j < TN; j++)
 #pragma unroll
                 for (int r = 0; r < 16; r++) acc[q][i][j][r] = 0.f;
-    gload(0);
-    sstore(0);
+    LN_GLOAD(0);
+    LN_SSTORE(0);
     __syncthreads();
     const int kh = 8 * (lane >> 5), l32 = lane & 31;
     for (int k0 = 0; k0 < K; k0 += BK) {
         const int buf = (k0 / BK) & 1;
         const bool more = k0 + BK < K;
-        if (more) gload(k0 + BK);
+        if (more) LN_GLOAD(k0 + BK);
         // all fragments of this stage first, then the MFMAs
         v8bf a[BK / 16][TM], b[BK / 16][TN];
 #pragma unroll
@@ -125,9 +126,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
                 for (int j = 0; j < TN; j++)
                     acc[kk % KACC][i][j] =
                         __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kk][i], b[kk][j], acc[kk % KACC][i][j], 0, 0, 0);
-        if (more) sstore(buf ^ 1);
+        if (more) LN_SSTORE(buf ^ 1);
         __syncthreads();
     }
+#undef LN_GLOAD
+#undef LN_SSTORE
 #pragma unroll
     for (int q = 1; q < KACC; q++)
 #pragma unroll

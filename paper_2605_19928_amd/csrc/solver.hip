@@ -153,7 +153,7 @@ __device__ __forceinline__ bool has_card(uint32_t hc, int c) {
     return (int)(hc & 0xffu) == c || (int)(hc >> 8) == c;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int MAXA>
 __global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                     int count, int Hp, const T* __restrict__ R, const T* __restrict__ S,
                                                     const T* __restrict__ Mp, T* __restrict__ reach,
@@ -184,7 +184,10 @@ __global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ no
         return;
     }
     switch (nd.n_child) {
-#define PCFR_FWD_CASE(A) case A: fwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach); break;
+#define PCFR_FWD_CASE(A) \
+    case A:              \
+        if constexpr (A <= MAXA) fwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach); \
+        break;
         PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
         PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
 #undef PCFR_FWD_CASE
@@ -264,7 +267,7 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int MAXA>
 __global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                      int count, int Hp, T* __restrict__ R, T* __restrict__ S,
                                                      T* __restrict__ Mp, const T* __restrict__ reach,
@@ -293,7 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ n
         return;
     }
     switch (nd.n_child) {
-#define PCFR_BWD_CASE(A) case A: bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach, cfv, st); break;
+#define PCFR_BWD_CASE(A) \
+    case A:              \
+        if constexpr (A <= MAXA) bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach, cfv, st); \
+        break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
 #undef PCFR_BWD_CASE
@@ -313,7 +319,7 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
     T* x0 = lds;                  // [Hp]
     T* x1 = x0 + Hp;              // [Hp]
     T* pc = x1 + Hp;              // [2][52]
-    T* red = pc + 104;            // [2][kBlock]
+    T* red = pc + 208;            // [2][kBlock]  (pc holds two half-sums per card first)
     int16_t* lst = reinterpret_cast<int16_t*>(red + 2 * kBlock);   // [2 * Hp]
     const T* r0 = reach + n * 2 * Hp;
     const T* r1 = r0 + Hp;
@@ -331,17 +337,25 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
     red[tid] = s0;
     red[kBlock + tid] = s1;
     __syncthreads();
-    if (tid < 104) {
-        const int p = tid / 52, c = tid - p * 52;
+    if (tid < 208) {
+        // two threads per (player, card), each summing half of the card's list
+        const int pcix = tid >> 1, half = tid & 1;
+        const int p = pcix / 52, c = pcix - p * 52;
         const T* x = p ? x1 : x0;
+        const int lo = coff[c], hi = coff[c + 1], mid = lo + ((hi - lo) >> 1);
         T acc = T(0);
-        for (int j = coff[c]; j < coff[c + 1]; j++) acc += x[lst[j]];
+        for (int j = half ? mid : lo; j < (half ? hi : mid); j++) acc += x[lst[j]];
         pc[tid] = acc;
     }
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (tid < w) { red[tid] += red[tid + w]; red[kBlock + tid] += red[kBlock + tid + w]; }
         __syncthreads();
     }
+    T pcv0 = T(0), pcv1 = T(0);
+    if (tid < 104) { pcv0 = pc[2 * tid]; pcv1 = pc[2 * tid + 1]; }
+    __syncthreads();
+    if (tid < 104) pc[tid] = pcv0 + pcv1;
+    __syncthreads();
     const T tot0 = red[0], tot1 = red[kBlock];
     const int f = nd.player;
     const T pay = (T)nd.pay;
@@ -822,7 +836,7 @@ struct Plan {
     size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
-    size_t lds_bytes;
+    size_t lds_bytes, lds_fold, lds_show;
 };
 
 struct Prepared {
@@ -832,6 +846,8 @@ struct Prepared {
     std::vector<DNode> nodes;
     std::vector<int32_t> fwd, term;
     std::vector<int64_t> fwd_off;         // per level start into fwd (size levels+1)
+    std::vector<int32_t> lvl_maxa;        // per level: most actions of a decision node
+    std::vector<int32_t> folds, shows;    // terminal lists by kind
     std::vector<uint16_t> hcards;         // [n_sub][Hp]
     std::vector<int32_t> coff;            // [n_sub][53]
     std::vector<int16_t> chands;          // [n_sub][chand_stride]
@@ -990,10 +1006,18 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
         else P.next_cards.push_back((int8_t)c);
     }
     P.fwd_off.assign(P.levels + 1, 0);
+    P.lvl_maxa.assign(P.levels, 0);
     for (int l = 0; l < P.levels; l++) {
         P.fwd_off[l] = (int64_t)P.fwd.size();
-        for (auto x : per_level[l]) P.fwd.push_back(x);
+        for (auto x : per_level[l]) {
+            P.fwd.push_back(x);
+            if (P.nodes[x].type == PCFR_NODE_DECISION) P.lvl_maxa[l] = std::max(P.lvl_maxa[l], P.nodes[x].n_child);
+        }
     }
+    for (auto x : P.term) (P.nodes[x].type == PCFR_NODE_FOLD ? P.folds : P.shows).push_back(x);
+    P.term.clear();
+    P.term.insert(P.term.end(), P.folds.begin(), P.folds.end());
+    P.term.insert(P.term.end(), P.shows.begin(), P.shows.end());
     P.fwd_off[P.levels] = (int64_t)P.fwd.size();
     // strength tables
     const int64_t nbds = (int64_t)board_id.size();
@@ -1112,7 +1136,9 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
     const size_t sd_lds = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn);
-    const size_t fold_lds = L.esz * (2 * L.Hp + 104 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp;
+    const size_t fold_lds = L.esz * (2 * L.Hp + 208 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp;
+    L.lds_fold = fold_lds;
+    L.lds_show = sd_lds;
     L.lds_bytes = std::max(sd_lds, fold_lds);
 }
 
@@ -1179,22 +1205,36 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->cfg.beta, s->cfg.gamma);
         if (tm) tm->after();
     }
+    // the kernels are instantiated for at most 3, 6 or 12 actions; a level
+    // uses the smallest that covers its nodes (fewer registers, more waves)
+#define PCFR_BUCKET(KER, l, ...)                                                                      \
+    do {                                                                                              \
+        const int ma = P.lvl_maxa[l];                                                                 \
+        if (ma <= 3) hipLaunchKernelGGL((KER<T, MODE, 3>), __VA_ARGS__);                              \
+        else if (ma <= 6) hipLaunchKernelGGL((KER<T, MODE, 6>), __VA_ARGS__);                         \
+        else hipLaunchKernelGGL((KER<T, MODE, 12>), __VA_ARGS__);                                     \
+    } while (0)
     for (int l = 0; l < P.levels; l++) {
         int64_t cnt = P.fwd_off[l + 1] - P.fwd_off[l];
         if (!cnt) continue;
         int64_t threads = cnt * groups;
         dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
         if (tm) tm->before(1);
-        hipLaunchKernelGGL((k_forward<T, MODE>), grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l],
-                           (int)cnt, Hp, R, S, Mp, reach, s->at<uint16_t>(L.off_hc));
+        PCFR_BUCKET(k_forward, l, grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
+                    reach, s->at<uint16_t>(L.off_hc));
         if (tm) tm->after();
     }
-    if (L.term) {
+    // terminals: folds and showdowns in separate launches, each with the LDS it needs
+    const int64_t n_fold = (int64_t)P.folds.size(), n_show = (int64_t)P.shows.size();
+    for (int kind = 0; kind < 2; kind++) {
+        const int64_t cnt = kind ? n_show : n_fold;
+        if (!cnt) continue;
         if (tm) tm->before(2);
-        hipLaunchKernelGGL((k_terminal<T>), dim3((unsigned)L.term), dim3(kBlock), L.lds_bytes, stream, nodes,
-                           s->at<int32_t>(L.off_term), Hp, reach, cfv, s->at<uint16_t>(L.off_hc),
-                           s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands), (int)L.chand_stride,
-                           s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn));
+        hipLaunchKernelGGL((k_terminal<T>), dim3((unsigned)cnt), dim3(kBlock), kind ? L.lds_show : L.lds_fold, stream,
+                           nodes, s->at<int32_t>(L.off_term) + (kind ? n_fold : 0), Hp, reach, cfv,
+                           s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
+                           (int)L.chand_stride, s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride,
+                           s->at<int32_t>(L.off_sdn));
         if (tm) tm->after();
     }
     // depth-limit leaves: exact equity for all-in leaves (and for every leaf
@@ -1240,10 +1280,11 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         int64_t threads = cnt * groups;
         dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
         if (tm) tm->before(3);
-        hipLaunchKernelGGL((k_backward<T, MODE>), grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l],
-                           (int)cnt, Hp, R, S, Mp, reach, cfv, st);
+        PCFR_BUCKET(k_backward, l, grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
+                    reach, cfv, st);
         if (tm) tm->after();
     }
+#undef PCFR_BUCKET
     if (MODE == MODE_ITER) {
         int64_t n = 2 * L.Hp * P.n_sub;
         if (tm) tm->before(0);
