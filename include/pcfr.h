@@ -166,8 +166,9 @@ int32_t pcfr_synchronize(pcfr_solver* s);
  * device time and launch count per kernel class: [0] iteration bookkeeping,
  * [1] forward reach sweep, [2] fold/showdown terminals, [3] backward value
  * and regret sweep, [4] depth-limit leaves (exact equity, network input and
- * combine), [5] leaf-network GEMMs, [6..7] unused.  ms and launches are host
- * arrays of 8.  Synchronises. */
+ * combine), [5] leaf-network hidden-layer GEMMs (bias + ReLU), [6] its output
+ * layer GEMM, [7] unused.  ms and launches are host arrays of 8.
+ * Synchronises. */
 int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* launches);
 int32_t pcfr_iteration(pcfr_solver* s, int64_t* t);   /* synchronises */
 

@@ -60,29 +60,33 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
     __shared__ __align__(16) uint16_t sB[2][BN * LDK];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
     const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
-    // global -> register staging of the next K tile (no lambdas: the
-    // staging registers must not have their address taken)
-    u32x4 ra[CA], rb[CB];
-#define LN_GLOAD(k0)                                                                               \
+    // Global -> register -> LDS pipeline.  Tiles are fetched two K-stages
+    // ahead into a 3-slot register ring (slot indices are compile-time
+    // constants after the 3-way unroll below, so the ring stays in
+    // registers), stored to the idle LDS buffer one stage ahead, and consumed
+    // from LDS by the MFMAs.
+    constexpr int D = 3;
+    u32x4 ra[D][CA], rb[D][CB];
+#define LN_GLOAD(slot, k0)                                                                         \
     do {                                                                                           \
         _Pragma("unroll") for (int i = 0; i < CA; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            ra[i] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + (k0) + col);            \
+            ra[slot][i] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + (k0) + col);      \
         }                                                                                          \
         _Pragma("unroll") for (int i = 0; i < CB; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            rb[i] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + (k0) + col);            \
+            rb[slot][i] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + (k0) + col);      \
         }                                                                                          \
     } while (0)
-#define LN_SSTORE(buf)                                                                             \
+#define LN_SSTORE(slot, buf)                                                                       \
     do {                                                                                           \
         _Pragma("unroll") for (int i = 0; i < CA; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            *reinterpret_cast<u32x4*>(&sA[buf][row * LDK + col]) = ra[i];                          \
+            *reinterpret_cast<u32x4*>(&sA[buf][row * LDK + col]) = ra[slot][i];                    \
         }                                                                                          \
         _Pragma("unroll") for (int i = 0; i < CB; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            *reinterpret_cast<u32x4*>(&sB[buf][row * LDK + col]) = rb[i];                          \
+            *reinterpret_cast<u32x4*>(&sB[buf][row * LDK + col]) = rb[slot][i];                    \
         }                                                                                          \
     } while (0)
     // KACC independent accumulator chains per output tile, so consecutive
@@ -97,38 +101,43 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
             for (int j = 0; j < TN; j++)
 #pragma unroll
                 for (int r = 0; r < 16; r++) acc[q][i][j][r] = 0.f;
-    LN_GLOAD(0);
-    LN_SSTORE(0);
-    __syncthreads();
+    const int nk = K / BK;
     const int kh = 8 * (lane >> 5), l32 = lane & 31;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        const int buf = (k0 / BK) & 1;
-        const bool more = k0 + BK < K;
-        if (more) LN_GLOAD(k0 + BK);
-        // all fragments of this stage first, then the MFMAs
-        v8bf a[BK / 16][TM], b[BK / 16][TN];
-#pragma unroll
-        for (int kk = 0; kk < BK / 16; kk++) {
-#pragma unroll
-            for (int i = 0; i < TM; i++)
-                a[kk][i] = *reinterpret_cast<const v8bf*>(
-                    &sA[buf][(wm * (BM / 2) + i * 32 + l32) * LDK + kk * 16 + kh]);
-#pragma unroll
-            for (int j = 0; j < TN; j++)
-                b[kk][j] = *reinterpret_cast<const v8bf*>(
-                    &sB[buf][(wn * (BN / 2) + j * 32 + l32) * LDK + kk * 16 + kh]);
-        }
-#pragma unroll
-        for (int kk = 0; kk < BK / 16; kk++)
-#pragma unroll
-            for (int i = 0; i < TM; i++)
-#pragma unroll
-                for (int j = 0; j < TN; j++)
-                    acc[kk % KACC][i][j] =
-                        __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kk][i], b[kk][j], acc[kk % KACC][i][j], 0, 0, 0);
-        if (more) LN_SSTORE(buf ^ 1);
-        __syncthreads();
+    LN_GLOAD(0, 0);
+    if (nk > 1) LN_GLOAD(1, BK);
+    LN_SSTORE(0, 0);
+    __syncthreads();
+#define LN_COMPUTE(buf)                                                                            \
+    do {                                                                                           \
+        v8bf fa[BK / 16][TM], fb[BK / 16][TN];                                                     \
+        _Pragma("unroll") for (int kk = 0; kk < BK / 16; kk++) {                                   \
+            _Pragma("unroll") for (int i = 0; i < TM; i++) fa[kk][i] = *reinterpret_cast<const v8bf*>( \
+                &sA[buf][(wm * (BM / 2) + i * 32 + l32) * LDK + kk * 16 + kh]);                    \
+            _Pragma("unroll") for (int j = 0; j < TN; j++) fb[kk][j] = *reinterpret_cast<const v8bf*>( \
+                &sB[buf][(wn * (BN / 2) + j * 32 + l32) * LDK + kk * 16 + kh]);                    \
+        }                                                                                          \
+        _Pragma("unroll") for (int kk = 0; kk < BK / 16; kk++)                                     \
+            _Pragma("unroll") for (int i = 0; i < TM; i++)                                         \
+                _Pragma("unroll") for (int j = 0; j < TN; j++)                                     \
+                    acc[kk % KACC][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(               \
+                        fa[kk][i], fb[kk][j], acc[kk % KACC][i][j], 0, 0, 0);                      \
+    } while (0)
+    // one stage: prefetch stage kt+2 into slot LSLOT, compute stage kt, move
+    // stage kt+1 (slot SSLOT) into the other LDS buffer
+#define LN_STAGE(kt, LSLOT, SSLOT)                                                                 \
+    do {                                                                                           \
+        if ((kt) + 2 < nk) LN_GLOAD(LSLOT, ((kt) + 2) * BK);                                       \
+        LN_COMPUTE((kt) & 1);                                                                      \
+        if ((kt) + 1 < nk) LN_SSTORE(SSLOT, ((kt) + 1) & 1);                                       \
+        __syncthreads();                                                                           \
+    } while (0)
+    for (int kt = 0; kt < nk; kt += 3) {
+        LN_STAGE(kt, 2, 1);
+        if (kt + 1 < nk) LN_STAGE(kt + 1, 0, 2);
+        if (kt + 2 < nk) LN_STAGE(kt + 2, 1, 0);
     }
+#undef LN_STAGE
+#undef LN_COMPUTE
 #undef LN_GLOAD
 #undef LN_SSTORE
 #pragma unroll
@@ -492,13 +501,14 @@ int32_t pcfr_leafnet_get_grads(pcfr_leafnet* n, float* host) {
 namespace pcfr {
 
 // Forward over the rows already staged in the bf16 input buffer; M = padded rows.
-int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st) {
+int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st, LaunchTimer* tm) {
     const LeafNetPlan& P = n->P;
     const uint16_t* in = reinterpret_cast<const uint16_t*>(n->ws + P.off_x);
     for (int l = 0; l < P.L; l++) {
         const uint16_t* W = reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l];
         const float* b = reinterpret_cast<const float*>(n->ws + P.off_p) + P.boff[l];
         int32_t rc;
+        if (tm) tm->before(l + 1 < P.L ? 5 : 6);
         if (l + 1 < P.L) {
             uint16_t* h = reinterpret_cast<uint16_t*>(n->ws + P.off_h[l + 1]);
             rc = launch_gemm(st, EPI_BIAS_RELU_BF, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
@@ -508,6 +518,7 @@ int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st) {
             rc = launch_gemm(st, EPI_BIAS_F32, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
                              P.pdims[l], b, n->ws + P.off_y, (int)P.pdims[l + 1], nullptr);
         }
+        if (tm) tm->after();
         if (rc) return rc;
     }
     return PCFR_OK;

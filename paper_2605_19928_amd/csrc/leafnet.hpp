@@ -36,5 +36,28 @@ struct pcfr_leafnet {
 };
 
 namespace pcfr {
-int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st);
+
+// Optional per-launch timing: events recorded around every launch, tagged
+// with a kernel class (0 bookkeeping, 1 forward, 2 terminal, 3 backward,
+// 4 leaves, 5 hidden-layer GEMMs, 6 output-layer GEMM).
+struct LaunchTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> cls;
+    hipStream_t stream;
+    void before(int c) {
+        hipEvent_t a;
+        (void)hipEventCreate(&a);
+        (void)hipEventRecord(a, stream);
+        ev.push_back(a);
+        cls.push_back(c);
+    }
+    void after() {
+        hipEvent_t b;
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(b, stream);
+        ev.push_back(b);
+    }
+};
+
+int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st, LaunchTimer* tm = nullptr);
 }

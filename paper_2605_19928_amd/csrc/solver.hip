@@ -513,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
 // The sum over o is split into kEqSplit slices, each slice of J leaves one
 // workgroup with the slice of their reach vectors in LDS; a second kernel adds
 // the slices in a fixed order (deterministic) and applies the contribution.
-constexpr int kEqSplit = 8;
+constexpr int kEqSplit = 32;
 constexpr int kMaxHp = 1216;    // flop: 1176 compatible combos padded to 64
 
 template <typename T, int J>
@@ -630,6 +630,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_input(const int32_t* __restrict
 // chance probability): v_i(h) = pot/K * sum_{c not in h} EV_i(h | c) *
 // M_{-i}(h | c), where M(h | c) is the opponent reach over hands sharing no
 // card with h or c:  T - C[a] - C[b] - C[c] + r(ab) + r(ac) + r(bc).
+// One workgroup per (leaf, tile of 64 hands); its 4 waves take every 4th
+// next card and the partial sums are added in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restrict__ leaves,
                                                          const double* __restrict__ pot_over_k, int n_next,
@@ -675,31 +677,44 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
         __syncthreads();
     }
     const T t0 = red[0][0], t1 = red[1][0];
-    const T scale = (T)pot_over_k[li];
-    T* v0 = cfv + n * 2 * Hp;
-    T* v1 = v0 + Hp;
-    // blockIdx.y picks a tile of kBlock hands; the sums above are per leaf
-    const int h = blockIdx.y * kBlock + tid;
-    if (h >= Hp) return;
-    if (h >= H) { v0[h] = T(0); v1[h] = T(0); return; }
-    const uint32_t hc = hcards[h];
-    const int a = hc & 0xff, b = hc >> 8;
-    const int combo = hand_combo[h];
-    const T base0 = t0 - cs[0][a] - cs[0][b] + x[0][h];
-    const T base1 = t1 - cs[1][a] - cs[1][b] + x[1][h];
-    const float* y = Y + (int64_t)li * n_next * ldy;
+    __syncthreads();   // red is reused for the partial sums below
+    const int lane = tid & 63, grp = tid >> 6;
+    const int h = blockIdx.y * 64 + lane;
     T acc0 = T(0), acc1 = T(0);
-    for (int k = 0; k < n_next; k++) {
-        const int c = nxt[k];
-        if (c == a || c == b) continue;
-        const int ha = c2h[combo_index(a, c)], hb = c2h[combo_index(b, c)];
-        const T m1 = base1 - cs[1][c] + (ha >= 0 ? x[1][ha] : T(0)) + (hb >= 0 ? x[1][hb] : T(0));
-        const T m0 = base0 - cs[0][c] + (ha >= 0 ? x[0][ha] : T(0)) + (hb >= 0 ? x[0][hb] : T(0));
-        acc0 += (T)y[(int64_t)k * ldy + combo] * m1;
-        acc1 += (T)y[(int64_t)k * ldy + kCombos + combo] * m0;
+    const bool live = h < H;
+    int a = 0, b = 0, combo = 0;
+    T base0 = T(0), base1 = T(0);
+    if (live) {
+        const uint32_t hc = hcards[h];
+        a = hc & 0xff;
+        b = hc >> 8;
+        combo = hand_combo[h];
+        base0 = t0 - cs[0][a] - cs[0][b] + x[0][h];
+        base1 = t1 - cs[1][a] - cs[1][b] + x[1][h];
+        const float* y = Y + (int64_t)li * n_next * ldy;
+        for (int k = grp; k < n_next; k += 4) {
+            const int c = nxt[k];
+            if (c == a || c == b) continue;
+            const int ha = c2h[combo_index(a, c)], hb = c2h[combo_index(b, c)];
+            const T m1 = base1 - cs[1][c] + (ha >= 0 ? x[1][ha] : T(0)) + (hb >= 0 ? x[1][hb] : T(0));
+            const T m0 = base0 - cs[0][c] + (ha >= 0 ? x[0][ha] : T(0)) + (hb >= 0 ? x[0][hb] : T(0));
+            acc0 += (T)y[(int64_t)k * ldy + combo] * m1;
+            acc1 += (T)y[(int64_t)k * ldy + kCombos + combo] * m0;
+        }
     }
-    v0[h] = scale * acc0;
-    v1[h] = scale * acc1;
+    red[0][tid] = acc0;
+    red[1][tid] = acc1;
+    __syncthreads();
+    if (grp == 0 && h < Hp) {
+        T* v0 = cfv + n * 2 * Hp;
+        T* v1 = v0 + Hp;
+        if (!live) { v0[h] = T(0); v1[h] = T(0); return; }
+        const T scale = (T)pot_over_k[li];
+        const T f0 = ((red[0][lane] + red[0][64 + lane]) + red[0][128 + lane]) + red[0][192 + lane];
+        const T f1 = ((red[1][lane] + red[1][64 + lane]) + red[1][128 + lane]) + red[1][192 + lane];
+        v0[h] = scale * f0;
+        v1[h] = scale * f1;
+    }
 }
 
 // ------------------------------------------------------------ leaf-network samples
@@ -1164,27 +1179,6 @@ struct pcfr_solver {
 
 namespace pcfr {
 
-// Optional per-launch timing: events recorded around every launch, tagged
-// with a kernel class (0 small kernels, 1 forward, 2 terminal, 3 backward).
-struct LaunchTimer {
-    std::vector<hipEvent_t> ev;
-    std::vector<int> cls;
-    hipStream_t stream;
-    void before(int c) {
-        hipEvent_t a;
-        (void)hipEventCreate(&a);
-        (void)hipEventRecord(a, stream);
-        ev.push_back(a);
-        cls.push_back(c);
-    }
-    void after() {
-        hipEvent_t b;
-        (void)hipEventCreate(&b);
-        (void)hipEventRecord(b, stream);
-        ev.push_back(b);
-    }
-};
-
 template <typename T, int MODE>
 static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm = nullptr) {
     const Plan& L = s->L;
@@ -1260,12 +1254,11 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->at<float>(L.off_spr), (int)L.n_next, s->at<int8_t>(L.off_next), Hp, (int)L.H, reach,
                            s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_c2h), s->at<uint8_t>(L.off_hot),
                            reinterpret_cast<uint16_t*>(net->ws + net->P.off_x), (int)net->P.pdims[0]);
-        if (tm) { tm->after(); tm->before(5); }
-        int32_t rc = leafnet_forward_staged(net, Mp, stream);
         if (tm) tm->after();
+        int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
         if (rc) return rc;
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)((Hp + kBlock - 1) / kBlock)),
+        hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)((Hp + 63) / 64)),
                            dim3(kBlock), 0, stream,
                            s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), (int)L.n_next,
                            s->at<int8_t>(L.off_next), Hp, (int)L.H, reach, cfv, s->at<uint16_t>(L.off_hc),
