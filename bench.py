@@ -23,6 +23,12 @@ Dirichlet(1) ranges, pot 166, stacks 1006 (seed 0 of pot log-uniform in
 all-in, at most 3 per street: 77,529 nodes, 74,312 action rows, FP32.  Its
 685 MB of regret and average-strategy state is the HBM-bound part.
 
+Batch workload (``--workload batch``, and ``batch`` inside the flop line):
+256 independent subgames, 179 river + 77 turn, each with its own board,
+ranges, pot, stack and bet abstraction, redrawn until 10-2000 nodes; one
+forest advanced by one graph replay per iteration after the launch-schedule
+autotuner, against the same subgames solved one at a time.
+
 Prints one JSON line.  ``--gpus`` above 1 is refused: the solver runs on one
 GPU.
 """
@@ -46,10 +52,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="flop", choices=["flop", "turn"])
+    ap.add_argument("--workload", default="flop", choices=["flop", "turn", "batch"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--profile-iters", type=int, default=5)
-    ap.add_argument("--no-secondary", action="store_true", help="skip the turn tree-sweep measurement")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the turn and batch measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-mb", type=int, default=0,
@@ -191,6 +197,63 @@ def tree_sweep(args, seed, steps, warmup):
     return out, spec, r
 
 
+def batch_sweep(args, seed, steps, warmup, individual=True):
+    """256 river/turn subgames of uneven size in one forest: ms per batched
+    iteration (after the autotuner) against the same subgames solved one at a
+    time, and the backward kernel's HBM roofline over the whole forest."""
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+
+    cases = I.batch_config(seed, lambda s: P.Tree(**s).n_nodes, n=256, river_share=0.7, lo=10, hi=2000)
+    trees = [P.Tree(**s) for s, _ in cases]
+    nodes = np.array([t.n_nodes for t in trees])
+    rows = np.array([t.n_rows for t in trees])
+    hands = np.array([t.n_hands for t in trees])
+    n_river = sum(1 for s, _ in cases if len(s["board"]) == 5)
+    log(f"batch of {len(trees)}: {n_river} river + {len(trees) - n_river} turn, nodes {nodes.min()}..{nodes.max()} "
+        f"(median {int(np.median(nodes))}), {int(nodes.sum())} in all")
+    b = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=args.dtype))
+    before, after = b.autotune(5)
+    log(f"autotune: {before:.4f} -> {after:.4f} ms/iter")
+    ms = timed(b, steps, warmup)
+    pms, pl = b.profile(args.profile_iters)
+    pms, pl = pms / args.profile_iters, pl // args.profile_iters
+    esz = 8 if args.dtype == "f64" else 4
+    alg_bytes = 4 * esz * float((rows * hands).sum())
+    achieved = alg_bytes / (pms[3] * 1e-3) / 1e9
+    expl, _ = b.exploitability_all()
+    out = {
+        "workload": f"256 river/turn subgames in one forest, seed {seed}",
+        "subgames": len(trees), "river": n_river, "turn": len(trees) - n_river,
+        "nodes_min": int(nodes.min()), "nodes_median": int(np.median(nodes)), "nodes_max": int(nodes.max()),
+        "nodes_total": int(nodes.sum()), "action_rows_total": int(rows.sum()),
+        "ms_per_iter": ms, "iters_per_s": 1000.0 / ms,
+        "autotune_ms_per_iter_before_after": [before, after],
+        "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
+        "exploitability_mbb_per_hand_mean": float(np.mean(expl)) * 100.0,
+        "roofline": {
+            "kernel": "k_backward<float,0> over the forest", "bound": "hbm", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_us": 1e3 * pms[3] / max(pl[3], 1), "launches_per_iter": int(pl[3]),
+            "alg_bytes_per_iter": alg_bytes,
+        },
+    }
+    b.close()
+    if individual:
+        # the same subgames one at a time, default launch schedule where no
+        # size bucket was tuned; iterates are bitwise those of the batch
+        tot = 0.0
+        isteps = max(10, steps // 4)
+        for (s, r), t in zip(cases, trees):
+            one = P.Solver(t, r, P.SolverConfig(dtype=args.dtype))
+            tot += timed(one, isteps, 3)
+            one.close()
+        out["one_at_a_time_ms_per_iter"] = tot
+        out["batched_speedup"] = tot / ms
+        log(f"batch: {ms:.4f} ms/iter batched, {tot:.4f} ms one at a time ({tot / ms:.1f}x)")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -208,6 +271,19 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration kernel: read {args.calibrate_mb} MiB, wrote {args.calibrate_mb} MiB")
         del x, y
+
+    if args.workload == "batch":
+        out = batch_sweep(args, args.seed, args.steps, args.warmup)
+        result = {
+            "metric": "DCFR ms/iter & iters/sec, flop depth-limited subgame; exploitability mbb/hand",
+            "value": out["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": out["ms_per_iter"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+            "config": {k: v for k, v in out.items() if k not in ("roofline", "kernel_ms_per_iter")},
+            "roofline": out["roofline"],
+        }
+        print(json.dumps(result), flush=True)
+        return
 
     if args.workload == "turn":
         sweep, spec, r = tree_sweep(args, args.seed, args.steps, args.warmup)
@@ -236,6 +312,8 @@ def main():
     net.set_params(params)
     solver.attach_leafnet(net)
     flops_alg = 2.0 * rows * sum(o * i for o, i in net.layer_shapes())
+    tune_before, tune_after = solver.autotune(5)
+    log(f"autotune: {tune_before:.4f} -> {tune_after:.4f} ms/iter; network GEMM tiles {net.tiles}")
     ms = timed(solver, args.steps, args.warmup)
     log(f"{args.steps} steps: {ms:.4f} ms/iter")
     pms, pl = solver.profile(args.profile_iters)
@@ -275,10 +353,13 @@ def main():
         },
         "exploitability_mbb_per_hand": expl * 100.0,
         "exploitability_note": "of the average strategy within the depth-limited game, leaves valued by the network",
+        "autotune_ms_per_iter_before_after": [tune_before, tune_after],
+        "leaf_gemm_tiles": net.tiles,
         "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
         "leaf_gemm_all_layers_tflops": all_gemm_tflops,
         "roofline": {
-            "kernel": "k_gemm_nt<64,64,1> (leaf network hidden layers: bias + ReLU, bf16 MFMA 32x32x16)",
+            "kernel": "k_gemm_nt<BM,BN,1> (leaf network hidden layers: bias + ReLU, bf16 MFMA 32x32x16; "
+                      "tile per layer from the autotuner)",
             "bound": "mfma",
             "achieved": achieved,
             "peak": BF16_PEAK_TFLOPS,
@@ -294,6 +375,7 @@ def main():
     if not args.no_secondary:
         sweep, _, _ = tree_sweep(args, 0, max(20, args.steps // 4), 5)
         result["tree_sweep"] = sweep
+        result["batch"] = batch_sweep(args, 0, max(20, args.steps // 4), 5)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(spec, r, args.cpu_seconds, leaf_params=params)

@@ -217,6 +217,21 @@ int32_t pcfr_batch_get_root_cfv(pcfr_solver* s, int32_t sub, int32_t which, doub
 /* chips_per_hand: host [n]; br: host [n][2] or NULL.  Synchronises. */
 int32_t pcfr_batch_exploitability(pcfr_solver* s, double* chips_per_hand, double* br);
 
+/* Launch-schedule autotuner for a solver or batch that has not iterated yet
+ * (else PCFR_E_STATE).  Each level's forward and backward sweep launch is
+ * timed at workgroup sizes 64, 128, 256 and 512 over reps >= 1 iterations;
+ * the fastest size per launch is kept, cached for the launch's size bucket
+ * (phase, dtype, action-count bucket, log2 of its thread count) so that
+ * solvers created later in the process start from it, and the iteration is
+ * captured again.  ms_before / ms_after: host doubles, ms per iteration of
+ * the captured iteration before and after tuning.  The sweep schedule
+ * changes no arithmetic: without a network, iterates stay bitwise identical.
+ * When a leaf network is attached, its forward GEMM tiles are tuned too (as
+ * pcfr_leafnet_autotune for the solver's network rows; that choice can move
+ * network outputs in the last bits).  The state is reset to iteration 0 on
+ * return.  Synchronises. */
+int32_t pcfr_autotune(pcfr_solver* s, int32_t reps, double* ms_before, double* ms_after);
+
 /* ---------------------------------------------------------------- leaf network
  * The value network f_theta of depth-limited solving (Sec. 3): a ReLU MLP
  * d_in -> width x depth -> d_out evaluated for all leaves of an iteration in
@@ -242,6 +257,25 @@ int32_t pcfr_leafnet_get_grads(pcfr_leafnet* net, float* host);
 /* y[m][d_out] = f(x[m][d_in]); x and y device FP32 (x is rounded to bf16
  * on the device).  Asynchronous. */
 int32_t pcfr_leafnet_forward(pcfr_leafnet* net, const float* x, int32_t m, float* y);
+
+/* Tile autotuner of the forward GEMMs for batches of m rows: every layer is
+ * timed over reps >= 1 launches with each workgroup tile (64x64, 128x64,
+ * 64x128, 128x128 rows x columns) that divides its output width, and the
+ * fastest is kept for all later forward calls (including the solver's leaf
+ * stage).  Tiles group the FP32 partial sums differently, so outputs may
+ * change in the last bits; for a fixed choice they are deterministic.  ms_before /
+ * ms_after: host doubles, ms per forward pass before and after.  Clobbers
+ * the staged activations.  Synchronises. */
+int32_t pcfr_leafnet_autotune(pcfr_leafnet* net, int32_t m, int32_t reps, double* ms_before, double* ms_after);
+
+/* Forward GEMM tile per layer (count = depth + 1 layers): PCFR_TILE_DEFAULT
+ * (-1, chosen from the shape), PCFR_TILE_64x64, PCFR_TILE_128x64,
+ * PCFR_TILE_64x128 or PCFR_TILE_128x128 (rows x columns; the column count
+ * must divide the layer's output width padded to 64, else
+ * PCFR_E_INVALID_ARG).  get returns the current choice. */
+enum { PCFR_TILE_DEFAULT = -1, PCFR_TILE_64x64 = 0, PCFR_TILE_128x64 = 1, PCFR_TILE_64x128 = 2, PCFR_TILE_128x128 = 3 };
+int32_t pcfr_leafnet_set_tiles(pcfr_leafnet* net, const int32_t* tiles, int32_t count);
+int32_t pcfr_leafnet_get_tiles(pcfr_leafnet* net, int32_t* tiles, int32_t count);
 
 /* One Adam step (beta 0.9/0.999, eps 1e-8, learning rate lr) on the Huber
  * loss (delta 1) between f(x) and target over entries where mask != 0,

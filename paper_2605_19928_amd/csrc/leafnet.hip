@@ -48,9 +48,11 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 //   EPI_MASK_BF       C = (A B^T) * [mask > 0]   (bf16 out, mask bf16 [M][ldc])
 enum { EPI_BIAS_F32 = 0, EPI_BIAS_RELU_BF = 1, EPI_F32 = 2, EPI_MASK_BF = 3 };
 
+// Rows of A past M (the last row tile of a 128-row tiling) are read as row
+// M - 1 and their outputs are not stored.
 template <int BM, int BN, int EPI>
 __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
-                                                 const uint16_t* __restrict__ B, int ldb, int K,
+                                                 const uint16_t* __restrict__ B, int ldb, int M, int K,
                                                  const float* __restrict__ bias, void* __restrict__ Cout, int ldc,
                                                  const uint16_t* __restrict__ mask) {
     constexpr int BK = 64, LDK = BK + 8;
@@ -71,7 +73,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
     do {                                                                                           \
         _Pragma("unroll") for (int i = 0; i < CA; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            ra[slot][i] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + (k0) + col);      \
+            const int64_t ar = m0 + row < M ? m0 + row : M - 1;                                    \
+            ra[slot][i] = *reinterpret_cast<const u32x4*>(A + ar * lda + (k0) + col);              \
         }                                                                                          \
         _Pragma("unroll") for (int i = 0; i < CB; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
@@ -157,6 +160,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int64_t row = m0 + wm * (BM / 2) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row >= M) continue;
                 float v = acc[0][i][j][r] + bv;
                 if (EPI == EPI_BIAS_F32 || EPI == EPI_F32) {
                     reinterpret_cast<float*>(Cout)[row * ldc + col] = v;
@@ -297,33 +301,40 @@ static int32_t hipchk(hipError_t e, const char* what) {
 static int64_t r64(int64_t x) { return (x + 63) / 64 * 64; }
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool gemm_tile_valid(int tile, int64_t N) {
+    static const int bn[kGemmTiles] = {64, 64, 128, 128};
+    return tile >= 0 && tile < kGemmTiles && N % bn[tile] == 0;
+}
+
 int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M,
-                    int64_t N, int64_t K, const float* bias, void* C, int ldc, const uint16_t* mask) {
+                    int64_t N, int64_t K, const float* bias, void* C, int ldc, const uint16_t* mask, int tile) {
     if (M % 64 || N % 64 || K % 64 || M <= 0 || N <= 0 || K <= 0) {
         set_error("GEMM dims must be positive multiples of 64");
         return PCFR_E_INVALID_ARG;
     }
-    // 128 x 128 tiles when they still give at least one workgroup per CU
-    const bool big = (M % 128 == 0) && (N % 128 == 0) && (M / 128) * (N / 128) >= 256;
-    dim3 blk(256);
-#define LN_GEMM(BMv, BNv, E)                                                                                      \
-    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E>), dim3((unsigned)(N / BNv), (unsigned)(M / BMv)), blk, 0, st, A, \
-                       lda, B, ldb, (int)K, bias, C, ldc, mask)
-    if (big) {
-        switch (epi) {
-            case EPI_BIAS_F32: LN_GEMM(128, 128, EPI_BIAS_F32); break;
-            case EPI_BIAS_RELU_BF: LN_GEMM(128, 128, EPI_BIAS_RELU_BF); break;
-            case EPI_F32: LN_GEMM(128, 128, EPI_F32); break;
-            default: LN_GEMM(128, 128, EPI_MASK_BF); break;
-        }
-    } else {
-        switch (epi) {
-            case EPI_BIAS_F32: LN_GEMM(64, 64, EPI_BIAS_F32); break;
-            case EPI_BIAS_RELU_BF: LN_GEMM(64, 64, EPI_BIAS_RELU_BF); break;
-            case EPI_F32: LN_GEMM(64, 64, EPI_F32); break;
-            default: LN_GEMM(64, 64, EPI_MASK_BF); break;
-        }
+    if (tile < 0) {
+        // default: 128 x 128 tiles when they still give at least one workgroup per CU
+        tile = (M % 128 == 0) && (N % 128 == 0) && (M / 128) * (N / 128) >= 256 ? GEMM_128x128 : GEMM_64x64;
     }
+    if (!gemm_tile_valid(tile, N)) { set_error("GEMM tile does not divide N"); return PCFR_E_INVALID_ARG; }
+    dim3 blk(256);
+#define LN_GEMM(BMv, BNv, E)                                                                                   \
+    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E>), dim3((unsigned)(N / BNv), (unsigned)((M + BMv - 1) / BMv)), \
+                       blk, 0, st, A, lda, B, ldb, (int)M, (int)K, bias, C, ldc, mask)
+#define LN_EPI(BMv, BNv)                                                   \
+    switch (epi) {                                                         \
+        case EPI_BIAS_F32: LN_GEMM(BMv, BNv, EPI_BIAS_F32); break;         \
+        case EPI_BIAS_RELU_BF: LN_GEMM(BMv, BNv, EPI_BIAS_RELU_BF); break; \
+        case EPI_F32: LN_GEMM(BMv, BNv, EPI_F32); break;                   \
+        default: LN_GEMM(BMv, BNv, EPI_MASK_BF); break;                    \
+    }
+    switch (tile) {
+        case GEMM_64x64: LN_EPI(64, 64); break;
+        case GEMM_128x64: LN_EPI(128, 64); break;
+        case GEMM_64x128: LN_EPI(64, 128); break;
+        default: LN_EPI(128, 128); break;
+    }
+#undef LN_EPI
 #undef LN_GEMM
     return hipchk(hipGetLastError(), "gemm launch");
 }
@@ -501,32 +512,105 @@ int32_t pcfr_leafnet_get_grads(pcfr_leafnet* n, float* host) {
 namespace pcfr {
 
 // Forward over the rows already staged in the bf16 input buffer; M = padded rows.
+// Forward layer l on the first M rows of the staged activations.
+static int32_t forward_layer(pcfr_leafnet* n, int l, int64_t M, hipStream_t st, int tile) {
+    const LeafNetPlan& P = n->P;
+    const uint16_t* in = reinterpret_cast<const uint16_t*>(n->ws + (l == 0 ? P.off_x : P.off_h[l]));
+    const uint16_t* W = reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l];
+    const float* b = reinterpret_cast<const float*>(n->ws + P.off_p) + P.boff[l];
+    if (l + 1 < P.L)
+        return launch_gemm(st, EPI_BIAS_RELU_BF, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
+                           P.pdims[l], b, n->ws + P.off_h[l + 1], (int)P.pdims[l + 1], nullptr, tile);
+    return launch_gemm(st, EPI_BIAS_F32, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1], P.pdims[l], b,
+                       n->ws + P.off_y, (int)P.pdims[l + 1], nullptr, tile);
+}
+
 int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st, LaunchTimer* tm) {
     const LeafNetPlan& P = n->P;
-    const uint16_t* in = reinterpret_cast<const uint16_t*>(n->ws + P.off_x);
     for (int l = 0; l < P.L; l++) {
-        const uint16_t* W = reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l];
-        const float* b = reinterpret_cast<const float*>(n->ws + P.off_p) + P.boff[l];
-        int32_t rc;
         if (tm) tm->before(l + 1 < P.L ? 5 : 6);
-        if (l + 1 < P.L) {
-            uint16_t* h = reinterpret_cast<uint16_t*>(n->ws + P.off_h[l + 1]);
-            rc = launch_gemm(st, EPI_BIAS_RELU_BF, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
-                             P.pdims[l], b, h, (int)P.pdims[l + 1], nullptr);
-            in = h;
-        } else {
-            rc = launch_gemm(st, EPI_BIAS_F32, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
-                             P.pdims[l], b, n->ws + P.off_y, (int)P.pdims[l + 1], nullptr);
-        }
+        const int32_t rc = forward_layer(n, l, M, st, l < (int)n->fwd_tile.size() ? n->fwd_tile[l] : -1);
         if (tm) tm->after();
         if (rc) return rc;
     }
     return PCFR_OK;
 }
 
+// Average ms of `reps` back-to-back runs of fn() on the net's stream.
+template <typename F>
+static int32_t time_ms(hipStream_t st, int reps, double* ms, F fn) {
+    hipEvent_t a = nullptr, b = nullptr;
+    LN_CHK(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) { (void)hipEventDestroy(a); return hipchk(e, "hipEventCreate"); }
+    int32_t rc = fn();                      // untimed first run
+    if (rc == PCFR_OK) e = hipEventRecord(a, st);
+    for (int r = 0; r < reps && rc == PCFR_OK && e == hipSuccess; r++) rc = fn();
+    if (rc == PCFR_OK && e == hipSuccess) e = hipEventRecord(b, st);
+    if (rc == PCFR_OK && e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0;
+    if (rc == PCFR_OK && e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    LN_CHK(e);
+    *ms = (double)t / std::max(reps, 1);
+    return PCFR_OK;
+}
+
+// Tile autotuner of the forward GEMMs for M rows: each layer is timed with
+// every tile that divides its output width and keeps the fastest.  Tiles
+// differ in how many partial-sum chains an output's K range is split into, so
+// outputs may change in the last bits with the choice (fixed once made).
+int32_t leafnet_autotune(pcfr_leafnet* n, int64_t M, int reps, double* ms_before, double* ms_after) {
+    const LeafNetPlan& P = n->P;
+    if (M <= 0 || M > P.Mp || M % 64) { set_error("autotune rows must be a multiple of 64 within max_batch"); return PCFR_E_INVALID_ARG; }
+    hipStream_t st = n->stream;
+    int32_t rc = time_ms(st, reps, ms_before, [&] { return leafnet_forward_staged(n, M, st); });
+    if (rc) return rc;
+    std::vector<int> pick(P.L, -1);
+    for (int l = 0; l < P.L; l++) {
+        double best = 1e30;
+        for (int tile = 0; tile < kGemmTiles; tile++) {
+            if (!gemm_tile_valid(tile, P.pdims[l + 1])) continue;
+            double ms = 0;
+            if ((rc = time_ms(st, reps, &ms, [&] { return forward_layer(n, l, M, st, tile); }))) return rc;
+            if (ms < best) { best = ms; pick[l] = tile; }
+        }
+    }
+    n->fwd_tile = pick;
+    return time_ms(st, reps, ms_after, [&] { return leafnet_forward_staged(n, M, st); });
+}
+
 }  // namespace pcfr
 
 extern "C" {
+
+int32_t pcfr_leafnet_set_tiles(pcfr_leafnet* n, const int32_t* tiles, int32_t count) {
+    if (!n || !tiles) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    const LeafNetPlan& P = n->P;
+    if (count != P.L) { set_error("one tile per layer is needed"); return PCFR_E_INVALID_ARG; }
+    for (int l = 0; l < P.L; l++)
+        if (tiles[l] != -1 && !gemm_tile_valid(tiles[l], P.pdims[l + 1])) {
+            set_error("tile does not divide the layer's output width");
+            return PCFR_E_INVALID_ARG;
+        }
+    n->fwd_tile.assign(tiles, tiles + count);
+    return PCFR_OK;
+}
+
+int32_t pcfr_leafnet_get_tiles(pcfr_leafnet* n, int32_t* tiles, int32_t count) {
+    if (!n || !tiles) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (count != n->P.L) { set_error("one tile per layer is needed"); return PCFR_E_INVALID_ARG; }
+    for (int l = 0; l < count; l++) tiles[l] = l < (int)n->fwd_tile.size() ? n->fwd_tile[l] : -1;
+    return PCFR_OK;
+}
+
+int32_t pcfr_leafnet_autotune(pcfr_leafnet* n, int32_t m, int32_t reps, double* ms_before, double* ms_after) {
+    if (!n || m <= 0 || reps < 1 || !ms_before || !ms_after) { set_error("null argument, empty batch or reps < 1"); return PCFR_E_INVALID_ARG; }
+    if (m > n->P.Mp) { set_error("batch larger than max_batch"); return PCFR_E_INVALID_ARG; }
+    return leafnet_autotune(n, r64(m), reps, ms_before, ms_after);
+}
 
 int32_t pcfr_leafnet_forward(pcfr_leafnet* n, const float* x, int32_t m, float* y) {
     if (!n || !x || !y || m <= 0) { set_error("null argument or empty batch"); return PCFR_E_INVALID_ARG; }

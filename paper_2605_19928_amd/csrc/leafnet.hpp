@@ -23,8 +23,13 @@ struct LeafNetPlan {
     void make(int d_in, int width, int depth, int d_out, int max_batch);
 };
 
+// GEMM workgroup tiles (rows x columns of C); 4 waves, each a quarter tile.
+enum { GEMM_64x64 = 0, GEMM_128x64 = 1, GEMM_64x128 = 2, GEMM_128x128 = 3, kGemmTiles = 4 };
+bool gemm_tile_valid(int tile, int64_t N);
+
+// C = A B^T with an epilogue; tile < 0 picks a default for the shape.
 int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M,
-                    int64_t N, int64_t K, const float* bias, void* C, int ldc, const uint16_t* mask);
+                    int64_t N, int64_t K, const float* bias, void* C, int ldc, const uint16_t* mask, int tile = -1);
 
 }  // namespace pcfr
 
@@ -33,6 +38,7 @@ struct pcfr_leafnet {
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     int64_t adam_t = 0;
+    std::vector<int> fwd_tile;            // per forward layer GEMM tile, -1 = default
 };
 
 namespace pcfr {
@@ -42,14 +48,15 @@ namespace pcfr {
 // 4 leaves, 5 hidden-layer GEMMs, 6 output-layer GEMM).
 struct LaunchTimer {
     std::vector<hipEvent_t> ev;
-    std::vector<int> cls;
+    std::vector<int> cls, tag;   // per timed launch: cost class, and a caller tag (-1 if none)
     hipStream_t stream;
-    void before(int c) {
+    void before(int c, int t = -1) {
         hipEvent_t a;
         (void)hipEventCreate(&a);
         (void)hipEventRecord(a, stream);
         ev.push_back(a);
         cls.push_back(c);
+        tag.push_back(t);
     }
     void after() {
         hipEvent_t b;
@@ -60,4 +67,5 @@ struct LaunchTimer {
 };
 
 int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st, LaunchTimer* tm = nullptr);
+int32_t leafnet_autotune(pcfr_leafnet* n, int64_t M, int reps, double* ms_before, double* ms_after);
 }

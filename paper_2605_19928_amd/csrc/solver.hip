@@ -27,8 +27,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstddef>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -42,10 +45,21 @@ enum { MODE_ITER = 0, MODE_BR = 1, MODE_EV = 2 };
 
 struct __align__(16) DNode {
     int32_t type, player, first_child, n_child;
-    int32_t rs, aux, card, sub;   // aux: showdown board table, or chance divisor K
-    int32_t dead, pad0;           // cards dealt since the root, packed c1 | c2 << 8 (0xff = none)
+    int32_t rs, aux, sub, dead;   // aux: showdown board table, or chance divisor K;
+                                  // dead: cards dealt since the root, c1 | c2 << 8 (0xff = none)
+    int32_t slot[2];              // reach slot of each player (see below)
     double pay;                   // fold: folder's contribution; showdown: each contribution
 };
+
+// Reach slots.  A player's reach only changes at that player's own decision
+// nodes, so a node shares the opponent's reach vector with its parent and a
+// chance node's children share both of the parent's.  Slots 2g and 2g+1 hold
+// subgame g's root ranges; the actor's reach after action a of the decision
+// node with rows rs.. lives in slot 2 * n_sub + rs + a.  A slot read below a
+// chance node still carries mass on hands holding a dealt card: every reader
+// that needs those hands at zero (the average-strategy update, fold
+// terminals) masks them with the node's dead cards; the showdown tables
+// never list them.
 
 // Per-iteration Stage-7 coefficients, computed on the device from t:
 //   R <- (R + r) * (R + r > 0 ? dpos : dneg);   S <- (S + wadd * pi * sigma) * wmul
@@ -57,9 +71,11 @@ struct IterState {
     int64_t t;
     int32_t variant, pad;
     double dpos, dneg, wadd, wmul;
+    double alpha, beta, gamma;    // set once at creation
 };
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;       // terminal, leaf and helper kernels
+constexpr int kSweepMaxBlock = 512;
 constexpr int kSdHeader = 64;     // card-list offsets per board table (53 used)
 
 // ------------------------------------------------------------ vector I/O
@@ -82,22 +98,33 @@ __device__ __forceinline__ void st4(double* p, const V4<double>& v) {
     *reinterpret_cast<double2*>(p + 2) = make_double2(v.e[2], v.e[3]);
 }
 
+__device__ __forceinline__ bool has_card(uint32_t hc, int c) {
+    return (int)(hc & 0xffu) == c || (int)(hc >> 8) == c;
+}
+
+// true when a hand's two cards (packed c1 | c2 << 8, 0xffff for padding) avoid both dead cards
+__device__ __forceinline__ bool hand_alive(uint32_t hc, int dead) {
+    const int a = hc & 0xff, b = hc >> 8, d1 = dead & 0xff, d2 = (dead >> 8) & 0xff;
+    return a != 0xff && a != d1 && a != d2 && b != d1 && b != d2;
+}
+
 // ------------------------------------------------------------ iteration state
-__global__ void k_begin_iter(IterState* st, int variant, double alpha, double beta, double gamma) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Advances t and sets the coefficients; run by one thread of the first
+// forward launch of an iteration (every later launch reads them).
+__device__ void begin_iteration(IterState* st) {
     int64_t t = st->t + 1;
     st->t = t;
     double td = (double)t;
-    if (variant == PCFR_DCFR) {
-        double ta = pow(td, alpha), tb = pow(td, beta);
+    if (st->variant == PCFR_DCFR) {
+        double ta = pow(td, st->alpha), tb = pow(td, st->beta);
         st->dpos = ta / (ta + 1.0);
         st->dneg = tb / (tb + 1.0);
         st->wadd = 1.0;
-        st->wmul = pow(td / (td + 1.0), gamma);
+        st->wmul = pow(td / (td + 1.0), st->gamma);
     } else {
         st->dpos = 1.0;
         st->dneg = 0.0;
-        st->wadd = variant == PCFR_CFRPLUS ? td : td * td;
+        st->wadd = st->variant == PCFR_CFRPLUS ? td : td * td;
         st->wmul = 1.0;
     }
 }
@@ -112,14 +139,13 @@ __device__ __forceinline__ T strat(T x, T den, T inv_a) {
     return den > T(0) ? x / den : inv_a;
 }
 
+// Only the actor's reach is written: child a's actor slot gets the actor's
+// reach times the probability of a; the other player's slot is shared.
 template <typename T, int MODE, int A>
-__device__ __forceinline__ void fwd_decision(const DNode& nd, int64_t n, int h, int Hp, const T* __restrict__ R,
+__device__ __forceinline__ void fwd_decision(const DNode& nd, int h, int Hp, int cbase, const T* __restrict__ R,
                                              const T* __restrict__ S, const T* __restrict__ Mp,
                                              T* __restrict__ reach) {
-    const int p = nd.player, o = 1 - p;
-    const T* rn = reach + n * 2 * Hp;
-    const V4<T> rp = ld4(rn + (int64_t)p * Hp + h);
-    const V4<T> ro = ld4(rn + (int64_t)o * Hp + h);
+    const V4<T> rp = ld4(reach + (int64_t)nd.slot[nd.player] * Hp + h);
     const T* src = (MODE == MODE_ITER ? R : S) + (int64_t)nd.rs * Hp + h;
     V4<T> x[A];
 #pragma unroll
@@ -138,55 +164,35 @@ __device__ __forceinline__ void fwd_decision(const DNode& nd, int64_t n, int h, 
 #pragma unroll
         for (int j = 0; j < 4; j++) den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
     const T inv_a = T(1) / T(A);
+    T* dst = reach + (int64_t)(cbase + nd.rs) * Hp + h;
 #pragma unroll
     for (int a = 0; a < A; a++) {
         V4<T> q;
 #pragma unroll
         for (int j = 0; j < 4; j++) q.e[j] = rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a);
-        T* rc = reach + (int64_t)(nd.first_child + a) * 2 * Hp;
-        st4(rc + (int64_t)p * Hp + h, q);
-        st4(rc + (int64_t)o * Hp + h, ro);
+        st4(dst + (int64_t)a * Hp, q);
     }
 }
 
-__device__ __forceinline__ bool has_card(uint32_t hc, int c) {
-    return (int)(hc & 0xffu) == c || (int)(hc >> 8) == c;
-}
-
+// One thread per (decision node, 4 hands) of a level; chance nodes have no
+// forward work (their children share their reach slots).
 template <typename T, int MODE, int MAXA>
-__global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
-                                                    int count, int Hp, const T* __restrict__ R, const T* __restrict__ S,
-                                                    const T* __restrict__ Mp, T* __restrict__ reach,
-                                                    const uint16_t* __restrict__ hcards) {
+__global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restrict__ nodes,
+                                                            const int32_t* __restrict__ list, int count, int Hp,
+                                                            int cbase, const T* __restrict__ R,
+                                                            const T* __restrict__ S, const T* __restrict__ Mp,
+                                                            T* __restrict__ reach, IterState* begin) {
+    if (begin && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin);
     const int groups = Hp >> 2;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
     const int h = (int)(gid - k * groups) * 4;
-    const int64_t n = list[k];
-    const DNode nd = nodes[n];
-    if (nd.type == PCFR_NODE_CHANCE) {
-        const T* rn = reach + n * 2 * Hp;
-        const V4<T> r0 = ld4(rn + h), r1 = ld4(rn + Hp + h);
-        const uint16_t* hc = hcards + (int64_t)nd.sub * Hp + h;
-        uint32_t c4[4] = {hc[0], hc[1], hc[2], hc[3]};
-        for (int c = 0; c < nd.n_child; c++) {
-            const int64_t ch = nd.first_child + c;
-            const int card = nodes[ch].card;
-            V4<T> m0 = r0, m1 = r1;
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (has_card(c4[j], card)) { m0.e[j] = T(0); m1.e[j] = T(0); }
-            T* rc = reach + ch * 2 * Hp;
-            st4(rc + h, m0);
-            st4(rc + Hp + h, m1);
-        }
-        return;
-    }
+    const DNode nd = nodes[list[k]];
     switch (nd.n_child) {
 #define PCFR_FWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) fwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach); \
+        if constexpr (A <= MAXA) fwd_decision<T, MODE, A>(nd, h, Hp, cbase, R, S, Mp, reach); \
         break;
         PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
         PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
@@ -199,7 +205,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(const DNode* __restrict__ no
 template <typename T, int MODE, int A>
 __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
                                              T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
-                                             T* __restrict__ cfv, const IterState* st) {
+                                             T* __restrict__ cfv, const IterState* st,
+                                             const uint16_t* __restrict__ hcards, T* __restrict__ root_dst) {
     const int p = nd.player, o = 1 - p;
     V4<T> x[A];
     T den[4] = {T(0), T(0), T(0), T(0)};
@@ -223,31 +230,43 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
             for (int j = 0; j < 4; j++)
                 den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
     }
+    // children's values, read once
+    V4<T> c[A];
     V4<T> vp = {{T(0), T(0), T(0), T(0)}}, vo = {{T(0), T(0), T(0), T(0)}};
 #pragma unroll
     for (int a = 0; a < A; a++) {
         const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
-        const V4<T> c = ld4(cc + (int64_t)p * Hp + h);
+        c[a] = ld4(cc + (int64_t)p * Hp + h);
         const V4<T> d = ld4(cc + (int64_t)o * Hp + h);
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             vo.e[j] += d.e[j];
-            if (MODE == MODE_BR) vp.e[j] = (a == 0 || c.e[j] > vp.e[j]) ? c.e[j] : vp.e[j];
-            else vp.e[j] += strat<T, MODE>(x[a].e[j], den[j], inv_a) * c.e[j];
+            if (MODE == MODE_BR) vp.e[j] = (a == 0 || c[a].e[j] > vp.e[j]) ? c[a].e[j] : vp.e[j];
+            else vp.e[j] += strat<T, MODE>(x[a].e[j], den[j], inv_a) * c[a].e[j];
         }
     }
     T* me = cfv + n * 2 * Hp;
     st4(me + (int64_t)p * Hp + h, vp);
     st4(me + (int64_t)o * Hp + h, vo);
+    if (root_dst) {
+        T* rd = root_dst + (int64_t)nd.sub * 2 * Hp;
+        st4(rd + (int64_t)p * Hp + h, vp);
+        st4(rd + (int64_t)o * Hp + h, vo);
+    }
     if (MODE == MODE_ITER) {
         // Stage 7: regret update, and the reach-weighted strategy added to the
         // average-strategy sum (Stage 1's accumulation, done here so that one
         // pass reads and writes both tables), each with its DCFR discount.
         const T dpos = (T)st->dpos, dneg = (T)st->dneg, wadd = (T)st->wadd, wmul = (T)st->wmul;
-        const V4<T> rp = ld4(reach + n * 2 * Hp + (int64_t)p * Hp + h);
+        V4<T> rp = ld4(reach + (int64_t)nd.slot[p] * Hp + h);
+        if (nd.dead != 0xffff) {
+            const uint16_t* hc = hcards + (int64_t)nd.sub * Hp + h;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (!hand_alive(hc[j], nd.dead)) rp.e[j] = T(0);
+        }
 #pragma unroll
         for (int a = 0; a < A; a++) {
-            const V4<T> c = ld4(cfv + (int64_t)(nd.first_child + a) * 2 * Hp + (int64_t)p * Hp + h);
             T* sp = S + (int64_t)(nd.rs + a) * Hp + h;
             T* rptr = R + (int64_t)(nd.rs + a) * Hp + h;
             V4<T> sv = ld4(sp);
@@ -255,7 +274,7 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
             V4<T> y, inst;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                inst.e[j] = c.e[j] - vp.e[j];
+                inst.e[j] = c[a].e[j] - vp.e[j];
                 T r = r0.e[j] + inst.e[j];
                 y.e[j] = r * (r > T(0) ? dpos : dneg);
                 sv.e[j] = (sv.e[j] + wadd * (rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a))) * wmul;
@@ -267,25 +286,46 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
     }
 }
 
+// One thread per (node, 4 hands) of a level, decision and chance nodes.
+// root_dst (the last launch of an iteration only) also receives each root's
+// values, which later evaluation sweeps do not overwrite.
 template <typename T, int MODE, int MAXA>
-__global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
-                                                     int count, int Hp, T* __restrict__ R, T* __restrict__ S,
-                                                     T* __restrict__ Mp, const T* __restrict__ reach,
-                                                     T* __restrict__ cfv, const IterState* __restrict__ st) {
+__global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __restrict__ nodes,
+                                                             const int32_t* __restrict__ list, int count, int Hp,
+                                                             T* __restrict__ R, T* __restrict__ S, T* __restrict__ Mp,
+                                                             const T* __restrict__ reach, T* __restrict__ cfv,
+                                                             const IterState* __restrict__ st,
+                                                             const uint16_t* __restrict__ hcards,
+                                                             T* __restrict__ root_dst) {
     const int groups = Hp >> 2;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
     const int h = (int)(gid - k * groups) * 4;
     const int64_t n = list[k];
     const DNode nd = nodes[n];
     if (nd.type == PCFR_NODE_CHANCE) {
+        // children in groups of 8: all loads of a group are issued before the
+        // adds, which keep the children's order
+        constexpr int G = 8;
         V4<T> a0 = {{T(0), T(0), T(0), T(0)}}, a1 = a0;
-        for (int c = 0; c < nd.n_child; c++) {
-            const T* cc = cfv + (int64_t)(nd.first_child + c) * 2 * Hp;
-            const V4<T> u = ld4(cc + h), w = ld4(cc + Hp + h);
+        for (int c0 = 0; c0 < nd.n_child; c0 += G) {
+            V4<T> u[G], w[G];
 #pragma unroll
-            for (int j = 0; j < 4; j++) { a0.e[j] += u.e[j]; a1.e[j] += w.e[j]; }
+            for (int q = 0; q < G; q++) {
+                if (c0 + q < nd.n_child) {
+                    const T* cc = cfv + (int64_t)(nd.first_child + c0 + q) * 2 * Hp;
+                    u[q] = ld4(cc + h);
+                    w[q] = ld4(cc + Hp + h);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < G; q++) {
+                if (c0 + q < nd.n_child) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) { a0.e[j] += u[q].e[j]; a1.e[j] += w[q].e[j]; }
+                }
+            }
         }
         const T inv_k = T(1) / T(nd.aux);
 #pragma unroll
@@ -298,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(const DNode* __restrict__ n
     switch (nd.n_child) {
 #define PCFR_BWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach, cfv, st); \
+        if constexpr (A <= MAXA) bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst); \
         break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
@@ -316,18 +356,21 @@ template <typename T>
 __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                           const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
                           const int16_t* __restrict__ chands, T* lds) {
+    // hands holding a card dealt below the root are staged as zero reach
     T* x0 = lds;                  // [Hp]
     T* x1 = x0 + Hp;              // [Hp]
     T* pc = x1 + Hp;              // [2][52]
     T* red = pc + 208;            // [2][kBlock]  (pc holds two half-sums per card first)
     int16_t* lst = reinterpret_cast<int16_t*>(red + 2 * kBlock);   // [2 * Hp]
-    const T* r0 = reach + n * 2 * Hp;
-    const T* r1 = r0 + Hp;
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
     const int nl = coff[52];
+    const bool masked = nd.dead != 0xffff;
     T s0 = T(0), s1 = T(0);
     for (int h = tid; h < Hp; h += kBlock) {
-        const T a = r0[h], b = r1[h];
+        T a = r0[h], b = r1[h];
+        if (masked && !hand_alive(hc[h], nd.dead)) { a = T(0); b = T(0); }
         x0[h] = a;
         x1[h] = b;
         s0 += a;
@@ -359,15 +402,13 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
     const T tot0 = red[0], tot1 = red[kBlock];
     const int f = nd.player;
     const T pay = (T)nd.pay;
-    const int d1 = nd.dead & 0xff, d2 = (nd.dead >> 8) & 0xff;
     T* v0 = cfv + n * 2 * Hp;
     T* v1 = v0 + Hp;
     for (int h = tid; h < Hp; h += kBlock) {
         const uint32_t c = hc[h];
         const int a = c & 0xff, b = c >> 8;
-        const bool alive = a != 0xff && a != d1 && a != d2 && b != d1 && b != d2;
         T m0 = T(0), m1 = T(0);
-        if (alive) {
+        if (hand_alive(c, nd.dead)) {
             m0 = tot0 - pc[a] - pc[b] + x0[h];
             m1 = tot1 - pc[52 + a] - pc[52 + b] + x1[h];
         }
@@ -402,8 +443,8 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     const int16_t* gclist = gcoff + kSdHeader;
     int16_t* coff = reinterpret_cast<int16_t*>(part + 2 * kBlock);    // [kSdHeader], LDS copy
     int16_t* clist = coff + kSdHeader;                                // [QN]: lists + total slots, LDS copy
-    const T* r0 = reach + n * 2 * Hp;
-    const T* r1 = r0 + Hp;
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
 
     for (int s = tid; s < Hb; s += kBlock) {
@@ -517,7 +558,8 @@ constexpr int kEqSplit = 32;
 constexpr int kMaxHp = 1216;    // flop: 1176 compatible combos padded to 64
 
 template <typename T, int J>
-__global__ __launch_bounds__(kBlock) void k_equity_partial(const int32_t* __restrict__ leaves, int n_leaves, int Hp,
+__global__ __launch_bounds__(kBlock) void k_equity_partial(const DNode* __restrict__ nodes,
+                                                           const int32_t* __restrict__ leaves, int n_leaves, int Hp,
                                                            const T* __restrict__ Et, const T* __restrict__ reach,
                                                            T* __restrict__ part) {
     constexpr int kChunk = (kMaxHp + kEqSplit - 1) / kEqSplit;
@@ -528,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_equity_partial(const int32_t* __rest
     const int o0 = blockIdx.z * chunk, o1 = min(Hp, o0 + chunk);
     for (int i = threadIdx.x; i < nj * 2 * chunk; i += kBlock) {
         const int j = i / (2 * chunk), rest = i - j * 2 * chunk, p = rest / chunk, o = o0 + rest - p * chunk;
-        rr[j][p][o - o0] = o < o1 ? reach[(int64_t)leaves[j0 + j] * 2 * Hp + (int64_t)p * Hp + o] : T(0);
+        rr[j][p][o - o0] = o < o1 ? reach[(int64_t)nodes[leaves[j0 + j]].slot[p] * Hp + o] : T(0);
     }
     __syncthreads();
     const int h = blockIdx.x * kBlock + threadIdx.x;
@@ -582,7 +624,8 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 // over the 1326 combos; then the board after c as 52 one-hot entries; then
 // the stack-to-pot ratio at the leaf; bf16, zero padded to ldx.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_input(const int32_t* __restrict__ leaves, const float* __restrict__ spr,
+__global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__ nodes,
+                                                       const int32_t* __restrict__ leaves, const float* __restrict__ spr,
                                                        int n_next, const int8_t* __restrict__ next_cards, int Hp, int H,
                                                        const T* __restrict__ reach, const uint16_t* __restrict__ hcards,
                                                        const int16_t* __restrict__ combo_hand,
@@ -592,9 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_input(const int32_t* __restrict
     const int q = blockIdx.x;
     const int li = q / n_next, k = q - li * n_next;
     const int c = next_cards[k];
-    const int64_t n = leaves[li];
-    const T* r0 = reach + n * 2 * Hp;
-    const T* r1 = r0 + Hp;
+    const DNode nd = nodes[leaves[li]];
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
     double s0 = 0.0, s1 = 0.0;
     for (int h = tid; h < H; h += kBlock)
@@ -633,7 +676,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_input(const int32_t* __restrict
 // One workgroup per (leaf, tile of 64 hands); its 4 waves take every 4th
 // next card and the partial sums are added in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restrict__ leaves,
+__global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict__ nodes,
+                                                         const int32_t* __restrict__ leaves,
                                                          const double* __restrict__ pot_over_k, int n_next,
                                                          const int8_t* __restrict__ next_cards, int Hp, int H,
                                                          const T* __restrict__ reach, T* __restrict__ cfv,
@@ -650,8 +694,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const int32_t* __restri
     __shared__ T red[2][kBlock];
     const int li = blockIdx.x;
     const int64_t n = leaves[li];
-    const T* r0 = reach + n * 2 * Hp;
-    const T* r1 = r0 + Hp;
+    const DNode nd = nodes[n];
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
     T s0 = T(0), s1 = T(0);
     for (int h = tid; h < Hp; h += kBlock) {
@@ -736,7 +781,7 @@ __global__ __launch_bounds__(kBlock) void k_samples(const int32_t* __restrict__ 
     __shared__ double red[2][kBlock];
     const int g = blockIdx.x, tid = threadIdx.x;
     const int64_t n = roots[g];
-    const T* r0 = reach + n * 2 * Hp;
+    const T* r0 = reach + (int64_t)(2 * g) * Hp;
     const T* r1 = r0 + Hp;
     const T* v0 = cfv + n * 2 * Hp;
     const T* v1 = v0 + Hp;
@@ -803,17 +848,6 @@ __global__ __launch_bounds__(kBlock) void k_samples(const int32_t* __restrict__ 
 }
 
 // ------------------------------------------------------------ small kernels
-// Root values of every subgame -> a slot that later sweeps do not overwrite.
-template <typename T>
-__global__ void k_gather_roots(const T* __restrict__ cfv, const int32_t* __restrict__ roots, int n_sub, int Hp,
-                               T* __restrict__ dst) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = 2 * (int64_t)Hp;
-    if (i >= per * n_sub) return;
-    const int64_t g = i / per;
-    dst[i] = cfv[(int64_t)roots[g] * per + (i - g * per)];
-}
-
 // Strategy of one decision node for every hand: which 0 = average, 1 = current.
 template <typename T>
 __global__ void k_strategy(const T* __restrict__ src, const T* __restrict__ pred, int rs, int A, int Hp, int which,
@@ -846,9 +880,9 @@ static int32_t hip_check(hipError_t e, const char* what) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
-    int64_t N, rows, Hp, H, n_boards, term, fwd, chand_stride, sd_stride, n_eq, n_net, n_next;
+    int64_t N, rows, Hp, H, n_boards, term, fwd, dec, slots, chand_stride, sd_stride, n_eq, n_net, n_next;
     size_t esz;
-    size_t off_nodes, off_fwd, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
+    size_t off_nodes, off_fwd, off_dec, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
     size_t lds_bytes, lds_fold, lds_show;
@@ -859,8 +893,10 @@ struct Prepared {
     int32_t n_sub = 0;
     std::vector<int64_t> node_base, root_node;
     std::vector<DNode> nodes;
-    std::vector<int32_t> fwd, term;
+    std::vector<int32_t> fwd, term;       // fwd: decision and chance nodes by level (backward sweep)
     std::vector<int64_t> fwd_off;         // per level start into fwd (size levels+1)
+    std::vector<int32_t> dec;             // decision nodes only, by level (forward sweep)
+    std::vector<int64_t> dec_off;
     std::vector<int32_t> lvl_maxa;        // per level: most actions of a decision node
     std::vector<int32_t> folds, shows;    // terminal lists by kind
     std::vector<uint16_t> hcards;         // [n_sub][Hp]
@@ -960,7 +996,8 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
             DNode d{};
             d.type = s.type; d.player = s.player; d.n_child = s.n_child;
             d.first_child = s.first_child < 0 ? -1 : (int32_t)(base + s.first_child);
-            d.rs = -1; d.aux = 0; d.card = s.chance_card; d.sub = g; d.pay = 0.0;
+            d.rs = -1; d.aux = 0; d.sub = g; d.pay = 0.0;
+            d.slot[0] = d.slot[1] = -1;
             uint64_t extra = s.board_mask & ~t.root_mask;
             int dd[2] = {0xff, 0xff}, nd = 0;
             for (int c = 0; c < 52 && nd < 2; c++) if (extra >> c & 1ull) dd[nd++] = c;
@@ -987,6 +1024,7 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
             } else if (s.type == PCFR_NODE_ALLIN_LEAF || s.type == PCFR_NODE_LEAF) {
                 if (K > 1) { set_error("depth-limited subgames cannot be batched"); return PCFR_E_UNSUPPORTED; }
                 if (s.contrib[0] != s.contrib[1]) { set_error("leaf with unequal contributions"); return PCFR_E_INVALID_ARG; }
+                if (s.board_mask != t.root_mask) { set_error("depth-limit leaf below a chance node"); return PCFR_E_UNSUPPORTED; }
             } else {
                 set_error("unknown node type");
                 return PCFR_E_INVALID_ARG;
@@ -994,6 +1032,25 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
             P.nodes[gi] = d;
         }
         if (rows > (int64_t)INT32_MAX) { set_error("too many action rows"); return PCFR_E_TOO_LARGE; }
+    }
+    if (2 * (int64_t)K + rows > (int64_t)INT32_MAX) { set_error("too many reach slots"); return PCFR_E_TOO_LARGE; }
+    for (int32_t g = 0; g < K; g++)
+        if (P.nodes[P.node_base[g]].type != PCFR_NODE_DECISION) { set_error("subgame root is not a decision node"); return PCFR_E_UNSUPPORTED; }
+    // reach slots, parents before children (breadth-first ids)
+    for (int32_t g = 0; g < K; g++) {
+        DNode& r = P.nodes[P.node_base[g]];
+        r.slot[0] = 2 * g;
+        r.slot[1] = 2 * g + 1;
+    }
+    for (int64_t i = 0; i < (int64_t)P.nodes.size(); i++) {
+        const DNode& d = P.nodes[i];
+        if (d.type != PCFR_NODE_DECISION && d.type != PCFR_NODE_CHANCE) continue;
+        for (int a = 0; a < d.n_child; a++) {
+            DNode& c = P.nodes[d.first_child + a];
+            c.slot[0] = d.slot[0];
+            c.slot[1] = d.slot[1];
+            if (d.type == PCFR_NODE_DECISION) c.slot[d.player] = (int32_t)(2 * K + d.rs + a);
+        }
     }
     if (N > (int64_t)INT32_MAX) { set_error("too many nodes"); return PCFR_E_TOO_LARGE; }
     if (K == 1) {
@@ -1021,14 +1078,20 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
         else P.next_cards.push_back((int8_t)c);
     }
     P.fwd_off.assign(P.levels + 1, 0);
+    P.dec_off.assign(P.levels + 1, 0);
     P.lvl_maxa.assign(P.levels, 0);
     for (int l = 0; l < P.levels; l++) {
         P.fwd_off[l] = (int64_t)P.fwd.size();
+        P.dec_off[l] = (int64_t)P.dec.size();
         for (auto x : per_level[l]) {
             P.fwd.push_back(x);
-            if (P.nodes[x].type == PCFR_NODE_DECISION) P.lvl_maxa[l] = std::max(P.lvl_maxa[l], P.nodes[x].n_child);
+            if (P.nodes[x].type == PCFR_NODE_DECISION) {
+                P.dec.push_back(x);
+                P.lvl_maxa[l] = std::max(P.lvl_maxa[l], P.nodes[x].n_child);
+            }
         }
     }
+    P.dec_off[P.levels] = (int64_t)P.dec.size();
     for (auto x : P.term) (P.nodes[x].type == PCFR_NODE_FOLD ? P.folds : P.shows).push_back(x);
     P.term.clear();
     P.term.insert(P.term.end(), P.folds.begin(), P.folds.end());
@@ -1110,6 +1173,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.n_boards = (int64_t)P.sdn.size();
     L.term = (int64_t)P.term.size();
     L.fwd = (int64_t)P.fwd.size();
+    L.dec = (int64_t)P.dec.size();
+    L.slots = 2 * (int64_t)P.n_sub + rows;
     L.chand_stride = P.chand_stride;
     L.sd_stride = P.sd_stride;
     L.esz = dtype == PCFR_F64 ? 8 : 4;
@@ -1117,6 +1182,7 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.off_nodes = take(sizeof(DNode) * L.N);
     L.off_fwd = take(sizeof(int32_t) * std::max<int64_t>(L.fwd, 1));
+    L.off_dec = take(sizeof(int32_t) * std::max<int64_t>(L.dec, 1));
     L.off_term = take(sizeof(int32_t) * std::max<int64_t>(L.term, 1));
     L.off_hc = take(sizeof(uint16_t) * L.Hp * P.n_sub);
     L.off_coff = take(sizeof(int32_t) * 53 * P.n_sub);
@@ -1126,7 +1192,7 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_state = take(sizeof(IterState));
     L.off_R = take(L.esz * L.rows * L.Hp);
     L.off_S = take(L.esz * L.rows * L.Hp);
-    L.off_reach = take(L.esz * L.N * 2 * L.Hp);
+    L.off_reach = take(L.esz * L.slots * L.Hp);
     L.off_cfv = take(L.esz * L.N * 2 * L.Hp);
     L.off_root = take(L.esz * 2 * L.Hp * P.n_sub);
     L.off_stage = take(L.esz * kMaxActions * L.Hp);
@@ -1161,11 +1227,21 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
 
 using namespace pcfr;
 
+namespace pcfr {
+// Launch schedule of the level sweeps: workgroup size per level and phase.
+// The arithmetic of each (node, hand) does not depend on it, so any schedule
+// gives bitwise the same iterates.
+struct Sched {
+    std::vector<int> fwd_block, bwd_block;
+};
+}  // namespace pcfr
+
 struct pcfr_solver {
     std::vector<Tree> trees;
     pcfr_solver_cfg cfg;
     Prepared P;
     Plan L;
+    Sched sched;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     std::vector<double> ranges;       // [n_sub][2][1326]
@@ -1187,18 +1263,13 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     const int groups = Hp / 4;
     DNode* nodes = s->at<DNode>(L.off_nodes);
     int32_t* fwd = s->at<int32_t>(L.off_fwd);
+    int32_t* dec = s->at<int32_t>(L.off_dec);
     T* R = s->at<T>(L.off_R);
     T* S = s->at<T>(L.off_S);
     T* reach = s->at<T>(L.off_reach);
     T* cfv = s->at<T>(L.off_cfv);
     T* Mp = s->cfg.variant == PCFR_PCFRPLUS ? s->at<T>(L.off_M) : nullptr;
     IterState* st = s->at<IterState>(L.off_state);
-    if (MODE == MODE_ITER) {
-        if (tm) tm->before(0);
-        hipLaunchKernelGGL(k_begin_iter, dim3(1), dim3(64), 0, stream, st, (int)s->cfg.variant, s->cfg.alpha,
-                           s->cfg.beta, s->cfg.gamma);
-        if (tm) tm->after();
-    }
     // the kernels are instantiated for at most 3, 6 or 12 actions; a level
     // uses the smallest that covers its nodes (fewer registers, more waves)
 #define PCFR_BUCKET(KER, l, ...)                                                                      \
@@ -1208,15 +1279,20 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         else if (ma <= 6) hipLaunchKernelGGL((KER<T, MODE, 6>), __VA_ARGS__);                         \
         else hipLaunchKernelGGL((KER<T, MODE, 12>), __VA_ARGS__);                                     \
     } while (0)
+    // forward: decision nodes only; the first launch of an iteration also
+    // advances t and sets the Stage-7 coefficients
+    bool first = MODE == MODE_ITER;
     for (int l = 0; l < P.levels; l++) {
-        int64_t cnt = P.fwd_off[l + 1] - P.fwd_off[l];
+        const int64_t cnt = P.dec_off[l + 1] - P.dec_off[l];
         if (!cnt) continue;
-        int64_t threads = cnt * groups;
-        dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
-        if (tm) tm->before(1);
-        PCFR_BUCKET(k_forward, l, grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
-                    reach, s->at<uint16_t>(L.off_hc));
+        const int bs = s->sched.fwd_block[l];
+        const int64_t threads = cnt * groups;
+        dim3 grid((unsigned)((threads + bs - 1) / bs));
+        if (tm) tm->before(1, l);
+        PCFR_BUCKET(k_forward, l, grid, dim3(bs), 0, stream, nodes, dec + P.dec_off[l], (int)cnt, Hp,
+                    (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr);
         if (tm) tm->after();
+        first = false;
     }
     // terminals: folds and showdowns in separate launches, each with the LDS it needs
     const int64_t n_fold = (int64_t)P.folds.size(), n_show = (int64_t)P.shows.size();
@@ -1238,7 +1314,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         constexpr int J = sizeof(T) == 8 ? 2 : 4;
         dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)((n_eq_active + J - 1) / J), kEqSplit);
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_equity_partial<T, J>), grid, dim3(kBlock), 0, stream, s->at<int32_t>(L.off_eq),
+        hipLaunchKernelGGL((k_equity_partial<T, J>), grid, dim3(kBlock), 0, stream, nodes, s->at<int32_t>(L.off_eq),
                            (int)n_eq_active, Hp, s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
         const int64_t tot = n_eq_active * 2 * (int64_t)Hp;
         hipLaunchKernelGGL((k_equity_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream,
@@ -1250,7 +1326,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         pcfr_leafnet* net = s->net;
         const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, s->at<int32_t>(L.off_net),
+        hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes, s->at<int32_t>(L.off_net),
                            s->at<float>(L.off_spr), (int)L.n_next, s->at<int8_t>(L.off_next), Hp, (int)L.H, reach,
                            s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_c2h), s->at<uint8_t>(L.off_hot),
                            reinterpret_cast<uint16_t*>(net->ws + net->P.off_x), (int)net->P.pdims[0]);
@@ -1259,7 +1335,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (rc) return rc;
         if (tm) tm->before(4);
         hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)((Hp + 63) / 64)),
-                           dim3(kBlock), 0, stream,
+                           dim3(kBlock), 0, stream, nodes,
                            s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), (int)L.n_next,
                            s->at<int8_t>(L.off_next), Hp, (int)L.H, reach, cfv, s->at<uint16_t>(L.off_hc),
                            s->at<int16_t>(L.off_h2c), s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff),
@@ -1267,24 +1343,21 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            (int)net->P.pdims[net->P.L]);
         if (tm) tm->after();
     }
+    // backward; level 0 holds exactly the roots, whose values of this
+    // iteration are also kept apart from later evaluation sweeps
     for (int l = P.levels - 1; l >= 0; l--) {
-        int64_t cnt = P.fwd_off[l + 1] - P.fwd_off[l];
+        const int64_t cnt = P.fwd_off[l + 1] - P.fwd_off[l];
         if (!cnt) continue;
-        int64_t threads = cnt * groups;
-        dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
-        if (tm) tm->before(3);
-        PCFR_BUCKET(k_backward, l, grid, dim3(kBlock), 0, stream, nodes, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
-                    reach, cfv, st);
+        const int bs = s->sched.bwd_block[l];
+        const int64_t threads = cnt * groups;
+        dim3 grid((unsigned)((threads + bs - 1) / bs));
+        if (tm) tm->before(3, 1000 + l);
+        PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, nodes, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
+                    reach, cfv, st, s->at<uint16_t>(L.off_hc),
+                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr);
         if (tm) tm->after();
     }
 #undef PCFR_BUCKET
-    if (MODE == MODE_ITER) {
-        int64_t n = 2 * L.Hp * P.n_sub;
-        if (tm) tm->before(0);
-        hipLaunchKernelGGL((k_gather_roots<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, cfv,
-                           s->at<int32_t>(L.off_roots), P.n_sub, Hp, s->at<T>(L.off_root));
-        if (tm) tm->after();
-    }
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
@@ -1336,6 +1409,39 @@ static int32_t fetch_hands(pcfr_solver* s, const void* dev, int rows, double* ou
 }  // namespace pcfr
 
 namespace pcfr {
+
+// ------------------------------------------------------------ schedules
+// Tuned workgroup sizes are cached per size bucket: (phase, dtype, action
+// bucket, floor(log2(threads of the launch))).  A new solver takes the cached
+// size of each of its launches' buckets, 256 where none was tuned.
+static std::mutex g_sched_mu;
+static std::map<std::tuple<int, int, int, int>, int> g_sched_cache;
+
+static int log2_bucket(int64_t x) {
+    int b = 0;
+    while (b < 62 && (int64_t(1) << (b + 1)) <= x) b++;
+    return b;
+}
+static int action_bucket(int ma) { return ma <= 3 ? 3 : ma <= 6 ? 6 : 12; }
+
+static std::tuple<int, int, int, int> sched_key(const pcfr_solver* s, int phase, int l) {
+    const Prepared& P = s->P;
+    const int64_t cnt = phase == 0 ? P.dec_off[l + 1] - P.dec_off[l] : P.fwd_off[l + 1] - P.fwd_off[l];
+    return std::make_tuple(phase, (int)s->L.esz, action_bucket(P.lvl_maxa[l]), log2_bucket(cnt * (s->L.Hp / 4)));
+}
+
+static void init_sched(pcfr_solver* s) {
+    const int levels = s->P.levels;
+    s->sched.fwd_block.assign(levels, 256);
+    s->sched.bwd_block.assign(levels, 256);
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    for (int l = 0; l < levels; l++) {
+        auto f = g_sched_cache.find(sched_key(s, 0, l));
+        if (f != g_sched_cache.end()) s->sched.fwd_block[l] = f->second;
+        auto b = g_sched_cache.find(sched_key(s, 1, l));
+        if (b != g_sched_cache.end()) s->sched.bwd_block[l] = b->second;
+    }
+}
 
 static int32_t check_cfg(const pcfr_solver_cfg* cfg) {
     if (cfg->dtype != PCFR_F32 && cfg->dtype != PCFR_F64) { set_error("dtype must be PCFR_F32 or PCFR_F64"); return PCFR_E_INVALID_ARG; }
@@ -1443,6 +1549,7 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     };
     if ((rc = up(L.off_nodes, P.nodes.data(), sizeof(DNode) * P.nodes.size()))) return rc;
     if ((rc = up(L.off_fwd, P.fwd.data(), sizeof(int32_t) * P.fwd.size()))) return rc;
+    if ((rc = up(L.off_dec, P.dec.data(), sizeof(int32_t) * P.dec.size()))) return rc;
     if ((rc = up(L.off_term, P.term.data(), sizeof(int32_t) * P.term.size()))) return rc;
     if ((rc = up(L.off_hc, P.hcards.data(), sizeof(uint16_t) * P.hcards.size()))) return rc;
     if ((rc = up(L.off_coff, P.coff.data(), sizeof(int32_t) * P.coff.size()))) return rc;
@@ -1504,29 +1611,36 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
             HIPCHK(hipStreamSynchronize(s->stream));
         }
     }
-    HIPCHK(hipMemsetAsync(s->ws + L.off_state, 0, sizeof(IterState), s->stream));
+    {
+        IterState st{};
+        st.variant = cfg->variant;
+        st.alpha = cfg->alpha;
+        st.beta = cfg->beta;
+        st.gamma = cfg->gamma;
+        if ((rc = up(L.off_state, &st, sizeof(st)))) return rc;
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
     HIPCHK(hipMemsetAsync(s->ws + L.off_R, 0, L.esz * L.rows * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_S, 0, L.esz * L.rows * L.Hp, s->stream));
     if (cfg->variant == PCFR_PCFRPLUS) HIPCHK(hipMemsetAsync(s->ws + L.off_M, 0, L.esz * L.rows * L.Hp, s->stream));
-    HIPCHK(hipMemsetAsync(s->ws + L.off_reach, 0, L.esz * L.N * 2 * L.Hp, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_reach, 0, L.esz * L.slots * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_cfv, 0, L.esz * L.N * 2 * L.Hp, s->stream));
     HIPCHK(hipMemsetAsync(s->ws + L.off_root, 0, L.esz * 2 * L.Hp * n, s->stream));
-    // root reach = ranges in hand order (the roots' reach slots are never written again)
+    // root reach = ranges in hand order, slots 2g and 2g + 1 (never written again)
     {
-        std::vector<char> rr(L.esz * 2 * L.Hp, 0);
-        for (int32_t g = 0; g < n; g++) {
-            std::fill(rr.begin(), rr.end(), 0);
+        std::vector<char> rr(L.esz * 2 * L.Hp * n, 0);
+        for (int32_t g = 0; g < n; g++)
             for (int p = 0; p < 2; p++)
                 for (int64_t h = 0; h < P.Hs[g]; h++) {
                     double v = s->ranges[((size_t)g * 2 + p) * kCombos + P.hand_combo[g][h]];
-                    size_t i = (size_t)p * L.Hp + h;
+                    size_t i = ((size_t)g * 2 + p) * L.Hp + h;
                     if (L.esz == 8) reinterpret_cast<double*>(rr.data())[i] = v;
                     else reinterpret_cast<float*>(rr.data())[i] = (float)v;
                 }
-            if ((rc = up(L.off_reach + L.esz * (size_t)P.root_node[g] * 2 * L.Hp, rr.data(), rr.size()))) return rc;
-            HIPCHK(hipStreamSynchronize(s->stream));
-        }
+        if ((rc = up(L.off_reach, rr.data(), rr.size()))) return rc;
+        HIPCHK(hipStreamSynchronize(s->stream));
     }
+    init_sched(s);
     if ((rc = build_graph(s))) return rc;
     *out = guard.release();
     return PCFR_OK;
@@ -1601,9 +1715,115 @@ static int32_t exploitability_impl(pcfr_solver* s, double* chips, double* br) {
     return PCFR_OK;
 }
 
+// Zero the iterate (t, R, S, m, stored root values): the state of a new solver.
+static int32_t reset_state(pcfr_solver* s) {
+    const Plan& L = s->L;
+    const int64_t t0 = 0;
+    HIPCHK(hipMemcpyAsync(s->ws + L.off_state + offsetof(IterState, t), &t0, sizeof(t0), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_R, 0, L.esz * L.rows * L.Hp, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_S, 0, L.esz * L.rows * L.Hp, s->stream));
+    if (s->cfg.variant == PCFR_PCFRPLUS) HIPCHK(hipMemsetAsync(s->ws + L.off_M, 0, L.esz * L.rows * L.Hp, s->stream));
+    HIPCHK(hipMemsetAsync(s->ws + L.off_root, 0, L.esz * 2 * L.Hp * s->P.n_sub, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->t_host = 0;
+    return PCFR_OK;
+}
+
+// Average ms per iteration of n graph replays (after one untimed replay).
+static int32_t time_replays(pcfr_solver* s, int32_t n, double* ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipGraphLaunch(s->graph, s->stream));
+    HIPCHK(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) { (void)hipEventDestroy(a); return hip_check(e, "hipEventCreate"); }
+    e = hipEventRecord(a, s->stream);
+    for (int32_t i = 0; i < n && e == hipSuccess; i++) e = hipGraphLaunch(s->graph, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    HIPCHK(e);
+    *ms = (double)t / std::max(n, 1);
+    return PCFR_OK;
+}
+
+// Autotuner of the level sweeps: every level's forward and backward launch is
+// timed at each candidate workgroup size over `reps` iterations (per-launch
+// events), the fastest size per launch is kept and cached for its size
+// bucket, the graph is captured again, and the state is reset to t = 0.
+static int32_t autotune_impl(pcfr_solver* s, int32_t reps, double* ms_before, double* ms_after) {
+    if (!s || reps < 1 || !ms_before || !ms_after) { set_error("null argument or reps < 1"); return PCFR_E_INVALID_ARG; }
+    int64_t t = 0;
+    {
+        IterState st;
+        HIPCHK(hipMemcpyAsync(&st, s->ws + s->L.off_state, sizeof(st), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        t = st.t;
+    }
+    if (t != 0 || s->t_host != 0) { set_error("autotune needs a solver that has not iterated yet"); return PCFR_E_STATE; }
+    int32_t rc = time_replays(s, reps, ms_before);
+    if (rc) return rc;
+    const int levels = s->P.levels;
+    const int cand[4] = {64, 128, 256, 512};
+    std::vector<double> best_f(levels, 1e30), best_b(levels, 1e30);
+    std::vector<int> pick_f(levels, 256), pick_b(levels, 256);
+    for (int c : cand) {
+        s->sched.fwd_block.assign(levels, c);
+        s->sched.bwd_block.assign(levels, c);
+        std::vector<double> tf(levels, 0.0), tb(levels, 0.0);
+        for (int32_t r = 0; r <= reps; r++) {
+            LaunchTimer tm;
+            tm.stream = s->stream;
+            rc = s->cfg.dtype == PCFR_F64 ? enqueue_sweep<double, MODE_ITER>(s, s->stream, &tm)
+                                          : enqueue_sweep<float, MODE_ITER>(s, s->stream, &tm);
+            hipError_t e = hipStreamSynchronize(s->stream);
+            for (size_t k = 0; k < tm.tag.size(); k++) {
+                float ms = 0;
+                if (r > 0 && rc == PCFR_OK && e == hipSuccess && tm.tag[k] >= 0) {
+                    (void)hipEventElapsedTime(&ms, tm.ev[2 * k], tm.ev[2 * k + 1]);
+                    if (tm.tag[k] >= 1000) tb[tm.tag[k] - 1000] += ms;
+                    else tf[tm.tag[k]] += ms;
+                }
+            }
+            for (auto ev : tm.ev) (void)hipEventDestroy(ev);
+            if (rc) return rc;
+            HIPCHK(e);
+        }
+        for (int l = 0; l < levels; l++) {
+            if (tf[l] < best_f[l]) { best_f[l] = tf[l]; pick_f[l] = c; }
+            if (tb[l] < best_b[l]) { best_b[l] = tb[l]; pick_b[l] = c; }
+        }
+    }
+    s->sched.fwd_block = pick_f;
+    s->sched.bwd_block = pick_b;
+    if (s->net && s->L.n_net) {
+        double nb = 0, na = 0;
+        const int64_t rows = (s->L.n_net * s->L.n_next + 63) / 64 * 64;
+        if ((rc = leafnet_autotune(s->net, rows, reps, &nb, &na))) return rc;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        for (int l = 0; l < levels; l++) {
+            if (s->P.dec_off[l + 1] > s->P.dec_off[l]) g_sched_cache[sched_key(s, 0, l)] = pick_f[l];
+            if (s->P.fwd_off[l + 1] > s->P.fwd_off[l]) g_sched_cache[sched_key(s, 1, l)] = pick_b[l];
+        }
+    }
+    if (s->graph) { (void)hipGraphExecDestroy(s->graph); s->graph = nullptr; }
+    if (s->graph_def) { (void)hipGraphDestroy(s->graph_def); s->graph_def = nullptr; }
+    if ((rc = build_graph(s))) return rc;
+    if ((rc = time_replays(s, reps, ms_after))) return rc;
+    return reset_state(s);
+}
+
 }  // namespace pcfr
 
 extern "C" {
+
+int32_t pcfr_autotune(pcfr_solver* s, int32_t reps, double* ms_before, double* ms_after) {
+    return autotune_impl(s, reps, ms_before, ms_after);
+}
 
 int32_t pcfr_solver_workspace_bytes(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, size_t* bytes) {
     const pcfr_tree* t[1] = {tree};
@@ -1778,9 +1998,8 @@ int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes) {
         return PCFR_E_INVALID_ARG;
     }
     size_t rb = L.esz * L.rows * L.Hp;
-    IterState st{};
-    st.t = hdr[0];
-    HIPCHK(hipMemcpyAsync(s->ws + L.off_state, &st, sizeof(st), hipMemcpyHostToDevice, s->stream));
+    const int64_t t = hdr[0];
+    HIPCHK(hipMemcpyAsync(s->ws + L.off_state + offsetof(IterState, t), &t, sizeof(t), hipMemcpyHostToDevice, s->stream));
     if (s->cfg.variant == PCFR_PCFRPLUS)
         HIPCHK(hipMemcpyAsync(s->ws + L.off_M, b + 16 + 2 * rb, rb, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->ws + L.off_R, b + 16, rb, hipMemcpyHostToDevice, s->stream));

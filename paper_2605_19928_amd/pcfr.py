@@ -81,6 +81,11 @@ _SIGS = {
     "pcfr_cfr_iterate": (C.c_int32, [C.c_void_p, C.c_int32]),
     "pcfr_synchronize": (C.c_int32, [C.c_void_p]),
     "pcfr_profile_iterations": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "pcfr_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pcfr_leafnet_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]),
+    "pcfr_leafnet_set_tiles": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "pcfr_leafnet_get_tiles": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "pcfr_iteration": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_get_strategy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "pcfr_get_root_cfv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
@@ -239,6 +244,13 @@ class Solver:
         cnt = np.zeros(8, dtype=np.int64)
         _check(lib().pcfr_profile_iterations(self._h, int(n), _p(ms), _p(cnt)))
         return ms, cnt
+
+    def autotune(self, reps: int = 5):
+        """Pick each level sweep's workgroup size by timing (fresh solvers only);
+        returns ms per iteration (before, after).  The state is left at t = 0."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib().pcfr_autotune(self._h, int(reps), C.byref(a), C.byref(b)))
+        return float(a.value), float(b.value)
 
     def synchronize(self):
         _check(lib().pcfr_synchronize(self._h))
@@ -420,6 +432,24 @@ class LeafNet:
         _check(lib().pcfr_leafnet_forward(self._h, C.c_void_p(x.data_ptr()), int(x.shape[0]),
                                           C.c_void_p(y.data_ptr())))
         return y
+
+    def autotune(self, m: int, reps: int = 10):
+        """Pick each forward layer's GEMM tile for m-row batches; returns ms per forward (before, after)."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib().pcfr_leafnet_autotune(self._h, int(m), int(reps), C.byref(a), C.byref(b)))
+        return float(a.value), float(b.value)
+
+    @property
+    def tiles(self):
+        """Forward GEMM tile per layer (-1 default, 0 64x64, 1 128x64, 2 64x128, 3 128x128)."""
+        t = np.zeros(len(self.layer_shapes()), dtype=np.int32)
+        _check(lib().pcfr_leafnet_get_tiles(self._h, _p(t), len(t)))
+        return [int(v) for v in t]
+
+    @tiles.setter
+    def tiles(self, tiles):
+        t = np.ascontiguousarray(tiles, dtype=np.int32)
+        _check(lib().pcfr_leafnet_set_tiles(self._h, _p(t), len(t)))
 
     def train_step(self, x, target, mask, lr: float, want_loss: bool = True):
         loss = C.c_float()

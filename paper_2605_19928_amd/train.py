@@ -128,3 +128,50 @@ def value_error_mbb(pred, Y, M, X, pots):
             err += float((r[i] * d * pots[g] * comp[1 - i]).sum())
         out.append(err / (2 * z) * 100.0)
     return float(np.mean(out)), out
+
+
+def _elapsed_ms(fn, stream):
+    import torch
+
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def forward_ms(net: "P.LeafNet", X, reps: int = 20):
+    """Device time of one network evaluation of the rows of X (ms)."""
+    import torch
+
+    net.forward(X)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(X.device)
+    return _elapsed_ms(lambda: [net.forward(X) for _ in range(reps)], stream) / reps
+
+
+def plain_solver_curve(cases, Yh, Mh, Xh, ks, dtype: str = "f32", device="cuda"):
+    """The method without the network: the same held-out subgames solved by
+    the plain batched solver for k iterations, for each k of the ascending
+    ks; returns [(k, value error in mbb/hand of the average-strategy values
+    against the targets)] and the device ms per batched iteration."""
+    import torch
+
+    trees = [P.Tree(**s) for s, _ in cases]
+    b = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=dtype), device=device)
+    X = torch.zeros_like(Xh)
+    Y = torch.zeros_like(Yh)
+    Mk = torch.zeros_like(Mh)
+    pots = [s["pot"] for s, _ in cases]
+    yh, mh, xh = Yh.cpu().numpy(), Mh.cpu().numpy(), Xh.cpu().numpy()
+    out, done, total = [], 0, 0.0
+    for k in ks:
+        total += _elapsed_ms(lambda: b.iterate(k - done), b.stream)
+        done = k
+        b.leaf_samples(X, Y, Mk)
+        err, _ = value_error_mbb(Y.cpu().numpy(), yh, mh, xh, pots)
+        out.append((int(k), float(err)))
+    b.close()
+    return out, total / max(done, 1)

@@ -62,3 +62,26 @@ def test_batch_member_matches_oracle():
         eo, _ = os_.exploitability()
         say(f"  root cfv max |d| = {d:.3e} pot; exploitability batch {e_all[g]:.9f} oracle {eo:.9f}")
         assert d <= 1e-9 and abs(e_all[g] - eo) / spec["pot"] <= 1e-9
+
+
+def test_autotune_keeps_iterates_bitwise():
+    """The autotuner only changes workgroup sizes: a tuned batch must iterate
+    bitwise like one created before tuning, and tuning leaves t = 0."""
+    cases = I.batch_config(5, count_nodes, n=12, river_share=0.7, lo=10, hi=1500)
+    trees = [P.Tree(**s) for s, _ in cases]
+    ranges = np.stack([r for _, r in cases])
+    ref = P.Batch(trees, ranges)           # schedule fixed at creation, before any tuning below
+    tuned = P.Batch(trees, ranges)
+    before, after = tuned.autotune(2)
+    say(f"case: autotune 12 subgames, {before:.4f} -> {after:.4f} ms/iter")
+    assert before > 0 and after > 0 and tuned.t == 0
+    T = 20
+    ref.iterate(T)
+    tuned.iterate(T)
+    for g in range(len(cases)):
+        np.testing.assert_array_equal(tuned.root_cfv_of(g, "current"), ref.root_cfv_of(g, "current"))
+        e = trees[g].export()
+        for n in np.flatnonzero(e["type"] == P.NODE_DECISION)[:4]:
+            np.testing.assert_array_equal(tuned.strategy_of(g, int(n)), ref.strategy_of(g, int(n)))
+    with pytest.raises(P.PcfrError):
+        tuned.autotune(1)                  # only a solver that has not iterated can be tuned

@@ -59,6 +59,39 @@ def test_forward_matches_fp64_reference(d_in, width, depth, d_out, m):
     close(y, ref, "forward")
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_forward_each_gemm_tile_matches_fp64_reference(tile):
+    """Every forward GEMM tile, on a row count (1029 -> 1088) that leaves the
+    last 128-row tile half empty, against the bf16-emulating FP64 reference."""
+    import torch
+    say(f"case: forward with GEMM tile {tile} on every layer, m=1029")
+    rng = np.random.default_rng(77)
+    net = P.LeafNet(P.LEAF_D_IN, 1536, 2, P.LEAF_D_OUT, max_batch=1029)
+    params = rand_params(rng, net.layer_shapes(), scale=1.5)
+    net.set_params(params)
+    net.tiles = [tile] * len(net.layer_shapes())
+    assert net.tiles == [tile] * len(net.layer_shapes())
+    x = rng.standard_normal((1029, P.LEAF_D_IN)).astype(np.float32)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    close(y, mlp.forward(params, x, emulate_bf16=True), f"forward tile {tile}")
+
+
+def test_forward_after_autotune():
+    import torch
+    rng = np.random.default_rng(78)
+    net = P.LeafNet(P.LEAF_D_IN, 1536, 4, P.LEAF_D_OUT, max_batch=1029)
+    params = rand_params(rng, net.layer_shapes(), scale=1.5)
+    net.set_params(params)
+    before, after = net.autotune(1029, 3)
+    say(f"case: GEMM tile autotune m=1029: {before:.4f} -> {after:.4f} ms per forward, tiles {net.tiles}")
+    assert before > 0 and after > 0 and all(t in (0, 1, 2, 3) for t in net.tiles)
+    x = rng.standard_normal((1029, P.LEAF_D_IN)).astype(np.float32)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    close(y, mlp.forward(params, x, emulate_bf16=True), "forward after autotune")
+    with pytest.raises(P.PcfrError):
+        net.tiles = [3] * (len(net.layer_shapes()) - 1)
+
+
 def test_train_step_gradients_and_adam():
     import torch
     d_in, width, depth, d_out, m = 200, 192, 2, 130, 100
