@@ -292,6 +292,15 @@ int32_t pcfr_leafnet_train_step(pcfr_leafnet* net, const float* x, const float* 
  * per unit of compatible opponent reach) and hold leaves x next-cards rows.
  * All-in leaves stay exact.  The net must outlive the attachment. */
 int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net);
+
+/* Zero-sum correction of network leaf values, on (1, the default) or off (0).
+ * For each (leaf, next card c) row, both players' outputs EV_i(h | c) are
+ * shifted by the same d = e / (2 z), e = sum_h r0(h) M1(h|c) EV0(h|c) +
+ * sum_h r1(h) M0(h|c) EV1(h|c), z = sum_h r0(h) M1(h|c) (hands holding c
+ * excluded), so that the row's values sum to zero over both players as
+ * solved values do.  The paper does not say how leaf values are kept
+ * consistent; this is a reading.  Re-captures the iteration graph. */
+int32_t pcfr_solver_set_leaf_zero_sum(pcfr_solver* s, int32_t on);
 /* Training samples for the leaf network from a solved batch (the survey of
  * the paper's depth-limited method: the network is trained on subgames the
  * solver itself solves).  Row g of x (device fp32 [n][ldx], ldx >= 2705):

@@ -135,3 +135,40 @@ def leaf_inputs(reach_leaf: np.ndarray, board, pot: float, stack_behind: float, 
             X[k, 2 * NCOMBO + b] = 1.0
         X[k, 2 * NCOMBO + 52] = stack_behind / pot
     return cards, X
+
+
+_COMPAT = None
+
+
+def _compat():
+    """[1326, 1326] float64: 1 where two combos share no card."""
+    global _COMPAT
+    if _COMPAT is None:
+        a, b = _CC[:, 0], _CC[:, 1]
+        share = (a[:, None] == a[None, :]) | (a[:, None] == b[None, :]) | (b[:, None] == a[None, :]) | \
+                (b[:, None] == b[None, :])
+        _COMPAT = (~share).astype(np.float64)
+    return _COMPAT
+
+
+def compatible_mass(r_opp: np.ndarray, card: int) -> np.ndarray:
+    """M(h | c) for every combo h: the opponent reach summed over combos that
+    share no card with h and do not hold the dealt card c (brute force)."""
+    keep = (_CC[:, 0] != card) & (_CC[:, 1] != card)
+    return _compat() @ (r_opp * keep)
+
+
+def zero_sum_shift(ev: np.ndarray, reach_leaf: np.ndarray, card: int) -> float:
+    """The zero-sum correction of one leaf row (a reading; the paper does not
+    say how leaf values are kept consistent).  ev: [2, 1326] network outputs
+    (value per pot unit and per unit of compatible opponent reach) after the
+    next card c; reach_leaf: [2, 1326].  Returns d such that subtracting d
+    from both players' EVs makes sum_h r0 M1 EV0 + sum_h r1 M0 EV1 = 0, with
+    only combos not holding c counted: d = e / (2 z), z = sum_h r0 M1."""
+    keep = (_CC[:, 0] != card) & (_CC[:, 1] != card)
+    r0, r1 = reach_leaf[0] * keep, reach_leaf[1] * keep
+    m1 = compatible_mass(reach_leaf[1], card)
+    m0 = compatible_mass(reach_leaf[0], card)
+    e = float((r0 * m1 * ev[0]).sum() + (r1 * m0 * ev[1]).sum())
+    z = float((r0 * m1).sum())
+    return e / (2.0 * z) if z > 0 else 0.0

@@ -48,6 +48,7 @@ struct __align__(16) DNode {
     int32_t rs, aux, sub, dead;   // aux: showdown board table, or chance divisor K;
                                   // dead: cards dealt since the root, c1 | c2 << 8 (0xff = none)
     int32_t slot[2];              // reach slot of each player (see below)
+    int32_t id, pad;              // the node's own id (copies in the level sweep lists)
     double pay;                   // fold: folder's contribution; showdown: each contribution
 };
 
@@ -145,7 +146,8 @@ template <typename T, int MODE, int A>
 __device__ __forceinline__ void fwd_decision(const DNode& nd, int h, int Hp, int cbase, const T* __restrict__ R,
                                              const T* __restrict__ S, const T* __restrict__ Mp,
                                              T* __restrict__ reach) {
-    const V4<T> rp = ld4(reach + (int64_t)nd.slot[nd.player] * Hp + h);
+    // (a select, not nd.slot[player]: a dynamic index would move nd to memory)
+    const V4<T> rp = ld4(reach + (int64_t)(nd.player ? nd.slot[1] : nd.slot[0]) * Hp + h);
     const T* src = (MODE == MODE_ITER ? R : S) + (int64_t)nd.rs * Hp + h;
     V4<T> x[A];
 #pragma unroll
@@ -174,11 +176,11 @@ __device__ __forceinline__ void fwd_decision(const DNode& nd, int h, int Hp, int
     }
 }
 
-// One thread per (decision node, 4 hands) of a level; chance nodes have no
-// forward work (their children share their reach slots).
+// One thread per (decision node, 4 hands) of a level, the level's node
+// records copied contiguously; chance nodes have no forward work (their
+// children share their reach slots).
 template <typename T, int MODE, int MAXA>
-__global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restrict__ nodes,
-                                                            const int32_t* __restrict__ list, int count, int Hp,
+__global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restrict__ level, int count, int Hp,
                                                             int cbase, const T* __restrict__ R,
                                                             const T* __restrict__ S, const T* __restrict__ Mp,
                                                             T* __restrict__ reach, IterState* begin) {
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restr
     const int64_t k = gid / groups;
     if (k >= count) return;
     const int h = (int)(gid - k * groups) * 4;
-    const DNode nd = nodes[list[k]];
+    const DNode nd = level[k];
     switch (nd.n_child) {
 #define PCFR_FWD_CASE(A) \
     case A:              \
@@ -258,7 +260,7 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         // average-strategy sum (Stage 1's accumulation, done here so that one
         // pass reads and writes both tables), each with its DCFR discount.
         const T dpos = (T)st->dpos, dneg = (T)st->dneg, wadd = (T)st->wadd, wmul = (T)st->wmul;
-        V4<T> rp = ld4(reach + (int64_t)nd.slot[p] * Hp + h);
+        V4<T> rp = ld4(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
         if (nd.dead != 0xffff) {
             const uint16_t* hc = hcards + (int64_t)nd.sub * Hp + h;
 #pragma unroll
@@ -290,8 +292,7 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
 // root_dst (the last launch of an iteration only) also receives each root's
 // values, which later evaluation sweeps do not overwrite.
 template <typename T, int MODE, int MAXA>
-__global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __restrict__ nodes,
-                                                             const int32_t* __restrict__ list, int count, int Hp,
+__global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __restrict__ level, int count, int Hp,
                                                              T* __restrict__ R, T* __restrict__ S, T* __restrict__ Mp,
                                                              const T* __restrict__ reach, T* __restrict__ cfv,
                                                              const IterState* __restrict__ st,
@@ -302,12 +303,12 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
     const int64_t k = gid / groups;
     if (k >= count) return;
     const int h = (int)(gid - k * groups) * 4;
-    const int64_t n = list[k];
-    const DNode nd = nodes[n];
+    const DNode nd = level[k];
+    const int64_t n = nd.id;
     if (nd.type == PCFR_NODE_CHANCE) {
-        // children in groups of 8: all loads of a group are issued before the
+        // children in groups of 4: all loads of a group are issued before the
         // adds, which keep the children's order
-        constexpr int G = 8;
+        constexpr int G = 4;
         V4<T> a0 = {{T(0), T(0), T(0), T(0)}}, a1 = a0;
         for (int c0 = 0; c0 < nd.n_child; c0 += G) {
             V4<T> u[G], w[G];
@@ -348,69 +349,144 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
 }
 
 // ------------------------------------------------------------ terminals
+// Both terminal kinds are latency-bound (a few thousand hands per workgroup),
+// so every stage first issues all of a thread's global loads (fixed trip
+// counts, predicated) and only then consumes them, and block reductions and
+// scans use wave shuffles with one LDS exchange between the 4 waves.
+constexpr int kMaxHp = 1216;                          // flop: 1176 compatible combos padded to 64
+constexpr int kHandIt = (kMaxHp + kBlock - 1) / kBlock;
+constexpr int kWaves = kBlock / 64;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+
+// Copy n int16 values (n a multiple of 8, both pointers 16-byte aligned) to LDS.
+template <int MAXV>
+__device__ __forceinline__ void copy_i16(int16_t* dst, const int16_t* __restrict__ src, int n) {
+    const int nv = n >> 3;
+    u32x4 v[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+        const int j = threadIdx.x + i * kBlock;
+        if (j < nv) v[i] = reinterpret_cast<const u32x4*>(src)[j];
+    }
+#pragma unroll
+    for (int i = 0; i < MAXV; i++) {
+        const int j = threadIdx.x + i * kBlock;
+        if (j < nv) reinterpret_cast<u32x4*>(dst)[j] = v[i];
+    }
+}
+
+// Sum over the workgroup of a and b (every thread gets both totals);
+// xch: LDS scratch of 2 * kWaves values.
+template <typename T>
+__device__ __forceinline__ void block_sum2(T& a, T& b, T* xch) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { xch[w] = a; xch[kWaves + w] = b; }
+    __syncthreads();
+    a = T(0);
+    b = T(0);
+#pragma unroll
+    for (int i = 0; i < kWaves; i++) { a += xch[i]; b += xch[kWaves + i]; }
+}
+
+// Exclusive scan over the workgroup of a and b in thread order; the totals
+// come back in ta, tb.  xch: LDS scratch of 2 * kWaves values.
+template <typename T>
+__device__ __forceinline__ void block_exscan2(T& a, T& b, T& ta, T& tb, T* xch) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T ia = a, ib = b;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T ua = __shfl_up(ia, o), ub = __shfl_up(ib, o);
+        if (lane >= o) { ia += ua; ib += ub; }
+    }
+    if (lane == 63) { xch[w] = ia; xch[kWaves + w] = ib; }
+    __syncthreads();
+    T oa = T(0), ob = T(0);
+    ta = T(0);
+    tb = T(0);
+#pragma unroll
+    for (int i = 0; i < kWaves; i++) {
+        if (i < w) { oa += xch[i]; ob += xch[kWaves + i]; }
+        ta += xch[i];
+        tb += xch[kWaves + i];
+    }
+    a = oa + ia - a;
+    b = ob + ib - b;
+}
+
 // Fold: v_i(h) = -+ c_f * M_{-i}(h) where M(h) is the opponent reach over
 // hands sharing no card with h: total - per-card(a) - per-card(b) + r(h)
 // (the hand itself was removed twice).  Both reach vectors and the per-card
-// hand lists are staged in LDS first, so the 104 per-card sums read LDS only.
+// hand lists are staged in LDS first, so the 104 per-card sums read LDS only;
+// hands holding a card dealt below the root are staged as zero reach.
 template <typename T>
 __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                           const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
                           const int16_t* __restrict__ chands, T* lds) {
-    // hands holding a card dealt below the root are staged as zero reach
     T* x0 = lds;                  // [Hp]
     T* x1 = x0 + Hp;              // [Hp]
-    T* pc = x1 + Hp;              // [2][52]
-    T* red = pc + 208;            // [2][kBlock]  (pc holds two half-sums per card first)
-    int16_t* lst = reinterpret_cast<int16_t*>(red + 2 * kBlock);   // [2 * Hp]
+    T* pc = x1 + Hp;              // [2][52], two half-sums per card first: [208]
+    T* xch = pc + 208;            // [2 * kWaves], padded to 2 * kBlock
+    int16_t* lst = reinterpret_cast<int16_t*>(xch + 2 * kBlock);     // [2 * Hp]
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
     const int nl = coff[52];
-    const bool masked = nd.dead != 0xffff;
-    T s0 = T(0), s1 = T(0);
-    for (int h = tid; h < Hp; h += kBlock) {
-        T a = r0[h], b = r1[h];
-        if (masked && !hand_alive(hc[h], nd.dead)) { a = T(0); b = T(0); }
-        x0[h] = a;
-        x1[h] = b;
-        s0 += a;
-        s1 += b;
+    copy_i16<(2 * kMaxHp / 8 + kBlock - 1) / kBlock>(lst, chands, (nl + 7) & ~7);
+    T a[kHandIt], b[kHandIt];
+    uint32_t c[kHandIt];
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h < Hp) { a[i] = r0[h]; b[i] = r1[h]; c[i] = hc[h]; }
     }
-    for (int j = tid; j < nl; j += kBlock) lst[j] = chands[j];
-    red[tid] = s0;
-    red[kBlock + tid] = s1;
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h < Hp) {
+            if (!hand_alive(c[i], nd.dead)) { a[i] = T(0); b[i] = T(0); }
+            x0[h] = a[i];
+            x1[h] = b[i];
+            s0 += a[i];
+            s1 += b[i];
+        }
+    }
     __syncthreads();
     if (tid < 208) {
         // two threads per (player, card), each summing half of the card's list
         const int pcix = tid >> 1, half = tid & 1;
-        const int p = pcix / 52, c = pcix - p * 52;
+        const int p = pcix / 52, cd = pcix - p * 52;
         const T* x = p ? x1 : x0;
-        const int lo = coff[c], hi = coff[c + 1], mid = lo + ((hi - lo) >> 1);
+        const int lo = coff[cd], hi = coff[cd + 1], mid = lo + ((hi - lo) >> 1);
         T acc = T(0);
         for (int j = half ? mid : lo; j < (half ? hi : mid); j++) acc += x[lst[j]];
         pc[tid] = acc;
     }
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) { red[tid] += red[tid + w]; red[kBlock + tid] += red[kBlock + tid + w]; }
-        __syncthreads();
-    }
+    block_sum2(s0, s1, xch);      // synchronises: the half-sums are visible after it
     T pcv0 = T(0), pcv1 = T(0);
     if (tid < 104) { pcv0 = pc[2 * tid]; pcv1 = pc[2 * tid + 1]; }
     __syncthreads();
     if (tid < 104) pc[tid] = pcv0 + pcv1;
     __syncthreads();
-    const T tot0 = red[0], tot1 = red[kBlock];
     const int f = nd.player;
     const T pay = (T)nd.pay;
     T* v0 = cfv + n * 2 * Hp;
     T* v1 = v0 + Hp;
-    for (int h = tid; h < Hp; h += kBlock) {
-        const uint32_t c = hc[h];
-        const int a = c & 0xff, b = c >> 8;
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h >= Hp) break;
+        const int ca = c[i] & 0xff, cb = c[i] >> 8;
         T m0 = T(0), m1 = T(0);
-        if (hand_alive(c, nd.dead)) {
-            m0 = tot0 - pc[a] - pc[b] + x0[h];
-            m1 = tot1 - pc[52 + a] - pc[52 + b] + x1[h];
+        if (hand_alive(c[i], nd.dead)) {
+            m0 = s0 - pc[ca] - pc[cb] + x0[h];
+            m1 = s1 - pc[52 + ca] - pc[52 + cb] + x1[h];
         }
         v0[h] = (f == 0 ? -pay : pay) * m1;
         v1[h] = (f == 1 ? -pay : pay) * m0;
@@ -422,39 +498,59 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
 // sorted positions of hands holding it, ascending, followed by one slot for
 // the list total; [alo, ahi) and [blo, bhi) are the tie group of a hand inside
 // the lists of its two cards.  W = opponent reach of compatible weaker hands,
-// L = of compatible stronger ones; ties pay nothing.
+// L = of compatible stronger ones; ties pay nothing.  The board's table
+// lists only hands alive on it, so no dealt-card masking is needed.
 template <typename T>
 __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                               const uint16_t* __restrict__ hc, const int16_t* __restrict__ tb, int Hb, T* lds) {
     const int QN = 2 * Hp + kSdHeader;
-    T* xs0 = lds;                 // [Hp + 1]: sorted reach, then its exclusive prefix
-    T* xs1 = xs0 + (Hp + 1);
-    T* q0 = xs1 + (Hp + 1);       // [QN]: card-list exclusive prefixes
+    T* xs0 = lds;                 // [Hp + 4]: sorted reach, then its exclusive prefix
+    T* xs1 = xs0 + (Hp + 4);
+    T* q0 = xs1 + (Hp + 4);       // [QN]: card-list exclusive prefixes
     T* q1 = q0 + QN;
-    T* part = q1 + QN;            // [2][kBlock]
-    const int16_t* perm = tb;
+    T* xch = q1 + QN;             // [2 * kWaves], padded to 2 * kBlock
+    int16_t* coff = reinterpret_cast<int16_t*>(xch + 2 * kBlock);     // [kSdHeader]
+    int16_t* clist = coff + kSdHeader;                                // [QN]
+    int16_t* perm = clist + QN;                                       // [Hp]
     const int16_t* glo = tb + Hp;
     const int16_t* ghi = tb + 2 * Hp;
     const int16_t* alo = tb + 3 * Hp;
     const int16_t* ahi = tb + 4 * Hp;
     const int16_t* blo = tb + 5 * Hp;
     const int16_t* bhi = tb + 6 * Hp;
-    const int16_t* gcoff = tb + 7 * Hp;
-    const int16_t* gclist = gcoff + kSdHeader;
-    int16_t* coff = reinterpret_cast<int16_t*>(part + 2 * kBlock);    // [kSdHeader], LDS copy
-    int16_t* clist = coff + kSdHeader;                                // [QN]: lists + total slots, LDS copy
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
 
-    for (int s = tid; s < Hb; s += kBlock) {
-        const int h = perm[s];
-        xs0[s] = r0[h];
-        xs1[s] = r1[h];
+    // card-list offsets, lists (2 * Hb + 52 entries <= QN) and the permutation
+    copy_i16<((kSdHeader + 2 * kMaxHp + kSdHeader) / 8 + kBlock - 1) / kBlock>(coff, tb + 7 * Hp, kSdHeader + QN);
+    copy_i16<(kMaxHp / 8 + kBlock - 1) / kBlock>(perm, tb, Hp);
+    // this thread's hands in the output stage: table entries and cards
+    int s_gl[kHandIt], s_gh[kHandIt], s_al[kHandIt], s_ah[kHandIt], s_bl[kHandIt], s_bh[kHandIt];
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int s = tid + i * kBlock;
+        if (s < Hb) {
+            s_gl[i] = glo[s]; s_gh[i] = ghi[s]; s_al[i] = alo[s];
+            s_ah[i] = ahi[s]; s_bl[i] = blo[s]; s_bh[i] = bhi[s];
+        }
     }
-    if (tid < kSdHeader) coff[tid] = gcoff[tid];
-    // the lists hold 2 * Hb + 52 entries (one total slot per card) <= QN
-    for (int j = tid; j < QN; j += kBlock) clist[j] = gclist[j];
+    __syncthreads();
+    int hh[kHandIt];
+    uint32_t cc[kHandIt];
+    T a[kHandIt], b[kHandIt];
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int s = tid + i * kBlock;
+        hh[i] = s < Hp ? perm[s] : 0;
+        if (s < Hb) { a[i] = r0[hh[i]]; b[i] = r1[hh[i]]; }
+        if (s < Hb) cc[i] = hc[hh[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int s = tid + i * kBlock;
+        if (s < Hb) { xs0[s] = a[i]; xs1[s] = b[i]; }
+    }
     __syncthreads();
     if (tid < 104) {
         const int p = tid / 52, c = tid - p * 52;
@@ -462,11 +558,20 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         T* q = p ? q1 : q0;
         const int lo = coff[c], hi = coff[c + 1] - 1;
         T acc = T(0);
-        for (int j = lo; j < hi; j++) { q[j] = acc; acc += xs[clist[j]]; }
+        int j = lo;
+        for (; j + 4 <= hi; j += 4) {
+            const T y0 = xs[clist[j]], y1 = xs[clist[j + 1]], y2 = xs[clist[j + 2]], y3 = xs[clist[j + 3]];
+            q[j] = acc; acc += y0;
+            q[j + 1] = acc; acc += y1;
+            q[j + 2] = acc; acc += y2;
+            q[j + 3] = acc; acc += y3;
+        }
+        for (; j < hi; j++) { q[j] = acc; acc += xs[clist[j]]; }
         q[hi] = acc;
     }
-    // block-wide exclusive scan of xs0 / xs1 over [0, Hb), total at [Hb]
-    constexpr int kMaxChunk = 8;
+    // exclusive scan of xs0 / xs1 over [0, Hb) in sorted order: each thread
+    // owns a contiguous chunk, chunk sums are scanned across the workgroup
+    constexpr int kMaxChunk = (kMaxHp + kBlock - 1) / kBlock;
     const int chunk = (Hb + kBlock - 1) / kBlock;
     const int beg = tid * chunk;
     T l0[kMaxChunk], l1[kMaxChunk];
@@ -480,45 +585,34 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         s0 += l0[i];
         s1 += l1[i];
     }
-    part[tid] = s0;
-    part[kBlock + tid] = s1;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        T a0 = tid >= off ? part[tid - off] : T(0);
-        T a1 = tid >= off ? part[kBlock + tid - off] : T(0);
-        __syncthreads();
-        part[tid] += a0;
-        part[kBlock + tid] += a1;
-        __syncthreads();
-    }
-    T e0 = part[tid] - s0, e1 = part[kBlock + tid] - s1;   // exclusive offset of this chunk
+    T tot0, tot1;
+    block_exscan2(s0, s1, tot0, tot1, xch);   // synchronises: every chunk was read above
+    __syncthreads();                          // all reads of xs done before it is overwritten
 #pragma unroll
     for (int i = 0; i < kMaxChunk; i++) {
         const int s = beg + i;
         if (i < chunk && s < Hb) {
-            xs0[s] = e0;
-            xs1[s] = e1;
-            e0 += l0[i];
-            e1 += l1[i];
+            xs0[s] = s0;
+            xs1[s] = s1;
+            s0 += l0[i];
+            s1 += l1[i];
         }
     }
-    if (tid == kBlock - 1) {
-        xs0[Hb] = part[kBlock - 1];
-        xs1[Hb] = part[2 * kBlock - 1];
-    }
+    if (tid == 0) { xs0[Hb] = tot0; xs1[Hb] = tot1; }
     __syncthreads();
 
     const T pay = (T)nd.pay;
     T* v0 = cfv + n * 2 * Hp;
     T* v1 = v0 + Hp;
-    const T tot0 = xs0[Hb], tot1 = xs1[Hb];
-    for (int s = tid; s < Hp; s += kBlock) {
-        const int h = perm[s];
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int s = tid + i * kBlock;
+        if (s >= Hp) break;
+        const int h = hh[i];
         if (s >= Hb) { v0[h] = T(0); v1[h] = T(0); continue; }
-        const uint32_t c = hc[h];
-        const int a = c & 0xff, b = c >> 8;
-        const int ae = coff[a + 1] - 1, be = coff[b + 1] - 1;
-        const int gl = glo[s], gh = ghi[s], al = alo[s], ah = ahi[s], bl = blo[s], bh = bhi[s];
+        const int ca = cc[i] & 0xff, cb = cc[i] >> 8;
+        const int ae = coff[ca + 1] - 1, be = coff[cb + 1] - 1;
+        const int gl = s_gl[i], gh = s_gh[i], al = s_al[i], ah = s_ah[i], bl = s_bl[i], bh = s_bh[i];
         // against player 1's reach (value of player 0)
         const T w1 = xs1[gl] - q1[al] - q1[bl];
         const T lo1 = (tot1 - xs1[gh]) - (q1[ae] - q1[ah]) - (q1[be] - q1[bh]);
@@ -555,7 +649,6 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
 // workgroup with the slice of their reach vectors in LDS; a second kernel adds
 // the slices in a fixed order (deterministic) and applies the contribution.
 constexpr int kEqSplit = 32;
-constexpr int kMaxHp = 1216;    // flop: 1176 compatible combos padded to 64
 
 template <typename T, int J>
 __global__ __launch_bounds__(kBlock) void k_equity_partial(const DNode* __restrict__ nodes,
@@ -570,7 +663,8 @@ __global__ __launch_bounds__(kBlock) void k_equity_partial(const DNode* __restri
     const int o0 = blockIdx.z * chunk, o1 = min(Hp, o0 + chunk);
     for (int i = threadIdx.x; i < nj * 2 * chunk; i += kBlock) {
         const int j = i / (2 * chunk), rest = i - j * 2 * chunk, p = rest / chunk, o = o0 + rest - p * chunk;
-        rr[j][p][o - o0] = o < o1 ? reach[(int64_t)nodes[leaves[j0 + j]].slot[p] * Hp + o] : T(0);
+        const DNode& lf = nodes[leaves[j0 + j]];
+        rr[j][p][o - o0] = o < o1 ? reach[(int64_t)(p ? lf.slot[1] : lf.slot[0]) * Hp + o] : T(0);
     }
     __syncthreads();
     const int h = blockIdx.x * kBlock + threadIdx.x;
@@ -668,6 +762,69 @@ __global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__
     }
 }
 
+// Zero-sum correction of the network's outputs (a reading: the paper does not
+// say how leaf values are kept consistent).  For one row (leaf, next card c)
+// the values pot * EV_i(h | c) weighted by own reach and by the opponent's
+// compatible reach M_{-i}(h | c) should sum to zero over both players, as the
+// solved targets do; the kernel finds the shift d = e / (2 z) with
+// e = sum_h r0 M1 EV0 + sum_h r1 M0 EV1 and z = sum_h r0 M1 (= sum_h r1 M0),
+// which the combine subtracts from both players' EVs of that row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_leaf_zerosum(const DNode* __restrict__ nodes,
+                                                         const int32_t* __restrict__ leaves, int n_next,
+                                                         const int8_t* __restrict__ next_cards, int Hp, int H,
+                                                         const T* __restrict__ reach,
+                                                         const uint16_t* __restrict__ hcards,
+                                                         const int16_t* __restrict__ hand_combo,
+                                                         const int16_t* __restrict__ combo_hand,
+                                                         const int32_t* __restrict__ coff,
+                                                         const int16_t* __restrict__ chands,
+                                                         const float* __restrict__ Y, int ldy, T* __restrict__ delta) {
+    __shared__ T x[2][kMaxHp];
+    __shared__ T cs[2][52];
+    __shared__ T xch[2 * kWaves];
+    const int row = blockIdx.x, li = row / n_next, k = row - li * n_next;
+    const int c = next_cards[k];
+    const DNode nd = nodes[leaves[li]];
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    const int tid = threadIdx.x;
+    T s0 = T(0), s1 = T(0);
+    for (int h = tid; h < Hp; h += kBlock) {
+        const T a = r0[h], b = r1[h];
+        x[0][h] = a;
+        x[1][h] = b;
+        s0 += a;
+        s1 += b;
+    }
+    __syncthreads();
+    if (tid < 104) {
+        const int p = tid / 52, cd = tid - p * 52;
+        T acc = T(0);
+        for (int j = coff[cd]; j < coff[cd + 1]; j++) acc += x[p][chands[j]];
+        cs[p][cd] = acc;
+    }
+    block_sum2(s0, s1, xch);      // synchronises: cs is visible after it
+    const float* y = Y + (int64_t)row * ldy;
+    T e = T(0), z = T(0);
+    for (int h = tid; h < H; h += kBlock) {
+        const uint32_t hc = hcards[h];
+        const int a = hc & 0xff, b = hc >> 8;
+        if (a == c || b == c) continue;
+        const int ha = combo_hand[combo_index(a, c)], hb = combo_hand[combo_index(b, c)];
+        const T m1 = s1 - cs[1][a] - cs[1][b] - cs[1][c] + x[1][h] + (ha >= 0 ? x[1][ha] : T(0)) +
+                     (hb >= 0 ? x[1][hb] : T(0));
+        const T m0 = s0 - cs[0][a] - cs[0][b] - cs[0][c] + x[0][h] + (ha >= 0 ? x[0][ha] : T(0)) +
+                     (hb >= 0 ? x[0][hb] : T(0));
+        const int combo = hand_combo[h];
+        e += x[0][h] * m1 * (T)y[combo] + x[1][h] * m0 * (T)y[kCombos + combo];
+        z += x[0][h] * m1;
+    }
+    __syncthreads();              // xch is reused
+    block_sum2(e, z, xch);
+    if (tid == 0) delta[row] = z > T(0) ? e / (T(2) * z) : T(0);
+}
+
 // Leaf counterfactual values from the network's per-card outputs (Sec. 4.4:
 // leaf predictions weighted by the opponent's counterfactual reach and the
 // chance probability): v_i(h) = pot/K * sum_{c not in h} EV_i(h | c) *
@@ -686,10 +843,12 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
                                                          const int16_t* __restrict__ combo_hand,
                                                          const int32_t* __restrict__ coff,
                                                          const int16_t* __restrict__ chands,
-                                                         const float* __restrict__ Y, int ldy) {
+                                                         const float* __restrict__ Y, int ldy,
+                                                         const T* __restrict__ delta) {
     __shared__ T x[2][kMaxHp];
     __shared__ int16_t c2h[kCombos];
     __shared__ int8_t nxt[52];
+    __shared__ T dl[52];
     __shared__ T cs[2][52];
     __shared__ T red[2][kBlock];
     const int li = blockIdx.x;
@@ -707,7 +866,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
         s1 += b;
     }
     for (int k = tid; k < kCombos; k += kBlock) c2h[k] = combo_hand[k];
-    if (tid < n_next) nxt[tid] = next_cards[tid];
+    if (tid < n_next) {
+        nxt[tid] = next_cards[tid];
+        dl[tid] = delta ? delta[li * n_next + tid] : T(0);
+    }
     red[0][tid] = s0;
     red[1][tid] = s1;
     __syncthreads();
@@ -743,8 +905,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
             const int ha = c2h[combo_index(a, c)], hb = c2h[combo_index(b, c)];
             const T m1 = base1 - cs[1][c] + (ha >= 0 ? x[1][ha] : T(0)) + (hb >= 0 ? x[1][hb] : T(0));
             const T m0 = base0 - cs[0][c] + (ha >= 0 ? x[0][ha] : T(0)) + (hb >= 0 ? x[0][hb] : T(0));
-            acc0 += (T)y[(int64_t)k * ldy + combo] * m1;
-            acc1 += (T)y[(int64_t)k * ldy + kCombos + combo] * m0;
+            acc0 += ((T)y[(int64_t)k * ldy + combo] - dl[k]) * m1;
+            acc1 += ((T)y[(int64_t)k * ldy + kCombos + combo] - dl[k]) * m0;
         }
     }
     red[0][tid] = acc0;
@@ -884,7 +1046,7 @@ struct Plan {
     size_t esz;
     size_t off_nodes, off_fwd, off_dec, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
+        off_potk, off_zs, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
     size_t lds_bytes, lds_fold, lds_show;
 };
 
@@ -897,6 +1059,7 @@ struct Prepared {
     std::vector<int64_t> fwd_off;         // per level start into fwd (size levels+1)
     std::vector<int32_t> dec;             // decision nodes only, by level (forward sweep)
     std::vector<int64_t> dec_off;
+    std::vector<DNode> fwd_rec, dec_rec;  // node records in the order of fwd and dec
     std::vector<int32_t> lvl_maxa;        // per level: most actions of a decision node
     std::vector<int32_t> folds, shows;    // terminal lists by kind
     std::vector<uint16_t> hcards;         // [n_sub][Hp]
@@ -949,10 +1112,11 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
     }
     P.H = P.Hs[0];
     P.Hp = (Hmax + 63) / 64 * 64;
+    if (P.Hp > kMaxHp) { set_error("more compatible hands than the kernels support"); return PCFR_E_TOO_LARGE; }
     const int64_t Hp = P.Hp;
     P.hcards.assign((size_t)K * Hp, 0xffff);
     P.coff.assign((size_t)K * 53, 0);
-    P.chand_stride = 2 * Hmax;
+    P.chand_stride = (2 * Hmax + 7) / 8 * 8;    // 16-byte aligned per subgame (read in 8-entry vectors)
     P.chands.assign((size_t)K * P.chand_stride, 0);
     for (int32_t g = 0; g < K; g++) {
         for (int64_t h = 0; h < P.Hs[g]; h++) {
@@ -1097,6 +1261,11 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
     P.term.insert(P.term.end(), P.folds.begin(), P.folds.end());
     P.term.insert(P.term.end(), P.shows.begin(), P.shows.end());
     P.fwd_off[P.levels] = (int64_t)P.fwd.size();
+    for (int64_t i = 0; i < (int64_t)P.nodes.size(); i++) P.nodes[i].id = (int32_t)i;
+    P.fwd_rec.clear();
+    P.dec_rec.clear();
+    for (auto x : P.fwd) P.fwd_rec.push_back(P.nodes[x]);
+    for (auto x : P.dec) P.dec_rec.push_back(P.nodes[x]);
     // strength tables
     const int64_t nbds = (int64_t)board_id.size();
     P.sd.assign((size_t)std::max<int64_t>(nbds, 1) * P.sd_stride, 0);
@@ -1181,8 +1350,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.off_nodes = take(sizeof(DNode) * L.N);
-    L.off_fwd = take(sizeof(int32_t) * std::max<int64_t>(L.fwd, 1));
-    L.off_dec = take(sizeof(int32_t) * std::max<int64_t>(L.dec, 1));
+    L.off_fwd = take(sizeof(DNode) * std::max<int64_t>(L.fwd, 1));
+    L.off_dec = take(sizeof(DNode) * std::max<int64_t>(L.dec, 1));
     L.off_term = take(sizeof(int32_t) * std::max<int64_t>(L.term, 1));
     L.off_hc = take(sizeof(uint16_t) * L.Hp * P.n_sub);
     L.off_coff = take(sizeof(int32_t) * 53 * P.n_sub);
@@ -1205,6 +1374,7 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_net = take(sizeof(int32_t) * std::max<int64_t>(L.n_net, 1));
     L.off_spr = take(sizeof(float) * std::max<int64_t>(L.n_net, 1));
     L.off_potk = take(sizeof(double) * std::max<int64_t>(L.n_net, 1));
+    L.off_zs = take(L.esz * std::max<int64_t>(L.n_net * L.n_next, 1));
     L.off_next = take(64);
     L.off_hot = take(64);
     L.off_c2h = take(sizeof(int16_t) * kCombos);
@@ -1216,7 +1386,7 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_eqpart = take(L.esz * kEqSplit * L.n_eq * 2 * L.Hp);
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
-    const size_t sd_lds = L.esz * (2 * (L.Hp + 1) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn);
+    const size_t sd_lds = L.esz * (2 * (L.Hp + 4) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn + L.Hp);
     const size_t fold_lds = L.esz * (2 * L.Hp + 208 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp;
     L.lds_fold = fold_lds;
     L.lds_show = sd_lds;
@@ -1249,6 +1419,7 @@ struct pcfr_solver {
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
     pcfr_leafnet* net = nullptr;
+    bool leaf_zero_sum = true;  // shift network outputs to zero-sum leaf values
     int64_t t_host = 0;     // iterations enqueued
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
 };
@@ -1262,8 +1433,8 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     const int Hp = (int)L.Hp;
     const int groups = Hp / 4;
     DNode* nodes = s->at<DNode>(L.off_nodes);
-    int32_t* fwd = s->at<int32_t>(L.off_fwd);
-    int32_t* dec = s->at<int32_t>(L.off_dec);
+    DNode* fwd = s->at<DNode>(L.off_fwd);
+    DNode* dec = s->at<DNode>(L.off_dec);
     T* R = s->at<T>(L.off_R);
     T* S = s->at<T>(L.off_S);
     T* reach = s->at<T>(L.off_reach);
@@ -1289,7 +1460,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         const int64_t threads = cnt * groups;
         dim3 grid((unsigned)((threads + bs - 1) / bs));
         if (tm) tm->before(1, l);
-        PCFR_BUCKET(k_forward, l, grid, dim3(bs), 0, stream, nodes, dec + P.dec_off[l], (int)cnt, Hp,
+        PCFR_BUCKET(k_forward, l, grid, dim3(bs), 0, stream, dec + P.dec_off[l], (int)cnt, Hp,
                     (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr);
         if (tm) tm->after();
         first = false;
@@ -1333,6 +1504,16 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (tm) tm->after();
         int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
         if (rc) return rc;
+        if (s->leaf_zero_sum) {
+            if (tm) tm->before(4);
+            hipLaunchKernelGGL((k_leaf_zerosum<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes,
+                               s->at<int32_t>(L.off_net), (int)L.n_next, s->at<int8_t>(L.off_next), Hp, (int)L.H,
+                               reach, s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_h2c),
+                               s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
+                               reinterpret_cast<const float*>(net->ws + net->P.off_y), (int)net->P.pdims[net->P.L],
+                               s->at<T>(L.off_zs));
+            if (tm) tm->after();
+        }
         if (tm) tm->before(4);
         hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)((Hp + 63) / 64)),
                            dim3(kBlock), 0, stream, nodes,
@@ -1340,7 +1521,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->at<int8_t>(L.off_next), Hp, (int)L.H, reach, cfv, s->at<uint16_t>(L.off_hc),
                            s->at<int16_t>(L.off_h2c), s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff),
                            s->at<int16_t>(L.off_chands), reinterpret_cast<const float*>(net->ws + net->P.off_y),
-                           (int)net->P.pdims[net->P.L]);
+                           (int)net->P.pdims[net->P.L], s->leaf_zero_sum ? s->at<T>(L.off_zs) : nullptr);
         if (tm) tm->after();
     }
     // backward; level 0 holds exactly the roots, whose values of this
@@ -1352,7 +1533,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         const int64_t threads = cnt * groups;
         dim3 grid((unsigned)((threads + bs - 1) / bs));
         if (tm) tm->before(3, 1000 + l);
-        PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, nodes, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
+        PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
                     reach, cfv, st, s->at<uint16_t>(L.off_hc),
                     (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr);
         if (tm) tm->after();
@@ -1548,8 +1729,8 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         return hip_check(hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream), "upload");
     };
     if ((rc = up(L.off_nodes, P.nodes.data(), sizeof(DNode) * P.nodes.size()))) return rc;
-    if ((rc = up(L.off_fwd, P.fwd.data(), sizeof(int32_t) * P.fwd.size()))) return rc;
-    if ((rc = up(L.off_dec, P.dec.data(), sizeof(int32_t) * P.dec.size()))) return rc;
+    if ((rc = up(L.off_fwd, P.fwd_rec.data(), sizeof(DNode) * P.fwd_rec.size()))) return rc;
+    if ((rc = up(L.off_dec, P.dec_rec.data(), sizeof(DNode) * P.dec_rec.size()))) return rc;
     if ((rc = up(L.off_term, P.term.data(), sizeof(int32_t) * P.term.size()))) return rc;
     if ((rc = up(L.off_hc, P.hcards.data(), sizeof(uint16_t) * P.hcards.size()))) return rc;
     if ((rc = up(L.off_coff, P.coff.data(), sizeof(int32_t) * P.coff.size()))) return rc;
@@ -1863,6 +2044,15 @@ int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net) {
     }
     HIPCHK(hipStreamSynchronize(s->stream));
     s->net = net;
+    if (s->graph) { (void)hipGraphExecDestroy(s->graph); s->graph = nullptr; }
+    if (s->graph_def) { (void)hipGraphDestroy(s->graph_def); s->graph_def = nullptr; }
+    return build_graph(s);
+}
+
+int32_t pcfr_solver_set_leaf_zero_sum(pcfr_solver* s, int32_t on) {
+    if (!s || (on != 0 && on != 1)) { set_error("null solver or flag not 0/1"); return PCFR_E_INVALID_ARG; }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->leaf_zero_sum = on != 0;
     if (s->graph) { (void)hipGraphExecDestroy(s->graph); s->graph = nullptr; }
     if (s->graph_def) { (void)hipGraphDestroy(s->graph_def); s->graph_def = nullptr; }
     return build_graph(s);

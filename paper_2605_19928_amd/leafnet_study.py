@@ -4,9 +4,10 @@ solver generates, then measure what it gains.
     python -m paper_2605_19928_amd.leafnet_study --out result.json
 
 1. Data: ``--train`` random turn subgames (``inputs.leaf_training_config``:
-   Dirichlet(0.5-2) ranges, log-uniform pot and stack-to-pot ratio, {75}% +
-   all-in continuation) solved ``--iters`` iterations each by the batched GPU
-   solver; each gives one sample (normalised ranges, board, ratio -> values
+   Dirichlet(0.5-2) ranges, log-uniform pot and stack-to-pot ratio; bet
+   abstraction ``--train-sizes`` + all-in, ``--train-cap`` bets per street)
+   solved ``--iters`` iterations each by the batched GPU solver; each gives
+   one sample (normalised ranges, board, ratio -> values
    under the average strategies per pot and compatible opponent mass).  A
    disjoint held-out set (``--heldout``, another seed) is made the same way.
 2. Training: the library's bf16-MFMA forward/backward/Adam kernels on the
@@ -71,13 +72,16 @@ def flop_comparison(net, seed: int, iters: int, out: dict):
     spec, r = I.flop_config(seed)
     # depth-limited, network leaves
     tree = P.Tree(**spec)
-    dl = P.Solver(tree, r)
-    n_leaves, n_next = dl.leaf_rows()
-    dl.attach_leafnet(net)
-    t_dl = T._elapsed_ms(lambda: dl.iterate(iters), dl.stream) / iters
-    v_dl = dl.root_cfv("avg")
-    e_dl, _ = dl.exploitability()
-    dl.close()
+    dl_runs = {}
+    for zs in (True, False):
+        dl = P.Solver(tree, r)
+        n_leaves, n_next = dl.leaf_rows()
+        dl.attach_leafnet(net)
+        dl.set_leaf_zero_sum(zs)
+        t_dl = T._elapsed_ms(lambda: dl.iterate(iters), dl.stream) / iters
+        e_dl, _ = dl.exploitability()
+        dl_runs[zs] = (t_dl, dl.root_cfv("avg"), e_dl)
+        dl.close()
     # the same subgame with every leaf valued by check-down equity (no network)
     stub = P.Solver(tree, r)
     stub.iterate(iters)
@@ -99,16 +103,19 @@ def flop_comparison(net, seed: int, iters: int, out: dict):
     ex.close()
     del ex
     torch.cuda.empty_cache()
+    t_dl = dl_runs[True][0]
     out["flop"] = {
         "spec": {k: (list(v) if isinstance(v, tuple) else v) for k, v in spec.items()},
         "iterations": iters,
         "depth_limited": {"network_rows_per_iter": n_leaves * n_next, "ms_per_iter": t_dl,
-                          "exploitability_mbb_per_hand_within_depth_limited_game": e_dl * 100.0},
+                          "exploitability_mbb_per_hand_within_depth_limited_game":
+                              {"zero_sum_leaves": dl_runs[True][2] * 100.0, "raw_leaves": dl_runs[False][2] * 100.0}},
         "exact_to_showdown": {"nodes": tx.n_nodes, "action_rows": tx.n_rows, "ms_per_iter": t_ex,
                               "exploitability_mbb_per_hand": e_ex * 100.0},
         "speedup_per_iteration": t_ex / t_dl,
         "root_value_gap_mbb_per_hand": {
-            "trained_network_leaves_vs_exact": root_value_gap_mbb(v_dl, v_ex, r),
+            "trained_network_leaves_zero_sum_vs_exact": root_value_gap_mbb(dl_runs[True][1], v_ex, r),
+            "trained_network_leaves_raw_vs_exact": root_value_gap_mbb(dl_runs[False][1], v_ex, r),
             "checkdown_equity_leaves_vs_exact": root_value_gap_mbb(v_stub, v_ex, r),
         },
     }
@@ -126,6 +133,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--train-sizes", default="75", help="bet sizes (%% of pot) of the training subgames")
+    ap.add_argument("--train-cap", type=int, default=2, help="bets/raises per street in the training subgames")
     ap.add_argument("--flop", action="store_true")
     ap.add_argument("--flop-iters", type=int, default=300)
     ap.add_argument("--out", default="")
@@ -136,8 +145,10 @@ def main(argv=None):
            "network": f"{P.LEAF_D_IN} -> {args.depth} x {args.width} -> {P.LEAF_D_OUT} ReLU, bf16 MFMA",
            "steps": args.steps, "batch": args.batch, "lr": args.lr}
     t0 = time.perf_counter()
-    X, Y, M, _ = T.generate(seed=101, n=args.train, iters=args.iters, batch=args.gen_batch, log=log)
-    Xh, Yh, Mh, sh = T.generate(seed=202, n=args.heldout, iters=args.iters, batch=args.gen_batch, log=log)
+    cfg = dict(sizes=tuple(int(x) for x in args.train_sizes.split(",")), max_raises=args.train_cap)
+    res["train_abstraction"] = {"sizes_pct": list(cfg["sizes"]), "allin": True, "max_raises": cfg["max_raises"]}
+    X, Y, M, _ = T.generate(seed=101, n=args.train, iters=args.iters, batch=args.gen_batch, log=log, **cfg)
+    Xh, Yh, Mh, sh = T.generate(seed=202, n=args.heldout, iters=args.iters, batch=args.gen_batch, log=log, **cfg)
     res["generate_s"] = time.perf_counter() - t0
     net = P.LeafNet(P.LEAF_D_IN, args.width, args.depth, P.LEAF_D_OUT,
                     max_batch=max(args.batch, args.heldout, 1088))

@@ -65,6 +65,7 @@ _SIGS = {
     "pcfr_leafnet_train_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                             C.c_float, C.POINTER(C.c_float)]),
     "pcfr_solver_attach_leafnet": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pcfr_solver_set_leaf_zero_sum": (C.c_int32, [C.c_void_p, C.c_int32]),
     "pcfr_batch_workspace_bytes": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SolverCfg), C.POINTER(C.c_size_t)]),
     "pcfr_batch_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SolverCfg), C.c_void_p, C.c_void_p,
                                       C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -292,6 +293,10 @@ class Solver:
     def attach_leafnet(self, net: "LeafNet | None"):
         _check(lib().pcfr_solver_attach_leafnet(self._h, net._h if net is not None else None))
         self._net = net
+
+    def set_leaf_zero_sum(self, on: bool):
+        """Shift network leaf values to zero-sum per (leaf, next card) (default on)."""
+        _check(lib().pcfr_solver_set_leaf_zero_sum(self._h, 1 if on else 0))
 
     def leaf_rows(self):
         a, b = C.c_int32(), C.c_int32()

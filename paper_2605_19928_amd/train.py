@@ -52,8 +52,9 @@ def suit_permutations():
 
 
 def generate(seed: int, n: int, iters: int, batch: int = 64, dtype: str = "f32", device="cuda", log=None,
-             start: int = 0):
-    """Solve n random turn subgames; return device tensors X [n, 2705], Y and M [n, 2652]."""
+             start: int = 0, **config):
+    """Solve n random turn subgames (``inputs.leaf_training_config(seed, i, **config)``);
+    return device tensors X [n, 2705], Y and M [n, 2652] and the cases."""
     import torch
 
     X = torch.zeros((n, P.LEAF_D_IN), dtype=torch.float32, device=device)
@@ -62,7 +63,7 @@ def generate(seed: int, n: int, iters: int, batch: int = 64, dtype: str = "f32",
     specs = []
     t0 = time.perf_counter()
     for b0 in range(0, n, batch):
-        cases = [I.leaf_training_config(seed, start + i) for i in range(b0, min(n, b0 + batch))]
+        cases = [I.leaf_training_config(seed, start + i, **config) for i in range(b0, min(n, b0 + batch))]
         trees = [P.Tree(**s) for s, _ in cases]
         solver = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=dtype), device=device)
         solver.iterate(iters)

@@ -155,10 +155,11 @@ def test_flop_depth_limited_exact_leaves(dtype, T):
             assert np.abs(gs.strategy(int(n)) - os_.strategy(int(n)))[:, ok].max() <= 1e-9
 
 
-def test_flop_depth_limited_network_leaves():
+@pytest.mark.parametrize("zero_sum", [True, False])
+def test_flop_depth_limited_network_leaves(zero_sum):
     import torch
     spec, r = flop_case(support=120, seed=1)
-    say(f"case: flop depth-limited, network leaves, {spec}")
+    say(f"case: flop depth-limited, network leaves, zero-sum correction {zero_sum}, {spec}")
     rng = np.random.default_rng(9)
     gt = P.Tree(**spec)
     gs = P.Solver(gt, r, P.SolverConfig(dtype="f64"))
@@ -168,6 +169,7 @@ def test_flop_depth_limited_network_leaves():
     params = rand_params(rng, net.layer_shapes(), scale=2.0)
     net.set_params(params)
     gs.attach_leafnet(net)
+    gs.set_leaf_zero_sum(zero_sum)
     ot = O.Tree.holdem(**spec)
     os_ = O.Solver(ot, r)
     e = ot.export()
@@ -183,8 +185,11 @@ def test_flop_depth_limited_network_leaves():
                                        d_in=P.LEAF_D_IN)
             Y = mlp.forward(params, X, emulate_bf16=True)
             for k, card in enumerate(cards):
-                ev[li, 0, card] = Y[k, :1326]
-                ev[li, 1, card] = Y[k, 1326:]
+                row = np.stack([Y[k, :1326], Y[k, 1326:]])
+                if zero_sum:
+                    row = row - mlp.zero_sum_shift(row, reach[n], card)
+                ev[li, 0, card] = row[0]
+                ev[li, 1, card] = row[1]
         os_.set_leaf_table(ev)
         os_.iterate(1)
         gs.iterate(1)

@@ -93,3 +93,39 @@ def test_leaf_inputs_structure():
         hot = X[k, 2652:2704]
         assert hot.sum() == 4 and hot[c] == 1 and all(hot[b] == 1 for b in board)
         assert X[k, 2704] == 2.5
+
+
+def test_compatible_mass_brute_force():
+    """M(h | c) against an explicit loop over opponent combos (sparse ranges)."""
+    rng = np.random.default_rng(5)
+    cc = mlp.combo_cards()
+    r = np.zeros(1326)
+    sup = rng.choice(1326, 40, replace=False)
+    r[sup] = rng.random(40)
+    card = 17
+    m = mlp.compatible_mass(r, card)
+    for h in rng.choice(1326, 60, replace=False):
+        want = sum(r[o] for o in sup
+                   if len({cc[h, 0], cc[h, 1], cc[o, 0], cc[o, 1]}) == 4 and card not in (cc[o, 0], cc[o, 1]))
+        assert abs(m[h] - want) < 1e-12
+
+
+def test_zero_sum_shift_closed_forms():
+    """Constant outputs a, b shift by (a + b) / 2 (the two joint masses are
+    equal); after any shift the weighted values of both players cancel."""
+    rng = np.random.default_rng(6)
+    cc = mlp.combo_cards()
+    board = [3, 20, 41]
+    ok = ~np.isin(cc, board).any(axis=1)
+    reach = np.zeros((2, 1326))
+    reach[:, ok] = rng.random((2, ok.sum()))
+    card = 9
+    ev = np.stack([np.full(1326, 0.3), np.full(1326, -0.1)])
+    assert abs(mlp.zero_sum_shift(ev, reach, card) - 0.1) < 1e-12
+    ev = rng.standard_normal((2, 1326))
+    d = mlp.zero_sum_shift(ev, reach, card)
+    keep = (cc[:, 0] != card) & (cc[:, 1] != card)
+    m1 = mlp.compatible_mass(reach[1], card)
+    m0 = mlp.compatible_mass(reach[0], card)
+    total = ((reach[0] * keep) * m1 * (ev[0] - d)).sum() + ((reach[1] * keep) * m0 * (ev[1] - d)).sum()
+    assert abs(total) < 1e-9 * ((reach[0] * m1).sum())
