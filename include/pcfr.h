@@ -218,7 +218,12 @@ int32_t pcfr_batch_get_root_cfv(pcfr_solver* s, int32_t sub, int32_t which, doub
 int32_t pcfr_batch_exploitability(pcfr_solver* s, double* chips_per_hand, double* br);
 
 /* Launch-schedule autotuner for a solver or batch that has not iterated yet
- * (else PCFR_E_STATE).  Each level's forward and backward sweep launch is
+ * (else PCFR_E_STATE).  First the level-fusion threshold: runs of
+ * consecutive levels with at most that many threads (nodes x padded hands /
+ * 4) are swept by one launch in which each workgroup owns a slice of hands
+ * and steps through the levels with workgroup barriers (candidates 0, 4096,
+ * 16384 (the default), 65536, 262144; whole-iteration replays decide).  Then
+ * each remaining level's forward and backward launch is
  * timed at workgroup sizes 64, 128, 256 and 512 over reps >= 1 iterations;
  * the fastest size per launch is kept, cached for the launch's size bucket
  * (phase, dtype, action-count bucket, log2 of its thread count) so that

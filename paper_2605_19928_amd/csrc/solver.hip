@@ -80,6 +80,7 @@ constexpr int kSweepMaxBlock = 512;
 constexpr int kSdHeader = 64;     // card-list offsets per board table (53 used)
 
 // ------------------------------------------------------------ vector I/O
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 template <typename T> struct V4 { T e[4]; };
 
 __device__ __forceinline__ V4<float> ld4(const float* p) {
@@ -204,19 +205,29 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restr
 }
 
 // ------------------------------------------------------------ backward
-template <typename T, int MODE, int A>
+// EARLY: load the average-strategy rows and own reach together with the
+// regrets (more registers, one memory round trip less on the critical path;
+// used where latency, not occupancy, limits).
+template <typename T, int MODE, int A, bool EARLY = false>
 __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
                                              T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
                                              T* __restrict__ cfv, const IterState* st,
                                              const uint16_t* __restrict__ hcards, T* __restrict__ root_dst) {
     const int p = nd.player, o = 1 - p;
     V4<T> x[A];
+    V4<T> s_early[EARLY && MODE == MODE_ITER ? A : 1];
+    V4<T> rp_early;
     T den[4] = {T(0), T(0), T(0), T(0)};
     const T inv_a = T(1) / T(A);
     if (MODE != MODE_BR) {
         const T* src = (MODE == MODE_ITER ? (const T*)R : S) + (int64_t)nd.rs * Hp + h;
 #pragma unroll
         for (int a = 0; a < A; a++) x[a] = ld4(src + (int64_t)a * Hp);
+        if constexpr (EARLY && MODE == MODE_ITER) {
+#pragma unroll
+            for (int a = 0; a < A; a++) s_early[a] = ld4(S + (int64_t)(nd.rs + a) * Hp + h);
+            rp_early = ld4(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
+        }
         if (MODE == MODE_ITER && Mp) {
             // the strategy of this iteration matched R + m; R itself is read again below
 #pragma unroll
@@ -260,7 +271,9 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         // average-strategy sum (Stage 1's accumulation, done here so that one
         // pass reads and writes both tables), each with its DCFR discount.
         const T dpos = (T)st->dpos, dneg = (T)st->dneg, wadd = (T)st->wadd, wmul = (T)st->wmul;
-        V4<T> rp = ld4(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
+        V4<T> rp;
+        if constexpr (EARLY) rp = rp_early;
+        else rp = ld4(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
         if (nd.dead != 0xffff) {
             const uint16_t* hc = hcards + (int64_t)nd.sub * Hp + h;
 #pragma unroll
@@ -271,7 +284,9 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         for (int a = 0; a < A; a++) {
             T* sp = S + (int64_t)(nd.rs + a) * Hp + h;
             T* rptr = R + (int64_t)(nd.rs + a) * Hp + h;
-            V4<T> sv = ld4(sp);
+            V4<T> sv;
+            if constexpr (EARLY) sv = s_early[a];
+            else sv = ld4(sp);
             const V4<T> r0 = Mp ? ld4(rptr) : x[a];
             V4<T> y, inst;
 #pragma unroll
@@ -288,22 +303,12 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
     }
 }
 
-// One thread per (node, 4 hands) of a level, decision and chance nodes.
-// root_dst (the last launch of an iteration only) also receives each root's
-// values, which later evaluation sweeps do not overwrite.
-template <typename T, int MODE, int MAXA>
-__global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __restrict__ level, int count, int Hp,
-                                                             T* __restrict__ R, T* __restrict__ S, T* __restrict__ Mp,
-                                                             const T* __restrict__ reach, T* __restrict__ cfv,
-                                                             const IterState* __restrict__ st,
-                                                             const uint16_t* __restrict__ hcards,
-                                                             T* __restrict__ root_dst) {
-    const int groups = Hp >> 2;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t k = gid / groups;
-    if (k >= count) return;
-    const int h = (int)(gid - k * groups) * 4;
-    const DNode nd = level[k];
+// Backward work of one node (decision or chance) for 4 hands.
+template <typename T, int MODE, int MAXA, bool EARLY = false>
+__device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __restrict__ R, T* __restrict__ S,
+                                         T* __restrict__ Mp, const T* __restrict__ reach, T* __restrict__ cfv,
+                                         const IterState* __restrict__ st, const uint16_t* __restrict__ hcards,
+                                         T* __restrict__ root_dst) {
     const int64_t n = nd.id;
     if (nd.type == PCFR_NODE_CHANCE) {
         // children in groups of 4: all loads of a group are issued before the
@@ -339,12 +344,100 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
     switch (nd.n_child) {
 #define PCFR_BWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) bwd_decision<T, MODE, A>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst); \
+        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, EARLY>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst); \
         break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
 #undef PCFR_BWD_CASE
         default: break;
+    }
+}
+
+// One thread per (node, 4 hands) of a level, decision and chance nodes.
+// root_dst (the last launch of an iteration only) also receives each root's
+// values, which later evaluation sweeps do not overwrite.
+template <typename T, int MODE, int MAXA>
+__global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __restrict__ level, int count, int Hp,
+                                                             T* __restrict__ R, T* __restrict__ S, T* __restrict__ Mp,
+                                                             const T* __restrict__ reach, T* __restrict__ cfv,
+                                                             const IterState* __restrict__ st,
+                                                             const uint16_t* __restrict__ hcards,
+                                                             T* __restrict__ root_dst) {
+    const int groups = Hp >> 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = gid / groups;
+    if (k >= count) return;
+    bwd_node<T, MODE, MAXA>(level[k], (int)(gid - k * groups) * 4, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst);
+}
+
+// Level-fused sweeps for runs of levels too small to fill the GPU.  A node's
+// reach at hand h depends only on its parent's at h, and its values at h only
+// on its children's at h, so a workgroup that owns a slice of kFuseHands
+// hands can run consecutive levels for that slice with workgroup barriers
+// in between: one launch instead of one per level.  Each workgroup has 16
+// hand groups of 4 hands times 16 node lanes; lvl_off holds the level starts
+// in the record list.
+constexpr int kFuseHands = 64;
+constexpr int kFuseRec = 256;     // node records staged in LDS per fused launch (else read from memory)
+
+// Copy n node records to LDS when they fit; every thread returns the same answer.
+__device__ __forceinline__ bool stage_records(DNode* dst, const DNode* __restrict__ src, int64_t n) {
+    if (n > kFuseRec) return false;
+    const int words = (int)n * (int)(sizeof(DNode) / 16);
+    for (int i = threadIdx.x; i < words; i += blockDim.x)
+        reinterpret_cast<u32x4*>(dst)[i] = reinterpret_cast<const u32x4*>(src)[i];
+    __syncthreads();
+    return true;
+}
+
+template <typename T, int MODE, int MAXA>
+__global__ __launch_bounds__(256) void k_forward_fused(const DNode* __restrict__ rec,
+                                                       const int64_t* __restrict__ lvl_off, int l0, int l1, int Hp,
+                                                       int cbase, const T* __restrict__ R, const T* __restrict__ S,
+                                                       const T* __restrict__ Mp, T* __restrict__ reach,
+                                                       IterState* begin) {
+    __shared__ DNode srec[kFuseRec];
+    const int64_t r0 = lvl_off[l0], nrec = lvl_off[l1] - r0;
+    const bool staged = stage_records(srec, rec + r0, nrec);
+    if (begin && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin);
+    const int h = blockIdx.x * kFuseHands + (threadIdx.x & 15) * 4, lane = threadIdx.x >> 4;
+    for (int l = l0; l < l1; l++) {
+        if (l > l0) __syncthreads();
+        const int64_t e = lvl_off[l + 1];
+        for (int64_t k = lvl_off[l] + lane; k < e; k += 16) {
+            const DNode nd = staged ? srec[k - r0] : rec[k];
+            switch (nd.n_child) {
+#define PCFR_FWD_CASE(A) \
+    case A:              \
+        if constexpr (A <= MAXA) fwd_decision<T, MODE, A>(nd, h, Hp, cbase, R, S, Mp, reach); \
+        break;
+                PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
+                PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
+#undef PCFR_FWD_CASE
+                default: break;
+            }
+        }
+    }
+}
+
+// Levels l_hi - 1 down to l_lo; root_dst as in k_backward (used when l_lo is 0).
+template <typename T, int MODE, int MAXA>
+__global__ __launch_bounds__(256) void k_backward_fused(const DNode* __restrict__ rec,
+                                                        const int64_t* __restrict__ lvl_off, int l_lo, int l_hi,
+                                                        int Hp, T* __restrict__ R, T* __restrict__ S,
+                                                        T* __restrict__ Mp, const T* __restrict__ reach,
+                                                        T* __restrict__ cfv, const IterState* __restrict__ st,
+                                                        const uint16_t* __restrict__ hcards, T* __restrict__ root_dst) {
+    __shared__ DNode srec[kFuseRec];
+    const int64_t r0 = lvl_off[l_lo], nrec = lvl_off[l_hi] - r0;
+    const bool staged = stage_records(srec, rec + r0, nrec);
+    const int h = blockIdx.x * kFuseHands + (threadIdx.x & 15) * 4, lane = threadIdx.x >> 4;
+    for (int l = l_hi - 1; l >= l_lo; l--) {
+        if (l < l_hi - 1) __syncthreads();
+        const int64_t e = lvl_off[l + 1];
+        for (int64_t k = lvl_off[l] + lane; k < e; k += 16)
+            bwd_node<T, MODE, MAXA, true>(staged ? srec[k - r0] : rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
+                                          l == 0 ? root_dst : nullptr);
     }
 }
 
@@ -356,7 +449,6 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
 constexpr int kMaxHp = 1216;                          // flop: 1176 compatible combos padded to 64
 constexpr int kHandIt = (kMaxHp + kBlock - 1) / kBlock;
 constexpr int kWaves = kBlock / 64;
-typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
 // Copy n int16 values (n a multiple of 8, both pointers 16-byte aligned) to LDS.
 template <int MAXV>
@@ -713,39 +805,84 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// Stage a leaf's reach (both players) in LDS x[2][kMaxHp]; per-card sums of
+// each player in cs[2][52] and the totals, all in A (the accumulation type).
+template <typename T, typename A>
+__device__ __forceinline__ void stage_leaf(const T* __restrict__ r0, const T* __restrict__ r1, int Hp,
+                                           const int32_t* __restrict__ coff, const int16_t* __restrict__ chands,
+                                           T (*x)[kMaxHp], A (*cs)[52], A* xch, A& t0, A& t1) {
+    const int tid = threadIdx.x;
+    T a[kHandIt], b[kHandIt];
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h < Hp) { a[i] = r0[h]; b[i] = r1[h]; }
+    }
+    t0 = A(0);
+    t1 = A(0);
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h < Hp) { x[0][h] = a[i]; x[1][h] = b[i]; t0 += (A)a[i]; t1 += (A)b[i]; }
+    }
+    __syncthreads();
+    if (tid < 104) {
+        const int p = tid / 52, c = tid - p * 52;
+        A acc = A(0);
+        for (int j = coff[c]; j < coff[c + 1]; j++) acc += (A)x[p][chands[j]];
+        cs[p][c] = acc;
+    }
+    block_sum2(t0, t1, xch);      // synchronises: cs is visible after it
+}
+
+// Per-leaf reach aggregates shared by the leaf-row kernels, once per leaf:
+// agg[leaf] = [2][53], each player's 52 per-card sums (reach of the hands
+// holding the card) then the total.
+constexpr int kAgg = 106;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_leaf_agg(const DNode* __restrict__ nodes, const int32_t* __restrict__ leaves,
+                                                     int Hp, const T* __restrict__ reach,
+                                                     const int32_t* __restrict__ coff,
+                                                     const int16_t* __restrict__ chands, T* __restrict__ agg) {
+    __shared__ T x[2][kMaxHp];
+    __shared__ T cs[2][52];
+    __shared__ T xch[2 * kWaves];
+    const int li = blockIdx.x;
+    const DNode nd = nodes[leaves[li]];
+    T t0, t1;
+    stage_leaf<T, T>(reach + (int64_t)nd.slot[0] * Hp, reach + (int64_t)nd.slot[1] * Hp, Hp, coff, chands, x, cs, xch,
+                     t0, t1);
+    T* out = agg + (int64_t)li * kAgg;
+    const int tid = threadIdx.x;
+    if (tid < 104) out[(tid / 52) * 53 + tid % 52] = cs[tid / 52][tid % 52];
+    if (tid == 0) { out[52] = t0; out[105] = t1; }
+}
+
 // Stage 2's batched leaf input (Sec. 4.2): one row per (leaf, next card c):
 // each player's reach with the hands holding c removed, normalised to sum 1,
 // over the 1326 combos; then the board after c as 52 one-hot entries; then
-// the stack-to-pot ratio at the leaf; bf16, zero padded to ldx.
+// the stack-to-pot ratio at the leaf; bf16, zero padded to ldx.  The
+// normaliser is the leaf total minus the per-card sum of c.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__ nodes,
                                                        const int32_t* __restrict__ leaves, const float* __restrict__ spr,
-                                                       int n_next, const int8_t* __restrict__ next_cards, int Hp, int H,
-                                                       const T* __restrict__ reach, const uint16_t* __restrict__ hcards,
+                                                       int n_next, const int8_t* __restrict__ next_cards, int Hp,
+                                                       const T* __restrict__ reach, const T* __restrict__ agg,
+                                                       const uint16_t* __restrict__ hcards,
                                                        const int16_t* __restrict__ combo_hand,
                                                        const uint8_t* __restrict__ board_hot, uint16_t* __restrict__ X,
                                                        int ldx) {
-    __shared__ double red[2][kBlock];
     const int q = blockIdx.x;
     const int li = q / n_next, k = q - li * n_next;
     const int c = next_cards[k];
     const DNode nd = nodes[leaves[li]];
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
-    const int tid = threadIdx.x;
-    double s0 = 0.0, s1 = 0.0;
-    for (int h = tid; h < H; h += kBlock)
-        if (!has_card(hcards[h], c)) { s0 += (double)r0[h]; s1 += (double)r1[h]; }
-    red[0][tid] = s0;
-    red[1][tid] = s1;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
-        __syncthreads();
-    }
-    const double S0 = red[0][0], S1 = red[1][0];
+    const T* ag = agg + (int64_t)li * kAgg;
+    const double S0 = (double)ag[52] - (double)ag[c], S1 = (double)ag[105] - (double)ag[53 + c];
     uint16_t* row = X + (int64_t)q * ldx;
-    for (int col = tid; col < ldx; col += kBlock) {
+    for (int col = threadIdx.x; col < ldx; col += kBlock) {
         float v = 0.f;
         if (col < 2 * kCombos) {
             const int p = col >= kCombos;
@@ -773,15 +910,12 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_leaf_zerosum(const DNode* __restrict__ nodes,
                                                          const int32_t* __restrict__ leaves, int n_next,
                                                          const int8_t* __restrict__ next_cards, int Hp, int H,
-                                                         const T* __restrict__ reach,
+                                                         const T* __restrict__ reach, const T* __restrict__ agg,
                                                          const uint16_t* __restrict__ hcards,
                                                          const int16_t* __restrict__ hand_combo,
                                                          const int16_t* __restrict__ combo_hand,
-                                                         const int32_t* __restrict__ coff,
-                                                         const int16_t* __restrict__ chands,
                                                          const float* __restrict__ Y, int ldy, T* __restrict__ delta) {
-    __shared__ T x[2][kMaxHp];
-    __shared__ T cs[2][52];
+    __shared__ T ag[kAgg];
     __shared__ T xch[2 * kWaves];
     const int row = blockIdx.x, li = row / n_next, k = row - li * n_next;
     const int c = next_cards[k];
@@ -789,22 +923,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_zerosum(const DNode* __restrict
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
-    T s0 = T(0), s1 = T(0);
-    for (int h = tid; h < Hp; h += kBlock) {
-        const T a = r0[h], b = r1[h];
-        x[0][h] = a;
-        x[1][h] = b;
-        s0 += a;
-        s1 += b;
-    }
+    if (tid < kAgg) ag[tid] = agg[(int64_t)li * kAgg + tid];
     __syncthreads();
-    if (tid < 104) {
-        const int p = tid / 52, cd = tid - p * 52;
-        T acc = T(0);
-        for (int j = coff[cd]; j < coff[cd + 1]; j++) acc += x[p][chands[j]];
-        cs[p][cd] = acc;
-    }
-    block_sum2(s0, s1, xch);      // synchronises: cs is visible after it
+    const T s0 = ag[52] - ag[c], s1 = ag[105] - ag[53 + c];     // totals without the hands holding c
     const float* y = Y + (int64_t)row * ldy;
     T e = T(0), z = T(0);
     for (int h = tid; h < H; h += kBlock) {
@@ -812,15 +933,13 @@ __global__ __launch_bounds__(kBlock) void k_leaf_zerosum(const DNode* __restrict
         const int a = hc & 0xff, b = hc >> 8;
         if (a == c || b == c) continue;
         const int ha = combo_hand[combo_index(a, c)], hb = combo_hand[combo_index(b, c)];
-        const T m1 = s1 - cs[1][a] - cs[1][b] - cs[1][c] + x[1][h] + (ha >= 0 ? x[1][ha] : T(0)) +
-                     (hb >= 0 ? x[1][hb] : T(0));
-        const T m0 = s0 - cs[0][a] - cs[0][b] - cs[0][c] + x[0][h] + (ha >= 0 ? x[0][ha] : T(0)) +
-                     (hb >= 0 ? x[0][hb] : T(0));
+        const T x0 = r0[h], x1 = r1[h];
+        const T m1 = s1 - ag[53 + a] - ag[53 + b] + x1 + (ha >= 0 ? r1[ha] : T(0)) + (hb >= 0 ? r1[hb] : T(0));
+        const T m0 = s0 - ag[a] - ag[b] + x0 + (ha >= 0 ? r0[ha] : T(0)) + (hb >= 0 ? r0[hb] : T(0));
         const int combo = hand_combo[h];
-        e += x[0][h] * m1 * (T)y[combo] + x[1][h] * m0 * (T)y[kCombos + combo];
-        z += x[0][h] * m1;
+        e += x0 * m1 * (T)y[combo] + x1 * m0 * (T)y[kCombos + combo];
+        z += x0 * m1;
     }
-    __syncthreads();              // xch is reused
     block_sum2(e, z, xch);
     if (tid == 0) delta[row] = z > T(0) ? e / (T(2) * z) : T(0);
 }
@@ -844,9 +963,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
                                                          const int32_t* __restrict__ coff,
                                                          const int16_t* __restrict__ chands,
                                                          const float* __restrict__ Y, int ldy,
-                                                         const T* __restrict__ delta) {
+                                                         const T* __restrict__ agg, const T* __restrict__ delta) {
     __shared__ T x[2][kMaxHp];
-    __shared__ int16_t c2h[kCombos];
+    __shared__ __align__(16) int16_t c2h[kCombos];
     __shared__ int8_t nxt[52];
     __shared__ T dl[52];
     __shared__ T cs[2][52];
@@ -857,33 +976,29 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
-    T s0 = T(0), s1 = T(0);
-    for (int h = tid; h < Hp; h += kBlock) {
-        const T a = r0[h], b = r1[h];
-        x[0][h] = a;
-        x[1][h] = b;
-        s0 += a;
-        s1 += b;
+    {
+        T a[kHandIt], b[kHandIt];
+#pragma unroll
+        for (int i = 0; i < kHandIt; i++) {
+            const int h = tid + i * kBlock;
+            if (h < Hp) { a[i] = r0[h]; b[i] = r1[h]; }
+        }
+#pragma unroll
+        for (int i = 0; i < kHandIt; i++) {
+            const int h = tid + i * kBlock;
+            if (h < Hp) { x[0][h] = a[i]; x[1][h] = b[i]; }
+        }
     }
-    for (int k = tid; k < kCombos; k += kBlock) c2h[k] = combo_hand[k];
+    copy_i16<(kCombos + 7) / 8 / kBlock + 1>(c2h, combo_hand, kCombos / 8 * 8);
+    if (tid < kCombos - kCombos / 8 * 8) c2h[kCombos / 8 * 8 + tid] = combo_hand[kCombos / 8 * 8 + tid];
     if (tid < n_next) {
         nxt[tid] = next_cards[tid];
         dl[tid] = delta ? delta[li * n_next + tid] : T(0);
     }
-    red[0][tid] = s0;
-    red[1][tid] = s1;
+    const T* ag = agg + (int64_t)li * kAgg;
+    if (tid < 104) cs[tid / 52][tid % 52] = ag[(tid / 52) * 53 + tid % 52];
+    const T t0 = ag[52], t1 = ag[105];
     __syncthreads();
-    if (tid < 104) {
-        const int p = tid / 52, c = tid - p * 52;
-        T acc = T(0);
-        for (int j = coff[c]; j < coff[c + 1]; j++) acc += x[p][chands[j]];
-        cs[p][c] = acc;
-    }
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
-        __syncthreads();
-    }
-    const T t0 = red[0][0], t1 = red[1][0];
     __syncthreads();   // red is reused for the partial sums below
     const int lane = tid & 63, grp = tid >> 6;
     const int h = blockIdx.y * 64 + lane;
@@ -1044,9 +1159,9 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Plan {
     int64_t N, rows, Hp, H, n_boards, term, fwd, dec, slots, chand_stride, sd_stride, n_eq, n_net, n_next;
     size_t esz;
-    size_t off_nodes, off_fwd, off_dec, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
+    size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_zs, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
+        off_potk, off_zs, off_agg, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
     size_t lds_bytes, lds_fold, lds_show;
 };
 
@@ -1352,6 +1467,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_nodes = take(sizeof(DNode) * L.N);
     L.off_fwd = take(sizeof(DNode) * std::max<int64_t>(L.fwd, 1));
     L.off_dec = take(sizeof(DNode) * std::max<int64_t>(L.dec, 1));
+    L.off_fwdoff = take(sizeof(int64_t) * (P.levels + 1));
+    L.off_decoff = take(sizeof(int64_t) * (P.levels + 1));
     L.off_term = take(sizeof(int32_t) * std::max<int64_t>(L.term, 1));
     L.off_hc = take(sizeof(uint16_t) * L.Hp * P.n_sub);
     L.off_coff = take(sizeof(int32_t) * 53 * P.n_sub);
@@ -1375,6 +1492,7 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_spr = take(sizeof(float) * std::max<int64_t>(L.n_net, 1));
     L.off_potk = take(sizeof(double) * std::max<int64_t>(L.n_net, 1));
     L.off_zs = take(L.esz * std::max<int64_t>(L.n_net * L.n_next, 1));
+    L.off_agg = take(L.esz * kAgg * std::max<int64_t>(L.n_net, 1));
     L.off_next = take(64);
     L.off_hot = take(64);
     L.off_c2h = take(sizeof(int16_t) * kCombos);
@@ -1403,6 +1521,9 @@ namespace pcfr {
 // gives bitwise the same iterates.
 struct Sched {
     std::vector<int> fwd_block, bwd_block;
+    // runs of consecutive levels with at most this many threads (nodes x
+    // Hp/4) each are swept by one level-fused launch; 0 = never
+    int64_t fuse_threads = 16384;
 };
 }  // namespace pcfr
 
@@ -1452,10 +1573,31 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     } while (0)
     // forward: decision nodes only; the first launch of an iteration also
     // advances t and sets the Stage-7 coefficients
+#define PCFR_BUCKET_MA(KER, ma, ...)                                                                  \
+    do {                                                                                              \
+        if ((ma) <= 3) hipLaunchKernelGGL((KER<T, MODE, 3>), __VA_ARGS__);                            \
+        else if ((ma) <= 6) hipLaunchKernelGGL((KER<T, MODE, 6>), __VA_ARGS__);                       \
+        else hipLaunchKernelGGL((KER<T, MODE, 12>), __VA_ARGS__);                                     \
+    } while (0)
+    const int64_t fuse = s->sched.fuse_threads;
+    const dim3 fgrid((unsigned)(Hp / kFuseHands));
+    auto dec_cnt = [&](int l) { return P.dec_off[l + 1] - P.dec_off[l]; };
+    auto all_cnt = [&](int l) { return P.fwd_off[l + 1] - P.fwd_off[l]; };
     bool first = MODE == MODE_ITER;
-    for (int l = 0; l < P.levels; l++) {
-        const int64_t cnt = P.dec_off[l + 1] - P.dec_off[l];
-        if (!cnt) continue;
+    for (int l = 0; l < P.levels;) {
+        const int64_t cnt = dec_cnt(l);
+        if (!cnt) { l++; continue; }
+        if (cnt * groups <= fuse) {
+            int l1 = l + 1, ma = P.lvl_maxa[l];
+            while (l1 < P.levels && dec_cnt(l1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[l1++]);
+            if (tm) tm->before(1);
+            PCFR_BUCKET_MA(k_forward_fused, ma, fgrid, dim3(256), 0, stream, dec, s->at<int64_t>(L.off_decoff), l,
+                           l1, Hp, (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr);
+            if (tm) tm->after();
+            first = false;
+            l = l1;
+            continue;
+        }
         const int bs = s->sched.fwd_block[l];
         const int64_t threads = cnt * groups;
         dim3 grid((unsigned)((threads + bs - 1) / bs));
@@ -1464,6 +1606,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                     (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr);
         if (tm) tm->after();
         first = false;
+        l++;
     }
     // terminals: folds and showdowns in separate launches, each with the LDS it needs
     const int64_t n_fold = (int64_t)P.folds.size(), n_show = (int64_t)P.shows.size();
@@ -1497,9 +1640,13 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         pcfr_leafnet* net = s->net;
         const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes, s->at<int32_t>(L.off_net),
-                           s->at<float>(L.off_spr), (int)L.n_next, s->at<int8_t>(L.off_next), Hp, (int)L.H, reach,
-                           s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_c2h), s->at<uint8_t>(L.off_hot),
+        hipLaunchKernelGGL((k_leaf_agg<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream, nodes,
+                           s->at<int32_t>(L.off_net), Hp, reach, s->at<int32_t>(L.off_coff),
+                           s->at<int16_t>(L.off_chands), s->at<T>(L.off_agg));
+        hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes,
+                           s->at<int32_t>(L.off_net), s->at<float>(L.off_spr), (int)L.n_next,
+                           s->at<int8_t>(L.off_next), Hp, reach, s->at<T>(L.off_agg), s->at<uint16_t>(L.off_hc),
+                           s->at<int16_t>(L.off_c2h), s->at<uint8_t>(L.off_hot),
                            reinterpret_cast<uint16_t*>(net->ws + net->P.off_x), (int)net->P.pdims[0]);
         if (tm) tm->after();
         int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
@@ -1508,8 +1655,8 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             if (tm) tm->before(4);
             hipLaunchKernelGGL((k_leaf_zerosum<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes,
                                s->at<int32_t>(L.off_net), (int)L.n_next, s->at<int8_t>(L.off_next), Hp, (int)L.H,
-                               reach, s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_h2c),
-                               s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
+                               reach, s->at<T>(L.off_agg), s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_h2c),
+                               s->at<int16_t>(L.off_c2h),
                                reinterpret_cast<const float*>(net->ws + net->P.off_y), (int)net->P.pdims[net->P.L],
                                s->at<T>(L.off_zs));
             if (tm) tm->after();
@@ -1521,14 +1668,26 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->at<int8_t>(L.off_next), Hp, (int)L.H, reach, cfv, s->at<uint16_t>(L.off_hc),
                            s->at<int16_t>(L.off_h2c), s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff),
                            s->at<int16_t>(L.off_chands), reinterpret_cast<const float*>(net->ws + net->P.off_y),
-                           (int)net->P.pdims[net->P.L], s->leaf_zero_sum ? s->at<T>(L.off_zs) : nullptr);
+                           (int)net->P.pdims[net->P.L], s->at<T>(L.off_agg),
+                           s->leaf_zero_sum ? s->at<T>(L.off_zs) : nullptr);
         if (tm) tm->after();
     }
     // backward; level 0 holds exactly the roots, whose values of this
     // iteration are also kept apart from later evaluation sweeps
-    for (int l = P.levels - 1; l >= 0; l--) {
-        const int64_t cnt = P.fwd_off[l + 1] - P.fwd_off[l];
-        if (!cnt) continue;
+    for (int l = P.levels - 1; l >= 0;) {
+        const int64_t cnt = all_cnt(l);
+        if (!cnt) { l--; continue; }
+        if (cnt * groups <= fuse) {
+            int l0 = l, ma = P.lvl_maxa[l];
+            while (l0 > 0 && all_cnt(l0 - 1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[--l0]);
+            if (tm) tm->before(3);
+            PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(256), 0, stream, fwd, s->at<int64_t>(L.off_fwdoff), l0,
+                           l + 1, Hp, R, S, Mp, reach, cfv, st, s->at<uint16_t>(L.off_hc),
+                           (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr);
+            if (tm) tm->after();
+            l = l0 - 1;
+            continue;
+        }
         const int bs = s->sched.bwd_block[l];
         const int64_t threads = cnt * groups;
         dim3 grid((unsigned)((threads + bs - 1) / bs));
@@ -1537,7 +1696,9 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                     reach, cfv, st, s->at<uint16_t>(L.off_hc),
                     (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr);
         if (tm) tm->after();
+        l--;
     }
+#undef PCFR_BUCKET_MA
 #undef PCFR_BUCKET
     return hip_check(hipGetLastError(), "kernel launch");
 }
@@ -1731,6 +1892,8 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     if ((rc = up(L.off_nodes, P.nodes.data(), sizeof(DNode) * P.nodes.size()))) return rc;
     if ((rc = up(L.off_fwd, P.fwd_rec.data(), sizeof(DNode) * P.fwd_rec.size()))) return rc;
     if ((rc = up(L.off_dec, P.dec_rec.data(), sizeof(DNode) * P.dec_rec.size()))) return rc;
+    if ((rc = up(L.off_fwdoff, P.fwd_off.data(), sizeof(int64_t) * P.fwd_off.size()))) return rc;
+    if ((rc = up(L.off_decoff, P.dec_off.data(), sizeof(int64_t) * P.dec_off.size()))) return rc;
     if ((rc = up(L.off_term, P.term.data(), sizeof(int32_t) * P.term.size()))) return rc;
     if ((rc = up(L.off_hc, P.hcards.data(), sizeof(uint16_t) * P.hcards.size()))) return rc;
     if ((rc = up(L.off_coff, P.coff.data(), sizeof(int32_t) * P.coff.size()))) return rc;
@@ -1896,6 +2059,12 @@ static int32_t exploitability_impl(pcfr_solver* s, double* chips, double* br) {
     return PCFR_OK;
 }
 
+static int32_t rebuild_graph(pcfr_solver* s) {
+    if (s->graph) { (void)hipGraphExecDestroy(s->graph); s->graph = nullptr; }
+    if (s->graph_def) { (void)hipGraphDestroy(s->graph_def); s->graph_def = nullptr; }
+    return build_graph(s);
+}
+
 // Zero the iterate (t, R, S, m, stored root values): the state of a new solver.
 static int32_t reset_state(pcfr_solver* s) {
     const Plan& L = s->L;
@@ -1946,6 +2115,19 @@ static int32_t autotune_impl(pcfr_solver* s, int32_t reps, double* ms_before, do
     if (t != 0 || s->t_host != 0) { set_error("autotune needs a solver that has not iterated yet"); return PCFR_E_STATE; }
     int32_t rc = time_replays(s, reps, ms_before);
     if (rc) return rc;
+    // level fusion threshold, by whole-iteration replays
+    {
+        const int64_t fcand[5] = {0, 4096, 16384, 65536, 262144};
+        double best = 1e30;
+        int64_t pick = s->sched.fuse_threads;
+        for (int64_t f : fcand) {
+            s->sched.fuse_threads = f;
+            double ms = 0;
+            if ((rc = rebuild_graph(s)) || (rc = time_replays(s, reps, &ms))) return rc;
+            if (ms < best) { best = ms; pick = f; }
+        }
+        s->sched.fuse_threads = pick;
+    }
     const int levels = s->P.levels;
     const int cand[4] = {64, 128, 256, 512};
     std::vector<double> best_f(levels, 1e30), best_b(levels, 1e30);
@@ -1973,8 +2155,8 @@ static int32_t autotune_impl(pcfr_solver* s, int32_t reps, double* ms_before, do
             HIPCHK(e);
         }
         for (int l = 0; l < levels; l++) {
-            if (tf[l] < best_f[l]) { best_f[l] = tf[l]; pick_f[l] = c; }
-            if (tb[l] < best_b[l]) { best_b[l] = tb[l]; pick_b[l] = c; }
+            if (tf[l] > 0 && tf[l] < best_f[l]) { best_f[l] = tf[l]; pick_f[l] = c; }
+            if (tb[l] > 0 && tb[l] < best_b[l]) { best_b[l] = tb[l]; pick_b[l] = c; }
         }
     }
     s->sched.fwd_block = pick_f;
@@ -1986,14 +2168,13 @@ static int32_t autotune_impl(pcfr_solver* s, int32_t reps, double* ms_before, do
     }
     {
         std::lock_guard<std::mutex> lk(g_sched_mu);
+        // only launches that ran on their own (not inside a fused run) were timed
         for (int l = 0; l < levels; l++) {
-            if (s->P.dec_off[l + 1] > s->P.dec_off[l]) g_sched_cache[sched_key(s, 0, l)] = pick_f[l];
-            if (s->P.fwd_off[l + 1] > s->P.fwd_off[l]) g_sched_cache[sched_key(s, 1, l)] = pick_b[l];
+            if (best_f[l] < 1e30) g_sched_cache[sched_key(s, 0, l)] = pick_f[l];
+            if (best_b[l] < 1e30) g_sched_cache[sched_key(s, 1, l)] = pick_b[l];
         }
     }
-    if (s->graph) { (void)hipGraphExecDestroy(s->graph); s->graph = nullptr; }
-    if (s->graph_def) { (void)hipGraphDestroy(s->graph_def); s->graph_def = nullptr; }
-    if ((rc = build_graph(s))) return rc;
+    if ((rc = rebuild_graph(s))) return rc;
     if ((rc = time_replays(s, reps, ms_after))) return rc;
     return reset_state(s);
 }
