@@ -43,6 +43,18 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+
+# HBM bytes measured with rocprofv3 hardware counters (FETCH_SIZE and
+# WRITE_SIZE, one run each, scaled by the same counters over a 1 GiB copy;
+# tables and commands in profiles/*_hbm_counters.md).  They describe the
+# kernels as they were measured; a changed kernel needs a new measurement.
+MEASURED_TRAFFIC = {
+    # k_gemm_nt<64,64,1> (hidden layers, 64x64 tiles), 1029 rows: per launch
+    "gemm_hidden_64x64": {"read": 37786631, "write": 3342336},
+    # k_backward<float,0,*> + k_backward_fused over one iteration of the
+    # seed-0 turn subgame (all backward launches)
+    "turn_backward_iteration": 2440516403,
+}
 CLASSES = ["bookkeeping", "forward", "terminal", "backward", "leaves", "leaf_gemm_hidden", "leaf_gemm_out"]
 
 
@@ -175,6 +187,7 @@ def tree_sweep(args, seed, steps, warmup):
     pms, pl = pms / args.profile_iters, pl // args.profile_iters
     achieved = alg_bytes / (pms[3] * 1e-3) / 1e9
     expl, _ = solver.exploitability()
+    traffic = MEASURED_TRAFFIC["turn_backward_iteration"] if seed == 0 and args.dtype == "f32" else None
     out = {
         "workload": f"turn subgame to showdown, seed {seed}",
         "board": spec["board"], "pot": spec["pot"], "stacks": list(spec["stacks"]),
@@ -188,7 +201,10 @@ def tree_sweep(args, seed, steps, warmup):
         "roofline": {
             "kernel": "k_backward<float,0> (values, DCFR regret and average-strategy update)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_note": "HBM bytes per iteration over all backward launches (hardware counters)",
+            "counter_gbs": None if traffic is None else traffic / (pms[3] * 1e-3) / 1e9,
+            "counter_frac": None if traffic is None else traffic / (pms[3] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "avg_launch_us": 1e3 * pms[3] / max(pl[3], 1), "launches_per_iter": int(pl[3]),
             "alg_bytes_per_iter": alg_bytes,
         },
@@ -326,6 +342,10 @@ def main():
     n_hidden = max(int(pl[5]), 1)
     achieved = (hidden_flops / n_hidden) / (gemm_ms / n_hidden * 1e-3) / 1e12
     all_gemm_tflops = flops_alg / ((pms[5] + pms[6]) * 1e-3) / 1e12
+    gemm_traffic = None
+    if args.dtype == "f32" and all(t == 0 for t in net.tiles[:-1]):
+        m = MEASURED_TRAFFIC["gemm_hidden_64x64"]
+        gemm_traffic = m["read"] + m["write"]
     expl, _ = solver.exploitability()
     log(f"kernel ms/iter {dict(zip(CLASSES, np.round(pms[:7], 4)))} launches {pl[:7].tolist()}")
     result = {
@@ -365,7 +385,8 @@ def main():
             "peak": BF16_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / BF16_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": gemm_traffic,
+            "traffic_note": "HBM bytes per launch (hardware counters); algorithmic operand bytes are ~9.6 MB",
             "avg_launch_us": 1e3 * gemm_ms / n_hidden,
             "launches_per_iter": n_hidden,
             "alg_flops_per_launch": hidden_flops / n_hidden,

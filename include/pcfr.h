@@ -264,8 +264,8 @@ int32_t pcfr_leafnet_get_grads(pcfr_leafnet* net, float* host);
 int32_t pcfr_leafnet_forward(pcfr_leafnet* net, const float* x, int32_t m, float* y);
 
 /* Tile autotuner of the forward GEMMs for batches of m rows: every layer is
- * timed over reps >= 1 launches with each workgroup tile (64x64, 128x64,
- * 64x128, 128x128 rows x columns) that divides its output width, and the
+ * timed over reps >= 1 launches with each workgroup tile (PCFR_TILE_*
+ * below) that divides its output width, and the
  * fastest is kept for all later forward calls (including the solver's leaf
  * stage).  Tiles group the FP32 partial sums differently, so outputs may
  * change in the last bits; for a fixed choice they are deterministic.  ms_before /
@@ -275,10 +275,15 @@ int32_t pcfr_leafnet_autotune(pcfr_leafnet* net, int32_t m, int32_t reps, double
 
 /* Forward GEMM tile per layer (count = depth + 1 layers): PCFR_TILE_DEFAULT
  * (-1, chosen from the shape), PCFR_TILE_64x64, PCFR_TILE_128x64,
- * PCFR_TILE_64x128 or PCFR_TILE_128x128 (rows x columns; the column count
- * must divide the layer's output width padded to 64, else
- * PCFR_E_INVALID_ARG).  get returns the current choice. */
-enum { PCFR_TILE_DEFAULT = -1, PCFR_TILE_64x64 = 0, PCFR_TILE_128x64 = 1, PCFR_TILE_64x128 = 2, PCFR_TILE_128x128 = 3 };
+ * PCFR_TILE_64x128, PCFR_TILE_128x128 (rows x columns, 4 waves), or
+ * PCFR_TILE_64x64_K2, PCFR_TILE_64x128_K2 (two 4-wave groups that split
+ * the K loop and add their partial sums); the column count must divide the
+ * layer's output width padded to 64, else PCFR_E_INVALID_ARG.  get returns
+ * the current choice. */
+enum {
+    PCFR_TILE_DEFAULT = -1, PCFR_TILE_64x64 = 0, PCFR_TILE_128x64 = 1, PCFR_TILE_64x128 = 2, PCFR_TILE_128x128 = 3,
+    PCFR_TILE_64x64_K2 = 4, PCFR_TILE_64x128_K2 = 5
+};
 int32_t pcfr_leafnet_set_tiles(pcfr_leafnet* net, const int32_t* tiles, int32_t count);
 int32_t pcfr_leafnet_get_tiles(pcfr_leafnet* net, int32_t* tiles, int32_t count);
 

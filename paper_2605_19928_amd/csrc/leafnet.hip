@@ -50,18 +50,35 @@ enum { EPI_BIAS_F32 = 0, EPI_BIAS_RELU_BF = 1, EPI_F32 = 2, EPI_MASK_BF = 3 };
 
 // Rows of A past M (the last row tile of a 128-row tiling) are read as row
 // M - 1 and their outputs are not stored.
-template <int BM, int BN, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
-                                                 const uint16_t* __restrict__ B, int ldb, int M, int K,
-                                                 const float* __restrict__ bias, void* __restrict__ Cout, int ldc,
-                                                 const uint16_t* __restrict__ mask) {
+//
+// KS > 1 splits each tile's K loop between KS groups of 4 waves in one
+// workgroup (group g takes a contiguous share of the K stages, with its own
+// LDS buffers and register ring); at the end the groups' accumulators are
+// added in group order through LDS and group 0 applies the epilogue.  This
+// doubles the waves in flight per tile for shapes whose tile count leaves
+// CUs idle.  Every group runs the same number of loop trips (a group with
+// fewer stages idles through its last ones), so the workgroup barriers match.
+template <int BM, int BN, int EPI, int KS = 1>
+__global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
+                                                      const uint16_t* __restrict__ B, int ldb, int M, int K,
+                                                      const float* __restrict__ bias, void* __restrict__ Cout,
+                                                      int ldc, const uint16_t* __restrict__ mask) {
     constexpr int BK = 64, LDK = BK + 8;
     constexpr int TM = BM / 64, TN = BN / 64;
     constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;
-    __shared__ __align__(16) uint16_t sA[2][BM * LDK];
-    __shared__ __align__(16) uint16_t sB[2][BN * LDK];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
+    __shared__ __align__(16) uint16_t sA[KS][2][BM * LDK];
+    __shared__ __align__(16) uint16_t sB[KS][2][BN * LDK];
+    const int grp = KS == 1 ? 0 : (int)(threadIdx.x >> 8);
+    const int tid = KS == 1 ? (int)threadIdx.x : (int)(threadIdx.x & 255);
+    const int lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
     const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    // this group's K stages: [sbeg, sbeg + ng); every group loops `trips` times
+    const int nk = K / BK;
+    const int trips = KS == 1 ? nk : (nk + KS - 1) / KS;
+    const int sbeg = KS == 1 ? 0 : grp * trips;
+    const int ng = KS == 1 ? nk : max(0, min(nk - sbeg, trips));
+    uint16_t(*gA)[BM * LDK] = sA[grp];
+    uint16_t(*gB)[BN * LDK] = sB[grp];
     // Global -> register -> LDS pipeline.  Tiles are fetched two K-stages
     // ahead into a 3-slot register ring (slot indices are compile-time
     // constants after the 3-way unroll below, so the ring stays in
@@ -69,27 +86,28 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
     // from LDS by the MFMAs.
     constexpr int D = 3;
     u32x4 ra[D][CA], rb[D][CB];
-#define LN_GLOAD(slot, k0)                                                                         \
+#define LN_GLOAD(slot, kt)                                                                         \
     do {                                                                                           \
+        const int64_t k0 = (int64_t)(sbeg + (kt)) * BK;                                            \
         _Pragma("unroll") for (int i = 0; i < CA; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
             const int64_t ar = m0 + row < M ? m0 + row : M - 1;                                    \
-            ra[slot][i] = *reinterpret_cast<const u32x4*>(A + ar * lda + (k0) + col);              \
+            ra[slot][i] = *reinterpret_cast<const u32x4*>(A + ar * lda + k0 + col);                \
         }                                                                                          \
         _Pragma("unroll") for (int i = 0; i < CB; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            rb[slot][i] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + (k0) + col);      \
+            rb[slot][i] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + k0 + col);        \
         }                                                                                          \
     } while (0)
 #define LN_SSTORE(slot, buf)                                                                       \
     do {                                                                                           \
         _Pragma("unroll") for (int i = 0; i < CA; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            *reinterpret_cast<u32x4*>(&sA[buf][row * LDK + col]) = ra[slot][i];                    \
+            *reinterpret_cast<u32x4*>(&gA[buf][row * LDK + col]) = ra[slot][i];                    \
         }                                                                                          \
         _Pragma("unroll") for (int i = 0; i < CB; i++) {                                           \
             const int c = tid + i * 256, row = c >> 3, col = (c & 7) * 8;                          \
-            *reinterpret_cast<u32x4*>(&sB[buf][row * LDK + col]) = rb[slot][i];                    \
+            *reinterpret_cast<u32x4*>(&gB[buf][row * LDK + col]) = rb[slot][i];                    \
         }                                                                                          \
     } while (0)
     // KACC independent accumulator chains per output tile, so consecutive
@@ -104,20 +122,19 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
             for (int j = 0; j < TN; j++)
 #pragma unroll
                 for (int r = 0; r < 16; r++) acc[q][i][j][r] = 0.f;
-    const int nk = K / BK;
     const int kh = 8 * (lane >> 5), l32 = lane & 31;
-    LN_GLOAD(0, 0);
-    if (nk > 1) LN_GLOAD(1, BK);
-    LN_SSTORE(0, 0);
+    if (KS == 1 || ng > 0) LN_GLOAD(0, 0);
+    if (ng > 1) LN_GLOAD(1, 1);
+    if (KS == 1 || ng > 0) LN_SSTORE(0, 0);
     __syncthreads();
 #define LN_COMPUTE(buf)                                                                            \
     do {                                                                                           \
         v8bf fa[BK / 16][TM], fb[BK / 16][TN];                                                     \
         _Pragma("unroll") for (int kk = 0; kk < BK / 16; kk++) {                                   \
             _Pragma("unroll") for (int i = 0; i < TM; i++) fa[kk][i] = *reinterpret_cast<const v8bf*>( \
-                &sA[buf][(wm * (BM / 2) + i * 32 + l32) * LDK + kk * 16 + kh]);                    \
+                &gA[buf][(wm * (BM / 2) + i * 32 + l32) * LDK + kk * 16 + kh]);                    \
             _Pragma("unroll") for (int j = 0; j < TN; j++) fb[kk][j] = *reinterpret_cast<const v8bf*>( \
-                &sB[buf][(wn * (BN / 2) + j * 32 + l32) * LDK + kk * 16 + kh]);                    \
+                &gB[buf][(wn * (BN / 2) + j * 32 + l32) * LDK + kk * 16 + kh]);                    \
         }                                                                                          \
         _Pragma("unroll") for (int kk = 0; kk < BK / 16; kk++)                                     \
             _Pragma("unroll") for (int i = 0; i < TM; i++)                                         \
@@ -126,18 +143,19 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
                         fa[kk][i], fb[kk][j], acc[kk % KACC][i][j], 0, 0, 0);                      \
     } while (0)
     // one stage: prefetch stage kt+2 into slot LSLOT, compute stage kt, move
-    // stage kt+1 (slot SSLOT) into the other LDS buffer
+    // stage kt+1 (slot SSLOT) into the other LDS buffer; stages past this
+    // group's count are skipped but the barrier is still taken
 #define LN_STAGE(kt, LSLOT, SSLOT)                                                                 \
     do {                                                                                           \
-        if ((kt) + 2 < nk) LN_GLOAD(LSLOT, ((kt) + 2) * BK);                                       \
-        LN_COMPUTE((kt) & 1);                                                                      \
-        if ((kt) + 1 < nk) LN_SSTORE(SSLOT, ((kt) + 1) & 1);                                       \
+        if ((kt) + 2 < ng) LN_GLOAD(LSLOT, (kt) + 2);                                              \
+        if (KS == 1 || (kt) < ng) LN_COMPUTE((kt) & 1);                                            \
+        if ((kt) + 1 < ng) LN_SSTORE(SSLOT, ((kt) + 1) & 1);                                       \
         __syncthreads();                                                                           \
     } while (0)
-    for (int kt = 0; kt < nk; kt += 3) {
+    for (int kt = 0; kt < trips; kt += 3) {
         LN_STAGE(kt, 2, 1);
-        if (kt + 1 < nk) LN_STAGE(kt + 1, 0, 2);
-        if (kt + 2 < nk) LN_STAGE(kt + 2, 1, 0);
+        if (kt + 1 < trips) LN_STAGE(kt + 1, 0, 2);
+        if (kt + 2 < trips) LN_STAGE(kt + 2, 1, 0);
     }
 #undef LN_STAGE
 #undef LN_COMPUTE
@@ -151,6 +169,33 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
             for (int j = 0; j < TN; j++)
 #pragma unroll
                 for (int r = 0; r < 16; r++) acc[0][i][j][r] += acc[q][i][j][r];
+    if constexpr (KS > 1) {
+        // groups 1.. hand their partial sums to group 0 through LDS, in group order
+        float* xr = reinterpret_cast<float*>(&sA[0][0][0]);   // reused: all stages are done
+        constexpr int PER = TM * TN * 16;                      // floats per lane
+        for (int g = 1; g < KS; g++) {
+            if (grp == g) {
+#pragma unroll
+                for (int i = 0; i < TM; i++)
+#pragma unroll
+                    for (int j = 0; j < TN; j++)
+#pragma unroll
+                        for (int r = 0; r < 16; r++) xr[((i * TN + j) * 16 + r) * 256 + tid] = acc[0][i][j][r];
+            }
+            __syncthreads();
+            if (grp == 0) {
+#pragma unroll
+                for (int i = 0; i < TM; i++)
+#pragma unroll
+                    for (int j = 0; j < TN; j++)
+#pragma unroll
+                        for (int r = 0; r < 16; r++) acc[0][i][j][r] += xr[((i * TN + j) * 16 + r) * 256 + tid];
+            }
+            __syncthreads();
+        }
+        static_assert(PER * 256 * 4 <= (int)sizeof(sA), "partial sums must fit in the A buffers");
+        if (grp != 0) return;
+    }
 #pragma unroll
     for (int i = 0; i < TM; i++)
 #pragma unroll
@@ -302,7 +347,7 @@ static int64_t r64(int64_t x) { return (x + 63) / 64 * 64; }
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool gemm_tile_valid(int tile, int64_t N) {
-    static const int bn[kGemmTiles] = {64, 64, 128, 128};
+    static const int bn[kGemmTiles] = {64, 64, 128, 128, 64, 128};
     return tile >= 0 && tile < kGemmTiles && N % bn[tile] == 0;
 }
 
@@ -317,22 +362,24 @@ int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const u
         tile = (M % 128 == 0) && (N % 128 == 0) && (M / 128) * (N / 128) >= 256 ? GEMM_128x128 : GEMM_64x64;
     }
     if (!gemm_tile_valid(tile, N)) { set_error("GEMM tile does not divide N"); return PCFR_E_INVALID_ARG; }
-    dim3 blk(256);
-#define LN_GEMM(BMv, BNv, E)                                                                                   \
-    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E>), dim3((unsigned)(N / BNv), (unsigned)((M + BMv - 1) / BMv)), \
-                       blk, 0, st, A, lda, B, ldb, (int)M, (int)K, bias, C, ldc, mask)
-#define LN_EPI(BMv, BNv)                                                   \
-    switch (epi) {                                                         \
-        case EPI_BIAS_F32: LN_GEMM(BMv, BNv, EPI_BIAS_F32); break;         \
-        case EPI_BIAS_RELU_BF: LN_GEMM(BMv, BNv, EPI_BIAS_RELU_BF); break; \
-        case EPI_F32: LN_GEMM(BMv, BNv, EPI_F32); break;                   \
-        default: LN_GEMM(BMv, BNv, EPI_MASK_BF); break;                    \
+#define LN_GEMM(BMv, BNv, E, KSv)                                                                        \
+    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E, KSv>),                                                   \
+                       dim3((unsigned)(N / BNv), (unsigned)((M + BMv - 1) / BMv)), dim3(256 * KSv), 0, st, \
+                       A, lda, B, ldb, (int)M, (int)K, bias, C, ldc, mask)
+#define LN_EPI(BMv, BNv, KSv)                                                       \
+    switch (epi) {                                                                  \
+        case EPI_BIAS_F32: LN_GEMM(BMv, BNv, EPI_BIAS_F32, KSv); break;             \
+        case EPI_BIAS_RELU_BF: LN_GEMM(BMv, BNv, EPI_BIAS_RELU_BF, KSv); break;     \
+        case EPI_F32: LN_GEMM(BMv, BNv, EPI_F32, KSv); break;                       \
+        default: LN_GEMM(BMv, BNv, EPI_MASK_BF, KSv); break;                        \
     }
     switch (tile) {
-        case GEMM_64x64: LN_EPI(64, 64); break;
-        case GEMM_128x64: LN_EPI(128, 64); break;
-        case GEMM_64x128: LN_EPI(64, 128); break;
-        default: LN_EPI(128, 128); break;
+        case GEMM_64x64: LN_EPI(64, 64, 1); break;
+        case GEMM_128x64: LN_EPI(128, 64, 1); break;
+        case GEMM_64x128: LN_EPI(64, 128, 1); break;
+        case GEMM_128x128: LN_EPI(128, 128, 1); break;
+        case GEMM_64x64_K2: LN_EPI(64, 64, 2); break;
+        default: LN_EPI(64, 128, 2); break;
     }
 #undef LN_EPI
 #undef LN_GEMM

@@ -23,8 +23,12 @@ struct LeafNetPlan {
     void make(int d_in, int width, int depth, int d_out, int max_batch);
 };
 
-// GEMM workgroup tiles (rows x columns of C); 4 waves, each a quarter tile.
-enum { GEMM_64x64 = 0, GEMM_128x64 = 1, GEMM_64x128 = 2, GEMM_128x128 = 3, kGemmTiles = 4 };
+// GEMM workgroup tiles (rows x columns of C); 4 waves, each a quarter tile;
+// the _K2 variants run two such groups that split K (8 waves).
+enum {
+    GEMM_64x64 = 0, GEMM_128x64 = 1, GEMM_64x128 = 2, GEMM_128x128 = 3, GEMM_64x64_K2 = 4, GEMM_64x128_K2 = 5,
+    kGemmTiles = 6
+};
 bool gemm_tile_valid(int tile, int64_t N);
 
 // C = A B^T with an epilogue; tile < 0 picks a default for the shape.

@@ -764,12 +764,20 @@ __global__ __launch_bounds__(kBlock) void k_equity_partial(const DNode* __restri
     T acc[J][2];
 #pragma unroll
     for (int j = 0; j < J; j++) { acc[j][0] = T(0); acc[j][1] = T(0); }
-    for (int o = o0; o < o1; o++) {
-        const T e = Et[(int64_t)o * Hp + h];
+    // 8 rows of Et in flight at a time; the sums still run in row order
+    constexpr int G = 8;
+    for (int ob = o0; ob < o1; ob += G) {
+        T e[G];
 #pragma unroll
-        for (int j = 0; j < J; j++) {
-            acc[j][0] += e * rr[j][1][o - o0];   // player 0 against player 1's reach
-            acc[j][1] += e * rr[j][0][o - o0];
+        for (int q = 0; q < G; q++) e[q] = ob + q < o1 ? Et[(int64_t)(ob + q) * Hp + h] : T(0);
+#pragma unroll
+        for (int q = 0; q < G; q++) {
+            if (ob + q >= o1) break;
+#pragma unroll
+            for (int j = 0; j < J; j++) {
+                acc[j][0] += e[q] * rr[j][1][ob + q - o0];   // player 0 against player 1's reach
+                acc[j][1] += e[q] * rr[j][0][ob + q - o0];
+            }
         }
     }
 #pragma unroll
@@ -835,52 +843,52 @@ __device__ __forceinline__ void stage_leaf(const T* __restrict__ r0, const T* __
     block_sum2(t0, t1, xch);      // synchronises: cs is visible after it
 }
 
-// Per-leaf reach aggregates shared by the leaf-row kernels, once per leaf:
+// Per-leaf reach aggregates shared by the zero-sum and combine kernels:
 // agg[leaf] = [2][53], each player's 52 per-card sums (reach of the hands
-// holding the card) then the total.
+// holding the card) then the total; written by the leaf-input workgroup of
+// the leaf's first next card.
 constexpr int kAgg = 106;
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_agg(const DNode* __restrict__ nodes, const int32_t* __restrict__ leaves,
-                                                     int Hp, const T* __restrict__ reach,
-                                                     const int32_t* __restrict__ coff,
-                                                     const int16_t* __restrict__ chands, T* __restrict__ agg) {
-    __shared__ T x[2][kMaxHp];
-    __shared__ T cs[2][52];
-    __shared__ T xch[2 * kWaves];
-    const int li = blockIdx.x;
-    const DNode nd = nodes[leaves[li]];
-    T t0, t1;
-    stage_leaf<T, T>(reach + (int64_t)nd.slot[0] * Hp, reach + (int64_t)nd.slot[1] * Hp, Hp, coff, chands, x, cs, xch,
-                     t0, t1);
-    T* out = agg + (int64_t)li * kAgg;
-    const int tid = threadIdx.x;
-    if (tid < 104) out[(tid / 52) * 53 + tid % 52] = cs[tid / 52][tid % 52];
-    if (tid == 0) { out[52] = t0; out[105] = t1; }
-}
 
 // Stage 2's batched leaf input (Sec. 4.2): one row per (leaf, next card c):
 // each player's reach with the hands holding c removed, normalised to sum 1,
 // over the 1326 combos; then the board after c as 52 one-hot entries; then
-// the stack-to-pot ratio at the leaf; bf16, zero padded to ldx.  The
-// normaliser is the leaf total minus the per-card sum of c.
+// the stack-to-pot ratio at the leaf; bf16, zero padded to ldx.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__ nodes,
                                                        const int32_t* __restrict__ leaves, const float* __restrict__ spr,
                                                        int n_next, const int8_t* __restrict__ next_cards, int Hp,
-                                                       const T* __restrict__ reach, const T* __restrict__ agg,
-                                                       const uint16_t* __restrict__ hcards,
+                                                       const T* __restrict__ reach, const uint16_t* __restrict__ hcards,
                                                        const int16_t* __restrict__ combo_hand,
+                                                       const int32_t* __restrict__ coff,
+                                                       const int16_t* __restrict__ chands,
                                                        const uint8_t* __restrict__ board_hot, uint16_t* __restrict__ X,
-                                                       int ldx) {
+                                                       int ldx, T* __restrict__ agg) {
+    __shared__ T x[2][kMaxHp];
+    __shared__ T cs[2][52];
+    __shared__ T txch[2 * kWaves];
+    __shared__ double dxch[2 * kWaves];
     const int q = blockIdx.x;
     const int li = q / n_next, k = q - li * n_next;
     const int c = next_cards[k];
     const DNode nd = nodes[leaves[li]];
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
-    const T* ag = agg + (int64_t)li * kAgg;
-    const double S0 = (double)ag[52] - (double)ag[c], S1 = (double)ag[105] - (double)ag[53 + c];
+    const int tid = threadIdx.x;
+    if (k == 0) {
+        T t0, t1;
+        stage_leaf<T, T>(r0, r1, Hp, coff, chands, x, cs, txch, t0, t1);
+        T* out = agg + (int64_t)li * kAgg;
+        if (tid < 104) out[(tid / 52) * 53 + tid % 52] = cs[tid / 52][tid % 52];
+        if (tid == 0) { out[52] = t0; out[105] = t1; }
+    }
+    // normaliser: the reach of the hands without c
+    double S0 = 0.0, S1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h < Hp && !has_card(hcards[h], c)) { S0 += (double)r0[h]; S1 += (double)r1[h]; }
+    }
+    block_sum2(S0, S1, dxch);
     uint16_t* row = X + (int64_t)q * ldx;
     for (int col = threadIdx.x; col < ldx; col += kBlock) {
         float v = 0.f;
@@ -1534,6 +1542,10 @@ struct pcfr_solver {
     Plan L;
     Sched sched;
     hipStream_t stream = nullptr;
+    // second stream and fork/join events: terminals and exact leaves run
+    // beside the network stage (a parallel branch of the captured graph)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char* ws = nullptr;
     std::vector<double> ranges;       // [n_sub][2][1326]
     std::vector<double> pair_mass;    // [n_sub]
@@ -1543,6 +1555,14 @@ struct pcfr_solver {
     bool leaf_zero_sum = true;  // shift network outputs to zero-sum leaf values
     int64_t t_host = 0;     // iterations enqueued
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+    ~pcfr_solver() {
+        if (stream && ws) (void)hipStreamSynchronize(stream);
+        if (aux) { (void)hipStreamSynchronize(aux); (void)hipStreamDestroy(aux); }
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (graph_def) (void)hipGraphDestroy(graph_def);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+    }
 };
 
 namespace pcfr {
@@ -1608,13 +1628,22 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         first = false;
         l++;
     }
+    // terminals and exact-equity leaves do not depend on the network stage:
+    // without per-launch timing they go to the second stream, joined before
+    // the backward sweep
+    const bool fork = !tm && s->aux && s->net && L.n_net;
+    hipStream_t side = fork ? s->aux : stream;
+    if (fork) {
+        HIPCHK(hipEventRecord(s->ev_fork, stream));
+        HIPCHK(hipStreamWaitEvent(side, s->ev_fork, 0));
+    }
     // terminals: folds and showdowns in separate launches, each with the LDS it needs
     const int64_t n_fold = (int64_t)P.folds.size(), n_show = (int64_t)P.shows.size();
     for (int kind = 0; kind < 2; kind++) {
         const int64_t cnt = kind ? n_show : n_fold;
         if (!cnt) continue;
         if (tm) tm->before(2);
-        hipLaunchKernelGGL((k_terminal<T>), dim3((unsigned)cnt), dim3(kBlock), kind ? L.lds_show : L.lds_fold, stream,
+        hipLaunchKernelGGL((k_terminal<T>), dim3((unsigned)cnt), dim3(kBlock), kind ? L.lds_show : L.lds_fold, side,
                            nodes, s->at<int32_t>(L.off_term) + (kind ? n_fold : 0), Hp, reach, cfv,
                            s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
                            (int)L.chand_stride, s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride,
@@ -1628,10 +1657,10 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         constexpr int J = sizeof(T) == 8 ? 2 : 4;
         dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)((n_eq_active + J - 1) / J), kEqSplit);
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_equity_partial<T, J>), grid, dim3(kBlock), 0, stream, nodes, s->at<int32_t>(L.off_eq),
+        hipLaunchKernelGGL((k_equity_partial<T, J>), grid, dim3(kBlock), 0, side, nodes, s->at<int32_t>(L.off_eq),
                            (int)n_eq_active, Hp, s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
         const int64_t tot = n_eq_active * 2 * (int64_t)Hp;
-        hipLaunchKernelGGL((k_equity_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL((k_equity_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, side,
                            s->at<int32_t>(L.off_eq), s->at<double>(L.off_eqpay), (int)n_eq_active, Hp,
                            s->at<T>(L.off_eqpart), cfv);
         if (tm) tm->after();
@@ -1640,14 +1669,12 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         pcfr_leafnet* net = s->net;
         const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_leaf_agg<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream, nodes,
-                           s->at<int32_t>(L.off_net), Hp, reach, s->at<int32_t>(L.off_coff),
-                           s->at<int16_t>(L.off_chands), s->at<T>(L.off_agg));
         hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes,
                            s->at<int32_t>(L.off_net), s->at<float>(L.off_spr), (int)L.n_next,
-                           s->at<int8_t>(L.off_next), Hp, reach, s->at<T>(L.off_agg), s->at<uint16_t>(L.off_hc),
-                           s->at<int16_t>(L.off_c2h), s->at<uint8_t>(L.off_hot),
-                           reinterpret_cast<uint16_t*>(net->ws + net->P.off_x), (int)net->P.pdims[0]);
+                           s->at<int8_t>(L.off_next), Hp, reach, s->at<uint16_t>(L.off_hc),
+                           s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
+                           s->at<uint8_t>(L.off_hot), reinterpret_cast<uint16_t*>(net->ws + net->P.off_x),
+                           (int)net->P.pdims[0], s->at<T>(L.off_agg));
         if (tm) tm->after();
         int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
         if (rc) return rc;
@@ -1671,6 +1698,10 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            (int)net->P.pdims[net->P.L], s->at<T>(L.off_agg),
                            s->leaf_zero_sum ? s->at<T>(L.off_zs) : nullptr);
         if (tm) tm->after();
+    }
+    if (fork) {
+        HIPCHK(hipEventRecord(s->ev_join, side));
+        HIPCHK(hipStreamWaitEvent(stream, s->ev_join, 0));
     }
     // backward; level 0 holds exactly the roots, whose values of this
     // iteration are also kept apart from later evaluation sweeps
@@ -1885,6 +1916,9 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     }
     s->stream = reinterpret_cast<hipStream_t>(stream);
     s->ws = reinterpret_cast<char*>(workspace);
+    HIPCHK(hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     auto up = [&](size_t off, const void* src, size_t bytes) -> int32_t {
         if (!bytes) return PCFR_OK;
         return hip_check(hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream), "upload");
@@ -2247,11 +2281,7 @@ int32_t pcfr_leaf_rows(pcfr_solver* s, int32_t* n_leaves, int32_t* n_next) {
 }
 
 int32_t pcfr_solver_free(pcfr_solver* s) {
-    if (!s) return PCFR_OK;
-    if (s->stream) (void)hipStreamSynchronize(s->stream);
-    if (s->graph) (void)hipGraphExecDestroy(s->graph);
-    if (s->graph_def) (void)hipGraphDestroy(s->graph_def);
-    delete s;
+    delete s;   // the destructor waits for the streams and releases graph, stream and events
     return PCFR_OK;
 }
 

@@ -446,7 +446,8 @@ class LeafNet:
 
     @property
     def tiles(self):
-        """Forward GEMM tile per layer (-1 default, 0 64x64, 1 128x64, 2 64x128, 3 128x128)."""
+        """Forward GEMM tile per layer (-1 default, 0 64x64, 1 128x64, 2 64x128, 3 128x128,
+        4 64x64 and 5 64x128 with the K loop split between two wave groups)."""
         t = np.zeros(len(self.layer_shapes()), dtype=np.int32)
         _check(lib().pcfr_leafnet_get_tiles(self._h, _p(t), len(t)))
         return [int(v) for v in t]
