@@ -76,6 +76,7 @@ def lib():
             "ora_set_traverser_hands": (None, [P, P]),
             "ora_max_threads": (I, []),
             "ora_set_variant": (None, [P, I]),
+            "ora_set_alternating": (None, [P, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -177,16 +178,19 @@ class Tree:
 
 
 class Solver:
-    """Per-history DCFR with simultaneous updates, in FP64."""
+    """Per-history DCFR in FP64; simultaneous updates, or alternating ones
+    (player 0, then player 1 against player 0's new strategy)."""
 
     VARIANTS = {"dcfr": 0, "cfr+": 1, "pcfr+": 2}
 
-    def __init__(self, tree: Tree, ranges, alpha=1.5, beta=0.0, gamma=2.0, support_only=False, variant="dcfr"):
+    def __init__(self, tree: Tree, ranges, alpha=1.5, beta=0.0, gamma=2.0, support_only=False, variant="dcfr",
+                 alternating=False):
         self.tree = tree
         r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, tree.nh)
         self._r = r
         self._h = lib().ora_solver_create(tree._h, _p(r), alpha, beta, gamma, int(support_only))
         lib().ora_set_variant(self._h, self.VARIANTS[variant])
+        lib().ora_set_alternating(self._h, 1 if alternating else 0)
 
     def iterate(self, n: int, threads: int = 0):
         lib().ora_iterate(self._h, int(n), int(threads))

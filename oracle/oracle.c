@@ -558,6 +558,8 @@ typedef struct {
     double cfv[2][NCOMBO];
     int64_t t;
     int support_only;
+    int alternating;       /* 0: both players from the same strategies; 1: player 0, then player 1 */
+    unsigned char* row_player;  /* [nrows]: the player acting at the row's node */
     unsigned char* tmask;  /* optional [2][nh]: traverser hands to evaluate (NULL = all) */
     int leaf_kind;
     double* leaf_ev;      /* LEAF_TABLE: [leaf node][player][card][nh] expected value per pot */
@@ -579,6 +581,10 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
     s->sig = calloc(n, sizeof(double)); s->rinst = calloc(n, sizeof(double));
     s->sadd = calloc(n, sizeof(double));
     s->pred = calloc(n, sizeof(double));
+    s->row_player = calloc(g->nrows > 0 ? g->nrows : 1, 1);
+    for (int i = 0; i < g->n; i++)
+        if (g->nd[i].type == T_DEC)
+            for (int a = 0; a < g->nd[i].n_child; a++) s->row_player[g->nd[i].rs + a] = (unsigned char)g->nd[i].player;
     s->leaf_slot = malloc(sizeof(int) * g->n);
     for (int i = 0; i < g->n; i++) {
         s->leaf_slot[i] = -1;
@@ -591,7 +597,7 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
 void ora_solver_free(osolver* s) {
     if (!s) return;
     free(s->R); free(s->S); free(s->sig); free(s->rinst); free(s->sadd); free(s->pred);
-    free(s->leaf_ev); free(s->leaf_slot); free(s->tmask); free(s);
+    free(s->leaf_ev); free(s->leaf_slot); free(s->tmask); free(s->row_player); free(s);
 }
 
 /* Restrict the traverser's hands whose values and regrets are computed (the
@@ -741,6 +747,7 @@ static void own_reach(osolver* s, int n, int p, int h, double pi) {
 }
 
 void ora_set_variant(osolver* s, int variant) { s->variant = variant; }
+void ora_set_alternating(osolver* s, int on) { s->alternating = on; }
 
 /* Regrets the next strategy is matched on: R, or R + m for PCFR+. */
 static const double* matched_regrets(const osolver* s, double* tmp) {
@@ -750,12 +757,28 @@ static const double* matched_regrets(const osolver* s, double* tmp) {
     return tmp;
 }
 
-/* One iteration with simultaneous updates of both players. */
+/* One iteration.  Simultaneous updates: both players' regrets and averages
+ * from the same strategies sigma^t.  Alternating updates: player 0 is
+ * updated first; player 1 then traverses against player 0's new strategy
+ * (matched on the just-updated regrets); both halves use iteration t's
+ * discounts, and each updates only its own player's rows. */
+static void half_step(osolver* s, int upd, double t);
+
 static void iterate_once(osolver* s) {
-    ogame* g = s->g;
-    int nh = g->nh;
     s->t++;
     double t = (double)s->t;
+    if (!s->alternating) {
+        half_step(s, -1, t);
+    } else {
+        half_step(s, 0, t);
+        half_step(s, 1, t);
+    }
+}
+
+/* Traverse for the players in {upd} (both when upd < 0) and update their rows. */
+static void half_step(osolver* s, int upd, double t) {
+    ogame* g = s->g;
+    int nh = g->nh;
     double ta = pow(t, s->alpha), tb = pow(t, s->beta);
     double dpos = ta / (ta + 1.0), dneg = tb / (tb + 1.0);
     double davg = pow(t / (t + 1.0), s->gamma);
@@ -764,6 +787,7 @@ static void iterate_once(osolver* s) {
     memset(s->rinst, 0, n * sizeof(double));
     memset(s->sadd, 0, n * sizeof(double));
     for (int i = 0; i < 2; i++) {
+        if (upd >= 0 && i != upd) continue;
         int op = 1 - i;
         int* olist = malloc(sizeof(int) * nh);
         int no = 0;
@@ -786,12 +810,14 @@ static void iterate_once(osolver* s) {
         free(olist);
     }
     for (int p = 0; p < 2; p++) {
+        if (upd >= 0 && p != upd) continue;
         #pragma omp parallel for schedule(dynamic)
         for (int h = 0; h < nh; h++)
             if (g->hvalid[h]) own_reach(s, 0, p, h, s->rng[p][h]);
     }
     #pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; k++) {
+        if (upd >= 0 && s->row_player[k / nh] != upd) continue;
         double r = s->R[k] + s->rinst[k];
         if (s->variant == V_DCFR) {
             s->R[k] = r * (r > 0 ? dpos : dneg);

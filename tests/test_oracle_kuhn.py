@@ -183,3 +183,45 @@ def test_variant_first_iterations_match_brute_force(kuhn, variant):
                 key = next(h for h in INFOSETS if NODE_OF[h] == node)
                 want = rm(R[(key, c)] + (M[(key, c)] if variant == "pcfr+" else 0))
                 np.testing.assert_allclose(cur[:, c], want, atol=1e-14)
+
+
+@pytest.mark.parametrize("variant", ["dcfr", "cfr+", "pcfr+"])
+def test_alternating_first_iterations_match_brute_force(kuhn, variant):
+    """Alternating updates: within iteration t player 0 is updated from
+    sigma^t, then player 1 against player 0's new strategy (regret matching
+    of the updated regrets, plus the prediction for PCFR+); both halves use
+    iteration t's discounts and touch only their own player's rows."""
+    s = O.Solver(kuhn, np.ones((2, 3)), variant=variant, alternating=True)
+    R = {k: np.zeros(2) for k in ((h, c) for h in INFOSETS for c in range(3))}
+    S = {k: np.zeros(2) for k in R}
+    M = {k: np.zeros(2) for k in R}
+    rows_of = {0: 0, 1: 2, 2: 4, 4: 6}
+    for t in (1, 2, 3):
+        for upd in (0, 1):
+            sig = {k: rm(R[k] + (M[k] if variant == "pcfr+" else 0)) for k in R}
+            reg, sadd = brute_iteration(sig)
+            for k in R:
+                if ACTOR[k[0]] != upd:
+                    continue
+                x = R[k] + reg[k]
+                if variant == "dcfr":
+                    R[k] = np.where(x > 0, x * t ** ALPHA / (t ** ALPHA + 1), x * t ** BETA / (t ** BETA + 1))
+                    S[k] = (S[k] + sadd[k]) * (t / (t + 1)) ** GAMMA
+                else:
+                    R[k] = np.maximum(x, 0.0)
+                    S[k] = S[k] + (t if variant == "cfr+" else t * t) * sadd[k]
+                    M[k] = reg[k]
+        s.iterate(1)
+        Ro, So = s.rows("R"), s.rows("S")
+        for (h, c), v in R.items():
+            row = rows_of[NODE_OF[h]]
+            np.testing.assert_allclose(Ro[row:row + 2, c], v, atol=1e-14)
+            np.testing.assert_allclose(So[row:row + 2, c], S[(h, c)], atol=1e-14)
+
+
+def test_alternating_reaches_the_game_value(kuhn):
+    s = O.Solver(kuhn, np.ones((2, 3)), ALPHA, BETA, GAMMA, alternating=True)
+    s.iterate(5000)
+    e, _ = s.exploitability()
+    assert 0 <= e < 1e-3
+    assert abs(s.root_cfv("avg")[0].sum() / s.pair_mass() + 1 / 18) < 1e-3
