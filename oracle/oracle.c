@@ -703,8 +703,16 @@ static double walk(osolver* s, int n, int i, int hi, int ho, double w) {
             va[a] = walk(s, o->first_child + a, i, hi, ho, w);
             v += sg[(size_t)a * g->nh + hi] * va[a];
         }
+        /* instantaneous regret v(I.a) - v(I), written as sum_b sigma_b (v_a - v_b):
+         * the same quantity (the sigma_b sum to one), but actions whose values are
+         * exactly tied get exactly zero regret whatever the summation order, so
+         * regret matching does not flip on the sign of a rounding residue */
         double* ri = s->rinst + (size_t)o->rs * g->nh;
-        for (int a = 0; a < A; a++) ri[(size_t)a * g->nh + hi] += w * (va[a] - v);
+        for (int a = 0; a < A; a++) {
+            double r = 0;
+            for (int b = 0; b < A; b++) r += sg[(size_t)b * g->nh + hi] * (va[a] - va[b]);
+            ri[(size_t)a * g->nh + hi] += w * r;
+        }
         return v;
     }
     double v = 0;

@@ -1,4 +1,4 @@
-"""Stage-7 variants (CFR+, predictive CFR+) on the GPU vs the oracle.
+"""Stage-7 variants (CFR+, predictive CFR+) and alternating updates on the GPU vs the oracle.
 
 The paper changes only the regret update between CFR variants (Sec. 4.4) and
 compares DCFR with PCFR+ (Sec. 5, convergence).  FP64: 1e-9 pot on root
@@ -20,9 +20,10 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("variant", ["cfr+", "pcfr+"])
+@pytest.mark.parametrize("variant,alternating", [("cfr+", False), ("pcfr+", False), ("dcfr", True),
+                                                 ("pcfr+", True)])
 @pytest.mark.parametrize("which", ["river", "turn"])
-def test_variant_matches_oracle(variant, which):
+def test_variant_matches_oracle(variant, alternating, which):
     if which == "river":
         spec, r = I.river_config(4, support=140)
         so = False
@@ -30,12 +31,12 @@ def test_variant_matches_oracle(variant, which):
         spec, r = I.turn_config(5, support=40, spr=1.5)
         so = True
     T = 40
-    say(f"case: {variant} {which} {spec} T={T}")
+    say(f"case: {variant} alternating={alternating} {which} {spec} T={T}")
     ot = O.Tree.holdem(**spec)
-    os_ = O.Solver(ot, r, support_only=so, variant=variant)
+    os_ = O.Solver(ot, r, support_only=so, variant=variant, alternating=alternating)
     os_.iterate(T)
     gt = P.Tree(**spec)
-    gs = P.Solver(gt, r, P.SolverConfig(dtype="f64", variant=variant))
+    gs = P.Solver(gt, r, P.SolverConfig(dtype="f64", variant=variant, alternating=int(alternating)))
     gs.iterate(T)
     pot = spec["pot"]
     mask = (r > 0) if so else np.ones_like(r, dtype=bool)
@@ -66,3 +67,27 @@ def test_pcfrplus_checkpoint_resume_bitwise():
     b.iterate(8)
     assert a.save_state() == b.save_state()
     np.testing.assert_array_equal(a.root_cfv("current"), b.root_cfv("current"))
+
+
+def test_alternating_flop_network_leaves_runs_and_resumes():
+    """Alternating updates with the network stage (two leaf batches per
+    iteration): a checkpoint resume is bitwise and t counts iterations."""
+    spec, r = I.flop_config(2, support=200)
+    t = P.Tree(**spec)
+    cfg = P.SolverConfig(alternating=1)
+    a = P.Solver(t, r, cfg)
+    n_leaves, n_next = a.leaf_rows()
+    net = P.LeafNet(P.LEAF_D_IN, 64, 2, P.LEAF_D_OUT, max_batch=n_leaves * n_next)
+    rng = np.random.default_rng(3)
+    net.set_params([((rng.standard_normal((o, i)) / np.sqrt(i)).astype(np.float32), np.zeros(o, np.float32))
+                    for o, i in net.layer_shapes()])
+    a.attach_leafnet(net)
+    a.iterate(5)
+    blob = a.save_state()
+    a.iterate(4)
+    b = P.Solver(t, r, cfg)
+    b.attach_leafnet(net)
+    b.load_state(blob)
+    b.iterate(4)
+    assert a.t == 9 and b.t == 9
+    assert a.save_state() == b.save_state()
