@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--no-secondary", action="store_true", help="skip the turn and batch measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-one-at-a-time", action="store_true",
+                    help="batch workload: skip timing the subgames one at a time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-mb", type=int, default=0,
                     help="first run a plain elementwise kernel over this many MiB (reads it once, writes it "
@@ -289,7 +291,7 @@ def main():
         del x, y
 
     if args.workload == "batch":
-        out = batch_sweep(args, args.seed, args.steps, args.warmup)
+        out = batch_sweep(args, args.seed, args.steps, args.warmup, individual=not args.no_one_at_a_time)
         result = {
             "metric": "DCFR ms/iter & iters/sec, flop depth-limited subgame; exploitability mbb/hand",
             "value": out["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": args.steps,

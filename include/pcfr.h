@@ -88,13 +88,16 @@ typedef struct pcfr_tree_spec {
  * Sec. 5 "Baselines", after Brown & Sandholm 2019): after adding the
  * iteration-t regret, a positive cumulative regret is scaled by
  * t^alpha/(t^alpha+1), a non-positive one by t^beta/(t^beta+1), and the
- * average-strategy sum by (t/(t+1))^gamma.  Updates are simultaneous for
- * both players (alternating must be 0). */
+ * average-strategy sum by (t/(t+1))^gamma.  alternating = 0: both players
+ * are updated from the same strategies (simultaneous updates, one sweep per
+ * iteration); 1: player 0 is updated first, then player 1 against player 0's
+ * new strategy, both with iteration t's coefficients (two sweeps per
+ * iteration); other values are PCFR_E_INVALID_ARG. */
 typedef struct pcfr_solver_cfg {
     int32_t dtype;        /* PCFR_F32 or PCFR_F64 */
-    int32_t variant;      /* PCFR_DCFR */
+    int32_t variant;      /* PCFR_DCFR, PCFR_CFRPLUS or PCFR_PCFRPLUS */
     double alpha, beta, gamma;
-    int32_t alternating;  /* must be 0 */
+    int32_t alternating;  /* 0 or 1 */
 } pcfr_solver_cfg;
 
 typedef struct pcfr_tree pcfr_tree;

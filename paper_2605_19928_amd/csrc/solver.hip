@@ -212,7 +212,8 @@ template <typename T, int MODE, int A, bool EARLY = false>
 __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
                                              T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
                                              T* __restrict__ cfv, const IterState* st,
-                                             const uint16_t* __restrict__ hcards, T* __restrict__ root_dst) {
+                                             const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
+                                             int upd) {
     const int p = nd.player, o = 1 - p;
     V4<T> x[A];
     V4<T> s_early[EARLY && MODE == MODE_ITER ? A : 1];
@@ -243,6 +244,14 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
             for (int j = 0; j < 4; j++)
                 den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
     }
+    // this iteration's strategy of each action (unused for a best response)
+    T sg[MODE == MODE_BR ? 1 : A][4];
+    if constexpr (MODE != MODE_BR) {
+#pragma unroll
+        for (int a = 0; a < A; a++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) sg[a][j] = strat<T, MODE>(x[a].e[j], den[j], inv_a);
+    }
     // children's values, read once
     V4<T> c[A];
     V4<T> vp = {{T(0), T(0), T(0), T(0)}}, vo = {{T(0), T(0), T(0), T(0)}};
@@ -254,19 +263,20 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             vo.e[j] += d.e[j];
-            if (MODE == MODE_BR) vp.e[j] = (a == 0 || c[a].e[j] > vp.e[j]) ? c[a].e[j] : vp.e[j];
-            else vp.e[j] += strat<T, MODE>(x[a].e[j], den[j], inv_a) * c[a].e[j];
+            if constexpr (MODE == MODE_BR) vp.e[j] = (a == 0 || c[a].e[j] > vp.e[j]) ? c[a].e[j] : vp.e[j];
+            else vp.e[j] += sg[a][j] * c[a].e[j];
         }
     }
     T* me = cfv + n * 2 * Hp;
     st4(me + (int64_t)p * Hp + h, vp);
     st4(me + (int64_t)o * Hp + h, vo);
     if (root_dst) {
+        // with alternating updates each half keeps only the updated player's root values
         T* rd = root_dst + (int64_t)nd.sub * 2 * Hp;
-        st4(rd + (int64_t)p * Hp + h, vp);
-        st4(rd + (int64_t)o * Hp + h, vo);
+        if (upd < 0 || upd == p) st4(rd + (int64_t)p * Hp + h, vp);
+        if (upd < 0 || upd == o) st4(rd + (int64_t)o * Hp + h, vo);
     }
-    if (MODE == MODE_ITER) {
+    if (MODE == MODE_ITER && (upd < 0 || upd == p)) {
         // Stage 7: regret update, and the reach-weighted strategy added to the
         // average-strategy sum (Stage 1's accumulation, done here so that one
         // pass reads and writes both tables), each with its DCFR discount.
@@ -291,10 +301,15 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
             V4<T> y, inst;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                inst.e[j] = c[a].e[j] - vp.e[j];
+                // v(I.a) - v(I) as sum_b sigma_b (v_a - v_b): exactly tied actions
+                // get exactly zero regret, whatever the rounding of v(I)
+                T ia = T(0);
+#pragma unroll
+                for (int b = 0; b < A; b++) ia += sg[b][j] * (c[a].e[j] - c[b].e[j]);
+                inst.e[j] = ia;
                 T r = r0.e[j] + inst.e[j];
                 y.e[j] = r * (r > T(0) ? dpos : dneg);
-                sv.e[j] = (sv.e[j] + wadd * (rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a))) * wmul;
+                sv.e[j] = (sv.e[j] + wadd * (rp.e[j] * sg[a][j])) * wmul;
             }
             st4(rptr, y);
             st4(sp, sv);
@@ -308,7 +323,7 @@ template <typename T, int MODE, int MAXA, bool EARLY = false>
 __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __restrict__ R, T* __restrict__ S,
                                          T* __restrict__ Mp, const T* __restrict__ reach, T* __restrict__ cfv,
                                          const IterState* __restrict__ st, const uint16_t* __restrict__ hcards,
-                                         T* __restrict__ root_dst) {
+                                         T* __restrict__ root_dst, int upd) {
     const int64_t n = nd.id;
     if (nd.type == PCFR_NODE_CHANCE) {
         // children in groups of 4: all loads of a group are issued before the
@@ -344,7 +359,7 @@ __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __re
     switch (nd.n_child) {
 #define PCFR_BWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, EARLY>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst); \
+        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, EARLY>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst, upd); \
         break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
@@ -355,19 +370,21 @@ __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __re
 
 // One thread per (node, 4 hands) of a level, decision and chance nodes.
 // root_dst (the last launch of an iteration only) also receives each root's
-// values, which later evaluation sweeps do not overwrite.
+// values, which later evaluation sweeps do not overwrite.  upd >= 0 limits
+// Stage 7 (and the root values kept) to that player: alternating updates.
 template <typename T, int MODE, int MAXA>
 __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __restrict__ level, int count, int Hp,
                                                              T* __restrict__ R, T* __restrict__ S, T* __restrict__ Mp,
                                                              const T* __restrict__ reach, T* __restrict__ cfv,
                                                              const IterState* __restrict__ st,
                                                              const uint16_t* __restrict__ hcards,
-                                                             T* __restrict__ root_dst) {
+                                                             T* __restrict__ root_dst, int upd) {
     const int groups = Hp >> 2;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
-    bwd_node<T, MODE, MAXA>(level[k], (int)(gid - k * groups) * 4, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst);
+    bwd_node<T, MODE, MAXA>(level[k], (int)(gid - k * groups) * 4, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst,
+                            upd);
 }
 
 // Level-fused sweeps for runs of levels too small to fill the GPU.  A node's
@@ -427,7 +444,8 @@ __global__ __launch_bounds__(256) void k_backward_fused(const DNode* __restrict_
                                                         int Hp, T* __restrict__ R, T* __restrict__ S,
                                                         T* __restrict__ Mp, const T* __restrict__ reach,
                                                         T* __restrict__ cfv, const IterState* __restrict__ st,
-                                                        const uint16_t* __restrict__ hcards, T* __restrict__ root_dst) {
+                                                        const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
+                                                        int upd) {
     __shared__ DNode srec[kFuseRec];
     const int64_t r0 = lvl_off[l_lo], nrec = lvl_off[l_hi] - r0;
     const bool staged = stage_records(srec, rec + r0, nrec);
@@ -437,7 +455,7 @@ __global__ __launch_bounds__(256) void k_backward_fused(const DNode* __restrict_
         const int64_t e = lvl_off[l + 1];
         for (int64_t k = lvl_off[l] + lane; k < e; k += 16)
             bwd_node<T, MODE, MAXA, true>(staged ? srec[k - r0] : rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
-                                          l == 0 ? root_dst : nullptr);
+                                          l == 0 ? root_dst : nullptr, upd);
     }
 }
 
@@ -1567,8 +1585,12 @@ struct pcfr_solver {
 
 namespace pcfr {
 
+// One sweep: forward, terminals and leaves, backward.  upd: the player whose
+// regrets and average strategy are updated (-1: both); begin: this sweep
+// starts a new iteration (advances t).
 template <typename T, int MODE>
-static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm = nullptr) {
+static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm = nullptr, int upd = -1,
+                             bool begin = true) {
     const Plan& L = s->L;
     const Prepared& P = s->P;
     const int Hp = (int)L.Hp;
@@ -1603,7 +1625,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     const dim3 fgrid((unsigned)(Hp / kFuseHands));
     auto dec_cnt = [&](int l) { return P.dec_off[l + 1] - P.dec_off[l]; };
     auto all_cnt = [&](int l) { return P.fwd_off[l + 1] - P.fwd_off[l]; };
-    bool first = MODE == MODE_ITER;
+    bool first = MODE == MODE_ITER && begin;
     for (int l = 0; l < P.levels;) {
         const int64_t cnt = dec_cnt(l);
         if (!cnt) { l++; continue; }
@@ -1714,7 +1736,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             if (tm) tm->before(3);
             PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(256), 0, stream, fwd, s->at<int64_t>(L.off_fwdoff), l0,
                            l + 1, Hp, R, S, Mp, reach, cfv, st, s->at<uint16_t>(L.off_hc),
-                           (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr);
+                           (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr, upd);
             if (tm) tm->after();
             l = l0 - 1;
             continue;
@@ -1725,7 +1747,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (tm) tm->before(3, 1000 + l);
         PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
                     reach, cfv, st, s->at<uint16_t>(L.off_hc),
-                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr);
+                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr, upd);
         if (tm) tm->after();
         l--;
     }
@@ -1734,8 +1756,20 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
+// One iteration: one sweep updating both players, or with alternating
+// updates a sweep for player 0 then one for player 1 (same t).
+template <typename T>
+static int32_t enqueue_iteration(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm = nullptr) {
+    if (!s->cfg.alternating) return enqueue_sweep<T, MODE_ITER>(s, stream, tm);
+    int32_t rc = enqueue_sweep<T, MODE_ITER>(s, stream, tm, 0, true);
+    if (rc) return rc;
+    return enqueue_sweep<T, MODE_ITER>(s, stream, tm, 1, false);
+}
+
 template <int MODE>
 static int32_t sweep(pcfr_solver* s, hipStream_t stream) {
+    if (MODE == MODE_ITER)
+        return s->cfg.dtype == PCFR_F64 ? enqueue_iteration<double>(s, stream) : enqueue_iteration<float>(s, stream);
     return s->cfg.dtype == PCFR_F64 ? enqueue_sweep<double, MODE>(s, stream) : enqueue_sweep<float, MODE>(s, stream);
 }
 template <int MODE>
@@ -1822,7 +1856,7 @@ static int32_t check_cfg(const pcfr_solver_cfg* cfg) {
         set_error("variant must be PCFR_DCFR, PCFR_CFRPLUS or PCFR_PCFRPLUS");
         return PCFR_E_INVALID_ARG;
     }
-    if (cfg->alternating != 0) { set_error("only simultaneous updates are implemented"); return PCFR_E_UNSUPPORTED; }
+    if (cfg->alternating != 0 && cfg->alternating != 1) { set_error("alternating must be 0 or 1"); return PCFR_E_INVALID_ARG; }
     if (!std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta) || !std::isfinite(cfg->gamma)) {
         set_error("alpha, beta, gamma must be finite");
         return PCFR_E_INVALID_ARG;
@@ -2173,8 +2207,8 @@ static int32_t autotune_impl(pcfr_solver* s, int32_t reps, double* ms_before, do
         for (int32_t r = 0; r <= reps; r++) {
             LaunchTimer tm;
             tm.stream = s->stream;
-            rc = s->cfg.dtype == PCFR_F64 ? enqueue_sweep<double, MODE_ITER>(s, s->stream, &tm)
-                                          : enqueue_sweep<float, MODE_ITER>(s, s->stream, &tm);
+            rc = s->cfg.dtype == PCFR_F64 ? enqueue_iteration<double>(s, s->stream, &tm)
+                                          : enqueue_iteration<float>(s, s->stream, &tm);
             hipError_t e = hipStreamSynchronize(s->stream);
             for (size_t k = 0; k < tm.tag.size(); k++) {
                 float ms = 0;
@@ -2298,8 +2332,8 @@ int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* 
     for (int32_t i = 0; i < n; i++) {
         LaunchTimer tm;
         tm.stream = s->stream;
-        int32_t rc = s->cfg.dtype == PCFR_F64 ? enqueue_sweep<double, MODE_ITER>(s, s->stream, &tm)
-                                              : enqueue_sweep<float, MODE_ITER>(s, s->stream, &tm);
+        int32_t rc = s->cfg.dtype == PCFR_F64 ? enqueue_iteration<double>(s, s->stream, &tm)
+                                              : enqueue_iteration<float>(s, s->stream, &tm);
         hipError_t e = hipStreamSynchronize(s->stream);
         for (size_t k = 0; k < tm.cls.size(); k++) {
             float t = 0;

@@ -20,9 +20,9 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("variant,alternating", [("cfr+", False), ("pcfr+", False), ("dcfr", True),
-                                                 ("pcfr+", True)])
-@pytest.mark.parametrize("which", ["river", "turn"])
+@pytest.mark.parametrize("variant,alternating,which", [
+    ("cfr+", False, "river"), ("pcfr+", False, "river"), ("dcfr", True, "river"), ("pcfr+", True, "river"),
+    ("cfr+", False, "turn"), ("pcfr+", False, "turn")])
 def test_variant_matches_oracle(variant, alternating, which):
     if which == "river":
         spec, r = I.river_config(4, support=140)
@@ -91,3 +91,31 @@ def test_alternating_flop_network_leaves_runs_and_resumes():
     b.iterate(4)
     assert a.t == 9 and b.t == 9
     assert a.save_state() == b.save_state()
+
+
+@pytest.mark.parametrize("variant", ["dcfr", "pcfr+"])
+def test_alternating_turn_close_to_oracle(variant):
+    """Alternating updates on a turn tree (chance nodes): per-iterate FP64
+    parity does not hold here.  Below a chance node the library's regrets
+    are K (= 44) times the oracle's -- it applies the chance probability
+    1/K at the chance node, the oracle inside each history's weight -- which
+    regret matching ignores; but after player 0's half-step some of player
+    1's infosets carry regrets at rounding level, whose sign flips their
+    strategy, and the two iterates drift apart (about 1e-3 pot after 40
+    iterations on every seed tried).  What both reach is checked instead:
+    the exploitability after 40 iterations within 5% of the oracle's
+    (measured 0.1-2.2%), and below its value after one iteration."""
+    spec, r = I.turn_config(5, support=40, spr=1.5)
+    say(f"case: alternating {variant} turn {spec}")
+    ot = O.Tree.holdem(**spec)
+    os_ = O.Solver(ot, r, support_only=True, variant=variant, alternating=True)
+    os_.iterate(40)
+    gs = P.Solver(P.Tree(**spec), r, P.SolverConfig(dtype="f64", variant=variant, alternating=1))
+    gs.iterate(1)
+    e1, _ = gs.exploitability()
+    gs.iterate(39)
+    eg, _ = gs.exploitability()
+    eo, _ = os_.exploitability()
+    say(f"  exploitability after 40: gpu {eg:.6f} oracle {eo:.6f} (after 1: {e1:.4f}) chips/hand")
+    assert abs(eg - eo) <= 0.05 * eo
+    assert eg < e1
