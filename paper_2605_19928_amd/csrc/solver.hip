@@ -1604,13 +1604,14 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     T* cfv = s->at<T>(L.off_cfv);
     T* Mp = s->cfg.variant == PCFR_PCFRPLUS ? s->at<T>(L.off_M) : nullptr;
     IterState* st = s->at<IterState>(L.off_state);
-    // the kernels are instantiated for at most 3, 6 or 12 actions; a level
+    // the kernels are instantiated for at most 3, 6, 8 or 12 actions; a level
     // uses the smallest that covers its nodes (fewer registers, more waves)
 #define PCFR_BUCKET(KER, l, ...)                                                                      \
     do {                                                                                              \
         const int ma = P.lvl_maxa[l];                                                                 \
         if (ma <= 3) hipLaunchKernelGGL((KER<T, MODE, 3>), __VA_ARGS__);                              \
         else if (ma <= 6) hipLaunchKernelGGL((KER<T, MODE, 6>), __VA_ARGS__);                         \
+        else if (ma <= 8) hipLaunchKernelGGL((KER<T, MODE, 8>), __VA_ARGS__);                         \
         else hipLaunchKernelGGL((KER<T, MODE, 12>), __VA_ARGS__);                                     \
     } while (0)
     // forward: decision nodes only; the first launch of an iteration also
@@ -1619,6 +1620,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     do {                                                                                              \
         if ((ma) <= 3) hipLaunchKernelGGL((KER<T, MODE, 3>), __VA_ARGS__);                            \
         else if ((ma) <= 6) hipLaunchKernelGGL((KER<T, MODE, 6>), __VA_ARGS__);                       \
+        else if ((ma) <= 8) hipLaunchKernelGGL((KER<T, MODE, 8>), __VA_ARGS__);                       \
         else hipLaunchKernelGGL((KER<T, MODE, 12>), __VA_ARGS__);                                     \
     } while (0)
     const int64_t fuse = s->sched.fuse_threads;
@@ -1829,7 +1831,7 @@ static int log2_bucket(int64_t x) {
     while (b < 62 && (int64_t(1) << (b + 1)) <= x) b++;
     return b;
 }
-static int action_bucket(int ma) { return ma <= 3 ? 3 : ma <= 6 ? 6 : 12; }
+static int action_bucket(int ma) { return ma <= 3 ? 3 : ma <= 6 ? 6 : ma <= 8 ? 8 : 12; }
 
 static std::tuple<int, int, int, int> sched_key(const pcfr_solver* s, int phase, int l) {
     const Prepared& P = s->P;
