@@ -240,6 +240,11 @@ int32_t pcfr_batch_exploitability(pcfr_solver* s, double* chips_per_hand, double
  * return.  Synchronises. */
 int32_t pcfr_autotune(pcfr_solver* s, int32_t reps, double* ms_before, double* ms_after);
 
+/* pcfr_autotune with the trial length chosen to spend about budget_ms > 0 of
+ * device time (at least one iteration per trial, at most 50).  Same
+ * preconditions and effects. */
+int32_t pcfr_batch_autotune(pcfr_solver* s, int32_t budget_ms);
+
 /* ---------------------------------------------------------------- leaf network
  * The value network f_theta of depth-limited solving (Sec. 3): a ReLU MLP
  * d_in -> width x depth -> d_out evaluated for all leaves of an iteration in

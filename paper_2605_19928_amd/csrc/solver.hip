@@ -76,6 +76,7 @@ struct IterState {
 };
 
 constexpr int kBlock = 256;       // terminal, leaf and helper kernels
+constexpr int kFuseHands = 64;    // hands per workgroup of the level-fused sweeps
 constexpr int kSweepMaxBlock = 512;
 constexpr int kSdHeader = 64;     // card-list offsets per board table (53 used)
 
@@ -98,6 +99,29 @@ __device__ __forceinline__ void st4(float* p, const V4<float>& v) {
 __device__ __forceinline__ void st4(double* p, const V4<double>& v) {
     *reinterpret_cast<double2*>(p) = make_double2(v.e[0], v.e[1]);
     *reinterpret_cast<double2*>(p + 2) = make_double2(v.e[2], v.e[3]);
+}
+
+// LDS-typed pointers (address space 3), so that accesses compile to ds_*
+// instructions and LDS-only barriers cover them.
+#define PCFR_LDS __attribute__((address_space(3)))
+template <typename T> using lds_ptr = PCFR_LDS T*;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ V4<float> ld4(const PCFR_LDS float* p) {
+    const f32x4 v = *reinterpret_cast<const PCFR_LDS f32x4*>(p);
+    return V4<float>{{v.x, v.y, v.z, v.w}};
+}
+__device__ __forceinline__ V4<double> ld4(const PCFR_LDS double* p) {
+    const f64x2 a = *reinterpret_cast<const PCFR_LDS f64x2*>(p);
+    const f64x2 b = *reinterpret_cast<const PCFR_LDS f64x2*>(p + 2);
+    return V4<double>{{a.x, a.y, b.x, b.y}};
+}
+__device__ __forceinline__ void st4(PCFR_LDS float* p, const V4<float>& v) {
+    *reinterpret_cast<PCFR_LDS f32x4*>(p) = f32x4{v.e[0], v.e[1], v.e[2], v.e[3]};
+}
+__device__ __forceinline__ void st4(PCFR_LDS double* p, const V4<double>& v) {
+    *reinterpret_cast<PCFR_LDS f64x2*>(p) = f64x2{v.e[0], v.e[1]};
+    *reinterpret_cast<PCFR_LDS f64x2*>(p + 2) = f64x2{v.e[2], v.e[3]};
 }
 
 __device__ __forceinline__ bool has_card(uint32_t hc, int c) {
@@ -208,12 +232,12 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restr
 // EARLY: load the average-strategy rows and own reach together with the
 // regrets (more registers, one memory round trip less on the critical path;
 // used where latency, not occupancy, limits).
-template <typename T, int MODE, int A, bool EARLY = false>
+template <typename T, int MODE, int A, bool EARLY = false, bool LV = false>
 __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
                                              T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
                                              T* __restrict__ cfv, const IterState* st,
                                              const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
-                                             int upd) {
+                                             int upd, lds_ptr<T> vl, int64_t id_lo, int hl) {
     const int p = nd.player, o = 1 - p;
     V4<T> x[A];
     V4<T> s_early[EARLY && MODE == MODE_ITER ? A : 1];
@@ -257,9 +281,16 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
     V4<T> vp = {{T(0), T(0), T(0), T(0)}}, vo = {{T(0), T(0), T(0), T(0)}};
 #pragma unroll
     for (int a = 0; a < A; a++) {
-        const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
-        c[a] = ld4(cc + (int64_t)p * Hp + h);
-        const V4<T> d = ld4(cc + (int64_t)o * Hp + h);
+        V4<T> d;
+        if constexpr (LV) {
+            const lds_ptr<T> lc = vl + (nd.first_child + a - id_lo) * 2 * kFuseHands + hl;
+            c[a] = ld4(lc + p * kFuseHands);
+            d = ld4(lc + o * kFuseHands);
+        } else {
+            const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
+            c[a] = ld4(cc + (int64_t)p * Hp + h);
+            d = ld4(cc + (int64_t)o * Hp + h);
+        }
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             vo.e[j] += d.e[j];
@@ -270,6 +301,11 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
     T* me = cfv + n * 2 * Hp;
     st4(me + (int64_t)p * Hp + h, vp);
     st4(me + (int64_t)o * Hp + h, vo);
+    if constexpr (LV) {
+        lds_ptr<T> lm = vl + (n - id_lo) * 2 * kFuseHands + hl;
+        st4(lm + p * kFuseHands, vp);
+        st4(lm + o * kFuseHands, vo);
+    }
     if (root_dst) {
         // with alternating updates each half keeps only the updated player's root values
         T* rd = root_dst + (int64_t)nd.sub * 2 * Hp;
@@ -319,11 +355,12 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
 }
 
 // Backward work of one node (decision or chance) for 4 hands.
-template <typename T, int MODE, int MAXA, bool EARLY = false>
+template <typename T, int MODE, int MAXA, bool EARLY = false, bool LV = false>
 __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __restrict__ R, T* __restrict__ S,
                                          T* __restrict__ Mp, const T* __restrict__ reach, T* __restrict__ cfv,
                                          const IterState* __restrict__ st, const uint16_t* __restrict__ hcards,
-                                         T* __restrict__ root_dst, int upd) {
+                                         T* __restrict__ root_dst, int upd, lds_ptr<T> vl = nullptr,
+                                         int64_t id_lo = 0, int hl = 0) {
     const int64_t n = nd.id;
     if (nd.type == PCFR_NODE_CHANCE) {
         // children in groups of 4: all loads of a group are issued before the
@@ -335,9 +372,15 @@ __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __re
 #pragma unroll
             for (int q = 0; q < G; q++) {
                 if (c0 + q < nd.n_child) {
-                    const T* cc = cfv + (int64_t)(nd.first_child + c0 + q) * 2 * Hp;
-                    u[q] = ld4(cc + h);
-                    w[q] = ld4(cc + Hp + h);
+                    if constexpr (LV) {
+                        const lds_ptr<T> lc = vl + (nd.first_child + c0 + q - id_lo) * 2 * kFuseHands + hl;
+                        u[q] = ld4(lc);
+                        w[q] = ld4(lc + kFuseHands);
+                    } else {
+                        const T* cc = cfv + (int64_t)(nd.first_child + c0 + q) * 2 * Hp;
+                        u[q] = ld4(cc + h);
+                        w[q] = ld4(cc + Hp + h);
+                    }
                 }
             }
 #pragma unroll
@@ -354,12 +397,17 @@ __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __re
         T* me = cfv + n * 2 * Hp;
         st4(me + h, a0);
         st4(me + Hp + h, a1);
+        if constexpr (LV) {
+            lds_ptr<T> lm = vl + (n - id_lo) * 2 * kFuseHands + hl;
+            st4(lm, a0);
+            st4(lm + kFuseHands, a1);
+        }
         return;
     }
     switch (nd.n_child) {
 #define PCFR_BWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, EARLY>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst, upd); \
+        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, EARLY, LV>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst, upd, vl, id_lo, hl); \
         break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
@@ -394,8 +442,8 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
 // in between: one launch instead of one per level.  Each workgroup has 16
 // hand groups of 4 hands times 16 node lanes; lvl_off holds the level starts
 // in the record list.
-constexpr int kFuseHands = 64;
-constexpr int kFuseRec = 256;     // node records staged in LDS per fused launch (else read from memory)
+constexpr int kFuseRec = 256;
+constexpr int64_t kFuseWinBytes = 96 * 1024;   // LDS value window of a fused backward run, at most     // node records staged in LDS per fused launch (else read from memory)
 
 // Copy n node records to LDS when they fit; every thread returns the same answer.
 __device__ __forceinline__ bool stage_records(DNode* dst, const DNode* __restrict__ src, int64_t n) {
@@ -437,7 +485,41 @@ __global__ __launch_bounds__(256) void k_forward_fused(const DNode* __restrict__
     }
 }
 
+// Levels l_hi - 1 down to l_lo of a fused backward run for one workgroup's
+// hands.  LV: node values go through the LDS window vl as well as memory and
+// the level barriers wait for LDS traffic only (the memory writes are read by
+// later launches alone).
+template <typename T, int MODE, int MAXA, bool LV>
+__device__ __forceinline__ void fused_bwd_levels(const DNode* __restrict__ rec, const DNode* srec, bool staged,
+                                                 int64_t r0, const int64_t* __restrict__ lvl_off, int l_lo, int l_hi,
+                                                 int Hp, T* __restrict__ R, T* __restrict__ S, T* __restrict__ Mp,
+                                                 const T* __restrict__ reach, T* __restrict__ cfv,
+                                                 const IterState* __restrict__ st,
+                                                 const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
+                                                 int upd, lds_ptr<T> vl, int64_t id_lo) {
+    const int hl = (threadIdx.x & 15) * 4, lane = threadIdx.x >> 4;
+    const int h = blockIdx.x * kFuseHands + hl;
+    for (int l = l_hi - 1; l >= l_lo; l--) {
+        if (l < l_hi - 1) {
+            if constexpr (LV) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            } else {
+                __syncthreads();
+            }
+        }
+        const int64_t e = lvl_off[l + 1];
+        for (int64_t k = lvl_off[l] + lane; k < e; k += 16)
+            bwd_node<T, MODE, MAXA, true, LV>(staged ? srec[k - r0] : rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
+                                              l == 0 ? root_dst : nullptr, upd, vl, id_lo, hl);
+    }
+}
+
 // Levels l_hi - 1 down to l_lo; root_dst as in k_backward (used when l_lo is 0).
+// win > 0: the values of nodes id_lo .. id_lo + win - 1 (the run's levels
+// and the level below them) for this workgroup's hands are kept in dynamic
+// LDS (win * 2 * kFuseHands elements); children are read there.
 template <typename T, int MODE, int MAXA>
 __global__ __launch_bounds__(256) void k_backward_fused(const DNode* __restrict__ rec,
                                                         const int64_t* __restrict__ lvl_off, int l_lo, int l_hi,
@@ -445,17 +527,26 @@ __global__ __launch_bounds__(256) void k_backward_fused(const DNode* __restrict_
                                                         T* __restrict__ Mp, const T* __restrict__ reach,
                                                         T* __restrict__ cfv, const IterState* __restrict__ st,
                                                         const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
-                                                        int upd) {
+                                                        int upd, int64_t id_lo, int win) {
     __shared__ DNode srec[kFuseRec];
+    extern __shared__ __align__(16) unsigned char dyn[];
     const int64_t r0 = lvl_off[l_lo], nrec = lvl_off[l_hi] - r0;
     const bool staged = stage_records(srec, rec + r0, nrec);
-    const int h = blockIdx.x * kFuseHands + (threadIdx.x & 15) * 4, lane = threadIdx.x >> 4;
-    for (int l = l_hi - 1; l >= l_lo; l--) {
-        if (l < l_hi - 1) __syncthreads();
-        const int64_t e = lvl_off[l + 1];
-        for (int64_t k = lvl_off[l] + lane; k < e; k += 16)
-            bwd_node<T, MODE, MAXA, true>(staged ? srec[k - r0] : rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
-                                          l == 0 ? root_dst : nullptr, upd);
+    if (win > 0) {
+        lds_ptr<T> vl = (lds_ptr<T>)(dyn);
+        const int chunks = win * 2 * (kFuseHands / 4);
+        for (int i = threadIdx.x; i < chunks; i += blockDim.x) {
+            const int node = i / (2 * (kFuseHands / 4)), rest = i - node * 2 * (kFuseHands / 4);
+            const int pl = rest / (kFuseHands / 4), q = rest - pl * (kFuseHands / 4);
+            st4(vl + (node * 2 + pl) * kFuseHands + q * 4,
+                ld4(cfv + (id_lo + node) * 2 * Hp + (int64_t)pl * Hp + blockIdx.x * kFuseHands + q * 4));
+        }
+        __syncthreads();
+        fused_bwd_levels<T, MODE, MAXA, true>(rec, srec, staged, r0, lvl_off, l_lo, l_hi, Hp, R, S, Mp, reach, cfv, st,
+                                              hcards, root_dst, upd, vl, id_lo);
+    } else {
+        fused_bwd_levels<T, MODE, MAXA, false>(rec, srec, staged, r0, lvl_off, l_lo, l_hi, Hp, R, S, Mp, reach, cfv,
+                                               st, hcards, root_dst, upd, nullptr, 0);
     }
 }
 
@@ -1202,6 +1293,7 @@ struct Prepared {
     std::vector<int64_t> dec_off;
     std::vector<DNode> fwd_rec, dec_rec;  // node records in the order of fwd and dec
     std::vector<int32_t> lvl_maxa;        // per level: most actions of a decision node
+    std::vector<int64_t> lvl_id_lo, lvl_id_hi;   // per depth: smallest node id, largest + 1 (all node kinds)
     std::vector<int32_t> folds, shows;    // terminal lists by kind
     std::vector<uint16_t> hcards;         // [n_sub][Hp]
     std::vector<int32_t> coff;            // [n_sub][53]
@@ -1382,6 +1474,15 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
         if (P.root_mask[0] >> c & 1ull) P.board_hot[c] = 1;
         else P.next_cards.push_back((int8_t)c);
     }
+    P.lvl_id_lo.assign(P.levels, INT64_MAX);
+    P.lvl_id_hi.assign(P.levels, 0);
+    for (int32_t g = 0; g < K; g++)
+        for (size_t i = 0; i < trees[g]->nodes.size(); i++) {
+            const int d = trees[g]->nodes[i].depth;
+            const int64_t gi = P.node_base[g] + (int64_t)i;
+            P.lvl_id_lo[d] = std::min(P.lvl_id_lo[d], gi);
+            P.lvl_id_hi[d] = std::max(P.lvl_id_hi[d], gi + 1);
+        }
     P.fwd_off.assign(P.levels + 1, 0);
     P.dec_off.assign(P.levels + 1, 0);
     P.lvl_maxa.assign(P.levels, 0);
@@ -1736,9 +1837,17 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             int l0 = l, ma = P.lvl_maxa[l];
             while (l0 > 0 && all_cnt(l0 - 1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[--l0]);
             if (tm) tm->before(3);
-            PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(256), 0, stream, fwd, s->at<int64_t>(L.off_fwdoff), l0,
-                           l + 1, Hp, R, S, Mp, reach, cfv, st, s->at<uint16_t>(L.off_hc),
-                           (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr, upd);
+            // LDS value window: node ids of levels l0 .. l + 1 (contiguous for
+            // one subgame; a forest's window spans other subgames and is used
+            // only while it fits)
+            int64_t id_lo = P.lvl_id_lo[l0], id_hi = 0;
+            for (int d = l0; d <= std::min(l + 1, P.levels - 1); d++) id_hi = std::max(id_hi, P.lvl_id_hi[d]);
+            int64_t win = MODE == MODE_ITER ? id_hi - id_lo : 0;
+            if (win * 2 * kFuseHands * (int64_t)sizeof(T) > kFuseWinBytes) win = 0;
+            PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(256), (size_t)(win * 2 * kFuseHands * sizeof(T)), stream,
+                           fwd, s->at<int64_t>(L.off_fwdoff), l0, l + 1, Hp, R, S, Mp, reach, cfv, st,
+                           s->at<uint16_t>(L.off_hc), (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr,
+                           upd, id_lo, (int)win);
             if (tm) tm->after();
             l = l0 - 1;
             continue;
@@ -1923,6 +2032,21 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes)
                            : hipFuncSetAttribute(reinterpret_cast<const void*>(&k_terminal<float>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+        if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+    }
+    {
+        // the fused backward's LDS value window may exceed the default 64 KB
+        const int dyn = (int)kFuseWinBytes;
+        hipError_t e = hipSuccess;
+        if (cfg->dtype == PCFR_F64) {
+            const void* f[4] = {(const void*)&k_backward_fused<double, MODE_ITER, 3>, (const void*)&k_backward_fused<double, MODE_ITER, 6>,
+                                (const void*)&k_backward_fused<double, MODE_ITER, 8>, (const void*)&k_backward_fused<double, MODE_ITER, 12>};
+            for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipFuncSetAttribute(f[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        } else {
+            const void* f[4] = {(const void*)&k_backward_fused<float, MODE_ITER, 3>, (const void*)&k_backward_fused<float, MODE_ITER, 6>,
+                                (const void*)&k_backward_fused<float, MODE_ITER, 8>, (const void*)&k_backward_fused<float, MODE_ITER, 12>};
+            for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipFuncSetAttribute(f[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+        }
         if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
     }
     // ranges and the joint mass of compatible pairs: r0 . (total1 - per-card sums + r1)
@@ -2255,6 +2379,25 @@ extern "C" {
 
 int32_t pcfr_autotune(pcfr_solver* s, int32_t reps, double* ms_before, double* ms_after) {
     return autotune_impl(s, reps, ms_before, ms_after);
+}
+
+int32_t pcfr_batch_autotune(pcfr_solver* s, int32_t budget_ms) {
+    if (!s || budget_ms <= 0) { set_error("null solver or non-positive budget"); return PCFR_E_INVALID_ARG; }
+    {
+        int64_t t = 0;
+        int32_t rc = pcfr_iteration(s, &t);
+        if (rc) return rc;
+        if (t != 0 || s->t_host != 0) { set_error("autotune needs a solver that has not iterated yet"); return PCFR_E_STATE; }
+    }
+    // the tuner runs about 12 trials of reps iterations (5 fusion thresholds,
+    // 4 workgroup sizes, before/after); one replay estimates an iteration
+    double ms = 0;
+    int32_t rc = time_replays(s, 1, &ms);
+    if (rc) return rc;
+    if ((rc = reset_state(s))) return rc;
+    const int32_t reps = (int32_t)std::max(1.0, std::min(50.0, budget_ms / (12.0 * std::max(ms, 1e-3))));
+    double before = 0, after = 0;
+    return autotune_impl(s, reps, &before, &after);
 }
 
 int32_t pcfr_solver_workspace_bytes(const pcfr_tree* tree, const pcfr_solver_cfg* cfg, size_t* bytes) {

@@ -83,6 +83,7 @@ _SIGS = {
     "pcfr_synchronize": (C.c_int32, [C.c_void_p]),
     "pcfr_profile_iterations": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "pcfr_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pcfr_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int32]),
     "pcfr_leafnet_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                           C.POINTER(C.c_double)]),
     "pcfr_leafnet_set_tiles": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
@@ -252,6 +253,10 @@ class Solver:
         a, b = C.c_double(), C.c_double()
         _check(lib().pcfr_autotune(self._h, int(reps), C.byref(a), C.byref(b)))
         return float(a.value), float(b.value)
+
+    def autotune_budget(self, budget_ms: int = 200):
+        """The autotuner within a device-time budget (fresh solvers only)."""
+        _check(lib().pcfr_batch_autotune(self._h, int(budget_ms)))
 
     def synchronize(self):
         _check(lib().pcfr_synchronize(self._h))

@@ -85,3 +85,13 @@ def test_autotune_keeps_iterates_bitwise():
             np.testing.assert_array_equal(tuned.strategy_of(g, int(n)), ref.strategy_of(g, int(n)))
     with pytest.raises(P.PcfrError):
         tuned.autotune(1)                  # only a solver that has not iterated can be tuned
+
+
+def test_autotune_with_budget():
+    cases = I.batch_config(7, count_nodes, n=6, river_share=1.0, lo=10, hi=2000)
+    trees = [P.Tree(**s) for s, _ in cases]
+    b = P.Batch(trees, np.stack([r for _, r in cases]))
+    b.autotune_budget(50)
+    assert b.t == 0
+    b.iterate(3)
+    assert b.t == 3
