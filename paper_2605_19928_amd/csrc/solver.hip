@@ -82,46 +82,40 @@ constexpr int kSdHeader = 64;     // card-list offsets per board table (53 used)
 
 // ------------------------------------------------------------ vector I/O
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
-template <typename T> struct V4 { T e[4]; };
+// NH consecutive hands of one row: the sweep kernels give each thread 4
+// hands (one 16-byte access for FP32) where a level fills the GPU, 1 where
+// a wave must cover one node's 64 hands.
+template <typename T, int NH> struct VN { T e[NH]; };
 
-__device__ __forceinline__ V4<float> ld4(const float* p) {
-    float4 v = *reinterpret_cast<const float4*>(p);
-    return V4<float>{{v.x, v.y, v.z, v.w}};
+template <int NH, typename T>
+__device__ __forceinline__ VN<T, NH> ldv(const T* p) {
+    VN<T, NH> v;
+    if constexpr (NH == 4 && sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        v.e[0] = q.x; v.e[1] = q.y; v.e[2] = q.z; v.e[3] = q.w;
+    } else if constexpr (NH % 2 == 0 && sizeof(T) == 8) {
+#pragma unroll
+        for (int i = 0; i < NH / 2; i++) {
+            const double2 q = reinterpret_cast<const double2*>(p)[i];
+            v.e[2 * i] = q.x; v.e[2 * i + 1] = q.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NH; i++) v.e[i] = p[i];
+    }
+    return v;
 }
-__device__ __forceinline__ V4<double> ld4(const double* p) {
-    double2 a = *reinterpret_cast<const double2*>(p);
-    double2 b = *reinterpret_cast<const double2*>(p + 2);
-    return V4<double>{{a.x, a.y, b.x, b.y}};
-}
-__device__ __forceinline__ void st4(float* p, const V4<float>& v) {
-    *reinterpret_cast<float4*>(p) = make_float4(v.e[0], v.e[1], v.e[2], v.e[3]);
-}
-__device__ __forceinline__ void st4(double* p, const V4<double>& v) {
-    *reinterpret_cast<double2*>(p) = make_double2(v.e[0], v.e[1]);
-    *reinterpret_cast<double2*>(p + 2) = make_double2(v.e[2], v.e[3]);
-}
-
-// LDS-typed pointers (address space 3), so that accesses compile to ds_*
-// instructions and LDS-only barriers cover them.
-#define PCFR_LDS __attribute__((address_space(3)))
-template <typename T> using lds_ptr = PCFR_LDS T*;
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ V4<float> ld4(const PCFR_LDS float* p) {
-    const f32x4 v = *reinterpret_cast<const PCFR_LDS f32x4*>(p);
-    return V4<float>{{v.x, v.y, v.z, v.w}};
-}
-__device__ __forceinline__ V4<double> ld4(const PCFR_LDS double* p) {
-    const f64x2 a = *reinterpret_cast<const PCFR_LDS f64x2*>(p);
-    const f64x2 b = *reinterpret_cast<const PCFR_LDS f64x2*>(p + 2);
-    return V4<double>{{a.x, a.y, b.x, b.y}};
-}
-__device__ __forceinline__ void st4(PCFR_LDS float* p, const V4<float>& v) {
-    *reinterpret_cast<PCFR_LDS f32x4*>(p) = f32x4{v.e[0], v.e[1], v.e[2], v.e[3]};
-}
-__device__ __forceinline__ void st4(PCFR_LDS double* p, const V4<double>& v) {
-    *reinterpret_cast<PCFR_LDS f64x2*>(p) = f64x2{v.e[0], v.e[1]};
-    *reinterpret_cast<PCFR_LDS f64x2*>(p + 2) = f64x2{v.e[2], v.e[3]};
+template <int NH, typename T>
+__device__ __forceinline__ void stv(T* p, const VN<T, NH>& v) {
+    if constexpr (NH == 4 && sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(v.e[0], v.e[1], v.e[2], v.e[3]);
+    } else if constexpr (NH % 2 == 0 && sizeof(T) == 8) {
+#pragma unroll
+        for (int i = 0; i < NH / 2; i++) reinterpret_cast<double2*>(p)[i] = make_double2(v.e[2 * i], v.e[2 * i + 1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NH; i++) p[i] = v.e[i];
+    }
 }
 
 __device__ __forceinline__ bool has_card(uint32_t hc, int c) {
@@ -167,37 +161,52 @@ __device__ __forceinline__ T strat(T x, T den, T inv_a) {
 
 // Only the actor's reach is written: child a's actor slot gets the actor's
 // reach times the probability of a; the other player's slot is shared.
-template <typename T, int MODE, int A>
+template <typename T, int MODE, int A, int NH>
 __device__ __forceinline__ void fwd_decision(const DNode& nd, int h, int Hp, int cbase, const T* __restrict__ R,
                                              const T* __restrict__ S, const T* __restrict__ Mp,
                                              T* __restrict__ reach) {
     // (a select, not nd.slot[player]: a dynamic index would move nd to memory)
-    const V4<T> rp = ld4(reach + (int64_t)(nd.player ? nd.slot[1] : nd.slot[0]) * Hp + h);
+    const VN<T, NH> rp = ldv<NH>(reach + (int64_t)(nd.player ? nd.slot[1] : nd.slot[0]) * Hp + h);
     const T* src = (MODE == MODE_ITER ? R : S) + (int64_t)nd.rs * Hp + h;
-    V4<T> x[A];
+    VN<T, NH> x[A];
 #pragma unroll
-    for (int a = 0; a < A; a++) x[a] = ld4(src + (int64_t)a * Hp);
+    for (int a = 0; a < A; a++) x[a] = ldv<NH>(src + (int64_t)a * Hp);
     if (MODE == MODE_ITER && Mp) {
 #pragma unroll
         for (int a = 0; a < A; a++) {
-            const V4<T> m = ld4(Mp + (int64_t)(nd.rs + a) * Hp + h);
+            const VN<T, NH> m = ldv<NH>(Mp + (int64_t)(nd.rs + a) * Hp + h);
 #pragma unroll
-            for (int j = 0; j < 4; j++) x[a].e[j] += m.e[j];
+            for (int j = 0; j < NH; j++) x[a].e[j] += m.e[j];
         }
     }
-    T den[4] = {T(0), T(0), T(0), T(0)};
+    T den[NH] = {};
 #pragma unroll
     for (int a = 0; a < A; a++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
+        for (int j = 0; j < NH; j++) den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
     const T inv_a = T(1) / T(A);
     T* dst = reach + (int64_t)(cbase + nd.rs) * Hp + h;
 #pragma unroll
     for (int a = 0; a < A; a++) {
-        V4<T> q;
+        VN<T, NH> q;
 #pragma unroll
-        for (int j = 0; j < 4; j++) q.e[j] = rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a);
-        st4(dst + (int64_t)a * Hp, q);
+        for (int j = 0; j < NH; j++) q.e[j] = rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a);
+        stv<NH>(dst + (int64_t)a * Hp, q);
+    }
+}
+
+template <typename T, int MODE, int MAXA, int NH>
+__device__ __forceinline__ void fwd_node(const DNode& nd, int h, int Hp, int cbase, const T* __restrict__ R,
+                                         const T* __restrict__ S, const T* __restrict__ Mp, T* __restrict__ reach) {
+    switch (nd.n_child) {
+#define PCFR_FWD_CASE(A) \
+    case A:              \
+        if constexpr (A <= MAXA) fwd_decision<T, MODE, A, NH>(nd, h, Hp, cbase, R, S, Mp, reach); \
+        break;
+        PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
+        PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
+#undef PCFR_FWD_CASE
+        default: break;
     }
 }
 
@@ -214,129 +223,107 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restr
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
-    const int h = (int)(gid - k * groups) * 4;
-    const DNode nd = level[k];
-    switch (nd.n_child) {
-#define PCFR_FWD_CASE(A) \
-    case A:              \
-        if constexpr (A <= MAXA) fwd_decision<T, MODE, A>(nd, h, Hp, cbase, R, S, Mp, reach); \
-        break;
-        PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
-        PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
-#undef PCFR_FWD_CASE
-        default: break;
-    }
+    fwd_node<T, MODE, MAXA, 4>(level[k], (int)(gid - k * groups) * 4, Hp, cbase, R, S, Mp, reach);
 }
 
 // ------------------------------------------------------------ backward
 // EARLY: load the average-strategy rows and own reach together with the
 // regrets (more registers, one memory round trip less on the critical path;
 // used where latency, not occupancy, limits).
-template <typename T, int MODE, int A, bool EARLY = false, bool LV = false>
+template <typename T, int MODE, int A, int NH, bool EARLY>
 __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
                                              T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
                                              T* __restrict__ cfv, const IterState* st,
                                              const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
-                                             int upd, lds_ptr<T> vl, int64_t id_lo, int hl) {
+                                             int upd) {
+    using V = VN<T, NH>;
     const int p = nd.player, o = 1 - p;
-    V4<T> x[A];
-    V4<T> s_early[EARLY && MODE == MODE_ITER ? A : 1];
-    V4<T> rp_early;
-    T den[4] = {T(0), T(0), T(0), T(0)};
+    V x[A];
+    V s_early[EARLY && MODE == MODE_ITER ? A : 1];
+    V rp_early;
+    T den[NH] = {};
     const T inv_a = T(1) / T(A);
     if (MODE != MODE_BR) {
         const T* src = (MODE == MODE_ITER ? (const T*)R : S) + (int64_t)nd.rs * Hp + h;
 #pragma unroll
-        for (int a = 0; a < A; a++) x[a] = ld4(src + (int64_t)a * Hp);
+        for (int a = 0; a < A; a++) x[a] = ldv<NH>(src + (int64_t)a * Hp);
         if constexpr (EARLY && MODE == MODE_ITER) {
 #pragma unroll
-            for (int a = 0; a < A; a++) s_early[a] = ld4(S + (int64_t)(nd.rs + a) * Hp + h);
-            rp_early = ld4(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
+            for (int a = 0; a < A; a++) s_early[a] = ldv<NH>(S + (int64_t)(nd.rs + a) * Hp + h);
+            rp_early = ldv<NH>(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
         }
         if (MODE == MODE_ITER && Mp) {
             // the strategy of this iteration matched R + m; R itself is read again below
 #pragma unroll
             for (int a = 0; a < A; a++) {
-                const V4<T> m = ld4(Mp + (int64_t)(nd.rs + a) * Hp + h);
+                const V m = ldv<NH>(Mp + (int64_t)(nd.rs + a) * Hp + h);
 #pragma unroll
-                for (int j = 0; j < 4; j++) x[a].e[j] += m.e[j];
+                for (int j = 0; j < NH; j++) x[a].e[j] += m.e[j];
             }
         }
 #pragma unroll
         for (int a = 0; a < A; a++)
 #pragma unroll
-            for (int j = 0; j < 4; j++)
+            for (int j = 0; j < NH; j++)
                 den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
     }
     // this iteration's strategy of each action (unused for a best response)
-    T sg[MODE == MODE_BR ? 1 : A][4];
+    T sg[MODE == MODE_BR ? 1 : A][NH];
     if constexpr (MODE != MODE_BR) {
 #pragma unroll
         for (int a = 0; a < A; a++)
 #pragma unroll
-            for (int j = 0; j < 4; j++) sg[a][j] = strat<T, MODE>(x[a].e[j], den[j], inv_a);
+            for (int j = 0; j < NH; j++) sg[a][j] = strat<T, MODE>(x[a].e[j], den[j], inv_a);
     }
     // children's values, read once
-    V4<T> c[A];
-    V4<T> vp = {{T(0), T(0), T(0), T(0)}}, vo = {{T(0), T(0), T(0), T(0)}};
+    V c[A];
+    V vp = {}, vo = {};
 #pragma unroll
     for (int a = 0; a < A; a++) {
-        V4<T> d;
-        if constexpr (LV) {
-            const lds_ptr<T> lc = vl + (nd.first_child + a - id_lo) * 2 * kFuseHands + hl;
-            c[a] = ld4(lc + p * kFuseHands);
-            d = ld4(lc + o * kFuseHands);
-        } else {
-            const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
-            c[a] = ld4(cc + (int64_t)p * Hp + h);
-            d = ld4(cc + (int64_t)o * Hp + h);
-        }
+        const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
+        c[a] = ldv<NH>(cc + (int64_t)p * Hp + h);
+        const V d = ldv<NH>(cc + (int64_t)o * Hp + h);
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < NH; j++) {
             vo.e[j] += d.e[j];
             if constexpr (MODE == MODE_BR) vp.e[j] = (a == 0 || c[a].e[j] > vp.e[j]) ? c[a].e[j] : vp.e[j];
             else vp.e[j] += sg[a][j] * c[a].e[j];
         }
     }
     T* me = cfv + n * 2 * Hp;
-    st4(me + (int64_t)p * Hp + h, vp);
-    st4(me + (int64_t)o * Hp + h, vo);
-    if constexpr (LV) {
-        lds_ptr<T> lm = vl + (n - id_lo) * 2 * kFuseHands + hl;
-        st4(lm + p * kFuseHands, vp);
-        st4(lm + o * kFuseHands, vo);
-    }
+    stv<NH>(me + (int64_t)p * Hp + h, vp);
+    stv<NH>(me + (int64_t)o * Hp + h, vo);
     if (root_dst) {
         // with alternating updates each half keeps only the updated player's root values
         T* rd = root_dst + (int64_t)nd.sub * 2 * Hp;
-        if (upd < 0 || upd == p) st4(rd + (int64_t)p * Hp + h, vp);
-        if (upd < 0 || upd == o) st4(rd + (int64_t)o * Hp + h, vo);
+        if (upd < 0 || upd == p) stv<NH>(rd + (int64_t)p * Hp + h, vp);
+        if (upd < 0 || upd == o) stv<NH>(rd + (int64_t)o * Hp + h, vo);
     }
     if (MODE == MODE_ITER && (upd < 0 || upd == p)) {
         // Stage 7: regret update, and the reach-weighted strategy added to the
         // average-strategy sum (Stage 1's accumulation, done here so that one
         // pass reads and writes both tables), each with its DCFR discount.
         const T dpos = (T)st->dpos, dneg = (T)st->dneg, wadd = (T)st->wadd, wmul = (T)st->wmul;
-        V4<T> rp;
+        V rp;
         if constexpr (EARLY) rp = rp_early;
-        else rp = ld4(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
+        else rp = ldv<NH>(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
         if (nd.dead != 0xffff) {
             const uint16_t* hc = hcards + (int64_t)nd.sub * Hp + h;
 #pragma unroll
-            for (int j = 0; j < 4; j++)
+            for (int j = 0; j < NH; j++)
                 if (!hand_alive(hc[j], nd.dead)) rp.e[j] = T(0);
         }
 #pragma unroll
         for (int a = 0; a < A; a++) {
             T* sp = S + (int64_t)(nd.rs + a) * Hp + h;
             T* rptr = R + (int64_t)(nd.rs + a) * Hp + h;
-            V4<T> sv;
+            V sv;
             if constexpr (EARLY) sv = s_early[a];
-            else sv = ld4(sp);
-            const V4<T> r0 = Mp ? ld4(rptr) : x[a];
-            V4<T> y, inst;
+            else sv = ldv<NH>(sp);
+            const V r0 = Mp ? ldv<NH>(rptr) : x[a];
+            V y, inst;
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
+            for (int j = 0; j < NH; j++) {
                 // v(I.a) - v(I) as sum_b sigma_b (v_a - v_b): exactly tied actions
                 // get exactly zero regret, whatever the rounding of v(I)
                 T ia = T(0);
@@ -347,67 +334,56 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
                 y.e[j] = r * (r > T(0) ? dpos : dneg);
                 sv.e[j] = (sv.e[j] + wadd * (rp.e[j] * sg[a][j])) * wmul;
             }
-            st4(rptr, y);
-            st4(sp, sv);
-            if (Mp) st4(Mp + (int64_t)(nd.rs + a) * Hp + h, inst);
+            stv<NH>(rptr, y);
+            stv<NH>(sp, sv);
+            if (Mp) stv<NH>(Mp + (int64_t)(nd.rs + a) * Hp + h, inst);
         }
     }
 }
 
-// Backward work of one node (decision or chance) for 4 hands.
-template <typename T, int MODE, int MAXA, bool EARLY = false, bool LV = false>
+// Backward work of one node (decision or chance) for NH hands.
+template <typename T, int MODE, int MAXA, int NH, bool EARLY>
 __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __restrict__ R, T* __restrict__ S,
                                          T* __restrict__ Mp, const T* __restrict__ reach, T* __restrict__ cfv,
                                          const IterState* __restrict__ st, const uint16_t* __restrict__ hcards,
-                                         T* __restrict__ root_dst, int upd, lds_ptr<T> vl = nullptr,
-                                         int64_t id_lo = 0, int hl = 0) {
+                                         T* __restrict__ root_dst, int upd) {
+    using V = VN<T, NH>;
     const int64_t n = nd.id;
     if (nd.type == PCFR_NODE_CHANCE) {
         // children in groups of 4: all loads of a group are issued before the
         // adds, which keep the children's order
         constexpr int G = 4;
-        V4<T> a0 = {{T(0), T(0), T(0), T(0)}}, a1 = a0;
+        V a0 = {}, a1 = {};
         for (int c0 = 0; c0 < nd.n_child; c0 += G) {
-            V4<T> u[G], w[G];
+            V u[G], w[G];
 #pragma unroll
             for (int q = 0; q < G; q++) {
                 if (c0 + q < nd.n_child) {
-                    if constexpr (LV) {
-                        const lds_ptr<T> lc = vl + (nd.first_child + c0 + q - id_lo) * 2 * kFuseHands + hl;
-                        u[q] = ld4(lc);
-                        w[q] = ld4(lc + kFuseHands);
-                    } else {
-                        const T* cc = cfv + (int64_t)(nd.first_child + c0 + q) * 2 * Hp;
-                        u[q] = ld4(cc + h);
-                        w[q] = ld4(cc + Hp + h);
-                    }
+                    const T* cc = cfv + (int64_t)(nd.first_child + c0 + q) * 2 * Hp;
+                    u[q] = ldv<NH>(cc + h);
+                    w[q] = ldv<NH>(cc + Hp + h);
                 }
             }
 #pragma unroll
             for (int q = 0; q < G; q++) {
                 if (c0 + q < nd.n_child) {
 #pragma unroll
-                    for (int j = 0; j < 4; j++) { a0.e[j] += u[q].e[j]; a1.e[j] += w[q].e[j]; }
+                    for (int j = 0; j < NH; j++) { a0.e[j] += u[q].e[j]; a1.e[j] += w[q].e[j]; }
                 }
             }
         }
         const T inv_k = T(1) / T(nd.aux);
 #pragma unroll
-        for (int j = 0; j < 4; j++) { a0.e[j] *= inv_k; a1.e[j] *= inv_k; }
+        for (int j = 0; j < NH; j++) { a0.e[j] *= inv_k; a1.e[j] *= inv_k; }
         T* me = cfv + n * 2 * Hp;
-        st4(me + h, a0);
-        st4(me + Hp + h, a1);
-        if constexpr (LV) {
-            lds_ptr<T> lm = vl + (n - id_lo) * 2 * kFuseHands + hl;
-            st4(lm, a0);
-            st4(lm + kFuseHands, a1);
-        }
+        stv<NH>(me + h, a0);
+        stv<NH>(me + Hp + h, a1);
         return;
     }
     switch (nd.n_child) {
 #define PCFR_BWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, EARLY, LV>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst, upd, vl, id_lo, hl); \
+        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, NH, EARLY && (sizeof(T) == 4 || A <= 8)>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst, upd); \
         break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
@@ -431,122 +407,59 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
-    bwd_node<T, MODE, MAXA>(level[k], (int)(gid - k * groups) * 4, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst,
-                            upd);
+    bwd_node<T, MODE, MAXA, 4, false>(level[k], (int)(gid - k * groups) * 4, Hp, R, S, Mp, reach, cfv, st, hcards,
+                                      root_dst, upd);
 }
 
 // Level-fused sweeps for runs of levels too small to fill the GPU.  A node's
 // reach at hand h depends only on its parent's at h, and its values at h only
 // on its children's at h, so a workgroup that owns a slice of kFuseHands
 // hands can run consecutive levels for that slice with workgroup barriers
-// in between: one launch instead of one per level.  Each workgroup has 16
-// hand groups of 4 hands times 16 node lanes; lvl_off holds the level starts
-// in the record list.
-constexpr int kFuseRec = 256;
-constexpr int64_t kFuseWinBytes = 96 * 1024;   // LDS value window of a fused backward run, at most     // node records staged in LDS per fused launch (else read from memory)
+// in between: one launch instead of one per level.  Each wave takes one
+// node at a time, one hand per lane, so that the node (its record, its
+// action count, its kind) is the same across the wave: scalar record loads
+// and no divergence between nodes of different shapes.  The workgroup's
+// kFuseWaves waves are its node lanes; lvl_off holds the level starts in the
+// record list.
+constexpr int kFuseWaves = 16;
+constexpr int kFuseBlock = kFuseWaves * 64;
+static_assert(kFuseHands == 64, "one hand per lane of a wave");
 
-// Copy n node records to LDS when they fit; every thread returns the same answer.
-__device__ __forceinline__ bool stage_records(DNode* dst, const DNode* __restrict__ src, int64_t n) {
-    if (n > kFuseRec) return false;
-    const int words = (int)n * (int)(sizeof(DNode) / 16);
-    for (int i = threadIdx.x; i < words; i += blockDim.x)
-        reinterpret_cast<u32x4*>(dst)[i] = reinterpret_cast<const u32x4*>(src)[i];
-    __syncthreads();
-    return true;
-}
+__device__ __forceinline__ int fuse_lane() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 template <typename T, int MODE, int MAXA>
-__global__ __launch_bounds__(256) void k_forward_fused(const DNode* __restrict__ rec,
-                                                       const int64_t* __restrict__ lvl_off, int l0, int l1, int Hp,
-                                                       int cbase, const T* __restrict__ R, const T* __restrict__ S,
-                                                       const T* __restrict__ Mp, T* __restrict__ reach,
-                                                       IterState* begin) {
-    __shared__ DNode srec[kFuseRec];
-    const int64_t r0 = lvl_off[l0], nrec = lvl_off[l1] - r0;
-    const bool staged = stage_records(srec, rec + r0, nrec);
+__global__ __launch_bounds__(kFuseBlock) void k_forward_fused(const DNode* __restrict__ rec,
+                                                              const int64_t* __restrict__ lvl_off, int l0, int l1,
+                                                              int Hp, int cbase, const T* __restrict__ R,
+                                                              const T* __restrict__ S, const T* __restrict__ Mp,
+                                                              T* __restrict__ reach, IterState* begin) {
     if (begin && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin);
-    const int h = blockIdx.x * kFuseHands + (threadIdx.x & 15) * 4, lane = threadIdx.x >> 4;
+    const int h = blockIdx.x * kFuseHands + (int)(threadIdx.x & 63), lane = fuse_lane();
     for (int l = l0; l < l1; l++) {
         if (l > l0) __syncthreads();
         const int64_t e = lvl_off[l + 1];
-        for (int64_t k = lvl_off[l] + lane; k < e; k += 16) {
-            const DNode nd = staged ? srec[k - r0] : rec[k];
-            switch (nd.n_child) {
-#define PCFR_FWD_CASE(A) \
-    case A:              \
-        if constexpr (A <= MAXA) fwd_decision<T, MODE, A>(nd, h, Hp, cbase, R, S, Mp, reach); \
-        break;
-                PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
-                PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
-#undef PCFR_FWD_CASE
-                default: break;
-            }
-        }
-    }
-}
-
-// Levels l_hi - 1 down to l_lo of a fused backward run for one workgroup's
-// hands.  LV: node values go through the LDS window vl as well as memory and
-// the level barriers wait for LDS traffic only (the memory writes are read by
-// later launches alone).
-template <typename T, int MODE, int MAXA, bool LV>
-__device__ __forceinline__ void fused_bwd_levels(const DNode* __restrict__ rec, const DNode* srec, bool staged,
-                                                 int64_t r0, const int64_t* __restrict__ lvl_off, int l_lo, int l_hi,
-                                                 int Hp, T* __restrict__ R, T* __restrict__ S, T* __restrict__ Mp,
-                                                 const T* __restrict__ reach, T* __restrict__ cfv,
-                                                 const IterState* __restrict__ st,
-                                                 const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
-                                                 int upd, lds_ptr<T> vl, int64_t id_lo) {
-    const int hl = (threadIdx.x & 15) * 4, lane = threadIdx.x >> 4;
-    const int h = blockIdx.x * kFuseHands + hl;
-    for (int l = l_hi - 1; l >= l_lo; l--) {
-        if (l < l_hi - 1) {
-            if constexpr (LV) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                __builtin_amdgcn_s_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-            } else {
-                __syncthreads();
-            }
-        }
-        const int64_t e = lvl_off[l + 1];
-        for (int64_t k = lvl_off[l] + lane; k < e; k += 16)
-            bwd_node<T, MODE, MAXA, true, LV>(staged ? srec[k - r0] : rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
-                                              l == 0 ? root_dst : nullptr, upd, vl, id_lo, hl);
+        for (int64_t k = lvl_off[l] + lane; k < e; k += kFuseWaves)
+            fwd_node<T, MODE, MAXA, 1>(rec[k], h, Hp, cbase, R, S, Mp, reach);
     }
 }
 
 // Levels l_hi - 1 down to l_lo; root_dst as in k_backward (used when l_lo is 0).
-// win > 0: the values of nodes id_lo .. id_lo + win - 1 (the run's levels
-// and the level below them) for this workgroup's hands are kept in dynamic
-// LDS (win * 2 * kFuseHands elements); children are read there.
 template <typename T, int MODE, int MAXA>
-__global__ __launch_bounds__(256) void k_backward_fused(const DNode* __restrict__ rec,
-                                                        const int64_t* __restrict__ lvl_off, int l_lo, int l_hi,
-                                                        int Hp, T* __restrict__ R, T* __restrict__ S,
-                                                        T* __restrict__ Mp, const T* __restrict__ reach,
-                                                        T* __restrict__ cfv, const IterState* __restrict__ st,
-                                                        const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
-                                                        int upd, int64_t id_lo, int win) {
-    __shared__ DNode srec[kFuseRec];
-    extern __shared__ __align__(16) unsigned char dyn[];
-    const int64_t r0 = lvl_off[l_lo], nrec = lvl_off[l_hi] - r0;
-    const bool staged = stage_records(srec, rec + r0, nrec);
-    if (win > 0) {
-        lds_ptr<T> vl = (lds_ptr<T>)(dyn);
-        const int chunks = win * 2 * (kFuseHands / 4);
-        for (int i = threadIdx.x; i < chunks; i += blockDim.x) {
-            const int node = i / (2 * (kFuseHands / 4)), rest = i - node * 2 * (kFuseHands / 4);
-            const int pl = rest / (kFuseHands / 4), q = rest - pl * (kFuseHands / 4);
-            st4(vl + (node * 2 + pl) * kFuseHands + q * 4,
-                ld4(cfv + (id_lo + node) * 2 * Hp + (int64_t)pl * Hp + blockIdx.x * kFuseHands + q * 4));
-        }
-        __syncthreads();
-        fused_bwd_levels<T, MODE, MAXA, true>(rec, srec, staged, r0, lvl_off, l_lo, l_hi, Hp, R, S, Mp, reach, cfv, st,
-                                              hcards, root_dst, upd, vl, id_lo);
-    } else {
-        fused_bwd_levels<T, MODE, MAXA, false>(rec, srec, staged, r0, lvl_off, l_lo, l_hi, Hp, R, S, Mp, reach, cfv,
-                                               st, hcards, root_dst, upd, nullptr, 0);
+__global__ __launch_bounds__(kFuseBlock) void k_backward_fused(const DNode* __restrict__ rec,
+                                                               const int64_t* __restrict__ lvl_off, int l_lo,
+                                                               int l_hi, int Hp, T* __restrict__ R,
+                                                               T* __restrict__ S, T* __restrict__ Mp,
+                                                               const T* __restrict__ reach, T* __restrict__ cfv,
+                                                               const IterState* __restrict__ st,
+                                                               const uint16_t* __restrict__ hcards,
+                                                               T* __restrict__ root_dst, int upd) {
+    const int h = blockIdx.x * kFuseHands + (int)(threadIdx.x & 63), lane = fuse_lane();
+    for (int l = l_hi - 1; l >= l_lo; l--) {
+        if (l < l_hi - 1) __syncthreads();
+        const int64_t e = lvl_off[l + 1];
+        for (int64_t k = lvl_off[l] + lane; k < e; k += kFuseWaves)
+            bwd_node<T, MODE, MAXA, 1, true>(rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
+                                             l == 0 ? root_dst : nullptr, upd);
     }
 }
 
@@ -1293,7 +1206,6 @@ struct Prepared {
     std::vector<int64_t> dec_off;
     std::vector<DNode> fwd_rec, dec_rec;  // node records in the order of fwd and dec
     std::vector<int32_t> lvl_maxa;        // per level: most actions of a decision node
-    std::vector<int64_t> lvl_id_lo, lvl_id_hi;   // per depth: smallest node id, largest + 1 (all node kinds)
     std::vector<int32_t> folds, shows;    // terminal lists by kind
     std::vector<uint16_t> hcards;         // [n_sub][Hp]
     std::vector<int32_t> coff;            // [n_sub][53]
@@ -1474,15 +1386,6 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
         if (P.root_mask[0] >> c & 1ull) P.board_hot[c] = 1;
         else P.next_cards.push_back((int8_t)c);
     }
-    P.lvl_id_lo.assign(P.levels, INT64_MAX);
-    P.lvl_id_hi.assign(P.levels, 0);
-    for (int32_t g = 0; g < K; g++)
-        for (size_t i = 0; i < trees[g]->nodes.size(); i++) {
-            const int d = trees[g]->nodes[i].depth;
-            const int64_t gi = P.node_base[g] + (int64_t)i;
-            P.lvl_id_lo[d] = std::min(P.lvl_id_lo[d], gi);
-            P.lvl_id_hi[d] = std::max(P.lvl_id_hi[d], gi + 1);
-        }
     P.fwd_off.assign(P.levels + 1, 0);
     P.dec_off.assign(P.levels + 1, 0);
     P.lvl_maxa.assign(P.levels, 0);
@@ -1736,7 +1639,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             int l1 = l + 1, ma = P.lvl_maxa[l];
             while (l1 < P.levels && dec_cnt(l1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[l1++]);
             if (tm) tm->before(1);
-            PCFR_BUCKET_MA(k_forward_fused, ma, fgrid, dim3(256), 0, stream, dec, s->at<int64_t>(L.off_decoff), l,
+            PCFR_BUCKET_MA(k_forward_fused, ma, fgrid, dim3(kFuseBlock), 0, stream, dec, s->at<int64_t>(L.off_decoff), l,
                            l1, Hp, (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr);
             if (tm) tm->after();
             first = false;
@@ -1837,17 +1740,10 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             int l0 = l, ma = P.lvl_maxa[l];
             while (l0 > 0 && all_cnt(l0 - 1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[--l0]);
             if (tm) tm->before(3);
-            // LDS value window: node ids of levels l0 .. l + 1 (contiguous for
-            // one subgame; a forest's window spans other subgames and is used
-            // only while it fits)
-            int64_t id_lo = P.lvl_id_lo[l0], id_hi = 0;
-            for (int d = l0; d <= std::min(l + 1, P.levels - 1); d++) id_hi = std::max(id_hi, P.lvl_id_hi[d]);
-            int64_t win = MODE == MODE_ITER ? id_hi - id_lo : 0;
-            if (win * 2 * kFuseHands * (int64_t)sizeof(T) > kFuseWinBytes) win = 0;
-            PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(256), (size_t)(win * 2 * kFuseHands * sizeof(T)), stream,
+            PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(kFuseBlock), 0, stream,
                            fwd, s->at<int64_t>(L.off_fwdoff), l0, l + 1, Hp, R, S, Mp, reach, cfv, st,
                            s->at<uint16_t>(L.off_hc), (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr,
-                           upd, id_lo, (int)win);
+                           upd);
             if (tm) tm->after();
             l = l0 - 1;
             continue;
@@ -2032,21 +1928,6 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes)
                            : hipFuncSetAttribute(reinterpret_cast<const void*>(&k_terminal<float>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
-        if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
-    }
-    {
-        // the fused backward's LDS value window may exceed the default 64 KB
-        const int dyn = (int)kFuseWinBytes;
-        hipError_t e = hipSuccess;
-        if (cfg->dtype == PCFR_F64) {
-            const void* f[4] = {(const void*)&k_backward_fused<double, MODE_ITER, 3>, (const void*)&k_backward_fused<double, MODE_ITER, 6>,
-                                (const void*)&k_backward_fused<double, MODE_ITER, 8>, (const void*)&k_backward_fused<double, MODE_ITER, 12>};
-            for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipFuncSetAttribute(f[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-        } else {
-            const void* f[4] = {(const void*)&k_backward_fused<float, MODE_ITER, 3>, (const void*)&k_backward_fused<float, MODE_ITER, 6>,
-                                (const void*)&k_backward_fused<float, MODE_ITER, 8>, (const void*)&k_backward_fused<float, MODE_ITER, 12>};
-            for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipFuncSetAttribute(f[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-        }
         if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
     }
     // ranges and the joint mass of compatible pairs: r0 . (total1 - per-card sums + r1)
