@@ -867,66 +867,124 @@ __device__ __forceinline__ void stage_leaf(const T* __restrict__ r0, const T* __
 
 // Per-leaf reach aggregates shared by the zero-sum and combine kernels:
 // agg[leaf] = [2][53], each player's 52 per-card sums (reach of the hands
-// holding the card) then the total; written by the leaf-input workgroup of
-// the leaf's first next card.
+// holding the card) then the total; written by k_leaf_ranges.
 constexpr int kAgg = 106;
 
-// Stage 2's batched leaf input (Sec. 4.2): one row per (leaf, next card c):
-// each player's reach with the hands holding c removed, normalised to sum 1,
-// over the 1326 combos; then the board after c as 52 one-hot entries; then
-// the stack-to-pot ratio at the leaf; bf16, zero padded to ldx.
+// Stage 2's batched leaf input (Sec. 4.2) for Stage 5's network (Sec. 4.3):
+// one row per (leaf, next card c): each player's reach with the hands
+// holding c removed, normalised to sum 1, over the 1326 combos; then the
+// board after c as 52 one-hot entries; then the stack-to-pot ratio at the
+// leaf; bf16, zero padded to ldx.  k_leaf_ranges works once per leaf: dense
+// combo-indexed ranges, the aggregates, and per card c the reciprocal of
+// S_p(c), the reach of the hands without c (zero when nothing is left);
+// k_leaf_x then writes the rows.
+constexpr int kComboPad = 1344;           // 1326 combos padded to 64
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__ nodes,
-                                                       const int32_t* __restrict__ leaves, const float* __restrict__ spr,
-                                                       int n_next, const int8_t* __restrict__ next_cards, int Hp,
-                                                       const T* __restrict__ reach, const uint16_t* __restrict__ hcards,
-                                                       const int16_t* __restrict__ combo_hand,
-                                                       const int32_t* __restrict__ coff,
-                                                       const int16_t* __restrict__ chands,
-                                                       const uint8_t* __restrict__ board_hot, uint16_t* __restrict__ X,
-                                                       int ldx, T* __restrict__ agg) {
+__global__ __launch_bounds__(kBlock) void k_leaf_ranges(const DNode* __restrict__ nodes,
+                                                        const int32_t* __restrict__ leaves, int Hp,
+                                                        const T* __restrict__ reach,
+                                                        const int16_t* __restrict__ combo_hand,
+                                                        T* __restrict__ Rc, double* __restrict__ sinv,
+                                                        T* __restrict__ agg) {
+    constexpr int RI = (2 * kComboPad + kBlock - 1) / kBlock;
     __shared__ T x[2][kMaxHp];
-    __shared__ T cs[2][52];
-    __shared__ T txch[2 * kWaves];
+    __shared__ double xc[2][kComboPad];
     __shared__ double dxch[2 * kWaves];
-    const int q = blockIdx.x;
-    const int li = q / n_next, k = q - li * n_next;
-    const int c = next_cards[k];
+    const int li = blockIdx.x, tid = threadIdx.x;
     const DNode nd = nodes[leaves[li]];
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
-    const int tid = threadIdx.x;
-    if (k == 0) {
-        T t0, t1;
-        stage_leaf<T, T>(r0, r1, Hp, coff, chands, x, cs, txch, t0, t1);
-        T* out = agg + (int64_t)li * kAgg;
-        if (tid < 104) out[(tid / 52) * 53 + tid % 52] = cs[tid / 52][tid % 52];
-        if (tid == 0) { out[52] = t0; out[105] = t1; }
-    }
-    // normaliser: the reach of the hands without c
-    double S0 = 0.0, S1 = 0.0;
+    // every load of the thread first: its hands' reach and its combos' hands
+    T a[kHandIt], b[kHandIt];
+    int hk[RI];
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int h = tid + i * kBlock;
-        if (h < Hp && !has_card(hcards[h], c)) { S0 += (double)r0[h]; S1 += (double)r1[h]; }
+        a[i] = h < Hp ? r0[h] : T(0);
+        b[i] = h < Hp ? r1[h] : T(0);
     }
-    block_sum2(S0, S1, dxch);
-    uint16_t* row = X + (int64_t)q * ldx;
-    for (int col = threadIdx.x; col < ldx; col += kBlock) {
-        float v = 0.f;
+#pragma unroll
+    for (int i = 0; i < RI; i++) {
+        const int k = tid + i * kBlock, kk = k >= kComboPad ? k - kComboPad : k;
+        hk[i] = (k < 2 * kComboPad && kk < kCombos) ? combo_hand[kk] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h < Hp) { x[0][h] = a[i]; x[1][h] = b[i]; }
+    }
+    __syncthreads();
+    // dense combo-indexed ranges (to memory for the products, to LDS for the sums)
+    T* rc = Rc + (int64_t)li * 2 * kComboPad;
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RI; i++) {
+        const int k = tid + i * kBlock;
+        if (k < 2 * kComboPad) {
+            const int p = k >= kComboPad, kk = k - p * kComboPad;
+            const T v = hk[i] >= 0 ? x[p][hk[i]] : T(0);
+            rc[k] = v;
+            xc[p][kk] = (double)v;
+            if (p) t1 += (double)v; else t0 += (double)v;
+        }
+    }
+    block_sum2(t0, t1, dxch);      // synchronises: xc is visible after it
+    if (tid < 104) {
+        // per-card sums over the 51 combos holding the card, then 1/S for each card
+        const int p = tid / 52, c = tid - p * 52;
+        double cs = 0.0;
+#pragma unroll
+        for (int xi = 0; xi < 51; xi++) cs += xc[p][combo_index(c, xi < c ? xi : xi + 1)];
+        agg[(int64_t)li * kAgg + p * 53 + c] = (T)cs;
+        // a remainder below 1e-9 of the total is rounding of an empty set
+        const double tot = p ? t1 : t0, rest = tot - cs;
+        sinv[((int64_t)li * 2 + p) * 52 + c] = rest > 1e-9 * tot ? 1.0 / rest : 0.0;
+    }
+    if (tid == 0) { agg[(int64_t)li * kAgg + 52] = (T)t0; agg[(int64_t)li * kAgg + 105] = (T)t1; }
+}
+
+// One input row per workgroup, 8 consecutive columns per thread (one
+// 16-byte store).  Normalised entries are formed in double and rounded
+// once to float, as r / S would be.
+constexpr int kLeafXBlock = 384;
+template <typename T>
+__global__ __launch_bounds__(kLeafXBlock) void k_leaf_x(const T* __restrict__ Rc, const double* __restrict__ sinv,
+                                                        const float* __restrict__ spr, int n_next,
+                                                        const int8_t* __restrict__ next_cards, int4 board, int ldx,
+                                                        uint16_t* __restrict__ X) {
+    const int row = blockIdx.x, leaf = row / n_next, ci = row - leaf * n_next;
+    const int c = next_cards[ci];
+    const int col0 = threadIdx.x * 8;
+    if (col0 >= ldx) return;
+    const T* rc = Rc + (int64_t)leaf * 2 * kComboPad;
+    const double s0 = sinv[(int64_t)leaf * 104 + c], s1 = sinv[(int64_t)leaf * 104 + 52 + c];
+    // cards (a > b) of the combo in column col0 of its player's block
+    int k = col0 >= kCombos ? col0 - kCombos : col0;
+    int a = (int)((1.f + sqrtf(1.f + 8.f * (float)k)) * 0.5f);
+    if (a * (a - 1) / 2 > k) a--;
+    else if ((a + 1) * a / 2 <= k) a++;
+    int b = k - a * (a - 1) / 2;
+    uint16_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int col = col0 + j;
+        float x = 0.f;
         if (col < 2 * kCombos) {
-            const int p = col >= kCombos;
-            const int h = combo_hand[col - p * kCombos];
-            const double S = p ? S1 : S0;
-            if (h >= 0 && S > 0.0 && !has_card(hcards[h], c)) v = (float)((double)(p ? r1[h] : r0[h]) / S);
+            if (col == kCombos) { a = 1; b = 0; }           // player 1's block restarts at combo 0
+            const int pp = col >= kCombos, kk = col - pp * kCombos;
+            if (a != c && b != c) x = (float)((double)rc[pp * kComboPad + kk] * (pp ? s1 : s0));
+            if (++b == a) { a++; b = 0; }
         } else if (col < 2 * kCombos + 52) {
             const int card = col - 2 * kCombos;
-            v = (board_hot[card] || card == c) ? 1.f : 0.f;
+            x = (card == c || card == board.x || card == board.y || card == board.z || card == board.w) ? 1.f : 0.f;
         } else if (col == 2 * kCombos + 52) {
-            v = spr[li];
+            x = spr[leaf];
         }
-        row[col] = to_bf16(v);
+        v[j] = to_bf16(x);
     }
+    *reinterpret_cast<u32x4*>(X + (int64_t)row * ldx + col0) =
+        u32x4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+              (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
 }
 
 // Zero-sum correction of the network's outputs (a reading: the paper does not
@@ -1191,8 +1249,10 @@ struct Plan {
     size_t esz;
     size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_zs, off_agg, off_next, off_hot, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart, total;
+        off_potk, off_zs, off_agg, off_rc, off_sinv, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
+        total;
     size_t lds_bytes, lds_fold, lds_show;
+    int4 board4;                          // root board cards, -1 past the last
 };
 
 struct Prepared {
@@ -1229,7 +1289,7 @@ struct Prepared {
     std::vector<float> net_spr;
     std::vector<double> net_potk;
     std::vector<int8_t> next_cards;
-    std::vector<uint8_t> board_hot;
+    std::vector<int32_t> board;           // root board cards (subgame 0)
 };
 
 // Host preprocessing of a forest of subgames: node records, merged level work
@@ -1381,9 +1441,8 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
             }
         P.n_allin = (int64_t)t.count[PCFR_NODE_ALLIN_LEAF];
     }
-    P.board_hot.assign(52, 0);
     for (int c = 0; c < 52; c++) {
-        if (P.root_mask[0] >> c & 1ull) P.board_hot[c] = 1;
+        if (P.root_mask[0] >> c & 1ull) P.board.push_back(c);
         else P.next_cards.push_back((int8_t)c);
     }
     P.fwd_off.assign(P.levels + 1, 0);
@@ -1514,6 +1573,11 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_stage = take(L.esz * kMaxActions * L.Hp);
     L.n_eq = (int64_t)P.eq_leaves.size();
     L.n_net = (int64_t)P.net_leaves.size();
+    {
+        int b4[4] = {-1, -1, -1, -1};
+        for (size_t i = 0; i < P.board.size() && i < 4; i++) b4[i] = P.board[i];
+        L.board4 = make_int4(b4[0], b4[1], b4[2], b4[3]);
+    }
     L.n_next = (int64_t)P.next_cards.size();
     L.off_et = take(L.n_eq ? L.esz * L.Hp * L.Hp : 0);
     L.off_eq = take(sizeof(int32_t) * std::max<int64_t>(L.n_eq, 1));
@@ -1523,8 +1587,9 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_potk = take(sizeof(double) * std::max<int64_t>(L.n_net, 1));
     L.off_zs = take(L.esz * std::max<int64_t>(L.n_net * L.n_next, 1));
     L.off_agg = take(L.esz * kAgg * std::max<int64_t>(L.n_net, 1));
+    L.off_rc = take(L.esz * 2 * kComboPad * std::max<int64_t>(L.n_net, 1));
+    L.off_sinv = take(sizeof(double) * 104 * std::max<int64_t>(L.n_net, 1));
     L.off_next = take(64);
-    L.off_hot = take(64);
     L.off_c2h = take(sizeof(int16_t) * kCombos);
     L.off_h2c = take(sizeof(int16_t) * L.Hp);
     L.off_roots = take(sizeof(int32_t) * P.n_sub);
@@ -1697,12 +1762,12 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         pcfr_leafnet* net = s->net;
         const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes,
-                           s->at<int32_t>(L.off_net), s->at<float>(L.off_spr), (int)L.n_next,
-                           s->at<int8_t>(L.off_next), Hp, reach, s->at<uint16_t>(L.off_hc),
-                           s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
-                           s->at<uint8_t>(L.off_hot), reinterpret_cast<uint16_t*>(net->ws + net->P.off_x),
-                           (int)net->P.pdims[0], s->at<T>(L.off_agg));
+        hipLaunchKernelGGL((k_leaf_ranges<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream, nodes,
+                           s->at<int32_t>(L.off_net), Hp, reach, s->at<int16_t>(L.off_c2h), s->at<T>(L.off_rc),
+                           s->at<double>(L.off_sinv), s->at<T>(L.off_agg));
+        hipLaunchKernelGGL((k_leaf_x<T>), dim3((unsigned)rows), dim3(kLeafXBlock), 0, stream, s->at<T>(L.off_rc),
+                           s->at<double>(L.off_sinv), s->at<float>(L.off_spr), (int)L.n_next, s->at<int8_t>(L.off_next),
+                           L.board4, (int)net->P.pdims[0], reinterpret_cast<uint16_t*>(net->ws + net->P.off_x));
         if (tm) tm->after();
         int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
         if (rc) return rc;
@@ -2004,7 +2069,6 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         if ((rc = up(L.off_c2h, c2h.data(), sizeof(int16_t) * kCombos))) return rc;
         if ((rc = up(L.off_h2c, h2c.data(), sizeof(int16_t) * L.Hp))) return rc;
         if ((rc = up(L.off_next, P.next_cards.data(), P.next_cards.size()))) return rc;
-        if ((rc = up(L.off_hot, P.board_hot.data(), 52))) return rc;
         if ((rc = up(L.off_eq, P.eq_leaves.data(), sizeof(int32_t) * P.eq_leaves.size()))) return rc;
         if ((rc = up(L.off_eqpay, P.eq_pay.data(), sizeof(double) * P.eq_pay.size()))) return rc;
         if ((rc = up(L.off_net, P.net_leaves.data(), sizeof(int32_t) * P.net_leaves.size()))) return rc;
@@ -2316,6 +2380,7 @@ int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net) {
             return PCFR_E_INVALID_ARG;
         }
         if (s->L.n_net * s->L.n_next > N.Mp) { set_error("leaf network max_batch below leaves x next cards"); return PCFR_E_INVALID_ARG; }
+        if (N.pdims[0] > kLeafXBlock * 8) { set_error("leaf network input wider than the input kernel"); return PCFR_E_INVALID_ARG; }
     }
     HIPCHK(hipStreamSynchronize(s->stream));
     s->net = net;
