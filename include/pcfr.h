@@ -92,12 +92,22 @@ typedef struct pcfr_tree_spec {
  * are updated from the same strategies (simultaneous updates, one sweep per
  * iteration); 1: player 0 is updated first, then player 1 against player 0's
  * new strategy, both with iteration t's coefficients (two sweeps per
- * iteration); other values are PCFR_E_INVALID_ARG. */
+ * iteration); other values are PCFR_E_INVALID_ARG.  suit_iso = 1: lossless
+ * suit isomorphism (Sec. 4.5, information abstraction).  The suit
+ * permutations that map a subgame's root board onto itself and leave both
+ * root ranges exactly unchanged form its symmetry group; below each chance
+ * node only one child per orbit of the dealt card (under the permutations
+ * that also fix the cards dealt above the node) is swept, and the node reads
+ * the other children's values through the hand permutation.  Results equal
+ * those of suit_iso = 0 up to rounding order; ranges without symmetry change
+ * nothing.  Strategies inside a skipped subtree are not kept
+ * (pcfr_get_strategy returns PCFR_E_UNSUPPORTED there). */
 typedef struct pcfr_solver_cfg {
     int32_t dtype;        /* PCFR_F32 or PCFR_F64 */
     int32_t variant;      /* PCFR_DCFR, PCFR_CFRPLUS or PCFR_PCFRPLUS */
     double alpha, beta, gamma;
     int32_t alternating;  /* 0 or 1 */
+    int32_t suit_iso;     /* 0 or 1: lossless suit isomorphism at chance nodes */
 } pcfr_solver_cfg;
 
 typedef struct pcfr_tree pcfr_tree;
@@ -127,6 +137,19 @@ int32_t pcfr_tree_info(const pcfr_tree* tree, int64_t* out);
 int32_t pcfr_tree_export(const pcfr_tree* tree, int32_t* type, int32_t* player, int32_t* parent,
                          int32_t* action, int32_t* depth, int64_t* contrib, int32_t* chance_card,
                          int32_t* first_child, int32_t* n_child);
+
+/* Lossless suit isomorphism of one subgame (host only; what a solver with
+ * suit_iso = 1 uses).  ranges: [2][1326] host doubles, as for
+ * pcfr_solver_create.  group: bit q set when suit permutation q (the q-th
+ * permutation of (0, 1, 2, 3) in lexicographic order, suit s -> perm[s])
+ * maps the root board and both ranges onto themselves.  Per node (caller
+ * buffers of length nodes): src, for a chance child, the child whose values
+ * stand for it (itself for a representative, the smallest card of its
+ * orbit), else -1; perm, for a mapped child, the permutation taking the
+ * representative's card to its own, else -1; skip, 1 inside subtrees that
+ * are not swept. */
+int32_t pcfr_suit_iso_map(const pcfr_tree* tree, const double* ranges, uint32_t* group, int32_t* src,
+                          int32_t* perm, int8_t* skip);
 
 /* Seven-card hand values, host side (used to order hands at showdown,
  * Sec. 4.3 Stage 4).  cards: n*7 card ids; out: n values.  Value layout:
@@ -181,6 +204,9 @@ int32_t pcfr_iteration(pcfr_solver* s, int64_t* t);   /* synchronises */
  * where no regret is positive).  out: host [A][1326] doubles, A = the node's
  * action count; combos blocked by the board get 0.  Synchronises. */
 int32_t pcfr_get_strategy(pcfr_solver* s, int32_t node, int32_t which, double* out);
+/* Nodes the sweeps visit (decision, chance and terminal nodes outside the
+ * subtrees suit isomorphism skips), over all subgames. */
+int32_t pcfr_solver_swept_nodes(pcfr_solver* s, int64_t* n);
 
 /* Root counterfactual values in chips (eq. cfv: each hand's value summed over
  * compatible opponent hands weighted by their reach).  PCFR_CURRENT: from the

@@ -1,6 +1,7 @@
 // Host-side structures of the library: card helpers, the public tree, and
 // the per-board tables the showdown kernel reads.
 #pragma once
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -47,6 +48,22 @@ struct Tree {
 };
 
 int32_t build_tree(const pcfr_tree_spec& spec, Tree& out);
+
+// Lossless suit isomorphism at chance nodes (iso.cpp).  Node ids are those
+// of the forest: subgame g's nodes follow the nodes of subgames 0 .. g-1.
+struct IsoMap {
+    std::vector<char> skip;       // per node: inside a subtree solved through its representative
+    std::vector<int32_t> src;     // per chance child: the child whose values stand for it (itself for a
+                                  // representative), -1 for other nodes
+    std::vector<int8_t> perm;     // per chance child: index of the permutation taking the representative's
+                                  // card to its own, -1 for representatives and other nodes
+    std::vector<char> mapped;     // per chance node: some child is read through a permutation
+    std::vector<uint32_t> group;  // per subgame: bit q set when permutation q maps board and ranges onto themselves
+};
+const std::array<std::array<int8_t, 4>, 24>& suit_perms();
+int32_t suit_iso_map(const std::vector<const Tree*>& trees, const double* ranges, IsoMap& out);
+void suit_hand_maps(const std::vector<int32_t>& hand_combo, const std::vector<int32_t>& combo_hand, uint32_t group,
+                    int64_t Hp, int16_t* out);
 
 // Pairwise check-down equity E[h][o] over a hand list on a partial board.
 void equity_matrix(uint64_t board, const std::vector<int32_t>& hand_combo, std::vector<double>& E);

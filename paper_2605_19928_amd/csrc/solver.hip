@@ -341,14 +341,55 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
     }
 }
 
+// Suit isomorphism tables (null when off): cmap[2 node] = the child whose
+// values stand for a chance child, cmap[2 node + 1] = the permutation taking
+// that representative's card to the child's (-1: the child itself);
+// hmap[(subgame * 24 + q) * Hp + h] = the hand pi_q^-1(h).
+struct IsoTabs {
+    const int32_t* cmap;
+    const int16_t* hmap;
+};
+
 // Backward work of one node (decision or chance) for NH hands.
 template <typename T, int MODE, int MAXA, int NH, bool EARLY>
 __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __restrict__ R, T* __restrict__ S,
                                          T* __restrict__ Mp, const T* __restrict__ reach, T* __restrict__ cfv,
                                          const IterState* __restrict__ st, const uint16_t* __restrict__ hcards,
-                                         T* __restrict__ root_dst, int upd) {
+                                         T* __restrict__ root_dst, int upd, IsoTabs iso) {
     using V = VN<T, NH>;
     const int64_t n = nd.id;
+    if (nd.type == PCFR_NODE_CHANCE && nd.pad) {
+        // some children solved through a suit-isomorphic representative:
+        // v(h | pi c) = v(pi^-1 h | c); children added in their order
+        V a0 = {}, a1 = {};
+        for (int j = 0; j < nd.n_child; j++) {
+            const int64_t ch = nd.first_child + j;
+            const int32_t src = iso.cmap[2 * ch], q = iso.cmap[2 * ch + 1];
+            const T* cc = cfv + (int64_t)src * 2 * Hp;
+            V u, w;
+            if (q < 0) {
+                u = ldv<NH>(cc + h);
+                w = ldv<NH>(cc + Hp + h);
+            } else {
+                const int16_t* mp = iso.hmap + ((int64_t)nd.sub * 24 + q) * Hp + h;
+#pragma unroll
+                for (int e = 0; e < NH; e++) {
+                    const int hm = mp[e];
+                    u.e[e] = cc[hm];
+                    w.e[e] = cc[Hp + hm];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < NH; e++) { a0.e[e] += u.e[e]; a1.e[e] += w.e[e]; }
+        }
+        const T inv_k = T(1) / T(nd.aux);
+#pragma unroll
+        for (int e = 0; e < NH; e++) { a0.e[e] *= inv_k; a1.e[e] *= inv_k; }
+        T* me = cfv + n * 2 * Hp;
+        stv<NH>(me + h, a0);
+        stv<NH>(me + Hp + h, a1);
+        return;
+    }
     if (nd.type == PCFR_NODE_CHANCE) {
         // children in groups of 4: all loads of a group are issued before the
         // adds, which keep the children's order
@@ -402,13 +443,13 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
                                                              const T* __restrict__ reach, T* __restrict__ cfv,
                                                              const IterState* __restrict__ st,
                                                              const uint16_t* __restrict__ hcards,
-                                                             T* __restrict__ root_dst, int upd) {
+                                                             T* __restrict__ root_dst, int upd, IsoTabs iso) {
     const int groups = Hp >> 2;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
     bwd_node<T, MODE, MAXA, 4, false>(level[k], (int)(gid - k * groups) * 4, Hp, R, S, Mp, reach, cfv, st, hcards,
-                                      root_dst, upd);
+                                      root_dst, upd, iso);
 }
 
 // Level-fused sweeps for runs of levels too small to fill the GPU.  A node's
@@ -452,14 +493,14 @@ __global__ __launch_bounds__(kFuseBlock) void k_backward_fused(const DNode* __re
                                                                const T* __restrict__ reach, T* __restrict__ cfv,
                                                                const IterState* __restrict__ st,
                                                                const uint16_t* __restrict__ hcards,
-                                                               T* __restrict__ root_dst, int upd) {
+                                                               T* __restrict__ root_dst, int upd, IsoTabs iso) {
     const int h = blockIdx.x * kFuseHands + (int)(threadIdx.x & 63), lane = fuse_lane();
     for (int l = l_hi - 1; l >= l_lo; l--) {
         if (l < l_hi - 1) __syncthreads();
         const int64_t e = lvl_off[l + 1];
         for (int64_t k = lvl_off[l] + lane; k < e; k += kFuseWaves)
             bwd_node<T, MODE, MAXA, 1, true>(rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
-                                             l == 0 ? root_dst : nullptr, upd);
+                                             l == 0 ? root_dst : nullptr, upd, iso);
     }
 }
 
@@ -958,6 +999,15 @@ __global__ __launch_bounds__(kLeafXBlock) void k_leaf_x(const T* __restrict__ Rc
     if (col0 >= ldx) return;
     const T* rc = Rc + (int64_t)leaf * 2 * kComboPad;
     const double s0 = sinv[(int64_t)leaf * 104 + c], s1 = sinv[(int64_t)leaf * 104 + 52 + c];
+    const float ratio = spr[leaf];
+    // every range load first (the eight entries, clamped into the leaf's rows)
+    T rv[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int col = col0 + j, pp = col >= kCombos;
+        const int kk = col < 2 * kCombos ? col - pp * kCombos : 0;
+        rv[j] = rc[pp * kComboPad + kk];
+    }
     // cards (a > b) of the combo in column col0 of its player's block
     int k = col0 >= kCombos ? col0 - kCombos : col0;
     int a = (int)((1.f + sqrtf(1.f + 8.f * (float)k)) * 0.5f);
@@ -971,14 +1021,14 @@ __global__ __launch_bounds__(kLeafXBlock) void k_leaf_x(const T* __restrict__ Rc
         float x = 0.f;
         if (col < 2 * kCombos) {
             if (col == kCombos) { a = 1; b = 0; }           // player 1's block restarts at combo 0
-            const int pp = col >= kCombos, kk = col - pp * kCombos;
-            if (a != c && b != c) x = (float)((double)rc[pp * kComboPad + kk] * (pp ? s1 : s0));
+            const int pp = col >= kCombos;
+            if (a != c && b != c) x = (float)((double)rv[j] * (pp ? s1 : s0));
             if (++b == a) { a++; b = 0; }
         } else if (col < 2 * kCombos + 52) {
             const int card = col - 2 * kCombos;
             x = (card == c || card == board.x || card == board.y || card == board.z || card == board.w) ? 1.f : 0.f;
         } else if (col == 2 * kCombos + 52) {
-            x = spr[leaf];
+            x = ratio;
         }
         v[j] = to_bf16(x);
     }
@@ -995,37 +1045,54 @@ __global__ __launch_bounds__(kLeafXBlock) void k_leaf_x(const T* __restrict__ Rc
 // e = sum_h r0 M1 EV0 + sum_h r1 M0 EV1 and z = sum_h r0 M1 (= sum_h r1 M0),
 // which the combine subtracts from both players' EVs of that row.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_zerosum(const DNode* __restrict__ nodes,
-                                                         const int32_t* __restrict__ leaves, int n_next,
-                                                         const int8_t* __restrict__ next_cards, int Hp, int H,
-                                                         const T* __restrict__ reach, const T* __restrict__ agg,
-                                                         const uint16_t* __restrict__ hcards,
-                                                         const int16_t* __restrict__ hand_combo,
-                                                         const int16_t* __restrict__ combo_hand,
+__global__ __launch_bounds__(kBlock) void k_leaf_zerosum(int n_next, const int8_t* __restrict__ next_cards,
+                                                         const T* __restrict__ Rc, const T* __restrict__ agg,
                                                          const float* __restrict__ Y, int ldy, T* __restrict__ delta) {
+    constexpr int CI = (kCombos + kBlock - 1) / kBlock;
+    __shared__ T rs[2][kComboPad];
     __shared__ T ag[kAgg];
     __shared__ T xch[2 * kWaves];
-    const int row = blockIdx.x, li = row / n_next, k = row - li * n_next;
-    const int c = next_cards[k];
-    const DNode nd = nodes[leaves[li]];
-    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
-    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    const int row = blockIdx.x, li = row / n_next, kc = row - li * n_next;
+    const int c = next_cards[kc];
     const int tid = threadIdx.x;
-    if (tid < kAgg) ag[tid] = agg[(int64_t)li * kAgg + tid];
+    // every global load first: the leaf's combo-indexed ranges, aggregates and this row's outputs
+    const T* rc = Rc + (int64_t)li * 2 * kComboPad;
+    T rv[2][CI];
+    float y0[CI], y1[CI];
+    const float* y = Y + (int64_t)row * ldy;
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock, kk = k < kCombos ? k : 0;
+        rv[0][i] = rc[kk];
+        rv[1][i] = rc[kComboPad + kk];
+        y0[i] = y[kk];
+        y1[i] = y[kCombos + kk];
+    }
+    const T agv = tid < kAgg ? agg[(int64_t)li * kAgg + tid] : T(0);
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock;
+        if (k < kCombos) { rs[0][k] = rv[0][i]; rs[1][k] = rv[1][i]; }
+    }
+    if (tid < kAgg) ag[tid] = agv;
     __syncthreads();
     const T s0 = ag[52] - ag[c], s1 = ag[105] - ag[53 + c];     // totals without the hands holding c
-    const float* y = Y + (int64_t)row * ldy;
     T e = T(0), z = T(0);
-    for (int h = tid; h < H; h += kBlock) {
-        const uint32_t hc = hcards[h];
-        const int a = hc & 0xff, b = hc >> 8;
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock;
+        if (k >= kCombos) continue;
+        int a = (int)((1.f + sqrtf(1.f + 8.f * (float)k)) * 0.5f);
+        if (a * (a - 1) / 2 > k) a--;
+        else if ((a + 1) * a / 2 <= k) a++;
+        const int b = k - a * (a - 1) / 2;
         if (a == c || b == c) continue;
-        const int ha = combo_hand[combo_index(a, c)], hb = combo_hand[combo_index(b, c)];
-        const T x0 = r0[h], x1 = r1[h];
-        const T m1 = s1 - ag[53 + a] - ag[53 + b] + x1 + (ha >= 0 ? r1[ha] : T(0)) + (hb >= 0 ? r1[hb] : T(0));
-        const T m0 = s0 - ag[a] - ag[b] + x0 + (ha >= 0 ? r0[ha] : T(0)) + (hb >= 0 ? r0[hb] : T(0));
-        const int combo = hand_combo[h];
-        e += x0 * m1 * (T)y[combo] + x1 * m0 * (T)y[kCombos + combo];
+        const int ka = combo_index(a, c), kb = combo_index(b, c);
+        const T x0 = rs[0][k], x1 = rs[1][k];
+        // blocked combos carry zero range, so they add nothing here
+        const T m1 = s1 - ag[53 + a] - ag[53 + b] + x1 + rs[1][ka] + rs[1][kb];
+        const T m0 = s0 - ag[a] - ag[b] + x0 + rs[0][ka] + rs[0][kb];
+        e += x0 * m1 * (T)y0[i] + x1 * m0 * (T)y1[i];
         z += x0 * m1;
     }
     block_sum2(e, z, xch);
@@ -1099,17 +1166,29 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
         a = hc & 0xff;
         b = hc >> 8;
         combo = hand_combo[h];
+        // every output load of this hand first (next cards grp, grp + 4, ...)
+        constexpr int KI = (52 + 3) / 4;
+        float ya[KI], yb[KI];
+        const float* y = Y + (int64_t)li * n_next * ldy;
+#pragma unroll
+        for (int i = 0; i < KI; i++) {
+            const int k = grp + 4 * i, kk = k < n_next ? k : 0;
+            ya[i] = y[(int64_t)kk * ldy + combo];
+            yb[i] = y[(int64_t)kk * ldy + kCombos + combo];
+        }
         base0 = t0 - cs[0][a] - cs[0][b] + x[0][h];
         base1 = t1 - cs[1][a] - cs[1][b] + x[1][h];
-        const float* y = Y + (int64_t)li * n_next * ldy;
-        for (int k = grp; k < n_next; k += 4) {
+#pragma unroll
+        for (int i = 0; i < KI; i++) {
+            const int k = grp + 4 * i;
+            if (k >= n_next) break;
             const int c = nxt[k];
             if (c == a || c == b) continue;
             const int ha = c2h[combo_index(a, c)], hb = c2h[combo_index(b, c)];
             const T m1 = base1 - cs[1][c] + (ha >= 0 ? x[1][ha] : T(0)) + (hb >= 0 ? x[1][hb] : T(0));
             const T m0 = base0 - cs[0][c] + (ha >= 0 ? x[0][ha] : T(0)) + (hb >= 0 ? x[0][hb] : T(0));
-            acc0 += ((T)y[(int64_t)k * ldy + combo] - dl[k]) * m1;
-            acc1 += ((T)y[(int64_t)k * ldy + kCombos + combo] - dl[k]) * m0;
+            acc0 += ((T)ya[i] - dl[k]) * m1;
+            acc1 += ((T)yb[i] - dl[k]) * m0;
         }
     }
     red[0][tid] = acc0;
@@ -1250,7 +1329,7 @@ struct Plan {
     size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_zs, off_agg, off_rc, off_sinv, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
-        total;
+        off_cmap, off_hmap, total;
     size_t lds_bytes, lds_fold, lds_show;
     int4 board4;                          // root board cards, -1 past the last
 };
@@ -1266,6 +1345,7 @@ struct Prepared {
     std::vector<int64_t> dec_off;
     std::vector<DNode> fwd_rec, dec_rec;  // node records in the order of fwd and dec
     std::vector<int32_t> lvl_maxa;        // per level: most actions of a decision node
+    std::vector<char> lvl_perm;           // per level: holds a chance node reading children through a hand permutation
     std::vector<int32_t> folds, shows;    // terminal lists by kind
     std::vector<uint16_t> hcards;         // [n_sub][Hp]
     std::vector<int32_t> coff;            // [n_sub][53]
@@ -1295,7 +1375,7 @@ struct Prepared {
 // Host preprocessing of a forest of subgames: node records, merged level work
 // lists, hand cards, per-card hand lists, and one strength-sorted table per
 // (subgame, showdown board).
-static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
+static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const IsoMap* iso = nullptr) {
     const ComboTable& cc = combos();
     const int32_t K = (int32_t)trees.size();
     P.n_sub = K;
@@ -1367,6 +1447,8 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
             d.first_child = s.first_child < 0 ? -1 : (int32_t)(base + s.first_child);
             d.rs = -1; d.aux = 0; d.sub = g; d.pay = 0.0;
             d.slot[0] = d.slot[1] = -1;
+            const bool swept = !(iso && iso->skip[gi]);
+            if (iso && iso->mapped[gi]) d.pad = 1;   // chance node reading some children through a permutation
             uint64_t extra = s.board_mask & ~t.root_mask;
             int dd[2] = {0xff, 0xff}, nd = 0;
             for (int c = 0; c < 52 && nd < 2; c++) if (extra >> c & 1ull) dd[nd++] = c;
@@ -1376,20 +1458,22 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
                 rows += s.n_child;
                 if (s.n_child > kMaxActions || s.n_child < 1) { set_error("unsupported action count"); return PCFR_E_TOO_LARGE; }
                 P.max_a = std::max(P.max_a, s.n_child);
-                per_level[s.depth].push_back((int32_t)gi);
+                if (swept) per_level[s.depth].push_back((int32_t)gi);
             } else if (s.type == PCFR_NODE_CHANCE) {
                 d.aux = 52 - __builtin_popcountll(s.board_mask) - 4;
-                per_level[s.depth].push_back((int32_t)gi);
+                if (swept) per_level[s.depth].push_back((int32_t)gi);
             } else if (s.type == PCFR_NODE_FOLD) {
                 d.pay = (double)s.contrib[s.player];
-                P.term.push_back((int32_t)gi);
+                if (swept) P.term.push_back((int32_t)gi);
             } else if (s.type == PCFR_NODE_SHOWDOWN) {
                 d.pay = (double)s.contrib[0];
-                auto key = std::make_pair(g, s.board_mask);
-                auto it = board_id.find(key);
-                if (it == board_id.end()) it = board_id.emplace(key, (int32_t)board_id.size()).first;
-                d.aux = it->second;
-                P.term.push_back((int32_t)gi);
+                if (swept) {
+                    auto key = std::make_pair(g, s.board_mask);
+                    auto it = board_id.find(key);
+                    if (it == board_id.end()) it = board_id.emplace(key, (int32_t)board_id.size()).first;
+                    d.aux = it->second;
+                    P.term.push_back((int32_t)gi);
+                }
             } else if (s.type == PCFR_NODE_ALLIN_LEAF || s.type == PCFR_NODE_LEAF) {
                 if (K > 1) { set_error("depth-limited subgames cannot be batched"); return PCFR_E_UNSUPPORTED; }
                 if (s.contrib[0] != s.contrib[1]) { set_error("leaf with unequal contributions"); return PCFR_E_INVALID_ARG; }
@@ -1448,10 +1532,12 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
     P.fwd_off.assign(P.levels + 1, 0);
     P.dec_off.assign(P.levels + 1, 0);
     P.lvl_maxa.assign(P.levels, 0);
+    P.lvl_perm.assign(P.levels, 0);
     for (int l = 0; l < P.levels; l++) {
         P.fwd_off[l] = (int64_t)P.fwd.size();
         P.dec_off[l] = (int64_t)P.dec.size();
         for (auto x : per_level[l]) {
+            if (P.nodes[x].type == PCFR_NODE_CHANCE && P.nodes[x].pad) P.lvl_perm[l] = 1;
             P.fwd.push_back(x);
             if (P.nodes[x].type == PCFR_NODE_DECISION) {
                 P.dec.push_back(x);
@@ -1538,7 +1624,7 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P) {
     return PCFR_OK;
 }
 
-static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, Plan& L) {
+static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, bool iso, Plan& L) {
     L.N = (int64_t)P.nodes.size();
     L.rows = rows;
     L.Hp = P.Hp;
@@ -1589,6 +1675,9 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, P
     L.off_agg = take(L.esz * kAgg * std::max<int64_t>(L.n_net, 1));
     L.off_rc = take(L.esz * 2 * kComboPad * std::max<int64_t>(L.n_net, 1));
     L.off_sinv = take(sizeof(double) * 104 * std::max<int64_t>(L.n_net, 1));
+    // suit isomorphism: per node (source child, permutation); per subgame and permutation, the hand map
+    L.off_cmap = take(iso ? sizeof(int32_t) * 2 * L.N : 0);
+    L.off_hmap = take(iso ? sizeof(int16_t) * 24 * L.Hp * P.n_sub : 0);
     L.off_next = take(64);
     L.off_c2h = take(sizeof(int16_t) * kCombos);
     L.off_h2c = take(sizeof(int16_t) * L.Hp);
@@ -1639,6 +1728,7 @@ struct pcfr_solver {
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
     pcfr_leafnet* net = nullptr;
+    IsoMap iso;                 // suit isomorphism map (suit_iso = 1)
     bool leaf_zero_sum = true;  // shift network outputs to zero-sum leaf values
     int64_t t_host = 0;     // iterations enqueued
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -1773,10 +1863,8 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (rc) return rc;
         if (s->leaf_zero_sum) {
             if (tm) tm->before(4);
-            hipLaunchKernelGGL((k_leaf_zerosum<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, nodes,
-                               s->at<int32_t>(L.off_net), (int)L.n_next, s->at<int8_t>(L.off_next), Hp, (int)L.H,
-                               reach, s->at<T>(L.off_agg), s->at<uint16_t>(L.off_hc), s->at<int16_t>(L.off_h2c),
-                               s->at<int16_t>(L.off_c2h),
+            hipLaunchKernelGGL((k_leaf_zerosum<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, (int)L.n_next,
+                               s->at<int8_t>(L.off_next), s->at<T>(L.off_rc), s->at<T>(L.off_agg),
                                reinterpret_cast<const float*>(net->ws + net->P.off_y), (int)net->P.pdims[net->P.L],
                                s->at<T>(L.off_zs));
             if (tm) tm->after();
@@ -1798,17 +1886,22 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     }
     // backward; level 0 holds exactly the roots, whose values of this
     // iteration are also kept apart from later evaluation sweeps
+    const IsoTabs iso = {s->cfg.suit_iso ? s->at<int32_t>(L.off_cmap) : nullptr,
+                         s->cfg.suit_iso ? s->at<int16_t>(L.off_hmap) : nullptr};
     for (int l = P.levels - 1; l >= 0;) {
         const int64_t cnt = all_cnt(l);
         if (!cnt) { l--; continue; }
         if (cnt * groups <= fuse) {
+            // a run does not climb to a level whose chance nodes read other
+            // hands of their children (suit isomorphism): those children
+            // must be complete for every hand, i.e. from an earlier launch
             int l0 = l, ma = P.lvl_maxa[l];
-            while (l0 > 0 && all_cnt(l0 - 1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[--l0]);
+            while (l0 > 0 && all_cnt(l0 - 1) * groups <= fuse && !P.lvl_perm[l0 - 1]) ma = std::max(ma, P.lvl_maxa[--l0]);
             if (tm) tm->before(3);
             PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(kFuseBlock), 0, stream,
                            fwd, s->at<int64_t>(L.off_fwdoff), l0, l + 1, Hp, R, S, Mp, reach, cfv, st,
                            s->at<uint16_t>(L.off_hc), (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr,
-                           upd);
+                           upd, iso);
             if (tm) tm->after();
             l = l0 - 1;
             continue;
@@ -1819,7 +1912,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (tm) tm->before(3, 1000 + l);
         PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
                     reach, cfv, st, s->at<uint16_t>(L.off_hc),
-                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr, upd);
+                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr, upd, iso);
         if (tm) tm->after();
         l--;
     }
@@ -1929,6 +2022,7 @@ static int32_t check_cfg(const pcfr_solver_cfg* cfg) {
         return PCFR_E_INVALID_ARG;
     }
     if (cfg->alternating != 0 && cfg->alternating != 1) { set_error("alternating must be 0 or 1"); return PCFR_E_INVALID_ARG; }
+    if (cfg->suit_iso != 0 && cfg->suit_iso != 1) { set_error("suit_iso must be 0 or 1"); return PCFR_E_INVALID_ARG; }
     if (!std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta) || !std::isfinite(cfg->gamma)) {
         set_error("alpha, beta, gamma must be finite");
         return PCFR_E_INVALID_ARG;
@@ -1951,7 +2045,7 @@ static int32_t workspace_for(const pcfr_tree* const* trees, int32_t n, const pcf
     try { rc = prepare(tv, P); } catch (const std::bad_alloc&) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
     if (rc != PCFR_OK) return rc;
     Plan L;
-    make_plan(P, rows, cfg->dtype, cfg->variant, L);
+    make_plan(P, rows, cfg->dtype, cfg->variant, cfg->suit_iso != 0, L);
     *bytes = L.total;
     return PCFR_OK;
 }
@@ -1974,14 +2068,18 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         }
         std::vector<const Tree*> tv;
         for (auto& t : s->trees) tv.push_back(&t);
-        rc = prepare(tv, s->P);
+        if (cfg->suit_iso) {
+            rc = suit_iso_map(tv, ranges, s->iso);
+            if (rc != PCFR_OK) return rc;
+        }
+        rc = prepare(tv, s->P, cfg->suit_iso ? &s->iso : nullptr);
         if (rc != PCFR_OK) return rc;
     } catch (const std::bad_alloc&) {
         set_error("out of host memory");
         return PCFR_E_OUT_OF_MEMORY;
     }
     s->cfg = *cfg;
-    make_plan(s->P, rows, cfg->dtype, cfg->variant, s->L);
+    make_plan(s->P, rows, cfg->dtype, cfg->variant, cfg->suit_iso != 0, s->L);
     const Plan& L = s->L;
     const Prepared& P = s->P;
     if (workspace_bytes < L.total) { set_error("workspace smaller than the size the library asked for"); return PCFR_E_OUT_OF_MEMORY; }
@@ -2043,6 +2141,16 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     std::vector<int32_t> roots(n);
     for (int32_t g = 0; g < n; g++) roots[g] = (int32_t)P.root_node[g];
     if ((rc = up(L.off_roots, roots.data(), sizeof(int32_t) * n))) return rc;
+    if (cfg->suit_iso) {
+        std::vector<int32_t> cmap(2 * (size_t)L.N);
+        for (int64_t i = 0; i < L.N; i++) { cmap[2 * i] = s->iso.src[i]; cmap[2 * i + 1] = s->iso.perm[i]; }
+        std::vector<int16_t> hmap((size_t)24 * L.Hp * n);
+        for (int32_t g = 0; g < n; g++)
+            suit_hand_maps(P.hand_combo[g], P.combo_hand[g], s->iso.group[g], L.Hp, hmap.data() + (size_t)g * 24 * L.Hp);
+        if ((rc = up(L.off_cmap, cmap.data(), sizeof(int32_t) * cmap.size()))) return rc;
+        if ((rc = up(L.off_hmap, hmap.data(), sizeof(int16_t) * hmap.size()))) return rc;
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
     {
         // per-subgame tables of the leaf-network sample builder
         std::vector<float> ps(2 * n);
@@ -2137,6 +2245,10 @@ static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t wh
     if (node < 0 || node >= nn || s->trees[g].nodes[node].type != PCFR_NODE_DECISION) {
         set_error("node is not a decision node");
         return PCFR_E_INVALID_ARG;
+    }
+    if (!s->iso.skip.empty() && s->iso.skip[s->P.node_base[g] + node]) {
+        set_error("node lies in a subtree solved through its suit-isomorphic representative");
+        return PCFR_E_UNSUPPORTED;
     }
     const DNode& d = s->P.nodes[s->P.node_base[g] + node];
     const Plan& L = s->L;
@@ -2457,6 +2569,12 @@ int32_t pcfr_iteration(pcfr_solver* s, int64_t* t) {
 
 int32_t pcfr_get_strategy(pcfr_solver* s, int32_t node, int32_t which, double* out) {
     return strategy_impl(s, 0, node, which, out);
+}
+
+int32_t pcfr_solver_swept_nodes(pcfr_solver* s, int64_t* n) {
+    if (!s || !n) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    *n = (int64_t)(s->P.fwd.size() + s->P.term.size());
+    return PCFR_OK;
 }
 
 int32_t pcfr_batch_get_strategy(pcfr_solver* s, int32_t sub, int32_t node, int32_t which, double* out) {

@@ -10,6 +10,7 @@ Conventions: card = 4*rank + suit (rank 0..12 = 2..A); a two-card combo
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
@@ -53,6 +54,45 @@ def dirichlet_range(rng: np.random.Generator, board, alpha: float = 1.0, support
     r = np.zeros(NCOMBO, dtype=np.float64)
     r[ok] = w
     return r
+
+
+def suit_stabilizer(board) -> list:
+    """Suit permutations p (suit s -> p[s], tuples) mapping the board onto itself."""
+    b = set(int(c) for c in board)
+    return [p for p in itertools.permutations(range(4)) if {4 * (c // 4) + p[c % 4] for c in b} == b]
+
+
+def symmetric_range(rng: np.random.Generator, board, alpha: float = 1.0, support: int | None = None) -> np.ndarray:
+    """A range invariant under every suit permutation that fixes the board.
+
+    The board-compatible combos fall into orbits under those permutations;
+    Dirichlet(alpha) weights are drawn per orbit (``support=k``: only k
+    orbits, picked uniformly, get mass) and every combo of an orbit carries
+    its orbit's weight, then the range is scaled to sum 1, so combos of one
+    orbit hold bitwise equal values."""
+    cc = combo_cards()
+    group = suit_stabilizer(board)
+    blocked = blocked_mask(board)
+    orbit = np.full(NCOMBO, -1)
+    n_orb = 0
+    for k in range(NCOMBO):
+        if blocked[k] or orbit[k] >= 0:
+            continue
+        a, b = (int(x) for x in cc[k])
+        for p in group:
+            a2, b2 = 4 * (a // 4) + p[a % 4], 4 * (b // 4) + p[b % 4]
+            hi, lo = max(a2, b2), min(a2, b2)
+            orbit[hi * (hi - 1) // 2 + lo] = n_orb
+        n_orb += 1
+    live = np.arange(n_orb)
+    if support is not None:
+        live = np.sort(rng.choice(live, size=min(support, n_orb), replace=False))
+    w = np.zeros(n_orb)
+    w[live] = rng.dirichlet(np.full(live.size, alpha))
+    r = np.zeros(NCOMBO, dtype=np.float64)
+    ok = orbit >= 0
+    r[ok] = w[orbit[ok]]
+    return r / r.sum()
 
 
 def draw_pot_stack(rng: np.random.Generator, spr_lo: float = 1.0, spr_hi: float = 8.0,

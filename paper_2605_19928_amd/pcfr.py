@@ -38,7 +38,7 @@ class TreeSpec(C.Structure):
 
 class SolverCfg(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("variant", C.c_int32), ("alpha", C.c_double),
-                ("beta", C.c_double), ("gamma", C.c_double), ("alternating", C.c_int32)]
+                ("beta", C.c_double), ("gamma", C.c_double), ("alternating", C.c_int32), ("suit_iso", C.c_int32)]
 
 
 _lib = None
@@ -52,6 +52,8 @@ _SIGS = {
     "pcfr_tree_info": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pcfr_tree_export": (C.c_int32, [C.c_void_p] * 10),
     "pcfr_eval7_batch": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "pcfr_suit_iso_map": (C.c_int32, [C.c_void_p] * 6),
+    "pcfr_solver_swept_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_equity_table": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pcfr_leafnet_workspace_bytes": (C.c_int32, [C.c_int32] * 5 + [C.POINTER(C.c_size_t)]),
     "pcfr_leafnet_create": (C.c_int32, [C.c_int32] * 5 + [C.c_void_p, C.c_size_t, C.c_void_p,
@@ -171,6 +173,18 @@ class Tree:
         _check(lib().pcfr_equity_table(self._h, _p(out)))
         return out
 
+    def suit_iso_map(self, ranges) -> dict:
+        """The library's suit isomorphism map for root ranges [2, 1326]: group
+        (bitmask over the 24 suit permutations), per node src, perm, skip."""
+        r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, NCOMBO)
+        n = self.n_nodes
+        grp = C.c_uint32()
+        src = np.zeros(n, dtype=np.int32)
+        perm = np.zeros(n, dtype=np.int32)
+        skip = np.zeros(n, dtype=np.int8)
+        _check(lib().pcfr_suit_iso_map(self._h, _p(r), C.byref(grp), _p(src), _p(perm), _p(skip)))
+        return {"group": int(grp.value), "src": src, "perm": perm, "skip": skip}
+
     def export(self) -> dict:
         n = self.n_nodes
         out = {k: np.zeros(n, dtype=np.int32) for k in
@@ -199,13 +213,14 @@ class SolverConfig:
     gamma: float = 2.0
     variant: str = "dcfr"
     alternating: int = 0
+    suit_iso: int = 0
 
     def to_c(self) -> SolverCfg:
         c = SolverCfg()
         c.dtype = F64 if self.dtype == "f64" else F32
         v = VARIANTS[self.variant] if isinstance(self.variant, str) else int(self.variant)
-        c.variant, c.alpha, c.beta, c.gamma, c.alternating = (v, self.alpha, self.beta, self.gamma,
-                                                             self.alternating)
+        c.variant, c.alpha, c.beta, c.gamma, c.alternating, c.suit_iso = (v, self.alpha, self.beta, self.gamma,
+                                                                         self.alternating, self.suit_iso)
         return c
 
 
@@ -238,6 +253,12 @@ class Solver:
 
     def iterate(self, n: int):
         _check(lib().pcfr_cfr_iterate(self._h, int(n)))
+
+    def swept_nodes(self) -> int:
+        """Nodes the sweeps visit (fewer than the tree's with suit isomorphism)."""
+        n = C.c_int64()
+        _check(lib().pcfr_solver_swept_nodes(self._h, C.byref(n)))
+        return int(n.value)
 
     def profile(self, n: int):
         """Run n iterations with per-launch event timing; returns (ms[8], launches[8])
