@@ -272,6 +272,30 @@ def batch_sweep(args, seed, steps, warmup, individual=True):
     return out
 
 
+def suit_iso_sweep(args, steps, warmup):
+    """Lossless suit isomorphism: the turn abstraction of the tree-sweep line
+    on a one-suit board (the three other suits interchangeable) with
+    suit-symmetric Dirichlet ranges, timed plain and with suit_iso = 1 (the
+    iterates agree up to rounding order; tested)."""
+    board = [50, 46, 26, 10]
+    rng = np.random.default_rng(0)
+    r = np.stack([I.symmetric_range(rng, board), I.symmetric_range(rng, board)])
+    spec = dict(board=board, pot=100, stacks=(400, 400), sizes=[33, 75, 150], allin=True, max_raises=3,
+                depth_limit=0)
+    tree = P.Tree(**spec)
+    out = {"workload": "turn to showdown on a one-suit board, suit-symmetric Dirichlet(1) ranges, seed 0",
+           "board": board, "pot": spec["pot"], "stacks": list(spec["stacks"]), "nodes": tree.n_nodes}
+    for name, iso in (("plain", 0), ("suit_iso", 1)):
+        s = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype, suit_iso=iso))
+        out[f"swept_nodes_{name}"] = s.swept_nodes()
+        out[f"ms_per_iter_{name}"] = timed(s, steps, warmup)
+        s.close()
+    out["speedup"] = out["ms_per_iter_plain"] / out["ms_per_iter_suit_iso"]
+    log(f"suit isomorphism: {out['ms_per_iter_plain']:.4f} -> {out['ms_per_iter_suit_iso']:.4f} ms/iter "
+        f"({out['swept_nodes_plain']} -> {out['swept_nodes_suit_iso']} swept nodes)")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -399,6 +423,7 @@ def main():
         sweep, _, _ = tree_sweep(args, 0, max(20, args.steps // 4), 5)
         result["tree_sweep"] = sweep
         result["batch"] = batch_sweep(args, 0, max(20, args.steps // 4), 5)
+        result["suit_isomorphism"] = suit_iso_sweep(args, max(20, args.steps // 4), 5)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(spec, r, args.cpu_seconds, leaf_params=params)
