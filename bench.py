@@ -277,6 +277,9 @@ def suit_iso_sweep(args, steps, warmup):
     on a one-suit board (the three other suits interchangeable) with
     suit-symmetric Dirichlet ranges, timed plain and with suit_iso = 1 (the
     iterates agree up to rounding order; tested)."""
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+
     board = [50, 46, 26, 10]
     rng = np.random.default_rng(0)
     r = np.stack([I.symmetric_range(rng, board), I.symmetric_range(rng, board)])
