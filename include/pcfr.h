@@ -100,8 +100,9 @@ typedef struct pcfr_tree_spec {
  * that also fix the cards dealt above the node) is swept, and the node reads
  * the other children's values through the hand permutation.  Results equal
  * those of suit_iso = 0 up to rounding order; ranges without symmetry change
- * nothing.  Strategies inside a skipped subtree are not kept
- * (pcfr_get_strategy returns PCFR_E_UNSUPPORTED there). */
+ * nothing.  Strategies inside a skipped subtree are not stored;
+ * pcfr_get_strategy returns the representative's with the hands relabelled
+ * by the permutation. */
 typedef struct pcfr_solver_cfg {
     int32_t dtype;        /* PCFR_F32 or PCFR_F64 */
     int32_t variant;      /* PCFR_DCFR, PCFR_CFRPLUS or PCFR_PCFRPLUS */

@@ -58,9 +58,14 @@ struct IsoMap {
     std::vector<int8_t> perm;     // per chance child: index of the permutation taking the representative's
                                   // card to its own, -1 for representatives and other nodes
     std::vector<char> mapped;     // per chance node: some child is read through a permutation
+    std::vector<int32_t> corr;    // per skipped node: the node it is the image of (one level up the chain
+                                  // of representatives), else -1
+    std::vector<int8_t> cperm;    // per skipped node: the permutation carrying corr's subtree onto its own
     std::vector<uint32_t> group;  // per subgame: bit q set when permutation q maps board and ranges onto themselves
 };
 const std::array<std::array<int8_t, 4>, 24>& suit_perms();
+int suit_perm_compose(int q1, int q2);   // index of pi_q1 o pi_q2 (pi_q2 applied first)
+int suit_perm_card(int q, int card);     // pi_q(card)
 int32_t suit_iso_map(const std::vector<const Tree*>& trees, const double* ranges, IsoMap& out);
 void suit_hand_maps(const std::vector<int32_t>& hand_combo, const std::vector<int32_t>& combo_hand, uint32_t group,
                     int64_t Hp, int16_t* out);

@@ -34,6 +34,17 @@ const std::array<std::array<int8_t, 4>, 24>& suit_perms() {
 
 static inline int map_card(const std::array<int8_t, 4>& pi, int c) { return 4 * (c / 4) + pi[c % 4]; }
 
+int suit_perm_card(int q, int card) { return map_card(suit_perms()[q], card); }
+
+int suit_perm_compose(int q1, int q2) {
+    const auto& perms = suit_perms();
+    std::array<int8_t, 4> c{};
+    for (int s = 0; s < 4; s++) c[s] = perms[q1][perms[q2][s]];
+    for (int q = 0; q < 24; q++)
+        if (perms[q] == c) return q;
+    return 0;   // unreachable: S4 is closed under composition
+}
+
 static uint64_t map_mask(const std::array<int8_t, 4>& pi, uint64_t m) {
     uint64_t out = 0;
     for (int c = 0; c < 52; c++)
@@ -52,6 +63,8 @@ int32_t suit_iso_map(const std::vector<const Tree*>& trees, const double* ranges
     out.src.assign(N, -1);
     out.perm.assign(N, -1);
     out.mapped.assign(N, 0);
+    out.corr.assign(N, -1);
+    out.cperm.assign(N, -1);
     out.group.assign(K, 0u);
     for (int32_t g = 0; g < K; g++) {
         const Tree& t = *trees[g];
@@ -109,6 +122,30 @@ int32_t suit_iso_map(const std::vector<const Tree*>& trees, const double* ranges
                     out.perm[cb] = (int8_t)q;
                     out.skip[cb] = 1;
                     out.mapped[gi] = 1;
+                    // node-by-node correspondence of the two subtrees: actions
+                    // in the same order, chance children by permuted card
+                    std::vector<std::pair<int32_t, int32_t>> stack{{(int32_t)(ca - base[g]), (int32_t)(cb - base[g])}};
+                    while (!stack.empty()) {
+                        const auto [xa, xb] = stack.back();
+                        stack.pop_back();
+                        out.corr[base[g] + xb] = (int32_t)(base[g] + xa);
+                        out.cperm[base[g] + xb] = (int8_t)q;
+                        const Node& na = t.nodes[xa];
+                        const Node& nb = t.nodes[xb];
+                        if (na.type == PCFR_NODE_CHANCE) {
+                            int bychild[52];
+                            std::fill(bychild, bychild + 52, -1);
+                            for (int e = 0; e < nb.n_child; e++) bychild[t.nodes[nb.first_child + e].chance_card] = nb.first_child + e;
+                            for (int e = 0; e < na.n_child; e++) {
+                                const int ya = na.first_child + e;
+                                const int yb = bychild[map_card(perms[q], t.nodes[ya].chance_card)];
+                                if (yb >= 0) stack.push_back({ya, yb});
+                            }
+                        } else {
+                            for (int e = 0; e < na.n_child && e < nb.n_child; e++)
+                                stack.push_back({na.first_child + e, nb.first_child + e});
+                        }
+                    }
                 }
             }
         }

@@ -150,7 +150,7 @@ __device__ void begin_iteration(IterState* st) {
 }
 
 // ------------------------------------------------------------ forward
-// Strategy of a row group for 4 hands: regret matching of R (MODE_ITER) or
+// Strategy of one action for one hand: regret matching of R (MODE_ITER) or
 // the normalised average-strategy sum S (other modes); uniform when the
 // denominator vanishes.
 template <typename T, int MODE>
@@ -2246,11 +2246,16 @@ static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t wh
         set_error("node is not a decision node");
         return PCFR_E_INVALID_ARG;
     }
-    if (!s->iso.skip.empty() && s->iso.skip[s->P.node_base[g] + node]) {
-        set_error("node lies in a subtree solved through its suit-isomorphic representative");
-        return PCFR_E_UNSUPPORTED;
+    // a node skipped by suit isomorphism: its representative's strategy with
+    // hands relabelled, sigma_n(h) = sigma_rep(Pi^-1 h), Pi composed along
+    // the chain of representatives
+    int64_t gn = s->P.node_base[g] + node;
+    int Pi = 0;
+    while (!s->iso.skip.empty() && s->iso.skip[gn]) {
+        Pi = suit_perm_compose(Pi, s->iso.cperm[gn]);
+        gn = s->iso.corr[gn];
     }
-    const DNode& d = s->P.nodes[s->P.node_base[g] + node];
+    const DNode& d = s->P.nodes[gn];
     const Plan& L = s->L;
     void* stage = s->ws + L.off_stage;
     dim3 grid((unsigned)((L.Hp + 255) / 256));
@@ -2272,6 +2277,15 @@ static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t wh
     for (int a = 0; a < d.n_child; a++)
         for (int k = 0; k < kCombos; k++)
             if (s->P.combo_hand[g][k] < 0) out[(size_t)a * kCombos + k] = 0;
+    if (Pi != 0) {
+        // out[a][k] = rep[a][Pi^-1 k]: combo Pi(j) takes the representative's combo j
+        const ComboTable& cc = combos();
+        std::vector<double> rep(out, out + (size_t)d.n_child * kCombos);
+        for (int j = 0; j < kCombos; j++) {
+            const int k = combo_of(suit_perm_card(Pi, cc.hi[j]), suit_perm_card(Pi, cc.lo[j]));
+            for (int a = 0; a < d.n_child; a++) out[(size_t)a * kCombos + k] = rep[(size_t)a * kCombos + j];
+        }
+    }
     return PCFR_OK;
 }
 

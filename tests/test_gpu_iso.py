@@ -49,19 +49,18 @@ def test_turn_iso_matches_oracle(board, seed):
     eo, _ = os_.exploitability()
     say(f"  exploitability gpu {eg:.9f} oracle {eo:.9f} chips")
     assert abs(eg - eo) / pot <= 1e-9
-    # strategies at every swept decision node
+    # strategies at every decision node: swept ones directly, skipped ones
+    # through their representative with the hands relabelled
     m = gt.suit_iso_map(r)
     e = ot.export()
-    worst = 0.0
+    worst = {False: 0.0, True: 0.0}
     for n in np.flatnonzero(e["type"] == O.T_DEC):
-        if m["skip"][n]:
-            with pytest.raises(P.PcfrError):
-                gi.strategy(int(n), "avg")
-            continue
         own = mask[int(e["player"][n])]
-        worst = max(worst, float(np.abs(gi.strategy(int(n), "avg") - os_.strategy(int(n), "avg"))[:, own].max()))
-    say(f"  avg strategy at swept nodes max |d| = {worst:.3e}")
-    assert worst <= 1e-9
+        for which in ("avg", "current"):
+            d = float(np.abs(gi.strategy(int(n), which) - os_.strategy(int(n), which))[:, own].max())
+            worst[bool(m["skip"][n])] = max(worst[bool(m["skip"][n])], d)
+    say(f"  strategies max |d|: swept nodes {worst[False]:.3e}, skipped nodes {worst[True]:.3e}")
+    assert worst[False] <= 1e-9 and worst[True] <= 1e-9
 
 
 def test_iso_without_symmetry_is_bitwise_plain():
