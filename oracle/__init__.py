@@ -55,6 +55,8 @@ def lib():
             "ora_build_tree": (P, [I, P, I64, I64, I64, I, P, I, I, I]),
             "ora_build_kuhn": (P, []),
             "ora_tree_free": (None, [P]),
+            "ora_tree_prune": (P, [P, P]),
+            "ora_prune_dominated": (None, [P, P, P, P, P]),
             "ora_tree_info": (None, [P, P]),
             "ora_tree_export": (None, [P] * 10),
             "ora_solver_create": (P, [P, P, D, D, D, I]),
@@ -158,6 +160,40 @@ class Tree:
         lib().ora_tree_export(self._h, _p(out["type"]), _p(out["player"]), _p(out["parent"]),
                               _p(out["action"]), _p(out["depth"]), _p(out["contrib"]),
                               _p(out["chance_card"]), _p(out["first_child"]), _p(out["n_child"]))
+        return out
+
+    def prune(self, removed):
+        """The reduced game of online pruning (Sec. 5): removed[n] != 0 on a
+        child of a decision node drops that action and its subtree.  Returns
+        the reduced tree and, per node of this tree, its id in the reduced
+        one (-1 when dropped)."""
+        rm = np.ascontiguousarray(np.asarray(removed).astype(np.uint8))
+        if rm.shape != (self.n_nodes,):
+            raise ValueError("one flag per node")
+        h = lib().ora_tree_prune(self._h, _p(rm))
+        if not h:
+            raise ValueError("invalid pruning flags")
+        t = Tree(h, kuhn=self.kuhn)
+        parent = self.export()["parent"]
+        kept = np.zeros(self.n_nodes, dtype=bool)
+        for n in range(self.n_nodes):
+            kept[n] = not rm[n] and (parent[n] < 0 or kept[parent[n]])
+        new_id = np.where(kept, np.cumsum(kept) - 1, -1).astype(np.int64)
+        return t, new_id
+
+    def prune_dominated(self, ranges, lo, hi) -> np.ndarray:
+        """Flags of the actions online pruning removes (Sec. 5) given value
+        bounds lo, hi [n_nodes][nh] indexed by the child node an action leads
+        to: an action goes when, for every hand of the actor's range not
+        blocked by the node's board, its upper bound lies below a sibling's
+        lower bound."""
+        r = np.ascontiguousarray(ranges, dtype=np.float64)
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        if r.shape != (2, self.nh) or lo.shape != (self.n_nodes, self.nh) or hi.shape != lo.shape:
+            raise ValueError("ranges [2][nh], bounds [n_nodes][nh]")
+        out = np.zeros(self.n_nodes, dtype=np.uint8)
+        lib().ora_prune_dominated(self._h, _p(r), _p(lo), _p(hi), _p(out))
         return out
 
     def node_board(self, node: int) -> list:

@@ -514,6 +514,67 @@ ogame* ora_build_kuhn(void) {
     return game_from_builder(&b, 1, NULL, 0);
 }
 
+/* Online pruning (Sec. 5, "Online Pruning"): actions removed before the
+ * iterations begin.  removed[n] != 0 on a child of a decision node drops the
+ * action leading to n together with n's whole subtree; every other node is
+ * copied as it is, its children kept in their order, and the reduced game is
+ * renumbered breadth-first like any built tree.  Returns NULL when a flag
+ * sits on a node whose parent is not a decision node, or when a decision
+ * node would keep no action. */
+ogame* ora_tree_prune(const ogame* g, const unsigned char* removed) {
+    builder b;
+    memset(&b, 0, sizeof(b));
+    b.kuhn = g->kuhn;
+    int* pool = malloc(sizeof(int) * g->n);
+    int bad = 0;
+    for (int i = 0; i < g->n && !bad; i++) {
+        const onode* o = &g->nd[i];
+        if (removed[i] && (o->parent < 0 || g->nd[o->parent].type != T_DEC)) { bad = 1; break; }
+        if (removed[i] || (o->parent >= 0 && pool[o->parent] < 0)) { pool[i] = -1; continue; }
+        pool[i] = b_new(&b, o->type, o->player, o->depth, o->c, o->nb, o->board, o->chance_card);
+        if (o->parent >= 0) b_addch(&b, pool[o->parent], pool[i]);
+    }
+    for (int i = 0; i < g->n && !bad; i++)
+        if (pool[i] >= 0 && g->nd[i].type == T_DEC && b.v[pool[i]].nch == 0) bad = 1;
+    free(pool);
+    if (bad) {
+        for (int i = 0; i < b.n; i++) free(b.v[i].ch);
+        free(b.v);
+        return NULL;
+    }
+    return game_from_builder(&b, g->kuhn, g->kuhn ? NULL : g->nd[0].board, g->kuhn ? 0 : g->nd[0].nb);
+}
+
+/* Dominance test of online pruning (Sec. 5): at a decision node of player p
+ * an action a is dominated for hand h when its optimistic value hi[a][h]
+ * lies below the pessimistic value lo[b][h] of one of its siblings b.  The
+ * action is removed from the public tree when it is dominated for every hand
+ * h of p's range (r_p(h) > 0) that the node's board does not block; a node
+ * where p holds no such hand removes nothing.  lo, hi: [n][nh], row = the
+ * child node the action leads to; removed: [n]. */
+void ora_prune_dominated(const ogame* g, const double* ranges, const double* lo, const double* hi,
+                         unsigned char* removed) {
+    int nh = g->nh;
+    memset(removed, 0, (size_t)g->n);
+    for (int i = 0; i < g->n; i++) {
+        const onode* o = &g->nd[i];
+        if (o->type != T_DEC) continue;
+        int p = o->player, fc = o->first_child, A = o->n_child;
+        for (int a = 0; a < A; a++) {
+            int any = 0, all = 1;
+            for (int h = 0; h < nh && all; h++) {
+                if (!g->hvalid[h] || !(ranges[p * nh + h] > 0) || (g->hmask[h] & o->bmask)) continue;
+                any = 1;
+                int dom = 0;
+                for (int b = 0; b < A && !dom; b++)
+                    if (b != a && hi[(size_t)(fc + a) * nh + h] < lo[(size_t)(fc + b) * nh + h]) dom = 1;
+                if (!dom) all = 0;
+            }
+            removed[fc + a] = (unsigned char)(any && all);
+        }
+    }
+}
+
 void ora_tree_free(ogame* g) { game_free(g); }
 
 /* counts: nodes, decision, fold, showdown, chance, leaf, allin-leaf, levels, rows */
