@@ -299,6 +299,67 @@ def suit_iso_sweep(args, steps, warmup):
     return out
 
 
+def pruning_sweep(args, spec, r, steps, warmup, warm_iters=100, eps=0.1):
+    """Online pruning on the turn of the tree-sweep line.  The bounds are the
+    node values under the average strategies after a short solve, widened by
+    eps times each hand's spread between sibling actions (standing in for the
+    intervals of a value-network ensemble, which this library does not
+    train); the dominance test runs on the GPU, the dominated actions leave
+    the tree, and the reduced tree is timed against the full one."""
+    import torch
+
+    from paper_2605_19928_amd import pcfr as P
+
+    tree = P.Tree(**spec)
+    s = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
+    ms_full = timed(s, steps, warmup)
+    s.iterate(warm_iters)
+    t0 = time.perf_counter()
+    V = s.node_values()
+    s.close()
+    e = tree.export()
+    dec = np.flatnonzero(e["type"] == P.NODE_DECISION)
+    cnt = e["n_child"][dec]
+    par = np.repeat(dec, cnt)
+    child = (np.repeat(e["first_child"][dec] - np.cumsum(cnt) + cnt, cnt) + np.arange(int(cnt.sum())))
+    dev = V.device
+    C = torch.from_numpy(child).to(dev)
+    Pn = torch.from_numpy(par).to(dev)
+    v = V[C, torch.from_numpy(e["player"][par].astype(np.int64)).to(dev)]
+    del V
+    n = tree.n_nodes
+    idx = Pn[:, None].expand_as(v)
+    vmax = torch.full((n, P.NCOMBO), -np.inf, dtype=torch.float64, device=dev).scatter_reduce(0, idx, v, "amax")
+    vmin = torch.full((n, P.NCOMBO), np.inf, dtype=torch.float64, device=dev).scatter_reduce(0, idx, v, "amin")
+    spread = (vmax - vmin)[Pn]
+    del vmax, vmin
+    lo = torch.full((n, P.NCOMBO), -np.inf, dtype=torch.float64, device=dev)
+    hi = torch.full((n, P.NCOMBO), np.inf, dtype=torch.float64, device=dev)
+    lo[C] = v - eps * spread
+    hi[C] = v + eps * spread
+    del v, spread
+    t1 = time.perf_counter()
+    flags = tree.prune_dominated(r, lo, hi)
+    t2 = time.perf_counter()
+    del lo, hi
+    pruned, _ = tree.prune(flags)
+    t3 = time.perf_counter()
+    s2 = P.Solver(pruned, r, P.SolverConfig(dtype=args.dtype))
+    ms_pruned = timed(s2, steps, warmup)
+    s2.close()
+    out = {
+        "workload": "turn of the tree-sweep line; bounds = node values of the average strategies after "
+                    f"{warmup + steps + warm_iters} iterations +- {eps} x the per-hand spread of sibling actions",
+        "nodes_full": n, "nodes_pruned": pruned.n_nodes, "rho": pruned.n_nodes / n,
+        "actions_removed": int(flags.sum()), "action_rows_full": tree.n_rows, "action_rows_pruned": pruned.n_rows,
+        "bounds_ms": 1e3 * (t1 - t0), "dominance_test_ms": 1e3 * (t2 - t1), "tree_reduction_ms": 1e3 * (t3 - t2),
+        "ms_per_iter_full": ms_full, "ms_per_iter_pruned": ms_pruned, "speedup": ms_full / ms_pruned,
+    }
+    log(f"pruning: {n} -> {pruned.n_nodes} nodes (rho {out['rho']:.3f}), {ms_full:.4f} -> {ms_pruned:.4f} ms/iter, "
+        f"dominance test {out['dominance_test_ms']:.1f} ms")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -423,10 +484,11 @@ def main():
     }
     del solver, net
     if not args.no_secondary:
-        sweep, _, _ = tree_sweep(args, 0, max(20, args.steps // 4), 5)
+        sweep, tspec, tr = tree_sweep(args, 0, max(20, args.steps // 4), 5)
         result["tree_sweep"] = sweep
         result["batch"] = batch_sweep(args, 0, max(20, args.steps // 4), 5)
         result["suit_isomorphism"] = suit_iso_sweep(args, max(20, args.steps // 4), 5)
+        result["pruning"] = [pruning_sweep(args, tspec, tr, max(20, args.steps // 4), 5, eps=e) for e in (0.0, 0.05)]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(spec, r, args.cpu_seconds, leaf_params=params)

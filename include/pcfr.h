@@ -152,6 +152,39 @@ int32_t pcfr_tree_export(const pcfr_tree* tree, int32_t* type, int32_t* player, 
 int32_t pcfr_suit_iso_map(const pcfr_tree* tree, const double* ranges, uint32_t* group, int32_t* src,
                           int32_t* perm, int8_t* skip);
 
+/* Online pruning (Sec. 5, "Online Pruning"): dominated actions are removed
+ * once, before any iteration, and every later iteration sweeps the smaller
+ * tree.
+ *
+ * pcfr_prune_dominated runs the dominance test on the GPU, one workgroup per
+ * decision node (the decisions at the information sets are independent).
+ * lo, hi: device doubles [nodes][1326], row n = lower and upper bounds on the
+ * value to the actor of the action leading to node n (rows of nodes that no
+ * decision leads to are not read), per combo, on any scale shared by the
+ * siblings of one node (counterfactual values, or values given the node is
+ * reached).  ranges: host [2][1326], as for pcfr_solver_create.  Action a of
+ * a node is dominated for hand h when hi[a][h] < lo[b][h] for some sibling b;
+ * removed[n] (host, length nodes) becomes 1 when the action into n is
+ * dominated for every hand h of the actor's range (range > 0) that the
+ * node's board does not block, else 0 (so a node where the actor holds no
+ * such hand removes nothing).  With lo <= hi the action holding the largest
+ * lower bound of some hand survives, so no node loses every action.
+ * Synchronises the device's null stream; the bounds must be complete before
+ * the call.
+ *
+ * pcfr_tree_prune builds the reduced tree (host only): the actions flagged
+ * in removed (a flag on a child of a decision node drops that action and its
+ * subtree) are gone, kept nodes keep their breadth-first order and their
+ * children's order, and a child's action index becomes its position among
+ * the kept siblings.  new_id (caller buffer of length nodes, may be NULL)
+ * receives each node's id in the reduced tree, -1 when dropped.  Fails with
+ * PCFR_E_INVALID_ARG when a flag sits on a node no decision leads to or a
+ * decision node would keep no action.  The library owns *out; release with
+ * pcfr_tree_free. */
+int32_t pcfr_prune_dominated(const pcfr_tree* tree, const double* ranges, const double* lo, const double* hi,
+                             uint8_t* removed);
+int32_t pcfr_tree_prune(const pcfr_tree* tree, const uint8_t* removed, pcfr_tree** out, int32_t* new_id);
+
 /* Seven-card hand values, host side (used to order hands at showdown,
  * Sec. 4.3 Stage 4).  cards: n*7 card ids; out: n values.  Value layout:
  * category (0 high card .. 8 straight flush) in bits 20..23 and the
@@ -214,6 +247,15 @@ int32_t pcfr_solver_swept_nodes(pcfr_solver* s, int64_t* n);
  * last iteration, under the strategy it used; PCFR_AVG: under the average
  * strategies of both players.  out: host [2][1326]; blocked combos get 0. */
 int32_t pcfr_get_root_cfv(pcfr_solver* s, int32_t which, double* out);
+
+/* Counterfactual values of every node of subgame sub (0 for a single
+ * subgame) under the average strategies of both players, as
+ * pcfr_get_root_cfv with PCFR_AVG gives them at the root.  out: device
+ * doubles [nodes of the subgame][2][1326] (player 0 row, then player 1);
+ * combos blocked by the root board get 0, combos blocked by cards dealt
+ * above a node carry no meaning.  Not available with suit_iso.
+ * Synchronises. */
+int32_t pcfr_node_values(pcfr_solver* s, int32_t sub, double* out);
 
 /* Exploitability of the average strategy in chips per hand:
  * (BR_0 + BR_1) / 2, BR_i = best-response value of player i against the

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpcfr.so")
 ARCH = os.environ.get("PCFR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "cards.cpp", "tree.cpp", "equity.cpp", "iso.cpp", "solver.hip", "leafnet.hip"]
+SOURCES = ["api.cpp", "cards.cpp", "tree.cpp", "equity.cpp", "iso.cpp", "solver.hip", "leafnet.hip", "prune.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

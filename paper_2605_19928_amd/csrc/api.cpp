@@ -40,6 +40,24 @@ int32_t pcfr_tree_free(pcfr_tree* tree) {
     return PCFR_OK;
 }
 
+int32_t pcfr_tree_prune(const pcfr_tree* tree, const uint8_t* removed, pcfr_tree** out, int32_t* new_id) {
+    if (!tree || !removed || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    pcfr_tree* t = new (std::nothrow) pcfr_tree;
+    if (!t) { set_error("out of host memory"); return PCFR_E_OUT_OF_MEMORY; }
+    int32_t rc;
+    std::vector<int32_t> ids;
+    try {
+        rc = prune_tree(tree->t, removed, t->t, ids);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory pruning the tree");
+        rc = PCFR_E_OUT_OF_MEMORY;
+    }
+    if (rc != PCFR_OK) { delete t; return rc; }
+    if (new_id) std::memcpy(new_id, ids.data(), ids.size() * sizeof(int32_t));
+    *out = t;
+    return PCFR_OK;
+}
+
 int32_t pcfr_tree_info(const pcfr_tree* tree, int64_t* out) {
     if (!tree || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
     const Tree& t = tree->t;

@@ -48,6 +48,7 @@ struct Tree {
 };
 
 int32_t build_tree(const pcfr_tree_spec& spec, Tree& out);
+int32_t prune_tree(const Tree& in, const uint8_t* removed, Tree& out, std::vector<int32_t>& new_id);
 
 // Lossless suit isomorphism at chance nodes (iso.cpp).  Node ids are those
 // of the forest: subgame g's nodes follow the nodes of subgames 0 .. g-1.

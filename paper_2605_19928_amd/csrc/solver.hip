@@ -2302,6 +2302,56 @@ static int32_t root_cfv_impl(pcfr_solver* s, int32_t g, int32_t which, double* o
     return fetch_hands(s, s->ws + L.off_cfv + L.esz * 2 * L.Hp * (size_t)s->P.root_node[g], 2, out, g);
 }
 
+// Counterfactual values of every node of one subgame, combo-indexed (zero on
+// combos the root board blocks): out[(node * 2 + p) * 1326 + k].
+template <typename T>
+__global__ void k_node_values(const T* __restrict__ cfv, int64_t node0, int Hp, const int16_t* __restrict__ c2h,
+                              double* __restrict__ out) {
+    const int64_t row = blockIdx.x;   // node * 2 + player within the subgame
+    const T* src = cfv + (node0 * 2 + row) * Hp;
+    for (int k = threadIdx.x; k < kCombos; k += blockDim.x) {
+        const int h = c2h[k];
+        out[row * kCombos + k] = h >= 0 ? (double)src[h] : 0.0;
+    }
+}
+
+// Values of every node of subgame g under the average strategy profile, into
+// device memory [n_nodes][2][1326].
+static int32_t node_values_impl(pcfr_solver* s, int32_t g, double* out) {
+    if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (g < 0 || g >= s->P.n_sub) { set_error("subgame index out of range"); return PCFR_E_INVALID_ARG; }
+    if (s->cfg.suit_iso) { set_error("node values are not kept for subtrees solved through suit isomorphism"); return PCFR_E_UNSUPPORTED; }
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, out) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("out must be device memory");
+        return PCFR_E_INVALID_ARG;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) { set_error("out must be device memory"); return PCFR_E_INVALID_ARG; }
+    const Plan& L = s->L;
+    const int64_t n0 = s->P.node_base[g];
+    const int64_t nn = (g + 1 < s->P.n_sub ? s->P.node_base[g + 1] : (int64_t)s->P.nodes.size()) - n0;
+    int32_t rc = sweep<MODE_EV>(s);
+    if (rc) return rc;
+    std::vector<int16_t> c2h(kCombos);
+    for (int k = 0; k < kCombos; k++) c2h[k] = (int16_t)s->P.combo_hand[g][k];
+    void* dc = nullptr;
+    HIPCHK(hipMalloc(&dc, sizeof(int16_t) * kCombos));
+    hipError_t e = hipMemcpyAsync(dc, c2h.data(), sizeof(int16_t) * kCombos, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && nn > 0) {
+        if (L.esz == 8)
+            hipLaunchKernelGGL((k_node_values<double>), dim3((unsigned)(2 * nn)), dim3(256), 0, s->stream,
+                               s->at<double>(L.off_cfv), n0, (int)L.Hp, (const int16_t*)dc, out);
+        else
+            hipLaunchKernelGGL((k_node_values<float>), dim3((unsigned)(2 * nn)), dim3(256), 0, s->stream,
+                               s->at<float>(L.off_cfv), n0, (int)L.Hp, (const int16_t*)dc, out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(dc);
+    return e == hipSuccess ? PCFR_OK : hip_check(e, "node values");
+}
+
 // Best-response sweep for every subgame, then per subgame
 // (BR_0 + BR_1) / 2 per unit of joint pair mass.
 static int32_t exploitability_impl(pcfr_solver* s, double* chips, double* br) {
@@ -2600,6 +2650,8 @@ int32_t pcfr_get_root_cfv(pcfr_solver* s, int32_t which, double* out) { return r
 int32_t pcfr_batch_get_root_cfv(pcfr_solver* s, int32_t sub, int32_t which, double* out) {
     return root_cfv_impl(s, sub, which, out, true);
 }
+
+int32_t pcfr_node_values(pcfr_solver* s, int32_t sub, double* out) { return node_values_impl(s, sub, out); }
 
 int32_t pcfr_exploitability(pcfr_solver* s, double* chips_per_hand, double* br) {
     if (!s || !chips_per_hand) { set_error("null argument"); return PCFR_E_INVALID_ARG; }

@@ -169,4 +169,59 @@ int32_t build_tree(const pcfr_tree_spec& sp, Tree& t) {
     return PCFR_OK;
 }
 
+// Online pruning (Sec. 5): the tree with the flagged actions removed before
+// any iteration.  removed[n] != 0 on a child of a decision node drops the
+// action leading to n and n's whole subtree.  Dropping whole subtrees keeps
+// the surviving nodes in breadth-first order with siblings adjacent, so the
+// reduced ids are the ranks of the kept nodes; new_id[n] is that rank, -1
+// for a dropped node.  Children keep their order and their action index
+// becomes their position among the kept siblings.
+int32_t prune_tree(const Tree& in, const uint8_t* removed, Tree& out, std::vector<int32_t>& new_id) {
+    const int32_t N = (int32_t)in.nodes.size();
+    new_id.assign(N, -1);
+    int32_t k = 0;
+    for (int32_t i = 0; i < N; i++) {
+        const Node& n = in.nodes[i];
+        if (removed[i]) {
+            if (n.parent < 0 || in.nodes[n.parent].type != PCFR_NODE_DECISION) {
+                set_error("a pruning flag is set on a node that no decision action leads to");
+                return PCFR_E_INVALID_ARG;
+            }
+            continue;
+        }
+        if (n.parent >= 0 && new_id[n.parent] < 0) continue;
+        new_id[i] = k++;
+    }
+    Tree t{};
+    t.spec = in.spec;
+    t.root_mask = in.root_mask;
+    t.nodes.reserve(k);
+    for (int32_t i = 0; i < N; i++) {
+        if (new_id[i] < 0) continue;
+        const Node& src = in.nodes[i];
+        Node nd = src;
+        nd.parent = src.parent >= 0 ? new_id[src.parent] : -1;
+        nd.first_child = -1;
+        nd.n_child = 0;
+        for (int32_t c = 0; c < src.n_child; c++) {
+            const int32_t x = new_id[src.first_child + c];
+            if (x < 0) continue;
+            if (nd.first_child < 0) nd.first_child = x;
+            nd.n_child++;
+        }
+        if (src.type == PCFR_NODE_DECISION && nd.n_child == 0) {
+            set_error("pruning would remove every action of a decision node");
+            return PCFR_E_INVALID_ARG;
+        }
+        t.nodes.push_back(nd);
+        t.count[nd.type]++;
+        if (nd.type == PCFR_NODE_DECISION) t.rows += nd.n_child;
+        if (nd.depth + 1 > t.n_levels) t.n_levels = nd.depth + 1;
+    }
+    for (const Node& nd : t.nodes)
+        for (int32_t c = 0; c < nd.n_child; c++) t.nodes[nd.first_child + c].action = c;
+    out = std::move(t);
+    return PCFR_OK;
+}
+
 }  // namespace pcfr

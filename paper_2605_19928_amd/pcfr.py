@@ -53,6 +53,8 @@ _SIGS = {
     "pcfr_tree_export": (C.c_int32, [C.c_void_p] * 10),
     "pcfr_eval7_batch": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p]),
     "pcfr_suit_iso_map": (C.c_int32, [C.c_void_p] * 6),
+    "pcfr_prune_dominated": (C.c_int32, [C.c_void_p] * 5),
+    "pcfr_tree_prune": (C.c_int32, [C.c_void_p] * 4),
     "pcfr_solver_swept_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_equity_table": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pcfr_leafnet_workspace_bytes": (C.c_int32, [C.c_int32] * 5 + [C.POINTER(C.c_size_t)]),
@@ -93,6 +95,7 @@ _SIGS = {
     "pcfr_iteration": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_get_strategy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "pcfr_get_root_cfv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "pcfr_node_values": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "pcfr_exploitability": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     "pcfr_state_bytes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "pcfr_save_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -163,6 +166,9 @@ class Tree:
         self._h = h
         self.spec = dict(board=list(board), pot=pot, stacks=tuple(stacks), sizes=list(sizes), allin=allin,
                          max_raises=max_raises, depth_limit=depth_limit)
+        self._load_info()
+
+    def _load_info(self):
         info = np.zeros(16, dtype=np.int64)
         _check(lib().pcfr_tree_info(self._h, _p(info)))
         (self.n_nodes, self.n_decision, self.n_fold, self.n_showdown, self.n_chance, self.n_leaf,
@@ -184,6 +190,39 @@ class Tree:
         skip = np.zeros(n, dtype=np.int8)
         _check(lib().pcfr_suit_iso_map(self._h, _p(r), C.byref(grp), _p(src), _p(perm), _p(skip)))
         return {"group": int(grp.value), "src": src, "perm": perm, "skip": skip}
+
+    def prune_dominated(self, ranges, lo, hi) -> np.ndarray:
+        """Dominance test of online pruning on the GPU.  lo, hi: CUDA float64
+        tensors [n_nodes, 1326] of bounds on the actor's value of the action
+        leading to each node.  Returns uint8 flags [n_nodes]: 1 where that
+        action is dominated for every hand of the actor's range."""
+        import torch
+
+        r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, NCOMBO)
+        for b in (lo, hi):
+            if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64
+                    and b.is_contiguous() and tuple(b.shape) == (self.n_nodes, NCOMBO)):
+                raise ValueError("bounds must be contiguous CUDA float64 tensors [n_nodes, 1326]")
+        torch.cuda.current_stream(lo.device).synchronize()
+        out = np.zeros(self.n_nodes, dtype=np.uint8)
+        _check(lib().pcfr_prune_dominated(self._h, _p(r), C.c_void_p(lo.data_ptr()), C.c_void_p(hi.data_ptr()),
+                                          _p(out)))
+        return out
+
+    def prune(self, removed):
+        """The reduced tree without the flagged actions and their subtrees,
+        and each node's id in it (-1 when dropped)."""
+        rm = np.ascontiguousarray(np.asarray(removed).astype(np.uint8))
+        if rm.shape != (self.n_nodes,):
+            raise ValueError("one flag per node")
+        new_id = np.zeros(self.n_nodes, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib().pcfr_tree_prune(self._h, _p(rm), C.byref(h), _p(new_id)))
+        t = Tree.__new__(Tree)
+        t._h = h
+        t.spec = dict(self.spec)
+        t._load_info()
+        return t, new_id
 
     def export(self) -> dict:
         n = self.n_nodes
@@ -297,6 +336,17 @@ class Solver:
     def root_cfv(self, which: str = "current") -> np.ndarray:
         out = np.zeros((2, NCOMBO), dtype=np.float64)
         _check(lib().pcfr_get_root_cfv(self._h, CURRENT if which == "current" else AVG, _p(out)))
+        return out
+
+    def node_values(self, sub: int = 0):
+        """Counterfactual values of every node under the average strategies:
+        CUDA float64 tensor [n_nodes, 2, 1326]."""
+        import torch
+
+        n = self.tree.n_nodes if not hasattr(self, "trees") else self.trees[sub].n_nodes
+        out = torch.zeros((n, 2, NCOMBO), dtype=torch.float64, device=self.device)
+        self.stream.synchronize()
+        _check(lib().pcfr_node_values(self._h, int(sub), C.c_void_p(out.data_ptr())))
         return out
 
     def exploitability(self):

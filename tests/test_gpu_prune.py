@@ -1,0 +1,145 @@
+"""Online pruning on the GPU (Sec. 5): the dominance kernel against the
+oracle's test (integer flags, bit-exact), the solve of the library's reduced
+tree against the oracle's solve of its own reduced tree (FP64 bound), and the
+per-node values the bounds of a later pass can be built from."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_19928_amd import inputs as I
+from paper_2605_19928_amd import pcfr as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def spec_of(board, stacks=(150, 150), sizes=(50,), max_raises=2):
+    return dict(board=list(board), pot=100, stacks=stacks, sizes=list(sizes), allin=True, max_raises=max_raises,
+                depth_limit=0)
+
+
+def synthetic_bounds(rng, e, spread=40.0, noise=10.0, width=5.0):
+    """Per action an offset shared by every hand plus per-hand noise, and
+    intervals of random half-width: some public actions end up dominated for
+    every hand, most do not."""
+    n = len(e["type"])
+    mid = rng.normal(size=(n, P.NCOMBO)) * noise
+    for v in np.flatnonzero(e["type"] == P.NODE_DECISION):
+        fc, A = int(e["first_child"][v]), int(e["n_child"][v])
+        mid[fc: fc + A] += rng.normal(size=(A, 1)) * spread
+    half = rng.random((n, P.NCOMBO)) * width
+    return mid - half, mid + half
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("case", ["river", "turn"])
+def test_dominance_flags_match_oracle(case):
+    rng = np.random.default_rng(11)
+    if case == "river":
+        spec, r = I.river_config(2, support=300)
+    else:
+        board = [50, 46, 26, 10]
+        spec = spec_of(board)
+        r = np.stack([I.dirichlet_range(rng, board, support=200), I.dirichlet_range(rng, board, support=200)])
+    say(f"case: dominance flags, {case}, board={spec['board']}")
+    gt, ot = P.Tree(**spec), O.Tree.holdem(**spec)
+    e = gt.export()
+    lo, hi = synthetic_bounds(rng, e)
+    fg = gt.prune_dominated(r, _dev(lo), _dev(hi))
+    fo = ot.prune_dominated(r, lo, hi)
+    say(f"  {int(fg.sum())} actions removed of {gt.n_rows}")
+    assert fg.sum() > 0
+    np.testing.assert_array_equal(fg, fo)
+    # infinite bounds, ties (strict comparison) and an empty range remove nothing
+    inf = np.full_like(lo, np.inf)
+    assert not gt.prune_dominated(r, _dev(-inf), _dev(inf)).any()
+    same = np.zeros_like(lo)
+    assert not gt.prune_dominated(r, _dev(same), _dev(same)).any()
+    r0 = r.copy()
+    r0[:] = 0
+    assert not gt.prune_dominated(r0, _dev(lo), _dev(hi)).any()
+    # one player's range emptied: only the other player's actions can go
+    r1 = r.copy()
+    r1[1] = 0
+    f1 = gt.prune_dominated(r1, _dev(lo), _dev(hi))
+    np.testing.assert_array_equal(f1, ot.prune_dominated(r1, lo, hi))
+    par = e["parent"][np.flatnonzero(f1)]
+    assert np.all(e["player"][par] == 0)
+
+
+@pytest.mark.parametrize("case", ["river", "turn"])
+def test_pruned_solve_matches_oracle(case):
+    rng = np.random.default_rng(5)
+    if case == "river":
+        spec, r = I.river_config(3, support=120)
+        T = 60
+    else:
+        board = [48, 44, 21, 17]
+        spec = spec_of(board)
+        r = np.stack([I.dirichlet_range(rng, board, support=30), I.dirichlet_range(rng, board, support=30)])
+        T = 20
+    say(f"case: pruned solve vs oracle, {case}, board={spec['board']} T={T}")
+    gt, ot = P.Tree(**spec), O.Tree.holdem(**spec)
+    # milder offsets than the flag test, so that the reduced trees keep a fair share of their nodes
+    lo, hi = synthetic_bounds(rng, gt.export(), spread=20.0, width=10.0)
+    gr, gmap = gt.prune(gt.prune_dominated(r, _dev(lo), _dev(hi)))
+    orr, omap = ot.prune(ot.prune_dominated(r, lo, hi))
+    say(f"  nodes {gt.n_nodes} -> {gr.n_nodes}")
+    assert gt.n_nodes // 8 < gr.n_nodes < gt.n_nodes and gr.n_nodes == orr.n_nodes
+    np.testing.assert_array_equal(gmap, omap)
+    gs = P.Solver(gr, r, P.SolverConfig(dtype="f64"))
+    gs.iterate(T)
+    os_ = O.Solver(orr, r, support_only=True)
+    os_.iterate(T)
+    pot = spec["pot"]
+    mask = (r > 0) & ~I.blocked_mask(spec["board"])[None, :]
+    for which in ("current", "avg"):
+        d = np.abs(gs.root_cfv(which) - os_.root_cfv(which))[mask].max() / pot
+        say(f"  root cfv ({which}) max |d| = {d:.3e} pot")
+        assert d <= 1e-9
+    eg, _ = gs.exploitability()
+    eo, _ = os_.exploitability()
+    say(f"  exploitability gpu {eg:.9f} oracle {eo:.9f}")
+    assert abs(eg - eo) / pot <= 1e-9
+    e = orr.export()
+    worst = 0.0
+    for n in np.flatnonzero(e["type"] == O.T_DEC):
+        own = mask[int(e["player"][n])]
+        worst = max(worst, float(np.abs(gs.strategy(int(n), "avg") - os_.strategy(int(n), "avg"))[:, own].max()))
+    say(f"  avg strategies max |d| = {worst:.3e}")
+    assert worst <= 1e-9
+
+
+def test_node_values_consistent():
+    """Node values under the average strategies: the root rows are the root
+    values the library reports, and at every decision node the actor's value
+    is the average-strategy mix of its children's and the other player's the
+    sum of its children's (eq. cfv, the opponent's reach carries the actor's
+    probabilities)."""
+    spec, r = I.river_config(4, support=200)
+    say(f"case: node values, river board={spec['board']}")
+    gt = P.Tree(**spec)
+    gs = P.Solver(gt, r, P.SolverConfig(dtype="f64"))
+    gs.iterate(40)
+    V = gs.node_values().cpu().numpy()
+    root = gs.root_cfv("avg")
+    assert np.abs(V[0] - root).max() <= 1e-12 * spec["pot"]
+    e = gt.export()
+    valid = ~I.blocked_mask(spec["board"])
+    worst = 0.0
+    for n in np.flatnonzero(e["type"] == P.NODE_DECISION):
+        p = int(e["player"][n])
+        fc, A = int(e["first_child"][n]), int(e["n_child"][n])
+        sg = gs.strategy(int(n), "avg")
+        mix = (sg * V[fc: fc + A, p]).sum(axis=0)
+        tot = V[fc: fc + A, 1 - p].sum(axis=0)
+        worst = max(worst, float(np.abs(mix - V[n, p])[valid].max()), float(np.abs(tot - V[n, 1 - p])[valid].max()))
+    say(f"  decision-node consistency max |d| = {worst:.3e} chips")
+    assert worst <= 1e-9 * spec["pot"]

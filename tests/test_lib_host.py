@@ -113,3 +113,42 @@ def test_equity_table_matches_oracle(nb):
     ora_t = O.Tree.holdem(**spec)
     leaf = int(np.flatnonzero(ora_t.export()["type"] == O.T_LEAF)[0])
     np.testing.assert_array_equal(lib_t.equity_table(), ora_t.equity_table(leaf))
+
+
+@pytest.mark.parametrize("spec", SPECS[:6], ids=[f"s{i}" for i in range(6)])
+def test_pruned_tree_arrays_identical(spec):
+    """The library's reduced tree of online pruning (one pass over the
+    breadth-first ids) against the oracle's (a rebuilt pool renumbered
+    breadth-first), for the same random flags."""
+    a = P.Tree(**spec)
+    b = O.Tree.holdem(**spec)
+    e = a.export()
+    rng = np.random.default_rng(len(e["type"]))
+    flags = np.zeros(a.n_nodes, dtype=np.uint8)
+    for n in np.flatnonzero(e["type"] == P.NODE_DECISION):
+        fc, A = int(e["first_child"][n]), int(e["n_child"][n])
+        if A >= 2 and rng.random() < 0.3:
+            flags[fc + rng.integers(A)] = 1
+    ra, ma = a.prune(flags)
+    rb, mb = b.prune(flags)
+    assert ra.n_nodes == rb.n_nodes < a.n_nodes
+    np.testing.assert_array_equal(ma, mb)
+    ea, eb = ra.export(), rb.export()
+    for k in ("type", "player", "parent", "action", "depth", "chance_card", "first_child", "n_child", "contrib"):
+        np.testing.assert_array_equal(ea[k], eb[k], err_msg=k)
+    assert (ra.n_decision, ra.n_fold, ra.n_showdown, ra.n_chance, ra.n_leaf, ra.n_allin, ra.n_levels, ra.n_rows) == \
+        (rb.n_decision, rb.n_fold, rb.n_showdown, rb.n_chance, rb.n_leaf, rb.n_allin, rb.n_levels, rb.n_rows)
+
+
+def test_prune_rejects_invalid_flags():
+    a = P.Tree(**SPECS[0])
+    e = a.export()
+    flags = np.zeros(a.n_nodes, dtype=np.uint8)
+    flags[0] = 1
+    with pytest.raises(P.PcfrError):
+        a.prune(flags)
+    flags[:] = 0
+    n = int(np.flatnonzero(e["type"] == P.NODE_DECISION)[0])
+    flags[e["first_child"][n]: e["first_child"][n] + e["n_child"][n]] = 1
+    with pytest.raises(P.PcfrError):
+        a.prune(flags)
