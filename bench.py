@@ -49,8 +49,12 @@ BF16_PEAK_TFLOPS = 2500.0
 # tables and commands in profiles/*_hbm_counters.md).  They describe the
 # kernels as they were measured; a changed kernel needs a new measurement.
 MEASURED_TRAFFIC = {
-    # k_gemm_nt<64,64,1> (hidden layers, 64x64 tiles), 1029 rows: per launch
-    "gemm_hidden_64x64": {"read": 38112592, "write": 3342336},
+    # k_gemm_nt<BM,BN,1,KS,PF> (hidden layers, bias + ReLU), 1029 rows: per
+    # launch for each forward tile (PCFR_TILE_*), averaged over the hidden
+    # layers that used it in the counter runs: (read, write) bytes
+    "gemm_hidden_by_tile": {0: (37446393, 3342336), 1: (37863007, 3342336), 2: (43517025, 3342336),
+                            3: (43590750, 3342336), 4: (36116077, 3342336), 5: (43531446, 3342336),
+                            6: (41565068, 3342336), 7: (43539552, 3342336)},
     # k_backward<float,0,*> + k_backward_fused over one iteration of the
     # seed-0 turn subgame (all backward launches)
     "turn_backward_iteration": 2440954947,
@@ -433,9 +437,9 @@ def main():
     achieved = (hidden_flops / n_hidden) / (gemm_ms / n_hidden * 1e-3) / 1e12
     all_gemm_tflops = flops_alg / ((pms[5] + pms[6]) * 1e-3) / 1e12
     gemm_traffic = None
-    if args.dtype == "f32" and all(t == 0 for t in net.tiles[:-1]):
-        m = MEASURED_TRAFFIC["gemm_hidden_64x64"]
-        gemm_traffic = m["read"] + m["write"]
+    by_tile = MEASURED_TRAFFIC["gemm_hidden_by_tile"]
+    if args.dtype == "f32" and all(t in by_tile for t in net.tiles[:-1]):
+        gemm_traffic = float(np.mean([sum(by_tile[t]) for t in net.tiles[:-1]]))
     expl, _ = solver.exploitability()
     log(f"kernel ms/iter {dict(zip(CLASSES, np.round(pms[:7], 4)))} launches {pl[:7].tolist()}")
     result = {
@@ -476,7 +480,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / BF16_PEAK_TFLOPS,
             "traffic": gemm_traffic,
-            "traffic_note": "HBM bytes per launch (hardware counters); algorithmic operand bytes are ~9.6 MB",
+            "traffic_note": "HBM bytes per launch (hardware counters per tile variant, mean over the hidden "
+                            "layers' tiles); algorithmic operand bytes are ~9.6 MB",
             "avg_launch_us": 1e3 * gemm_ms / n_hidden,
             "launches_per_iter": n_hidden,
             "alg_flops_per_launch": hidden_flops / n_hidden,

@@ -352,14 +352,15 @@ int32_t pcfr_leafnet_autotune(pcfr_leafnet* net, int32_t m, int32_t reps, double
 
 /* Forward GEMM tile per layer (count = depth + 1 layers): PCFR_TILE_DEFAULT
  * (-1, chosen from the shape), PCFR_TILE_64x64, PCFR_TILE_128x64,
- * PCFR_TILE_64x128, PCFR_TILE_128x128 (rows x columns, 4 waves), or
+ * PCFR_TILE_64x128, PCFR_TILE_128x128 (rows x columns, 4 waves),
  * PCFR_TILE_64x64_K2, PCFR_TILE_64x128_K2 (two 4-wave groups that split
- * the K loop and add their partial sums); the column count must divide the
- * layer's output width padded to 64, else PCFR_E_INVALID_ARG.  get returns
- * the current choice. */
+ * the K loop and add their partial sums), or PCFR_TILE_64x64_P4,
+ * PCFR_TILE_64x128_P4 (4 waves, global loads four K stages ahead instead
+ * of two); the column count must divide the layer's output width padded to
+ * 64, else PCFR_E_INVALID_ARG.  get returns the current choice. */
 enum {
     PCFR_TILE_DEFAULT = -1, PCFR_TILE_64x64 = 0, PCFR_TILE_128x64 = 1, PCFR_TILE_64x128 = 2, PCFR_TILE_128x128 = 3,
-    PCFR_TILE_64x64_K2 = 4, PCFR_TILE_64x128_K2 = 5
+    PCFR_TILE_64x64_K2 = 4, PCFR_TILE_64x128_K2 = 5, PCFR_TILE_64x64_P4 = 6, PCFR_TILE_64x128_P4 = 7
 };
 int32_t pcfr_leafnet_set_tiles(pcfr_leafnet* net, const int32_t* tiles, int32_t count);
 int32_t pcfr_leafnet_get_tiles(pcfr_leafnet* net, int32_t* tiles, int32_t count);

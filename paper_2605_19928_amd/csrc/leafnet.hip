@@ -58,7 +58,11 @@ enum { EPI_BIAS_F32 = 0, EPI_BIAS_RELU_BF = 1, EPI_F32 = 2, EPI_MASK_BF = 3 };
 // doubles the waves in flight per tile for shapes whose tile count leaves
 // CUs idle.  Every group runs the same number of loop trips (a group with
 // fewer stages idles through its last ones), so the workgroup barriers match.
-template <int BM, int BN, int EPI, int KS = 1>
+//
+// PF is how many K stages ahead the global loads run (a ring of PF + 1
+// register slots).  Two stages hide an L2 hit; operands that come from
+// another XCD's L2 or from HBM need more.
+template <int BM, int BN, int EPI, int KS = 1, int PF = 2>
 __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
                                                       const uint16_t* __restrict__ B, int ldb, int M, int K,
                                                       const float* __restrict__ bias, void* __restrict__ Cout,
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict
     // constants after the 3-way unroll below, so the ring stays in
     // registers), stored to the idle LDS buffer one stage ahead, and consumed
     // from LDS by the MFMAs.
-    constexpr int D = 3;
+    constexpr int D = PF + 1;
     u32x4 ra[D][CA], rb[D][CB];
 #define LN_GLOAD(slot, kt)                                                                         \
     do {                                                                                           \
@@ -123,8 +127,23 @@ __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict
 #pragma unroll
                 for (int r = 0; r < 16; r++) acc[q][i][j][r] = 0.f;
     const int kh = 8 * (lane >> 5), l32 = lane & 31;
-    if (KS == 1 || ng > 0) LN_GLOAD(0, 0);
-    if (ng > 1) LN_GLOAD(1, 1);
+    // Branch-free steady state (enough stages): every stage issues
+    // its prefetch unconditionally, so the compiler can count the loads in
+    // flight and wait for exactly the slot an LDS store needs; behind a
+    // conditional prefetch it must assume the worst and wait for all of them.
+    // (with KS groups, the steady loop runs the trip count of the group with
+    // the fewest stages in every group, so that all take the same barriers)
+    const int ng_min = KS == 1 ? nk : max(0, min(nk - (KS - 1) * trips, trips));
+    const bool steady = ng_min >= PF + D;
+    if (steady) {
+#pragma unroll
+        for (int q = 0; q < PF; q++) LN_GLOAD(q, q);
+    } else {
+        if (KS == 1 || ng > 0) LN_GLOAD(0, 0);
+#pragma unroll
+        for (int q = 1; q < PF; q++)
+            if (ng > q) LN_GLOAD(q, q);
+    }
     if (KS == 1 || ng > 0) LN_SSTORE(0, 0);
     __syncthreads();
 #define LN_COMPUTE(buf)                                                                            \
@@ -142,21 +161,44 @@ __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict
                     acc[kk % KACC][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(               \
                         fa[kk][i], fb[kk][j], acc[kk % KACC][i][j], 0, 0, 0);                      \
     } while (0)
-    // one stage: prefetch stage kt+2 into slot LSLOT, compute stage kt, move
+    // one stage: prefetch stage kt+PF into slot LSLOT, compute stage kt, move
     // stage kt+1 (slot SSLOT) into the other LDS buffer; stages past this
     // group's count are skipped but the barrier is still taken
+    // The stage barrier orders LDS traffic only: this wave's LDS reads of the
+    // buffer just consumed and its writes of the next one are complete
+    // (lgkmcnt 0) before any wave passes.  __syncthreads() would also wait
+    // for every global load in flight (vmcnt 0), i.e. for the prefetches
+    // issued this very stage, and serialise the pipeline on memory latency;
+    // the register-ring loads need no barrier, the compiler waits for each
+    // slot before its LDS store.
 #define LN_STAGE(kt, LSLOT, SSLOT)                                                                 \
     do {                                                                                           \
-        if ((kt) + 2 < ng) LN_GLOAD(LSLOT, (kt) + 2);                                              \
+        if ((kt) + PF < ng) LN_GLOAD(LSLOT, (kt) + PF);                                            \
         if (KS == 1 || (kt) < ng) LN_COMPUTE((kt) & 1);                                            \
         if ((kt) + 1 < ng) LN_SSTORE(SSLOT, ((kt) + 1) & 1);                                       \
-        __syncthreads();                                                                           \
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");                            \
     } while (0)
-    for (int kt = 0; kt < trips; kt += 3) {
-        LN_STAGE(kt, 2, 1);
-        if (kt + 1 < trips) LN_STAGE(kt + 1, 0, 2);
-        if (kt + 2 < trips) LN_STAGE(kt + 2, 1, 0);
+#define LN_STAGE_STEADY(kt, LSLOT, SSLOT)                                                          \
+    do {                                                                                           \
+        LN_GLOAD(LSLOT, (kt) + PF);                                                                \
+        LN_COMPUTE((kt) & 1);                                                                      \
+        LN_SSTORE(SSLOT, ((kt) + 1) & 1);                                                          \
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");                            \
+    } while (0)
+    // unrolled D ways, so that every slot index is a compile-time constant
+    int kt0 = 0;
+    if (steady) {
+        for (; kt0 + D <= ng_min - PF; kt0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; u++) LN_STAGE_STEADY(kt0 + u, (u + PF) % D, (u + 1) % D);
+        }
     }
+    for (int kt = kt0; kt < trips; kt += D) {
+#pragma unroll
+        for (int u = 0; u < D; u++)
+            if (kt + u < trips) LN_STAGE(kt + u, (u + PF) % D, (u + 1) % D);
+    }
+#undef LN_STAGE_STEADY
 #undef LN_STAGE
 #undef LN_COMPUTE
 #undef LN_GLOAD
@@ -347,7 +389,7 @@ static int64_t r64(int64_t x) { return (x + 63) / 64 * 64; }
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool gemm_tile_valid(int tile, int64_t N) {
-    static const int bn[kGemmTiles] = {64, 64, 128, 128, 64, 128};
+    static const int bn[kGemmTiles] = {64, 64, 128, 128, 64, 128, 64, 128};
     return tile >= 0 && tile < kGemmTiles && N % bn[tile] == 0;
 }
 
@@ -362,24 +404,26 @@ int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const u
         tile = (M % 128 == 0) && (N % 128 == 0) && (M / 128) * (N / 128) >= 256 ? GEMM_128x128 : GEMM_64x64;
     }
     if (!gemm_tile_valid(tile, N)) { set_error("GEMM tile does not divide N"); return PCFR_E_INVALID_ARG; }
-#define LN_GEMM(BMv, BNv, E, KSv)                                                                        \
-    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E, KSv>),                                                   \
+#define LN_GEMM(BMv, BNv, E, KSv, PFv)                                                                   \
+    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E, KSv, PFv>),                                              \
                        dim3((unsigned)(N / BNv), (unsigned)((M + BMv - 1) / BMv)), dim3(256 * KSv), 0, st, \
                        A, lda, B, ldb, (int)M, (int)K, bias, C, ldc, mask)
-#define LN_EPI(BMv, BNv, KSv)                                                       \
-    switch (epi) {                                                                  \
-        case EPI_BIAS_F32: LN_GEMM(BMv, BNv, EPI_BIAS_F32, KSv); break;             \
-        case EPI_BIAS_RELU_BF: LN_GEMM(BMv, BNv, EPI_BIAS_RELU_BF, KSv); break;     \
-        case EPI_F32: LN_GEMM(BMv, BNv, EPI_F32, KSv); break;                       \
-        default: LN_GEMM(BMv, BNv, EPI_MASK_BF, KSv); break;                        \
+#define LN_EPI(BMv, BNv, KSv, PFv)                                                       \
+    switch (epi) {                                                                       \
+        case EPI_BIAS_F32: LN_GEMM(BMv, BNv, EPI_BIAS_F32, KSv, PFv); break;             \
+        case EPI_BIAS_RELU_BF: LN_GEMM(BMv, BNv, EPI_BIAS_RELU_BF, KSv, PFv); break;     \
+        case EPI_F32: LN_GEMM(BMv, BNv, EPI_F32, KSv, PFv); break;                       \
+        default: LN_GEMM(BMv, BNv, EPI_MASK_BF, KSv, PFv); break;                        \
     }
     switch (tile) {
-        case GEMM_64x64: LN_EPI(64, 64, 1); break;
-        case GEMM_128x64: LN_EPI(128, 64, 1); break;
-        case GEMM_64x128: LN_EPI(64, 128, 1); break;
-        case GEMM_128x128: LN_EPI(128, 128, 1); break;
-        case GEMM_64x64_K2: LN_EPI(64, 64, 2); break;
-        default: LN_EPI(64, 128, 2); break;
+        case GEMM_64x64: LN_EPI(64, 64, 1, 2); break;
+        case GEMM_128x64: LN_EPI(128, 64, 1, 2); break;
+        case GEMM_64x128: LN_EPI(64, 128, 1, 2); break;
+        case GEMM_128x128: LN_EPI(128, 128, 1, 2); break;
+        case GEMM_64x64_K2: LN_EPI(64, 64, 2, 2); break;
+        case GEMM_64x128_K2: LN_EPI(64, 128, 2, 2); break;
+        case GEMM_64x64_P4: LN_EPI(64, 64, 1, 4); break;
+        default: LN_EPI(64, 128, 1, 4); break;
     }
 #undef LN_EPI
 #undef LN_GEMM

@@ -27,7 +27,8 @@ struct LeafNetPlan {
 // the _K2 variants run two such groups that split K (8 waves).
 enum {
     GEMM_64x64 = 0, GEMM_128x64 = 1, GEMM_64x128 = 2, GEMM_128x128 = 3, GEMM_64x64_K2 = 4, GEMM_64x128_K2 = 5,
-    kGemmTiles = 6
+    GEMM_64x64_P4 = 6, GEMM_64x128_P4 = 7,
+    kGemmTiles = 8
 };
 bool gemm_tile_valid(int tile, int64_t N);
 
