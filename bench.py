@@ -36,6 +36,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -96,6 +97,51 @@ def pair_count(r0, r1, cc):
     return int((~clash).sum())
 
 
+def history_visits(tree, spec, r):
+    """Per-iteration history visits in the paper's sense: over every node, the
+    number of (hand, opponent hand) pairs with mass on both sides that share
+    no card with each other or with the node's board."""
+    from paper_2605_19928_amd import inputs as I
+
+    cc = I.combo_cards()
+    e = tree.export()
+    n = len(e["type"])
+    dealt = [()] * n
+    for v in range(1, n):
+        c = int(e["chance_card"][v])
+        dealt[v] = dealt[e["parent"][v]] + ((c,) if c >= 0 else ())
+    groups = {}
+    for d in dealt:
+        groups[d] = groups.get(d, 0) + 1
+    total = 0
+    for d, cnt in groups.items():
+        keep = np.ones(len(cc), dtype=bool)
+        for c in d:
+            keep &= (cc[:, 0] != c) & (cc[:, 1] != c)
+        total += cnt * pair_count(r[0] * keep, r[1] * keep, cc)
+    return total
+
+
+def copy_ceiling_gbs(mib=1024, reps=10):
+    """HBM copy bandwidth of the box: a device-to-device copy of `mib` MiB
+    (read once, written once), event-timed."""
+    import torch
+
+    x = torch.ones(mib * (1 << 18), dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / reps * 1e-3
+    del x, y
+    return 2.0 * mib * (1 << 20) / sec / 1e9
+
+
 def cpu_baseline(spec, r, budget_s, leaf_params=None):
     """Time the FP64 oracle on the same tree with sparse-support ranges at two
     support sizes, fit time = fixed + per_pair * pairs, and extrapolate to the
@@ -139,6 +185,30 @@ def cpu_baseline(spec, r, budget_s, leaf_params=None):
                 break
         pts.append((2 * pair_count(rs[0], rs[1], cc), el / n))
         del s
+    # the tree walk alone (no network refresh) on the larger sample, on every
+    # host thread and on one, for the oracle's parallel speedup
+    cores = O.max_threads()
+    pick = np.sort(np.random.default_rng(1234).choice(ok, 24, replace=False))
+    rs = np.zeros_like(r)
+    rs[:, pick] = r[:, pick]
+    walk = {}
+    for th in (cores, 1):
+        s = O.Solver(t, rs, support_only=True)
+        n1, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < min(budget_s / 6, 3.0) and n1 < 50:
+            s.iterate(1, threads=th)
+            n1 += 1
+        walk[th] = (time.perf_counter() - t0) / max(n1, 1)
+        del s
+    O.Solver(t, rs, support_only=True).iterate(0, threads=cores)   # restore the thread count
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     (p1, t1), (p2, t2) = pts
     per_pair = max((t2 - t1) / max(p2 - p1, 1), 0.0)
     fixed = max(t1 - per_pair * p1, 0.0)
@@ -146,8 +216,10 @@ def cpu_baseline(spec, r, budget_s, leaf_params=None):
     return {
         "value": 1.0 / sec_full,
         "unit": "iters/s",
-        "cores": O.max_threads(),
+        "cores": cores,
         "kind": "oracle",
+        "host_cpu": cpu_model, "host_nproc": os.cpu_count(),
+        "walk_s_per_iter_24combo": {"threads": cores, "all_threads": walk[cores], "one_thread": walk[1]},
         "sample": (f"oracle on the same tree with random 8- and 24-combo supports per player "
                    f"({pts[0][1]:.3f} and {pts[1][1]:.3f} s/iter over {pts[0][0]} and {pts[1][0]} hand pairs"
                    + (", FP64 leaf network included" if leaf_params is not None else "")
@@ -189,6 +261,7 @@ def tree_sweep(args, seed, steps, warmup):
     esz = 8 if args.dtype == "f64" else 4
     alg_bytes = 4 * esz * tree.n_rows * tree.n_hands   # R and S, each read and written once
     ms = timed(solver, steps, warmup)
+    visits = history_visits(tree, spec, r)
     pms, pl = solver.profile(args.profile_iters)
     pms, pl = pms / args.profile_iters, pl // args.profile_iters
     achieved = alg_bytes / (pms[3] * 1e-3) / 1e9
@@ -201,6 +274,7 @@ def tree_sweep(args, seed, steps, warmup):
         "action_rows": tree.n_rows, "hands": tree.n_hands, "levels": tree.n_levels,
         "state_bytes_R_S": 2 * esz * tree.n_rows * tree.n_hands_padded,
         "ms_per_iter": ms, "iters_per_s": 1000.0 / ms,
+        "history_visits_per_iter": visits, "history_visits_per_s": visits * 1000.0 / ms,
         "iteration_hbm_frac": (alg_bytes / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
         "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
         "exploitability_mbb_per_hand": expl * 100.0,
@@ -364,6 +438,59 @@ def pruning_sweep(args, spec, r, steps, warmup, warm_iters=100, eps=0.1):
     return out
 
 
+def spr_sweep(args, steps, warmup, seed=0):
+    """The turn abstraction at stack-to-pot ratios 1, 2, 4 and 8: nodes, sum of
+    A*H over decision nodes, R + S bytes, ms/iter and the backward kernels'
+    algorithmic HBM fraction (16 B per (row, hand) in FP32); only trees whose
+    R + S exceed the 256 MB last-level cache count toward a bandwidth claim."""
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+
+    out = []
+    esz = 8 if args.dtype == "f64" else 4
+    for spr in (1, 2, 4, 8):
+        spec, r = I.turn_config(seed, spr=spr)
+        tree = P.Tree(**spec)
+        s = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
+        ms = timed(s, steps, warmup)
+        pms, _ = s.profile(args.profile_iters)
+        pms = pms / args.profile_iters
+        sum_ah = tree.n_rows * tree.n_hands
+        alg = 4 * esz * sum_ah
+        out.append({"spr": spr, "pot": spec["pot"], "stacks": list(spec["stacks"]), "nodes": tree.n_nodes,
+                    "decision_nodes": tree.n_decision, "chance_nodes": tree.n_chance, "sum_AH": sum_ah,
+                    "r_plus_s_bytes": 2 * esz * sum_ah, "ms_per_iter": ms,
+                    "backward_ms_per_iter": float(pms[3]),
+                    "backward_alg_hbm_frac": alg / (pms[3] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "iteration_alg_hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "counts_toward_bandwidth_claim": 2 * esz * sum_ah > 256 * (1 << 20)})
+        s.close()
+        log(f"turn SPR {spr}: {tree.n_nodes} nodes, {ms:.4f} ms/iter, backward "
+            f"{out[-1]['backward_alg_hbm_frac']:.3f} of HBM peak (algorithmic)")
+    return out
+
+
+def gemm_shape_point(args, m=2048, reps=50):
+    """The leaf network's forward at m rows (the second GEMM shape point),
+    after the tile autotuner: us per forward and TFLOP/s."""
+    import torch
+
+    from paper_2605_19928_amd import pcfr as P
+    from paper_2605_19928_amd import train as T
+
+    net = P.LeafNet(P.LEAF_D_IN, 1536, 4, P.LEAF_D_OUT, max_batch=m)
+    net.set_params(he_params(net.layer_shapes(), 0))
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal((m, P.LEAF_D_IN)).astype(np.float32)).cuda()
+    net.autotune(m, 10)
+    ms = T.forward_ms(net, x, reps=reps)
+    flops = 2.0 * m * sum(o * i for o, i in net.layer_shapes())
+    out = {"rows": m, "us_per_forward": ms * 1e3, "tflops": flops / (ms * 1e-3) / 1e12, "tiles": list(net.tiles)}
+    net.close()
+    log(f"leaf network forward at {m} rows: {ms * 1e3:.1f} us, {out['tflops']:.0f} TFLOP/s")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -467,6 +594,9 @@ def main():
         },
         "exploitability_mbb_per_hand": expl * 100.0,
         "exploitability_note": "of the average strategy within the depth-limited game, leaves valued by the network",
+        "history_visits_per_s": history_visits(tree, spec, r) * 1000.0 / ms,
+        "history_visits_note": "per iteration, over every node, hand pairs with mass on both sides that share no "
+                               "card with each other or the node's board; the paper reports about 2.0e10/s",
         "autotune_ms_per_iter_before_after": [tune_before, tune_after],
         "leaf_gemm_tiles": net.tiles,
         "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
@@ -494,6 +624,10 @@ def main():
         result["batch"] = batch_sweep(args, 0, max(20, args.steps // 4), 5)
         result["suit_isomorphism"] = suit_iso_sweep(args, max(20, args.steps // 4), 5)
         result["pruning"] = [pruning_sweep(args, tspec, tr, max(20, args.steps // 4), 5, eps=e) for e in (0.0, 0.05)]
+        result["turn_spr_sweep"] = spr_sweep(args, max(20, args.steps // 4), 5)
+        result["leaf_gemm_m2048"] = gemm_shape_point(args)
+        result["hbm_copy_ceiling_gbs"] = copy_ceiling_gbs()
+        log(f"HBM copy ceiling: {result['hbm_copy_ceiling_gbs']:.0f} GB/s")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(spec, r, args.cpu_seconds, leaf_params=params)
