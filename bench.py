@@ -53,9 +53,10 @@ MEASURED_TRAFFIC = {
     # k_gemm_nt<BM,BN,1,KS,PF> (hidden layers, bias + ReLU), 1029 rows: per
     # launch for each forward tile (PCFR_TILE_*), averaged over the hidden
     # layers that used it in the counter runs: (read, write) bytes
-    "gemm_hidden_by_tile": {0: (37446393, 3342336), 1: (37863007, 3342336), 2: (43517025, 3342336),
-                            3: (43590750, 3342336), 4: (36116077, 3342336), 5: (43531446, 3342336),
-                            6: (41565068, 3342336), 7: (43539552, 3342336)},
+    "gemm_hidden_by_tile": {0: (38504466, 3342336), 1: (37855857, 3342336), 2: (43517046, 3342336),
+                            3: (43587955, 3342336), 4: (39483758, 3342336), 5: (43535477, 3342336),
+                            6: (35164813, 3342336), 7: (43539573, 3342336), 8: (31696514, 3342336),
+                            9: (31653864, 3342336)},
     # k_backward<float,0,*> + k_backward_fused over one iteration of the
     # seed-0 turn subgame (all backward launches)
     "turn_backward_iteration": 2440954947,

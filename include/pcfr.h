@@ -356,11 +356,19 @@ int32_t pcfr_leafnet_autotune(pcfr_leafnet* net, int32_t m, int32_t reps, double
  * PCFR_TILE_64x64_K2, PCFR_TILE_64x128_K2 (two 4-wave groups that split
  * the K loop and add their partial sums), or PCFR_TILE_64x64_P4,
  * PCFR_TILE_64x128_P4 (4 waves, global loads four K stages ahead instead
- * of two); the column count must divide the layer's output width padded to
- * 64, else PCFR_E_INVALID_ARG.  get returns the current choice. */
+ * of two), or PCFR_TILE_DIRECT, PCFR_TILE_DIRECT_K2 (one wave per 64 x 64
+ * output tile, two with _K2 splitting K, both operands read straight into
+ * registers from copies in an MFMA-ready layout, no LDS stage; only for
+ * layers after the first whose input width is 1536, and every layer after a
+ * direct layer must be direct too, since a direct layer's input is written
+ * in that layout by the layer before).  The column count must divide the
+ * layer's output width padded to 64; a tile that does not fit the layer
+ * gives PCFR_E_INVALID_ARG.  Training steps run direct layers with the
+ * default tile.  get returns the current choice. */
 enum {
     PCFR_TILE_DEFAULT = -1, PCFR_TILE_64x64 = 0, PCFR_TILE_128x64 = 1, PCFR_TILE_64x128 = 2, PCFR_TILE_128x128 = 3,
-    PCFR_TILE_64x64_K2 = 4, PCFR_TILE_64x128_K2 = 5, PCFR_TILE_64x64_P4 = 6, PCFR_TILE_64x128_P4 = 7
+    PCFR_TILE_64x64_K2 = 4, PCFR_TILE_64x128_K2 = 5, PCFR_TILE_64x64_P4 = 6, PCFR_TILE_64x128_P4 = 7,
+    PCFR_TILE_DIRECT = 8, PCFR_TILE_DIRECT_K2 = 9
 };
 int32_t pcfr_leafnet_set_tiles(pcfr_leafnet* net, const int32_t* tiles, int32_t count);
 int32_t pcfr_leafnet_get_tiles(pcfr_leafnet* net, int32_t* tiles, int32_t count);

@@ -46,7 +46,18 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 //   EPI_BIAS_RELU_BF  C = relu(A B^T + bias)     (bf16 out)
 //   EPI_F32           C = A B^T                  (float out)
 //   EPI_MASK_BF       C = (A B^T) * [mask > 0]   (bf16 out, mask bf16 [M][ldc])
-enum { EPI_BIAS_F32 = 0, EPI_BIAS_RELU_BF = 1, EPI_F32 = 2, EPI_MASK_BF = 3 };
+//   EPI_BIAS_RELU_SWZ C = relu(A B^T + bias)     (bf16 out, in the swizzled layout below)
+enum { EPI_BIAS_F32 = 0, EPI_BIAS_RELU_BF = 1, EPI_F32 = 2, EPI_MASK_BF = 3, EPI_BIAS_RELU_SWZ = 4 };
+
+// Swizzled bf16 layout of an [R][K] matrix (R a multiple of 32, K of 16),
+// for operands read straight into MFMA registers: the 16-byte chunk of row r
+// holding columns [8q, 8q + 8) is chunk (r % 32) + 32 (q % 2) of block
+// (r / 32, q / 2); blocks of 64 chunks are ordered by row block, then column
+// block.  One A or B operand of v_mfma_f32_32x32x16_bf16 (32 rows x 16 K
+// values) is then one block: 1 KB, lane l reading chunk l.
+__host__ __device__ __forceinline__ int64_t swz_index(int64_t r, int64_t k, int64_t K) {
+    return ((((r >> 5) * (K >> 4) + (k >> 4)) * 64) + (r & 31) + 32 * ((k >> 3) & 1)) * 8 + (k & 7);
+}
 
 // Rows of A past M (the last row tile of a 128-row tiling) are read as row
 // M - 1 and their outputs are not stored.
@@ -243,7 +254,8 @@ __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict
 #pragma unroll
         for (int j = 0; j < TN; j++) {
             const int64_t col = n0 + wn * (BN / 2) + j * 32 + l32;
-            const float bv = (EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_RELU_BF) ? bias[col] : 0.f;
+            const float bv =
+                (EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_RELU_BF || EPI == EPI_BIAS_RELU_SWZ) ? bias[col] : 0.f;
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int64_t row = m0 + wm * (BM / 2) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -253,12 +265,116 @@ __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict
                     reinterpret_cast<float*>(Cout)[row * ldc + col] = v;
                 } else if (EPI == EPI_BIAS_RELU_BF) {
                     reinterpret_cast<uint16_t*>(Cout)[row * ldc + col] = f2bf(v > 0.f ? v : 0.f);
+                } else if (EPI == EPI_BIAS_RELU_SWZ) {
+                    reinterpret_cast<uint16_t*>(Cout)[swz_index(row, col, ldc)] = f2bf(v > 0.f ? v : 0.f);
                 } else {
                     const bool on = bf2f(mask[row * ldc + col]) > 0.f;
                     reinterpret_cast<uint16_t*>(Cout)[row * ldc + col] = f2bf(on ? v : 0.f);
                 }
             }
         }
+}
+
+// GEMM with both operands in the swizzled layout and no LDS stage: one wave
+// per 64 x 64 output tile (2 x 2 MFMA tiles of 32 x 32), so every operand
+// block feeds two MFMAs and a wave needs 1 KB of operands per MFMA, half of
+// what a 32 x 32 wave tile needs.  Each operand block is one coalesced 1 KB
+// load straight into registers, prefetched PF k-blocks ahead in a ring of
+// PF + 1 slots; the loads are unconditional (clamped to the last block) so
+// the compiler waits for exactly the slot it needs.  With KSPLIT = 2 two
+// waves take halves of K and add their sums through LDS (wave 0 adds wave
+// 1's).  K = 16 KBT is a compile-time constant; M and N are multiples of 64.
+template <int EPI, int KSPLIT, int PF, int KBT>
+__global__ __launch_bounds__(64 * KSPLIT) void k_gemm_direct(const uint16_t* __restrict__ A,
+                                                            const uint16_t* __restrict__ B, int M,
+                                                            const float* __restrict__ bias, void* __restrict__ Cout,
+                                                            int ldc) {
+    constexpr int D = PF + 1, KB = KBT, per = KBT / KSPLIT;
+    static_assert(KBT % KSPLIT == 0 && per > PF, "k blocks per wave");
+    const int lane = threadIdx.x & 63, grp = KSPLIT == 1 ? 0 : (int)(threadIdx.x >> 6);
+    const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+    const int64_t kb0 = (int64_t)grp * per;
+    const v8bf* a0 = reinterpret_cast<const v8bf*>(A) + ((m0 >> 5) * KB + kb0) * 64 + lane;
+    const v8bf* a1 = a0 + (int64_t)KB * 64;
+    const v8bf* b0 = reinterpret_cast<const v8bf*>(B) + ((n0 >> 5) * KB + kb0) * 64 + lane;
+    const v8bf* b1 = b0 + (int64_t)KB * 64;
+    v8bf ra[D][2], rb[D][2];
+    v16f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[i][j][r] = 0.f;
+#define LD_BLOCKS(slot, kb)                                                                        \
+    do {                                                                                           \
+        const int64_t o = (int64_t)(kb) * 64;                                                      \
+        ra[slot][0] = a0[o];                                                                       \
+        ra[slot][1] = a1[o];                                                                       \
+        rb[slot][0] = b0[o];                                                                       \
+        rb[slot][1] = b1[o];                                                                       \
+    } while (0)
+#pragma unroll
+    for (int q = 0; q < PF; q++) LD_BLOCKS(q, q);
+    // fully unrolled (K is a compile-time constant): straight-line code, so
+    // the compiler waits for exactly the ring slot each step consumes
+#pragma unroll
+    for (int kb = 0; kb < per; kb++) {
+        if (kb + PF < per) LD_BLOCKS((kb + PF) % D, kb + PF);
+        // keep the prefetch where it is: the scheduler would otherwise sink
+        // the loads to their MFMAs and wait for each one
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ra[kb % D][i], rb[kb % D][j], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#undef LD_BLOCKS
+    if constexpr (KSPLIT > 1) {
+        __shared__ float xr[4 * 16 * 64];
+        if (grp == 1) {
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+#pragma unroll
+                    for (int r = 0; r < 16; r++) xr[((i * 2 + j) * 16 + r) * 64 + lane] = acc[i][j][r];
+        }
+        __syncthreads();
+        if (grp != 0) return;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) acc[i][j][r] += xr[((i * 2 + j) * 16 + r) * 64 + lane];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int64_t col = n0 + j * 32 + (lane & 31);
+            const float bv = bias[col];
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int64_t row = m0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row >= M) continue;
+                const float v = acc[i][j][r] + bv;
+                if (EPI == EPI_BIAS_F32) reinterpret_cast<float*>(Cout)[row * ldc + col] = v;
+                else reinterpret_cast<uint16_t*>(Cout)[swz_index(row, col, ldc)] = f2bf(v > 0.f ? v : 0.f);
+            }
+        }
+}
+
+// Row-major bf16 [R][K] -> the swizzled layout, one 16-byte chunk per thread.
+__global__ void k_swizzle_bf16(const uint16_t* __restrict__ in, int64_t R, int64_t K, uint16_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q8 = K >> 3;
+    if (i >= R * q8) return;
+    const int64_t r = i / q8, k = (i - r * q8) * 8;
+    *reinterpret_cast<u32x4*>(out + swz_index(r, k, K)) = *reinterpret_cast<const u32x4*>(in + r * K + k);
 }
 
 // bf16 transpose: out[c][r] = in[r][c], both dims multiples of 64.
@@ -389,8 +505,42 @@ static int64_t r64(int64_t x) { return (x + 63) / 64 * 64; }
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool gemm_tile_valid(int tile, int64_t N) {
-    static const int bn[kGemmTiles] = {64, 64, 128, 128, 64, 128, 64, 128};
+    static const int bn[kGemmTiles] = {64, 64, 128, 128, 64, 128, 64, 128, 64, 64};
     return tile >= 0 && tile < kGemmTiles && N % bn[tile] == 0;
+}
+
+constexpr int kDirectPF = 7;    // prefetch distance of the DIRECT tiles, in k-blocks of 16
+constexpr int kDirectKB = 96;   // their input width in k-blocks (1536, the hidden width)
+
+bool gemm_tile_valid_layer(int tile, int l, int64_t N, int64_t K) {
+    if (!gemm_tile_valid(tile, N)) return false;
+    if (!gemm_tile_direct(tile)) return true;
+    return l > 0 && K == 16 * kDirectKB;
+}
+
+// C = A B^T with both operands swizzled (M, N multiples of 64); out_swz: the
+// bf16 ReLU output swizzled for the next layer, else the FP32 output row-major.
+static int32_t launch_gemm_direct(hipStream_t st, int tile, const uint16_t* A, const uint16_t* B, int64_t M,
+                                  int64_t N, int64_t K, const float* bias, void* C, int ldc, bool relu_swz) {
+    if (K != 16 * kDirectKB) { set_error("direct tiles need an input width of 1536"); return PCFR_E_INVALID_ARG; }
+    const dim3 grid((unsigned)(N / 64), (unsigned)(M / 64));
+    const int ks = tile == GEMM_DIRECT_K2 ? 2 : 1;
+    if (relu_swz) {
+        if (ks == 1)
+            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_RELU_SWZ, 1, kDirectPF, kDirectKB>), grid, dim3(64), 0, st, A,
+                               B, (int)M, bias, C, ldc);
+        else
+            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_RELU_SWZ, 2, kDirectPF, kDirectKB>), grid, dim3(128), 0, st,
+                               A, B, (int)M, bias, C, ldc);
+    } else {
+        if (ks == 1)
+            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_F32, 1, kDirectPF, kDirectKB>), grid, dim3(64), 0, st, A, B,
+                               (int)M, bias, C, ldc);
+        else
+            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_F32, 2, kDirectPF, kDirectKB>), grid, dim3(128), 0, st, A, B,
+                               (int)M, bias, C, ldc);
+    }
+    return hipchk(hipGetLastError(), "direct gemm launch");
 }
 
 int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M,
@@ -413,6 +563,7 @@ int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const u
         case EPI_BIAS_F32: LN_GEMM(BMv, BNv, EPI_BIAS_F32, KSv, PFv); break;             \
         case EPI_BIAS_RELU_BF: LN_GEMM(BMv, BNv, EPI_BIAS_RELU_BF, KSv, PFv); break;     \
         case EPI_F32: LN_GEMM(BMv, BNv, EPI_F32, KSv, PFv); break;                       \
+        case EPI_BIAS_RELU_SWZ: LN_GEMM(BMv, BNv, EPI_BIAS_RELU_SWZ, KSv, PFv); break;   \
         default: LN_GEMM(BMv, BNv, EPI_MASK_BF, KSv, PFv); break;                        \
     }
     switch (tile) {
@@ -423,7 +574,8 @@ int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const u
         case GEMM_64x64_K2: LN_EPI(64, 64, 2, 2); break;
         case GEMM_64x128_K2: LN_EPI(64, 128, 2, 2); break;
         case GEMM_64x64_P4: LN_EPI(64, 64, 1, 4); break;
-        default: LN_EPI(64, 128, 1, 4); break;
+        case GEMM_64x128_P4: LN_EPI(64, 128, 1, 4); break;
+        default: set_error("direct tiles are launched through launch_gemm_direct"); return PCFR_E_INVALID_ARG;
     }
 #undef LN_EPI
 #undef LN_GEMM
@@ -464,6 +616,7 @@ void LeafNetPlan::make(int d_in_, int width_, int depth_, int d_out_, int max_ba
     auto take = [&](size_t b) { size_t at = s; s = a256(s + b); return at; };
     off_p = take(4 * n_padded);
     off_pb = take(2 * n_padded);
+    off_pbs = take(2 * n_padded);
     off_g = take(4 * n_padded);
     off_m = take(4 * n_padded);
     off_v = take(4 * n_padded);
@@ -481,6 +634,8 @@ void LeafNetPlan::make(int d_in_, int width_, int depth_, int d_out_, int max_ba
     off_cnt = take(16);
     total = s;
 }
+
+static int32_t swizzle_weights(pcfr_leafnet* n, hipStream_t st);   // below, with the forward
 
 }  // namespace pcfr
 
@@ -567,6 +722,7 @@ int32_t pcfr_leafnet_set_params(pcfr_leafnet* n, const float* host) {
                        reinterpret_cast<float*>(n->ws + P.off_p), reinterpret_cast<uint16_t*>(n->ws + P.off_pb),
                        P.n_padded);
     LN_CHK(hipGetLastError());
+    if (int32_t rc = swizzle_weights(n, n->stream)) return rc;
     LN_CHK(hipMemsetAsync(n->ws + P.off_m, 0, 4 * P.n_padded, n->stream));
     LN_CHK(hipMemsetAsync(n->ws + P.off_v, 0, 4 * P.n_padded, n->stream));
     n->adam_t = 0;
@@ -604,27 +760,61 @@ namespace pcfr {
 
 // Forward over the rows already staged in the bf16 input buffer; M = padded rows.
 // Forward layer l on the first M rows of the staged activations.
-static int32_t forward_layer(pcfr_leafnet* n, int l, int64_t M, hipStream_t st, int tile) {
-    const LeafNetPlan& P = n->P;
-    const uint16_t* in = reinterpret_cast<const uint16_t*>(n->ws + (l == 0 ? P.off_x : P.off_h[l]));
-    const uint16_t* W = reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l];
-    const float* b = reinterpret_cast<const float*>(n->ws + P.off_p) + P.boff[l];
-    if (l + 1 < P.L)
-        return launch_gemm(st, EPI_BIAS_RELU_BF, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1],
-                           P.pdims[l], b, n->ws + P.off_h[l + 1], (int)P.pdims[l + 1], nullptr, tile);
-    return launch_gemm(st, EPI_BIAS_F32, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1], P.pdims[l], b,
-                       n->ws + P.off_y, (int)P.pdims[l + 1], nullptr, tile);
+// The tile layer l runs with: its chosen tile, or the default where direct
+// tiles are not allowed.
+static int layer_tile(const pcfr_leafnet* n, int l, bool allow_direct) {
+    const int t = l < (int)n->fwd_tile.size() ? n->fwd_tile[l] : -1;
+    return (gemm_tile_direct(t) && !allow_direct) ? -1 : t;
 }
 
-int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st, LaunchTimer* tm) {
+// Layer l with `tile`; its input is swizzled when the tile is direct, its
+// hidden output swizzled when the next layer's tile (next_tile) is direct.
+static int32_t forward_layer(pcfr_leafnet* n, int l, int64_t M, hipStream_t st, int tile, int next_tile) {
+    const LeafNetPlan& P = n->P;
+    const uint16_t* in = reinterpret_cast<const uint16_t*>(n->ws + (l == 0 ? P.off_x : P.off_h[l]));
+    const float* b = reinterpret_cast<const float*>(n->ws + P.off_p) + P.boff[l];
+    const bool hidden = l + 1 < P.L;
+    void* out = hidden ? (void*)(n->ws + P.off_h[l + 1]) : (void*)(n->ws + P.off_y);
+    if (gemm_tile_direct(tile)) {
+        if (!gemm_tile_valid_layer(tile, l, P.pdims[l + 1], P.pdims[l]) || M % 64) {
+            set_error("direct tile not valid for this layer");
+            return PCFR_E_INVALID_ARG;
+        }
+        const uint16_t* Ws = reinterpret_cast<const uint16_t*>(n->ws + P.off_pbs) + P.woff[l];
+        if (hidden && !gemm_tile_direct(next_tile)) {
+            set_error("a direct layer's output feeds a direct layer only");
+            return PCFR_E_INVALID_ARG;
+        }
+        return launch_gemm_direct(st, tile, in, Ws, M, P.pdims[l + 1], P.pdims[l], b, out, (int)P.pdims[l + 1], hidden);
+    }
+    const uint16_t* W = reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l];
+    const int epi = !hidden ? EPI_BIAS_F32 : gemm_tile_direct(next_tile) ? EPI_BIAS_RELU_SWZ : EPI_BIAS_RELU_BF;
+    return launch_gemm(st, epi, in, (int)P.pdims[l], W, (int)P.pdims[l], M, P.pdims[l + 1], P.pdims[l], b, out,
+                       (int)P.pdims[l + 1], nullptr, tile);
+}
+
+int32_t leafnet_forward_staged(pcfr_leafnet* n, int64_t M, hipStream_t st, LaunchTimer* tm, bool allow_direct) {
     const LeafNetPlan& P = n->P;
     for (int l = 0; l < P.L; l++) {
         if (tm) tm->before(l + 1 < P.L ? 5 : 6);
-        const int32_t rc = forward_layer(n, l, M, st, l < (int)n->fwd_tile.size() ? n->fwd_tile[l] : -1);
+        const int32_t rc = forward_layer(n, l, M, st, layer_tile(n, l, allow_direct),
+                                         l + 1 < P.L ? layer_tile(n, l + 1, allow_direct) : -1);
         if (tm) tm->after();
         if (rc) return rc;
     }
     return PCFR_OK;
+}
+
+// Swizzled copies of the bf16 weights, for the direct tiles.
+static int32_t swizzle_weights(pcfr_leafnet* n, hipStream_t st) {
+    const LeafNetPlan& P = n->P;
+    for (int l = 0; l < P.L; l++) {
+        const int64_t R = P.pdims[l + 1], K = P.pdims[l], chunks = R * K / 8;
+        hipLaunchKernelGGL(k_swizzle_bf16, dim3((unsigned)((chunks + 255) / 256)), dim3(256), 0, st,
+                           reinterpret_cast<const uint16_t*>(n->ws + P.off_pb) + P.woff[l], R, K,
+                           reinterpret_cast<uint16_t*>(n->ws + P.off_pbs) + P.woff[l]);
+    }
+    return hipchk(hipGetLastError(), "weight swizzle");
 }
 
 // Average ms of `reps` back-to-back runs of fn() on the net's stream.
@@ -659,16 +849,38 @@ int32_t leafnet_autotune(pcfr_leafnet* n, int64_t M, int reps, double* ms_before
     hipStream_t st = n->stream;
     int32_t rc = time_ms(st, reps, ms_before, [&] { return leafnet_forward_staged(n, M, st); });
     if (rc) return rc;
+    // Layers are timed one at a time (their inputs' contents do not matter
+    // for timing).  Direct tiles need the layers after them direct too (a
+    // direct layer writes swizzled output), so they are chosen as a suffix:
+    // the best first layer of the suffix is decided by comparing, for every
+    // split, the LDS-staged prefix plus the direct suffix.
     std::vector<int> pick(P.L, -1);
+    std::vector<double> best_std(P.L, 1e30), best_dir(P.L, 1e30);
+    std::vector<int> tile_std(P.L, -1), tile_dir(P.L, -1);
     for (int l = 0; l < P.L; l++) {
-        double best = 1e30;
         for (int tile = 0; tile < kGemmTiles; tile++) {
-            if (!gemm_tile_valid(tile, P.pdims[l + 1])) continue;
+            if (!gemm_tile_valid_layer(tile, l, P.pdims[l + 1], P.pdims[l])) continue;
+            const bool dir = gemm_tile_direct(tile);
             double ms = 0;
-            if ((rc = time_ms(st, reps, &ms, [&] { return forward_layer(n, l, M, st, tile); }))) return rc;
-            if (ms < best) { best = ms; pick[l] = tile; }
+            if ((rc = time_ms(st, reps, &ms, [&] { return forward_layer(n, l, M, st, tile, dir ? tile : -1); })))
+                return rc;
+            if (dir && ms < best_dir[l]) { best_dir[l] = ms; tile_dir[l] = tile; }
+            if (!dir && ms < best_std[l]) { best_std[l] = ms; tile_std[l] = tile; }
         }
     }
+    int split = P.L;   // layers [split, L) run direct
+    double best_total = 1e30;
+    for (int sp = 1; sp <= P.L; sp++) {
+        double t = 0;
+        bool ok = true;
+        for (int l = 0; l < P.L; l++) {
+            const double v = l < sp ? best_std[l] : best_dir[l];
+            if (!(v < 1e29)) { ok = false; break; }
+            t += v;
+        }
+        if (ok && t < best_total) { best_total = t; split = sp; }
+    }
+    for (int l = 0; l < P.L; l++) pick[l] = l < split ? tile_std[l] : tile_dir[l];
     n->fwd_tile = pick;
     return time_ms(st, reps, ms_after, [&] { return leafnet_forward_staged(n, M, st); });
 }
@@ -681,11 +893,16 @@ int32_t pcfr_leafnet_set_tiles(pcfr_leafnet* n, const int32_t* tiles, int32_t co
     if (!n || !tiles) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
     const LeafNetPlan& P = n->P;
     if (count != P.L) { set_error("one tile per layer is needed"); return PCFR_E_INVALID_ARG; }
-    for (int l = 0; l < P.L; l++)
-        if (tiles[l] != -1 && !gemm_tile_valid(tiles[l], P.pdims[l + 1])) {
-            set_error("tile does not divide the layer's output width");
+    for (int l = 0; l < P.L; l++) {
+        if (tiles[l] != -1 && !gemm_tile_valid_layer(tiles[l], l, P.pdims[l + 1], P.pdims[l])) {
+            set_error("tile does not divide the layer's output width, or a direct tile on the first layer");
             return PCFR_E_INVALID_ARG;
         }
+        if (l + 1 < P.L && gemm_tile_direct(tiles[l]) && !gemm_tile_direct(tiles[l + 1])) {
+            set_error("a direct tile must be followed by direct tiles");
+            return PCFR_E_INVALID_ARG;
+        }
+    }
     n->fwd_tile.assign(tiles, tiles + count);
     return PCFR_OK;
 }
@@ -737,7 +954,7 @@ int32_t pcfr_leafnet_train_step(pcfr_leafnet* n, const float* x, const float* ta
                            P.dims[0], reinterpret_cast<uint16_t*>(n->ws + P.off_x), (int)P.pdims[0], M);
         LN_CHK(hipGetLastError());
     }
-    int32_t rc = leafnet_forward_staged(n, M, st);
+    int32_t rc = leafnet_forward_staged(n, M, st, nullptr, false);
     if (rc) return rc;
     const int64_t ny = (int64_t)m * P.dims[P.L];
     float* inv_n = reinterpret_cast<float*>(n->ws + P.off_cnt);
@@ -787,6 +1004,7 @@ int32_t pcfr_leafnet_train_step(pcfr_leafnet* n, const float* x, const float* ta
                        reinterpret_cast<float*>(n->ws + P.off_v), reinterpret_cast<uint16_t*>(n->ws + P.off_pb),
                        reinterpret_cast<const uint8_t*>(n->ws + P.off_live), P.n_padded, lr, b1, b2, eps, c1, c2);
     LN_CHK(hipGetLastError());
+    if ((rc = swizzle_weights(n, st))) return rc;
     if (loss) {
         std::vector<double> hp(nblk);
         float iv = 1.f;

@@ -59,18 +59,28 @@ def test_forward_matches_fp64_reference(d_in, width, depth, d_out, m):
     close(y, ref, "forward")
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_forward_each_gemm_tile_matches_fp64_reference(tile):
     """Every forward GEMM tile, on a row count (1029 -> 1088) that leaves the
     last 128-row tile half empty, against the bf16-emulating FP64 reference."""
     import torch
-    say(f"case: forward with GEMM tile {tile} on every layer, m=1029")
+    # direct tiles read their input in the layout the layer before writes, so
+    # never on the first layer; they also serve the output layer
+    say(f"case: forward with GEMM tile {tile} on every layer it fits, m=1029")
     rng = np.random.default_rng(77)
     net = P.LeafNet(P.LEAF_D_IN, 1536, 2, P.LEAF_D_OUT, max_batch=1029)
     params = rand_params(rng, net.layer_shapes(), scale=1.5)
     net.set_params(params)
-    net.tiles = [tile] * len(net.layer_shapes())
-    assert net.tiles == [tile] * len(net.layer_shapes())
+    L = len(net.layer_shapes())
+    tiles = [0] + [tile] * (L - 1) if tile >= 8 else [tile] * L
+    net.tiles = tiles
+    assert net.tiles == tiles
+    if tile >= 8:
+        with pytest.raises(P.PcfrError):
+            net.tiles = [tile] * L                   # not on the first layer
+        with pytest.raises(P.PcfrError):
+            net.tiles = [0, tile] + [0] * (L - 2)    # a direct layer feeds direct layers only
+        assert net.tiles == tiles
     x = rng.standard_normal((1029, P.LEAF_D_IN)).astype(np.float32)
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     close(y, mlp.forward(params, x, emulate_bf16=True), f"forward tile {tile}")
@@ -84,7 +94,7 @@ def test_forward_after_autotune():
     net.set_params(params)
     before, after = net.autotune(1029, 3)
     say(f"case: GEMM tile autotune m=1029: {before:.4f} -> {after:.4f} ms per forward, tiles {net.tiles}")
-    assert before > 0 and after > 0 and all(t in range(8) for t in net.tiles)
+    assert before > 0 and after > 0 and all(t in range(10) for t in net.tiles)
     x = rng.standard_normal((1029, P.LEAF_D_IN)).astype(np.float32)
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     close(y, mlp.forward(params, x, emulate_bf16=True), "forward after autotune")
