@@ -677,29 +677,41 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
 
-    // card-list offsets, lists (2 * Hb + 52 entries <= QN) and the permutation
-    copy_i16<((kSdHeader + 2 * kMaxHp + kSdHeader) / 8 + kBlock - 1) / kBlock>(coff, tb + 7 * Hp, kSdHeader + QN);
+    // Every global load first, none through the permutation: the card-list
+    // offsets and lists (2 * Hb + 52 entries <= QN), the permutation, this
+    // thread's table entries and the cards of its sorted hands, and both
+    // reach rows in hand order (coalesced).  The reach rows are staged in q0 /
+    // q1, which the card-list prefixes overwrite only after the permuted
+    // gather below has read them from LDS.
+    copy_i16<((kSdHeader + 2 * kMaxHp + kSdHeader) / 8 + kBlock - 1) / kBlock>(coff, tb + 8 * Hp, kSdHeader + QN);
     copy_i16<(kMaxHp / 8 + kBlock - 1) / kBlock>(perm, tb, Hp);
-    // this thread's hands in the output stage: table entries and cards
+    const uint16_t* scard = reinterpret_cast<const uint16_t*>(tb + 7 * Hp);
     int s_gl[kHandIt], s_gh[kHandIt], s_al[kHandIt], s_ah[kHandIt], s_bl[kHandIt], s_bh[kHandIt];
+    uint32_t cc[kHandIt];
+    T ra[kHandIt], rb[kHandIt];
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int s = tid + i * kBlock;
         if (s < Hb) {
             s_gl[i] = glo[s]; s_gh[i] = ghi[s]; s_al[i] = alo[s];
             s_ah[i] = ahi[s]; s_bl[i] = blo[s]; s_bh[i] = bhi[s];
+            cc[i] = scard[s];
         }
+        if (s < Hp) { ra[i] = r0[s]; rb[i] = r1[s]; }
+    }
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = tid + i * kBlock;
+        if (h < Hp) { q0[h] = ra[i]; q1[h] = rb[i]; }
     }
     __syncthreads();
     int hh[kHandIt];
-    uint32_t cc[kHandIt];
     T a[kHandIt], b[kHandIt];
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int s = tid + i * kBlock;
         hh[i] = s < Hp ? perm[s] : 0;
-        if (s < Hb) { a[i] = r0[hh[i]]; b[i] = r1[hh[i]]; }
-        if (s < Hb) cc[i] = hc[hh[i]];
+        if (s < Hb) { a[i] = q0[hh[i]]; b[i] = q1[hh[i]]; }
     }
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
@@ -1421,7 +1433,7 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
         }
         P.coff[(size_t)g * 53 + 52] = pos;
     }
-    P.sd_stride = (7 * Hp + kSdHeader + 2 * Hp + kSdHeader + 63) / 64 * 64;
+    P.sd_stride = (8 * Hp + kSdHeader + 2 * Hp + kSdHeader + 63) / 64 * 64;
     std::map<std::pair<int32_t, uint64_t>, int32_t> board_id;
     int64_t N = 0;
     P.node_base.assign(K, 0);
@@ -1578,9 +1590,14 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
         const int Hb = (int)alive.size();
         P.sdn[kv.second] = Hb;
         int16_t *perm = tb, *glo = tb + Hp, *ghi = tb + 2 * Hp, *alo = tb + 3 * Hp, *ahi = tb + 4 * Hp,
-                *blo = tb + 5 * Hp, *bhi = tb + 6 * Hp, *coff = tb + 7 * Hp, *clist = coff + kSdHeader;
+                *blo = tb + 5 * Hp, *bhi = tb + 6 * Hp, *scard = tb + 7 * Hp, *coff = tb + 8 * Hp,
+                *clist = coff + kSdHeader;
         int s = 0;
-        for (auto& x : alive) perm[s++] = (int16_t)x.second;
+        for (auto& x : alive) {
+            const int k = hcmb[x.second];
+            scard[s] = (int16_t)(uint16_t)(cc.hi[k] | (cc.lo[k] << 8));
+            perm[s++] = (int16_t)x.second;
+        }
         for (int64_t h = 0; h < Hp; h++) if (!is_alive[h]) perm[s++] = (int16_t)h;
         for (int i = 0; i < Hb;) {
             int j = i;
