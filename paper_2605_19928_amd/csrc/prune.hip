@@ -27,6 +27,7 @@ struct PruneNode {
 };
 
 constexpr int kPruneBlock = 256;
+static_assert(kMaxActions < 31, "one mask bit per action plus the examined bit");
 
 // For a hand h of the actor's range not blocked by the node's board, action
 // a is dominated when hi[a][h] < max over b != a of lo[b][h]: the largest

@@ -2269,6 +2269,10 @@ static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t wh
     int64_t gn = s->P.node_base[g] + node;
     int Pi = 0;
     while (!s->iso.skip.empty() && s->iso.skip[gn]) {
+        if (s->iso.corr[gn] < 0 || s->iso.cperm[gn] < 0) {
+            set_error("internal: a node skipped by suit isomorphism has no representative");
+            return PCFR_E_STATE;
+        }
         Pi = suit_perm_compose(Pi, s->iso.cperm[gn]);
         gn = s->iso.corr[gn];
     }
