@@ -3,8 +3,10 @@
 // result).
 //
 // A suit permutation pi (card 4 r + s -> 4 r + pi(s)) that maps the root
-// board onto itself and leaves both root ranges unchanged (r_p(pi h) =
-// r_p(h) for every combo h, compared exactly) maps the subgame onto itself:
+// board onto itself, leaves both root ranges unchanged (r_p(pi h) = r_p(h)
+// for every combo h, compared exactly) and maps the tree onto itself (always
+// true for a built tree; checked, for trees pruned unevenly) maps the
+// subgame onto itself:
 // every iterate of CFR is then invariant under pi.  Below a chance node
 // whose dealt cards pi also fixes, the child dealt card pi(c) is the image
 // of the child dealt c, and its values are v(h | pi c) = v(pi^-1 h | c).
@@ -52,6 +54,40 @@ static uint64_t map_mask(const std::array<int8_t, 4>& pi, uint64_t m) {
     return out;
 }
 
+// True when the suit permutation pi maps the tree onto itself: every node and
+// its image have the same type, player, action count and contributions,
+// actions correspond in order and the chance child dealt c corresponds to the
+// one dealt pi(c).  A built tree always is (betting does not depend on the
+// cards); a tree pruned unevenly across chance children may not be, and then
+// pi is no symmetry of the game.
+static bool tree_invariant(const Tree& t, const std::array<int8_t, 4>& pi) {
+    if (t.nodes.empty()) return true;
+    std::vector<std::pair<int32_t, int32_t>> stack{{0, 0}};
+    int card_child[52];
+    while (!stack.empty()) {
+        const auto [x, y] = stack.back();
+        stack.pop_back();
+        const Node& a = t.nodes[x];
+        const Node& b = t.nodes[y];
+        if (a.type != b.type || a.player != b.player || a.n_child != b.n_child || a.contrib[0] != b.contrib[0] ||
+            a.contrib[1] != b.contrib[1])
+            return false;
+        if (a.type == PCFR_NODE_CHANCE) {
+            std::fill(card_child, card_child + 52, -1);
+            for (int e = 0; e < b.n_child; e++) card_child[t.nodes[b.first_child + e].chance_card] = b.first_child + e;
+            for (int e = 0; e < a.n_child; e++) {
+                const int ya = a.first_child + e;
+                const int yb = card_child[map_card(pi, t.nodes[ya].chance_card)];
+                if (yb < 0) return false;
+                stack.push_back({ya, yb});
+            }
+        } else {
+            for (int e = 0; e < a.n_child; e++) stack.push_back({a.first_child + e, b.first_child + e});
+        }
+    }
+    return true;
+}
+
 int32_t suit_iso_map(const std::vector<const Tree*>& trees, const double* ranges, IsoMap& out) {
     const ComboTable& cc = combos();
     const auto& perms = suit_perms();
@@ -79,6 +115,7 @@ int32_t suit_iso_map(const std::vector<const Tree*>& trees, const double* ranges
                 const int pk = combo_of(map_card(pi, cc.hi[k]), map_card(pi, cc.lo[k]));
                 ok = r[pk] == r[k] && r[kCombos + pk] == r[kCombos + k];
             }
+            if (ok && q != 0 && !tree_invariant(t, pi)) ok = false;
             if (ok) grp |= 1u << q;
         }
         out.group[g] = grp;
@@ -117,34 +154,47 @@ int32_t suit_iso_map(const std::vector<const Tree*>& trees, const double* ranges
                     if (b < 0) continue;   // cannot happen for a group fixing the board
                     const int64_t cb = base[g] + nd.first_child + b;
                     if (done[b]) continue;
+                    // node-by-node correspondence of the two subtrees (actions in
+                    // the same order, chance children by permuted card); a
+                    // subtree of another shape (a tree pruned unevenly) is not
+                    // the image and stays swept on its own
+                    std::vector<std::pair<int32_t, int32_t>> pairs, stack{{(int32_t)(ca - base[g]), (int32_t)(cb - base[g])}};
+                    bool same = true;
+                    while (!stack.empty() && same) {
+                        const auto [xa, xb] = stack.back();
+                        stack.pop_back();
+                        pairs.push_back({xa, xb});
+                        const Node& na = t.nodes[xa];
+                        const Node& nb = t.nodes[xb];
+                        if (na.type != nb.type || na.n_child != nb.n_child || na.player != nb.player ||
+                            na.contrib[0] != nb.contrib[0] || na.contrib[1] != nb.contrib[1]) {
+                            same = false;
+                            break;
+                        }
+                        if (na.type == PCFR_NODE_CHANCE) {
+                            int bychild[52];
+                            std::fill(bychild, bychild + 52, -1);
+                            for (int e = 0; e < nb.n_child; e++) bychild[t.nodes[nb.first_child + e].chance_card] = nb.first_child + e;
+                            for (int e = 0; e < na.n_child && same; e++) {
+                                const int ya = na.first_child + e;
+                                const int yb = bychild[map_card(perms[q], t.nodes[ya].chance_card)];
+                                if (yb < 0) same = false;
+                                else stack.push_back({ya, yb});
+                            }
+                        } else {
+                            for (int e = 0; e < na.n_child; e++)
+                                stack.push_back({na.first_child + e, nb.first_child + e});
+                        }
+                    }
+                    if (!same) continue;
                     done[b] = 1;
                     out.src[cb] = ca;
                     out.perm[cb] = (int8_t)q;
                     out.skip[cb] = 1;
                     out.mapped[gi] = 1;
-                    // node-by-node correspondence of the two subtrees: actions
-                    // in the same order, chance children by permuted card
-                    std::vector<std::pair<int32_t, int32_t>> stack{{(int32_t)(ca - base[g]), (int32_t)(cb - base[g])}};
-                    while (!stack.empty()) {
-                        const auto [xa, xb] = stack.back();
-                        stack.pop_back();
+                    for (const auto& [xa, xb] : pairs) {
                         out.corr[base[g] + xb] = (int32_t)(base[g] + xa);
                         out.cperm[base[g] + xb] = (int8_t)q;
-                        const Node& na = t.nodes[xa];
-                        const Node& nb = t.nodes[xb];
-                        if (na.type == PCFR_NODE_CHANCE) {
-                            int bychild[52];
-                            std::fill(bychild, bychild + 52, -1);
-                            for (int e = 0; e < nb.n_child; e++) bychild[t.nodes[nb.first_child + e].chance_card] = nb.first_child + e;
-                            for (int e = 0; e < na.n_child; e++) {
-                                const int ya = na.first_child + e;
-                                const int yb = bychild[map_card(perms[q], t.nodes[ya].chance_card)];
-                                if (yb >= 0) stack.push_back({ya, yb});
-                            }
-                        } else {
-                            for (int e = 0; e < na.n_child && e < nb.n_child; e++)
-                                stack.push_back({na.first_child + e, nb.first_child + e});
-                        }
                     }
                 }
             }

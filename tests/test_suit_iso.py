@@ -135,3 +135,62 @@ def test_symmetric_range_is_invariant():
         idx = np.array([combo(mapc(p, int(a)), mapc(p, int(b))) for a, b in cc])
         assert np.array_equal(r[idx], r)
     assert abs(r.sum() - 1.0) < 1e-12 and (r[I.blocked_mask(board)] == 0).all()
+
+
+def _subtree_shape(e, root, perm):
+    """Node-by-node shape of a subtree: types, action counts, players and
+    contributions in action order, chance children keyed by their card (mapped
+    through the suit permutation `perm`, identity when None)."""
+    out = []
+    stack = [root]
+    while stack:
+        v = stack.pop()
+        out.append((int(e["type"][v]), int(e["n_child"][v]), int(e["player"][v]),
+                    int(e["contrib"][v][0]), int(e["contrib"][v][1])))
+        kids = list(range(int(e["first_child"][v]), int(e["first_child"][v]) + int(e["n_child"][v])))
+        if e["type"][v] == P.NODE_CHANCE:
+            key = (lambda c: mapc(perm, c)) if perm is not None else (lambda c: c)
+            kids = sorted(kids, key=lambda x: key(int(e["chance_card"][x])))
+        stack.extend(reversed(kids))
+    return out
+
+
+def test_unevenly_pruned_tree_maps_only_identical_subtrees():
+    """A tree pruned in one chance child's subtree only: the suit permutations
+    moving that child no longer map the game onto itself and leave the group;
+    the child is paired with no other; every pair the map makes has identical
+    subtrees."""
+    board = [50, 46, 26, 10]
+    spec = dict(board=board, pot=100, stacks=(150, 150), sizes=[50], allin=True, max_raises=2, depth_limit=0)
+    rng = np.random.default_rng(4)
+    r = np.stack([I.symmetric_range(rng, board, support=40), I.symmetric_range(rng, board, support=40)])
+    t = P.Tree(**spec)
+    m0 = t.suit_iso_map(r)
+    e = t.export()
+    # a mapped chance child, and the first decision with two or more actions in its subtree
+    mapped = np.flatnonzero((m0["perm"] >= 0))
+    assert len(mapped) > 0
+    child = int(mapped[0])
+    partner = int(m0["src"][child])
+    node = child
+    while not (e["type"][node] == P.NODE_DECISION and e["n_child"][node] >= 2):
+        node = int(e["first_child"][node])
+    flags = np.zeros(t.n_nodes, dtype=np.uint8)
+    flags[int(e["first_child"][node]) + int(e["n_child"][node]) - 1] = 1
+    tp, new = t.prune(flags)
+    m = tp.suit_iso_map(r)
+    f = tp.export()
+    c, pa = int(new[child]), int(new[partner])
+    assert m["src"][c] == c and m["perm"][c] < 0          # no longer read through its partner
+    assert all(m["src"][x] != c for x in range(tp.n_nodes) if x != c)
+    for x in np.flatnonzero(m["perm"] >= 0):
+        s = int(m["src"][x])
+        assert _subtree_shape(f, x, None) == _subtree_shape(f, s, PERMS[int(m["perm"][x])])
+    # the symmetry group shrinks to the permutations that map the pruned tree
+    # onto itself, and what survives still maps some children
+    assert m["group"] != m0["group"] and (m["group"] & ~m0["group"]) == 0
+    for q in range(24):
+        if m["group"] >> q & 1:
+            assert _subtree_shape(f, 0, PERMS[q]) == _subtree_shape(f, 0, None)
+    assert (m["perm"] >= 0).sum() > 0
+    assert pa >= 0
