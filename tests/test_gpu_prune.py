@@ -158,3 +158,46 @@ def test_node_values_consistent():
         worst = max(worst, float(np.abs(mix - V[n, p])[valid].max()), float(np.abs(tot - V[n, 1 - p])[valid].max()))
     say(f"  decision-node consistency max |d| = {worst:.3e} chips")
     assert worst <= 1e-9 * spec["pot"]
+
+
+def test_pruned_depth_limited_flop_matches_oracle():
+    """Pruning a depth-limited flop tree (leaves valued by exact check-down
+    equity): the reduced tree keeps its leaves' layout, and the GPU's solve of
+    it matches the oracle's solve of its own reduced tree."""
+    spec, r = I.flop_config(5, support=24)
+    T = 30
+    say(f"case: pruned depth-limited flop, board={spec['board']} T={T}")
+    rng = np.random.default_rng(9)
+    gt, ot = P.Tree(**spec), O.Tree.holdem(**spec)
+    lo, hi = synthetic_bounds(rng, gt.export(), spread=20.0, width=10.0)
+    fg = gt.prune_dominated(r, _dev(lo), _dev(hi))
+    np.testing.assert_array_equal(fg, ot.prune_dominated(r, lo, hi))
+    gr, _ = gt.prune(fg)
+    orr, _ = ot.prune(fg)
+    say(f"  nodes {gt.n_nodes} -> {gr.n_nodes}, leaves {gt.n_leaf} -> {gr.n_leaf}")
+    assert gr.n_nodes < gt.n_nodes and gr.n_leaf + gr.n_allin > 0
+    gs = P.Solver(gr, r, P.SolverConfig(dtype="f64"))
+    gs.iterate(T)
+    os_ = O.Solver(orr, r, support_only=True)
+    os_.iterate(T)
+    pot = spec["pot"]
+    mask = (r > 0) & ~I.blocked_mask(spec["board"])[None, :]
+    for which in ("current", "avg"):
+        d = np.abs(gs.root_cfv(which) - os_.root_cfv(which))[mask].max() / pot
+        say(f"  root cfv ({which}) max |d| = {d:.3e} pot")
+        assert d <= 1e-9
+
+
+def test_node_values_of_batch_subgames():
+    """Node values of each subgame of a batch: the root rows are that
+    subgame's root values under the average strategies."""
+    cases = [I.river_config(5, support=100), I.river_config(6, support=100)]
+    trees = [P.Tree(**s) for s, _ in cases]
+    b = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype="f64"))
+    b.iterate(20)
+    for sub in range(2):
+        V = b.node_values(sub).cpu().numpy()
+        assert V.shape == (trees[sub].n_nodes, 2, P.NCOMBO)
+        d = np.abs(V[0] - b.root_cfv_of(sub, "avg")).max()
+        say(f"  subgame {sub}: root rows vs root values max |d| = {d:.3e}")
+        assert d <= 1e-12 * cases[sub][0]["pot"]
