@@ -276,8 +276,12 @@ int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes);
  * so one graph replay advances every subgame by one iteration.  The handle is
  * a pcfr_solver; the single-subgame calls act on subgame 0, the batch calls
  * take a subgame index.  ranges: host [n][2][1326].  Depth-limited trees
- * cannot be batched (PCFR_E_UNSUPPORTED).  Results are bitwise identical to
- * solving each subgame alone. */
+ * batch too (their leaves are evaluated together: one equity table per
+ * subgame, and with a leaf network one input row per leaf and next card of
+ * every subgame in the same GEMMs); the subgames holding depth-limit leaves
+ * must have boards of one size, else PCFR_E_UNSUPPORTED.  Results are bitwise
+ * identical to solving each subgame alone (with a network, when its layers
+ * use the same GEMM tiles in both). */
 int32_t pcfr_batch_workspace_bytes(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg,
                                    size_t* bytes);
 int32_t pcfr_batch_create(const pcfr_tree* const* trees, int32_t n, const pcfr_solver_cfg* cfg,

@@ -812,20 +812,24 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
 // Exact leaf values from pairwise check-down equity (all-in leaves, and every
 // leaf when no network is attached): v_i(h) = c * sum_o E(h,o) r_{-i}(o).
 // Et is stored transposed, [o][h], so consecutive threads read consecutive h.
-// The sum over o is split into kEqSplit slices, each slice of J leaves one
-// workgroup with the slice of their reach vectors in LDS; a second kernel adds
-// the slices in a fixed order (deterministic) and applies the contribution.
+// The sum over o is split into kEqSplit slices, each slice of a group of up
+// to J leaves of one subgame (so one table, [n_sub][Hp][Hp]) one workgroup
+// with the slice of their reach vectors in LDS; a second kernel adds the
+// slices in a fixed order (deterministic) and applies the contribution.
 constexpr int kEqSplit = 32;
 
 template <typename T, int J>
 __global__ __launch_bounds__(kBlock) void k_equity_partial(const DNode* __restrict__ nodes,
                                                            const int32_t* __restrict__ leaves, int n_leaves, int Hp,
+                                                           const int4* __restrict__ groups,
                                                            const T* __restrict__ Et, const T* __restrict__ reach,
                                                            T* __restrict__ part) {
     constexpr int kChunk = (kMaxHp + kEqSplit - 1) / kEqSplit;
     __shared__ T rr[J][2][kChunk];
-    const int j0 = blockIdx.y * J;
-    const int nj = min(J, n_leaves - j0);
+    const int4 gr = groups[blockIdx.y];    // first leaf, count (<= J), subgame
+    const int j0 = gr.x;
+    const int nj = gr.y;
+    Et += (int64_t)gr.z * Hp * Hp;
     const int chunk = (Hp + kEqSplit - 1) / kEqSplit;
     const int o0 = blockIdx.z * chunk, o1 = min(Hp, o0 + chunk);
     for (int i = threadIdx.x; i < nj * 2 * chunk; i += kBlock) {
@@ -936,7 +940,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_leaf_ranges(const DNode* __restrict__ nodes,
                                                         const int32_t* __restrict__ leaves, int Hp,
                                                         const T* __restrict__ reach,
-                                                        const int16_t* __restrict__ combo_hand,
+                                                        const int16_t* __restrict__ combo_hand /* [n_sub][1326] */,
                                                         T* __restrict__ Rc, double* __restrict__ sinv,
                                                         T* __restrict__ agg) {
     constexpr int RI = (2 * kComboPad + kBlock - 1) / kBlock;
@@ -947,6 +951,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_ranges(const DNode* __restrict_
     const DNode nd = nodes[leaves[li]];
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    combo_hand += (int64_t)nd.sub * kCombos;
     // every load of the thread first: its hands' reach and its combos' hands
     T a[kHandIt], b[kHandIt];
     int hk[RI];
@@ -1003,10 +1008,14 @@ constexpr int kLeafXBlock = 384;
 template <typename T>
 __global__ __launch_bounds__(kLeafXBlock) void k_leaf_x(const T* __restrict__ Rc, const double* __restrict__ sinv,
                                                         const float* __restrict__ spr, int n_next,
-                                                        const int8_t* __restrict__ next_cards, int4 board, int ldx,
+                                                        const int32_t* __restrict__ leaf_sub,
+                                                        const int8_t* __restrict__ next_cards /* [n_sub][64] */,
+                                                        const int4* __restrict__ boards /* [n_sub] */, int ldx,
                                                         uint16_t* __restrict__ X) {
     const int row = blockIdx.x, leaf = row / n_next, ci = row - leaf * n_next;
-    const int c = next_cards[ci];
+    const int sub = leaf_sub[leaf];
+    const int c = next_cards[sub * 64 + ci];
+    const int4 board = boards[sub];
     const int col0 = threadIdx.x * 8;
     if (col0 >= ldx) return;
     const T* rc = Rc + (int64_t)leaf * 2 * kComboPad;
@@ -1057,7 +1066,8 @@ __global__ __launch_bounds__(kLeafXBlock) void k_leaf_x(const T* __restrict__ Rc
 // e = sum_h r0 M1 EV0 + sum_h r1 M0 EV1 and z = sum_h r0 M1 (= sum_h r1 M0),
 // which the combine subtracts from both players' EVs of that row.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_zerosum(int n_next, const int8_t* __restrict__ next_cards,
+__global__ __launch_bounds__(kBlock) void k_leaf_zerosum(int n_next, const int32_t* __restrict__ leaf_sub,
+                                                         const int8_t* __restrict__ next_cards /* [n_sub][64] */,
                                                          const T* __restrict__ Rc, const T* __restrict__ agg,
                                                          const float* __restrict__ Y, int ldy, T* __restrict__ delta) {
     constexpr int CI = (kCombos + kBlock - 1) / kBlock;
@@ -1065,7 +1075,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_zerosum(int n_next, const int8_
     __shared__ T ag[kAgg];
     __shared__ T xch[2 * kWaves];
     const int row = blockIdx.x, li = row / n_next, kc = row - li * n_next;
-    const int c = next_cards[kc];
+    const int c = next_cards[leaf_sub[li] * 64 + kc];
     const int tid = threadIdx.x;
     // every global load first: the leaf's combo-indexed ranges, aggregates and this row's outputs
     const T* rc = Rc + (int64_t)li * 2 * kComboPad;
@@ -1122,13 +1132,12 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict__ nodes,
                                                          const int32_t* __restrict__ leaves,
                                                          const double* __restrict__ pot_over_k, int n_next,
-                                                         const int8_t* __restrict__ next_cards, int Hp, int H,
+                                                         const int8_t* __restrict__ next_cards /* [n_sub][64] */,
+                                                         int Hp, int H,
                                                          const T* __restrict__ reach, T* __restrict__ cfv,
-                                                         const uint16_t* __restrict__ hcards,
-                                                         const int16_t* __restrict__ hand_combo,
-                                                         const int16_t* __restrict__ combo_hand,
-                                                         const int32_t* __restrict__ coff,
-                                                         const int16_t* __restrict__ chands,
+                                                         const uint16_t* __restrict__ hcards /* [n_sub][Hp] */,
+                                                         const int16_t* __restrict__ hand_combo /* [n_sub][Hp] */,
+                                                         const int16_t* __restrict__ combo_hand /* [n_sub][1326] */,
                                                          const float* __restrict__ Y, int ldy,
                                                          const T* __restrict__ agg, const T* __restrict__ delta) {
     __shared__ T x[2][kMaxHp];
@@ -1142,6 +1151,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
     const DNode nd = nodes[n];
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    hcards += (int64_t)nd.sub * Hp;
+    hand_combo += (int64_t)nd.sub * Hp;
+    combo_hand += (int64_t)nd.sub * kCombos;
+    next_cards += nd.sub * 64;
     const int tid = threadIdx.x;
     {
         T a[kHandIt], b[kHandIt];
@@ -1341,9 +1354,11 @@ struct Plan {
     size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_zs, off_agg, off_rc, off_sinv, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
+        off_eqgrp, off_nsub, off_b4,
         off_cmap, off_hmap, total;
     size_t lds_bytes, lds_fold, lds_show;
-    int4 board4;                          // root board cards, -1 past the last
+    int64_t n_grp = 0, n_grp_allin = 0;   // equity groups: all leaves, the all-in prefix
+    int64_t H_leaf = 0;                   // hands of the subgames holding depth-limit leaves
 };
 
 struct Prepared {
@@ -1371,13 +1386,19 @@ struct Prepared {
     std::vector<uint64_t> root_mask;
     int64_t Hp = 0, H = 0, sd_stride = 0;  // H: hands of subgame 0
     int32_t levels = 0, max_a = 0;
-    // depth-limit leaves (single subgame only): all-in leaves first, then
+    // depth-limit leaves of every subgame: all-in leaves first, then
     // network leaves (so the all-in prefix is what stays exact when a
-    // network is attached)
+    // network is attached); subgames holding leaves share one board size
     std::vector<int32_t> eq_leaves;
+    std::vector<int32_t> eq_sub;           // per leaf: its subgame
     std::vector<double> eq_pay;
     int64_t n_allin = 0;
+    int leaf_board = -1;                   // board size of the subgames with leaves
+    int64_t leaf_H = 0;                    // their hands
     std::vector<int32_t> net_leaves;
+    std::vector<int32_t> net_sub;          // per network leaf: its subgame
+    std::vector<int32_t> board4s;          // [n_sub][4] root boards, -1 past the last card
+    std::vector<int8_t> next_all;          // [n_sub][64] cards that can come next, -1 past the last
     std::vector<float> net_spr;
     std::vector<double> net_potk;
     std::vector<int8_t> next_cards;
@@ -1447,6 +1468,12 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
     }
     P.nodes.resize(N);
     std::vector<std::vector<int32_t>> per_level(P.levels);
+    // subgames with depth-limit leaves must share their board size, so that
+    // every leaf has the same number of network rows and hands
+    int leaf_board = -1;
+    for (int32_t g = 0; g < K && leaf_board < 0; g++)
+        if (trees[g]->count[PCFR_NODE_LEAF] + trees[g]->count[PCFR_NODE_ALLIN_LEAF] > 0)
+            leaf_board = __builtin_popcountll(trees[g]->root_mask);
     int64_t rows = 0;
     for (int32_t g = 0; g < K; g++) {
         const Tree& t = *trees[g];
@@ -1487,7 +1514,10 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
                     P.term.push_back((int32_t)gi);
                 }
             } else if (s.type == PCFR_NODE_ALLIN_LEAF || s.type == PCFR_NODE_LEAF) {
-                if (K > 1) { set_error("depth-limited subgames cannot be batched"); return PCFR_E_UNSUPPORTED; }
+                if (__builtin_popcountll(t.root_mask) != leaf_board) {
+                    set_error("batched depth-limited subgames must have boards of one size");
+                    return PCFR_E_UNSUPPORTED;
+                }
                 if (s.contrib[0] != s.contrib[1]) { set_error("leaf with unequal contributions"); return PCFR_E_INVALID_ARG; }
                 if (s.board_mask != t.root_mask) { set_error("depth-limit leaf below a chance node"); return PCFR_E_UNSUPPORTED; }
             } else {
@@ -1518,28 +1548,50 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
         }
     }
     if (N > (int64_t)INT32_MAX) { set_error("too many nodes"); return PCFR_E_TOO_LARGE; }
-    if (K == 1) {
-        const Tree& t = *trees[0];
-        const int64_t eff = std::min(t.spec.stack[0], t.spec.stack[1]);
-        const int64_t cap = t.spec.pot / 2 + eff;
-        for (int pass = 0; pass < 2; pass++)
+    // depth-limit leaves of every subgame: all-in leaves first (exact
+    // equity), then the others (the network's, or exact equity without one)
+    P.n_allin = 0;
+    P.leaf_board = leaf_board;
+    P.leaf_H = 0;
+    for (int32_t g = 0; g < K; g++)
+        if (__builtin_popcountll(P.root_mask[g]) == leaf_board) { P.leaf_H = P.Hs[g]; break; }
+    for (int pass = 0; pass < 2; pass++)
+        for (int32_t g = 0; g < K; g++) {
+            const Tree& t = *trees[g];
+            const int64_t eff = std::min(t.spec.stack[0], t.spec.stack[1]);
+            const int64_t cap = t.spec.pot / 2 + eff;
             for (size_t i = 0; i < t.nodes.size(); i++) {
                 const Node& s = t.nodes[i];
                 if (s.type != (pass == 0 ? PCFR_NODE_ALLIN_LEAF : PCFR_NODE_LEAF)) continue;
-                P.eq_leaves.push_back((int32_t)i);
+                P.eq_leaves.push_back((int32_t)(P.node_base[g] + (int64_t)i));
+                P.eq_sub.push_back(g);
                 P.eq_pay.push_back((double)s.contrib[0]);
+                if (pass == 0) P.n_allin++;
                 if (pass == 1) {
                     const int nb = __builtin_popcountll(s.board_mask);
-                    P.net_leaves.push_back((int32_t)i);
+                    P.net_leaves.push_back((int32_t)(P.node_base[g] + (int64_t)i));
+                    P.net_sub.push_back(g);
                     P.net_spr.push_back((float)((double)(cap - s.contrib[0]) / (double)(2 * s.contrib[0])));
                     P.net_potk.push_back((double)(2 * s.contrib[0]) / (double)(52 - nb - 4));
                 }
             }
-        P.n_allin = (int64_t)t.count[PCFR_NODE_ALLIN_LEAF];
-    }
-    for (int c = 0; c < 52; c++) {
-        if (P.root_mask[0] >> c & 1ull) P.board.push_back(c);
-        else P.next_cards.push_back((int8_t)c);
+        }
+    // per subgame: the root board (up to 4 cards, -1 past the last) and the
+    // cards that can come next (one table row of 64 per subgame)
+    P.board4s.assign((size_t)K * 4, -1);
+    P.next_all.assign((size_t)K * 64, -1);
+    for (int32_t g = 0; g < K; g++) {
+        int nb = 0, nn = 0;
+        for (int c = 0; c < 52; c++) {
+            if (P.root_mask[g] >> c & 1ull) {
+                if (nb < 4) P.board4s[(size_t)g * 4 + nb] = c;
+                nb++;
+                if (g == 0) P.board.push_back(c);
+            } else {
+                P.next_all[(size_t)g * 64 + nn++] = (int8_t)c;
+                if (g == 0) P.next_cards.push_back((int8_t)c);
+            }
+        }
     }
     P.fwd_off.assign(P.levels + 1, 0);
     P.dec_off.assign(P.levels + 1, 0);
@@ -1641,6 +1693,24 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
     return PCFR_OK;
 }
 
+// Workgroup groups of the equity kernel: runs of up to J consecutive leaves of
+// one subgame, never across the end of the all-in prefix; {first, count,
+// subgame, 0} each.  n_allin_groups: the groups of the all-in prefix.
+static void equity_groups(const Prepared& P, int J, std::vector<int32_t>& out, int64_t& n_allin_groups) {
+    out.clear();
+    n_allin_groups = 0;
+    const int64_t n = (int64_t)P.eq_leaves.size();
+    for (int64_t i = 0; i < n;) {
+        int64_t j = i + 1;
+        while (j < n && j - i < J && P.eq_sub[j] == P.eq_sub[i] && j != P.n_allin) j++;
+        out.insert(out.end(), {(int32_t)i, (int32_t)(j - i), P.eq_sub[i], 0});
+        if (j <= P.n_allin) n_allin_groups++;
+        i = j;
+    }
+}
+
+static int equity_group_width(size_t esz) { return esz == 8 ? 2 : 4; }
+
 static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, bool iso, Plan& L) {
     L.N = (int64_t)P.nodes.size();
     L.rows = rows;
@@ -1677,12 +1747,17 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.n_eq = (int64_t)P.eq_leaves.size();
     L.n_net = (int64_t)P.net_leaves.size();
     {
-        int b4[4] = {-1, -1, -1, -1};
-        for (size_t i = 0; i < P.board.size() && i < 4; i++) b4[i] = P.board[i];
-        L.board4 = make_int4(b4[0], b4[1], b4[2], b4[3]);
+        std::vector<int32_t> grp;
+        equity_groups(P, equity_group_width(L.esz), grp, L.n_grp_allin);
+        L.n_grp = (int64_t)grp.size() / 4;
     }
-    L.n_next = (int64_t)P.next_cards.size();
-    L.off_et = take(L.n_eq ? L.esz * L.Hp * L.Hp : 0);
+    L.H_leaf = P.leaf_H;
+    L.n_next = P.leaf_board >= 0 ? 52 - P.leaf_board : (int64_t)P.next_cards.size();
+    // one pairwise equity table per subgame, [n_sub][Hp][Hp], when any subgame has leaves
+    L.off_et = take(L.n_eq ? L.esz * L.Hp * L.Hp * P.n_sub : 0);
+    L.off_eqgrp = take(sizeof(int32_t) * 4 * std::max<int64_t>(L.n_grp, 1));
+    L.off_nsub = take(sizeof(int32_t) * std::max<int64_t>(L.n_net, 1));
+    L.off_b4 = take(sizeof(int32_t) * 4 * P.n_sub);
     L.off_eq = take(sizeof(int32_t) * std::max<int64_t>(L.n_eq, 1));
     L.off_eqpay = take(sizeof(double) * std::max<int64_t>(L.n_eq, 1));
     L.off_net = take(sizeof(int32_t) * std::max<int64_t>(L.n_net, 1));
@@ -1695,9 +1770,9 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     // suit isomorphism: per node (source child, permutation); per subgame and permutation, the hand map
     L.off_cmap = take(iso ? sizeof(int32_t) * 2 * L.N : 0);
     L.off_hmap = take(iso ? sizeof(int16_t) * 24 * L.Hp * P.n_sub : 0);
-    L.off_next = take(64);
-    L.off_c2h = take(sizeof(int16_t) * kCombos);
-    L.off_h2c = take(sizeof(int16_t) * L.Hp);
+    L.off_next = take(64 * (size_t)P.n_sub);
+    L.off_c2h = take(sizeof(int16_t) * kCombos * P.n_sub);
+    L.off_h2c = take(sizeof(int16_t) * L.Hp * P.n_sub);
     L.off_roots = take(sizeof(int32_t) * P.n_sub);
     L.off_M = take(variant == PCFR_PCFRPLUS ? L.esz * L.rows * L.Hp : 0);
     L.off_samp = take(align256(sizeof(float) * 2 * P.n_sub) + align256((size_t)P.n_sub * 52) +
@@ -1855,10 +1930,13 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     const int64_t n_eq_active = s->net ? P.n_allin : L.n_eq;
     if (n_eq_active) {
         constexpr int J = sizeof(T) == 8 ? 2 : 4;
-        dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)((n_eq_active + J - 1) / J), kEqSplit);
+        static_assert(J == (sizeof(T) == 8 ? 2 : 4), "the groups are built for this width");
+        const int64_t n_grp = s->net ? L.n_grp_allin : L.n_grp;
+        dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)n_grp, kEqSplit);
         if (tm) tm->before(4);
         hipLaunchKernelGGL((k_equity_partial<T, J>), grid, dim3(kBlock), 0, side, nodes, s->at<int32_t>(L.off_eq),
-                           (int)n_eq_active, Hp, s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
+                           (int)n_eq_active, Hp, reinterpret_cast<const int4*>(s->at<int32_t>(L.off_eqgrp)),
+                           s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
         const int64_t tot = n_eq_active * 2 * (int64_t)Hp;
         hipLaunchKernelGGL((k_equity_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, side,
                            s->at<int32_t>(L.off_eq), s->at<double>(L.off_eqpay), (int)n_eq_active, Hp,
@@ -1873,15 +1951,17 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->at<int32_t>(L.off_net), Hp, reach, s->at<int16_t>(L.off_c2h), s->at<T>(L.off_rc),
                            s->at<double>(L.off_sinv), s->at<T>(L.off_agg));
         hipLaunchKernelGGL((k_leaf_x<T>), dim3((unsigned)rows), dim3(kLeafXBlock), 0, stream, s->at<T>(L.off_rc),
-                           s->at<double>(L.off_sinv), s->at<float>(L.off_spr), (int)L.n_next, s->at<int8_t>(L.off_next),
-                           L.board4, (int)net->P.pdims[0], reinterpret_cast<uint16_t*>(net->ws + net->P.off_x));
+                           s->at<double>(L.off_sinv), s->at<float>(L.off_spr), (int)L.n_next, s->at<int32_t>(L.off_nsub),
+                           s->at<int8_t>(L.off_next), reinterpret_cast<const int4*>(s->at<int32_t>(L.off_b4)),
+                           (int)net->P.pdims[0], reinterpret_cast<uint16_t*>(net->ws + net->P.off_x));
         if (tm) tm->after();
         int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
         if (rc) return rc;
         if (s->leaf_zero_sum) {
             if (tm) tm->before(4);
             hipLaunchKernelGGL((k_leaf_zerosum<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, (int)L.n_next,
-                               s->at<int8_t>(L.off_next), s->at<T>(L.off_rc), s->at<T>(L.off_agg),
+                               s->at<int32_t>(L.off_nsub), s->at<int8_t>(L.off_next), s->at<T>(L.off_rc),
+                               s->at<T>(L.off_agg),
                                reinterpret_cast<const float*>(net->ws + net->P.off_y), (int)net->P.pdims[net->P.L],
                                s->at<T>(L.off_zs));
             if (tm) tm->after();
@@ -1890,9 +1970,9 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         hipLaunchKernelGGL((k_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)((Hp + 63) / 64)),
                            dim3(kBlock), 0, stream, nodes,
                            s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), (int)L.n_next,
-                           s->at<int8_t>(L.off_next), Hp, (int)L.H, reach, cfv, s->at<uint16_t>(L.off_hc),
-                           s->at<int16_t>(L.off_h2c), s->at<int16_t>(L.off_c2h), s->at<int32_t>(L.off_coff),
-                           s->at<int16_t>(L.off_chands), reinterpret_cast<const float*>(net->ws + net->P.off_y),
+                           s->at<int8_t>(L.off_next), Hp, (int)L.H_leaf, reach, cfv, s->at<uint16_t>(L.off_hc),
+                           s->at<int16_t>(L.off_h2c), s->at<int16_t>(L.off_c2h),
+                           reinterpret_cast<const float*>(net->ws + net->P.off_y),
                            (int)net->P.pdims[net->P.L], s->at<T>(L.off_agg),
                            s->leaf_zero_sum ? s->at<T>(L.off_zs) : nullptr);
         if (tm) tm->after();
@@ -2188,34 +2268,50 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         HIPCHK(hipStreamSynchronize(s->stream));
     }
     {
-        std::vector<int16_t> c2h(kCombos), h2c(L.Hp, -1);
-        for (int k = 0; k < kCombos; k++) c2h[k] = (int16_t)P.combo_hand[0][k];
-        for (int64_t h = 0; h < P.H; h++) h2c[h] = (int16_t)P.hand_combo[0][h];
-        if ((rc = up(L.off_c2h, c2h.data(), sizeof(int16_t) * kCombos))) return rc;
-        if ((rc = up(L.off_h2c, h2c.data(), sizeof(int16_t) * L.Hp))) return rc;
-        if ((rc = up(L.off_next, P.next_cards.data(), P.next_cards.size()))) return rc;
+        // per subgame: combo -> hand, hand -> combo, next cards, root board
+        std::vector<int16_t> c2h((size_t)n * kCombos), h2c((size_t)n * L.Hp, -1);
+        for (int32_t g = 0; g < n; g++) {
+            for (int k = 0; k < kCombos; k++) c2h[(size_t)g * kCombos + k] = (int16_t)P.combo_hand[g][k];
+            for (int64_t h = 0; h < P.Hs[g]; h++) h2c[(size_t)g * L.Hp + h] = (int16_t)P.hand_combo[g][h];
+        }
+        std::vector<int32_t> grp;
+        int64_t n_grp_allin = 0;
+        equity_groups(P, equity_group_width(L.esz), grp, n_grp_allin);
+        if ((rc = up(L.off_c2h, c2h.data(), sizeof(int16_t) * c2h.size()))) return rc;
+        if ((rc = up(L.off_h2c, h2c.data(), sizeof(int16_t) * h2c.size()))) return rc;
+        if ((rc = up(L.off_next, P.next_all.data(), P.next_all.size()))) return rc;
+        if ((rc = up(L.off_b4, P.board4s.data(), sizeof(int32_t) * P.board4s.size()))) return rc;
+        if ((rc = up(L.off_eqgrp, grp.data(), sizeof(int32_t) * grp.size()))) return rc;
+        if ((rc = up(L.off_nsub, P.net_sub.data(), sizeof(int32_t) * P.net_sub.size()))) return rc;
         if ((rc = up(L.off_eq, P.eq_leaves.data(), sizeof(int32_t) * P.eq_leaves.size()))) return rc;
         if ((rc = up(L.off_eqpay, P.eq_pay.data(), sizeof(double) * P.eq_pay.size()))) return rc;
         if ((rc = up(L.off_net, P.net_leaves.data(), sizeof(int32_t) * P.net_leaves.size()))) return rc;
         if ((rc = up(L.off_spr, P.net_spr.data(), sizeof(float) * P.net_spr.size()))) return rc;
         if ((rc = up(L.off_potk, P.net_potk.data(), sizeof(double) * P.net_potk.size()))) return rc;
-        if (L.n_eq) {
+        HIPCHK(hipStreamSynchronize(s->stream));
+        // pairwise equity table of each subgame holding depth-limit leaves
+        std::vector<char> has_leaf(n, 0);
+        for (int32_t g : P.eq_sub) has_leaf[g] = 1;
+        for (int32_t g = 0; g < n && L.n_eq; g++) {
+            if (!has_leaf[g]) continue;
+            const int64_t Hg = P.Hs[g];
             std::vector<double> E;
+            std::vector<char> et;
             try {
-                equity_matrix(P.root_mask[0], P.hand_combo[0], E);
+                equity_matrix(P.root_mask[g], P.hand_combo[g], E);
+                et.assign(L.esz * L.Hp * L.Hp, 0);
             } catch (const std::bad_alloc&) {
                 set_error("out of host memory for the equity table");
                 return PCFR_E_OUT_OF_MEMORY;
             }
-            std::vector<char> et(L.esz * L.Hp * L.Hp, 0);
-            for (int64_t h = 0; h < P.H; h++)
-                for (int64_t o = 0; o < P.H; o++) {
-                    const double v = E[(size_t)h * P.H + o];
+            for (int64_t h = 0; h < Hg; h++)
+                for (int64_t o = 0; o < Hg; o++) {
+                    const double v = E[(size_t)h * Hg + o];
                     const size_t i = (size_t)o * L.Hp + h;   // transposed
                     if (L.esz == 8) reinterpret_cast<double*>(et.data())[i] = v;
                     else reinterpret_cast<float*>(et.data())[i] = (float)v;
                 }
-            if ((rc = up(L.off_et, et.data(), et.size()))) return rc;
+            if ((rc = up(L.off_et + L.esz * L.Hp * L.Hp * (size_t)g, et.data(), et.size()))) return rc;
             HIPCHK(hipStreamSynchronize(s->stream));
         }
     }

@@ -523,7 +523,10 @@ class LeafNet:
     @property
     def tiles(self):
         """Forward GEMM tile per layer (-1 default, 0 64x64, 1 128x64, 2 64x128, 3 128x128,
-        4 64x64 and 5 64x128 with the K loop split between two wave groups)."""
+        4 64x64 and 5 64x128 with the K loop split between two wave groups, 6 64x64 and
+        7 64x128 with a deeper prefetch, 8 and 9 direct tiles reading operands straight
+        into registers, 9 with K split in two; direct tiles only as a suffix of layers
+        after the first)."""
         t = np.zeros(len(self.layer_shapes()), dtype=np.int32)
         _check(lib().pcfr_leafnet_get_tiles(self._h, _p(t), len(t)))
         return [int(v) for v in t]

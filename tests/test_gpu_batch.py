@@ -95,3 +95,81 @@ def test_autotune_with_budget():
     assert b.t == 0
     b.iterate(3)
     assert b.t == 3
+
+
+def depth_limited_cases():
+    """A river (no leaves) first, then two depth-limited flops on different
+    boards: subgame 0 has no leaves and another board size, so every leaf
+    table is read at a subgame index other than 0."""
+    river = I.batch_config(6, count_nodes, n=1, river_share=1.0, lo=10, hi=300)[0]
+    flops = [I.flop_config(s, support=150) for s in (0, 2)]
+    return [river] + flops
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_depth_limited_exact_leaves(dtype):
+    cases = depth_limited_cases()
+    say(f"case: batch of a river and two depth-limited flops, exact leaves, {dtype}")
+    trees = [P.Tree(**s) for s, _ in cases]
+    assert [t.n_leaf > 0 for t in trees] == [False, True, True]
+    b = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=dtype))
+    T = 12
+    b.iterate(T)
+    eb, _ = b.exploitability_all()
+    for g, (spec, r) in enumerate(cases):
+        s = P.Solver(trees[g], r, P.SolverConfig(dtype=dtype))
+        s.iterate(T)
+        np.testing.assert_array_equal(b.root_cfv_of(g, "current"), s.root_cfv("current"))
+        np.testing.assert_array_equal(b.root_cfv_of(g, "avg"), s.root_cfv("avg"))
+        es, _ = s.exploitability()
+        assert es == eb[g]
+        s.close()
+    if dtype == "f64":
+        spec, r = cases[2]
+        ot = O.Tree.holdem(**spec)
+        os_ = O.Solver(ot, r)
+        os_.iterate(T)
+        ok = ~I.blocked_mask(spec["board"])
+        d = np.abs(b.root_cfv_of(2, "current") - os_.root_cfv("current"))[:, ok].max() / spec["pot"]
+        say(f"  member 2 against the oracle: root cfv max |d| = {d:.3e} pot")
+        assert d <= 1e-9
+
+
+def test_batch_depth_limited_network_leaves():
+    """With a leaf network, the batch feeds every subgame's (leaf, next card)
+    rows through one set of GEMMs; on fixed tiles each member must match its
+    own solve bitwise."""
+    cases = depth_limited_cases()
+    trees = [P.Tree(**s) for s, _ in cases]
+    b = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype="f64"))
+    n_leaves, n_next = b.leaf_rows()
+    assert (n_leaves, n_next) == (2 * 21, 49)
+    rng = np.random.default_rng(17)
+    params = None
+
+    def make_net(rows):
+        nonlocal params
+        net = P.LeafNet(P.LEAF_D_IN, 64, 2, P.LEAF_D_OUT, max_batch=rows)
+        if params is None:
+            params = [((rng.standard_normal((o, i)) * 2.0 / np.sqrt(i)).astype(np.float32),
+                       (rng.standard_normal(o) * 0.05).astype(np.float32)) for o, i in net.layer_shapes()]
+        net.set_params(params)
+        net.tiles = [0] * len(params)
+        return net
+
+    netb = make_net(n_leaves * n_next)
+    b.attach_leafnet(netb)
+    say(f"case: batch with a leaf network, {n_leaves} leaves x {n_next} next cards")
+    T = 3
+    b.iterate(T)
+    for g in (1, 2):
+        spec, r = cases[g]
+        s = P.Solver(trees[g], r, P.SolverConfig(dtype="f64"))
+        nl, nn = s.leaf_rows()
+        net = make_net(nl * nn)
+        s.attach_leafnet(net)
+        s.iterate(T)
+        d = np.abs(b.root_cfv_of(g, "current") - s.root_cfv("current")).max()
+        say(f"  member {g}: root cfv max |d| against its own solve = {d:.3e}")
+        np.testing.assert_array_equal(b.root_cfv_of(g, "current"), s.root_cfv("current"))
+        s.close()

@@ -152,3 +152,29 @@ def test_prune_rejects_invalid_flags():
     flags[e["first_child"][n]: e["first_child"][n] + e["n_child"][n]] = 1
     with pytest.raises(P.PcfrError):
         a.prune(flags)
+
+
+def _batch_workspace(trees):
+    cfg = P.SolverConfig().to_c()
+    arr = (ctypes.c_void_p * len(trees))(*[t._h.value for t in trees])
+    nb = ctypes.c_size_t()
+    rc = P.lib().pcfr_batch_workspace_bytes(arr, len(trees), ctypes.byref(cfg), ctypes.byref(nb))
+    return rc, int(nb.value)
+
+
+def test_batch_of_depth_limited_subgames_planned():
+    """Depth-limited subgames batch when every subgame holding leaves has a
+    board of one size (a river without leaves may join); a flop and a
+    depth-limited turn together are refused."""
+    flops = [P.Tree(**I.flop_config(s, support=150)[0]) for s in (0, 2)]
+    river = P.Tree(board=[0, 13, 26, 39, 51], pot=100, stacks=(400, 400), sizes=[75], allin=True, max_raises=1)
+    rc, nb = _batch_workspace([river] + flops)
+    assert rc == P.OK and nb > 0
+    rc1, nb1 = _batch_workspace(flops[:1])
+    assert rc1 == P.OK and nb1 < nb
+    turn = P.Tree(board=[0, 13, 26, 40], pot=100, stacks=(400, 400), sizes=[75], allin=True, max_raises=1,
+                  depth_limit=1)
+    assert turn.n_leaf > 0
+    rc, _ = _batch_workspace([flops[0], turn])
+    assert rc == P.E_UNSUPPORTED
+    assert "one size" in P.lib().pcfr_last_error().decode()
