@@ -569,6 +569,9 @@ def main():
     if args.dtype == "f32" and all(t in by_tile for t in net.tiles[:-1]):
         gemm_traffic = float(np.mean([sum(by_tile[t]) for t in net.tiles[:-1]]))
     expl, _ = solver.exploitability()
+    # the same K-step window five more times (after the exploitability, which
+    # is then that of the timed run): the spread of the measurement
+    repeats = [timed(solver, args.steps, 0) for _ in range(5)]
     log(f"kernel ms/iter {dict(zip(CLASSES, np.round(pms[:7], 4)))} launches {pl[:7].tolist()}")
     result = {
         "metric": "DCFR ms/iter & iters/sec, flop depth-limited subgame; exploitability mbb/hand",
@@ -595,6 +598,9 @@ def main():
         },
         "exploitability_mbb_per_hand": expl * 100.0,
         "exploitability_note": "of the average strategy within the depth-limited game, leaves valued by the network",
+        "repeat_ms_per_step": repeats,
+        "repeat_note": "five more windows of the same K steps after the timed one (median "
+                       f"{float(np.median(repeats)):.4f} ms, spread {100 * (max(repeats) - min(repeats)) / float(np.median(repeats)):.1f}%)",
         "history_visits_per_s": history_visits(tree, spec, r) * 1000.0 / ms,
         "history_visits_note": "per iteration, over every node, hand pairs with mass on both sides that share no "
                                "card with each other or the node's board; the paper reports about 2.0e10/s",
