@@ -29,6 +29,11 @@ ranges, pot, stack and bet abstraction, redrawn until 10-2000 nodes; one
 forest advanced by one graph replay per iteration after the launch-schedule
 autotuner, against the same subgames solved one at a time.
 
+Flop batch (``--workload flop-batch``, and ``flop_batch`` inside the flop
+line): 8 and 32 depth-limited flops of the default abstraction, each with its
+own board and ranges, in one forest with one leaf network (1536 x 4), so
+every iteration sends all their (leaf, next card) rows through the same GEMMs.
+
 Prints one JSON line.  ``--gpus`` above 1 is refused: the solver runs on one
 GPU.
 """
@@ -70,7 +75,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="flop", choices=["flop", "turn", "batch"])
+    ap.add_argument("--workload", default="flop", choices=["flop", "turn", "batch", "flop-batch"])
+    ap.add_argument("--batch-flops", type=int, default=32, help="flops per forest for --workload flop-batch")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--no-secondary", action="store_true", help="skip the turn and batch measurements")
@@ -471,6 +477,50 @@ def spr_sweep(args, steps, warmup, seed=0):
     return out
 
 
+def flop_batch_sweep(args, steps, warmup, sizes=(8, 32)):
+    """B depth-limited flops (the headline abstraction, each with its own
+    board and ranges) in one forest with one leaf network, so each iteration
+    sends B x leaves x next cards rows through the same GEMMs: ms per batched
+    iteration, per flop, and the hidden-layer GEMM rate at that many rows."""
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+
+    out = []
+    for B in sizes:
+        cases = [I.flop_config(args.seed + k) for k in range(B)]
+        trees = [P.Tree(**s) for s, _ in cases]
+        b = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=args.dtype))
+        n_leaves, n_next = b.leaf_rows()
+        rows = n_leaves * n_next
+        net = P.LeafNet(P.LEAF_D_IN, 1536, 4, P.LEAF_D_OUT, max_batch=rows)
+        net.set_params(he_params(net.layer_shapes(), 7))
+        b.attach_leafnet(net)
+        before, after = b.autotune(5)
+        ms = timed(b, steps, warmup)
+        pms, pl = b.profile(args.profile_iters)
+        pms, pl = pms / args.profile_iters, pl // args.profile_iters
+        shapes = net.layer_shapes()
+        hidden_flops = 2.0 * rows * sum(o * i for o, i in shapes[:-1])
+        all_flops = 2.0 * rows * sum(o * i for o, i in shapes)
+        expl, _ = b.exploitability_all()
+        out.append({
+            "workload": f"{B} depth-limited flops (seeds {args.seed}..{args.seed + B - 1}) in one forest, "
+                        f"leaf network 1536x4",
+            "subgames": B, "nodes_total": int(sum(t.n_nodes for t in trees)), "network_rows": rows,
+            "ms_per_iter": ms, "ms_per_flop_iter": ms / B, "flop_iters_per_s": 1000.0 * B / ms,
+            "autotune_ms_per_iter_before_after": [before, after], "leaf_gemm_tiles": net.tiles,
+            "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
+            "leaf_gemm_hidden_tflops": hidden_flops / (pms[5] * 1e-3) / 1e12,
+            "leaf_gemm_all_layers_tflops": all_flops / ((pms[5] + pms[6]) * 1e-3) / 1e12,
+            "exploitability_mbb_per_hand_mean": float(np.mean(expl)) * 100.0,
+        })
+        log(f"{B} flops batched: {ms:.4f} ms/iter ({ms / B:.4f} ms per flop), {rows} network rows, hidden GEMM "
+            f"{out[-1]['leaf_gemm_hidden_tflops']:.0f} TFLOP/s")
+        b.close()
+        net.close()
+    return out
+
+
 def gemm_shape_point(args, m=2048, reps=50):
     """The leaf network's forward at m rows (the second GEMM shape point),
     after the tile autotuner: us per forward and TFLOP/s."""
@@ -519,6 +569,19 @@ def main():
             "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
             "config": {k: v for k, v in out.items() if k not in ("roofline", "kernel_ms_per_iter")},
             "roofline": out["roofline"],
+        }
+        print(json.dumps(result), flush=True)
+        return
+
+    if args.workload == "flop-batch":
+        out = flop_batch_sweep(args, args.steps, args.warmup, sizes=(args.batch_flops,))[0]
+        result = {
+            "metric": "DCFR ms/iter & iters/sec, flop depth-limited subgame; exploitability mbb/hand",
+            "value": out["flop_iters_per_s"], "unit": "flop iters/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": out["ms_per_iter"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+            "config": {k: v for k, v in out.items() if k != "kernel_ms_per_iter"},
+            "kernel_ms_per_iter": out["kernel_ms_per_iter"],
         }
         print(json.dumps(result), flush=True)
         return
@@ -633,6 +696,7 @@ def main():
         result["pruning"] = [pruning_sweep(args, tspec, tr, max(20, args.steps // 4), 5, eps=e) for e in (0.0, 0.05)]
         result["turn_spr_sweep"] = spr_sweep(args, max(20, args.steps // 4), 5)
         result["leaf_gemm_m2048"] = gemm_shape_point(args)
+        result["flop_batch"] = flop_batch_sweep(args, max(20, args.steps // 4), 5)
         result["hbm_copy_ceiling_gbs"] = copy_ceiling_gbs()
         log(f"HBM copy ceiling: {result['hbm_copy_ceiling_gbs']:.0f} GB/s")
     if not args.no_cpu_baseline:

@@ -1358,6 +1358,7 @@ struct Plan {
         off_cmap, off_hmap, total;
     size_t lds_bytes, lds_fold, lds_show;
     int64_t n_grp = 0, n_grp_allin = 0;   // equity groups: all leaves, the all-in prefix
+    int eq_J = 0;                         // leaves per equity group at most
     int64_t H_leaf = 0;                   // hands of the subgames holding depth-limit leaves
 };
 
@@ -1709,7 +1710,13 @@ static void equity_groups(const Prepared& P, int J, std::vector<int32_t>& out, i
     }
 }
 
-static int equity_group_width(size_t esz) { return esz == 8 ? 2 : 4; }
+// One subgame: narrow groups keep many workgroups in flight (its table stays
+// in cache across them).  Several: wide groups, so each subgame's table is
+// streamed from HBM about once per iteration rather than once per few leaves.
+static int equity_group_width(size_t esz, int32_t n_sub) {
+    if (n_sub > 1) return esz == 8 ? 8 : 16;
+    return esz == 8 ? 2 : 4;
+}
 
 static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, bool iso, Plan& L) {
     L.N = (int64_t)P.nodes.size();
@@ -1748,7 +1755,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.n_net = (int64_t)P.net_leaves.size();
     {
         std::vector<int32_t> grp;
-        equity_groups(P, equity_group_width(L.esz), grp, L.n_grp_allin);
+        L.eq_J = equity_group_width(L.esz, P.n_sub);
+        equity_groups(P, L.eq_J, grp, L.n_grp_allin);
         L.n_grp = (int64_t)grp.size() / 4;
     }
     L.H_leaf = P.leaf_H;
@@ -1929,14 +1937,22 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     // without a network), the network for the others
     const int64_t n_eq_active = s->net ? P.n_allin : L.n_eq;
     if (n_eq_active) {
-        constexpr int J = sizeof(T) == 8 ? 2 : 4;
-        static_assert(J == (sizeof(T) == 8 ? 2 : 4), "the groups are built for this width");
         const int64_t n_grp = s->net ? L.n_grp_allin : L.n_grp;
         dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)n_grp, kEqSplit);
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_equity_partial<T, J>), grid, dim3(kBlock), 0, side, nodes, s->at<int32_t>(L.off_eq),
-                           (int)n_eq_active, Hp, reinterpret_cast<const int4*>(s->at<int32_t>(L.off_eqgrp)),
-                           s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
+        // the kernel's width must be the one the groups were built for
+        constexpr int J1 = sizeof(T) == 8 ? 2 : 4, J2 = sizeof(T) == 8 ? 8 : 16;
+        const int4* grp = reinterpret_cast<const int4*>(s->at<int32_t>(L.off_eqgrp));
+        if (L.eq_J == J1)
+            hipLaunchKernelGGL((k_equity_partial<T, J1>), grid, dim3(kBlock), 0, side, nodes, s->at<int32_t>(L.off_eq),
+                               (int)n_eq_active, Hp, grp, s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
+        else if (L.eq_J == J2)
+            hipLaunchKernelGGL((k_equity_partial<T, J2>), grid, dim3(kBlock), 0, side, nodes, s->at<int32_t>(L.off_eq),
+                               (int)n_eq_active, Hp, grp, s->at<T>(L.off_et), reach, s->at<T>(L.off_eqpart));
+        else {
+            set_error("equity group width does not match a kernel");
+            return PCFR_E_STATE;
+        }
         const int64_t tot = n_eq_active * 2 * (int64_t)Hp;
         hipLaunchKernelGGL((k_equity_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, side,
                            s->at<int32_t>(L.off_eq), s->at<double>(L.off_eqpay), (int)n_eq_active, Hp,
@@ -2276,7 +2292,7 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         }
         std::vector<int32_t> grp;
         int64_t n_grp_allin = 0;
-        equity_groups(P, equity_group_width(L.esz), grp, n_grp_allin);
+        equity_groups(P, L.eq_J, grp, n_grp_allin);
         if ((rc = up(L.off_c2h, c2h.data(), sizeof(int16_t) * c2h.size()))) return rc;
         if ((rc = up(L.off_h2c, h2c.data(), sizeof(int16_t) * h2c.size()))) return rc;
         if ((rc = up(L.off_next, P.next_all.data(), P.next_all.size()))) return rc;
