@@ -412,7 +412,8 @@ int32_t pcfr_solver_set_leaf_zero_sum(pcfr_solver* s, int32_t on);
  * under the average strategies.  Synchronises. */
 int32_t pcfr_batch_leaf_samples(pcfr_solver* s, float* x, int32_t ldx, float* y, float* mask, int32_t ldy);
 
-/* Network leaves and next cards per leaf (rows = product). */
+/* Network leaves and next cards per leaf (rows = product); for a batch, the
+ * leaves of every subgame (the network's max_batch must hold all rows). */
 int32_t pcfr_leaf_rows(pcfr_solver* s, int32_t* n_leaves, int32_t* n_next);
 
 #ifdef __cplusplus
