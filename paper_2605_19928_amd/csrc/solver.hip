@@ -924,30 +924,41 @@ __device__ __forceinline__ void stage_leaf(const T* __restrict__ r0, const T* __
 
 // Per-leaf reach aggregates shared by the zero-sum and combine kernels:
 // agg[leaf] = [2][53], each player's 52 per-card sums (reach of the hands
-// holding the card) then the total; written by k_leaf_ranges.
+// holding the card) then the total; written by k_leaf_input (group 0).
 constexpr int kAgg = 106;
 
 // Stage 2's batched leaf input (Sec. 4.2) for Stage 5's network (Sec. 4.3):
 // one row per (leaf, next card c): each player's reach with the hands
 // holding c removed, normalised to sum 1, over the 1326 combos; then the
 // board after c as 52 one-hot entries; then the stack-to-pot ratio at the
-// leaf; bf16, zero padded to ldx.  k_leaf_ranges works once per leaf: dense
-// combo-indexed ranges, the aggregates, and per card c the reciprocal of
-// S_p(c), the reach of the hands without c (zero when nothing is left);
-// k_leaf_x then writes the rows.
+// leaf; bf16, zero padded to ldx.
+//
+// One workgroup per (leaf, group of next cards).  Each rebuilds the leaf's
+// dense combo-indexed ranges in LDS, the per-card sums C_p(c) and, per card,
+// the reciprocal of S_p(c) = total - C_p(c), the reach of the hands without c
+// (zero when nothing is left) -- the same sums in the same order in every
+// group -- then writes its cards' rows, 8 consecutive columns per step (one
+// 16-byte store).  Normalised entries are formed in double and rounded once
+// to float, as r / S would be.  Group 0 also stores the ranges (Rc) and the
+// aggregates (agg) read by the zero-sum and combine kernels.
 constexpr int kComboPad = 1344;           // 1326 combos padded to 64
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_ranges(const DNode* __restrict__ nodes,
-                                                        const int32_t* __restrict__ leaves, int Hp,
-                                                        const T* __restrict__ reach,
-                                                        const int16_t* __restrict__ combo_hand /* [n_sub][1326] */,
-                                                        T* __restrict__ Rc, double* __restrict__ sinv,
-                                                        T* __restrict__ agg) {
+__global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__ nodes,
+                                                       const int32_t* __restrict__ leaves, int Hp,
+                                                       const T* __restrict__ reach,
+                                                       const int16_t* __restrict__ combo_hand /* [n_sub][1326] */,
+                                                       T* __restrict__ Rc, T* __restrict__ agg,
+                                                       const float* __restrict__ spr, int n_next, int cards_per_group,
+                                                       const int8_t* __restrict__ next_cards /* [n_sub][64] */,
+                                                       const int4* __restrict__ boards /* [n_sub] */, int ldx,
+                                                       uint16_t* __restrict__ X) {
     constexpr int RI = (2 * kComboPad + kBlock - 1) / kBlock;
     __shared__ T x[2][kMaxHp];
     __shared__ double xc[2][kComboPad];
+    __shared__ double sv[2][52];
     __shared__ double dxch[2 * kWaves];
     const int li = blockIdx.x, tid = threadIdx.x;
+    const bool lead = blockIdx.y == 0;
     const DNode nd = nodes[leaves[li]];
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
@@ -972,7 +983,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_ranges(const DNode* __restrict_
         if (h < Hp) { x[0][h] = a[i]; x[1][h] = b[i]; }
     }
     __syncthreads();
-    // dense combo-indexed ranges (to memory for the products, to LDS for the sums)
+    // dense combo-indexed ranges (to LDS for the rows and sums, and from
+    // group 0 to memory for the zero-sum and combine kernels)
     T* rc = Rc + (int64_t)li * 2 * kComboPad;
     double t0 = 0.0, t1 = 0.0;
 #pragma unroll
@@ -981,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_ranges(const DNode* __restrict_
         if (k < 2 * kComboPad) {
             const int p = k >= kComboPad, kk = k - p * kComboPad;
             const T v = hk[i] >= 0 ? x[p][hk[i]] : T(0);
-            rc[k] = v;
+            if (lead) rc[k] = v;
             xc[p][kk] = (double)v;
             if (p) t1 += (double)v; else t0 += (double)v;
         }
@@ -993,69 +1005,51 @@ __global__ __launch_bounds__(kBlock) void k_leaf_ranges(const DNode* __restrict_
         double cs = 0.0;
 #pragma unroll
         for (int xi = 0; xi < 51; xi++) cs += xc[p][combo_index(c, xi < c ? xi : xi + 1)];
-        agg[(int64_t)li * kAgg + p * 53 + c] = (T)cs;
+        if (lead) agg[(int64_t)li * kAgg + p * 53 + c] = (T)cs;
         // a remainder below 1e-9 of the total is rounding of an empty set
         const double tot = p ? t1 : t0, rest = tot - cs;
-        sinv[((int64_t)li * 2 + p) * 52 + c] = rest > 1e-9 * tot ? 1.0 / rest : 0.0;
+        sv[p][c] = rest > 1e-9 * tot ? 1.0 / rest : 0.0;
     }
-    if (tid == 0) { agg[(int64_t)li * kAgg + 52] = (T)t0; agg[(int64_t)li * kAgg + 105] = (T)t1; }
-}
-
-// One input row per workgroup, 8 consecutive columns per thread (one
-// 16-byte store).  Normalised entries are formed in double and rounded
-// once to float, as r / S would be.
-constexpr int kLeafXBlock = 384;
-template <typename T>
-__global__ __launch_bounds__(kLeafXBlock) void k_leaf_x(const T* __restrict__ Rc, const double* __restrict__ sinv,
-                                                        const float* __restrict__ spr, int n_next,
-                                                        const int32_t* __restrict__ leaf_sub,
-                                                        const int8_t* __restrict__ next_cards /* [n_sub][64] */,
-                                                        const int4* __restrict__ boards /* [n_sub] */, int ldx,
-                                                        uint16_t* __restrict__ X) {
-    const int row = blockIdx.x, leaf = row / n_next, ci = row - leaf * n_next;
-    const int sub = leaf_sub[leaf];
-    const int c = next_cards[sub * 64 + ci];
-    const int4 board = boards[sub];
-    const int col0 = threadIdx.x * 8;
-    if (col0 >= ldx) return;
-    const T* rc = Rc + (int64_t)leaf * 2 * kComboPad;
-    const double s0 = sinv[(int64_t)leaf * 104 + c], s1 = sinv[(int64_t)leaf * 104 + 52 + c];
-    const float ratio = spr[leaf];
-    // every range load first (the eight entries, clamped into the leaf's rows)
-    T rv[8];
+    if (lead && tid == 0) { agg[(int64_t)li * kAgg + 52] = (T)t0; agg[(int64_t)li * kAgg + 105] = (T)t1; }
+    __syncthreads();
+    const int4 board = boards[nd.sub];
+    const float ratio = spr[li];
+    const int8_t* nc = next_cards + nd.sub * 64;
+    const int k0 = blockIdx.y * cards_per_group, k1 = min(n_next, k0 + cards_per_group);
+    const int chunks = ldx / 8;
+    for (int it = tid; it < (k1 - k0) * chunks; it += kBlock) {
+        const int q = it / chunks, ci = k0 + q, col0 = (it - q * chunks) * 8;
+        const int c = nc[ci];
+        const double s0 = sv[0][c], s1 = sv[1][c];
+        // cards (a > b) of the combo in column col0 of its player's block
+        int k = col0 >= kCombos ? col0 - kCombos : col0;
+        if (k >= kCombos) k = 0;            // past both blocks: unused
+        int ca = (int)((1.f + sqrtf(1.f + 8.f * (float)k)) * 0.5f);
+        if (ca * (ca - 1) / 2 > k) ca--;
+        else if ((ca + 1) * ca / 2 <= k) ca++;
+        int cb = k - ca * (ca - 1) / 2;
+        uint16_t v[8];
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-        const int col = col0 + j, pp = col >= kCombos;
-        const int kk = col < 2 * kCombos ? col - pp * kCombos : 0;
-        rv[j] = rc[pp * kComboPad + kk];
-    }
-    // cards (a > b) of the combo in column col0 of its player's block
-    int k = col0 >= kCombos ? col0 - kCombos : col0;
-    int a = (int)((1.f + sqrtf(1.f + 8.f * (float)k)) * 0.5f);
-    if (a * (a - 1) / 2 > k) a--;
-    else if ((a + 1) * a / 2 <= k) a++;
-    int b = k - a * (a - 1) / 2;
-    uint16_t v[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-        const int col = col0 + j;
-        float x = 0.f;
-        if (col < 2 * kCombos) {
-            if (col == kCombos) { a = 1; b = 0; }           // player 1's block restarts at combo 0
-            const int pp = col >= kCombos;
-            if (a != c && b != c) x = (float)((double)rv[j] * (pp ? s1 : s0));
-            if (++b == a) { a++; b = 0; }
-        } else if (col < 2 * kCombos + 52) {
-            const int card = col - 2 * kCombos;
-            x = (card == c || card == board.x || card == board.y || card == board.z || card == board.w) ? 1.f : 0.f;
-        } else if (col == 2 * kCombos + 52) {
-            x = ratio;
+        for (int j = 0; j < 8; j++) {
+            const int col = col0 + j;
+            float xv = 0.f;
+            if (col < 2 * kCombos) {
+                if (col == kCombos) { ca = 1; cb = 0; }      // player 1's block restarts at combo 0
+                const int pp = col >= kCombos;
+                if (ca != c && cb != c) xv = (float)(xc[pp][col - pp * kCombos] * (pp ? s1 : s0));
+                if (++cb == ca) { ca++; cb = 0; }
+            } else if (col < 2 * kCombos + 52) {
+                const int card = col - 2 * kCombos;
+                xv = (card == c || card == board.x || card == board.y || card == board.z || card == board.w) ? 1.f : 0.f;
+            } else if (col == 2 * kCombos + 52) {
+                xv = ratio;
+            }
+            v[j] = to_bf16(xv);
         }
-        v[j] = to_bf16(x);
+        *reinterpret_cast<u32x4*>(X + ((int64_t)li * n_next + ci) * ldx + col0) =
+            u32x4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                  (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
     }
-    *reinterpret_cast<u32x4*>(X + (int64_t)row * ldx + col0) =
-        u32x4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
-              (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
 }
 
 // Zero-sum correction of the network's outputs (a reading: the paper does not
@@ -1353,7 +1347,7 @@ struct Plan {
     size_t esz;
     size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
-        off_potk, off_zs, off_agg, off_rc, off_sinv, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
+        off_potk, off_zs, off_agg, off_rc, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
         off_eqgrp, off_nsub, off_b4,
         off_cmap, off_hmap, total;
     size_t lds_bytes, lds_fold, lds_show;
@@ -1774,7 +1768,6 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.off_zs = take(L.esz * std::max<int64_t>(L.n_net * L.n_next, 1));
     L.off_agg = take(L.esz * kAgg * std::max<int64_t>(L.n_net, 1));
     L.off_rc = take(L.esz * 2 * kComboPad * std::max<int64_t>(L.n_net, 1));
-    L.off_sinv = take(sizeof(double) * 104 * std::max<int64_t>(L.n_net, 1));
     // suit isomorphism: per node (source child, permutation); per subgame and permutation, the hand map
     L.off_cmap = take(iso ? sizeof(int32_t) * 2 * L.N : 0);
     L.off_hmap = take(iso ? sizeof(int16_t) * 24 * L.Hp * P.n_sub : 0);
@@ -1963,13 +1956,15 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         pcfr_leafnet* net = s->net;
         const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_leaf_ranges<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream, nodes,
+        const int ldx = (int)net->P.pdims[0];   // a multiple of 8, checked when the network is attached
+        // about 1024 row groups per launch (at least one card per group)
+        const int cpg = (int)std::min<int64_t>(L.n_next, std::max<int64_t>(1, (rows + 1023) / 1024));
+        const int n_grp = (int)((L.n_next + cpg - 1) / cpg);
+        hipLaunchKernelGGL((k_leaf_input<T>), dim3((unsigned)L.n_net, (unsigned)n_grp), dim3(kBlock), 0, stream, nodes,
                            s->at<int32_t>(L.off_net), Hp, reach, s->at<int16_t>(L.off_c2h), s->at<T>(L.off_rc),
-                           s->at<double>(L.off_sinv), s->at<T>(L.off_agg));
-        hipLaunchKernelGGL((k_leaf_x<T>), dim3((unsigned)rows), dim3(kLeafXBlock), 0, stream, s->at<T>(L.off_rc),
-                           s->at<double>(L.off_sinv), s->at<float>(L.off_spr), (int)L.n_next, s->at<int32_t>(L.off_nsub),
-                           s->at<int8_t>(L.off_next), reinterpret_cast<const int4*>(s->at<int32_t>(L.off_b4)),
-                           (int)net->P.pdims[0], reinterpret_cast<uint16_t*>(net->ws + net->P.off_x));
+                           s->at<T>(L.off_agg), s->at<float>(L.off_spr), (int)L.n_next, cpg,
+                           s->at<int8_t>(L.off_next), reinterpret_cast<const int4*>(s->at<int32_t>(L.off_b4)), ldx,
+                           reinterpret_cast<uint16_t*>(net->ws + net->P.off_x));
         if (tm) tm->after();
         int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
         if (rc) return rc;
@@ -2689,7 +2684,7 @@ int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net) {
             return PCFR_E_INVALID_ARG;
         }
         if (s->L.n_net * s->L.n_next > N.Mp) { set_error("leaf network max_batch below leaves x next cards"); return PCFR_E_INVALID_ARG; }
-        if (N.pdims[0] > kLeafXBlock * 8) { set_error("leaf network input wider than the input kernel"); return PCFR_E_INVALID_ARG; }
+        if (N.pdims[0] % 8) { set_error("leaf network input rows must be padded to 8 columns"); return PCFR_E_INVALID_ARG; }
     }
     HIPCHK(hipStreamSynchronize(s->stream));
     s->net = net;
