@@ -150,64 +150,54 @@ def copy_ceiling_gbs(mib=1024, reps=10):
 
 
 def cpu_baseline(spec, r, budget_s, leaf_params=None):
-    """Time the FP64 oracle on the same tree with sparse-support ranges at two
-    support sizes, fit time = fixed + per_pair * pairs, and extrapolate to the
-    full ranges' pair count.  With a leaf network, each oracle iteration also
-    builds the leaf inputs and runs the FP64 network (its cost is in `fixed`)."""
+    """Time the FP64 oracle on the full workload: whole iterations on the same
+    tree and full ranges (one warm-up iteration, then as many as fit in
+    budget_s, at least two).  With a leaf network each iteration first
+    refreshes the leaf table (leaf inputs + FP64 forward of every leaf row)
+    from the current reach, then walks the tree; both parts are timed."""
     import oracle as O
     from oracle import mlp
-    from paper_2605_19928_amd import inputs as I
 
-    cc = I.combo_cards()
     t = O.Tree.holdem(**spec)
-    full_pairs = 2 * pair_count(r[0], r[1], cc)
-    rng = np.random.default_rng(1234)
-    ok = np.flatnonzero(~I.blocked_mask(spec["board"]))
     e = t.export()
     leaves = np.flatnonzero(e["type"] == O.T_LEAF)
     eff = min(spec["stacks"])
-    pts = []
-    for k in (8, 24):
-        pick = np.sort(rng.choice(ok, k, replace=False))
-        rs = np.zeros_like(r)
-        rs[:, pick] = r[:, pick]
-        s = O.Solver(t, rs, support_only=True)
-        n, t0 = 0, time.perf_counter()
-        while True:
-            if leaf_params is not None and len(leaves):
-                reach = s.reach_current()
-                ev = np.zeros((len(leaves), 2, 52, 1326))
-                for li, node in enumerate(leaves):
-                    c = e["contrib"][node][0]
-                    cards, X = mlp.leaf_inputs(reach[node], spec["board"], 2 * c, spec["pot"] // 2 + eff - c, 2705)
-                    Y = mlp.forward(leaf_params, X, emulate_bf16=True)
-                    for kk, card in enumerate(cards):
-                        ev[li, 0, card] = Y[kk, :1326]
-                        ev[li, 1, card] = Y[kk, 1326:]
-                s.set_leaf_table(ev)
-            s.iterate(1)
-            n += 1
-            el = time.perf_counter() - t0
-            if el > budget_s / 2 or n >= 50:
-                break
-        pts.append((2 * pair_count(rs[0], rs[1], cc), el / n))
-        del s
-    # the tree walk alone (no network refresh) on the larger sample, on every
-    # host thread and on one, for the oracle's parallel speedup
     cores = O.max_threads()
-    pick = np.sort(np.random.default_rng(1234).choice(ok, 24, replace=False))
-    rs = np.zeros_like(r)
-    rs[:, pick] = r[:, pick]
-    walk = {}
-    for th in (cores, 1):
-        s = O.Solver(t, rs, support_only=True)
-        n1, t0 = 0, time.perf_counter()
-        while time.perf_counter() - t0 < min(budget_s / 6, 3.0) and n1 < 50:
-            s.iterate(1, threads=th)
-            n1 += 1
-        walk[th] = (time.perf_counter() - t0) / max(n1, 1)
-        del s
-    O.Solver(t, rs, support_only=True).iterate(0, threads=cores)   # restore the thread count
+    if leaf_params is None:
+        return cpu_baseline_ladder(t, r, spec, budget_s, cores)
+    s = O.Solver(t, r)
+
+    def refresh():
+        if leaf_params is None or not len(leaves):
+            return
+        reach = s.reach_current()
+        ev = np.zeros((len(leaves), 2, 52, 1326))
+        for li, node in enumerate(leaves):
+            c = e["contrib"][node][0]
+            cards, X = mlp.leaf_inputs(reach[node], spec["board"], 2 * c, spec["pot"] // 2 + eff - c, 2705)
+            Y = mlp.forward(leaf_params, X, emulate_bf16=True)
+            for kk, card in enumerate(cards):
+                ev[li, 0, card] = Y[kk, :1326]
+                ev[li, 1, card] = Y[kk, 1326:]
+        s.set_leaf_table(ev)
+
+    refresh()
+    s.iterate(1, threads=cores)                 # warm-up (allocation)
+    net_s = walk_s = 0.0
+    n, t0 = 0, time.perf_counter()
+    while True:
+        ta = time.perf_counter()
+        refresh()
+        tb = time.perf_counter()
+        s.iterate(1, threads=cores)
+        tc = time.perf_counter()
+        net_s += tb - ta
+        walk_s += tc - tb
+        n += 1
+        if n >= 2 and time.perf_counter() - t0 > budget_s:
+            break
+    sec = (time.perf_counter() - t0) / n
+    del s
     cpu_model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -216,22 +206,56 @@ def cpu_baseline(spec, r, budget_s, leaf_params=None):
                 break
     except OSError:
         pass
-    (p1, t1), (p2, t2) = pts
-    per_pair = max((t2 - t1) / max(p2 - p1, 1), 0.0)
-    fixed = max(t1 - per_pair * p1, 0.0)
-    sec_full = fixed + per_pair * full_pairs
     return {
-        "value": 1.0 / sec_full,
+        "value": 1.0 / sec,
         "unit": "iters/s",
         "cores": cores,
         "kind": "oracle",
         "host_cpu": cpu_model, "host_nproc": os.cpu_count(),
-        "walk_s_per_iter_24combo": {"threads": cores, "all_threads": walk[cores], "one_thread": walk[1]},
-        "sample": (f"oracle on the same tree with random 8- and 24-combo supports per player "
-                   f"({pts[0][1]:.3f} and {pts[1][1]:.3f} s/iter over {pts[0][0]} and {pts[1][0]} hand pairs"
-                   + (", FP64 leaf network included" if leaf_params is not None else "")
-                   + f"); time = fixed + per-pair cost fitted and extrapolated to the full ranges' "
-                     f"{full_pairs} pairs"),
+        "parts_s_per_iter": {"leaf_network": net_s / n, "walk": walk_s / n},
+        "sample": (f"{n} oracle iterations of the full workload (same tree, full ranges) after one warm-up, "
+                   f"{sec:.3f} s each: FP64 leaf-network refresh {net_s / n:.3f} s + tree walk "
+                   f"{walk_s / n:.3f} s on {cores} threads"),
+    }
+
+
+def cpu_baseline_ladder(t, r, spec, budget_s, cores):
+    """For trees whose full oracle iteration takes minutes (the turn): one
+    iteration at random supports of 24, 48, 96, ... combos per player until
+    one takes an eighth of budget_s or the support is full; seconds per
+    iteration extrapolated linearly in hand pairs from the last two points."""
+    import oracle as O
+    from paper_2605_19928_amd import inputs as I
+
+    cc = I.combo_cards()
+    ok = np.flatnonzero(~I.blocked_mask(spec["board"]))
+    full_pairs = 2 * pair_count(r[0], r[1], cc)
+    pts, k, t_all = [], 24, time.perf_counter()
+    while True:
+        pick = np.sort(np.random.default_rng(1234 + k).choice(ok, min(k, len(ok)), replace=False))
+        rs = np.zeros_like(r)
+        rs[:, pick] = r[:, pick]
+        s = O.Solver(t, rs, support_only=True)
+        s.iterate(1, threads=cores)             # warm-up (allocation)
+        t0 = time.perf_counter()
+        s.iterate(1, threads=cores)
+        pts.append((2 * pair_count(rs[0], rs[1], cc), time.perf_counter() - t0))
+        del s
+        if k >= len(ok) or pts[-1][1] > budget_s / 8 or time.perf_counter() - t_all > budget_s:
+            break
+        k *= 2
+    if len(pts) == 1 or pts[-1][0] >= full_pairs:
+        sec = pts[-1][1] * full_pairs / max(pts[-1][0], 1)
+    else:
+        (p1, t1), (p2, t2) = pts[-2], pts[-1]
+        per_pair = max((t2 - t1) / max(p2 - p1, 1), 0.0)
+        sec = max(t2 + per_pair * (full_pairs - p2), t2)
+    return {
+        "value": 1.0 / sec, "unit": "iters/s", "cores": cores, "kind": "oracle",
+        "host_nproc": os.cpu_count(),
+        "sample": (f"oracle walk at random supports per player, one iteration each: "
+                   + ", ".join(f"{p} pairs {x:.3f} s" for p, x in pts)
+                   + f"; extrapolated linearly in pairs from the last two to the full ranges' {full_pairs} pairs"),
     }
 
 
