@@ -813,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
 // leaf when no network is attached): v_i(h) = c * sum_o E(h,o) r_{-i}(o).
 // Et is stored transposed, [o][h], so consecutive threads read consecutive h.
 // The sum over o is split into kEqSplit slices, each slice of a group of up
-// to J leaves of one subgame (so one table, [n_sub][Hp][Hp]) one workgroup
+// to J leaves of one subgame (so one table, [n_et][Hp][Hp]) one workgroup
 // with the slice of their reach vectors in LDS; a second kernel adds the
 // slices in a fixed order (deterministic) and applies the contribution.
 constexpr int kEqSplit = 32;
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(kBlock) void k_equity_partial(const DNode* __restri
                                                            T* __restrict__ part) {
     constexpr int kChunk = (kMaxHp + kEqSplit - 1) / kEqSplit;
     __shared__ T rr[J][2][kChunk];
-    const int4 gr = groups[blockIdx.y];    // first leaf, count (<= J), subgame
+    const int4 gr = groups[blockIdx.y];    // first leaf, count (<= J), equity table
     const int j0 = gr.x;
     const int nj = gr.y;
     Et += (int64_t)gr.z * Hp * Hp;
@@ -1386,6 +1386,8 @@ struct Prepared {
     // network is attached); subgames holding leaves share one board size
     std::vector<int32_t> eq_leaves;
     std::vector<int32_t> eq_sub;           // per leaf: its subgame
+    std::vector<int32_t> et_slot;          // per subgame: its equity table, -1 without leaves
+    int32_t n_et = 0;                      // subgames holding depth-limit leaves
     std::vector<double> eq_pay;
     int64_t n_allin = 0;
     int leaf_board = -1;                   // board size of the subgames with leaves
@@ -1571,6 +1573,11 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
                 }
             }
         }
+    // an equity table only for the subgames that hold leaves
+    P.et_slot.assign(K, -1);
+    P.n_et = 0;
+    for (int32_t g : P.eq_sub)
+        if (P.et_slot[g] < 0) P.et_slot[g] = P.n_et++;
     // per subgame: the root board (up to 4 cards, -1 past the last) and the
     // cards that can come next (one table row of 64 per subgame)
     P.board4s.assign((size_t)K * 4, -1);
@@ -1690,7 +1697,7 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
 
 // Workgroup groups of the equity kernel: runs of up to J consecutive leaves of
 // one subgame, never across the end of the all-in prefix; {first, count,
-// subgame, 0} each.  n_allin_groups: the groups of the all-in prefix.
+// equity table of the subgame, 0} each.  n_allin_groups: the groups of the all-in prefix.
 static void equity_groups(const Prepared& P, int J, std::vector<int32_t>& out, int64_t& n_allin_groups) {
     out.clear();
     n_allin_groups = 0;
@@ -1698,7 +1705,7 @@ static void equity_groups(const Prepared& P, int J, std::vector<int32_t>& out, i
     for (int64_t i = 0; i < n;) {
         int64_t j = i + 1;
         while (j < n && j - i < J && P.eq_sub[j] == P.eq_sub[i] && j != P.n_allin) j++;
-        out.insert(out.end(), {(int32_t)i, (int32_t)(j - i), P.eq_sub[i], 0});
+        out.insert(out.end(), {(int32_t)i, (int32_t)(j - i), P.et_slot[P.eq_sub[i]], 0});
         if (j <= P.n_allin) n_allin_groups++;
         i = j;
     }
@@ -1755,8 +1762,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     }
     L.H_leaf = P.leaf_H;
     L.n_next = P.leaf_board >= 0 ? 52 - P.leaf_board : (int64_t)P.next_cards.size();
-    // one pairwise equity table per subgame, [n_sub][Hp][Hp], when any subgame has leaves
-    L.off_et = take(L.n_eq ? L.esz * L.Hp * L.Hp * P.n_sub : 0);
+    // one pairwise equity table per subgame holding leaves, [n_et][Hp][Hp]
+    L.off_et = take(L.esz * L.Hp * L.Hp * (size_t)P.n_et);
     L.off_eqgrp = take(sizeof(int32_t) * 4 * std::max<int64_t>(L.n_grp, 1));
     L.off_nsub = take(sizeof(int32_t) * std::max<int64_t>(L.n_net, 1));
     L.off_b4 = take(sizeof(int32_t) * 4 * P.n_sub);
@@ -2301,10 +2308,8 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         if ((rc = up(L.off_potk, P.net_potk.data(), sizeof(double) * P.net_potk.size()))) return rc;
         HIPCHK(hipStreamSynchronize(s->stream));
         // pairwise equity table of each subgame holding depth-limit leaves
-        std::vector<char> has_leaf(n, 0);
-        for (int32_t g : P.eq_sub) has_leaf[g] = 1;
-        for (int32_t g = 0; g < n && L.n_eq; g++) {
-            if (!has_leaf[g]) continue;
+        for (int32_t g = 0; g < n; g++) {
+            if (P.et_slot[g] < 0) continue;
             const int64_t Hg = P.Hs[g];
             std::vector<double> E;
             std::vector<char> et;
@@ -2322,7 +2327,7 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
                     if (L.esz == 8) reinterpret_cast<double*>(et.data())[i] = v;
                     else reinterpret_cast<float*>(et.data())[i] = (float)v;
                 }
-            if ((rc = up(L.off_et + L.esz * L.Hp * L.Hp * (size_t)g, et.data(), et.size()))) return rc;
+            if ((rc = up(L.off_et + L.esz * L.Hp * L.Hp * (size_t)P.et_slot[g], et.data(), et.size()))) return rc;
             HIPCHK(hipStreamSynchronize(s->stream));
         }
     }
