@@ -135,6 +135,28 @@ def test_batch_depth_limited_exact_leaves(dtype):
         assert d <= 1e-9
 
 
+@pytest.mark.parametrize("variant,alternating", [("pcfr+", 1), ("cfr+", 0)])
+def test_batch_depth_limited_variants(variant, alternating):
+    """The other update rules on a batch with exact leaves: members bitwise
+    equal to their own solves (alternating updates sweep each player in turn,
+    so the leaves are evaluated twice per iteration)."""
+    cases = depth_limited_cases()
+    say(f"case: batch of a river and two depth-limited flops, {variant}, alternating {alternating}")
+    cfg = P.SolverConfig(dtype="f64", variant=variant, alternating=alternating)
+    trees = [P.Tree(**s) for s, _ in cases]
+    b = P.Batch(trees, np.stack([r for _, r in cases]), cfg)
+    T = 8
+    b.iterate(T)
+    for g, (spec, r) in enumerate(cases):
+        s = P.Solver(trees[g], r, cfg)
+        s.iterate(T)
+        np.testing.assert_array_equal(b.root_cfv_of(g, "current"), s.root_cfv("current"))
+        e = trees[g].export()
+        for n in np.flatnonzero(e["type"] == P.NODE_DECISION)[:4]:
+            np.testing.assert_array_equal(b.strategy_of(g, int(n)), s.strategy(int(n)))
+        s.close()
+
+
 def test_batch_depth_limited_network_leaves():
     """With a leaf network, the batch feeds every subgame's (leaf, next card)
     rows through one set of GEMMs; on fixed tiles each member must match its
