@@ -165,16 +165,30 @@ def test_flop_depth_limited_exact_leaves(dtype, T):
             assert np.abs(gs.strategy(int(n)) - os_.strategy(int(n)))[:, ok].max() <= 1e-9
 
 
-@pytest.mark.parametrize("zero_sum", [True, False])
-def test_flop_depth_limited_network_leaves(zero_sum):
+def turn_leaf_case(support=120, seed=3):
+    """Depth-limited turn (leaves at the river card): 4-card board, so the
+    network rows carry four board cards plus the next card and there are 48
+    next cards per leaf."""
+    rng = np.random.default_rng(seed)
+    board = I.draw_board(rng, 4)
+    r = np.stack([I.dirichlet_range(rng, board, 1.0, support), I.dirichlet_range(rng, board, 1.0, support)])
+    spec = dict(board=board, pot=100, stacks=(400, 400), sizes=[50, 100], allin=True, max_raises=2, depth_limit=1)
+    return spec, r
+
+
+@pytest.mark.parametrize("street,zero_sum", [("flop", True), ("flop", False), ("turn", True)])
+def test_flop_depth_limited_network_leaves(street, zero_sum):
     import torch
-    spec, r = flop_case(support=120, seed=1)
-    say(f"case: flop depth-limited, network leaves, zero-sum correction {zero_sum}, {spec}")
+    spec, r = flop_case(support=120, seed=1) if street == "flop" else turn_leaf_case()
+    say(f"case: {street} depth-limited, network leaves, zero-sum correction {zero_sum}, {spec}")
     rng = np.random.default_rng(9)
     gt = P.Tree(**spec)
     gs = P.Solver(gt, r, P.SolverConfig(dtype="f64"))
     n_leaves, n_next = gs.leaf_rows()
-    assert (n_leaves, n_next) == (21, 49)
+    if street == "flop":
+        assert (n_leaves, n_next) == (21, 49)
+    else:
+        assert n_leaves > 0 and n_next == 48
     net = P.LeafNet(P.LEAF_D_IN, 64, 2, P.LEAF_D_OUT, max_batch=n_leaves * n_next)
     params = rand_params(rng, net.layer_shapes(), scale=2.0)
     net.set_params(params)
