@@ -157,15 +157,30 @@ def test_batch_depth_limited_variants(variant, alternating):
         s.close()
 
 
-def test_batch_depth_limited_network_leaves():
+def depth_limited_turn_cases():
+    """A river, then two depth-limited turns (leaves at the river card) on
+    different 4-card boards."""
+    river = I.batch_config(6, count_nodes, n=1, river_share=1.0, lo=10, hi=300)[0]
+    out = [river]
+    for seed in (3, 5):
+        rng = np.random.default_rng(seed)
+        board = I.draw_board(rng, 4)
+        r = np.stack([I.dirichlet_range(rng, board, 1.0, 150), I.dirichlet_range(rng, board, 1.0, 150)])
+        out.append((dict(board=board, pot=100, stacks=(400, 400), sizes=[50, 100], allin=True, max_raises=2,
+                         depth_limit=1), r))
+    return out
+
+
+@pytest.mark.parametrize("street", ["flop", "turn"])
+def test_batch_depth_limited_network_leaves(street):
     """With a leaf network, the batch feeds every subgame's (leaf, next card)
     rows through one set of GEMMs; on fixed tiles each member must match its
     own solve bitwise."""
-    cases = depth_limited_cases()
+    cases = depth_limited_cases() if street == "flop" else depth_limited_turn_cases()
     trees = [P.Tree(**s) for s, _ in cases]
     b = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype="f64"))
     n_leaves, n_next = b.leaf_rows()
-    assert (n_leaves, n_next) == (2 * 21, 49)
+    assert n_leaves == trees[1].n_leaf + trees[2].n_leaf and n_next == (49 if street == "flop" else 48)
     rng = np.random.default_rng(17)
     params = None
 
