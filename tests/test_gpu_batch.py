@@ -194,6 +194,11 @@ def test_batch_depth_limited_network_leaves(street):
         net.tiles = [0] * len(params)
         return net
 
+    # a network sized for one subgame's rows is refused by the batch
+    small = make_net(trees[1].n_leaf * n_next)
+    with pytest.raises(P.PcfrError, match="max_batch"):
+        b.attach_leafnet(small)
+    small.close()
     netb = make_net(n_leaves * n_next)
     b.attach_leafnet(netb)
     say(f"case: batch with a leaf network, {n_leaves} leaves x {n_next} next cards")
