@@ -185,6 +185,20 @@ int32_t pcfr_prune_dominated(const pcfr_tree* tree, const double* ranges, const 
                              uint8_t* removed);
 int32_t pcfr_tree_prune(const pcfr_tree* tree, const uint8_t* removed, pcfr_tree** out, int32_t* new_id);
 
+/* pcfr_prune_dominated without any device allocation, for callers that
+ * cannot allocate (serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, checks and result as pcfr_prune_dominated; the node list,
+ * combo masks, ranges and flags live in a static device array of the
+ * library (about 1.9 MB per GPU, held until the process ends), reached
+ * through the current device's symbol address.  Trees with more than 65536
+ * decision nodes or 262144 nodes give PCFR_E_TOO_LARGE.  Work runs on the
+ * device's null stream and the call returns after the flags are copied
+ * back.  Every call on one GPU shares that array, so calls that overlap on
+ * one GPU (from several host threads) race; each call clears the flags it
+ * uses. */
+int32_t pcfr_prune_dominated_noalloc(const pcfr_tree* tree, const double* ranges, const double* lo,
+                                     const double* hi, uint8_t* removed);
+
 /* Seven-card hand values, host side (used to order hands at showdown,
  * Sec. 4.3 Stage 4).  cards: n*7 card ids; out: n values.  Value layout:
  * category (0 high card .. 8 straight flush) in bits 20..23 and the

@@ -10,8 +10,10 @@
 // node's board does not block (prune_tree then drops its subtree).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -89,6 +91,69 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
+// Host half shared by both entry points: validate the arguments and list
+// the decision nodes and each combo's card mask.
+int32_t prune_inputs(const pcfr_tree* tree, const double* ranges, const double* lo, const double* hi,
+                     uint8_t* removed, std::vector<PruneNode>& dec, std::vector<uint64_t>& cm) {
+    if (!tree || !ranges || !lo || !hi || !removed) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (!on_device(lo) || !on_device(hi)) { set_error("the bounds must be device memory"); return PCFR_E_INVALID_ARG; }
+    for (int i = 0; i < 2 * kCombos; i++)
+        if (!(ranges[i] >= 0.0) || !std::isfinite(ranges[i])) { set_error("ranges must be finite and >= 0"); return PCFR_E_INVALID_ARG; }
+    const Tree& t = tree->t;
+    try {
+        for (const Node& n : t.nodes)
+            if (n.type == PCFR_NODE_DECISION) dec.push_back(PruneNode{n.first_child, n.n_child, n.player, 0, n.board_mask});
+        cm.resize(kCombos);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return PCFR_E_OUT_OF_MEMORY;
+    }
+    const ComboTable& cc = combos();
+    for (int k = 0; k < kCombos; k++) cm[k] = (1ull << cc.hi[k]) | (1ull << cc.lo[k]);
+    std::memset(removed, 0, t.nodes.size());
+    return PCFR_OK;
+}
+
+__global__ void k_zero_u8(uint8_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Device scratch of the allocation-free entry point, one copy per GPU for
+// the life of the process: the decision-node list, the combo masks, the
+// ranges and the per-node flags.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kScratchDecisions = 65536;
+constexpr int64_t kScratchNodes = 262144;
+constexpr size_t kScrNodesOff = 0;
+constexpr size_t kScrMaskOff = kScrNodesOff + sizeof(PruneNode) * kScratchDecisions;
+constexpr size_t kScrRangeOff = kScrMaskOff + sizeof(uint64_t) * kCombos;
+constexpr size_t kScrFlagOff = kScrRangeOff + sizeof(double) * 2 * kCombos;
+constexpr size_t kScratchBytes = kScrFlagOff + kScratchNodes;
+static_assert(kScrMaskOff % 16 == 0 && kScrRangeOff % 16 == 0 && kScrFlagOff % 16 == 0, "aligned sections");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of scratch (looked up once per device).
+int32_t scratch_for_current_device(unsigned char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) { set_error("device index beyond the scratch table"); return PCFR_E_DEVICE; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+        if (!p) { set_error("hipGetSymbolAddress returned no address"); return PCFR_E_DEVICE; }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return PCFR_OK;
+}
+
 }  // namespace
 }  // namespace pcfr
 
@@ -96,27 +161,11 @@ using namespace pcfr;
 
 extern "C" int32_t pcfr_prune_dominated(const pcfr_tree* tree, const double* ranges, const double* lo,
                                         const double* hi, uint8_t* removed) {
-    if (!tree || !ranges || !lo || !hi || !removed) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
-    if (!on_device(lo) || !on_device(hi)) { set_error("the bounds must be device memory"); return PCFR_E_INVALID_ARG; }
-    for (int i = 0; i < 2 * kCombos; i++)
-        if (!(ranges[i] >= 0.0) || !std::isfinite(ranges[i])) { set_error("ranges must be finite and >= 0"); return PCFR_E_INVALID_ARG; }
-    const Tree& t = tree->t;
-    const size_t N = t.nodes.size();
     std::vector<PruneNode> dec;
-    std::vector<uint64_t> cm(kCombos);
-    try {
-        for (size_t i = 0; i < N; i++) {
-            const Node& n = t.nodes[i];
-            if (n.type != PCFR_NODE_DECISION) continue;
-            dec.push_back(PruneNode{n.first_child, n.n_child, n.player, 0, n.board_mask});
-        }
-    } catch (const std::bad_alloc&) {
-        set_error("out of host memory");
-        return PCFR_E_OUT_OF_MEMORY;
-    }
-    const ComboTable& cc = combos();
-    for (int k = 0; k < kCombos; k++) cm[k] = (1ull << cc.hi[k]) | (1ull << cc.lo[k]);
-    std::memset(removed, 0, N);
+    std::vector<uint64_t> cm;
+    int32_t rc = prune_inputs(tree, ranges, lo, hi, removed, dec, cm);
+    if (rc != PCFR_OK) return rc;
+    const size_t N = tree->t.nodes.size();
     if (dec.empty()) return PCFR_OK;
     DevBuf dn, dm, dr, dout;
     hipError_t e;
@@ -132,5 +181,39 @@ extern "C" int32_t pcfr_prune_dominated(const pcfr_tree* tree, const double* ran
                        (const PruneNode*)dn.p, (const uint64_t*)dm.p, (const double*)dr.p, lo, hi, (uint8_t*)dout.p);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_prune_dominated");
     if ((e = hipMemcpy(removed, dout.p, N, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "hipMemcpy");
+    return PCFR_OK;
+}
+
+extern "C" int32_t pcfr_prune_dominated_noalloc(const pcfr_tree* tree, const double* ranges, const double* lo,
+                                                const double* hi, uint8_t* removed) {
+    std::vector<PruneNode> dec;
+    std::vector<uint64_t> cm;
+    int32_t rc = prune_inputs(tree, ranges, lo, hi, removed, dec, cm);
+    if (rc != PCFR_OK) return rc;
+    const int64_t N = (int64_t)tree->t.nodes.size();
+    if ((int64_t)dec.size() > kScratchDecisions || N > kScratchNodes) {
+        set_error("tree exceeds the static scratch of pcfr_prune_dominated_noalloc (65536 decision nodes, "
+                  "262144 nodes)");
+        return PCFR_E_TOO_LARGE;
+    }
+    if (dec.empty()) return PCFR_OK;
+    unsigned char* base = nullptr;
+    if ((rc = scratch_for_current_device(&base)) != PCFR_OK) return rc;
+    PruneNode* dn = reinterpret_cast<PruneNode*>(base + kScrNodesOff);
+    uint64_t* dm = reinterpret_cast<uint64_t*>(base + kScrMaskOff);
+    double* dr = reinterpret_cast<double*>(base + kScrRangeOff);
+    uint8_t* dout = base + kScrFlagOff;
+    hipError_t e;
+    if ((e = hipMemcpy(dn, dec.data(), sizeof(PruneNode) * dec.size(), hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
+    if ((e = hipMemcpy(dm, cm.data(), sizeof(uint64_t) * kCombos, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
+    if ((e = hipMemcpy(dr, ranges, sizeof(double) * 2 * kCombos, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
+    // the flags of the previous call are still there: clear this call's span
+    const unsigned zb = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_zero_u8, dim3(zb), dim3(256), 0, 0, dout, N);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_zero_u8");
+    hipLaunchKernelGGL(k_prune_dominated, dim3((unsigned)dec.size()), dim3(kPruneBlock), 0, 0,
+                       (const PruneNode*)dn, (const uint64_t*)dm, (const double*)dr, lo, hi, dout);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "k_prune_dominated");
+    if ((e = hipMemcpy(removed, dout, (size_t)N, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "hipMemcpy");
     return PCFR_OK;
 }

@@ -54,6 +54,7 @@ _SIGS = {
     "pcfr_eval7_batch": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p]),
     "pcfr_suit_iso_map": (C.c_int32, [C.c_void_p] * 6),
     "pcfr_prune_dominated": (C.c_int32, [C.c_void_p] * 5),
+    "pcfr_prune_dominated_noalloc": (C.c_int32, [C.c_void_p] * 5),
     "pcfr_tree_prune": (C.c_int32, [C.c_void_p] * 4),
     "pcfr_solver_swept_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_equity_table": (C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -191,11 +192,12 @@ class Tree:
         _check(lib().pcfr_suit_iso_map(self._h, _p(r), C.byref(grp), _p(src), _p(perm), _p(skip)))
         return {"group": int(grp.value), "src": src, "perm": perm, "skip": skip}
 
-    def prune_dominated(self, ranges, lo, hi) -> np.ndarray:
+    def prune_dominated(self, ranges, lo, hi, noalloc: bool = False) -> np.ndarray:
         """Dominance test of online pruning on the GPU.  lo, hi: CUDA float64
         tensors [n_nodes, 1326] of bounds on the actor's value of the action
         leading to each node.  Returns uint8 flags [n_nodes]: 1 where that
-        action is dominated for every hand of the actor's range."""
+        action is dominated for every hand of the actor's range.  noalloc:
+        use the entry point that allocates no device memory."""
         import torch
 
         r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, NCOMBO)
@@ -205,8 +207,8 @@ class Tree:
                 raise ValueError("bounds must be contiguous CUDA float64 tensors [n_nodes, 1326]")
         torch.cuda.current_stream(lo.device).synchronize()
         out = np.zeros(self.n_nodes, dtype=np.uint8)
-        _check(lib().pcfr_prune_dominated(self._h, _p(r), C.c_void_p(lo.data_ptr()), C.c_void_p(hi.data_ptr()),
-                                          _p(out)))
+        fn = lib().pcfr_prune_dominated_noalloc if noalloc else lib().pcfr_prune_dominated
+        _check(fn(self._h, _p(r), C.c_void_p(lo.data_ptr()), C.c_void_p(hi.data_ptr()), _p(out)))
         return out
 
     def prune(self, removed):
