@@ -349,12 +349,24 @@ def batch_sweep(args, seed, steps, warmup, individual=True):
     alg_bytes = 4 * esz * float((rows * hands).sum())
     achieved = alg_bytes / (pms[3] * 1e-3) / 1e9
     expl, _ = b.exploitability_all()
+    # the same forest with every iteration of the timed window in one
+    # persistent cooperative launch (grid barriers between the phases);
+    # identical iterates, so the same exploitability
+    pb = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=args.dtype))
+    pb.set_launch(True)
+    ms_persist = timed(pb, steps, warmup)
+    pb.close()
+    log(f"batch: graph {ms:.4f} ms/iter, persistent launch {ms_persist:.4f} ms/iter")
     out = {
         "workload": f"256 river/turn subgames in one forest, seed {seed}",
         "subgames": len(trees), "river": n_river, "turn": len(trees) - n_river,
         "nodes_min": int(nodes.min()), "nodes_median": int(np.median(nodes)), "nodes_max": int(nodes.max()),
         "nodes_total": int(nodes.sum()), "action_rows_total": int(rows.sum()),
         "ms_per_iter": ms, "iters_per_s": 1000.0 / ms,
+        "persistent_launch_ms_per_iter": ms_persist,
+        "persistent_launch_note": "all timed iterations in one cooperative launch of a resident grid, grid "
+                                  "barriers between level sweeps and terminals; ms_per_iter is the autotuned "
+                                  "graph of per-level launches",
         "autotune_ms_per_iter_before_after": [before, after],
         "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
         "exploitability_mbb_per_hand_mean": float(np.mean(expl)) * 100.0,
@@ -459,6 +471,9 @@ def pruning_sweep(args, spec, r, steps, warmup, warm_iters=100, eps=0.1):
     out = {
         "workload": "turn of the tree-sweep line; bounds = node values of the average strategies after "
                     f"{warmup + steps + warm_iters} iterations +- {eps} x the per-hand spread of sibling actions",
+        "bounds_kind": "heuristic: point values of a short solve widened by a margin, not sound bounds (the "
+                       "value-network ensemble that gives sound ones is not part of this library); the line "
+                       "times the dominance test and the reduced tree, not a lossless pruning",
         "nodes_full": n, "nodes_pruned": pruned.n_nodes, "rho": pruned.n_nodes / n,
         "actions_removed": int(flags.sum()), "action_rows_full": tree.n_rows, "action_rows_pruned": pruned.n_rows,
         "bounds_ms": 1e3 * (t1 - t0), "dominance_test_ms": 1e3 * (t2 - t1), "tree_reduction_ms": 1e3 * (t3 - t2),
@@ -466,6 +481,40 @@ def pruning_sweep(args, spec, r, steps, warmup, warm_iters=100, eps=0.1):
     }
     log(f"pruning: {n} -> {pruned.n_nodes} nodes (rho {out['rho']:.3f}), {ms_full:.4f} -> {ms_pruned:.4f} ms/iter, "
         f"dominance test {out['dominance_test_ms']:.1f} ms")
+    return out
+
+
+def rbp_sweep(args, spec, r, steps, warmup, warm_iters=100):
+    """Regret-based pruning of unreachable subtrees (exact: the iterates equal
+    the unpruned ones) on the turn of the tree-sweep line, without and with
+    dynamic thresholding (actions below thr0 / sqrt(t) dropped, which makes
+    unreachable subtrees common): ms/iter pruned vs unpruned at the same
+    threshold after warm_iters iterations, the share of nodes skipped, and
+    the exploitability after the same number of iterations."""
+    from paper_2605_19928_amd import pcfr as P
+
+    tree = P.Tree(**spec)
+    out = []
+    for thr in (0.0, 0.05):
+        res = {"threshold_thr0": thr}
+        for prune in (0, 1):
+            s = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype, threshold=thr, prune=prune))
+            s.iterate(warm_iters)
+            ms = timed(s, steps, warmup)
+            res["ms_per_iter_pruned" if prune else "ms_per_iter_unpruned"] = ms
+            if prune:
+                res["nodes_skipped_last_iter"] = s.unreached_nodes()
+                res["iterations"] = warm_iters + warmup + steps
+                e, _ = s.exploitability()
+                res["exploitability_mbb_per_hand"] = e * 100.0
+            s.close()
+        res["nodes"] = tree.n_nodes
+        res["skipped_share"] = res["nodes_skipped_last_iter"] / tree.n_nodes
+        res["speedup"] = res["ms_per_iter_unpruned"] / res["ms_per_iter_pruned"]
+        log(f"regret-based pruning thr0={thr}: {res['ms_per_iter_unpruned']:.4f} -> {res['ms_per_iter_pruned']:.4f} "
+            f"ms/iter, {res['nodes_skipped_last_iter']} of {tree.n_nodes} nodes skipped, exploitability "
+            f"{res['exploitability_mbb_per_hand']:.1f} mbb/hand")
+        out.append(res)
     return out
 
 
@@ -718,6 +767,7 @@ def main():
         result["batch"] = batch_sweep(args, 0, max(20, args.steps // 4), 5)
         result["suit_isomorphism"] = suit_iso_sweep(args, max(20, args.steps // 4), 5)
         result["pruning"] = [pruning_sweep(args, tspec, tr, max(20, args.steps // 4), 5, eps=e) for e in (0.0, 0.05)]
+        result["regret_based_pruning"] = rbp_sweep(args, tspec, tr, max(20, args.steps // 4), 5)
         result["turn_spr_sweep"] = spr_sweep(args, max(20, args.steps // 4), 5)
         result["leaf_gemm_m2048"] = gemm_shape_point(args)
         result["flop_batch"] = flop_batch_sweep(args, max(20, args.steps // 4), 5)

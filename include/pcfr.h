@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define PCFR_ABI_VERSION 1
+#define PCFR_ABI_VERSION 2
 #define PCFR_NCOMBO 1326
 
 enum {
@@ -102,13 +102,30 @@ typedef struct pcfr_tree_spec {
  * those of suit_iso = 0 up to rounding order; ranges without symmetry change
  * nothing.  Strategies inside a skipped subtree are not stored;
  * pcfr_get_strategy returns the representative's with the hands relabelled
- * by the permutation. */
+ * by the permutation.
+ *
+ * threshold = thr0 > 0: dynamic thresholding (cited in Sec. 2 among the
+ * pruning methods: low-probability actions are dropped on the fly).  In
+ * iteration t, after regret matching, every action whose probability is
+ * below thr0 / sqrt(t) is set to 0 and the others are renormalised (the
+ * threshold shrinks as the regret-matching error bound does, so the average
+ * strategy still converges); PCFR_CURRENT strategies are those of the next
+ * iteration.  prune = 1: regret-based pruning as Sec. 2 describes it --
+ * subtrees unreachable under the current strategy profile are skipped.  A
+ * node whose reach is zero for every hand of both players contributes exact
+ * zeros (every value in its subtree is weighted by the other player's
+ * reach); the iteration does not load its regrets or evaluate its terminals,
+ * and only applies the Stage-7 discount to its regret and average rows, so
+ * the iterates are bitwise those of prune = 0.  Thresholding makes such
+ * subtrees common. */
 typedef struct pcfr_solver_cfg {
     int32_t dtype;        /* PCFR_F32 or PCFR_F64 */
     int32_t variant;      /* PCFR_DCFR, PCFR_CFRPLUS or PCFR_PCFRPLUS */
     double alpha, beta, gamma;
     int32_t alternating;  /* 0 or 1 */
     int32_t suit_iso;     /* 0 or 1: lossless suit isomorphism at chance nodes */
+    double threshold;     /* dynamic thresholding: 0 (off) or thr0 in (0, 1/12) */
+    int32_t prune;        /* 0 or 1: skip subtrees no hand of either player reaches */
 } pcfr_solver_cfg;
 
 typedef struct pcfr_tree pcfr_tree;
@@ -234,6 +251,24 @@ int32_t pcfr_solver_free(pcfr_solver* s);
  * replayed; the iteration counter lives on the device. */
 int32_t pcfr_cfr_iterate(pcfr_solver* s, int32_t n);
 int32_t pcfr_synchronize(pcfr_solver* s);
+
+/* How pcfr_cfr_iterate runs the iterations of a solver or batch.
+ * PCFR_LAUNCH_GRAPH (the default): each iteration is a replay of the
+ * captured HIP graph of per-level launches.  PCFR_LAUNCH_PERSISTENT: one
+ * cooperative launch of a resident grid runs all n iterations, the level
+ * sweeps and terminals separated by grid barriers (the batching workload of
+ * many subgames in one persistent launch); for solvers whose subgames are
+ * played to showdown (no depth-limit leaves), with simultaneous updates and
+ * without suit isomorphism, else PCFR_E_UNSUPPORTED.  Both modes compute
+ * bitwise the same iterates; other calls (strategies, values,
+ * exploitability, autotuning, profiling) are unaffected. */
+enum { PCFR_LAUNCH_GRAPH = 0, PCFR_LAUNCH_PERSISTENT = 1 };
+int32_t pcfr_solver_set_launch(pcfr_solver* s, int32_t mode);
+
+/* Nodes (over all subgames) that the last iteration found unreachable and
+ * skipped, for a solver created with prune = 1 (else PCFR_E_STATE); with
+ * alternating updates, those of the second half-step.  Synchronises. */
+int32_t pcfr_solver_unreached_nodes(pcfr_solver* s, int64_t* n);
 
 /* Run n iterations like pcfr_cfr_iterate, but launch by launch with HIP
  * events around every kernel on the solver's stream, and return the summed
@@ -374,19 +409,22 @@ int32_t pcfr_leafnet_autotune(pcfr_leafnet* net, int32_t m, int32_t reps, double
  * PCFR_TILE_64x64_K2, PCFR_TILE_64x128_K2 (two 4-wave groups that split
  * the K loop and add their partial sums), or PCFR_TILE_64x64_P4,
  * PCFR_TILE_64x128_P4 (4 waves, global loads four K stages ahead instead
- * of two), or PCFR_TILE_DIRECT, PCFR_TILE_DIRECT_K2 (one wave per 64 x 64
- * output tile, two with _K2 splitting K, both operands read straight into
- * registers from copies in an MFMA-ready layout, no LDS stage; only for
+ * of two), or PCFR_TILE_DIRECT, PCFR_TILE_DIRECT_K2, PCFR_TILE_DIRECT_K4
+ * (one wave per 64 x 64 output tile, two or four with _K2 or _K4 splitting
+ * K, both operands read straight into registers from copies in an
+ * MFMA-ready layout, no LDS stage; only for
  * layers after the first whose input width is 1536, and every layer after a
  * direct layer must be direct too, since a direct layer's input is written
  * in that layout by the layer before).  The column count must divide the
  * layer's output width padded to 64; a tile that does not fit the layer
  * gives PCFR_E_INVALID_ARG.  Training steps run direct layers with the
- * default tile.  get returns the current choice. */
+ * default tile.  get returns the current choice.  Every tile spreads its
+ * workgroups over the GPU's XCDs so that each XCD's L2 serves one block of
+ * output rows x columns; that placement changes no arithmetic. */
 enum {
     PCFR_TILE_DEFAULT = -1, PCFR_TILE_64x64 = 0, PCFR_TILE_128x64 = 1, PCFR_TILE_64x128 = 2, PCFR_TILE_128x128 = 3,
     PCFR_TILE_64x64_K2 = 4, PCFR_TILE_64x128_K2 = 5, PCFR_TILE_64x64_P4 = 6, PCFR_TILE_64x128_P4 = 7,
-    PCFR_TILE_DIRECT = 8, PCFR_TILE_DIRECT_K2 = 9
+    PCFR_TILE_DIRECT = 8, PCFR_TILE_DIRECT_K2 = 9, PCFR_TILE_DIRECT_K4 = 10
 };
 int32_t pcfr_leafnet_set_tiles(pcfr_leafnet* net, const int32_t* tiles, int32_t count);
 int32_t pcfr_leafnet_get_tiles(pcfr_leafnet* net, int32_t* tiles, int32_t count);

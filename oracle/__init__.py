@@ -79,6 +79,7 @@ def lib():
             "ora_max_threads": (I, []),
             "ora_set_variant": (None, [P, I]),
             "ora_set_alternating": (None, [P, I]),
+            "ora_set_threshold": (None, [P, D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -220,13 +221,16 @@ class Solver:
     VARIANTS = {"dcfr": 0, "cfr+": 1, "pcfr+": 2}
 
     def __init__(self, tree: Tree, ranges, alpha=1.5, beta=0.0, gamma=2.0, support_only=False, variant="dcfr",
-                 alternating=False):
+                 alternating=False, threshold=0.0):
         self.tree = tree
         r = np.ascontiguousarray(ranges, dtype=np.float64).reshape(2, tree.nh)
         self._r = r
         self._h = lib().ora_solver_create(tree._h, _p(r), alpha, beta, gamma, int(support_only))
         lib().ora_set_variant(self._h, self.VARIANTS[variant])
         lib().ora_set_alternating(self._h, 1 if alternating else 0)
+        if not (0.0 <= threshold < 1.0 / 12):
+            raise ValueError("threshold must lie in [0, 1/12)")
+        lib().ora_set_threshold(self._h, float(threshold))
 
     def iterate(self, n: int, threads: int = 0):
         lib().ora_iterate(self._h, int(n), int(threads))
@@ -248,7 +252,7 @@ class Solver:
 
     def rows(self, which: str) -> np.ndarray:
         out = np.zeros((self.tree.n_rows, self.tree.nh), dtype=np.float64)
-        lib().ora_get_rows(self._h, 0 if which == "R" else 1, _p(out))
+        lib().ora_get_rows(self._h, {"R": 0, "S": 1, "M": 2, "V": 3, "r": 4}[which], _p(out))
         return out
 
     def set_rows(self, R, S, t):

@@ -172,3 +172,23 @@ def zero_sum_shift(ev: np.ndarray, reach_leaf: np.ndarray, card: int) -> float:
     e = float((r0 * m1 * ev[0]).sum() + (r1 * m0 * ev[1]).sum())
     z = float((r0 * m1).sum())
     return e / (2.0 * z) if z > 0 else 0.0
+
+
+def zero_sum_shifts(ev_rows: np.ndarray, reach_leaf: np.ndarray, cards) -> np.ndarray:
+    """zero_sum_shift for several next cards of one leaf at once: ev_rows
+    [k, 2, 1326] (row j after next card cards[j]), reach_leaf [2, 1326];
+    returns the k shifts.  The same sums as zero_sum_shift, with the
+    compatible masses of all k cards formed by one product per player."""
+    cards = np.asarray(cards)
+    keep = (_CC[:, 0][None, :] != cards[:, None]) & (_CC[:, 1][None, :] != cards[:, None])   # [k, 1326]
+    r0 = reach_leaf[0][None, :] * keep
+    r1 = reach_leaf[1][None, :] * keep
+    K = _compat()
+    m1 = r1 @ K          # [k, 1326]: M over player 1's reach without the card (K is symmetric)
+    m0 = r0 @ K
+    e = (r0 * m1 * ev_rows[:, 0]).sum(axis=1) + (r1 * m0 * ev_rows[:, 1]).sum(axis=1)
+    z = (r0 * m1).sum(axis=1)
+    out = np.zeros(len(cards))
+    pos = z > 0
+    out[pos] = e[pos] / (2.0 * z[pos])
+    return out

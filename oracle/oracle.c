@@ -610,16 +610,21 @@ enum { LEAF_EQUITY = 0, LEAF_TABLE = 1 };
  *         floored at zero; the average weights iteration t by t^2. */
 enum { V_DCFR = 0, V_CFRPLUS = 1, V_PCFRPLUS = 2 };
 
+/* Relative size below which an instantaneous regret counts as an exact tie. */
+#define TIE_REL 1e-10
+
 typedef struct {
     ogame* g;
     double alpha, beta, gamma;
     int variant;
     double rng[2][NCOMBO];
     double *R, *S, *sig, *rinst, *sadd, *pred;
+    double* cva;          /* per row and hand: the counterfactual value of the row's action (this half-step) */
     double cfv[2][NCOMBO];
     int64_t t;
     int support_only;
     int alternating;       /* 0: both players from the same strategies; 1: player 0, then player 1 */
+    double thr0;           /* dynamic threshold of iteration t: thr0 / sqrt(t); 0 = off */
     unsigned char* row_player;  /* [nrows]: the player acting at the row's node */
     unsigned char* tmask;  /* optional [2][nh]: traverser hands to evaluate (NULL = all) */
     int leaf_kind;
@@ -641,6 +646,7 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
     s->R = calloc(n, sizeof(double)); s->S = calloc(n, sizeof(double));
     s->sig = calloc(n, sizeof(double)); s->rinst = calloc(n, sizeof(double));
     s->sadd = calloc(n, sizeof(double));
+    s->cva = calloc(n, sizeof(double));
     s->pred = calloc(n, sizeof(double));
     s->row_player = calloc(g->nrows > 0 ? g->nrows : 1, 1);
     for (int i = 0; i < g->n; i++)
@@ -657,7 +663,7 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
 
 void ora_solver_free(osolver* s) {
     if (!s) return;
-    free(s->R); free(s->S); free(s->sig); free(s->rinst); free(s->sadd); free(s->pred);
+    free(s->R); free(s->S); free(s->sig); free(s->rinst); free(s->sadd); free(s->pred); free(s->cva);
     free(s->leaf_ev); free(s->leaf_slot); free(s->tmask); free(s->row_player); free(s);
 }
 
@@ -671,18 +677,36 @@ void ora_set_traverser_hands(osolver* s, const unsigned char* mask) {
     memcpy(s->tmask, mask, n);
 }
 
-/* Regret matching (eq. rm): positive part normalised, uniform if none. */
-static void regret_match(const double* R, double* out, int A, int nh, int h) {
+/* Threshold of iteration t (t >= 1): thr0 / sqrt(t). */
+static double threshold_at(const osolver* s, int64_t t) {
+    return s->thr0 > 0 && t > 0 ? s->thr0 / sqrt((double)t) : 0.0;
+}
+static const double* matched_regrets(const osolver* s, double* tmp);
+
+/* Regret matching (eq. rm): positive part normalised, uniform if none.
+ * With a threshold thr > 0 (dynamic thresholding, cited in Sec. 2): every
+ * action whose probability is below thr is set to 0 and the remaining ones
+ * are renormalised (the largest is at least 1/A > thr, so one stays). */
+static void regret_match(const double* R, double* out, int A, int nh, int h, double thr) {
     double den = 0;
     for (int a = 0; a < A; a++) { double x = R[(size_t)a * nh + h]; if (x > 0) den += x; }
     for (int a = 0; a < A; a++) {
         double x = R[(size_t)a * nh + h];
         out[(size_t)a * nh + h] = den > 0 ? (x > 0 ? x / den : 0.0) : 1.0 / A;
     }
+    if (thr > 0) {
+        double keep = 0;
+        for (int a = 0; a < A; a++) {
+            double* q = &out[(size_t)a * nh + h];
+            if (*q < thr) *q = 0.0;
+            keep += *q;
+        }
+        for (int a = 0; a < A; a++) out[(size_t)a * nh + h] /= keep;
+    }
 }
 
-static void strategy_rows(const ogame* g, const double* src, double* dst, int normalise_sum) {
-    /* normalise_sum = 0: regret matching of src; 1: src / sum(src), uniform if zero */
+static void strategy_rows(const ogame* g, const double* src, double* dst, int normalise_sum, double thr) {
+    /* normalise_sum = 0: regret matching of src (threshold thr); 1: src / sum(src), uniform if zero */
     for (int i = 0; i < g->n; i++) {
         const onode* o = &g->nd[i];
         if (o->type != T_DEC) continue;
@@ -690,7 +714,7 @@ static void strategy_rows(const ogame* g, const double* src, double* dst, int no
         const double* x = src + (size_t)o->rs * g->nh;
         double* y = dst + (size_t)o->rs * g->nh;
         for (int h = 0; h < g->nh; h++) {
-            if (!normalise_sum) { regret_match(x, y, A, g->nh, h); continue; }
+            if (!normalise_sum) { regret_match(x, y, A, g->nh, h, thr); continue; }
             double den = 0;
             for (int a = 0; a < A; a++) den += x[(size_t)a * g->nh + h];
             for (int a = 0; a < A; a++)
@@ -769,10 +793,12 @@ static double walk(osolver* s, int n, int i, int hi, int ho, double w) {
          * exactly tied get exactly zero regret whatever the summation order, so
          * regret matching does not flip on the sign of a rounding residue */
         double* ri = s->rinst + (size_t)o->rs * g->nh;
+        double* cv = s->cva + (size_t)o->rs * g->nh;
         for (int a = 0; a < A; a++) {
             double r = 0;
             for (int b = 0; b < A; b++) r += sg[(size_t)b * g->nh + hi] * (va[a] - va[b]);
             ri[(size_t)a * g->nh + hi] += w * r;
+            cv[(size_t)a * g->nh + hi] += w * va[a];
         }
         return v;
     }
@@ -817,6 +843,7 @@ static void own_reach(osolver* s, int n, int p, int h, double pi) {
 
 void ora_set_variant(osolver* s, int variant) { s->variant = variant; }
 void ora_set_alternating(osolver* s, int on) { s->alternating = on; }
+void ora_set_threshold(osolver* s, double thr0) { s->thr0 = thr0; }
 
 /* Regrets the next strategy is matched on: R, or R + m for PCFR+. */
 static const double* matched_regrets(const osolver* s, double* tmp) {
@@ -852,9 +879,10 @@ static void half_step(osolver* s, int upd, double t) {
     double dpos = ta / (ta + 1.0), dneg = tb / (tb + 1.0);
     double davg = pow(t / (t + 1.0), s->gamma);
     size_t n = (size_t)g->nrows * nh;
-    strategy_rows(g, matched_regrets(s, s->rinst), s->sig, 0);
+    strategy_rows(g, matched_regrets(s, s->rinst), s->sig, 0, threshold_at(s, (int64_t)t));
     memset(s->rinst, 0, n * sizeof(double));
     memset(s->sadd, 0, n * sizeof(double));
+    memset(s->cva, 0, n * sizeof(double));
     for (int i = 0; i < 2; i++) {
         if (upd >= 0 && i != upd) continue;
         int op = 1 - i;
@@ -883,6 +911,28 @@ static void half_step(osolver* s, int upd, double t) {
         #pragma omp parallel for schedule(dynamic)
         for (int h = 0; h < nh; h++)
             if (g->hvalid[h]) own_reach(s, 0, p, h, s->rng[p][h]);
+    }
+    /* Ties: an information set's instantaneous regret whose magnitude is at
+     * most TIE_REL of the largest counterfactual value of its actions is an
+     * exact tie (zero).  Regrets that vanish in exact arithmetic come out of
+     * any summation order as residues of either sign, and regret matching
+     * would follow that sign. */
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < g->n; i++) {
+        const onode* o = &g->nd[i];
+        if (o->type != T_DEC || (upd >= 0 && o->player != upd)) continue;
+        const int A = o->n_child;
+        for (int h = 0; h < nh; h++) {
+            double mx = 0;
+            for (int a = 0; a < A; a++) {
+                const double c = fabs(s->cva[((size_t)o->rs + a) * nh + h]);
+                if (c > mx) mx = c;
+            }
+            for (int a = 0; a < A; a++) {
+                double* ri = &s->rinst[((size_t)o->rs + a) * nh + h];
+                if (fabs(*ri) <= TIE_REL * mx) *ri = 0.0;
+            }
+        }
     }
     #pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; k++) {
@@ -923,7 +973,7 @@ int ora_get_strategy(const osolver* s, int node, int which, double* out) {
             for (int a = 0; a < A; a++)
                 cur[a] = src[(size_t)a * nh + h] + (s->variant == V_PCFRPLUS ? s->pred[((size_t)o->rs + a) * nh + h] : 0.0);
             double sg[64];
-            regret_match(cur, sg, A, 1, 0);
+            regret_match(cur, sg, A, 1, 0, threshold_at(s, s->t + 1));
             for (int a = 0; a < A; a++) out[(size_t)a * nh + h] = sg[a];
             continue;
         }
@@ -934,9 +984,13 @@ int ora_get_strategy(const osolver* s, int node, int which, double* out) {
     return 0;
 }
 
+/* which: 0 = cumulative regrets R, 1 = average-strategy sums S, 2 = the
+ * last instantaneous regrets (PCFR+'s prediction; zero for other rules),
+ * 3 = the last half-step's action values, 4 = its instantaneous regrets. */
 void ora_get_rows(const osolver* s, int which, double* out) {
     size_t n = (size_t)s->g->nrows * s->g->nh;
-    memcpy(out, which == 0 ? s->R : s->S, n * sizeof(double));
+    const double* src = which == 0 ? s->R : which == 1 ? s->S : which == 2 ? s->pred : which == 3 ? s->cva : s->rinst;
+    memcpy(out, src, n * sizeof(double));
 }
 
 void ora_set_rows(osolver* s, const double* R, const double* S, int64_t t) {
@@ -1021,7 +1075,7 @@ static double value_rec(osolver* s, const double* sbar, int n, int i, int hi, co
 static double* avg_strategy_all(const osolver* s) {
     size_t n = (size_t)s->g->nrows * s->g->nh;
     double* sb = malloc(n * sizeof(double));
-    strategy_rows(s->g, s->S, sb, 1);
+    strategy_rows(s->g, s->S, sb, 1, 0.0);
     return sb;
 }
 
@@ -1124,8 +1178,10 @@ static void reach_rec(const ogame* g, const double* sig, int n, const double* r0
 void ora_reach_current(const osolver* s, double* out) {
     size_t n = (size_t)s->g->nrows * s->g->nh;
     double* sig = malloc(n * sizeof(double));
-    strategy_rows(s->g, s->R, sig, 0);
+    double* tmp = malloc(n * sizeof(double));
+    strategy_rows(s->g, matched_regrets(s, tmp), sig, 0, threshold_at(s, s->t + 1));
     reach_rec(s->g, sig, 0, s->rng[0], s->rng[1], out);
+    free(tmp);
     free(sig);
 }
 

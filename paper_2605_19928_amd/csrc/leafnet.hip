@@ -59,6 +59,31 @@ __host__ __device__ __forceinline__ int64_t swz_index(int64_t r, int64_t k, int6
     return ((((r >> 5) * (K >> 4) + (k >> 4)) * 64) + (r & 31) + 32 * ((k >> 3) & 1)) * 8 + (k & 7);
 }
 
+// Output tile of workgroup `lin` of a 1-D grid over an mt x nt tile grid.
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup i to XCD
+// i mod 8), and each XCD has its own L2.  With sm > 0 the tile grid is cut
+// into sm row parts x (8 / sm) column parts and XCD x takes part x, its
+// tiles in column-major order, so that each XCD's L2 holds only its part's
+// operand rows and columns; the grid is 8 x the largest part, and a
+// workgroup past its part's tile count has no tile.  sm = 0: row-major
+// order over the whole grid (as a 2-D grid launch).  The mapping changes no
+// tile's arithmetic.
+__device__ __forceinline__ bool map_tile(int lin, int mt, int nt, int sm, int& tm, int& tn) {
+    if (sm == 0) {
+        tm = lin / nt;
+        tn = lin - tm * nt;
+        return tm < mt;
+    }
+    const int sn = 8 / sm, x = lin & 7, j = lin >> 3;
+    const int xm = x / sn, xn = x - xm * sn;
+    const int m_lo = xm * mt / sm, cm = (xm + 1) * mt / sm - m_lo;
+    const int n_lo = xn * nt / sn, cn = (xn + 1) * nt / sn - n_lo;
+    if (j >= cm * cn) return false;
+    tm = m_lo + j % cm;
+    tn = n_lo + j / cm;
+    return true;
+}
+
 // Rows of A past M (the last row tile of a 128-row tiling) are read as row
 // M - 1 and their outputs are not stored.
 //
@@ -77,7 +102,7 @@ template <int BM, int BN, int EPI, int KS = 1, int PF = 2>
 __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
                                                       const uint16_t* __restrict__ B, int ldb, int M, int K,
                                                       const float* __restrict__ bias, void* __restrict__ Cout,
-                                                      int ldc, const uint16_t* __restrict__ mask) {
+                                                      int ldc, const uint16_t* __restrict__ mask, int nt, int sm) {
     constexpr int BK = 64, LDK = BK + 8;
     constexpr int TM = BM / 64, TN = BN / 64;
     constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;
@@ -86,7 +111,9 @@ __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict
     const int grp = KS == 1 ? 0 : (int)(threadIdx.x >> 8);
     const int tid = KS == 1 ? (int)threadIdx.x : (int)(threadIdx.x & 255);
     const int lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
-    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    int tmi, tni;
+    if (!map_tile((int)blockIdx.x, (M + BM - 1) / BM, nt, sm, tmi, tni)) return;
+    const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
     // this group's K stages: [sbeg, sbeg + ng); every group loops `trips` times
     const int nk = K / BK;
     const int trips = KS == 1 ? nk : (nk + KS - 1) / KS;
@@ -281,18 +308,21 @@ __global__ __launch_bounds__(256 * KS) void k_gemm_nt(const uint16_t* __restrict
 // what a 32 x 32 wave tile needs.  Each operand block is one coalesced 1 KB
 // load straight into registers, prefetched PF k-blocks ahead in a ring of
 // PF + 1 slots; the loads are unconditional (clamped to the last block) so
-// the compiler waits for exactly the slot it needs.  With KSPLIT = 2 two
-// waves take halves of K and add their sums through LDS (wave 0 adds wave
-// 1's).  K = 16 KBT is a compile-time constant; M and N are multiples of 64.
+// the compiler waits for exactly the slot it needs.  With KSPLIT = 2 or 4
+// that many waves take equal shares of K and add their sums through LDS
+// (wave 0 adds the others' in wave order).  K = 16 KBT is a compile-time
+// constant; M and N are multiples of 64.
 template <int EPI, int KSPLIT, int PF, int KBT>
 __global__ __launch_bounds__(64 * KSPLIT) void k_gemm_direct(const uint16_t* __restrict__ A,
                                                             const uint16_t* __restrict__ B, int M,
                                                             const float* __restrict__ bias, void* __restrict__ Cout,
-                                                            int ldc) {
+                                                            int ldc, int nt, int sm) {
     constexpr int D = PF + 1, KB = KBT, per = KBT / KSPLIT;
     static_assert(KBT % KSPLIT == 0 && per > PF, "k blocks per wave");
     const int lane = threadIdx.x & 63, grp = KSPLIT == 1 ? 0 : (int)(threadIdx.x >> 6);
-    const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+    int tmi, tni;
+    if (!map_tile((int)blockIdx.x, M / 64, nt, sm, tmi, tni)) return;
+    const int64_t m0 = (int64_t)tmi * 64, n0 = (int64_t)tni * 64;
     const int64_t kb0 = (int64_t)grp * per;
     const v8bf* a0 = reinterpret_cast<const v8bf*>(A) + ((m0 >> 5) * KB + kb0) * 64 + lane;
     const v8bf* a1 = a0 + (int64_t)KB * 64;
@@ -333,23 +363,26 @@ __global__ __launch_bounds__(64 * KSPLIT) void k_gemm_direct(const uint16_t* __r
     }
 #undef LD_BLOCKS
     if constexpr (KSPLIT > 1) {
-        __shared__ float xr[4 * 16 * 64];
-        if (grp == 1) {
+        // waves 1.. hand their partial sums to wave 0, which adds them in wave order
+        __shared__ float xr[KSPLIT - 1][4 * 16 * 64];
+        if (grp > 0) {
 #pragma unroll
             for (int i = 0; i < 2; i++)
 #pragma unroll
                 for (int j = 0; j < 2; j++)
 #pragma unroll
-                    for (int r = 0; r < 16; r++) xr[((i * 2 + j) * 16 + r) * 64 + lane] = acc[i][j][r];
+                    for (int r = 0; r < 16; r++) xr[grp - 1][((i * 2 + j) * 16 + r) * 64 + lane] = acc[i][j][r];
         }
         __syncthreads();
         if (grp != 0) return;
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int g = 0; g < KSPLIT - 1; g++)
 #pragma unroll
-            for (int j = 0; j < 2; j++)
+            for (int i = 0; i < 2; i++)
 #pragma unroll
-                for (int r = 0; r < 16; r++) acc[i][j][r] += xr[((i * 2 + j) * 16 + r) * 64 + lane];
+                for (int j = 0; j < 2; j++)
+#pragma unroll
+                    for (int r = 0; r < 16; r++) acc[i][j][r] += xr[g][((i * 2 + j) * 16 + r) * 64 + lane];
     }
 #pragma unroll
     for (int i = 0; i < 2; i++)
@@ -502,10 +535,27 @@ static int32_t hipchk(hipError_t e, const char* what) {
     } while (0)
 
 static int64_t r64(int64_t x) { return (x + 63) / 64 * 64; }
+
+// XCD split of an mt x nt tile grid for map_tile: the row-part count sm
+// (1, 2, 4 or 8; 0 = no split for grids too small to share) that minimises
+// the operand rows plus columns one XCD touches, and the grid it needs.
+static void tile_grid(int64_t mt, int64_t nt, int64_t BM, int64_t BN, int* sm, int64_t* grid) {
+    *sm = 0;
+    *grid = mt * nt;
+    if (mt * nt < 32) return;
+    int64_t best = -1;
+    for (int s = 1; s <= 8; s *= 2) {
+        const int sn = 8 / s;
+        if (mt < s || nt < sn) continue;
+        const int64_t cm = (mt + s - 1) / s, cn = (nt + sn - 1) / sn;
+        const int64_t foot = cm * BM + cn * BN;
+        if (best < 0 || foot < best) { best = foot; *sm = s; *grid = 8 * cm * cn; }
+    }
+}
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool gemm_tile_valid(int tile, int64_t N) {
-    static const int bn[kGemmTiles] = {64, 64, 128, 128, 64, 128, 64, 128, 64, 64};
+    static const int bn[kGemmTiles] = {64, 64, 128, 128, 64, 128, 64, 128, 64, 64, 64};
     return tile >= 0 && tile < kGemmTiles && N % bn[tile] == 0;
 }
 
@@ -523,23 +573,25 @@ bool gemm_tile_valid_layer(int tile, int l, int64_t N, int64_t K) {
 static int32_t launch_gemm_direct(hipStream_t st, int tile, const uint16_t* A, const uint16_t* B, int64_t M,
                                   int64_t N, int64_t K, const float* bias, void* C, int ldc, bool relu_swz) {
     if (K != 16 * kDirectKB) { set_error("direct tiles need an input width of 1536"); return PCFR_E_INVALID_ARG; }
-    const dim3 grid((unsigned)(N / 64), (unsigned)(M / 64));
-    const int ks = tile == GEMM_DIRECT_K2 ? 2 : 1;
+    int sm;
+    int64_t ng;
+    tile_grid(M / 64, N / 64, 64, 64, &sm, &ng);
+    const dim3 grid((unsigned)ng);
+    const int nt = (int)(N / 64);
+    const int ks = tile == GEMM_DIRECT_K4 ? 4 : tile == GEMM_DIRECT_K2 ? 2 : 1;
+#define LN_DIRECT(E, KSv)                                                                                  \
+    hipLaunchKernelGGL((k_gemm_direct<E, KSv, kDirectPF, kDirectKB>), grid, dim3(64 * KSv), 0, st, A, B, (int)M, \
+                       bias, C, ldc, nt, sm)
     if (relu_swz) {
-        if (ks == 1)
-            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_RELU_SWZ, 1, kDirectPF, kDirectKB>), grid, dim3(64), 0, st, A,
-                               B, (int)M, bias, C, ldc);
-        else
-            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_RELU_SWZ, 2, kDirectPF, kDirectKB>), grid, dim3(128), 0, st,
-                               A, B, (int)M, bias, C, ldc);
+        if (ks == 1) LN_DIRECT(EPI_BIAS_RELU_SWZ, 1);
+        else if (ks == 2) LN_DIRECT(EPI_BIAS_RELU_SWZ, 2);
+        else LN_DIRECT(EPI_BIAS_RELU_SWZ, 4);
     } else {
-        if (ks == 1)
-            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_F32, 1, kDirectPF, kDirectKB>), grid, dim3(64), 0, st, A, B,
-                               (int)M, bias, C, ldc);
-        else
-            hipLaunchKernelGGL((k_gemm_direct<EPI_BIAS_F32, 2, kDirectPF, kDirectKB>), grid, dim3(128), 0, st, A, B,
-                               (int)M, bias, C, ldc);
+        if (ks == 1) LN_DIRECT(EPI_BIAS_F32, 1);
+        else if (ks == 2) LN_DIRECT(EPI_BIAS_F32, 2);
+        else LN_DIRECT(EPI_BIAS_F32, 4);
     }
+#undef LN_DIRECT
     return hipchk(hipGetLastError(), "direct gemm launch");
 }
 
@@ -555,9 +607,13 @@ int32_t launch_gemm(hipStream_t st, int epi, const uint16_t* A, int lda, const u
     }
     if (!gemm_tile_valid(tile, N)) { set_error("GEMM tile does not divide N"); return PCFR_E_INVALID_ARG; }
 #define LN_GEMM(BMv, BNv, E, KSv, PFv)                                                                   \
-    hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E, KSv, PFv>),                                              \
-                       dim3((unsigned)(N / BNv), (unsigned)((M + BMv - 1) / BMv)), dim3(256 * KSv), 0, st, \
-                       A, lda, B, ldb, (int)M, (int)K, bias, C, ldc, mask)
+    do {                                                                                                 \
+        int sm_;                                                                                         \
+        int64_t ng_;                                                                                     \
+        tile_grid((M + BMv - 1) / BMv, N / BNv, BMv, BNv, &sm_, &ng_);                                    \
+        hipLaunchKernelGGL((k_gemm_nt<BMv, BNv, E, KSv, PFv>), dim3((unsigned)ng_), dim3(256 * KSv), 0, st, \
+                           A, lda, B, ldb, (int)M, (int)K, bias, C, ldc, mask, (int)(N / BNv), sm_);      \
+    } while (0)
 #define LN_EPI(BMv, BNv, KSv, PFv)                                                       \
     switch (epi) {                                                                       \
         case EPI_BIAS_F32: LN_GEMM(BMv, BNv, EPI_BIAS_F32, KSv, PFv); break;             \

@@ -26,15 +26,18 @@ struct LeafNetPlan {
 // GEMM workgroup tiles (rows x columns of C); 4 waves, each a quarter tile;
 // the _K2 variants run two such groups that split K (8 waves).  The DIRECT
 // tiles read both operands in the swizzled layout with no LDS stage, one
-// wave (two with _K2) per 64 x 64 tile; a layer using them needs its input
-// written swizzled by the layer before, so never the first layer.
+// wave (two with _K2, four with _K4, splitting K) per 64 x 64 tile; a layer
+// using them needs its input written swizzled by the layer before, so never
+// the first layer.
 enum {
     GEMM_64x64 = 0, GEMM_128x64 = 1, GEMM_64x128 = 2, GEMM_128x128 = 3, GEMM_64x64_K2 = 4, GEMM_64x128_K2 = 5,
-    GEMM_64x64_P4 = 6, GEMM_64x128_P4 = 7, GEMM_DIRECT = 8, GEMM_DIRECT_K2 = 9,
-    kGemmTiles = 10
+    GEMM_64x64_P4 = 6, GEMM_64x128_P4 = 7, GEMM_DIRECT = 8, GEMM_DIRECT_K2 = 9, GEMM_DIRECT_K4 = 10,
+    kGemmTiles = 11
 };
 bool gemm_tile_valid(int tile, int64_t N);
-inline bool gemm_tile_direct(int tile) { return tile == GEMM_DIRECT || tile == GEMM_DIRECT_K2; }
+inline bool gemm_tile_direct(int tile) {
+    return tile == GEMM_DIRECT || tile == GEMM_DIRECT_K2 || tile == GEMM_DIRECT_K4;
+}
 // tile usable for forward layer l of output width N and input width K
 bool gemm_tile_valid_layer(int tile, int l, int64_t N, int64_t K);
 

@@ -22,6 +22,7 @@
 //   backward, level by level to the root (Stages 6-7): eq. backward at the
 //     actor's nodes, plain sums at the opponent's, 1/K-weighted sums at
 //     chance nodes, and the regret update with DCFR discounting.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -73,12 +74,14 @@ struct IterState {
     int32_t variant, pad;
     double dpos, dneg, wadd, wmul;
     double alpha, beta, gamma;    // set once at creation
+    double thr0, thr;             // dynamic threshold: thr0 (set at creation), thr = thr0 / sqrt(t)
 };
 
 constexpr int kBlock = 256;       // terminal, leaf and helper kernels
 constexpr int kFuseHands = 64;    // hands per workgroup of the level-fused sweeps
 constexpr int kSweepMaxBlock = 512;
 constexpr int kSdHeader = 64;     // card-list offsets per board table (53 used)
+constexpr double kTieRel = 1e-10;  // instantaneous regrets this small against the actions' values are ties
 
 // ------------------------------------------------------------ vector I/O
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
@@ -135,6 +138,7 @@ __device__ void begin_iteration(IterState* st) {
     int64_t t = st->t + 1;
     st->t = t;
     double td = (double)t;
+    st->thr = st->thr0 > 0.0 ? st->thr0 / sqrt(td) : 0.0;
     if (st->variant == PCFR_DCFR) {
         double ta = pow(td, st->alpha), tb = pow(td, st->beta);
         st->dpos = ta / (ta + 1.0);
@@ -159,12 +163,62 @@ __device__ __forceinline__ T strat(T x, T den, T inv_a) {
     return den > T(0) ? x / den : inv_a;
 }
 
+// Dynamic thresholding: probabilities below thr become 0 and the others are
+// renormalised (the largest probability is at least 1/A > thr, so one stays).
+template <typename T, int A, int NH>
+__device__ __forceinline__ void drop_below(T (&sg)[A][NH], T thr) {
+    if (!(thr > T(0))) return;
+#pragma unroll
+    for (int j = 0; j < NH; j++) {
+        T keep = T(0);
+#pragma unroll
+        for (int a = 0; a < A; a++) {
+            if (sg[a][j] < thr) sg[a][j] = T(0);
+            keep += sg[a][j];
+        }
+#pragma unroll
+        for (int a = 0; a < A; a++) sg[a][j] /= keep;
+    }
+}
+
+// Regret-based pruning flags: nzs[slot] != 0 when some hand has nonzero
+// reach in that reach slot this iteration.  A node whose two slots are both
+// unflagged is reached by no hand of either player.
+__device__ __forceinline__ bool node_dead(const int32_t* nzs, const DNode& nd) {
+    return nzs && nzs[nd.slot[0]] == 0 && nzs[nd.slot[1]] == 0;
+}
+
+// Sets nzs[slot] for the lanes whose rows hold a nonzero value, one atomic per
+// distinct slot among those lanes of the wave (a wave can span two nodes).
+__device__ __forceinline__ void flag_nonzero(int32_t* nzs, int slot, bool nz) {
+    bool pending = nz;
+    while (true) {
+        const unsigned long long m = __ballot(pending);
+        if (!m) break;
+        const int lead = __ffsll(m) - 1;
+        const int ls = __shfl(slot, lead);
+        if (pending && slot == ls) {
+            if ((int)__lane_id() == lead) atomicOr(&nzs[ls], 1);
+            pending = false;
+        }
+    }
+}
+
 // Only the actor's reach is written: child a's actor slot gets the actor's
 // reach times the probability of a; the other player's slot is shared.
 template <typename T, int MODE, int A, int NH>
 __device__ __forceinline__ void fwd_decision(const DNode& nd, int h, int Hp, int cbase, const T* __restrict__ R,
                                              const T* __restrict__ S, const T* __restrict__ Mp,
-                                             T* __restrict__ reach) {
+                                             T* __restrict__ reach, const IterState* __restrict__ st,
+                                             int32_t* __restrict__ nzs, bool skip) {
+    T* dst = reach + (int64_t)(cbase + nd.rs) * Hp + h;
+    if (skip && node_dead(nzs, nd)) {
+        // unreachable: the children's actor reach is zero; their flags stay clear
+        const VN<T, NH> z = {};
+#pragma unroll
+        for (int a = 0; a < A; a++) stv<NH>(dst + (int64_t)a * Hp, z);
+        return;
+    }
     // (a select, not nd.slot[player]: a dynamic index would move nd to memory)
     const VN<T, NH> rp = ldv<NH>(reach + (int64_t)(nd.player ? nd.slot[1] : nd.slot[0]) * Hp + h);
     const T* src = (MODE == MODE_ITER ? R : S) + (int64_t)nd.rs * Hp + h;
@@ -185,23 +239,34 @@ __device__ __forceinline__ void fwd_decision(const DNode& nd, int h, int Hp, int
 #pragma unroll
         for (int j = 0; j < NH; j++) den[j] += (MODE == MODE_ITER) ? (x[a].e[j] > T(0) ? x[a].e[j] : T(0)) : x[a].e[j];
     const T inv_a = T(1) / T(A);
-    T* dst = reach + (int64_t)(cbase + nd.rs) * Hp + h;
+    T sg[A][NH];
+#pragma unroll
+    for (int a = 0; a < A; a++)
+#pragma unroll
+        for (int j = 0; j < NH; j++) sg[a][j] = strat<T, MODE>(x[a].e[j], den[j], inv_a);
+    if (MODE == MODE_ITER && st) drop_below<T, A, NH>(sg, (T)st->thr);
 #pragma unroll
     for (int a = 0; a < A; a++) {
         VN<T, NH> q;
+        bool nz = false;
 #pragma unroll
-        for (int j = 0; j < NH; j++) q.e[j] = rp.e[j] * strat<T, MODE>(x[a].e[j], den[j], inv_a);
+        for (int j = 0; j < NH; j++) {
+            q.e[j] = rp.e[j] * sg[a][j];
+            nz |= q.e[j] != T(0);
+        }
         stv<NH>(dst + (int64_t)a * Hp, q);
+        if (nzs) flag_nonzero(nzs, cbase + nd.rs + a, nz);
     }
 }
 
 template <typename T, int MODE, int MAXA, int NH>
 __device__ __forceinline__ void fwd_node(const DNode& nd, int h, int Hp, int cbase, const T* __restrict__ R,
-                                         const T* __restrict__ S, const T* __restrict__ Mp, T* __restrict__ reach) {
+                                         const T* __restrict__ S, const T* __restrict__ Mp, T* __restrict__ reach,
+                                         const IterState* __restrict__ st, int32_t* __restrict__ nzs, bool skip) {
     switch (nd.n_child) {
 #define PCFR_FWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) fwd_decision<T, MODE, A, NH>(nd, h, Hp, cbase, R, S, Mp, reach); \
+        if constexpr (A <= MAXA) fwd_decision<T, MODE, A, NH>(nd, h, Hp, cbase, R, S, Mp, reach, st, nzs, skip); \
         break;
         PCFR_FWD_CASE(1) PCFR_FWD_CASE(2) PCFR_FWD_CASE(3) PCFR_FWD_CASE(4) PCFR_FWD_CASE(5) PCFR_FWD_CASE(6)
         PCFR_FWD_CASE(7) PCFR_FWD_CASE(8) PCFR_FWD_CASE(9) PCFR_FWD_CASE(10) PCFR_FWD_CASE(11) PCFR_FWD_CASE(12)
@@ -217,13 +282,14 @@ template <typename T, int MODE, int MAXA>
 __global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restrict__ level, int count, int Hp,
                                                             int cbase, const T* __restrict__ R,
                                                             const T* __restrict__ S, const T* __restrict__ Mp,
-                                                            T* __restrict__ reach, IterState* begin) {
+                                                            T* __restrict__ reach, IterState* begin,
+                                                            const IterState* __restrict__ st, int32_t* __restrict__ nzs) {
     if (begin && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin);
     const int groups = Hp >> 2;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
-    fwd_node<T, MODE, MAXA, 4>(level[k], (int)(gid - k * groups) * 4, Hp, cbase, R, S, Mp, reach);
+    fwd_node<T, MODE, MAXA, 4>(level[k], (int)(gid - k * groups) * 4, Hp, cbase, R, S, Mp, reach, st, nzs, true);
 }
 
 // ------------------------------------------------------------ backward
@@ -235,7 +301,9 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
                                              T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
                                              T* __restrict__ cfv, const IterState* st,
                                              const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
-                                             int upd) {
+                                             int upd, bool dead) {
+    // dead: no hand of either player reaches the node; its children's values
+    // and its own reach are zero, so they are not loaded (regret-based pruning)
     using V = VN<T, NH>;
     const int p = nd.player, o = 1 - p;
     V x[A];
@@ -250,7 +318,8 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         if constexpr (EARLY && MODE == MODE_ITER) {
 #pragma unroll
             for (int a = 0; a < A; a++) s_early[a] = ldv<NH>(S + (int64_t)(nd.rs + a) * Hp + h);
-            rp_early = ldv<NH>(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
+            if (dead) rp_early = V{};
+            else rp_early = ldv<NH>(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
         }
         if (MODE == MODE_ITER && Mp) {
             // the strategy of this iteration matched R + m; R itself is read again below
@@ -274,6 +343,7 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         for (int a = 0; a < A; a++)
 #pragma unroll
             for (int j = 0; j < NH; j++) sg[a][j] = strat<T, MODE>(x[a].e[j], den[j], inv_a);
+        if (MODE == MODE_ITER) drop_below<T, A, NH>(sg, (T)st->thr);
     }
     // children's values, read once
     V c[A];
@@ -281,8 +351,12 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
 #pragma unroll
     for (int a = 0; a < A; a++) {
         const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
-        c[a] = ldv<NH>(cc + (int64_t)p * Hp + h);
-        const V d = ldv<NH>(cc + (int64_t)o * Hp + h);
+        V d = {};
+        if (dead) c[a] = V{};
+        else {
+            c[a] = ldv<NH>(cc + (int64_t)p * Hp + h);
+            d = ldv<NH>(cc + (int64_t)o * Hp + h);
+        }
 #pragma unroll
         for (int j = 0; j < NH; j++) {
             vo.e[j] += d.e[j];
@@ -306,12 +380,25 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         const T dpos = (T)st->dpos, dneg = (T)st->dneg, wadd = (T)st->wadd, wmul = (T)st->wmul;
         V rp;
         if constexpr (EARLY) rp = rp_early;
+        else if (dead) rp = V{};
         else rp = ldv<NH>(reach + (int64_t)(p ? nd.slot[1] : nd.slot[0]) * Hp + h);
         if (nd.dead != 0xffff) {
             const uint16_t* hc = hcards + (int64_t)nd.sub * Hp + h;
 #pragma unroll
             for (int j = 0; j < NH; j++)
                 if (!hand_alive(hc[j], nd.dead)) rp.e[j] = T(0);
+        }
+        // ties: an instantaneous regret of at most kTieRel of the largest
+        // action value of the information set is an exact tie (zero), since
+        // regrets that vanish in exact arithmetic leave rounding residues of
+        // either sign, which regret matching would follow
+        T tie[NH];
+#pragma unroll
+        for (int j = 0; j < NH; j++) {
+            T mx = T(0);
+#pragma unroll
+            for (int a = 0; a < A; a++) mx = fmax(mx, fabs(c[a].e[j]));
+            tie[j] = T(kTieRel) * mx;
         }
 #pragma unroll
         for (int a = 0; a < A; a++) {
@@ -329,7 +416,7 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
                 T ia = T(0);
 #pragma unroll
                 for (int b = 0; b < A; b++) ia += sg[b][j] * (c[a].e[j] - c[b].e[j]);
-                inst.e[j] = ia;
+                inst.e[j] = fabs(ia) <= tie[j] ? T(0) : ia;
                 T r = r0.e[j] + inst.e[j];
                 y.e[j] = r * (r > T(0) ? dpos : dneg);
                 sv.e[j] = (sv.e[j] + wadd * (rp.e[j] * sg[a][j])) * wmul;
@@ -355,9 +442,16 @@ template <typename T, int MODE, int MAXA, int NH, bool EARLY>
 __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __restrict__ R, T* __restrict__ S,
                                          T* __restrict__ Mp, const T* __restrict__ reach, T* __restrict__ cfv,
                                          const IterState* __restrict__ st, const uint16_t* __restrict__ hcards,
-                                         T* __restrict__ root_dst, int upd, IsoTabs iso) {
+                                         T* __restrict__ root_dst, int upd, IsoTabs iso, const int32_t* __restrict__ nzs) {
     using V = VN<T, NH>;
     const int64_t n = nd.id;
+    const bool dead = MODE == MODE_ITER && node_dead(nzs, nd);
+    if (dead && nd.type == PCFR_NODE_CHANCE) {
+        T* me = cfv + n * 2 * Hp;
+        stv<NH>(me + h, V{});
+        stv<NH>(me + Hp + h, V{});
+        return;
+    }
     if (nd.type == PCFR_NODE_CHANCE && nd.pad) {
         // some children solved through a suit-isomorphic representative:
         // v(h | pi c) = v(pi^-1 h | c); children added in their order
@@ -424,7 +518,7 @@ __device__ __forceinline__ void bwd_node(const DNode& nd, int h, int Hp, T* __re
     switch (nd.n_child) {
 #define PCFR_BWD_CASE(A) \
     case A:              \
-        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, NH, EARLY && (sizeof(T) == 4 || A <= 8)>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst, upd); \
+        if constexpr (A <= MAXA) bwd_decision<T, MODE, A, NH, EARLY && (sizeof(T) == 4 || A <= 8)>(nd, n, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst, upd, dead); \
         break;
         PCFR_BWD_CASE(1) PCFR_BWD_CASE(2) PCFR_BWD_CASE(3) PCFR_BWD_CASE(4) PCFR_BWD_CASE(5) PCFR_BWD_CASE(6)
         PCFR_BWD_CASE(7) PCFR_BWD_CASE(8) PCFR_BWD_CASE(9) PCFR_BWD_CASE(10) PCFR_BWD_CASE(11) PCFR_BWD_CASE(12)
@@ -443,13 +537,14 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_backward(const DNode* __rest
                                                              const T* __restrict__ reach, T* __restrict__ cfv,
                                                              const IterState* __restrict__ st,
                                                              const uint16_t* __restrict__ hcards,
-                                                             T* __restrict__ root_dst, int upd, IsoTabs iso) {
+                                                             T* __restrict__ root_dst, int upd, IsoTabs iso,
+                                                             const int32_t* __restrict__ nzs) {
     const int groups = Hp >> 2;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t k = gid / groups;
     if (k >= count) return;
     bwd_node<T, MODE, MAXA, 4, false>(level[k], (int)(gid - k * groups) * 4, Hp, R, S, Mp, reach, cfv, st, hcards,
-                                      root_dst, upd, iso);
+                                      root_dst, upd, iso, nzs);
 }
 
 // Level-fused sweeps for runs of levels too small to fill the GPU.  A node's
@@ -473,14 +568,20 @@ __global__ __launch_bounds__(kFuseBlock) void k_forward_fused(const DNode* __res
                                                               const int64_t* __restrict__ lvl_off, int l0, int l1,
                                                               int Hp, int cbase, const T* __restrict__ R,
                                                               const T* __restrict__ S, const T* __restrict__ Mp,
-                                                              T* __restrict__ reach, IterState* begin) {
+                                                              T* __restrict__ reach, IterState* begin,
+                                                              const IterState* __restrict__ st,
+                                                              int32_t* __restrict__ nzs) {
     if (begin && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin);
     const int h = blockIdx.x * kFuseHands + (int)(threadIdx.x & 63), lane = fuse_lane();
+    // The pruning flags of a node's slots are set by every workgroup of this
+    // launch (each owns a slice of hands), so they are incomplete here: the
+    // fused levels set flags for later launches but skip nothing (an
+    // unreachable node's rows are zero and come out zero anyway).
     for (int l = l0; l < l1; l++) {
         if (l > l0) __syncthreads();
         const int64_t e = lvl_off[l + 1];
         for (int64_t k = lvl_off[l] + lane; k < e; k += kFuseWaves)
-            fwd_node<T, MODE, MAXA, 1>(rec[k], h, Hp, cbase, R, S, Mp, reach);
+            fwd_node<T, MODE, MAXA, 1>(rec[k], h, Hp, cbase, R, S, Mp, reach, st, nzs, false);
     }
 }
 
@@ -493,14 +594,15 @@ __global__ __launch_bounds__(kFuseBlock) void k_backward_fused(const DNode* __re
                                                                const T* __restrict__ reach, T* __restrict__ cfv,
                                                                const IterState* __restrict__ st,
                                                                const uint16_t* __restrict__ hcards,
-                                                               T* __restrict__ root_dst, int upd, IsoTabs iso) {
+                                                               T* __restrict__ root_dst, int upd, IsoTabs iso,
+                                                               const int32_t* __restrict__ nzs) {
     const int h = blockIdx.x * kFuseHands + (int)(threadIdx.x & 63), lane = fuse_lane();
     for (int l = l_hi - 1; l >= l_lo; l--) {
         if (l < l_hi - 1) __syncthreads();
         const int64_t e = lvl_off[l + 1];
         for (int64_t k = lvl_off[l] + lane; k < e; k += kFuseWaves)
             bwd_node<T, MODE, MAXA, 1, true>(rec[k], h, Hp, R, S, Mp, reach, cfv, st, hcards,
-                                             l == 0 ? root_dst : nullptr, upd, iso);
+                                             l == 0 ? root_dst : nullptr, upd, iso, nzs);
     }
 }
 
@@ -578,7 +680,11 @@ __device__ __forceinline__ void block_exscan2(T& a, T& b, T& ta, T& tb, T* xch) 
 // hands sharing no card with h: total - per-card(a) - per-card(b) + r(h)
 // (the hand itself was removed twice).  Both reach vectors and the per-card
 // hand lists are staged in LDS first, so the 104 per-card sums read LDS only;
-// hands holding a card dealt below the root are staged as zero reach.
+// hands holding a card dealt below the root are staged as zero reach.  The
+// same inclusion-exclusion over counts of hands with nonzero reach tells
+// when no compatible opponent hand has reach at all: M is then exactly 0 (as
+// a sum over those hands is), not the rounding residue of the difference,
+// so hands whose every action is worth nothing tie exactly.
 template <typename T>
 __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                           const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
@@ -586,8 +692,9 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
     T* x0 = lds;                  // [Hp]
     T* x1 = x0 + Hp;              // [Hp]
     T* pc = x1 + Hp;              // [2][52], two half-sums per card first: [208]
-    T* xch = pc + 208;            // [2 * kWaves], padded to 2 * kBlock
+    T* xch = pc + 208;            // [2 * kWaves] sums, then [2 * kWaves] counts; padded to 2 * kBlock
     int16_t* lst = reinterpret_cast<int16_t*>(xch + 2 * kBlock);     // [2 * Hp]
+    int32_t* pcn = reinterpret_cast<int32_t*>(lst + 2 * Hp);         // [208]: per-card counts, as pc
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
@@ -600,7 +707,7 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
         const int h = tid + i * kBlock;
         if (h < Hp) { a[i] = r0[h]; b[i] = r1[h]; c[i] = hc[h]; }
     }
-    T s0 = T(0), s1 = T(0);
+    T s0 = T(0), s1 = T(0), n0 = T(0), n1 = T(0);
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int h = tid + i * kBlock;
@@ -610,6 +717,8 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
             x1[h] = b[i];
             s0 += a[i];
             s1 += b[i];
+            n0 += a[i] != T(0) ? T(1) : T(0);
+            n1 += b[i] != T(0) ? T(1) : T(0);
         }
     }
     __syncthreads();
@@ -620,15 +729,24 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
         const T* x = p ? x1 : x0;
         const int lo = coff[cd], hi = coff[cd + 1], mid = lo + ((hi - lo) >> 1);
         T acc = T(0);
-        for (int j = half ? mid : lo; j < (half ? hi : mid); j++) acc += x[lst[j]];
+        int cnt = 0;
+        for (int j = half ? mid : lo; j < (half ? hi : mid); j++) {
+            const T v = x[lst[j]];
+            acc += v;
+            cnt += v != T(0);
+        }
         pc[tid] = acc;
+        pcn[tid] = cnt;
     }
     block_sum2(s0, s1, xch);      // synchronises: the half-sums are visible after it
+    block_sum2(n0, n1, xch + kBlock);
     T pcv0 = T(0), pcv1 = T(0);
-    if (tid < 104) { pcv0 = pc[2 * tid]; pcv1 = pc[2 * tid + 1]; }
+    int pcn0 = 0, pcn1 = 0;
+    if (tid < 104) { pcv0 = pc[2 * tid]; pcv1 = pc[2 * tid + 1]; pcn0 = pcn[2 * tid]; pcn1 = pcn[2 * tid + 1]; }
     __syncthreads();
-    if (tid < 104) pc[tid] = pcv0 + pcv1;
+    if (tid < 104) { pc[tid] = pcv0 + pcv1; pcn[tid] = pcn0 + pcn1; }
     __syncthreads();
+    const int nz0 = (int)n0, nz1 = (int)n1;
     const int f = nd.player;
     const T pay = (T)nd.pay;
     T* v0 = cfv + n * 2 * Hp;
@@ -640,8 +758,8 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
         const int ca = c[i] & 0xff, cb = c[i] >> 8;
         T m0 = T(0), m1 = T(0);
         if (hand_alive(c[i], nd.dead)) {
-            m0 = s0 - pc[ca] - pc[cb] + x0[h];
-            m1 = s1 - pc[52 + ca] - pc[52 + cb] + x1[h];
+            if (nz0 - pcn[ca] - pcn[cb] + (x0[h] != T(0)) > 0) m0 = s0 - pc[ca] - pc[cb] + x0[h];
+            if (nz1 - pcn[52 + ca] - pcn[52 + cb] + (x1[h] != T(0)) > 0) m1 = s1 - pc[52 + ca] - pc[52 + cb] + x1[h];
         }
         v0[h] = (f == 0 ? -pay : pay) * m1;
         v1[h] = (f == 1 ? -pay : pay) * m0;
@@ -654,7 +772,9 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
 // the list total; [alo, ahi) and [blo, bhi) are the tie group of a hand inside
 // the lists of its two cards.  W = opponent reach of compatible weaker hands,
 // L = of compatible stronger ones; ties pay nothing.  The board's table
-// lists only hands alive on it, so no dealt-card masking is needed.
+// lists only hands alive on it, so no dealt-card masking is needed.  As for
+// folds, a hand none of whose compatible opponent hands has nonzero reach
+// (counted by the same inclusion-exclusion) gets exactly 0.
 template <typename T>
 __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                               const uint16_t* __restrict__ hc, const int16_t* __restrict__ tb, int Hb, T* lds) {
@@ -663,10 +783,11 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     T* xs1 = xs0 + (Hp + 4);
     T* q0 = xs1 + (Hp + 4);       // [QN]: card-list exclusive prefixes
     T* q1 = q0 + QN;
-    T* xch = q1 + QN;             // [2 * kWaves], padded to 2 * kBlock
+    T* xch = q1 + QN;             // [2 * kWaves] scan, then [2 * kWaves] counts; padded to 2 * kBlock
     int16_t* coff = reinterpret_cast<int16_t*>(xch + 2 * kBlock);     // [kSdHeader]
     int16_t* clist = coff + kSdHeader;                                // [QN]
     int16_t* perm = clist + QN;                                       // [Hp]
+    int32_t* cnz = reinterpret_cast<int32_t*>(perm + Hp);             // [2][52]: hands with reach per card
     const int16_t* glo = tb + Hp;
     const int16_t* ghi = tb + 2 * Hp;
     const int16_t* alo = tb + 3 * Hp;
@@ -725,6 +846,7 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         T* q = p ? q1 : q0;
         const int lo = coff[c], hi = coff[c + 1] - 1;
         T acc = T(0);
+        int nz = 0;
         int j = lo;
         for (; j + 4 <= hi; j += 4) {
             const T y0 = xs[clist[j]], y1 = xs[clist[j + 1]], y2 = xs[clist[j + 2]], y3 = xs[clist[j + 3]];
@@ -732,9 +854,11 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
             q[j + 1] = acc; acc += y1;
             q[j + 2] = acc; acc += y2;
             q[j + 3] = acc; acc += y3;
+            nz += (y0 != T(0)) + (y1 != T(0)) + (y2 != T(0)) + (y3 != T(0));
         }
-        for (; j < hi; j++) { q[j] = acc; acc += xs[clist[j]]; }
+        for (; j < hi; j++) { const T y = xs[clist[j]]; q[j] = acc; acc += y; nz += y != T(0); }
         q[hi] = acc;
+        cnz[tid] = nz;
     }
     // exclusive scan of xs0 / xs1 over [0, Hb) in sorted order: each thread
     // owns a contiguous chunk, chunk sums are scanned across the workgroup
@@ -742,7 +866,7 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     const int chunk = (Hb + kBlock - 1) / kBlock;
     const int beg = tid * chunk;
     T l0[kMaxChunk], l1[kMaxChunk];
-    T s0 = T(0), s1 = T(0);
+    T s0 = T(0), s1 = T(0), n0 = T(0), n1 = T(0);
 #pragma unroll
     for (int i = 0; i < kMaxChunk; i++) {
         const int s = beg + i;
@@ -751,9 +875,13 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         l1[i] = in ? xs1[s] : T(0);
         s0 += l0[i];
         s1 += l1[i];
+        n0 += l0[i] != T(0) ? T(1) : T(0);
+        n1 += l1[i] != T(0) ? T(1) : T(0);
     }
     T tot0, tot1;
     block_exscan2(s0, s1, tot0, tot1, xch);   // synchronises: every chunk was read above
+    block_sum2(n0, n1, xch + kBlock);
+    const int nz0 = (int)n0, nz1 = (int)n1;
     __syncthreads();                          // all reads of xs done before it is overwritten
 #pragma unroll
     for (int i = 0; i < kMaxChunk; i++) {
@@ -785,8 +913,10 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         const T lo1 = (tot1 - xs1[gh]) - (q1[ae] - q1[ah]) - (q1[be] - q1[bh]);
         const T w0 = xs0[gl] - q0[al] - q0[bl];
         const T lo0 = (tot0 - xs0[gh]) - (q0[ae] - q0[ah]) - (q0[be] - q0[bh]);
-        v0[h] = pay * (w1 - lo1);
-        v1[h] = pay * (w0 - lo0);
+        const bool any1 = nz1 - cnz[52 + ca] - cnz[52 + cb] + (b[i] != T(0)) > 0;
+        const bool any0 = nz0 - cnz[ca] - cnz[cb] + (a[i] != T(0)) > 0;
+        v0[h] = any1 ? pay * (w1 - lo1) : T(0);
+        v1[h] = any0 ? pay * (w0 - lo0) : T(0);
     }
 }
 
@@ -796,16 +926,122 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
                                                      const uint16_t* __restrict__ hcards, const int32_t* __restrict__ coff,
                                                      const int16_t* __restrict__ chands, int chand_stride,
                                                      const int16_t* __restrict__ sd, int64_t sd_stride,
-                                                     const int32_t* __restrict__ sd_n) {
+                                                     const int32_t* __restrict__ sd_n,
+                                                     const int32_t* __restrict__ nzs) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     const int64_t n = list[blockIdx.x];
     const DNode nd = nodes[n];
+    if (node_dead(nzs, nd)) {
+        // unreachable (regret-based pruning): both value rows are zero
+        T* v = cfv + n * 2 * Hp;
+        for (int i = threadIdx.x; i < 2 * Hp; i += blockDim.x) v[i] = T(0);
+        return;
+    }
     const uint16_t* hc = hcards + (int64_t)nd.sub * Hp;
     if (nd.type == PCFR_NODE_FOLD)
         term_fold<T>(nd, n, Hp, reach, cfv, hc, coff + nd.sub * 53, chands + (int64_t)nd.sub * chand_stride, lds);
     else
         term_showdown<T>(nd, n, Hp, reach, cfv, hc, sd + (int64_t)nd.aux * sd_stride, sd_n[nd.aux], lds);
+}
+
+// ------------------------------------------------------------ persistent launch
+// Every phase of an iteration in one resident grid: the level sweeps stride
+// over the level's (node, 4-hand) work items, the terminals over their
+// nodes one workgroup at a time, and a grid barrier separates the phases
+// (each level needs the level above it, resp. below it, complete).  The
+// grid is launched cooperatively, so all its workgroups are resident, and
+// runs `iters` iterations before it exits.  Every workgroup takes every
+// barrier: the loop bounds come from the same device arrays for all, and no
+// workgroup leaves the loops early.  The per-node arithmetic is that of the
+// per-level kernels, so the iterates are bitwise those of the graph of
+// launches.  For forests of subgames played to showdown (no depth-limit
+// leaves), simultaneous updates, no suit isomorphism.
+// hands per work item of the persistent sweeps (4, as the per-level kernels;
+// 2 hands with twice the resident workgroups measured slower: 4.19 against
+// 3.60 ms per iteration of the 256-subgame forest)
+constexpr int kPersistNH = 4;
+
+struct PersistArgs {
+    const DNode* nodes;
+    const DNode* dec_rec;
+    const DNode* fwd_rec;
+    const int64_t* dec_off;
+    const int64_t* fwd_off;
+    const int32_t* term;
+    const uint16_t* hcards;
+    const int32_t* coff;
+    const int16_t* chands;
+    const int16_t* sd;
+    const int32_t* sdn;
+    void *R, *S, *Mp, *reach, *cfv, *root;
+    IterState* st;
+    int32_t* nzs;                 // pruning flags (null: no pruning)
+    int64_t sd_stride;
+    int32_t levels, Hp, cbase, n_term, chand_stride, iters, n_slots;
+};
+
+template <typename T, int MAXA>
+__global__ __launch_bounds__(kBlock) void k_iterate_persistent(PersistArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    T* R = static_cast<T*>(a.R);
+    T* S = static_cast<T*>(a.S);
+    T* Mp = static_cast<T*>(a.Mp);
+    T* reach = static_cast<T*>(a.reach);
+    T* cfv = static_cast<T*>(a.cfv);
+    T* root = static_cast<T*>(a.root);
+    const int Hp = a.Hp, groups = Hp / kPersistNH;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const IsoTabs no_iso = {nullptr, nullptr};
+    for (int it = 0; it < a.iters; it++) {
+        // t, the Stage-7 coefficients and the threshold, and cleared pruning
+        // flags of the action slots (the roots' stay set), before the forward
+        if (blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(a.st);
+        if (a.nzs)
+            for (int64_t i = a.cbase + gtid; i < a.n_slots; i += nthreads) a.nzs[i] = 0;
+        grid.sync();
+        for (int l = 0; l < a.levels; l++) {
+            const int64_t b = a.dec_off[l], cnt = a.dec_off[l + 1] - b;
+            if (cnt == 0) continue;
+            for (int64_t i = gtid; i < cnt * groups; i += nthreads) {
+                const int64_t k = i / groups;
+                fwd_node<T, MODE_ITER, MAXA, kPersistNH>(a.dec_rec[b + k], (int)(i - k * groups) * kPersistNH, Hp,
+                                                         a.cbase, R, S, Mp, reach, a.st, a.nzs, true);
+            }
+            grid.sync();
+        }
+        for (int w = blockIdx.x; w < a.n_term; w += gridDim.x) {
+            __syncthreads();   // the previous node's LDS is consumed
+            const int64_t n = a.term[w];
+            const DNode nd = a.nodes[n];
+            if (node_dead(a.nzs, nd)) {
+                T* v = cfv + n * 2 * Hp;
+                for (int i = threadIdx.x; i < 2 * Hp; i += blockDim.x) v[i] = T(0);
+                continue;
+            }
+            const uint16_t* hc = a.hcards + (int64_t)nd.sub * Hp;
+            if (nd.type == PCFR_NODE_FOLD)
+                term_fold<T>(nd, n, Hp, reach, cfv, hc, a.coff + nd.sub * 53, a.chands + (int64_t)nd.sub * a.chand_stride,
+                             lds);
+            else
+                term_showdown<T>(nd, n, Hp, reach, cfv, hc, a.sd + (int64_t)nd.aux * a.sd_stride, a.sdn[nd.aux], lds);
+        }
+        grid.sync();
+        for (int l = a.levels - 1; l >= 0; l--) {
+            const int64_t b = a.fwd_off[l], cnt = a.fwd_off[l + 1] - b;
+            if (cnt == 0) continue;
+            for (int64_t i = gtid; i < cnt * groups; i += nthreads) {
+                const int64_t k = i / groups;
+                bwd_node<T, MODE_ITER, MAXA, kPersistNH, false>(a.fwd_rec[b + k], (int)(i - k * groups) * kPersistNH, Hp,
+                                                                R, S, Mp, reach, cfv, a.st, a.hcards,
+                                                                l == 0 ? root : nullptr, -1, no_iso, a.nzs);
+            }
+            grid.sync();
+        }
+    }
 }
 
 // ------------------------------------------------------------ depth-limit leaves
@@ -946,7 +1182,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__ nodes,
                                                        const int32_t* __restrict__ leaves, int Hp,
                                                        const T* __restrict__ reach,
-                                                       const int16_t* __restrict__ combo_hand /* [n_sub][1326] */,
+                                                       const int16_t* __restrict__ combo_hand /* [n_sub][kComboPad] */,
                                                        T* __restrict__ Rc, T* __restrict__ agg,
                                                        const float* __restrict__ spr, int n_next, int cards_per_group,
                                                        const int8_t* __restrict__ next_cards /* [n_sub][64] */,
@@ -956,13 +1192,13 @@ __global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__
     __shared__ T x[2][kMaxHp];
     __shared__ double xc[2][kComboPad];
     __shared__ double sv[2][52];
-    __shared__ double dxch[2 * kWaves];
+    __shared__ double dxch[2 * kWaves], nxch[2 * kWaves];
     const int li = blockIdx.x, tid = threadIdx.x;
     const bool lead = blockIdx.y == 0;
     const DNode nd = nodes[leaves[li]];
     const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
-    combo_hand += (int64_t)nd.sub * kCombos;
+    combo_hand += (int64_t)nd.sub * kComboPad;
     // every load of the thread first: its hands' reach and its combos' hands
     T a[kHandIt], b[kHandIt];
     int hk[RI];
@@ -986,7 +1222,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__
     // dense combo-indexed ranges (to LDS for the rows and sums, and from
     // group 0 to memory for the zero-sum and combine kernels)
     T* rc = Rc + (int64_t)li * 2 * kComboPad;
-    double t0 = 0.0, t1 = 0.0;
+    double t0 = 0.0, t1 = 0.0, n0 = 0.0, n1 = 0.0;   // totals and counts of combos with reach
 #pragma unroll
     for (int i = 0; i < RI; i++) {
         const int k = tid + i * kBlock;
@@ -995,20 +1231,37 @@ __global__ __launch_bounds__(kBlock) void k_leaf_input(const DNode* __restrict__
             const T v = hk[i] >= 0 ? x[p][hk[i]] : T(0);
             if (lead) rc[k] = v;
             xc[p][kk] = (double)v;
-            if (p) t1 += (double)v; else t0 += (double)v;
+            if (p) { t1 += (double)v; n1 += v != T(0) ? 1.0 : 0.0; }
+            else { t0 += (double)v; n0 += v != T(0) ? 1.0 : 0.0; }
         }
     }
     block_sum2(t0, t1, dxch);      // synchronises: xc is visible after it
+    block_sum2(n0, n1, nxch);
     if (tid < 104) {
         // per-card sums over the 51 combos holding the card, then 1/S for each card
         const int p = tid / 52, c = tid - p * 52;
-        double cs = 0.0;
+        double cs = 0.0, nc = 0.0;
 #pragma unroll
-        for (int xi = 0; xi < 51; xi++) cs += xc[p][combo_index(c, xi < c ? xi : xi + 1)];
+        for (int xi = 0; xi < 51; xi++) {
+            const double v = xc[p][combo_index(c, xi < c ? xi : xi + 1)];
+            cs += v;
+            nc += v != 0.0 ? 1.0 : 0.0;
+        }
         if (lead) agg[(int64_t)li * kAgg + p * 53 + c] = (T)cs;
-        // a remainder below 1e-9 of the total is rounding of an empty set
-        const double tot = p ? t1 : t0, rest = tot - cs;
-        sv[p][c] = rest > 1e-9 * tot ? 1.0 / rest : 0.0;
+        // The row is empty exactly when no combo without c has reach (an
+        // integer count, as the plain sum's test for zero); otherwise S is
+        // total - C(c), or, where that difference has cancelled below 1e-6
+        // of the total, the direct sum of the combos without c.
+        const double tot = p ? t1 : t0, left = (p ? n1 : n0) - nc;
+        double rest = tot - cs;
+        if (left > 0.0 && !(rest > 1e-6 * tot)) {
+            rest = 0.0;
+            int k = 0;
+            for (int a = 1; a < 52; a++)
+                for (int b = 0; b < a; b++, k++)
+                    if (a != c && b != c) rest += xc[p][k];
+        }
+        sv[p][c] = left > 0.0 && rest > 0.0 ? 1.0 / rest : 0.0;
     }
     if (lead && tid == 0) { agg[(int64_t)li * kAgg + 52] = (T)t0; agg[(int64_t)li * kAgg + 105] = (T)t1; }
     __syncthreads();
@@ -1131,7 +1384,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
                                                          const T* __restrict__ reach, T* __restrict__ cfv,
                                                          const uint16_t* __restrict__ hcards /* [n_sub][Hp] */,
                                                          const int16_t* __restrict__ hand_combo /* [n_sub][Hp] */,
-                                                         const int16_t* __restrict__ combo_hand /* [n_sub][1326] */,
+                                                         const int16_t* __restrict__ combo_hand /* [n_sub][kComboPad] */,
                                                          const float* __restrict__ Y, int ldy,
                                                          const T* __restrict__ agg, const T* __restrict__ delta) {
     __shared__ T x[2][kMaxHp];
@@ -1147,7 +1400,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
     const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     hcards += (int64_t)nd.sub * Hp;
     hand_combo += (int64_t)nd.sub * Hp;
-    combo_hand += (int64_t)nd.sub * kCombos;
+    combo_hand += (int64_t)nd.sub * kComboPad;   // 16-byte aligned rows for copy_i16
     next_cards += nd.sub * 64;
     const int tid = threadIdx.x;
     {
@@ -1311,10 +1564,17 @@ __global__ __launch_bounds__(kBlock) void k_samples(const int32_t* __restrict__ 
 }
 
 // ------------------------------------------------------------ small kernels
-// Strategy of one decision node for every hand: which 0 = average, 1 = current.
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_begin_iteration(IterState* st) { begin_iteration(st); }
+
+// Strategy of one decision node for every hand: which 0 = average, 1 =
+// current (regret matching, then the threshold of the next iteration).
 template <typename T>
 __global__ void k_strategy(const T* __restrict__ src, const T* __restrict__ pred, int rs, int A, int Hp, int which,
-                           T* __restrict__ out) {
+                           const IterState* __restrict__ st, T* __restrict__ out) {
     int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= Hp) return;
     T den = T(0);
@@ -1325,6 +1585,16 @@ __global__ void k_strategy(const T* __restrict__ src, const T* __restrict__ pred
     for (int a = 0; a < A; a++) {
         T x = src[(int64_t)(rs + a) * Hp + h] + (pred ? pred[(int64_t)(rs + a) * Hp + h] : T(0));
         out[(int64_t)a * Hp + h] = den > T(0) ? ((which && !(x > T(0))) ? T(0) : x / den) : T(1) / T(A);
+    }
+    const T thr = (which && st->thr0 > 0.0) ? (T)(st->thr0 / sqrt((double)(st->t + 1))) : T(0);
+    if (thr > T(0)) {
+        T keep = T(0);
+        for (int a = 0; a < A; a++) {
+            T& q = out[(int64_t)a * Hp + h];
+            if (q < thr) q = T(0);
+            keep += q;
+        }
+        for (int a = 0; a < A; a++) out[(int64_t)a * Hp + h] /= keep;
     }
 }
 
@@ -1348,7 +1618,7 @@ struct Plan {
     size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_zs, off_agg, off_rc, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
-        off_eqgrp, off_nsub, off_b4,
+        off_eqgrp, off_nsub, off_b4, off_nzs,
         off_cmap, off_hmap, total;
     size_t lds_bytes, lds_fold, lds_show;
     int64_t n_grp = 0, n_grp_allin = 0;   // equity groups: all leaves, the all-in prefix
@@ -1779,17 +2049,19 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.off_cmap = take(iso ? sizeof(int32_t) * 2 * L.N : 0);
     L.off_hmap = take(iso ? sizeof(int16_t) * 24 * L.Hp * P.n_sub : 0);
     L.off_next = take(64 * (size_t)P.n_sub);
-    L.off_c2h = take(sizeof(int16_t) * kCombos * P.n_sub);
+    L.off_c2h = take(sizeof(int16_t) * kComboPad * P.n_sub);   // rows padded: 16-byte aligned per subgame
     L.off_h2c = take(sizeof(int16_t) * L.Hp * P.n_sub);
     L.off_roots = take(sizeof(int32_t) * P.n_sub);
     L.off_M = take(variant == PCFR_PCFRPLUS ? L.esz * L.rows * L.Hp : 0);
     L.off_samp = take(align256(sizeof(float) * 2 * P.n_sub) + align256((size_t)P.n_sub * 52) +
                       align256(sizeof(int16_t) * (size_t)P.n_sub * kCombos));
     L.off_eqpart = take(L.esz * kEqSplit * L.n_eq * 2 * L.Hp);
+    L.off_nzs = take(sizeof(int32_t) * (size_t)(2 * P.n_sub + L.rows));   // pruning flags per reach slot
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
-    const size_t sd_lds = L.esz * (2 * (L.Hp + 4) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn + L.Hp);
-    const size_t fold_lds = L.esz * (2 * L.Hp + 208 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp;
+    const size_t sd_lds = L.esz * (2 * (L.Hp + 4) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn + L.Hp) +
+                          sizeof(int32_t) * 104;
+    const size_t fold_lds = L.esz * (2 * L.Hp + 208 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp + sizeof(int32_t) * 208;
     L.lds_fold = fold_lds;
     L.lds_show = sd_lds;
     L.lds_bytes = std::max(sd_lds, fold_lds);
@@ -1831,6 +2103,8 @@ struct pcfr_solver {
     IsoMap iso;                 // suit isomorphism map (suit_iso = 1)
     bool leaf_zero_sum = true;  // shift network outputs to zero-sum leaf values
     int64_t t_host = 0;     // iterations enqueued
+    int32_t launch_mode = PCFR_LAUNCH_GRAPH;
+    int32_t persist_grid = 0, persist_maxa = 0;   // persistent launch: resident workgroups, action bucket
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
     ~pcfr_solver() {
         if (stream && ws) (void)hipStreamSynchronize(stream);
@@ -1887,6 +2161,20 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     auto dec_cnt = [&](int l) { return P.dec_off[l + 1] - P.dec_off[l]; };
     auto all_cnt = [&](int l) { return P.fwd_off[l + 1] - P.fwd_off[l]; };
     bool first = MODE == MODE_ITER && begin;
+    // regret-based pruning flags of this sweep (iteration sweeps only): the
+    // action slots' flags are cleared, the roots' stay set
+    int32_t* nzs = (MODE == MODE_ITER && s->cfg.prune) ? s->at<int32_t>(L.off_nzs) : nullptr;
+    if (nzs) {
+        const int64_t n = L.rows;
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 2048)), dim3(256), 0, stream,
+                           nzs + 2 * P.n_sub, n, 0);
+    }
+    // with thresholding every forward launch reads this iteration's
+    // threshold, so t advances in a launch of its own
+    if (first && s->cfg.threshold > 0) {
+        hipLaunchKernelGGL(k_begin_iteration, dim3(1), dim3(1), 0, stream, st);
+        first = false;
+    }
     for (int l = 0; l < P.levels;) {
         const int64_t cnt = dec_cnt(l);
         if (!cnt) { l++; continue; }
@@ -1895,7 +2183,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             while (l1 < P.levels && dec_cnt(l1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[l1++]);
             if (tm) tm->before(1);
             PCFR_BUCKET_MA(k_forward_fused, ma, fgrid, dim3(kFuseBlock), 0, stream, dec, s->at<int64_t>(L.off_decoff), l,
-                           l1, Hp, (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr);
+                           l1, Hp, (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr, st, nzs);
             if (tm) tm->after();
             first = false;
             l = l1;
@@ -1906,7 +2194,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         dim3 grid((unsigned)((threads + bs - 1) / bs));
         if (tm) tm->before(1, l);
         PCFR_BUCKET(k_forward, l, grid, dim3(bs), 0, stream, dec + P.dec_off[l], (int)cnt, Hp,
-                    (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr);
+                    (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr, st, nzs);
         if (tm) tm->after();
         first = false;
         l++;
@@ -1930,7 +2218,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            nodes, s->at<int32_t>(L.off_term) + (kind ? n_fold : 0), Hp, reach, cfv,
                            s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
                            (int)L.chand_stride, s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride,
-                           s->at<int32_t>(L.off_sdn));
+                           s->at<int32_t>(L.off_sdn), nzs);
         if (tm) tm->after();
     }
     // depth-limit leaves: exact equity for all-in leaves (and for every leaf
@@ -2016,7 +2304,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             PCFR_BUCKET_MA(k_backward_fused, ma, fgrid, dim3(kFuseBlock), 0, stream,
                            fwd, s->at<int64_t>(L.off_fwdoff), l0, l + 1, Hp, R, S, Mp, reach, cfv, st,
                            s->at<uint16_t>(L.off_hc), (MODE == MODE_ITER && l0 == 0) ? s->at<T>(L.off_root) : nullptr,
-                           upd, iso);
+                           upd, iso, nzs);
             if (tm) tm->after();
             l = l0 - 1;
             continue;
@@ -2027,7 +2315,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (tm) tm->before(3, 1000 + l);
         PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
                     reach, cfv, st, s->at<uint16_t>(L.off_hc),
-                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr, upd, iso);
+                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr, upd, iso, nzs);
         if (tm) tm->after();
         l--;
     }
@@ -2142,6 +2430,11 @@ static int32_t check_cfg(const pcfr_solver_cfg* cfg) {
         set_error("alpha, beta, gamma must be finite");
         return PCFR_E_INVALID_ARG;
     }
+    if (!(cfg->threshold >= 0.0 && cfg->threshold < 1.0 / 12)) {
+        set_error("threshold must lie in [0, 1/12)");
+        return PCFR_E_INVALID_ARG;
+    }
+    if (cfg->prune != 0 && cfg->prune != 1) { set_error("prune must be 0 or 1"); return PCFR_E_INVALID_ARG; }
     return PCFR_OK;
 }
 
@@ -2287,9 +2580,9 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     }
     {
         // per subgame: combo -> hand, hand -> combo, next cards, root board
-        std::vector<int16_t> c2h((size_t)n * kCombos), h2c((size_t)n * L.Hp, -1);
+        std::vector<int16_t> c2h((size_t)n * kComboPad, -1), h2c((size_t)n * L.Hp, -1);
         for (int32_t g = 0; g < n; g++) {
-            for (int k = 0; k < kCombos; k++) c2h[(size_t)g * kCombos + k] = (int16_t)P.combo_hand[g][k];
+            for (int k = 0; k < kCombos; k++) c2h[(size_t)g * kComboPad + k] = (int16_t)P.combo_hand[g][k];
             for (int64_t h = 0; h < P.Hs[g]; h++) h2c[(size_t)g * L.Hp + h] = (int16_t)P.hand_combo[g][h];
         }
         std::vector<int32_t> grp;
@@ -2337,7 +2630,12 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         st.alpha = cfg->alpha;
         st.beta = cfg->beta;
         st.gamma = cfg->gamma;
+        st.thr0 = cfg->threshold;
         if ((rc = up(L.off_state, &st, sizeof(st)))) return rc;
+        // pruning flags: the roots' reach slots hold the ranges, set once
+        std::vector<int32_t> nzs(2 * (size_t)P.n_sub + L.rows, 0);
+        for (int64_t i = 0; i < 2 * (int64_t)P.n_sub; i++) nzs[i] = 1;
+        if ((rc = up(L.off_nzs, nzs.data(), sizeof(int32_t) * nzs.size()))) return rc;
         HIPCHK(hipStreamSynchronize(s->stream));
     }
     HIPCHK(hipMemsetAsync(s->ws + L.off_R, 0, L.esz * L.rows * L.Hp, s->stream));
@@ -2397,13 +2695,13 @@ static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t wh
                            s->at<double>(which == PCFR_AVG ? L.off_S : L.off_R),
                            (which == PCFR_CURRENT && s->cfg.variant == PCFR_PCFRPLUS) ? s->at<double>(L.off_M) : nullptr,
                            d.rs, d.n_child, (int)L.Hp,
-                           which == PCFR_CURRENT ? 1 : 0, (double*)stage);
+                           which == PCFR_CURRENT ? 1 : 0, s->at<IterState>(L.off_state), (double*)stage);
     else
         hipLaunchKernelGGL((k_strategy<float>), grid, dim3(256), 0, s->stream,
                            s->at<float>(which == PCFR_AVG ? L.off_S : L.off_R),
                            (which == PCFR_CURRENT && s->cfg.variant == PCFR_PCFRPLUS) ? s->at<float>(L.off_M) : nullptr,
                            d.rs, d.n_child, (int)L.Hp,
-                           which == PCFR_CURRENT ? 1 : 0, (float*)stage);
+                           which == PCFR_CURRENT ? 1 : 0, s->at<IterState>(L.off_state), (float*)stage);
     HIPCHK(hipGetLastError());
     int32_t rc = fetch_hands(s, stage, d.n_child, out, g);
     if (rc) return rc;
@@ -2551,6 +2849,85 @@ static int32_t time_replays(pcfr_solver* s, int32_t n, double* ms) {
 // timed at each candidate workgroup size over `reps` iterations (per-launch
 // events), the fastest size per launch is kept and cached for its size
 // bucket, the graph is captured again, and the state is reset to t = 0.
+// Persistent launch (k_iterate_persistent): n iterations in one cooperative launch.
+template <typename T, int MAXA>
+static const void* persist_kernel() {
+    return reinterpret_cast<const void*>(&k_iterate_persistent<T, MAXA>);
+}
+static const void* persist_kernel_for(int dtype, int maxa) {
+    const bool d = dtype == PCFR_F64;
+    if (maxa <= 3) return d ? persist_kernel<double, 3>() : persist_kernel<float, 3>();
+    if (maxa <= 6) return d ? persist_kernel<double, 6>() : persist_kernel<float, 6>();
+    if (maxa <= 8) return d ? persist_kernel<double, 8>() : persist_kernel<float, 8>();
+    return d ? persist_kernel<double, 12>() : persist_kernel<float, 12>();
+}
+
+static int32_t set_launch_impl(pcfr_solver* s, int32_t mode) {
+    if (mode == PCFR_LAUNCH_GRAPH) { s->launch_mode = mode; return PCFR_OK; }
+    if (mode != PCFR_LAUNCH_PERSISTENT) { set_error("unknown launch mode"); return PCFR_E_INVALID_ARG; }
+    const Plan& L = s->L;
+    if (L.n_eq || L.n_net || s->net) { set_error("the persistent launch serves trees without depth-limit leaves"); return PCFR_E_UNSUPPORTED; }
+    if (s->cfg.alternating || s->cfg.suit_iso) {
+        set_error("the persistent launch runs simultaneous updates without suit isomorphism");
+        return PCFR_E_UNSUPPORTED;
+    }
+    int maxa = 1;
+    for (int32_t v : s->P.lvl_maxa) maxa = std::max(maxa, v);
+    const void* k = persist_kernel_for(s->cfg.dtype, maxa);
+    if (L.lds_bytes > 65536)
+        HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes));
+    int dev = 0, cus = 0, per_cu = 0, coop = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) { set_error("the device does not support cooperative launches"); return PCFR_E_UNSUPPORTED; }
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, L.lds_bytes));
+    if (per_cu < 1 || cus < 1) { set_error("the persistent kernel does not fit a compute unit"); return PCFR_E_UNSUPPORTED; }
+    s->persist_grid = per_cu * cus;
+    s->persist_maxa = maxa;
+    s->launch_mode = mode;
+    return PCFR_OK;
+}
+
+template <typename T>
+static int32_t persist_launch(pcfr_solver* s, int32_t iters) {
+    const Plan& L = s->L;
+    const Prepared& P = s->P;
+    PersistArgs a{};
+    a.nodes = s->at<DNode>(L.off_nodes);
+    a.dec_rec = s->at<DNode>(L.off_dec);
+    a.fwd_rec = s->at<DNode>(L.off_fwd);
+    a.dec_off = s->at<int64_t>(L.off_decoff);
+    a.fwd_off = s->at<int64_t>(L.off_fwdoff);
+    a.term = s->at<int32_t>(L.off_term);
+    a.hcards = s->at<uint16_t>(L.off_hc);
+    a.coff = s->at<int32_t>(L.off_coff);
+    a.chands = s->at<int16_t>(L.off_chands);
+    a.sd = s->at<int16_t>(L.off_sd);
+    a.sdn = s->at<int32_t>(L.off_sdn);
+    a.R = s->at<T>(L.off_R);
+    a.S = s->at<T>(L.off_S);
+    a.Mp = s->cfg.variant == PCFR_PCFRPLUS ? s->at<T>(L.off_M) : nullptr;
+    a.reach = s->at<T>(L.off_reach);
+    a.cfv = s->at<T>(L.off_cfv);
+    a.root = s->at<T>(L.off_root);
+    a.st = s->at<IterState>(L.off_state);
+    a.nzs = s->cfg.prune ? s->at<int32_t>(L.off_nzs) : nullptr;
+    a.n_slots = (int32_t)(2 * P.n_sub + L.rows);
+    a.sd_stride = (int64_t)L.sd_stride;
+    a.levels = P.levels;
+    a.Hp = (int32_t)L.Hp;
+    a.cbase = 2 * P.n_sub;
+    a.n_term = (int32_t)(P.folds.size() + P.shows.size());
+    a.chand_stride = (int32_t)L.chand_stride;
+    a.iters = iters;
+    void* params[] = {&a};
+    const void* k = persist_kernel_for(s->cfg.dtype, s->persist_maxa);
+    HIPCHK(hipLaunchCooperativeKernel(k, dim3((unsigned)s->persist_grid), dim3(kBlock), params, (unsigned)L.lds_bytes,
+                                      s->stream));
+    return PCFR_OK;
+}
+
 static int32_t autotune_impl(pcfr_solver* s, int32_t reps, double* ms_before, double* ms_after) {
     if (!s || reps < 1 || !ms_before || !ms_after) { set_error("null argument or reps < 1"); return PCFR_E_INVALID_ARG; }
     int64_t t = 0;
@@ -2721,6 +3098,14 @@ int32_t pcfr_solver_free(pcfr_solver* s) {
 
 int32_t pcfr_cfr_iterate(pcfr_solver* s, int32_t n) {
     if (!s || n < 0) { set_error("null solver or negative count"); return PCFR_E_INVALID_ARG; }
+    if (s->launch_mode == PCFR_LAUNCH_PERSISTENT) {
+        if (n > 0) {
+            const int32_t rc = s->cfg.dtype == PCFR_F64 ? persist_launch<double>(s, n) : persist_launch<float>(s, n);
+            if (rc) return rc;
+        }
+        s->t_host += n;
+        return PCFR_OK;
+    }
     for (int32_t i = 0; i < n; i++) HIPCHK(hipGraphLaunch(s->graph, s->stream));
     s->t_host += n;
     return PCFR_OK;
@@ -2747,6 +3132,25 @@ int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* 
     }
     s->t_host += n;
     return PCFR_OK;
+}
+
+int32_t pcfr_solver_unreached_nodes(pcfr_solver* s, int64_t* n) {
+    if (!s || !n) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
+    if (!s->cfg.prune) { set_error("the solver was created without pruning"); return PCFR_E_STATE; }
+    const Plan& L = s->L;
+    std::vector<int32_t> nzs(2 * (size_t)s->P.n_sub + L.rows);
+    HIPCHK(hipMemcpyAsync(nzs.data(), s->ws + L.off_nzs, sizeof(int32_t) * nzs.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    int64_t cnt = 0;
+    for (const DNode& d : s->P.nodes)
+        if (nzs[d.slot[0]] == 0 && nzs[d.slot[1]] == 0) cnt++;
+    *n = cnt;
+    return PCFR_OK;
+}
+
+int32_t pcfr_solver_set_launch(pcfr_solver* s, int32_t mode) {
+    if (!s) { set_error("null solver"); return PCFR_E_INVALID_ARG; }
+    return set_launch_impl(s, mode);
 }
 
 int32_t pcfr_synchronize(pcfr_solver* s) {

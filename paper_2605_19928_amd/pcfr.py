@@ -38,7 +38,8 @@ class TreeSpec(C.Structure):
 
 class SolverCfg(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("variant", C.c_int32), ("alpha", C.c_double),
-                ("beta", C.c_double), ("gamma", C.c_double), ("alternating", C.c_int32), ("suit_iso", C.c_int32)]
+                ("beta", C.c_double), ("gamma", C.c_double), ("alternating", C.c_int32), ("suit_iso", C.c_int32),
+                ("threshold", C.c_double), ("prune", C.c_int32)]
 
 
 _lib = None
@@ -55,6 +56,8 @@ _SIGS = {
     "pcfr_suit_iso_map": (C.c_int32, [C.c_void_p] * 6),
     "pcfr_prune_dominated": (C.c_int32, [C.c_void_p] * 5),
     "pcfr_prune_dominated_noalloc": (C.c_int32, [C.c_void_p] * 5),
+    "pcfr_solver_set_launch": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "pcfr_solver_unreached_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_tree_prune": (C.c_int32, [C.c_void_p] * 4),
     "pcfr_solver_swept_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_equity_table": (C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -255,6 +258,8 @@ class SolverConfig:
     variant: str = "dcfr"
     alternating: int = 0
     suit_iso: int = 0
+    threshold: float = 0.0
+    prune: int = 0
 
     def to_c(self) -> SolverCfg:
         c = SolverCfg()
@@ -262,6 +267,7 @@ class SolverConfig:
         v = VARIANTS[self.variant] if isinstance(self.variant, str) else int(self.variant)
         c.variant, c.alpha, c.beta, c.gamma, c.alternating, c.suit_iso = (v, self.alpha, self.beta, self.gamma,
                                                                          self.alternating, self.suit_iso)
+        c.threshold, c.prune = float(self.threshold), int(self.prune)
         return c
 
 
@@ -319,6 +325,18 @@ class Solver:
     def autotune_budget(self, budget_ms: int = 200):
         """The autotuner within a device-time budget (fresh solvers only)."""
         _check(lib().pcfr_batch_autotune(self._h, int(budget_ms)))
+
+    def set_launch(self, persistent: bool):
+        """Run iterate(n) as one persistent cooperative launch (True) or as
+        graph replays of per-level launches (False, the default); the iterates
+        are bitwise the same."""
+        _check(lib().pcfr_solver_set_launch(self._h, 1 if persistent else 0))
+
+    def unreached_nodes(self) -> int:
+        """Nodes the last iteration skipped as unreachable (solvers with prune=1)."""
+        n = C.c_int64()
+        _check(lib().pcfr_solver_unreached_nodes(self._h, C.byref(n)))
+        return int(n.value)
 
     def synchronize(self):
         _check(lib().pcfr_synchronize(self._h))
@@ -526,9 +544,9 @@ class LeafNet:
     def tiles(self):
         """Forward GEMM tile per layer (-1 default, 0 64x64, 1 128x64, 2 64x128, 3 128x128,
         4 64x64 and 5 64x128 with the K loop split between two wave groups, 6 64x64 and
-        7 64x128 with a deeper prefetch, 8 and 9 direct tiles reading operands straight
-        into registers, 9 with K split in two; direct tiles only as a suffix of layers
-        after the first)."""
+        7 64x128 with a deeper prefetch, 8, 9 and 10 direct tiles reading operands straight
+        into registers, 9 and 10 with K split in two and four; direct tiles only as a suffix
+        of layers after the first)."""
         t = np.zeros(len(self.layer_shapes()), dtype=np.int32)
         _check(lib().pcfr_leafnet_get_tiles(self._h, _p(t), len(t)))
         return [int(v) for v in t]

@@ -215,3 +215,83 @@ def test_batch_depth_limited_network_leaves(street):
         say(f"  member {g}: root cfv max |d| against its own solve = {d:.3e}")
         np.testing.assert_array_equal(b.root_cfv_of(g, "current"), s.root_cfv("current"))
         s.close()
+
+
+@pytest.mark.parametrize("dtype,variant", [("f32", "dcfr"), ("f64", "dcfr"), ("f32", "pcfr+")])
+def test_persistent_launch_is_bitwise_the_graph(dtype, variant):
+    """One cooperative launch running all iterations (grid barriers between
+    the level sweeps and the terminals) against graph replays of per-level
+    launches: the same iterates, bit for bit."""
+    cases = I.batch_config(6, count_nodes, n=12, river_share=0.7, lo=10, hi=1500)
+    trees = [P.Tree(**s) for s, _ in cases]
+    ranges = np.stack([r for _, r in cases])
+    say(f"case: persistent launch vs graph, 12 subgames, {dtype} {variant}")
+    cfg = P.SolverConfig(dtype=dtype, variant=variant)
+    g = P.Batch(trees, ranges, cfg)
+    p = P.Batch(trees, ranges, cfg)
+    p.set_launch(True)
+    T = 20
+    g.iterate(T)
+    p.iterate(7)
+    p.iterate(T - 7)
+    assert p.t == g.t == T
+    assert p.save_state() == g.save_state()
+    for k in (0, 5, 11):
+        np.testing.assert_array_equal(p.root_cfv_of(k, "current"), g.root_cfv_of(k, "current"))
+
+
+def test_persistent_launch_refuses_what_it_does_not_run():
+    spec, r = I.flop_config(0, support=100)
+    s = P.Solver(P.Tree(**spec), r)
+    with pytest.raises(P.PcfrError) as e:
+        s.set_launch(True)
+    assert e.value.code == P.E_UNSUPPORTED
+    spec, r = I.river_config(2)
+    s = P.Solver(P.Tree(**spec), r, P.SolverConfig(alternating=1))
+    with pytest.raises(P.PcfrError):
+        s.set_launch(True)
+
+
+def test_batch_of_256_subgames():
+    """The batching workload at its configured size: 256 river and turn
+    subgames (70% rivers) of uneven trees in one forest, FP32.  The
+    persistent launch and the graph give the same iterates bit for bit,
+    sampled members equal their own solves bit for bit, and river members
+    solved in FP64 match the oracle at 1e-9 pot."""
+    cases = I.batch_config(0, count_nodes, n=256, river_share=0.7, lo=10, hi=2000)
+    trees = [P.Tree(**s) for s, _ in cases]
+    ranges = np.stack([r for _, r in cases])
+    say(f"case: 256-subgame batch, {sum(t.n_nodes for t in trees)} nodes")
+    T = 12
+    g = P.Batch(trees, ranges)
+    g.iterate(T)
+    p = P.Batch(trees, ranges)
+    p.set_launch(True)
+    p.iterate(T)
+    assert p.save_state() == g.save_state()
+    del p
+    rng = np.random.default_rng(1)
+    for k in sorted(rng.choice(256, 6, replace=False)):
+        s = P.Solver(trees[k], ranges[k])
+        s.iterate(T)
+        np.testing.assert_array_equal(g.root_cfv_of(int(k), "current"), s.root_cfv("current"))
+        e = trees[k].export()
+        n = int(np.flatnonzero(e["type"] == P.NODE_DECISION)[-1])
+        np.testing.assert_array_equal(g.strategy_of(int(k), n), s.strategy(n))
+        s.close()
+    del g
+    b = P.Batch(trees, ranges, P.SolverConfig(dtype="f64"))
+    b.set_launch(True)
+    b.iterate(T)
+    e_all, _ = b.exploitability_all()
+    rivers = [k for k, (sp, _) in enumerate(cases) if len(sp["board"]) == 5]
+    for k in (rivers[0], rivers[len(rivers) // 2]):
+        spec, r = cases[k]
+        ot = O.Tree.holdem(**spec)
+        os_ = O.Solver(ot, r)
+        os_.iterate(T)
+        d = np.abs(b.root_cfv_of(k, "current") - os_.root_cfv("current")).max() / spec["pot"]
+        eo, _ = os_.exploitability()
+        say(f"  member {k} ({ot.n_nodes} nodes): root cfv max |d| = {d:.3e} pot; exploitability batch "
+            f"{e_all[k]:.9f} oracle {eo:.9f}")
+        assert d <= 1e-9 and abs(e_all[k] - eo) / spec["pot"] <= 1e-9

@@ -201,3 +201,91 @@ def test_node_values_of_batch_subgames():
         d = np.abs(V[0] - b.root_cfv_of(sub, "avg")).max()
         say(f"  subgame {sub}: root rows vs root values max |d| = {d:.3e}")
         assert d <= 1e-12 * cases[sub][0]["pot"]
+
+
+# ---------------------------------------------------------------- regret-based pruning, thresholding
+def _state_arrays(s, dtype):
+    b = s.save_state()
+    return np.frombuffer(b[16:], dtype=np.float64 if dtype == "f64" else np.float32)
+
+
+@pytest.mark.parametrize("case", ["river", "turn"])
+def test_thresholded_solve_matches_oracle(case):
+    """Dynamic thresholding (iteration t drops actions below thr0 / sqrt(t))
+    with regret-based pruning of unreachable subtrees, FP64, against the
+    oracle's thresholded solve: 1e-9 pot on root values and exploitability;
+    strategies where unique (tied entries checked as distributions)."""
+    if case == "river":
+        spec, r = I.river_config(3, support=120)
+        so, T = False, 60
+    else:
+        spec, r = I.turn_config(5, support=40, spr=1.5)
+        so, T = True, 30
+    thr = 0.05
+    say(f"case: thresholded + pruned solve vs oracle, {case}, thr0={thr} T={T}")
+    ot = O.Tree.holdem(**spec)
+    os_ = O.Solver(ot, r, support_only=so, threshold=thr)
+    os_.iterate(T)
+    gs = P.Solver(P.Tree(**spec), r, P.SolverConfig(dtype="f64", threshold=thr, prune=1))
+    gs.iterate(T)
+    pot = spec["pot"]
+    mask = ((r > 0) if so else np.ones_like(r, dtype=bool)) & ~I.blocked_mask(spec["board"])[None, :]
+    for which in ("current", "avg"):
+        d = np.abs(gs.root_cfv(which) - os_.root_cfv(which))[mask].max() / pot
+        say(f"  root cfv ({which}) max |d| = {d:.3e} pot")
+        assert d <= 1e-9
+    eg, _ = gs.exploitability()
+    eo, _ = os_.exploitability()
+    say(f"  exploitability gpu {eg:.9f} oracle {eo:.9f}")
+    assert abs(eg - eo) / pot <= 1e-9
+    e = ot.export()
+    rs = np.concatenate([[0], np.cumsum(np.where(e["type"] == O.T_DEC, e["n_child"], 0))])
+    R = os_.rows("R")
+    worst, tied, zeroed = 0.0, 0, 0
+    for n in np.flatnonzero(e["type"] == O.T_DEC):
+        own = mask[int(e["player"][n])].copy()
+        free = own & np.all(R[rs[n]: rs[n] + e["n_child"][n]] == 0, axis=0)
+        own &= ~free
+        tied += int(free.sum())
+        for which in ("avg", "current"):
+            g = gs.strategy(int(n), which)
+            o = os_.strategy(int(n), which)
+            worst = max(worst, float(np.abs(g - o)[:, own].max(initial=0.0)))
+            assert np.all(g[:, free] >= 0) and np.allclose(g[:, free].sum(axis=0), 1.0, rtol=0, atol=1e-12)
+            if which == "current":
+                rm = np.maximum(R[rs[n]: rs[n] + e["n_child"][n]], 0)
+                zeroed += int(((rm > 0) & (o == 0))[:, own].sum())
+    say(f"  strategies max |d| = {worst:.3e} ({tied} tied entries); {zeroed} positive-regret actions cut by the threshold")
+    assert worst <= 1e-9
+    assert zeroed > 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pruning_is_bitwise_neutral(dtype):
+    """Skipping unreachable subtrees changes no iterate: with a threshold
+    (which makes such subtrees common) and without, single solves, a batch,
+    a depth-limited flop with exact leaves and the persistent launch."""
+    thr = 0.06
+    cases = I.batch_config(8, lambda sp: P.Tree(**sp).n_nodes, n=6, river_share=0.5, lo=10, hi=1500)
+    trees = [P.Tree(**sp) for sp, _ in cases]
+    ranges = np.stack([r for _, r in cases])
+    say(f"case: pruning neutrality, {dtype}, 6 subgames + a flop")
+    for t in (0.0, thr):
+        a = P.Batch(trees, ranges, P.SolverConfig(dtype=dtype, threshold=t, prune=0))
+        b = P.Batch(trees, ranges, P.SolverConfig(dtype=dtype, threshold=t, prune=1))
+        c = P.Batch(trees, ranges, P.SolverConfig(dtype=dtype, threshold=t, prune=1))
+        c.set_launch(True)
+        for x in (a, b, c):
+            x.iterate(40)
+        np.testing.assert_array_equal(_state_arrays(a, dtype), _state_arrays(b, dtype))
+        np.testing.assert_array_equal(_state_arrays(a, dtype), _state_arrays(c, dtype))
+        for k in range(len(trees)):
+            np.testing.assert_array_equal(a.root_cfv_of(k, "current"), b.root_cfv_of(k, "current"))
+    spec, r = I.flop_config(1, support=300)
+    t = P.Tree(**spec)
+    a = P.Solver(t, r, P.SolverConfig(dtype=dtype, threshold=thr))
+    b = P.Solver(t, r, P.SolverConfig(dtype=dtype, threshold=thr, prune=1))
+    a.iterate(40)
+    b.iterate(40)
+    np.testing.assert_array_equal(_state_arrays(a, dtype), _state_arrays(b, dtype))
+    np.testing.assert_array_equal(a.root_cfv("current"), b.root_cfv("current"))

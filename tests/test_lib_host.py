@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 30
     for n in names:
         assert hasattr(L, n), n
-    assert L.pcfr_abi_version() == 1
+    assert L.pcfr_abi_version() == 2
 
 
 SPECS = [

@@ -225,3 +225,57 @@ def test_alternating_reaches_the_game_value(kuhn):
     e, _ = s.exploitability()
     assert 0 <= e < 1e-3
     assert abs(s.root_cfv("avg")[0].sum() / s.pair_mass() + 1 / 18) < 1e-3
+
+
+# ---------------------------------------------------------------- dynamic thresholding
+THR0 = 0.08
+
+
+def rm_thr(R, thr):
+    """Regret matching, then probabilities below thr set to 0 and the rest renormalised."""
+    q = rm(R)
+    q = np.where(q < thr, 0.0, q)
+    return q / q.sum()
+
+
+def test_thresholded_iterations_match_brute_force(kuhn):
+    """Dynamic thresholding (cited in Sec. 2): iteration t matches on the
+    regrets, drops every action below thr0 / sqrt(t) and renormalises.  The
+    first 25 DCFR iterations against the brute-force enumeration, with the
+    threshold applied there independently; some action falls below it."""
+    s = O.Solver(kuhn, np.ones((2, 3)), ALPHA, BETA, GAMMA, threshold=THR0)
+    R = {k: np.zeros(2) for k in ((h, c) for h in INFOSETS for c in range(3))}
+    S = {k: np.zeros(2) for k in R}
+    cut = 0
+    for t in range(1, 26):
+        thr = THR0 / np.sqrt(t)
+        sig = {k: rm_thr(R[k], thr) for k in R}
+        cut += sum(int(((rm(R[k]) > 0) & (sig[k] == 0)).any()) for k in R)
+        reg, sadd = brute_iteration(sig)
+        dpos = t ** ALPHA / (t ** ALPHA + 1)
+        dneg = t ** BETA / (t ** BETA + 1)
+        for k in R:
+            x = R[k] + reg[k]
+            R[k] = np.where(x > 0, x * dpos, x * dneg)
+            S[k] = (S[k] + sadd[k]) * (t / (t + 1)) ** GAMMA
+        s.iterate(1)
+        Ro, So = s.rows("R"), s.rows("S")
+        rows_of = {0: 0, 1: 2, 2: 4, 4: 6}
+        for (h, c), v in R.items():
+            row = rows_of[NODE_OF[h]]
+            np.testing.assert_allclose(Ro[row:row + 2, c], v, atol=1e-13)
+            np.testing.assert_allclose(So[row:row + 2, c], S[(h, c)], atol=1e-13)
+        # the current strategy the oracle reports is the one iteration t + 1 will use
+        for (h, c) in R:
+            np.testing.assert_allclose(s.strategy(NODE_OF[h], "current")[:, c],
+                                       rm_thr(R[(h, c)], THR0 / np.sqrt(t + 1)), atol=1e-14)
+    assert cut > 0
+
+
+def test_thresholded_dcfr_reaches_the_game_value(kuhn):
+    s = O.Solver(kuhn, np.ones((2, 3)), ALPHA, BETA, GAMMA, threshold=THR0)
+    s.iterate(10000)
+    expl, _ = s.exploitability()
+    v = s.root_cfv("avg")
+    assert 0 <= expl < 1e-3
+    assert abs(v[0].sum() / s.pair_mass() + 1 / 18) < 1e-3

@@ -129,3 +129,15 @@ def test_zero_sum_shift_closed_forms():
     m0 = mlp.compatible_mass(reach[0], card)
     total = ((reach[0] * keep) * m1 * (ev[0] - d)).sum() + ((reach[1] * keep) * m0 * (ev[1] - d)).sum()
     assert abs(total) < 1e-9 * ((reach[0] * m1).sum())
+
+
+def test_zero_sum_shifts_batched_equals_per_row():
+    rng = np.random.default_rng(4)
+    board = [3, 17, 40]
+    from paper_2605_19928_amd import inputs as I
+    reach = np.stack([I.dirichlet_range(rng, board), I.dirichlet_range(rng, board, support=30)])
+    cards = [c for c in range(52) if c not in board][:7]
+    ev = rng.standard_normal((len(cards), 2, 1326))
+    got = mlp.zero_sum_shifts(ev, reach, cards)
+    want = [mlp.zero_sum_shift(ev[j], reach, c) for j, c in enumerate(cards)]
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-15)
