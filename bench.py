@@ -81,6 +81,7 @@ def parse():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--no-secondary", action="store_true", help="skip the turn and batch measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip training a leaf network and the exact flop solve")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="batch workload: skip timing the subgames one at a time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -197,6 +198,19 @@ def cpu_baseline(spec, r, budget_s, leaf_params=None):
         if n >= 2 and time.perf_counter() - t0 > budget_s:
             break
     sec = (time.perf_counter() - t0) / n
+    # one more iteration on a single thread (the oracle's OpenMP walk and the
+    # FP64 network refresh's BLAS both held to one thread)
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        ta = time.perf_counter()
+        refresh()
+        tb = time.perf_counter()
+        s.iterate(1, threads=1)
+        tc = time.perf_counter()
+    single = {"value": 1.0 / (tc - ta), "unit": "iters/s", "cores": 1,
+              "parts_s_per_iter": {"leaf_network": tb - ta, "walk": tc - tb},
+              "sample": f"one oracle iteration of the full workload on one thread: {tc - ta:.3f} s"}
     del s
     cpu_model = ""
     try:
@@ -216,6 +230,7 @@ def cpu_baseline(spec, r, budget_s, leaf_params=None):
         "sample": (f"{n} oracle iterations of the full workload (same tree, full ranges) after one warm-up, "
                    f"{sec:.3f} s each: FP64 leaf-network refresh {net_s / n:.3f} s + tree walk "
                    f"{walk_s / n:.3f} s on {cores} threads"),
+        "single_thread": single,
     }
 
 
@@ -486,36 +501,135 @@ def pruning_sweep(args, spec, r, steps, warmup, warm_iters=100, eps=0.1):
 
 def rbp_sweep(args, spec, r, steps, warmup, warm_iters=100):
     """Regret-based pruning of unreachable subtrees (exact: the iterates equal
-    the unpruned ones) on the turn of the tree-sweep line, without and with
-    dynamic thresholding (actions below thr0 / sqrt(t) dropped, which makes
-    unreachable subtrees common): ms/iter pruned vs unpruned at the same
-    threshold after warm_iters iterations, the share of nodes skipped, and
-    the exploitability after the same number of iterations."""
+    the unpruned ones) without and with dynamic thresholding (actions below
+    thr0 / sqrt(t) dropped): ms/iter pruned vs unpruned at the same threshold
+    after warm_iters iterations, the nodes skipped in the last iteration, and
+    the exploitability after the same number of iterations.  Two range
+    profiles: the turn of the tree-sweep line with full Dirichlet ranges
+    (every action is some hand's choice, so little is unreachable), and a
+    turn whose players hold 64 combos each."""
+    from paper_2605_19928_amd import inputs as I
     from paper_2605_19928_amd import pcfr as P
 
-    tree = P.Tree(**spec)
     out = []
-    for thr in (0.0, 0.05):
-        res = {"threshold_thr0": thr}
-        for prune in (0, 1):
-            s = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype, threshold=thr, prune=prune))
-            s.iterate(warm_iters)
-            ms = timed(s, steps, warmup)
-            res["ms_per_iter_pruned" if prune else "ms_per_iter_unpruned"] = ms
-            if prune:
-                res["nodes_skipped_last_iter"] = s.unreached_nodes()
-                res["iterations"] = warm_iters + warmup + steps
-                e, _ = s.exploitability()
-                res["exploitability_mbb_per_hand"] = e * 100.0
-            s.close()
-        res["nodes"] = tree.n_nodes
-        res["skipped_share"] = res["nodes_skipped_last_iter"] / tree.n_nodes
-        res["speedup"] = res["ms_per_iter_unpruned"] / res["ms_per_iter_pruned"]
-        log(f"regret-based pruning thr0={thr}: {res['ms_per_iter_unpruned']:.4f} -> {res['ms_per_iter_pruned']:.4f} "
-            f"ms/iter, {res['nodes_skipped_last_iter']} of {tree.n_nodes} nodes skipped, exploitability "
-            f"{res['exploitability_mbb_per_hand']:.1f} mbb/hand")
-        out.append(res)
+    sspec, sr = I.turn_config(0, support=64)
+    for label, sp, rr in (("full Dirichlet(1) ranges", spec, r), ("64-combo supports", sspec, sr)):
+        tree = P.Tree(**sp)
+        for thr in (0.0, 0.05):
+            res = {"ranges": label, "threshold_thr0": thr, "nodes": tree.n_nodes}
+            for prune in (0, 1):
+                s = P.Solver(tree, rr, P.SolverConfig(dtype=args.dtype, threshold=thr, prune=prune))
+                s.iterate(warm_iters)
+                ms = timed(s, steps, warmup)
+                res["ms_per_iter_pruned" if prune else "ms_per_iter_unpruned"] = ms
+                if prune:
+                    res["nodes_skipped_last_iter"] = s.unreached_nodes()
+                    res["iterations"] = warm_iters + warmup + steps
+                    e, _ = s.exploitability()
+                    res["exploitability_mbb_per_hand"] = e * 100.0
+                s.close()
+            res["skipped_share"] = res["nodes_skipped_last_iter"] / tree.n_nodes
+            res["speedup"] = res["ms_per_iter_unpruned"] / res["ms_per_iter_pruned"]
+            log(f"regret-based pruning, {label}, thr0={thr}: {res['ms_per_iter_unpruned']:.4f} -> "
+                f"{res['ms_per_iter_pruned']:.4f} ms/iter, {res['nodes_skipped_last_iter']} of {tree.n_nodes} nodes "
+                f"skipped, exploitability {res['exploitability_mbb_per_hand']:.1f} mbb/hand")
+            out.append(res)
     return out
+
+
+def learned_leaf_sweep(args, n_train=4096, gen_iters=200, train_steps=2000, iters=300):
+    """The learned leaf against the exact solve, trained in the bench run
+    (seeded, so every run regenerates the same network): n_train random turn
+    subgames solved by the batched plain solver give the training samples,
+    the library's bf16 kernels train the 4 x 1536 network with Adam, and the
+    headline flop is solved `iters` iterations with that network at its
+    depth-limit leaves and, exactly, dealt out to showdown.  Matched quality:
+    the root values under the average strategies of the learned-leaf solve
+    are within `root_value_gap` of the exact solve's after `iters`
+    iterations; the exact solver's own root values reach that distance from
+    its final values only after `exact_iterations_to_match` iterations, and
+    the time for that is set against the learned-leaf solve's."""
+    import torch
+
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+    from paper_2605_19928_amd import train as T
+
+    t0 = time.perf_counter()
+    X, Y, M, _ = T.generate(seed=101, n=n_train, iters=gen_iters, batch=512, dtype="f32")
+    gen_s = time.perf_counter() - t0
+    net = P.LeafNet(P.LEAF_D_IN, 1536, 4, P.LEAF_D_OUT, max_batch=1088)
+    net.set_params(he_params(net.layer_shapes(), 0))
+    t0 = time.perf_counter()
+    hist = T.train(net, X, Y, M, steps=train_steps, batch=1024, lr=5e-4, log_every=max(train_steps // 4, 1))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, Y, M
+    spec, r = I.flop_config(args.seed)
+    tree = P.Tree(**spec)
+    dl = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
+    dl.attach_leafnet(net)
+    dl.autotune(3)
+    ms_dl = timed(dl, iters, 0)
+    v_dl = dl.root_cfv("avg")
+    e_dl, _ = dl.exploitability()
+    dl.close()
+    stub = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
+    stub.iterate(iters)
+    v_stub = stub.root_cfv("avg")
+    stub.close()
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    tx = P.Tree(**dict(spec, depth_limit=0))
+    build_s = time.perf_counter() - t0
+    ex = P.Solver(tx, r, P.SolverConfig(dtype=args.dtype))
+    checkpoints = [k for k in (1, 2, 4, 8, 16, 32, 64, 128, 256) if k < iters] + [iters]
+    snaps, done, ms_ex = {}, 0, 0.0
+    for k in checkpoints:
+        ms_ex += timed(ex, k - done, 0) * (k - done)
+        done = k
+        snaps[k] = ex.root_cfv("avg")
+    e_ex, _ = ex.exploitability()
+    ex.close()
+    del ex
+    torch.cuda.empty_cache()
+    ms_ex /= iters
+    ref = snaps[iters]
+    gap = lambda v: float((r * np.abs(v - ref)).sum() / (2.0 * pair_mass(r)) * 100.0)
+    g_dl, g_stub = gap(v_dl), gap(v_stub)
+    curve = [(k, gap(snaps[k])) for k in checkpoints[:-1]]
+    match = next((k for k, g in curve if g <= g_dl), iters)
+    out = {
+        "workload": f"the headline flop (seed {args.seed}); network trained in this run on {n_train} turn subgames "
+                    f"x {gen_iters} solver iterations, {train_steps} Adam steps (batch 1024)",
+        "generate_s": gen_s, "train_s": train_s, "train_loss_first_last": [hist[0][1], hist[-1][1]],
+        "iterations": iters,
+        "learned_leaf_ms_per_iter": ms_dl, "learned_leaf_iters_per_s": 1000.0 / ms_dl,
+        "learned_leaf_exploitability_mbb_per_hand_in_depth_limited_game": e_dl * 100.0,
+        "exact_nodes": tx.n_nodes, "exact_tree_build_s": build_s,
+        "exact_ms_per_iter": ms_ex, "exact_iters_per_s": 1000.0 / ms_ex,
+        "exact_exploitability_mbb_per_hand": e_ex * 100.0,
+        "root_value_gap_mbb_per_hand": {"learned_leaves_vs_exact": g_dl, "checkdown_equity_leaves_vs_exact": g_stub},
+        "exact_root_value_gap_by_iterations": curve,
+        "exact_iterations_to_match": match,
+        "time_to_matched_quality_ms": {"learned_leaf": ms_dl * iters, "exact": ms_ex * match},
+        "speedup_at_matched_quality": (ms_ex * match) / (ms_dl * iters),
+    }
+    log(f"learned leaf: {ms_dl:.4f} ms/iter, gap {g_dl:.1f} mbb/hand to exact ({ms_ex:.2f} ms/iter); exact needs "
+        f"{match} iterations for that gap: {out['speedup_at_matched_quality']:.1f}x")
+    return out
+
+
+def pair_mass(r):
+    """Joint mass of compatible hand pairs."""
+    from paper_2605_19928_amd import inputs as I
+
+    cc = I.combo_cards()
+    card = np.zeros(52)
+    np.add.at(card, cc[:, 0], r[1])
+    np.add.at(card, cc[:, 1], r[1])
+    comp = r[1].sum() - card[cc[:, 0]] - card[cc[:, 1]] + r[1]
+    return float((r[0] * comp).sum())
 
 
 def spr_sweep(args, steps, warmup, seed=0):
@@ -728,7 +842,9 @@ def main():
             "bet_sizes_pct": spec["sizes"], "allin": True, "max_raises_per_street": spec["max_raises"],
             "nodes": tree.n_nodes, "decision_nodes": tree.n_decision, "network_leaves": n_leaves,
             "allin_leaves": tree.n_allin, "next_cards": n_next, "network_rows": rows, "hands": tree.n_hands,
-            "leaf_network": "2705 -> 4 x 1536 -> 2652 ReLU MLP, bf16 weights, fp32 accumulate, He init",
+            "leaf_network": "2705 -> 4 x 1536 -> 2652 ReLU MLP, bf16 weights, fp32 accumulate, He init "
+                            "(random weights: a throughput measurement; learned_leaf trains one and compares "
+                            "against the exact solve)",
             "leaf_network_params": net.n_params,
             "leaf_flops_per_iter": flops_alg,
         },
@@ -772,6 +888,8 @@ def main():
         result["leaf_gemm_m2048"] = gemm_shape_point(args)
         result["flop_batch"] = flop_batch_sweep(args, max(20, args.steps // 4), 5)
         result["hbm_copy_ceiling_gbs"] = copy_ceiling_gbs()
+        if not args.no_learned:
+            result["learned_leaf"] = learned_leaf_sweep(args)
         log(f"HBM copy ceiling: {result['hbm_copy_ceiling_gbs']:.0f} GB/s")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
