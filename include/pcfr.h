@@ -265,6 +265,15 @@ int32_t pcfr_synchronize(pcfr_solver* s);
 enum { PCFR_LAUNCH_GRAPH = 0, PCFR_LAUNCH_PERSISTENT = 1 };
 int32_t pcfr_solver_set_launch(pcfr_solver* s, int32_t mode);
 
+/* Terminal fusion of the graph launches, on (1) or off (0, the default).
+ * On: every decision node at a backward level swept by per-node launches
+ * that has one or two fold or showdown children evaluates them in its own
+ * workgroup (LDS) and reads their values there, instead of a separate
+ * terminal launch writing them to memory for the backward launch to read
+ * back.  The arithmetic is the same, so the iterates are bitwise equal
+ * either way.  Re-captures the iteration graph. */
+int32_t pcfr_solver_set_terminal_fusion(pcfr_solver* s, int32_t on);
+
 /* Nodes (over all subgames) that the last iteration found unreachable and
  * skipped, for a solver created with prune = 1 (else PCFR_E_STATE); with
  * alternating updates, those of the second half-step.  Synchronises. */

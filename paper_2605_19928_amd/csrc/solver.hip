@@ -296,12 +296,14 @@ __global__ __launch_bounds__(kSweepMaxBlock) void k_forward(const DNode* __restr
 // EARLY: load the average-strategy rows and own reach together with the
 // regrets (more registers, one memory round trip less on the critical path;
 // used where latency, not occupancy, limits).
-template <typename T, int MODE, int A, int NH, bool EARLY>
+// TF: children whose tv[a] is set (terminal values already evaluated by the
+// calling workgroup into LDS rows [2][Hp]) are read there instead of from cfv.
+template <typename T, int MODE, int A, int NH, bool EARLY, bool TF = false>
 __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, int Hp, T* __restrict__ R,
                                              T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach,
                                              T* __restrict__ cfv, const IterState* st,
                                              const uint16_t* __restrict__ hcards, T* __restrict__ root_dst,
-                                             int upd, bool dead) {
+                                             int upd, bool dead, const T* const* tv = nullptr) {
     // dead: no hand of either player reaches the node; its children's values
     // and its own reach are zero, so they are not loaded (regret-based pruning)
     using V = VN<T, NH>;
@@ -353,7 +355,10 @@ __device__ __forceinline__ void bwd_decision(const DNode& nd, int64_t n, int h, 
         const T* cc = cfv + (int64_t)(nd.first_child + a) * 2 * Hp;
         V d = {};
         if (dead) c[a] = V{};
-        else {
+        else if (TF && tv[a]) {
+            c[a] = ldv<NH>(tv[a] + (int64_t)p * Hp + h);
+            d = ldv<NH>(tv[a] + (int64_t)o * Hp + h);
+        } else {
             c[a] = ldv<NH>(cc + (int64_t)p * Hp + h);
             d = ldv<NH>(cc + (int64_t)o * Hp + h);
         }
@@ -650,10 +655,33 @@ __device__ __forceinline__ void block_sum2(T& a, T& b, T* xch) {
     for (int i = 0; i < kWaves; i++) { a += xch[i]; b += xch[kWaves + i]; }
 }
 
-// Exclusive scan over the workgroup of a and b in thread order; the totals
-// come back in ta, tb.  xch: LDS scratch of 2 * kWaves values.
+// Sums over the workgroup of a, b, c, d (every thread gets all four totals);
+// xch: LDS scratch of 4 * kWaves values.
 template <typename T>
-__device__ __forceinline__ void block_exscan2(T& a, T& b, T& ta, T& tb, T* xch) {
+__device__ __forceinline__ void block_sum4(T& a, T& b, T& c, T& d, T* xch) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+        d += __shfl_xor(d, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { xch[w] = a; xch[kWaves + w] = b; xch[2 * kWaves + w] = c; xch[3 * kWaves + w] = d; }
+    __syncthreads();
+    a = b = c = d = T(0);
+#pragma unroll
+    for (int i = 0; i < kWaves; i++) {
+        a += xch[i]; b += xch[kWaves + i]; c += xch[2 * kWaves + i]; d += xch[3 * kWaves + i];
+    }
+}
+
+// Exclusive scan over the workgroup of a and b in thread order; the totals
+// come back in ta, tb.  xch: LDS scratch of 2 * kWaves values.  With
+// c, d given, their plain workgroup sums come back in them, through the
+// same exchange (xch then holds 4 * kWaves values).
+template <typename T, bool SUM2 = false>
+__device__ __forceinline__ void block_exscan2(T& a, T& b, T& ta, T& tb, T* xch, T* c = nullptr, T* d = nullptr) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     T ia = a, ib = b;
 #pragma unroll
@@ -661,16 +689,32 @@ __device__ __forceinline__ void block_exscan2(T& a, T& b, T& ta, T& tb, T* xch) 
         const T ua = __shfl_up(ia, o), ub = __shfl_up(ib, o);
         if (lane >= o) { ia += ua; ib += ub; }
     }
-    if (lane == 63) { xch[w] = ia; xch[kWaves + w] = ib; }
+    T sc = T(0), sd = T(0);
+    if constexpr (SUM2) {
+        sc = *c;
+        sd = *d;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sc += __shfl_xor(sc, o);
+            sd += __shfl_xor(sd, o);
+        }
+    }
+    if (lane == 63) {
+        xch[w] = ia;
+        xch[kWaves + w] = ib;
+        if constexpr (SUM2) { xch[2 * kWaves + w] = sc; xch[3 * kWaves + w] = sd; }
+    }
     __syncthreads();
     T oa = T(0), ob = T(0);
     ta = T(0);
     tb = T(0);
+    if constexpr (SUM2) { *c = T(0); *d = T(0); }
 #pragma unroll
     for (int i = 0; i < kWaves; i++) {
         if (i < w) { oa += xch[i]; ob += xch[kWaves + i]; }
         ta += xch[i];
         tb += xch[kWaves + i];
+        if constexpr (SUM2) { *c += xch[2 * kWaves + i]; *d += xch[3 * kWaves + i]; }
     }
     a = oa + ia - a;
     b = ob + ib - b;
@@ -685,27 +729,27 @@ __device__ __forceinline__ void block_exscan2(T& a, T& b, T& ta, T& tb, T* xch) 
 // when no compatible opponent hand has reach at all: M is then exactly 0 (as
 // a sum over those hands is), not the rounding residue of the difference,
 // so hands whose every action is worth nothing tie exactly.
+// Core of the fold terminal: a[i], b[i] are the two players' reach of the
+// thread's hands tid + i * kBlock (read by the caller), v0 / v1 receive the
+// node's values (global or LDS rows of Hp).
 template <typename T>
-__device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
-                          const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
-                          const int16_t* __restrict__ chands, T* lds) {
+__device__ void term_fold_core(const DNode& nd, int Hp, T (&a)[kHandIt], T (&b)[kHandIt],
+                               const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
+                               const int16_t* __restrict__ chands, T* lds, T* v0, T* v1) {
     T* x0 = lds;                  // [Hp]
     T* x1 = x0 + Hp;              // [Hp]
     T* pc = x1 + Hp;              // [2][52], two half-sums per card first: [208]
     T* xch = pc + 208;            // [2 * kWaves] sums, then [2 * kWaves] counts; padded to 2 * kBlock
     int16_t* lst = reinterpret_cast<int16_t*>(xch + 2 * kBlock);     // [2 * Hp]
     int32_t* pcn = reinterpret_cast<int32_t*>(lst + 2 * Hp);         // [208]: per-card counts, as pc
-    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
-    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
     const int nl = coff[52];
     copy_i16<(2 * kMaxHp / 8 + kBlock - 1) / kBlock>(lst, chands, (nl + 7) & ~7);
-    T a[kHandIt], b[kHandIt];
     uint32_t c[kHandIt];
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int h = tid + i * kBlock;
-        if (h < Hp) { a[i] = r0[h]; b[i] = r1[h]; c[i] = hc[h]; }
+        if (h < Hp) c[i] = hc[h];
     }
     T s0 = T(0), s1 = T(0), n0 = T(0), n1 = T(0);
 #pragma unroll
@@ -738,8 +782,7 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
         pc[tid] = acc;
         pcn[tid] = cnt;
     }
-    block_sum2(s0, s1, xch);      // synchronises: the half-sums are visible after it
-    block_sum2(n0, n1, xch + kBlock);
+    block_sum4(s0, s1, n0, n1, xch);   // synchronises: the half-sums are visible after it
     T pcv0 = T(0), pcv1 = T(0);
     int pcn0 = 0, pcn1 = 0;
     if (tid < 104) { pcv0 = pc[2 * tid]; pcv1 = pc[2 * tid + 1]; pcn0 = pcn[2 * tid]; pcn1 = pcn[2 * tid + 1]; }
@@ -749,8 +792,6 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
     const int nz0 = (int)n0, nz1 = (int)n1;
     const int f = nd.player;
     const T pay = (T)nd.pay;
-    T* v0 = cfv + n * 2 * Hp;
-    T* v1 = v0 + Hp;
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int h = tid + i * kBlock;
@@ -766,6 +807,22 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
     }
 }
 
+template <typename T>
+__device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
+                          const uint16_t* __restrict__ hc, const int32_t* __restrict__ coff,
+                          const int16_t* __restrict__ chands, T* lds) {
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    T a[kHandIt], b[kHandIt];
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = threadIdx.x + i * kBlock;
+        if (h < Hp) { a[i] = r0[h]; b[i] = r1[h]; }
+    }
+    T* v0 = cfv + n * 2 * Hp;
+    term_fold_core<T>(nd, Hp, a, b, hc, coff, chands, lds, v0, v0 + Hp);
+}
+
 // Showdown on a five-card board: hands sorted by value ascending (perm),
 // with tie groups [glo, ghi) in sorted positions; every card has the list of
 // sorted positions of hands holding it, ascending, followed by one slot for
@@ -775,9 +832,12 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
 // lists only hands alive on it, so no dealt-card masking is needed.  As for
 // folds, a hand none of whose compatible opponent hands has nonzero reach
 // (counted by the same inclusion-exclusion) gets exactly 0.
+// Core of the showdown terminal: ra[i], rb[i] are the two players' reach of
+// hand tid + i * kBlock in hand order (read by the caller); v0 / v1 receive
+// the node's values.
 template <typename T>
-__device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
-                              const uint16_t* __restrict__ hc, const int16_t* __restrict__ tb, int Hb, T* lds) {
+__device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T (&rb)[kHandIt],
+                                   const int16_t* __restrict__ tb, int Hb, T* lds, T* v0, T* v1) {
     const int QN = 2 * Hp + kSdHeader;
     T* xs0 = lds;                 // [Hp + 4]: sorted reach, then its exclusive prefix
     T* xs1 = xs0 + (Hp + 4);
@@ -794,8 +854,6 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     const int16_t* ahi = tb + 4 * Hp;
     const int16_t* blo = tb + 5 * Hp;
     const int16_t* bhi = tb + 6 * Hp;
-    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
-    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
     const int tid = threadIdx.x;
 
     // Every global load first, none through the permutation: the card-list
@@ -809,7 +867,6 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     const uint16_t* scard = reinterpret_cast<const uint16_t*>(tb + 7 * Hp);
     int s_gl[kHandIt], s_gh[kHandIt], s_al[kHandIt], s_ah[kHandIt], s_bl[kHandIt], s_bh[kHandIt];
     uint32_t cc[kHandIt];
-    T ra[kHandIt], rb[kHandIt];
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int s = tid + i * kBlock;
@@ -818,7 +875,6 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
             s_ah[i] = ahi[s]; s_bl[i] = blo[s]; s_bh[i] = bhi[s];
             cc[i] = scard[s];
         }
-        if (s < Hp) { ra[i] = r0[s]; rb[i] = r1[s]; }
     }
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
@@ -879,8 +935,7 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         n1 += l1[i] != T(0) ? T(1) : T(0);
     }
     T tot0, tot1;
-    block_exscan2(s0, s1, tot0, tot1, xch);   // synchronises: every chunk was read above
-    block_sum2(n0, n1, xch + kBlock);
+    block_exscan2<T, true>(s0, s1, tot0, tot1, xch, &n0, &n1);   // synchronises: every chunk was read above
     const int nz0 = (int)n0, nz1 = (int)n1;
     __syncthreads();                          // all reads of xs done before it is overwritten
 #pragma unroll
@@ -897,8 +952,6 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     __syncthreads();
 
     const T pay = (T)nd.pay;
-    T* v0 = cfv + n * 2 * Hp;
-    T* v1 = v0 + Hp;
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int s = tid + i * kBlock;
@@ -918,6 +971,21 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
         v0[h] = any1 ? pay * (w1 - lo1) : T(0);
         v1[h] = any0 ? pay * (w0 - lo0) : T(0);
     }
+}
+
+template <typename T>
+__device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
+                              const uint16_t* __restrict__ hc, const int16_t* __restrict__ tb, int Hb, T* lds) {
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    T ra[kHandIt], rb[kHandIt];
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int s = threadIdx.x + i * kBlock;
+        if (s < Hp) { ra[i] = r0[s]; rb[i] = r1[s]; }
+    }
+    T* v0 = cfv + n * 2 * Hp;
+    term_showdown_core<T>(nd, Hp, ra, rb, tb, Hb, lds, v0, v0 + Hp);
 }
 
 template <typename T>
@@ -943,6 +1011,89 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
         term_fold<T>(nd, n, Hp, reach, cfv, hc, coff + nd.sub * 53, chands + (int64_t)nd.sub * chand_stride, lds);
     else
         term_showdown<T>(nd, n, Hp, reach, cfv, hc, sd + (int64_t)nd.aux * sd_stride, sd_n[nd.aux], lds);
+}
+
+// ------------------------------------------------------------ terminal-fused backward
+// A decision node whose children include fold or showdown nodes, swept by
+// one workgroup over all its hands: the terminal children are evaluated into
+// LDS (the same arithmetic as k_terminal, from the reach rows the forward
+// sweep wrote), then the node's backward work reads them there instead of a
+// round trip of their value rows through memory.  At most two such children
+// per node (a fold and a showdown).  val: LDS [2][2][Hp] after the terminal
+// scratch.
+template <typename T, int A>
+__device__ void tf_node(const DNode& nd, const DNode* __restrict__ nodes, int Hp, T* __restrict__ R,
+                        T* __restrict__ S, T* __restrict__ Mp, const T* __restrict__ reach, T* __restrict__ cfv,
+                        const IterState* __restrict__ st, const uint16_t* __restrict__ hcards,
+                        const int32_t* __restrict__ coff, const int16_t* __restrict__ chands, int chand_stride,
+                        const int16_t* __restrict__ sd, int64_t sd_stride, const int32_t* __restrict__ sd_n,
+                        T* __restrict__ root_dst, int upd, const int32_t* __restrict__ nzs, T* lds, T* val) {
+    const bool dead = node_dead(nzs, nd);
+    const T* tv[A];
+#pragma unroll
+    for (int a = 0; a < A; a++) tv[a] = nullptr;
+    if (!dead) {
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < A; a++) {
+            const DNode ch = nodes[nd.first_child + a];
+            if (ch.type != PCFR_NODE_FOLD && ch.type != PCFR_NODE_SHOWDOWN) continue;
+            if (k) __syncthreads();   // the previous evaluation's LDS scratch is consumed
+            T* out = val + (int64_t)k * 2 * Hp;
+            const T* r0 = reach + (int64_t)ch.slot[0] * Hp;
+            const T* r1 = reach + (int64_t)ch.slot[1] * Hp;
+            T xa[kHandIt], xb[kHandIt];
+#pragma unroll
+            for (int i = 0; i < kHandIt; i++) {
+                const int h = threadIdx.x + i * kBlock;
+                if (h < Hp) { xa[i] = r0[h]; xb[i] = r1[h]; }
+            }
+            const uint16_t* hc = hcards + (int64_t)ch.sub * Hp;
+            if (ch.type == PCFR_NODE_FOLD)
+                term_fold_core<T>(ch, Hp, xa, xb, hc, coff + ch.sub * 53, chands + (int64_t)ch.sub * chand_stride, lds,
+                                  out, out + Hp);
+            else
+                term_showdown_core<T>(ch, Hp, xa, xb, sd + (int64_t)ch.aux * sd_stride, sd_n[ch.aux], lds, out,
+                                      out + Hp);
+            tv[a] = out;
+            k++;
+        }
+        __syncthreads();   // every terminal value visible to every thread
+    }
+#pragma unroll
+    for (int i = 0; i < kHandIt; i++) {
+        const int h = threadIdx.x + i * kBlock;
+        if (h < Hp)
+            bwd_decision<T, MODE_ITER, A, 1, false, true>(nd, nd.id, h, Hp, R, S, Mp, reach, cfv, st, hcards, root_dst,
+                                                          upd, dead, tv);
+    }
+}
+
+template <typename T, int MAXA>
+__global__ __launch_bounds__(kBlock) void k_backward_tf(const DNode* __restrict__ rec, const DNode* __restrict__ nodes,
+                                                        int Hp, T* __restrict__ R, T* __restrict__ S,
+                                                        T* __restrict__ Mp, const T* __restrict__ reach,
+                                                        T* __restrict__ cfv, const IterState* __restrict__ st,
+                                                        const uint16_t* __restrict__ hcards,
+                                                        const int32_t* __restrict__ coff,
+                                                        const int16_t* __restrict__ chands, int chand_stride,
+                                                        const int16_t* __restrict__ sd, int64_t sd_stride,
+                                                        const int32_t* __restrict__ sd_n, T* __restrict__ root_dst,
+                                                        int upd, const int32_t* __restrict__ nzs, int val_off) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    T* val = reinterpret_cast<T*>(smem + val_off);
+    const DNode nd = rec[blockIdx.x];
+    switch (nd.n_child) {
+#define PCFR_TF_CASE(A) \
+    case A:             \
+        if constexpr (A <= MAXA) tf_node<T, A>(nd, nodes, Hp, R, S, Mp, reach, cfv, st, hcards, coff, chands, chand_stride, sd, sd_stride, sd_n, root_dst, upd, nzs, lds, val); \
+        break;
+        PCFR_TF_CASE(1) PCFR_TF_CASE(2) PCFR_TF_CASE(3) PCFR_TF_CASE(4) PCFR_TF_CASE(5) PCFR_TF_CASE(6)
+        PCFR_TF_CASE(7) PCFR_TF_CASE(8) PCFR_TF_CASE(9) PCFR_TF_CASE(10) PCFR_TF_CASE(11) PCFR_TF_CASE(12)
+#undef PCFR_TF_CASE
+        default: break;
+    }
 }
 
 // ------------------------------------------------------------ persistent launch
@@ -1618,7 +1769,7 @@ struct Plan {
     size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_zs, off_agg, off_rc, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
-        off_eqgrp, off_nsub, off_b4, off_nzs,
+        off_eqgrp, off_nsub, off_b4, off_nzs, off_tfrec, off_tfrest, off_tfterm,
         off_cmap, off_hmap, total;
     size_t lds_bytes, lds_fold, lds_show;
     int64_t n_grp = 0, n_grp_allin = 0;   // equity groups: all leaves, the all-in prefix
@@ -2057,6 +2208,10 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
                       align256(sizeof(int16_t) * (size_t)P.n_sub * kCombos));
     L.off_eqpart = take(L.esz * kEqSplit * L.n_eq * 2 * L.Hp);
     L.off_nzs = take(sizeof(int32_t) * (size_t)(2 * P.n_sub + L.rows));   // pruning flags per reach slot
+    // terminal fusion: node records of the fused and the remaining backward work, terminals left over
+    L.off_tfrec = take(sizeof(DNode) * std::max<size_t>(P.dec.size(), 1));
+    L.off_tfrest = take(sizeof(DNode) * std::max<size_t>(P.fwd.size(), 1));
+    L.off_tfterm = take(sizeof(int32_t) * std::max<size_t>(P.term.size(), 1));
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
     const size_t sd_lds = L.esz * (2 * (L.Hp + 4) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn + L.Hp) +
@@ -2105,6 +2260,17 @@ struct pcfr_solver {
     int64_t t_host = 0;     // iterations enqueued
     int32_t launch_mode = PCFR_LAUNCH_GRAPH;
     int32_t persist_grid = 0, persist_maxa = 0;   // persistent launch: resident workgroups, action bucket
+    // terminal fusion (k_backward_tf): off by default (one workgroup per
+    // parent runs its terminals and its backward in series, slower on turns
+    // than the separate wide launches); the plan follows the level-fusion
+    // schedule and is rebuilt with the graph
+    bool tf_enabled = false;
+    struct {
+        bool on = false;
+        std::vector<int64_t> tf_off, rest_off;   // per level starts into the device record arrays
+        int64_t n_fold = 0, n_show = 0;          // terminals left to k_terminal
+        size_t lds = 0, val_off = 0;             // dynamic LDS of k_backward_tf, offset of its value rows
+    } tf;
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
     ~pcfr_solver() {
         if (stream && ws) (void)hipStreamSynchronize(stream);
@@ -2170,7 +2336,8 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            nzs + 2 * P.n_sub, n, 0);
     }
     // with thresholding every forward launch reads this iteration's
-    // threshold, so t advances in a launch of its own
+    // threshold (thr_st), so t advances in a launch of its own
+    const IterState* thr_st = (MODE == MODE_ITER && s->cfg.threshold > 0) ? st : nullptr;
     if (first && s->cfg.threshold > 0) {
         hipLaunchKernelGGL(k_begin_iteration, dim3(1), dim3(1), 0, stream, st);
         first = false;
@@ -2183,7 +2350,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             while (l1 < P.levels && dec_cnt(l1) * groups <= fuse) ma = std::max(ma, P.lvl_maxa[l1++]);
             if (tm) tm->before(1);
             PCFR_BUCKET_MA(k_forward_fused, ma, fgrid, dim3(kFuseBlock), 0, stream, dec, s->at<int64_t>(L.off_decoff), l,
-                           l1, Hp, (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr, st, nzs);
+                           l1, Hp, (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr, thr_st, nzs);
             if (tm) tm->after();
             first = false;
             l = l1;
@@ -2194,7 +2361,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         dim3 grid((unsigned)((threads + bs - 1) / bs));
         if (tm) tm->before(1, l);
         PCFR_BUCKET(k_forward, l, grid, dim3(bs), 0, stream, dec + P.dec_off[l], (int)cnt, Hp,
-                    (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr, st, nzs);
+                    (int)(2 * P.n_sub), R, S, Mp, reach, first ? st : nullptr, thr_st, nzs);
         if (tm) tm->after();
         first = false;
         l++;
@@ -2208,14 +2375,18 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         HIPCHK(hipEventRecord(s->ev_fork, stream));
         HIPCHK(hipStreamWaitEvent(side, s->ev_fork, 0));
     }
-    // terminals: folds and showdowns in separate launches, each with the LDS it needs
-    const int64_t n_fold = (int64_t)P.folds.size(), n_show = (int64_t)P.shows.size();
+    // terminals: folds and showdowns in separate launches, each with the LDS it
+    // needs; with terminal fusion only those whose parent does not evaluate them
+    const bool tfo = MODE == MODE_ITER && s->tf.on;
+    const int64_t n_fold = tfo ? s->tf.n_fold : (int64_t)P.folds.size();
+    const int64_t n_show = tfo ? s->tf.n_show : (int64_t)P.shows.size();
+    const int32_t* tlist = s->at<int32_t>(tfo ? L.off_tfterm : L.off_term);
     for (int kind = 0; kind < 2; kind++) {
         const int64_t cnt = kind ? n_show : n_fold;
         if (!cnt) continue;
         if (tm) tm->before(2);
         hipLaunchKernelGGL((k_terminal<T>), dim3((unsigned)cnt), dim3(kBlock), kind ? L.lds_show : L.lds_fold, side,
-                           nodes, s->at<int32_t>(L.off_term) + (kind ? n_fold : 0), Hp, reach, cfv,
+                           nodes, tlist + (kind ? n_fold : 0), Hp, reach, cfv,
                            s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
                            (int)L.chand_stride, s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride,
                            s->at<int32_t>(L.off_sdn), nzs);
@@ -2310,13 +2481,40 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
             continue;
         }
         const int bs = s->sched.bwd_block[l];
-        const int64_t threads = cnt * groups;
-        dim3 grid((unsigned)((threads + bs - 1) / bs));
-        if (tm) tm->before(3, 1000 + l);
-        PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, fwd + P.fwd_off[l], (int)cnt, Hp, R, S, Mp,
-                    reach, cfv, st, s->at<uint16_t>(L.off_hc),
-                    (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr, upd, iso, nzs);
-        if (tm) tm->after();
+        T* rootd = (MODE == MODE_ITER && l == 0) ? s->at<T>(L.off_root) : nullptr;
+        const DNode* lrec = fwd + P.fwd_off[l];
+        int64_t lcnt = cnt;
+        if (tfo) {
+            lrec = s->at<DNode>(L.off_tfrest) + s->tf.rest_off[l];
+            lcnt = s->tf.rest_off[l + 1] - s->tf.rest_off[l];
+            const int64_t ntf = s->tf.tf_off[l + 1] - s->tf.tf_off[l];
+            if constexpr (MODE == MODE_ITER) {
+                if (ntf) {
+                    if (tm) tm->before(3);   // untagged: its workgroup size is fixed
+                    const int ma = P.lvl_maxa[l];
+#define PCFR_TF_LAUNCH(MA)                                                                                          \
+    hipLaunchKernelGGL((k_backward_tf<T, MA>), dim3((unsigned)ntf), dim3(kBlock), s->tf.lds, stream,                  \
+                       s->at<DNode>(L.off_tfrec) + s->tf.tf_off[l], nodes, Hp, R, S, Mp, reach, cfv, st,              \
+                       s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),           \
+                       (int)L.chand_stride, s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn), \
+                       rootd, upd, nzs, (int)s->tf.val_off)
+                    if (ma <= 3) PCFR_TF_LAUNCH(3);
+                    else if (ma <= 6) PCFR_TF_LAUNCH(6);
+                    else if (ma <= 8) PCFR_TF_LAUNCH(8);
+                    else PCFR_TF_LAUNCH(12);
+#undef PCFR_TF_LAUNCH
+                    if (tm) tm->after();
+                }
+            }
+        }
+        if (lcnt) {
+            const int64_t threads = lcnt * groups;
+            dim3 grid((unsigned)((threads + bs - 1) / bs));
+            if (tm) tm->before(3, 1000 + l);
+            PCFR_BUCKET(k_backward, l, grid, dim3(bs), 0, stream, lrec, (int)lcnt, Hp, R, S, Mp,
+                        reach, cfv, st, s->at<uint16_t>(L.off_hc), rootd, upd, iso, nzs);
+            if (tm) tm->after();
+        }
         l--;
     }
 #undef PCFR_BUCKET_MA
@@ -2343,10 +2541,80 @@ static int32_t sweep(pcfr_solver* s, hipStream_t stream) {
 template <int MODE>
 static int32_t sweep(pcfr_solver* s) { return sweep<MODE>(s, s->stream); }
 
+// Terminal fusion plan: every decision node at a backward level swept by
+// per-node launches (not level-fused) with one or two fold or showdown
+// children evaluates them itself (k_backward_tf); the other nodes of the
+// level stay with k_backward and the other terminals with k_terminal.
+template <typename T>
+static int32_t tf_attrs(size_t lds) {
+    if (lds <= 65536) return PCFR_OK;
+    const void* ks[4] = {reinterpret_cast<const void*>(&k_backward_tf<T, 3>), reinterpret_cast<const void*>(&k_backward_tf<T, 6>),
+                         reinterpret_cast<const void*>(&k_backward_tf<T, 8>), reinterpret_cast<const void*>(&k_backward_tf<T, 12>)};
+    for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return PCFR_OK;
+}
+
+static int32_t make_tf_plan(pcfr_solver* s) {
+    const Prepared& P = s->P;
+    const Plan& L = s->L;
+    auto& tf = s->tf;
+    tf.on = false;
+    tf.tf_off.assign(P.levels + 1, 0);
+    tf.rest_off.assign(P.levels + 1, 0);
+    if (!s->tf_enabled) return PCFR_OK;
+    const int64_t groups = L.Hp / 4, fuse = s->sched.fuse_threads;
+    std::vector<DNode> tf_rec, rest_rec;
+    std::vector<char> handled(P.nodes.size(), 0);
+    for (int l = 0; l < P.levels; l++) {
+        tf.tf_off[l] = (int64_t)tf_rec.size();
+        tf.rest_off[l] = (int64_t)rest_rec.size();
+        const bool fused = (P.fwd_off[l + 1] - P.fwd_off[l]) * groups <= fuse;
+        for (int64_t k = P.fwd_off[l]; k < P.fwd_off[l + 1]; k++) {
+            const DNode& d = P.fwd_rec[k];
+            int nt = 0;
+            if (!fused && d.type == PCFR_NODE_DECISION)
+                for (int a = 0; a < d.n_child; a++) {
+                    const int32_t t = P.nodes[d.first_child + a].type;
+                    nt += t == PCFR_NODE_FOLD || t == PCFR_NODE_SHOWDOWN;
+                }
+            if (nt >= 1 && nt <= 2) {
+                tf_rec.push_back(d);
+                for (int a = 0; a < d.n_child; a++) handled[d.first_child + a] = 1;
+            } else {
+                rest_rec.push_back(d);
+            }
+        }
+    }
+    tf.tf_off[P.levels] = (int64_t)tf_rec.size();
+    tf.rest_off[P.levels] = (int64_t)rest_rec.size();
+    std::vector<int32_t> term;
+    for (int32_t x : P.folds) if (!handled[x]) term.push_back(x);
+    tf.n_fold = (int64_t)term.size();
+    for (int32_t x : P.shows) if (!handled[x]) term.push_back(x);
+    tf.n_show = (int64_t)term.size() - tf.n_fold;
+    if (tf_rec.empty()) return PCFR_OK;
+    tf.val_off = (L.lds_bytes + 15) & ~(size_t)15;
+    tf.lds = tf.val_off + 4 * L.Hp * L.esz;
+    if (tf.lds > 160 * 1024) return PCFR_OK;   // does not fit: stay with k_terminal
+    int32_t rc = L.esz == 8 ? tf_attrs<double>(tf.lds) : tf_attrs<float>(tf.lds);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(s->ws + L.off_tfrec, tf_rec.data(), sizeof(DNode) * tf_rec.size(), hipMemcpyHostToDevice, s->stream));
+    if (!rest_rec.empty())
+        HIPCHK(hipMemcpyAsync(s->ws + L.off_tfrest, rest_rec.data(), sizeof(DNode) * rest_rec.size(), hipMemcpyHostToDevice,
+                              s->stream));
+    if (!term.empty())
+        HIPCHK(hipMemcpyAsync(s->ws + L.off_tfterm, term.data(), sizeof(int32_t) * term.size(), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    tf.on = true;
+    return PCFR_OK;
+}
+
 // One iteration's launch sequence, captured once on a private stream (the
 // caller's may be the legacy default stream, which cannot be captured) and
 // replayed on the caller's stream.
 static int32_t build_graph(pcfr_solver* s) {
+    int32_t rc0 = make_tf_plan(s);
+    if (rc0) return rc0;
     hipStream_t cs = nullptr;
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -3146,6 +3414,12 @@ int32_t pcfr_solver_unreached_nodes(pcfr_solver* s, int64_t* n) {
         if (nzs[d.slot[0]] == 0 && nzs[d.slot[1]] == 0) cnt++;
     *n = cnt;
     return PCFR_OK;
+}
+
+int32_t pcfr_solver_set_terminal_fusion(pcfr_solver* s, int32_t on) {
+    if (!s || (on != 0 && on != 1)) { set_error("null solver or flag not 0/1"); return PCFR_E_INVALID_ARG; }
+    s->tf_enabled = on != 0;
+    return rebuild_graph(s);
 }
 
 int32_t pcfr_solver_set_launch(pcfr_solver* s, int32_t mode) {

@@ -57,6 +57,7 @@ _SIGS = {
     "pcfr_prune_dominated": (C.c_int32, [C.c_void_p] * 5),
     "pcfr_prune_dominated_noalloc": (C.c_int32, [C.c_void_p] * 5),
     "pcfr_solver_set_launch": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "pcfr_solver_set_terminal_fusion": (C.c_int32, [C.c_void_p, C.c_int32]),
     "pcfr_solver_unreached_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pcfr_tree_prune": (C.c_int32, [C.c_void_p] * 4),
     "pcfr_solver_swept_nodes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -331,6 +332,10 @@ class Solver:
         graph replays of per-level launches (False, the default); the iterates
         are bitwise the same."""
         _check(lib().pcfr_solver_set_launch(self._h, 1 if persistent else 0))
+
+    def set_terminal_fusion(self, on: bool):
+        """Evaluate fold/showdown children inside their parent's backward launch (default off)."""
+        _check(lib().pcfr_solver_set_terminal_fusion(self._h, 1 if on else 0))
 
     def unreached_nodes(self) -> int:
         """Nodes the last iteration skipped as unreachable (solvers with prune=1)."""
