@@ -55,16 +55,17 @@ BF16_PEAK_TFLOPS = 2500.0
 # tables and commands in profiles/*_hbm_counters.md).  They describe the
 # kernels as they were measured; a changed kernel needs a new measurement.
 MEASURED_TRAFFIC = {
-    # k_gemm_nt<BM,BN,1,KS,PF> (hidden layers, bias + ReLU), 1029 rows: per
-    # launch for each forward tile (PCFR_TILE_*), averaged over the hidden
-    # layers that used it in the counter runs: (read, write) bytes
-    "gemm_hidden_by_tile": {0: (38504466, 3342336), 1: (37855857, 3342336), 2: (43517046, 3342336),
-                            3: (43587955, 3342336), 4: (39483758, 3342336), 5: (43535477, 3342336),
-                            6: (35164813, 3342336), 7: (43539573, 3342336), 8: (31696514, 3342336),
-                            9: (31653864, 3342336)},
+    # hidden-layer GEMMs (bias + ReLU; k_gemm_nt<BM,BN,1,KS,PF> and
+    # k_gemm_direct<4,KSPLIT,..>), 1029 rows: per launch for each forward tile
+    # (PCFR_TILE_*), averaged over that tile's dispatches in the counter run
+    # (the autotuner's trials on the input and hidden layers): (read, write) bytes
+    "gemm_hidden_by_tile": {0: (28313758, 3342336), 1: (27523328, 3342336), 2: (27516928, 3342336),
+                            3: (27592704, 3342336), 4: (31257147, 3342336), 5: (27551872, 3342336),
+                            6: (27490667, 3342336), 7: (27545685, 3342336), 8: (23071744, 3342336),
+                            9: (23026688, 3342336), 10: (23012096, 3342336)},
     # k_backward<float,0,*> + k_backward_fused over one iteration of the
     # seed-0 turn subgame (all backward launches)
-    "turn_backward_iteration": 2440954947,
+    "turn_backward_iteration": 2442259200,
 }
 CLASSES = ["bookkeeping", "forward", "terminal", "backward", "leaves", "leaf_gemm_hidden", "leaf_gemm_out"]
 
