@@ -80,6 +80,10 @@ def lib():
             "ora_set_variant": (None, [P, I]),
             "ora_set_alternating": (None, [P, I]),
             "ora_set_threshold": (None, [P, D]),
+            "ora_canonical_flops": (I, [P, P, I]),
+            "ora_set_flop_leaf_table": (I, [P, P]),
+            "ora_has_flop_leaves": (I, [P]),
+            "ora_leaf_cfv": (I, [P, I, I, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -91,6 +95,20 @@ def lib():
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+N_CANONICAL_FLOPS = 1755
+
+
+def canonical_flops():
+    """The flops that no suit permutation maps to a smaller 52-bit card mask,
+    by their sorted cards in lexicographic order, with the size of each one's
+    orbit: (cards [1755, 3], orbit [1755])."""
+    cards = np.zeros((N_CANONICAL_FLOPS, 3), dtype=np.int32)
+    orbit = np.zeros(N_CANONICAL_FLOPS, dtype=np.int32)
+    n = lib().ora_canonical_flops(_p(cards), _p(orbit), N_CANONICAL_FLOPS)
+    assert n == N_CANONICAL_FLOPS
+    return cards, orbit
 
 
 def eval5(cards) -> int:
@@ -136,6 +154,7 @@ class Tree:
         (self.n_nodes, self.n_decision, self.n_fold, self.n_showdown, self.n_chance,
          self.n_leaf, self.n_allin, self.n_levels, self.n_rows) = (int(x) for x in info)
         self.nh = 3 if kuhn else NCOMBO
+        self.flop_leaves = bool(lib().ora_has_flop_leaves(self._h))
 
     @classmethod
     def holdem(cls, board, pot, stacks, sizes, allin=True, max_raises=2, depth_limit=0):
@@ -232,7 +251,12 @@ class Solver:
             raise ValueError("threshold must lie in [0, 1/12)")
         lib().ora_set_threshold(self._h, float(threshold))
 
+    def _leaves_ready(self):
+        if self.tree.flop_leaves and not getattr(self, "_flop_ev_set", False):
+            raise ValueError("a preflop tree's leaves need a flop leaf table (set_flop_leaf_table)")
+
     def iterate(self, n: int, threads: int = 0):
+        self._leaves_ready()
         lib().ora_iterate(self._h, int(n), int(threads))
 
     @property
@@ -261,6 +285,7 @@ class Solver:
         lib().ora_set_rows(self._h, _p(R), _p(S), int(t))
 
     def root_cfv(self, which: str = "current") -> np.ndarray:
+        self._leaves_ready()
         out = np.zeros((2, self.tree.nh), dtype=np.float64)
         if which == "current":
             lib().ora_root_cfv_current(self._h, _p(out))
@@ -272,6 +297,7 @@ class Solver:
         return float(lib().ora_pair_mass(self._h))
 
     def exploitability(self):
+        self._leaves_ready()
         br = np.zeros(2, dtype=np.float64)
         e = lib().ora_exploitability(self._h, _p(br))
         return float(e), br
@@ -279,7 +305,28 @@ class Solver:
     def num_leaves(self) -> int:
         return int(lib().ora_num_leaves(self._h))
 
+    def set_flop_leaf_table(self, ev: np.ndarray):
+        """Preflop trees: ev[leaf][player][flop][1326], expected values per
+        unit of pot on the canonical flops (canonical_flops() order)."""
+        ev = np.ascontiguousarray(ev, dtype=np.float64)
+        assert ev.shape == (self.num_leaves(), 2, N_CANONICAL_FLOPS, self.tree.nh)
+        if lib().ora_set_flop_leaf_table(self._h, _p(ev)) != 0:
+            raise ValueError("the tree has no leaf at the flop deal")
+        self._flop_ev_set = True
+
+    def leaf_cfv(self, node: int, player: int, r_opp) -> np.ndarray:
+        """Leaf node's counterfactual values of `player`'s hands against the
+        opponent reach r_opp [1326] (sum over histories of reach x leaf value)."""
+        self._leaves_ready()
+        ro = np.ascontiguousarray(r_opp, dtype=np.float64)
+        out = np.zeros(self.tree.nh, dtype=np.float64)
+        if lib().ora_leaf_cfv(self._h, int(node), int(player), _p(ro), _p(out)) != 0:
+            raise ValueError("not a leaf")
+        return out
+
     def set_leaf_table(self, ev: np.ndarray):
+        if self.tree.flop_leaves:
+            raise ValueError("a preflop tree takes a flop leaf table")
         ev = np.ascontiguousarray(ev, dtype=np.float64)
         assert ev.size == self.num_leaves() * 2 * 52 * self.tree.nh
         self._ev = ev

@@ -167,6 +167,7 @@ typedef struct {
     int kuhn;
     int64_t pot, cap;         /* cap = pot/2 + effective stack (max contribution) */
     int n_sizes, size_pct[8], allin, max_raises, depth_limit;
+    int err;                  /* set when the spec asks for something the builder does not support */
     /* pool */
     int n, capn;
     tnode* v;
@@ -208,6 +209,12 @@ static int b_street_end(builder* b, bstate s) {
     if (b->kuhn || s.nb == 5)
         return b_new(b, T_SHOW, -1, s.depth, s.c, s.nb, s.board, s.chance_card);
     int allin = (s.c[0] >= b->cap || s.c[1] >= b->cap);
+    /* Preflop (no board): only depth-limited trees whose betting never puts a
+     * player all in are built; their leaves sit at the flop deal. */
+    if (s.nb == 0 && (allin || !b->depth_limit)) {
+        b->err = 1;
+        return b_new(b, T_LEAF, -1, s.depth, s.c, s.nb, s.board, s.chance_card);
+    }
     if (b->depth_limit)
         return b_new(b, allin ? T_ALLIN : T_LEAF, -1, s.depth, s.c, s.nb, s.board, s.chance_card);
     int id = b_new(b, T_CHANCE, -1, s.depth, s.c, s.nb, s.board, s.chance_card);
@@ -469,13 +476,14 @@ static double* game_eq(ogame* g, int bi) {
 /* Equity tables are built before any parallel walk reads them. */
 static void game_prepare_leaves(ogame* g) {
     for (int i = 0; i < g->n; i++)
-        if (g->nd[i].type == T_LEAF || g->nd[i].type == T_ALLIN) game_eq(g, g->nd[i].bid);
+        if ((g->nd[i].type == T_LEAF || g->nd[i].type == T_ALLIN) && g->nd[i].nb > 0) game_eq(g, g->nd[i].bid);
 }
 
 /* Build a hold'em subgame.  Returns NULL on invalid input. */
 ogame* ora_build_tree(int n_board, const int32_t* board, int64_t pot, int64_t stack0, int64_t stack1,
                       int n_sizes, const int32_t* size_pct, int allin, int max_raises, int depth_limit) {
-    if (n_board < 3 || n_board > 5 || pot <= 0 || (pot & 1) || stack0 < 0 || stack1 < 0) return NULL;
+    if ((n_board != 0 && n_board < 3) || n_board > 5 || pot <= 0 || (pot & 1) || stack0 < 0 || stack1 < 0)
+        return NULL;
     if (n_sizes < 0 || n_sizes > 8 || max_raises < 0) return NULL;
     uint64_t m = 0;
     for (int i = 0; i < n_board; i++) {
@@ -496,6 +504,11 @@ ogame* ora_build_tree(int n_board, const int32_t* board, int64_t pot, int64_t st
     s.c[0] = s.c[1] = pot / 2;
     s.p = 0; s.nraises = 0; s.depth = 0; s.chance_card = -1;
     b_decision(&b, s);
+    if (b.err) {
+        for (int i = 0; i < b.n; i++) free(b.v[i].ch);
+        free(b.v);
+        return NULL;
+    }
     return game_from_builder(&b, 0, board, n_board);
 }
 
@@ -597,7 +610,7 @@ void ora_tree_export(const ogame* g, int32_t* type, int32_t* player, int32_t* pa
 }
 
 /* ------------------------------------------------------------- solver */
-enum { LEAF_EQUITY = 0, LEAF_TABLE = 1 };
+enum { LEAF_EQUITY = 0, LEAF_TABLE = 1, LEAF_FLOP = 2 };
 
 /* Stage-7 update rules (Sec. 4.4: the CFR variant only changes Stage 7).
  *   DCFR  (Brown & Sandholm 2019): discounted regrets and average, see
@@ -629,6 +642,12 @@ typedef struct {
     unsigned char* tmask;  /* optional [2][nh]: traverser hands to evaluate (NULL = all) */
     int leaf_kind;
     double* leaf_ev;      /* LEAF_TABLE: [leaf node][player][card][nh] expected value per pot */
+    /* LEAF_FLOP (preflop leaves): per leaf and player, sums of the expected
+     * value E(h | g) over the flops g that share no card with h -- in all
+     * (A[nh]), holding card x (B[nh][52]), holding both cards of combo xy
+     * (D[nh][nh]) -- so that a history's mean over the flops clear of both
+     * hands follows by inclusion-exclusion */
+    double *flopA, *flopB, *flopD;
     int* leaf_slot;       /* node -> leaf slot */
     int nleaf;
 } osolver;
@@ -664,7 +683,8 @@ osolver* ora_solver_create(ogame* g, const double* ranges, double alpha, double 
 void ora_solver_free(osolver* s) {
     if (!s) return;
     free(s->R); free(s->S); free(s->sig); free(s->rinst); free(s->sadd); free(s->pred); free(s->cva);
-    free(s->leaf_ev); free(s->leaf_slot); free(s->tmask); free(s->row_player); free(s);
+    free(s->leaf_ev); free(s->leaf_slot); free(s->tmask); free(s->row_player);
+    free(s->flopA); free(s->flopB); free(s->flopD); free(s);
 }
 
 /* Restrict the traverser's hands whose values and regrets are computed (the
@@ -732,11 +752,25 @@ static double leaf_value(osolver* s, int n, int i, int hi, int ho) {
         double* E = g->eq[o->bid];
         return (double)o->c[0] * E[(size_t)hi * g->nh + ho];
     }
+    int slot = s->leaf_slot[n];
+    double pot = (double)(o->c[0] + o->c[1]);
+    if (o->nb == 0) {
+        /* preflop leaf: mean over the C(48, 3) flops that neither hand touches
+         * of pot * E_i(hi | flop); flops holding a card x or y of the
+         * opponent's hand are taken out of the sum over all flops clear of hi
+         * by inclusion-exclusion (a flop holding both is removed twice) */
+        if (s->leaf_kind != LEAF_FLOP) abort();   /* refused before iterating */
+        size_t k = (size_t)slot * 2 + i, nh = g->nh;
+        int x = -1, y = -1;
+        for (int c = 0; c < 52; c++)
+            if (g->hmask[ho] >> c & 1) { if (y < 0) y = c; else x = c; }
+        double acc = s->flopA[k * nh + hi] - s->flopB[(k * nh + hi) * 52 + x] - s->flopB[(k * nh + hi) * 52 + y] +
+                     s->flopD[(k * nh + hi) * nh + combo_index(x, y)];
+        return pot * acc / 17296.0;
+    }
     /* LEAF_TABLE: the value network's expected value (per unit of pot) of
      * hand hi for player i after next card c, averaged over the cards that
      * neither hand holds: mean_c pot * EV_i(hi | c). */
-    int slot = s->leaf_slot[n];
-    double pot = (double)(o->c[0] + o->c[1]);
     double acc = 0; int cnt = 0;
     uint64_t used = o->bmask | g->hmask[hi] | g->hmask[ho];
     for (int c = 0; c < 52; c++) {
@@ -1147,6 +1181,170 @@ void ora_set_leaf_table(osolver* s, const double* ev) {
 }
 
 int ora_num_leaves(const osolver* s) { return s->nleaf; }
+
+/* ------------------------------------------------------------- flops at preflop leaves
+ * Suit permutations act on cards as 4 r + s -> 4 r + pi(s).  A flop (3 cards,
+ * as a 52-bit mask) is canonical when no permutation maps it to a smaller
+ * mask; the canonical flops, listed by their sorted cards in lexicographic
+ * order, stand for their orbits
+ * (the lossless suit abstraction of Sec. 4.5 applied to the flop deal). */
+static int PERM[24][4];
+static int PERM_INV[24];
+static void perms_init(void) {
+    static int done = 0;
+    if (done) return;
+    int q = 0;
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++)
+            for (int c = 0; c < 4; c++)
+                for (int d = 0; d < 4; d++) {
+                    if (a == b || a == c || a == d || b == c || b == d || c == d) continue;
+                    PERM[q][0] = a; PERM[q][1] = b; PERM[q][2] = c; PERM[q][3] = d;
+                    q++;
+                }
+    for (q = 0; q < 24; q++)
+        for (int r = 0; r < 24; r++) {
+            int id = 1;
+            for (int u = 0; u < 4; u++) id &= PERM[r][PERM[q][u]] == u;
+            if (id) PERM_INV[q] = r;
+        }
+    done = 1;
+}
+static int perm_card(int q, int c) { return 4 * (c / 4) + PERM[q][c % 4]; }
+static uint64_t perm_mask(int q, uint64_t m) {
+    uint64_t out = 0;
+    for (int c = 0; c < 52; c++) if (m >> c & 1) out |= 1ULL << perm_card(q, c);
+    return out;
+}
+static uint64_t canon_mask(uint64_t m) {
+    uint64_t best = m;
+    for (int q = 0; q < 24; q++) { uint64_t x = perm_mask(q, m); if (x < best) best = x; }
+    return best;
+}
+
+/* Canonical flops: writes up to cap entries of cards[3] (ascending) and the
+ * orbit size of each; returns how many there are. */
+int ora_canonical_flops(int32_t* cards, int32_t* orbit, int cap) {
+    perms_init();
+    static uint64_t canon[22100], mask[22100];
+    int k = 0;
+    for (int x = 0; x < 52; x++)
+        for (int y = x + 1; y < 52; y++)
+            for (int z = y + 1; z < 52; z++, k++) {
+                mask[k] = (1ULL << x) | (1ULL << y) | (1ULL << z);
+                canon[k] = canon_mask(mask[k]);
+            }
+    int n = 0;
+    for (int i = 0; i < 22100; i++) {
+        if (canon[i] != mask[i]) continue;
+        if (n < cap) {
+            int j = 0;
+            for (int c = 0; c < 52; c++) if (mask[i] >> c & 1) cards[3 * n + j++] = c;
+            int m = 0;
+            for (int u = 0; u < 22100; u++) m += canon[u] == mask[i];
+            orbit[n] = m;
+        }
+        n++;
+    }
+    return n;
+}
+
+/* Leaf values of a preflop tree from a table of expected values per unit of
+ * pot on the canonical flops: ev[leaf][player][flop][nh], flops as
+ * ora_canonical_flops lists them.  A flop g stands in the orbit of its
+ * canonical flop f; the expected value of hand h on g is the table's value
+ * on f of the hand mapped back, averaged over every permutation pi with
+ * pi(f) = g: E(h | g) = mean_pi ev[f][pi^-1(h)].  Returns 0, or 1 if the
+ * tree has no preflop leaf. */
+int ora_set_flop_leaf_table(osolver* s, const double* ev) {
+    ogame* g = s->g;
+    int any = 0;
+    for (int i = 0; i < g->n; i++) any |= g->nd[i].type == T_LEAF && g->nd[i].nb == 0;
+    if (!any || g->nh != NCOMBO) return 1;
+    perms_init();
+    enum { NF = 1755 };
+    static int32_t fc[NF * 3], fo[NF];
+    if (ora_canonical_flops(fc, fo, NF) != NF) abort();
+    /* every flop: its canonical flop and the permutations that map it there */
+    int nfl = 22100;
+    int32_t* fidx = malloc(sizeof(int32_t) * nfl);
+    int32_t* fq = malloc(sizeof(int32_t) * nfl * 24);
+    int32_t* fnq = malloc(sizeof(int32_t) * nfl);
+    uint64_t* fm = malloc(sizeof(uint64_t) * nfl);
+    int k = 0;
+    for (int x = 0; x < 52; x++)
+        for (int y = x + 1; y < 52; y++)
+            for (int z = y + 1; z < 52; z++, k++) {
+                uint64_t m = (1ULL << x) | (1ULL << y) | (1ULL << z);
+                uint64_t cm = canon_mask(m);
+                int f = -1;
+                for (int j = 0; j < NF; j++)
+                    if (((1ULL << fc[3 * j]) | (1ULL << fc[3 * j + 1]) | (1ULL << fc[3 * j + 2])) == cm) { f = j; break; }
+                fidx[k] = f; fm[k] = m; fnq[k] = 0;
+                for (int q = 0; q < 24; q++) if (perm_mask(q, cm) == m) fq[k * 24 + fnq[k]++] = q;
+            }
+    size_t nh = NCOMBO, L = (size_t)s->nleaf * 2;
+    int hc[2 * NCOMBO];
+    for (size_t h = 0; h < nh; h++) {
+        int j = 0;
+        for (int c = 0; c < 52; c++) if (g->hmask[h] >> c & 1) hc[2 * h + j++] = c;
+    }
+    free(s->flopA); free(s->flopB); free(s->flopD);
+    s->flopA = calloc(L * nh, sizeof(double));
+    s->flopB = calloc(L * nh * 52, sizeof(double));
+    s->flopD = calloc(L * nh * nh, sizeof(double));
+    #pragma omp parallel for schedule(dynamic)
+    for (long li = 0; li < (long)L; li++) {
+        const double* tab = ev + (size_t)li * NF * nh;
+        double* A = s->flopA + li * nh;
+        double* B = s->flopB + li * nh * 52;
+        double* D = s->flopD + li * nh * nh;
+        for (int q = 0; q < nfl; q++) {
+            int c3[3], n3 = 0;
+            for (int c = 0; c < 52; c++) if (fm[q] >> c & 1) c3[n3++] = c;
+            const double* row = tab + (size_t)fidx[q] * nh;
+            for (size_t h = 0; h < nh; h++) {
+                if (g->hmask[h] & fm[q]) continue;
+                double e = 0;
+                for (int j = 0; j < fnq[q]; j++) {
+                    int qi = PERM_INV[fq[q * 24 + j]];
+                    e += row[combo_index(perm_card(qi, hc[2 * h]), perm_card(qi, hc[2 * h + 1]))];
+                }
+                e /= fnq[q];
+                A[h] += e;
+                for (int u = 0; u < 3; u++) B[h * 52 + c3[u]] += e;
+                D[h * nh + combo_index(c3[1], c3[0])] += e;
+                D[h * nh + combo_index(c3[2], c3[0])] += e;
+                D[h * nh + combo_index(c3[2], c3[1])] += e;
+            }
+        }
+    }
+    free(fidx); free(fq); free(fnq); free(fm);
+    s->leaf_kind = LEAF_FLOP;
+    return 0;
+}
+
+/* Counterfactual value of every hand of player i at leaf node n against the
+ * opponent reach ro[nh]: out[h] = sum over compatible ho of ro[ho] times the
+ * history's leaf value.  Returns 1 if n is not a leaf. */
+int ora_leaf_cfv(osolver* s, int n, int i, const double* ro, double* out) {
+    ogame* g = s->g;
+    if (n < 0 || n >= g->n || (g->nd[n].type != T_LEAF && g->nd[n].type != T_ALLIN)) return 1;
+    for (int h = 0; h < g->nh; h++) {
+        double v = 0;
+        if (g->hvalid[h])
+            for (int o = 0; o < g->nh; o++)
+                if (g->hvalid[o] && compat(g, h, o) && ro[o] != 0) v += ro[o] * leaf_value(s, n, i, h, o);
+        out[h] = v;
+    }
+    return 0;
+}
+
+/* 1 when the tree has leaves at the flop deal (a preflop root). */
+int ora_has_flop_leaves(const ogame* g) {
+    for (int i = 0; i < g->n; i++) if (g->nd[i].type == T_LEAF && g->nd[i].nb == 0) return 1;
+    return 0;
+}
 
 /* Own reach of both players at every node under the current strategy
  * RM(R) (what the next iteration will use).  out: [n][2][nh]. */
