@@ -709,6 +709,53 @@ def flop_batch_sweep(args, steps, warmup, sizes=(8, 32)):
     return out
 
 
+def preflop_sweep(args, steps, warmup):
+    """Preflop root (no board, pot 20, 100 bb behind, {50, 100}% with up to 3
+    bets/raises, no all-in) solved over the 169 hand classes, its leaves at the
+    flop deal valued by the flop-level network (2705 -> 4 x 1536 -> 2652, He
+    init) on the 1755 canonical flops: ms per iteration and the GEMM rate at
+    that many rows.  The paper's preflop street takes 3.48 ms per iteration
+    (Table 2; its own tree and CPU/GPU split), context only."""
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+
+    spec, r = I.preflop_config(args.seed)
+    tree = P.Tree(**spec)
+    s = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
+    n_leaves, n_next = s.leaf_rows()
+    rows = n_leaves * n_next
+    net = P.LeafNet(P.LEAF_D_IN, 1536, 4, P.LEAF_D_OUT, max_batch=rows)
+    net.set_params(he_params(net.layer_shapes(), 7))
+    s.attach_leafnet(net)
+    before, after = s.autotune(3)
+    ms = timed(s, steps, warmup)
+    pms, pl = s.profile(args.profile_iters)
+    pms, pl = pms / args.profile_iters, pl // args.profile_iters
+    shapes = net.layer_shapes()
+    hidden_flops = 2.0 * rows * sum(o * i for o, i in shapes[:-1])
+    all_flops = 2.0 * rows * sum(o * i for o, i in shapes)
+    expl, _ = s.exploitability()
+    out = {
+        "workload": f"preflop root, seed {args.seed}: {tree.n_nodes} nodes, {n_leaves} leaves at the flop deal x "
+                    f"{n_next} canonical flops, 169 hand classes, leaf network 1536x4",
+        "spec": {k: (list(v) if isinstance(v, tuple) else v) for k, v in spec.items()},
+        "nodes": tree.n_nodes, "leaves": n_leaves, "canonical_flops": n_next, "network_rows": rows,
+        "hands": tree.n_hands, "ms_per_iter": ms, "iters_per_s": 1000.0 / ms,
+        "autotune_ms_per_iter_before_after": [before, after], "leaf_gemm_tiles": net.tiles,
+        "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
+        "leaf_gemm_hidden_tflops": hidden_flops / (pms[5] * 1e-3) / 1e12,
+        "leaf_gemm_all_layers_tflops": all_flops / ((pms[5] + pms[6]) * 1e-3) / 1e12,
+        "leaf_flops_per_iter": all_flops,
+        "exploitability_mbb_per_hand": expl * 100.0,
+        "paper_preflop_ms_per_iter": 3.48,
+        "paper_note": "Table 2, preflop street, 5 CPU threads + GPU leaf evaluation on another machine and tree",
+    }
+    log(f"preflop: {ms:.4f} ms/iter, {rows} network rows, hidden GEMM {out['leaf_gemm_hidden_tflops']:.0f} TFLOP/s")
+    s.close()
+    net.close()
+    return out
+
+
 def gemm_shape_point(args, m=2048, reps=50):
     """The leaf network's forward at m rows (the second GEMM shape point),
     after the tile autotuner: us per forward and TFLOP/s."""
@@ -888,6 +935,7 @@ def main():
         result["turn_spr_sweep"] = spr_sweep(args, max(20, args.steps // 4), 5)
         result["leaf_gemm_m2048"] = gemm_shape_point(args)
         result["flop_batch"] = flop_batch_sweep(args, max(20, args.steps // 4), 5)
+        result["preflop"] = preflop_sweep(args, max(20, args.steps // 4), 5)
         result["hbm_copy_ceiling_gbs"] = copy_ceiling_gbs()
         if not args.no_learned:
             result["learned_leaf"] = learned_leaf_sweep(args)

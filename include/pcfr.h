@@ -62,7 +62,16 @@ enum {
 
 /* Betting abstraction of a subgame (Sec. 5 "Game": fixed action
  * abstraction, stack-to-pot ratio, number of raise sizes).
- *   n_board      3, 4 or 5 public cards in board[0..n_board)
+ *   n_board      3, 4 or 5 public cards in board[0..n_board); or 0, a
+ *                preflop root: then depth_limit must be 1 (the leaves sit at
+ *                the flop deal) and no betting line may put a player all in
+ *                (else PCFR_E_UNSUPPORTED).  A preflop root is solved over
+ *                the 169 hand classes (pairs, suited and offsuit rank
+ *                pairs; lossless suit abstraction, Sec. 4.5): its ranges
+ *                must be equal on the combos of each class
+ *                (PCFR_E_INVALID_ARG otherwise), suit_iso does not apply
+ *                (PCFR_E_UNSUPPORTED), a batch holds preflop roots only,
+ *                and per-hand outputs repeat a class's value on its combos.
  *   pot          chips in the pot at the root; even, > 0
  *   stack[2]     chips behind per player; the smaller one caps every bet
  *   size_pct     n_sizes (<= 8) bet sizes as integer percent of the pot after
@@ -144,8 +153,9 @@ int32_t pcfr_build_tree(const pcfr_tree_spec* spec, pcfr_tree** out);
 int32_t pcfr_tree_free(pcfr_tree* tree);
 
 /* out[16]: nodes, decision, fold, showdown, chance, leaf, allin-leaf,
- * levels, action rows (sum of actions over decision nodes), hands
- * (board-compatible combos), padded hands, then zeros. */
+ * levels, action rows (sum of actions over decision nodes), hands the
+ * solver sweeps (board-compatible combos; the 169 hand classes of a preflop
+ * root), those padded to 64, then zeros. */
 int32_t pcfr_tree_info(const pcfr_tree* tree, int64_t* out);
 
 /* Node arrays, each of length nodes (contrib: 2 per node), caller-owned
@@ -451,7 +461,18 @@ int32_t pcfr_leafnet_train_step(pcfr_leafnet* net, const float* x, const float* 
  * normalised ranges after each next card, the board one-hot, the
  * stack-to-pot ratio) to 2*1326 outputs (each hand's value per pot unit and
  * per unit of compatible opponent reach) and hold leaves x next-cards rows.
- * All-in leaves stay exact.  The net must outlive the attachment. */
+ * All-in leaves stay exact.  The net must outlive the attachment.
+ *
+ * Preflop leaves (Sec. 4.3's leaf model at the flop deal): one row per
+ * (leaf, canonical flop) -- the 1755 flops that no suit permutation maps to a
+ * smaller card mask, by their sorted cards in lexicographic order -- with
+ * the ranges cleared of the flop's cards and the flop's three cards one-hot.
+ * A hand class's leaf value is pot / C(48,3) / |class| times the sum over
+ * the canonical flops of (flops in the orbit) x the sum over the class's
+ * combos clear of the flop of EV x the opponent's reach clear of combo and
+ * flop (exact for the suit-symmetric reach of a preflop root).  These leaves
+ * have no exact model: without a net, iterating and evaluating return
+ * PCFR_E_STATE. */
 int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net);
 
 /* Zero-sum correction of network leaf values, on (1, the default) or off (0).

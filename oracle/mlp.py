@@ -137,43 +137,52 @@ def leaf_inputs(reach_leaf: np.ndarray, board, pot: float, stack_behind: float, 
     return cards, X
 
 
+def _flop_keep(flops) -> np.ndarray:
+    """[k, 1326] bool: combos holding no card of each flop."""
+    flops = np.asarray(flops)
+    keep = np.ones((len(flops), NCOMBO), dtype=bool)
+    for j in range(3):
+        c = flops[:, j][:, None]
+        keep &= (_CC[:, 0][None, :] != c) & (_CC[:, 1][None, :] != c)
+    return keep
+
+
 def flop_leaf_inputs(reach_leaf: np.ndarray, flops, pot: float, stack_behind: float, d_in: int):
     """Network inputs of one preflop leaf for each flop of `flops` ([k, 3]
     cards): each player's reach with the combos holding a flop card removed,
     normalised to sum 1 (all zero if nothing is left), the flop's three cards
     one-hot (52 entries), the stack-to-pot ratio; zero padding up to d_in."""
     flops = np.asarray(flops)
+    keep = _flop_keep(flops)
     X = np.zeros((len(flops), d_in), dtype=np.float64)
-    for k, f in enumerate(flops):
-        keep = np.ones(NCOMBO, dtype=bool)
-        for c in f:
-            keep &= (_CC[:, 0] != c) & (_CC[:, 1] != c)
-        for p in range(2):
-            v = reach_leaf[p] * keep
-            s = v.sum()
-            if s > 0:
-                X[k, p * NCOMBO:(p + 1) * NCOMBO] = v / s
-        for c in f:
-            X[k, 2 * NCOMBO + c] = 1.0
-        X[k, 2 * NCOMBO + 52] = stack_behind / pot
+    for p in range(2):
+        v = reach_leaf[p][None, :] * keep
+        s = v.sum(axis=1)
+        nz = s > 0
+        X[nz, p * NCOMBO:(p + 1) * NCOMBO] = v[nz] / s[nz, None]
+    rows = np.arange(len(flops))
+    for j in range(3):
+        X[rows, 2 * NCOMBO + flops[:, j]] = 1.0
+    X[:, 2 * NCOMBO + 52] = stack_behind / pot
     return X
 
 
 def flop_zero_sum_shifts(ev_rows: np.ndarray, reach_leaf: np.ndarray, flops) -> np.ndarray:
     """The zero-sum correction (as zero_sum_shift) of each row of a preflop
     leaf: ev_rows [k, 2, 1326] after flop flops[k]; only combos clear of the
-    flop count, and M is the opponent reach clear of the hand and the flop."""
+    flop count, and M is the opponent reach clear of the hand and the flop
+    (brute force over opponent combos, one product per player)."""
+    keep = _flop_keep(flops)
     K = _compat()
-    out = np.zeros(len(flops))
-    for j, f in enumerate(np.asarray(flops)):
-        keep = np.ones(NCOMBO, dtype=bool)
-        for c in f:
-            keep &= (_CC[:, 0] != c) & (_CC[:, 1] != c)
-        r0, r1 = reach_leaf[0] * keep, reach_leaf[1] * keep
-        m1, m0 = K @ r1, K @ r0
-        e = float((r0 * m1 * ev_rows[j, 0]).sum() + (r1 * m0 * ev_rows[j, 1]).sum())
-        z = float((r0 * m1).sum())
-        out[j] = e / (2.0 * z) if z > 0 else 0.0
+    r0 = reach_leaf[0][None, :] * keep
+    r1 = reach_leaf[1][None, :] * keep
+    m1 = r1 @ K          # K is symmetric
+    m0 = r0 @ K
+    e = (r0 * m1 * ev_rows[:, 0]).sum(axis=1) + (r1 * m0 * ev_rows[:, 1]).sum(axis=1)
+    z = (r0 * m1).sum(axis=1)
+    out = np.zeros(len(keep))
+    pos = z > 0
+    out[pos] = e[pos] / (2.0 * z[pos])
     return out
 
 

@@ -70,6 +70,7 @@ int32_t pcfr_tree_info(const pcfr_tree* tree, int64_t* out) {
     const ComboTable& cc = combos();
     for (int k = 0; k < kCombos; k++)
         if (!((t.root_mask >> cc.hi[k] & 1ull) || (t.root_mask >> cc.lo[k] & 1ull))) h++;
+    if (t.root_mask == 0) h = 169;   // a preflop root is solved over the hand classes
     out[9] = h;
     out[10] = (h + 63) / 64 * 64;
     return PCFR_OK;

@@ -1629,6 +1629,285 @@ __global__ __launch_bounds__(kBlock) void k_leaf_combine(const DNode* __restrict
     }
 }
 
+// ------------------------------------------------------------ preflop roots
+// A preflop root (no board) is solved over the 169 hand classes -- pairs,
+// suited and offsuit rank pairs.  Its root ranges are suit-symmetric (equal
+// on the combos of each class), so every iterate is too (a suit permutation
+// maps the game onto itself; the lossless suit abstraction of Sec. 4.5): one
+// "hand" per class carries the reach, regrets and values that each of its
+// combos has.  Its leaves sit at the flop deal, where the flop-level network
+// (Sec. 4.3) is queried on the canonical flops only.
+
+// Fold over classes: M_{-i}(c) = sum_{c'} N[c][c'] r_{-i}(c'), with N[c][c']
+// the number of combos of class c' sharing no card with a combo of class c
+// (the same for every combo of c); the folder loses its contribution times
+// M, the other player wins it.  One workgroup per fold node, one class per
+// thread; sums of nonnegative terms in a fixed order, so zero mass is an
+// exact zero.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fold_class(const DNode* __restrict__ nodes, const int32_t* __restrict__ folds,
+                                                       int Hp, int Hc, const T* __restrict__ reach, T* __restrict__ cfv,
+                                                       const uint8_t* __restrict__ ncompat /* [Hc][Hc] */,
+                                                       const int32_t* __restrict__ nzs) {
+    __shared__ T x[2][kBlock];
+    const int64_t n = folds[blockIdx.x];
+    const DNode nd = nodes[n];
+    const int tid = threadIdx.x;
+    T* v0 = cfv + n * 2 * Hp;
+    T* v1 = v0 + Hp;
+    if (node_dead(nzs, nd)) {
+        for (int h = tid; h < Hp; h += kBlock) { v0[h] = T(0); v1[h] = T(0); }
+        return;
+    }
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    if (tid < Hc) { x[0][tid] = r0[tid]; x[1][tid] = r1[tid]; }
+    __syncthreads();
+    const T pay = (T)nd.pay, s0 = nd.player == 0 ? -pay : pay;
+    for (int c = tid; c < Hp; c += kBlock) {
+        T m1 = T(0), m0 = T(0);
+        if (c < Hc) {
+            const uint8_t* row = ncompat + (int64_t)c * Hc;
+            for (int j = 0; j < Hc; j++) {
+                const T w = (T)row[j];
+                m1 += w * x[1][j];
+                m0 += w * x[0][j];
+            }
+        }
+        v0[c] = s0 * m1;
+        v1[c] = -s0 * m0;
+    }
+}
+
+__device__ __forceinline__ void combo_cards(int k, int& a, int& b) {
+    a = (int)((1.f + sqrtf(1.f + 8.f * (float)k)) * 0.5f);
+    if (a * (a - 1) / 2 > k) a--;
+    else if ((a + 1) * a / 2 <= k) a++;
+    b = k - a * (a - 1) / 2;
+}
+
+// Network rows of the preflop leaves: one per (leaf, canonical flop f):
+// each player's per-combo reach with the combos holding a flop card removed,
+// normalised to sum 1 (zero if nothing is left), the flop's cards one-hot,
+// the stack-to-pot ratio; bf16, zero padded to ldx.  One workgroup per
+// (leaf, group of flops); each row's sums are direct sums in double over the
+// kept combos.  Group 0 also stores the leaf's combo-indexed reach (Rc) and
+// its per-card sums and totals (agg) for the zero-sum and combine kernels.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flop_leaf_input(const DNode* __restrict__ nodes,
+                                                            const int32_t* __restrict__ leaves, int Hp,
+                                                            const T* __restrict__ reach,
+                                                            const int16_t* __restrict__ combo_hand /* [n_sub][kComboPad] */,
+                                                            T* __restrict__ Rc, T* __restrict__ agg,
+                                                            const float* __restrict__ spr, int n_flops, int flops_per_group,
+                                                            const int8_t* __restrict__ flops /* [n_flops][4] */, int ldx,
+                                                            uint16_t* __restrict__ X) {
+    constexpr int CI = (kCombos + kBlock - 1) / kBlock;
+    __shared__ double xc[2][kComboPad];
+    __shared__ double xch[2 * kWaves];
+    const int li = blockIdx.x, tid = threadIdx.x;
+    const bool lead = blockIdx.y == 0;
+    const DNode nd = nodes[leaves[li]];
+    const T* r0 = reach + (int64_t)nd.slot[0] * Hp;
+    const T* r1 = reach + (int64_t)nd.slot[1] * Hp;
+    combo_hand += (int64_t)nd.sub * kComboPad;
+    T* rc = Rc + (int64_t)li * 2 * kComboPad;
+    int ka[CI], kb[CI];
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock;
+        ka[i] = -1;
+        kb[i] = -1;
+        if (k < kCombos) {
+            combo_cards(k, ka[i], kb[i]);
+            const int h = combo_hand[k];
+            const T v0 = h >= 0 ? r0[h] : T(0), v1 = h >= 0 ? r1[h] : T(0);
+            xc[0][k] = (double)v0;
+            xc[1][k] = (double)v1;
+            if (lead) { rc[k] = v0; rc[kComboPad + k] = v1; }
+        }
+    }
+    __syncthreads();
+    if (lead) {
+        if (tid < 104) {
+            const int p = tid / 52, c = tid - p * 52;
+            double cs = 0.0;
+            for (int j = 0; j < 51; j++) cs += xc[p][combo_index(c, j < c ? j : j + 1)];
+            agg[(int64_t)li * kAgg + p * 53 + c] = (T)cs;
+        }
+        double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < CI; i++)
+            if (ka[i] >= 0) { t0 += xc[0][tid + i * kBlock]; t1 += xc[1][tid + i * kBlock]; }
+        block_sum2(t0, t1, xch);
+        if (tid == 0) { agg[(int64_t)li * kAgg + 52] = (T)t0; agg[(int64_t)li * kAgg + 105] = (T)t1; }
+        __syncthreads();   // xch is reused below
+    }
+    const float ratio = spr[li];
+    const int chunks = ldx / 8;
+    const int f0 = blockIdx.y * flops_per_group, f1 = min(n_flops, f0 + flops_per_group);
+    for (int f = f0; f < f1; f++) {
+        const int x = flops[4 * f], y = flops[4 * f + 1], z = flops[4 * f + 2];
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < CI; i++) {
+            const int a = ka[i], b = kb[i];
+            if (a < 0 || a == x || a == y || a == z || b == x || b == y || b == z) continue;
+            s0 += xc[0][tid + i * kBlock];
+            s1 += xc[1][tid + i * kBlock];
+        }
+        block_sum2(s0, s1, xch);
+        const double i0 = s0 > 0.0 ? 1.0 / s0 : 0.0, i1 = s1 > 0.0 ? 1.0 / s1 : 0.0;
+        uint16_t* xr = X + ((int64_t)li * n_flops + f) * ldx;
+        for (int it = tid; it < chunks; it += kBlock) {
+            const int col0 = it * 8;
+            uint16_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const int col = col0 + j;
+                float xv = 0.f;
+                if (col < 2 * kCombos) {
+                    const int pp = col >= kCombos, k = col - pp * kCombos;
+                    int a, b;
+                    combo_cards(k, a, b);
+                    if (a != x && a != y && a != z && b != x && b != y && b != z)
+                        xv = (float)(xc[pp][k] * (pp ? i1 : i0));
+                } else if (col < 2 * kCombos + 52) {
+                    const int card = col - 2 * kCombos;
+                    xv = (card == x || card == y || card == z) ? 1.f : 0.f;
+                } else if (col == 2 * kCombos + 52) {
+                    xv = ratio;
+                }
+                v[j] = to_bf16(xv);
+            }
+            *reinterpret_cast<u32x4*>(xr + col0) =
+                u32x4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                      (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
+        }
+        __syncthreads();   // every thread has read xch before the next flop's sums overwrite it
+    }
+}
+
+// M_p(h | f): player p's reach over the combos sharing no card with combo ab
+// or flop xyz, by inclusion-exclusion over those five cards (a combo holds
+// two cards, so the series stops at the pairs): T - sum of the five per-card
+// sums + the reach of the ten combos they pair into (ab itself among them).
+template <typename T>
+__device__ __forceinline__ T flop_mass(const T* rs, const T* cs, T tot, int a, int b, int x, int y, int z) {
+    return tot - cs[a] - cs[b] - cs[x] - cs[y] - cs[z] + rs[combo_index(a, b)] + rs[combo_index(a, x)] +
+           rs[combo_index(a, y)] + rs[combo_index(a, z)] + rs[combo_index(b, x)] + rs[combo_index(b, y)] +
+           rs[combo_index(b, z)] + rs[combo_index(x, y)] + rs[combo_index(x, z)] + rs[combo_index(y, z)];
+}
+
+// Zero-sum shift of a preflop leaf row (as k_leaf_zerosum, with the flop's
+// three cards blocked): d = e / (2 z), e = sum_h r0 M1 EV0 + r1 M0 EV1,
+// z = sum_h r0 M1, over the combos clear of the flop.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flop_leaf_zerosum(int n_flops, const int8_t* __restrict__ flops,
+                                                              const T* __restrict__ Rc, const T* __restrict__ agg,
+                                                              const float* __restrict__ Y, int ldy,
+                                                              T* __restrict__ delta) {
+    constexpr int CI = (kCombos + kBlock - 1) / kBlock;
+    __shared__ T rs[2][kComboPad];
+    __shared__ T cs[2][52];
+    __shared__ T xch[2 * kWaves];
+    const int row = blockIdx.x, li = row / n_flops, f = row - li * n_flops, tid = threadIdx.x;
+    const int x = flops[4 * f], y = flops[4 * f + 1], z = flops[4 * f + 2];
+    const T* rc = Rc + (int64_t)li * 2 * kComboPad;
+    const float* yr = Y + (int64_t)row * ldy;
+    float e0[CI], e1[CI];
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock, kk = k < kCombos ? k : 0;
+        e0[i] = yr[kk];
+        e1[i] = yr[kCombos + kk];
+        if (k < kCombos) { rs[0][k] = rc[k]; rs[1][k] = rc[kComboPad + k]; }
+    }
+    if (tid < 104) cs[tid / 52][tid % 52] = agg[(int64_t)li * kAgg + (tid / 52) * 53 + tid % 52];
+    const T t0 = agg[(int64_t)li * kAgg + 52], t1 = agg[(int64_t)li * kAgg + 105];
+    __syncthreads();
+    T e = T(0), zz = T(0);
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock;
+        if (k >= kCombos) continue;
+        int a, b;
+        combo_cards(k, a, b);
+        if (a == x || a == y || a == z || b == x || b == y || b == z) continue;
+        const T m1 = flop_mass(rs[1], cs[1], t1, a, b, x, y, z);
+        const T m0 = flop_mass(rs[0], cs[0], t0, a, b, x, y, z);
+        e += rs[0][k] * m1 * (T)e0[i] + rs[1][k] * m0 * (T)e1[i];
+        zz += rs[0][k] * m1;
+    }
+    block_sum2(e, zz, xch);
+    if (tid == 0) delta[row] = zz > T(0) ? e / (T(2) * zz) : T(0);
+}
+
+// Preflop leaf values over the hand classes.  With suit-symmetric reach a
+// class c's value is pot / C(48,3) / |c| times the sum over canonical flops
+// f of orbit(f) x sum over the combos x of c clear of f of
+// (EV_i(x | f) - d_f) M_{-i}(x | f): the flops of f's orbit give the same
+// sum with the combos of c permuted among themselves.  One workgroup per
+// (leaf, hand); its threads stride over the flops, partial sums added in a
+// fixed order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flop_leaf_combine(const DNode* __restrict__ nodes,
+                                                              const int32_t* __restrict__ leaves,
+                                                              const double* __restrict__ pot_over_k, int n_flops,
+                                                              const int8_t* __restrict__ flops,
+                                                              const int32_t* __restrict__ orbit,
+                                                              const int32_t* __restrict__ hoff /* [n_sub][Hp + 1] */,
+                                                              const int16_t* __restrict__ hlist /* [n_sub][kComboPad] */,
+                                                              int Hp, int H, T* __restrict__ cfv,
+                                                              const float* __restrict__ Y, int ldy,
+                                                              const T* __restrict__ Rc, const T* __restrict__ agg,
+                                                              const T* __restrict__ delta) {
+    __shared__ T rs[2][kComboPad];
+    __shared__ T cs[2][52];
+    __shared__ T xch[2 * kWaves];
+    const int li = blockIdx.x, h = blockIdx.y, tid = threadIdx.x;
+    const int64_t n = leaves[li];
+    const DNode nd = nodes[n];
+    T* v0 = cfv + n * 2 * Hp;
+    T* v1 = v0 + Hp;
+    if (h >= H) {
+        if (tid == 0) { v0[h] = T(0); v1[h] = T(0); }
+        return;
+    }
+    const T* rc = Rc + (int64_t)li * 2 * kComboPad;
+    for (int k = tid; k < kCombos; k += kBlock) { rs[0][k] = rc[k]; rs[1][k] = rc[kComboPad + k]; }
+    if (tid < 104) cs[tid / 52][tid % 52] = agg[(int64_t)li * kAgg + (tid / 52) * 53 + tid % 52];
+    const T t0 = agg[(int64_t)li * kAgg + 52], t1 = agg[(int64_t)li * kAgg + 105];
+    const int32_t* ho = hoff + (int64_t)nd.sub * (Hp + 1);
+    const int16_t* hl = hlist + (int64_t)nd.sub * kComboPad;
+    const int j0 = ho[h], j1 = ho[h + 1];
+    __syncthreads();
+    T acc0 = T(0), acc1 = T(0);
+    for (int f = tid; f < n_flops; f += kBlock) {
+        const int x = flops[4 * f], y = flops[4 * f + 1], z = flops[4 * f + 2];
+        const float* yr = Y + ((int64_t)li * n_flops + f) * ldy;
+        const T d = delta ? delta[(int64_t)li * n_flops + f] : T(0);
+        T s0 = T(0), s1 = T(0);
+        for (int j = j0; j < j1; j++) {
+            const int k = hl[j];
+            int a, b;
+            combo_cards(k, a, b);
+            if (a == x || a == y || a == z || b == x || b == y || b == z) continue;
+            s0 += ((T)yr[k] - d) * flop_mass(rs[1], cs[1], t1, a, b, x, y, z);
+            s1 += ((T)yr[kCombos + k] - d) * flop_mass(rs[0], cs[0], t0, a, b, x, y, z);
+        }
+        const T w = (T)orbit[f];
+        acc0 += w * s0;
+        acc1 += w * s1;
+    }
+    block_sum2(acc0, acc1, xch);
+    if (tid == 0) {
+        const T scale = (T)(pot_over_k[li] / (double)(j1 - j0));
+        v0[h] = scale * acc0;
+        v1[h] = scale * acc1;
+    }
+}
+
 // ------------------------------------------------------------ leaf-network samples
 // One training sample per subgame of a solved batch, in the leaf network's
 // input/output layout: x = both root ranges normalised to sum 1 over the 1326
@@ -1770,7 +2049,7 @@ struct Plan {
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_zs, off_agg, off_rc, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
         off_eqgrp, off_nsub, off_b4, off_nzs, off_tfrec, off_tfrest, off_tfterm,
-        off_cmap, off_hmap, total;
+        off_cmap, off_hmap, off_ncompat, off_flops, off_orbit, off_hoff, off_hlist, total;
     size_t lds_bytes, lds_fold, lds_show;
     int64_t n_grp = 0, n_grp_allin = 0;   // equity groups: all leaves, the all-in prefix
     int eq_J = 0;                         // leaves per equity group at most
@@ -1821,7 +2100,59 @@ struct Prepared {
     std::vector<double> net_potk;
     std::vector<int8_t> next_cards;
     std::vector<int32_t> board;           // root board cards (subgame 0)
+    // preflop roots (every subgame, or none): hands are the 169 classes
+    bool preflop = false;
+    std::vector<uint8_t> ncompat;          // [169][169] combos of class c' clear of a combo of class c
+    std::vector<int8_t> flops;             // [n_flops][4] canonical flops (3 cards, pad)
+    std::vector<int32_t> flop_orbit;       // [n_flops]
+    std::vector<int32_t> hoff;             // [n_sub][Hp + 1] start of each hand's combos in hlist
+    std::vector<int16_t> hlist;            // [n_sub][kComboPad] combos grouped by hand
 };
+
+// Hand class of combo k (cards hi > lo): 0..12 pairs by rank, then the 78
+// suited and the 78 offsuit rank pairs, each by (high rank, low rank).
+static int hand_class(int hi, int lo) {
+    const int ra = hi / 4, rb = lo / 4;
+    if (ra == rb) return ra;
+    const int r1 = ra > rb ? ra : rb, r2 = ra > rb ? rb : ra;
+    const int pair_idx = r1 * (r1 - 1) / 2 + r2;   // 0..77
+    return 13 + (hi % 4 == lo % 4 ? 0 : 78) + pair_idx;
+}
+
+// Canonical flops: the flops that no suit permutation maps to a smaller
+// 52-bit mask, by their sorted cards in lexicographic order, with the number
+// of flops in each one's orbit.
+static void canonical_flops(std::vector<int8_t>& cards, std::vector<int32_t>& orbit) {
+    auto canon = [](uint64_t m) {
+        uint64_t best = m;
+        for (int q = 0; q < 24; q++) {
+            uint64_t x = 0;
+            for (int c = 0; c < 52; c++)
+                if (m >> c & 1ull) x |= 1ull << suit_perm_card(q, c);
+            best = std::min(best, x);
+        }
+        return best;
+    };
+    std::vector<uint64_t> masks, canons;
+    for (int x = 0; x < 52; x++)
+        for (int y = x + 1; y < 52; y++)
+            for (int z = y + 1; z < 52; z++) {
+                const uint64_t m = (1ull << x) | (1ull << y) | (1ull << z);
+                masks.push_back(m);
+                canons.push_back(canon(m));
+            }
+    std::map<uint64_t, int32_t> count;
+    for (uint64_t c : canons) count[c]++;
+    cards.clear();
+    orbit.clear();
+    for (size_t i = 0; i < masks.size(); i++) {
+        if (canons[i] != masks[i]) continue;
+        for (int c = 0; c < 52; c++)
+            if (masks[i] >> c & 1ull) cards.push_back((int8_t)c);
+        cards.push_back(-1);
+        orbit.push_back(count[masks[i]]);
+    }
+}
 
 // Host preprocessing of a forest of subgames: node records, merged level work
 // lists, hand cards, per-card hand lists, and one strength-sorted table per
@@ -1835,16 +2166,40 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
     P.Hs.assign(K, 0);
     P.root_mask.assign(K, 0);
     int64_t Hmax = 0;
+    int n_pre = 0;
+    for (int32_t g = 0; g < K; g++) n_pre += trees[g]->root_mask == 0;
+    if (n_pre && n_pre != K) { set_error("a batch mixes preflop roots with other subgames"); return PCFR_E_UNSUPPORTED; }
+    P.preflop = n_pre > 0;
     for (int32_t g = 0; g < K; g++) {
         const uint64_t rm = trees[g]->root_mask;
         P.root_mask[g] = rm;
-        for (int k = 0; k < kCombos; k++) {
-            if ((rm >> cc.hi[k] & 1ull) || (rm >> cc.lo[k] & 1ull)) continue;
-            P.combo_hand[g][k] = (int32_t)P.hand_combo[g].size();
-            P.hand_combo[g].push_back(k);
+        if (P.preflop) {
+            // one hand per class, represented by its first combo
+            P.hand_combo[g].assign(169, -1);
+            for (int k = 0; k < kCombos; k++) {
+                const int c = hand_class(cc.hi[k], cc.lo[k]);
+                P.combo_hand[g][k] = c;
+                if (P.hand_combo[g][c] < 0) P.hand_combo[g][c] = k;
+            }
+        } else {
+            for (int k = 0; k < kCombos; k++) {
+                if ((rm >> cc.hi[k] & 1ull) || (rm >> cc.lo[k] & 1ull)) continue;
+                P.combo_hand[g][k] = (int32_t)P.hand_combo[g].size();
+                P.hand_combo[g].push_back(k);
+            }
         }
         P.Hs[g] = (int64_t)P.hand_combo[g].size();
         Hmax = std::max(Hmax, P.Hs[g]);
+    }
+    if (P.preflop) {
+        P.ncompat.assign(169 * 169, 0);
+        for (int c = 0; c < 169; c++) {
+            const int k = P.hand_combo[0][c];
+            const uint64_t m = (1ull << cc.hi[k]) | (1ull << cc.lo[k]);
+            for (int j = 0; j < kCombos; j++)
+                if (!(m >> cc.hi[j] & 1ull) && !(m >> cc.lo[j] & 1ull)) P.ncompat[(size_t)c * 169 + P.combo_hand[0][j]]++;
+        }
+        canonical_flops(P.flops, P.flop_orbit);
     }
     P.H = P.Hs[0];
     P.Hp = (Hmax + 63) / 64 * 64;
@@ -1871,6 +2226,20 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
             for (auto x : lists[c]) P.chands[(size_t)g * P.chand_stride + pos++] = x;
         }
         P.coff[(size_t)g * 53 + 52] = pos;
+    }
+    // combos of each hand, grouped by hand (one each, or a class's combos)
+    P.hoff.assign((size_t)K * (Hp + 1), 0);
+    P.hlist.assign((size_t)K * kComboPad, 0);
+    for (int32_t g = 0; g < K; g++) {
+        std::vector<std::vector<int16_t>> per(Hp);
+        for (int k = 0; k < kCombos; k++)
+            if (P.combo_hand[g][k] >= 0) per[P.combo_hand[g][k]].push_back((int16_t)k);
+        int32_t pos = 0;
+        for (int64_t h = 0; h < Hp; h++) {
+            P.hoff[(size_t)g * (Hp + 1) + h] = pos;
+            for (auto k : per[h]) P.hlist[(size_t)g * kComboPad + pos++] = k;
+        }
+        P.hoff[(size_t)g * (Hp + 1) + Hp] = pos;
     }
     P.sd_stride = (8 * Hp + kSdHeader + 2 * Hp + kSdHeader + 63) / 64 * 64;
     std::map<std::pair<int32_t, uint64_t>, int32_t> board_id;
@@ -1990,7 +2359,8 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
                     P.net_leaves.push_back((int32_t)(P.node_base[g] + (int64_t)i));
                     P.net_sub.push_back(g);
                     P.net_spr.push_back((float)((double)(cap - s.contrib[0]) / (double)(2 * s.contrib[0])));
-                    P.net_potk.push_back((double)(2 * s.contrib[0]) / (double)(52 - nb - 4));
+                    // chance weight per history: 1 / (next cards, or flops, clear of both hands)
+                    P.net_potk.push_back((double)(2 * s.contrib[0]) / (nb == 0 ? 17296.0 : (double)(52 - nb - 4)));
                 }
             }
         }
@@ -1998,7 +2368,7 @@ static int32_t prepare(const std::vector<const Tree*>& trees, Prepared& P, const
     P.et_slot.assign(K, -1);
     P.n_et = 0;
     for (int32_t g : P.eq_sub)
-        if (P.et_slot[g] < 0) P.et_slot[g] = P.n_et++;
+        if (P.et_slot[g] < 0 && !P.preflop) P.et_slot[g] = P.n_et++;   // preflop leaves: the network only
     // per subgame: the root board (up to 4 cards, -1 past the last) and the
     // cards that can come next (one table row of 64 per subgame)
     P.board4s.assign((size_t)K * 4, -1);
@@ -2182,7 +2552,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
         L.n_grp = (int64_t)grp.size() / 4;
     }
     L.H_leaf = P.leaf_H;
-    L.n_next = P.leaf_board >= 0 ? 52 - P.leaf_board : (int64_t)P.next_cards.size();
+    L.n_next = P.preflop ? (int64_t)P.flop_orbit.size()
+                         : P.leaf_board >= 0 ? 52 - P.leaf_board : (int64_t)P.next_cards.size();
     // one pairwise equity table per subgame holding leaves, [n_et][Hp][Hp]
     L.off_et = take(L.esz * L.Hp * L.Hp * (size_t)P.n_et);
     L.off_eqgrp = take(sizeof(int32_t) * 4 * std::max<int64_t>(L.n_grp, 1));
@@ -2207,6 +2578,11 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.off_samp = take(align256(sizeof(float) * 2 * P.n_sub) + align256((size_t)P.n_sub * 52) +
                       align256(sizeof(int16_t) * (size_t)P.n_sub * kCombos));
     L.off_eqpart = take(L.esz * kEqSplit * L.n_eq * 2 * L.Hp);
+    L.off_ncompat = take(P.ncompat.size());
+    L.off_flops = take(P.flops.size());
+    L.off_orbit = take(sizeof(int32_t) * P.flop_orbit.size());
+    L.off_hoff = take(sizeof(int32_t) * P.hoff.size());
+    L.off_hlist = take(sizeof(int16_t) * P.hlist.size());
     L.off_nzs = take(sizeof(int32_t) * (size_t)(2 * P.n_sub + L.rows));   // pruning flags per reach slot
     // terminal fusion: node records of the fused and the remaining backward work, terminals left over
     L.off_tfrec = take(sizeof(DNode) * std::max<size_t>(P.dec.size(), 1));
@@ -2381,7 +2757,14 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     const int64_t n_fold = tfo ? s->tf.n_fold : (int64_t)P.folds.size();
     const int64_t n_show = tfo ? s->tf.n_show : (int64_t)P.shows.size();
     const int32_t* tlist = s->at<int32_t>(tfo ? L.off_tfterm : L.off_term);
-    for (int kind = 0; kind < 2; kind++) {
+    if (P.preflop && n_fold) {
+        // folds over the hand classes (a preflop tree has no showdown)
+        if (tm) tm->before(2);
+        hipLaunchKernelGGL((k_fold_class<T>), dim3((unsigned)n_fold), dim3(kBlock), 0, side, nodes, tlist, Hp,
+                           (int)P.H, reach, cfv, s->at<uint8_t>(L.off_ncompat), nzs);
+        if (tm) tm->after();
+    }
+    for (int kind = 0; kind < 2 && !P.preflop; kind++) {
         const int64_t cnt = kind ? n_show : n_fold;
         if (!cnt) continue;
         if (tm) tm->before(2);
@@ -2394,7 +2777,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     }
     // depth-limit leaves: exact equity for all-in leaves (and for every leaf
     // without a network), the network for the others
-    const int64_t n_eq_active = s->net ? P.n_allin : L.n_eq;
+    const int64_t n_eq_active = (s->net || P.preflop) ? P.n_allin : L.n_eq;
     if (n_eq_active) {
         const int64_t n_grp = s->net ? L.n_grp_allin : L.n_grp;
         dim3 grid((unsigned)((Hp + kBlock - 1) / kBlock), (unsigned)n_grp, kEqSplit);
@@ -2418,7 +2801,39 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->at<T>(L.off_eqpart), cfv);
         if (tm) tm->after();
     }
-    if (s->net && L.n_net) {
+    if (P.preflop && L.n_net && s->net) {
+        // preflop leaves: the flop-level network on the canonical flops (a
+        // solver without one refuses to iterate, leaves_ready)
+        pcfr_leafnet* net = s->net;
+        const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
+        const int ldx = (int)net->P.pdims[0], ldy = (int)net->P.pdims[net->P.L];
+        const float* Y = reinterpret_cast<const float*>(net->ws + net->P.off_y);
+        // about 1024 workgroups for the rows
+        const int fpg = (int)std::max<int64_t>(1, (rows + 1023) / 1024);
+        const int n_grp = (int)((L.n_next + fpg - 1) / fpg);
+        if (tm) tm->before(4);
+        hipLaunchKernelGGL((k_flop_leaf_input<T>), dim3((unsigned)L.n_net, (unsigned)n_grp), dim3(kBlock), 0, stream,
+                           nodes, s->at<int32_t>(L.off_net), Hp, reach, s->at<int16_t>(L.off_c2h), s->at<T>(L.off_rc),
+                           s->at<T>(L.off_agg), s->at<float>(L.off_spr), (int)L.n_next, fpg,
+                           s->at<int8_t>(L.off_flops), ldx, reinterpret_cast<uint16_t*>(net->ws + net->P.off_x));
+        if (tm) tm->after();
+        int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
+        if (rc) return rc;
+        if (s->leaf_zero_sum) {
+            if (tm) tm->before(4);
+            hipLaunchKernelGGL((k_flop_leaf_zerosum<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, (int)L.n_next,
+                               s->at<int8_t>(L.off_flops), s->at<T>(L.off_rc), s->at<T>(L.off_agg), Y, ldy,
+                               s->at<T>(L.off_zs));
+            if (tm) tm->after();
+        }
+        if (tm) tm->before(4);
+        hipLaunchKernelGGL((k_flop_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)Hp), dim3(kBlock), 0, stream,
+                           nodes, s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), (int)L.n_next,
+                           s->at<int8_t>(L.off_flops), s->at<int32_t>(L.off_orbit), s->at<int32_t>(L.off_hoff),
+                           s->at<int16_t>(L.off_hlist), Hp, (int)L.H_leaf, cfv, Y, ldy, s->at<T>(L.off_rc),
+                           s->at<T>(L.off_agg), s->leaf_zero_sum ? s->at<T>(L.off_zs) : nullptr);
+        if (tm) tm->after();
+    } else if (s->net && L.n_net) {
         pcfr_leafnet* net = s->net;
         const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
         if (tm) tm->before(4);
@@ -2561,7 +2976,7 @@ static int32_t make_tf_plan(pcfr_solver* s) {
     tf.on = false;
     tf.tf_off.assign(P.levels + 1, 0);
     tf.rest_off.assign(P.levels + 1, 0);
-    if (!s->tf_enabled) return PCFR_OK;
+    if (!s->tf_enabled || P.preflop) return PCFR_OK;   // preflop folds run over classes (k_fold_class)
     const int64_t groups = L.Hp / 4, fuse = s->sched.fuse_threads;
     std::vector<DNode> tf_rec, rest_rec;
     std::vector<char> handled(P.nodes.size(), 0);
@@ -2745,6 +3160,11 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         std::vector<const Tree*> tv;
         for (auto& t : s->trees) tv.push_back(&t);
         if (cfg->suit_iso) {
+            for (const Tree* t : tv)
+                if (t->root_mask == 0) {
+                    set_error("preflop roots are solved over hand classes already; suit_iso is for boards");
+                    return PCFR_E_UNSUPPORTED;
+                }
             rc = suit_iso_map(tv, ranges, s->iso);
             if (rc != PCFR_OK) return rc;
         }
@@ -2793,6 +3213,13 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         }
         s->pair_mass[g] = z;
         if (!(z > 0)) { set_error("no compatible pair of hands carries mass"); return PCFR_E_INVALID_ARG; }
+        if (P.preflop)
+            for (int p = 0; p < 2; p++)
+                for (int k = 0; k < kCombos; k++)
+                    if (rg[p * kCombos + k] != rg[p * kCombos + P.hand_combo[g][P.combo_hand[g][k]]]) {
+                        set_error("a preflop root needs suit-symmetric ranges (equal on the combos of each hand class)");
+                        return PCFR_E_INVALID_ARG;
+                    }
     }
     s->stream = reinterpret_cast<hipStream_t>(stream);
     s->ws = reinterpret_cast<char*>(workspace);
@@ -2867,6 +3294,13 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
         if ((rc = up(L.off_net, P.net_leaves.data(), sizeof(int32_t) * P.net_leaves.size()))) return rc;
         if ((rc = up(L.off_spr, P.net_spr.data(), sizeof(float) * P.net_spr.size()))) return rc;
         if ((rc = up(L.off_potk, P.net_potk.data(), sizeof(double) * P.net_potk.size()))) return rc;
+        if ((rc = up(L.off_hoff, P.hoff.data(), sizeof(int32_t) * P.hoff.size()))) return rc;
+        if ((rc = up(L.off_hlist, P.hlist.data(), sizeof(int16_t) * P.hlist.size()))) return rc;
+        if (P.preflop) {
+            if ((rc = up(L.off_ncompat, P.ncompat.data(), P.ncompat.size()))) return rc;
+            if ((rc = up(L.off_flops, P.flops.data(), P.flops.size()))) return rc;
+            if ((rc = up(L.off_orbit, P.flop_orbit.data(), sizeof(int32_t) * P.flop_orbit.size()))) return rc;
+        }
         HIPCHK(hipStreamSynchronize(s->stream));
         // pairwise equity table of each subgame holding depth-limit leaves
         for (int32_t g = 0; g < n; g++) {
@@ -2988,6 +3422,16 @@ static int32_t strategy_impl(pcfr_solver* s, int32_t g, int32_t node, int32_t wh
     return PCFR_OK;
 }
 
+// A preflop tree's leaves have no exact value: iterating and evaluating need
+// the flop-level network.
+static int32_t leaves_ready(const pcfr_solver* s) {
+    if (s->P.preflop && s->L.n_net && !s->net) {
+        set_error("leaves at the flop deal need a leaf network (pcfr_solver_attach_leafnet)");
+        return PCFR_E_STATE;
+    }
+    return PCFR_OK;
+}
+
 static int32_t root_cfv_impl(pcfr_solver* s, int32_t g, int32_t which, double* out, bool sweep_first) {
     if (!s || !out) { set_error("null argument"); return PCFR_E_INVALID_ARG; }
     if (g < 0 || g >= s->P.n_sub) { set_error("subgame index out of range"); return PCFR_E_INVALID_ARG; }
@@ -2995,7 +3439,9 @@ static int32_t root_cfv_impl(pcfr_solver* s, int32_t g, int32_t which, double* o
     if (which == PCFR_CURRENT) return fetch_hands(s, s->ws + L.off_root + L.esz * 2 * L.Hp * (size_t)g, 2, out, g);
     if (which != PCFR_AVG) { set_error("which must be PCFR_AVG or PCFR_CURRENT"); return PCFR_E_INVALID_ARG; }
     if (sweep_first) {
-        int32_t rc = sweep<MODE_EV>(s);
+        int32_t rc = leaves_ready(s);
+        if (rc) return rc;
+        rc = sweep<MODE_EV>(s);
         if (rc) return rc;
     }
     return fetch_hands(s, s->ws + L.off_cfv + L.esz * 2 * L.Hp * (size_t)s->P.root_node[g], 2, out, g);
@@ -3054,7 +3500,9 @@ static int32_t node_values_impl(pcfr_solver* s, int32_t g, double* out) {
 // Best-response sweep for every subgame, then per subgame
 // (BR_0 + BR_1) / 2 per unit of joint pair mass.
 static int32_t exploitability_impl(pcfr_solver* s, double* chips, double* br) {
-    int32_t rc = sweep<MODE_BR>(s);
+    int32_t rc = leaves_ready(s);
+    if (rc) return rc;
+    rc = sweep<MODE_BR>(s);
     if (rc) return rc;
     const int32_t n = s->P.n_sub;
     std::vector<double> v(2 * kCombos);
@@ -3277,11 +3725,13 @@ static int32_t autotune_impl(pcfr_solver* s, int32_t reps, double* ms_before, do
 extern "C" {
 
 int32_t pcfr_autotune(pcfr_solver* s, int32_t reps, double* ms_before, double* ms_after) {
+    if (s) if (const int32_t rc = leaves_ready(s)) return rc;
     return autotune_impl(s, reps, ms_before, ms_after);
 }
 
 int32_t pcfr_batch_autotune(pcfr_solver* s, int32_t budget_ms) {
     if (!s || budget_ms <= 0) { set_error("null solver or non-positive budget"); return PCFR_E_INVALID_ARG; }
+    if (const int32_t rc = leaves_ready(s)) return rc;
     {
         int64_t t = 0;
         int32_t rc = pcfr_iteration(s, &t);
@@ -3366,6 +3816,7 @@ int32_t pcfr_solver_free(pcfr_solver* s) {
 
 int32_t pcfr_cfr_iterate(pcfr_solver* s, int32_t n) {
     if (!s || n < 0) { set_error("null solver or negative count"); return PCFR_E_INVALID_ARG; }
+    if (const int32_t rc = leaves_ready(s)) return rc;
     if (s->launch_mode == PCFR_LAUNCH_PERSISTENT) {
         if (n > 0) {
             const int32_t rc = s->cfg.dtype == PCFR_F64 ? persist_launch<double>(s, n) : persist_launch<float>(s, n);
@@ -3381,6 +3832,7 @@ int32_t pcfr_cfr_iterate(pcfr_solver* s, int32_t n) {
 
 int32_t pcfr_profile_iterations(pcfr_solver* s, int32_t n, double* ms, int64_t* launches) {
     if (!s || n < 0 || !ms || !launches) { set_error("null argument or negative count"); return PCFR_E_INVALID_ARG; }
+    if (const int32_t rc = leaves_ready(s)) return rc;
     for (int k = 0; k < 8; k++) { ms[k] = 0; launches[k] = 0; }
     for (int32_t i = 0; i < n; i++) {
         LaunchTimer tm;

@@ -10,7 +10,9 @@
 // bet included, and need chips behind.  A betting round ends on check-check
 // or a call: at the river in a showdown, with a player all in in a chance
 // runout to showdown (or an exact all-in leaf under a depth limit), under a
-// depth limit in a leaf, else in a chance node dealing the next card.
+// depth limit in a leaf, else in a chance node dealing the next card.  A
+// preflop root (no board) is built depth-limited only, with its leaves at
+// the flop deal, and only when no betting line puts a player all in.
 //
 // Nodes are numbered in the order a FIFO queue pops them, so ids are
 // breadth-first and the children of a node are consecutive.
@@ -120,7 +122,11 @@ struct Builder {
 }  // namespace
 
 int32_t build_tree(const pcfr_tree_spec& sp, Tree& t) {
-    if (sp.n_board < 3 || sp.n_board > 5) { set_error("n_board must be 3, 4 or 5"); return PCFR_E_INVALID_ARG; }
+    if ((sp.n_board != 0 && sp.n_board < 3) || sp.n_board > 5) { set_error("n_board must be 0, 3, 4 or 5"); return PCFR_E_INVALID_ARG; }
+    if (sp.n_board == 0 && sp.depth_limit != 1) {
+        set_error("a preflop root (n_board = 0) needs depth_limit = 1: its leaves sit at the flop deal");
+        return PCFR_E_UNSUPPORTED;
+    }
     if (sp.pot <= 0 || (sp.pot & 1)) { set_error("pot must be positive and even"); return PCFR_E_INVALID_ARG; }
     if (sp.stack[0] < 0 || sp.stack[1] < 0) { set_error("stacks must be >= 0"); return PCFR_E_INVALID_ARG; }
     if (sp.n_sizes < 0 || sp.n_sizes > 8) { set_error("n_sizes must be in [0, 8]"); return PCFR_E_INVALID_ARG; }
@@ -165,6 +171,10 @@ int32_t build_tree(const pcfr_tree_spec& sp, Tree& t) {
         t.count[n.type]++;
         if (n.type == PCFR_NODE_DECISION) t.rows += nd.n_child;
         if (n.depth + 1 > t.n_levels) t.n_levels = n.depth + 1;
+    }
+    if (sp.n_board == 0 && t.count[PCFR_NODE_ALLIN_LEAF] > 0) {
+        set_error("a preflop tree whose betting can put a player all in is not supported (the runout has five cards)");
+        return PCFR_E_UNSUPPORTED;
     }
     return PCFR_OK;
 }

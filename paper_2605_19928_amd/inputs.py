@@ -152,6 +152,36 @@ def flop_config(seed: int, support: int | None = None, pot: int = 100, stack: in
     return spec, np.stack([r0, r1])
 
 
+def hand_classes() -> np.ndarray:
+    """[1326] the preflop hand class of each combo: 0..12 pairs by rank, then
+    suited and offsuit rank pairs (169 classes)."""
+    cc = combo_cards()
+    ra, rb = cc[:, 0] // 4, cc[:, 1] // 4
+    hi, lo = np.maximum(ra, rb), np.minimum(ra, rb)
+    pair_idx = hi * (hi - 1) // 2 + lo
+    suited = cc[:, 0] % 4 == cc[:, 1] % 4
+    return np.where(ra == rb, ra, 13 + np.where(suited, 0, 78) + pair_idx)
+
+
+def preflop_config(seed: int, pot: int = 20, stack: int = 1000, sizes=(50, 100), max_raises: int = 3,
+                   alpha: float = 1.0):
+    """Preflop root (no board) stopping at the flop deal: pot 20 (each player
+    in for 1 bb of 10 chips), 100 bb behind, sizes {50, 100}% without all-in,
+    max 3 bets/raises.  Ranges are suit-symmetric: a Dirichlet(alpha) weight
+    per hand class, spread evenly over the class's combos (uniform ranges are
+    the true preflop start; these keep the symmetry and vary the mass)."""
+    rng = np.random.default_rng(seed)
+    cls = hand_classes()
+    size = np.bincount(cls, minlength=169)
+    r = []
+    for _ in range(2):
+        w = rng.dirichlet(np.full(169, alpha))
+        r.append(w[cls] / size[cls])
+    spec = dict(board=[], pot=pot, stacks=(stack, stack), sizes=list(sizes), allin=False,
+                max_raises=max_raises, depth_limit=1)
+    return spec, np.stack(r)
+
+
 def batch_config(seed: int, count_nodes, n: int = 256, river_share: float = 0.7,
                  lo: int = 10, hi: int = 2000, sizes_pool=(33, 50, 75, 100, 150)):
     """Many independent river/turn subgames of uneven size.

@@ -1,0 +1,109 @@
+"""Preflop roots on the GPU vs the oracle: the tree solved over the 169 hand
+classes, folds over classes, and leaves at the flop deal valued by the
+flop-level network on the 1755 canonical flops.
+
+The oracle solves in combo space over every history; each iteration it
+builds the network rows of every canonical flop from its own reach, runs the
+FP64 network with the same bf16 roundings, applies the zero-sum shift per
+row and values each history by the mean over all C(48,3) flops clear of both
+hands (a flop's row is its canonical flop's, the hand mapped back).  Bound:
+1e-4 pot on root values after each of 3 iterations, as for the flop's
+network leaves (a bf16 rounding boundary can move one network output by an
+ulp).  With exact leaves absent, the solver refuses to iterate without a
+network; ranges that are not suit-symmetric are refused."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp
+from paper_2605_19928_amd import inputs as I
+from paper_2605_19928_amd import pcfr as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rand_params(rng, shapes, scale=1.0):
+    return [((rng.standard_normal((o, i)) * scale / np.sqrt(i)).astype(np.float32),
+             (rng.standard_normal(o) * 0.05).astype(np.float32)) for o, i in shapes]
+
+
+@pytest.mark.parametrize("dtype,zero_sum,max_raises", [("f64", True, 1), ("f64", False, 2), ("f32", True, 1)])
+def test_preflop_network_leaves_match_oracle(dtype, zero_sum, max_raises):
+    spec, r = I.preflop_config(3, sizes=(100,), max_raises=max_raises)
+    say(f"case: preflop {spec} {dtype} zero_sum={zero_sum}")
+    gt = P.Tree(**spec)
+    gs = P.Solver(gt, r, P.SolverConfig(dtype=dtype))
+    n_leaves, n_next = gs.leaf_rows()
+    assert n_next == 1755 and n_leaves == gt.n_leaf
+    rng = np.random.default_rng(11)
+    net = P.LeafNet(P.LEAF_D_IN, 64, 2, P.LEAF_D_OUT, max_batch=n_leaves * n_next)
+    params = rand_params(rng, net.layer_shapes(), scale=2.0)
+    net.set_params(params)
+    gs.attach_leafnet(net)
+    gs.set_leaf_zero_sum(zero_sum)
+    ot = O.Tree.holdem(**spec)
+    os_ = O.Solver(ot, r)
+    e = ot.export()
+    leaves = np.flatnonzero(e["type"] == O.T_LEAF)
+    flops, _ = O.canonical_flops()
+    eff = spec["stacks"][0]
+    pot = spec["pot"]
+    for it in range(3):
+        reach = os_.reach_current()
+        ev = np.zeros((len(leaves), 2, len(flops), 1326))
+        for li, n in enumerate(leaves):
+            c = e["contrib"][n][0]
+            X = mlp.flop_leaf_inputs(reach[n], flops, pot=2 * c, stack_behind=pot // 2 + eff - c, d_in=P.LEAF_D_IN)
+            Y = mlp.forward(params, X, emulate_bf16=True)
+            rows = np.stack([Y[:, :1326], Y[:, 1326:2652]], axis=1)
+            if zero_sum:
+                rows = rows - mlp.flop_zero_sum_shifts(rows, reach[n], flops)[:, None, None]
+            ev[li] = rows.transpose(1, 0, 2)
+        os_.set_flop_leaf_table(ev)
+        os_.iterate(1)
+        gs.iterate(1)
+        d = np.abs(gs.root_cfv("current") - os_.root_cfv("current")).max() / pot
+        say(f"  iteration {it + 1}: root cfv (current) max |d| = {d:.3e} pot")
+        assert d <= 1e-4
+    eg, _ = gs.exploitability()
+    assert np.isfinite(eg)
+
+
+def test_preflop_refusals():
+    spec, r = I.preflop_config(1, sizes=(100,), max_raises=1)
+    t = P.Tree(**spec)
+    s = P.Solver(t, r)
+    with pytest.raises(P.PcfrError) as e:       # no exact model at the flop deal
+        s.iterate(1)
+    assert e.value.code == P.E_STATE
+    bad = r.copy()
+    bad[0, 0] *= 1.5                           # breaks the suit symmetry of one class
+    with pytest.raises(P.PcfrError) as e:
+        P.Solver(t, bad)
+    assert e.value.code == P.E_INVALID_ARG
+    with pytest.raises(P.PcfrError) as e:
+        P.Solver(t, r, P.SolverConfig(suit_iso=1))
+    assert e.value.code == P.E_UNSUPPORTED
+
+
+def test_preflop_strategies_repeat_over_each_class():
+    """Per-combo outputs of a class-solved root repeat the class's value."""
+    spec, r = I.preflop_config(2, sizes=(100,), max_raises=1)
+    t = P.Tree(**spec)
+    s = P.Solver(t, r, P.SolverConfig(dtype="f64"))
+    n_leaves, n_next = s.leaf_rows()
+    net = P.LeafNet(P.LEAF_D_IN, 64, 2, P.LEAF_D_OUT, max_batch=n_leaves * n_next)
+    net.set_params(rand_params(np.random.default_rng(5), net.layer_shapes()))
+    s.attach_leafnet(net)
+    s.iterate(4)
+    cls = I.hand_classes()
+    st = s.strategy(0, "avg")
+    v = s.root_cfv("current")
+    for c in range(169):
+        m = cls == c
+        assert np.ptp(st[:, m], axis=1).max() == 0.0
+        assert np.ptp(v[:, m], axis=1).max() == 0.0

@@ -46,6 +46,9 @@ SPECS = [
     I.flop_config(0)[0],
     dict(board=[1, 9, 17], pot=40, stacks=(30, 500), sizes=[50], allin=True, max_raises=2, depth_limit=0),
     dict(board=[0, 4, 8, 12, 16], pot=2, stacks=(0, 0), sizes=[], allin=False, max_raises=0, depth_limit=0),
+    # preflop roots: leaves at the flop deal, no all-in
+    dict(board=[], pot=20, stacks=(1000, 1000), sizes=[100], allin=False, max_raises=1, depth_limit=1),
+    dict(board=[], pot=20, stacks=(1000, 1000), sizes=[50, 100], allin=False, max_raises=3, depth_limit=1),
 ]
 
 
@@ -60,7 +63,7 @@ def test_tree_arrays_identical(spec):
     assert (a.n_decision, a.n_fold, a.n_showdown, a.n_chance, a.n_leaf, a.n_allin, a.n_levels, a.n_rows) == \
         (b.n_decision, b.n_fold, b.n_showdown, b.n_chance, b.n_leaf, b.n_allin, b.n_levels, b.n_rows)
     nb = len(spec["board"])
-    assert a.n_hands == {3: 1176, 4: 1128, 5: 1081}[nb]
+    assert a.n_hands == {0: 169, 3: 1176, 4: 1128, 5: 1081}[nb]
     assert a.n_hands_padded % 64 == 0 and a.n_hands_padded >= a.n_hands
 
 
@@ -102,6 +105,21 @@ def test_invalid_specs_rejected(bad):
     with pytest.raises(P.PcfrError) as e:
         P.Tree(**bad)
     assert e.value.code == P.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("bad", [
+    dict(board=[], pot=20, stacks=(1000, 1000), sizes=[100], allin=False, max_raises=1, depth_limit=0),
+    dict(board=[], pot=20, stacks=(1000, 1000), sizes=[100], allin=True, max_raises=1, depth_limit=1),
+    dict(board=[], pot=20, stacks=(15, 15), sizes=[100], allin=False, max_raises=1, depth_limit=1),
+])
+def test_unsupported_preflop_specs_refused(bad):
+    """A preflop root must stop at the flop and never put a player all in;
+    the oracle refuses the same specs."""
+    with pytest.raises(P.PcfrError) as e:
+        P.Tree(**bad)
+    assert e.value.code == P.E_UNSUPPORTED
+    with pytest.raises(ValueError):
+        O.Tree.holdem(**bad)
 
 
 @pytest.mark.parametrize("nb", [4, 3])

@@ -179,3 +179,26 @@ def test_preflop_iterates_stay_suit_symmetric():
     v = s.root_cfv("current")
     for c in range(169):
         assert np.ptp(v[:, cls == c], axis=1).max() <= 1e-9 * np.abs(v).max()
+
+
+def test_flop_zero_sum_shift_makes_each_row_zero_sum():
+    """After the shift, sum_h r0 M1 (EV0 - d) + r1 M0 (EV1 - d) = 0 for each
+    flop row, with M summed over opponent combos one by one."""
+    rng = np.random.default_rng(6)
+    reach = rng.random((2, 1326))
+    flops = np.array([[0, 1, 2], [3, 17, 40]])
+    ev = rng.standard_normal((2, 2, 1326))
+    d = mlp.flop_zero_sum_shifts(ev, reach, flops)
+    cards = [set(int(c) for c in CC[h]) for h in range(1326)]
+    for j, f in enumerate(flops):
+        fs = set(int(c) for c in f)
+        clear = [h for h in range(1326) if not cards[h] & fs]
+        m = {p: np.zeros(1326) for p in (0, 1)}
+        for h in clear:
+            opp = [o for o in clear if not cards[o] & cards[h]]
+            m[1][h] = reach[1, opp].sum()
+            m[0][h] = reach[0, opp].sum()
+        z = sum(reach[0, h] * m[1][h] * (ev[j, 0, h] - d[j]) + reach[1, h] * m[0][h] * (ev[j, 1, h] - d[j])
+                for h in clear)
+        scale = sum(reach[0, h] * m[1][h] for h in clear)
+        assert abs(z) <= 1e-9 * scale
