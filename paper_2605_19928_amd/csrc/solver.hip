@@ -1705,6 +1705,7 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_input(const DNode* __restr
     constexpr int CI = (kCombos + kBlock - 1) / kBlock;
     __shared__ double xc[2][kComboPad];
     __shared__ double xch[2 * kWaves];
+    __shared__ uint16_t kc[kComboPad];   // cards of each combo, lo | hi << 8
     const int li = blockIdx.x, tid = threadIdx.x;
     const bool lead = blockIdx.y == 0;
     const DNode nd = nodes[leaves[li]];
@@ -1720,6 +1721,7 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_input(const DNode* __restr
         kb[i] = -1;
         if (k < kCombos) {
             combo_cards(k, ka[i], kb[i]);
+            kc[k] = (uint16_t)(kb[i] | (ka[i] << 8));
             const int h = combo_hand[k];
             const T v0 = h >= 0 ? r0[h] : T(0), v1 = h >= 0 ? r1[h] : T(0);
             xc[0][k] = (double)v0;
@@ -1768,8 +1770,7 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_input(const DNode* __restr
                 float xv = 0.f;
                 if (col < 2 * kCombos) {
                     const int pp = col >= kCombos, k = col - pp * kCombos;
-                    int a, b;
-                    combo_cards(k, a, b);
+                    const int a = kc[k] >> 8, b = kc[k] & 0xff;
                     if (a != x && a != y && a != z && b != x && b != y && b != z)
                         xv = (float)(xc[pp][k] * (pp ? i1 : i0));
                 } else if (col < 2 * kCombos + 52) {
@@ -1799,112 +1800,121 @@ __device__ __forceinline__ T flop_mass(const T* rs, const T* cs, T tot, int a, i
            rs[combo_index(b, z)] + rs[combo_index(x, y)] + rs[combo_index(x, z)] + rs[combo_index(y, z)];
 }
 
-// Zero-sum shift of a preflop leaf row (as k_leaf_zerosum, with the flop's
-// three cards blocked): d = e / (2 z), e = sum_h r0 M1 EV0 + r1 M0 EV1,
-// z = sum_h r0 M1, over the combos clear of the flop.
+// Preflop leaf values, first pass: one workgroup per (leaf, group of
+// canonical flops) reads each flop's network row once, coalesced (thread t
+// owns combos t, t + 256, ...).  Per row it forms M_{-i}(x | f) for its
+// combos, the row's zero-sum shift d = e / (2 z) (as k_leaf_zerosum, with
+// e = sum_x r0 M1 EV0 + r1 M0 EV1 and z = sum_x r0 M1 over the combos clear
+// of the flop) when the correction is on, and adds orbit(f) x
+// (EV_i(x | f) - d) M_{-i}(x | f) to its combos' sums, flop by flop.  At the
+// end each hand's sum over its combos (in hlist order) goes to
+// part[leaf][group][player][hand].  With suit-symmetric reach, the flops of
+// f's orbit give f's sum with a class's combos permuted among themselves, so
+// the canonical flops weighted by their orbits stand for all flops.
+constexpr int kFlopsPerGroup = 8;   // canonical flops per workgroup of the first pass
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_flop_leaf_zerosum(int n_flops, const int8_t* __restrict__ flops,
-                                                              const T* __restrict__ Rc, const T* __restrict__ agg,
-                                                              const float* __restrict__ Y, int ldy,
-                                                              T* __restrict__ delta) {
+__global__ __launch_bounds__(kBlock) void k_flop_leaf_sums(const DNode* __restrict__ nodes,
+                                                           const int32_t* __restrict__ leaves, int n_flops,
+                                                           int flops_per_group, const int8_t* __restrict__ flops,
+                                                           const int32_t* __restrict__ orbit,
+                                                           const int32_t* __restrict__ hoff /* [n_sub][Hp + 1] */,
+                                                           const int16_t* __restrict__ hlist /* [n_sub][kComboPad] */,
+                                                           int Hp, int H, const float* __restrict__ Y, int ldy,
+                                                           const T* __restrict__ Rc, const T* __restrict__ agg,
+                                                           int zero_sum, T* __restrict__ part) {
     constexpr int CI = (kCombos + kBlock - 1) / kBlock;
     __shared__ T rs[2][kComboPad];
     __shared__ T cs[2][52];
     __shared__ T xch[2 * kWaves];
-    const int row = blockIdx.x, li = row / n_flops, f = row - li * n_flops, tid = threadIdx.x;
-    const int x = flops[4 * f], y = flops[4 * f + 1], z = flops[4 * f + 2];
-    const T* rc = Rc + (int64_t)li * 2 * kComboPad;
-    const float* yr = Y + (int64_t)row * ldy;
-    float e0[CI], e1[CI];
-#pragma unroll
-    for (int i = 0; i < CI; i++) {
-        const int k = tid + i * kBlock, kk = k < kCombos ? k : 0;
-        e0[i] = yr[kk];
-        e1[i] = yr[kCombos + kk];
-        if (k < kCombos) { rs[0][k] = rc[k]; rs[1][k] = rc[kComboPad + k]; }
-    }
-    if (tid < 104) cs[tid / 52][tid % 52] = agg[(int64_t)li * kAgg + (tid / 52) * 53 + tid % 52];
-    const T t0 = agg[(int64_t)li * kAgg + 52], t1 = agg[(int64_t)li * kAgg + 105];
-    __syncthreads();
-    T e = T(0), zz = T(0);
-#pragma unroll
-    for (int i = 0; i < CI; i++) {
-        const int k = tid + i * kBlock;
-        if (k >= kCombos) continue;
-        int a, b;
-        combo_cards(k, a, b);
-        if (a == x || a == y || a == z || b == x || b == y || b == z) continue;
-        const T m1 = flop_mass(rs[1], cs[1], t1, a, b, x, y, z);
-        const T m0 = flop_mass(rs[0], cs[0], t0, a, b, x, y, z);
-        e += rs[0][k] * m1 * (T)e0[i] + rs[1][k] * m0 * (T)e1[i];
-        zz += rs[0][k] * m1;
-    }
-    block_sum2(e, zz, xch);
-    if (tid == 0) delta[row] = zz > T(0) ? e / (T(2) * zz) : T(0);
-}
-
-// Preflop leaf values over the hand classes.  With suit-symmetric reach a
-// class c's value is pot / C(48,3) / |c| times the sum over canonical flops
-// f of orbit(f) x sum over the combos x of c clear of f of
-// (EV_i(x | f) - d_f) M_{-i}(x | f): the flops of f's orbit give the same
-// sum with the combos of c permuted among themselves.  One workgroup per
-// (leaf, hand); its threads stride over the flops, partial sums added in a
-// fixed order.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_flop_leaf_combine(const DNode* __restrict__ nodes,
-                                                              const int32_t* __restrict__ leaves,
-                                                              const double* __restrict__ pot_over_k, int n_flops,
-                                                              const int8_t* __restrict__ flops,
-                                                              const int32_t* __restrict__ orbit,
-                                                              const int32_t* __restrict__ hoff /* [n_sub][Hp + 1] */,
-                                                              const int16_t* __restrict__ hlist /* [n_sub][kComboPad] */,
-                                                              int Hp, int H, T* __restrict__ cfv,
-                                                              const float* __restrict__ Y, int ldy,
-                                                              const T* __restrict__ Rc, const T* __restrict__ agg,
-                                                              const T* __restrict__ delta) {
-    __shared__ T rs[2][kComboPad];
-    __shared__ T cs[2][52];
-    __shared__ T xch[2 * kWaves];
-    const int li = blockIdx.x, h = blockIdx.y, tid = threadIdx.x;
-    const int64_t n = leaves[li];
-    const DNode nd = nodes[n];
-    T* v0 = cfv + n * 2 * Hp;
-    T* v1 = v0 + Hp;
-    if (h >= H) {
-        if (tid == 0) { v0[h] = T(0); v1[h] = T(0); }
-        return;
-    }
+    const int li = blockIdx.x, grp = blockIdx.y, tid = threadIdx.x;
+    const DNode nd = nodes[leaves[li]];
     const T* rc = Rc + (int64_t)li * 2 * kComboPad;
     for (int k = tid; k < kCombos; k += kBlock) { rs[0][k] = rc[k]; rs[1][k] = rc[kComboPad + k]; }
     if (tid < 104) cs[tid / 52][tid % 52] = agg[(int64_t)li * kAgg + (tid / 52) * 53 + tid % 52];
     const T t0 = agg[(int64_t)li * kAgg + 52], t1 = agg[(int64_t)li * kAgg + 105];
-    const int32_t* ho = hoff + (int64_t)nd.sub * (Hp + 1);
-    const int16_t* hl = hlist + (int64_t)nd.sub * kComboPad;
-    const int j0 = ho[h], j1 = ho[h + 1];
+    int ka[CI], kb[CI];
+    T acc0[CI], acc1[CI];
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock;
+        ka[i] = -1;
+        kb[i] = -1;
+        if (k < kCombos) combo_cards(k, ka[i], kb[i]);
+        acc0[i] = T(0);
+        acc1[i] = T(0);
+    }
     __syncthreads();
-    T acc0 = T(0), acc1 = T(0);
-    for (int f = tid; f < n_flops; f += kBlock) {
+    const int f0 = grp * flops_per_group, f1 = min(n_flops, f0 + flops_per_group);
+    for (int f = f0; f < f1; f++) {
         const int x = flops[4 * f], y = flops[4 * f + 1], z = flops[4 * f + 2];
         const float* yr = Y + ((int64_t)li * n_flops + f) * ldy;
-        const T d = delta ? delta[(int64_t)li * n_flops + f] : T(0);
-        T s0 = T(0), s1 = T(0);
-        for (int j = j0; j < j1; j++) {
-            const int k = hl[j];
-            int a, b;
-            combo_cards(k, a, b);
-            if (a == x || a == y || a == z || b == x || b == y || b == z) continue;
-            s0 += ((T)yr[k] - d) * flop_mass(rs[1], cs[1], t1, a, b, x, y, z);
-            s1 += ((T)yr[kCombos + k] - d) * flop_mass(rs[0], cs[0], t0, a, b, x, y, z);
+        T m0[CI], m1[CI], y0[CI], y1[CI];
+        T e = T(0), zz = T(0);
+#pragma unroll
+        for (int i = 0; i < CI; i++) {
+            const int k = tid + i * kBlock, a = ka[i], b = kb[i];
+            const bool live = a >= 0 && a != x && a != y && a != z && b != x && b != y && b != z;
+            y0[i] = live ? (T)yr[k] : T(0);
+            y1[i] = live ? (T)yr[kCombos + k] : T(0);
+            m1[i] = live ? flop_mass(rs[1], cs[1], t1, a, b, x, y, z) : T(0);
+            m0[i] = live ? flop_mass(rs[0], cs[0], t0, a, b, x, y, z) : T(0);
+            if (live) {
+                e += rs[0][k] * m1[i] * y0[i] + rs[1][k] * m0[i] * y1[i];
+                zz += rs[0][k] * m1[i];
+            }
+        }
+        T d = T(0);
+        if (zero_sum) {
+            block_sum2(e, zz, xch);
+            d = zz > T(0) ? e / (T(2) * zz) : T(0);
+            __syncthreads();   // xch is rewritten by the next flop
         }
         const T w = (T)orbit[f];
-        acc0 += w * s0;
-        acc1 += w * s1;
+#pragma unroll
+        for (int i = 0; i < CI; i++) {
+            acc0[i] += w * ((y0[i] - d) * m1[i]);
+            acc1[i] += w * ((y1[i] - d) * m0[i]);
+        }
     }
-    block_sum2(acc0, acc1, xch);
-    if (tid == 0) {
-        const T scale = (T)(pot_over_k[li] / (double)(j1 - j0));
-        v0[h] = scale * acc0;
-        v1[h] = scale * acc1;
+    // per-combo sums to LDS (the reach rows are no longer needed), then per hand
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CI; i++) {
+        const int k = tid + i * kBlock;
+        if (k < kCombos) { rs[0][k] = acc0[i]; rs[1][k] = acc1[i]; }
+    }
+    __syncthreads();
+    const int32_t* ho = hoff + (int64_t)nd.sub * (Hp + 1);
+    const int16_t* hl = hlist + (int64_t)nd.sub * kComboPad;
+    T* out = part + ((int64_t)li * gridDim.y + grp) * 2 * Hp;
+    for (int h = tid; h < Hp; h += kBlock) {
+        T s0 = T(0), s1 = T(0);
+        if (h < H)
+            for (int j = ho[h]; j < ho[h + 1]; j++) { s0 += rs[0][hl[j]]; s1 += rs[1][hl[j]]; }
+        out[h] = s0;
+        out[Hp + h] = s1;
+    }
+}
+
+// Second pass: v_i(h) = pot / C(48,3) / |h| x the sum over the groups, in
+// group order; zero on padding hands.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flop_leaf_values(const int32_t* __restrict__ leaves,
+                                                             const double* __restrict__ pot_over_k,
+                                                             const DNode* __restrict__ nodes,
+                                                             const int32_t* __restrict__ hoff, int n_groups, int Hp,
+                                                             int H, const T* __restrict__ part, T* __restrict__ cfv) {
+    const int li = blockIdx.x;
+    const int64_t n = leaves[li];
+    const DNode nd = nodes[n];
+    const int32_t* ho = hoff + (int64_t)nd.sub * (Hp + 1);
+    T* v = cfv + n * 2 * Hp;
+    for (int q = threadIdx.x; q < 2 * Hp; q += blockDim.x) {
+        const int h = q < Hp ? q : q - Hp;
+        T acc = T(0);
+        for (int g = 0; g < n_groups; g++) acc += part[((int64_t)li * n_groups + g) * 2 * Hp + q];
+        v[q] = h < H ? (T)(pot_over_k[li] / (double)(ho[h + 1] - ho[h])) * acc : T(0);
     }
 }
 
@@ -2049,7 +2059,8 @@ struct Plan {
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_zs, off_agg, off_rc, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
         off_eqgrp, off_nsub, off_b4, off_nzs, off_tfrec, off_tfrest, off_tfterm,
-        off_cmap, off_hmap, off_ncompat, off_flops, off_orbit, off_hoff, off_hlist, total;
+        off_cmap, off_hmap, off_ncompat, off_flops, off_orbit, off_hoff, off_hlist, off_fpart, total;
+    int64_t n_fgrp = 0;                   // preflop leaves: flop groups of the first pass
     size_t lds_bytes, lds_fold, lds_show;
     int64_t n_grp = 0, n_grp_allin = 0;   // equity groups: all leaves, the all-in prefix
     int eq_J = 0;                         // leaves per equity group at most
@@ -2583,6 +2594,8 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.off_orbit = take(sizeof(int32_t) * P.flop_orbit.size());
     L.off_hoff = take(sizeof(int32_t) * P.hoff.size());
     L.off_hlist = take(sizeof(int16_t) * P.hlist.size());
+    L.n_fgrp = P.preflop ? (L.n_next + kFlopsPerGroup - 1) / kFlopsPerGroup : 0;
+    L.off_fpart = take(L.esz * L.n_net * L.n_fgrp * 2 * L.Hp);
     L.off_nzs = take(sizeof(int32_t) * (size_t)(2 * P.n_sub + L.rows));   // pruning flags per reach slot
     // terminal fusion: node records of the fused and the remaining backward work, terminals left over
     L.off_tfrec = take(sizeof(DNode) * std::max<size_t>(P.dec.size(), 1));
@@ -2819,19 +2832,15 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (tm) tm->after();
         int32_t rc = leafnet_forward_staged(net, Mp, stream, tm);
         if (rc) return rc;
-        if (s->leaf_zero_sum) {
-            if (tm) tm->before(4);
-            hipLaunchKernelGGL((k_flop_leaf_zerosum<T>), dim3((unsigned)rows), dim3(kBlock), 0, stream, (int)L.n_next,
-                               s->at<int8_t>(L.off_flops), s->at<T>(L.off_rc), s->at<T>(L.off_agg), Y, ldy,
-                               s->at<T>(L.off_zs));
-            if (tm) tm->after();
-        }
         if (tm) tm->before(4);
-        hipLaunchKernelGGL((k_flop_leaf_combine<T>), dim3((unsigned)L.n_net, (unsigned)Hp), dim3(kBlock), 0, stream,
-                           nodes, s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), (int)L.n_next,
+        hipLaunchKernelGGL((k_flop_leaf_sums<T>), dim3((unsigned)L.n_net, (unsigned)L.n_fgrp), dim3(kBlock), 0, stream,
+                           nodes, s->at<int32_t>(L.off_net), (int)L.n_next, (int)kFlopsPerGroup,
                            s->at<int8_t>(L.off_flops), s->at<int32_t>(L.off_orbit), s->at<int32_t>(L.off_hoff),
-                           s->at<int16_t>(L.off_hlist), Hp, (int)L.H_leaf, cfv, Y, ldy, s->at<T>(L.off_rc),
-                           s->at<T>(L.off_agg), s->leaf_zero_sum ? s->at<T>(L.off_zs) : nullptr);
+                           s->at<int16_t>(L.off_hlist), Hp, (int)L.H_leaf, Y, ldy, s->at<T>(L.off_rc),
+                           s->at<T>(L.off_agg), s->leaf_zero_sum ? 1 : 0, s->at<T>(L.off_fpart));
+        hipLaunchKernelGGL((k_flop_leaf_values<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream,
+                           s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), nodes, s->at<int32_t>(L.off_hoff),
+                           (int)L.n_fgrp, Hp, (int)L.H_leaf, s->at<T>(L.off_fpart), cfv);
         if (tm) tm->after();
     } else if (s->net && L.n_net) {
         pcfr_leafnet* net = s->net;
