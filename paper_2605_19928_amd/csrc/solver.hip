@@ -774,7 +774,25 @@ __device__ void term_fold_core(const DNode& nd, int Hp, T (&a)[kHandIt], T (&b)[
         const int lo = coff[cd], hi = coff[cd + 1], mid = lo + ((hi - lo) >> 1);
         T acc = T(0);
         int cnt = 0;
-        for (int j = half ? mid : lo; j < (half ? hi : mid); j++) {
+        // eight list entries per step: their index loads, then their value
+        // loads, are issued together (one LDS round trip each per step
+        // instead of per entry); the sum keeps its sequential order
+        int j = half ? mid : lo;
+        const int je = half ? hi : mid;
+        for (; j + 8 <= je; j += 8) {
+            int ix[8];
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) ix[u] = lst[j + u];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = x[ix[u]];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                acc += v[u];
+                cnt += v[u] != T(0);
+            }
+        }
+        for (; j < je; j++) {
             const T v = x[lst[j]];
             acc += v;
             cnt += v != T(0);
@@ -904,13 +922,21 @@ __device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T 
         T acc = T(0);
         int nz = 0;
         int j = lo;
-        for (; j + 4 <= hi; j += 4) {
-            const T y0 = xs[clist[j]], y1 = xs[clist[j + 1]], y2 = xs[clist[j + 2]], y3 = xs[clist[j + 3]];
-            q[j] = acc; acc += y0;
-            q[j + 1] = acc; acc += y1;
-            q[j + 2] = acc; acc += y2;
-            q[j + 3] = acc; acc += y3;
-            nz += (y0 != T(0)) + (y1 != T(0)) + (y2 != T(0)) + (y3 != T(0));
+        // eight entries per step: index loads, then value loads, issued
+        // together; the prefix keeps its sequential order
+        for (; j + 8 <= hi; j += 8) {
+            int ix[8];
+            T y[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) ix[u] = clist[j + u];
+#pragma unroll
+            for (int u = 0; u < 8; u++) y[u] = xs[ix[u]];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                q[j + u] = acc;
+                acc += y[u];
+                nz += y[u] != T(0);
+            }
         }
         for (; j < hi; j++) { const T y = xs[clist[j]]; q[j] = acc; acc += y; nz += y != T(0); }
         q[hi] = acc;
