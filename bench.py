@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="flop", choices=["flop", "turn", "batch", "flop-batch"])
+    ap.add_argument("--workload", default="flop", choices=["flop", "turn", "batch", "flop-batch", "preflop"])
     ap.add_argument("--batch-flops", type=int, default=32, help="flops per forest for --workload flop-batch")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--profile-iters", type=int, default=5)
@@ -813,6 +813,19 @@ def main():
         result = {
             "metric": "DCFR ms/iter & iters/sec, flop depth-limited subgame; exploitability mbb/hand",
             "value": out["flop_iters_per_s"], "unit": "flop iters/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": out["ms_per_iter"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+            "config": {k: v for k, v in out.items() if k != "kernel_ms_per_iter"},
+            "kernel_ms_per_iter": out["kernel_ms_per_iter"],
+        }
+        print(json.dumps(result), flush=True)
+        return
+
+    if args.workload == "preflop":
+        out = preflop_sweep(args, args.steps, args.warmup)
+        result = {
+            "metric": "DCFR ms/iter & iters/sec, preflop root with leaves at the flop deal; exploitability mbb/hand",
+            "value": out["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": out["ms_per_iter"], "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
             "config": {k: v for k, v in out.items() if k != "kernel_ms_per_iter"},

@@ -1060,7 +1060,6 @@ __device__ void tf_node(const DNode& nd, const DNode* __restrict__ nodes, int Hp
     for (int a = 0; a < A; a++) tv[a] = nullptr;
     if (!dead) {
         int k = 0;
-#pragma unroll
         for (int a = 0; a < A; a++) {
             const DNode ch = nodes[nd.first_child + a];
             if (ch.type != PCFR_NODE_FOLD && ch.type != PCFR_NODE_SHOWDOWN) continue;
@@ -1774,20 +1773,29 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_input(const DNode* __restr
     const float ratio = spr[li];
     const int chunks = ldx / 8;
     const int f0 = blockIdx.y * flops_per_group, f1 = min(n_flops, f0 + flops_per_group);
-    for (int f = f0; f < f1; f++) {
+    // one wave per flop: its sums are wave reductions, no workgroup barrier
+    const int lane = tid & 63;
+    constexpr int CW = (kCombos + 63) / 64;
+    for (int f = f0 + (tid >> 6); f < f1; f += kWaves) {
         const int x = flops[4 * f], y = flops[4 * f + 1], z = flops[4 * f + 2];
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < CI; i++) {
-            const int a = ka[i], b = kb[i];
-            if (a < 0 || a == x || a == y || a == z || b == x || b == y || b == z) continue;
-            s0 += xc[0][tid + i * kBlock];
-            s1 += xc[1][tid + i * kBlock];
+        for (int i = 0; i < CW; i++) {
+            const int k = lane + i * 64;
+            if (k >= kCombos) break;
+            const int a = kc[k] >> 8, b = kc[k] & 0xff;
+            if (a == x || a == y || a == z || b == x || b == y || b == z) continue;
+            s0 += xc[0][k];
+            s1 += xc[1][k];
         }
-        block_sum2(s0, s1, xch);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o);
+            s1 += __shfl_xor(s1, o);
+        }
         const double i0 = s0 > 0.0 ? 1.0 / s0 : 0.0, i1 = s1 > 0.0 ? 1.0 / s1 : 0.0;
         uint16_t* xr = X + ((int64_t)li * n_flops + f) * ldx;
-        for (int it = tid; it < chunks; it += kBlock) {
+        for (int it = lane; it < chunks; it += 64) {
             const int col0 = it * 8;
             uint16_t v[8];
 #pragma unroll
@@ -1811,7 +1819,6 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_input(const DNode* __restr
                 u32x4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
                       (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
         }
-        __syncthreads();   // every thread has read xch before the next flop's sums overwrite it
     }
 }
 
@@ -1872,17 +1879,34 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_sums(const DNode* __restri
     }
     __syncthreads();
     const int f0 = grp * flops_per_group, f1 = min(n_flops, f0 + flops_per_group);
+    // the next flop's outputs are loaded while this flop's are used (the
+    // barriers below order LDS only, so those loads stay in flight)
+    float ny0[CI], ny1[CI];
+    auto load_row = [&](int f) {
+        const float* yr = Y + ((int64_t)li * n_flops + f) * ldy;
+#pragma unroll
+        for (int i = 0; i < CI; i++) {
+            const int k = tid + i * kBlock, kk = k < kCombos ? k : 0;
+            ny0[i] = yr[kk];
+            ny1[i] = yr[kCombos + kk];
+        }
+    };
+    if (f0 < f1) load_row(f0);
     for (int f = f0; f < f1; f++) {
         const int x = flops[4 * f], y = flops[4 * f + 1], z = flops[4 * f + 2];
-        const float* yr = Y + ((int64_t)li * n_flops + f) * ldy;
+        float cy0[CI], cy1[CI];
+#pragma unroll
+        for (int i = 0; i < CI; i++) { cy0[i] = ny0[i]; cy1[i] = ny1[i]; }
+        if (f + 1 < f1) load_row(f + 1);
         T m0[CI], m1[CI], y0[CI], y1[CI];
         T e = T(0), zz = T(0);
 #pragma unroll
         for (int i = 0; i < CI; i++) {
-            const int k = tid + i * kBlock, a = ka[i], b = kb[i];
+            const int a = ka[i], b = kb[i];
+            const int k = tid + i * kBlock;
             const bool live = a >= 0 && a != x && a != y && a != z && b != x && b != y && b != z;
-            y0[i] = live ? (T)yr[k] : T(0);
-            y1[i] = live ? (T)yr[kCombos + k] : T(0);
+            y0[i] = live ? (T)cy0[i] : T(0);
+            y1[i] = live ? (T)cy1[i] : T(0);
             m1[i] = live ? flop_mass(rs[1], cs[1], t1, a, b, x, y, z) : T(0);
             m0[i] = live ? flop_mass(rs[0], cs[0], t0, a, b, x, y, z) : T(0);
             if (live) {
@@ -1892,9 +1916,21 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_sums(const DNode* __restri
         }
         T d = T(0);
         if (zero_sum) {
-            block_sum2(e, zz, xch);
+            // workgroup sums of e and z, the same order as block_sum2, with
+            // barriers that wait for LDS traffic only
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                e += __shfl_xor(e, o);
+                zz += __shfl_xor(zz, o);
+            }
+            if ((tid & 63) == 0) { xch[tid >> 6] = e; xch[kWaves + (tid >> 6)] = zz; }
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            e = T(0);
+            zz = T(0);
+#pragma unroll
+            for (int w = 0; w < kWaves; w++) { e += xch[w]; zz += xch[kWaves + w]; }
             d = zz > T(0) ? e / (T(2) * zz) : T(0);
-            __syncthreads();   // xch is rewritten by the next flop
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");   // xch is rewritten by the next flop
         }
         const T w = (T)orbit[f];
 #pragma unroll
@@ -1925,22 +1961,40 @@ __global__ __launch_bounds__(kBlock) void k_flop_leaf_sums(const DNode* __restri
 
 // Second pass: v_i(h) = pot / C(48,3) / |h| x the sum over the groups, in
 // group order; zero on padding hands.
+// One workgroup per (leaf, 64 value entries); its 4 waves take every 4th
+// group, eight loads in flight per step, and add their sums in wave order.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flop_leaf_values(const int32_t* __restrict__ leaves,
                                                              const double* __restrict__ pot_over_k,
                                                              const DNode* __restrict__ nodes,
                                                              const int32_t* __restrict__ hoff, int n_groups, int Hp,
                                                              int H, const T* __restrict__ part, T* __restrict__ cfv) {
-    const int li = blockIdx.x;
+    static_assert(kWaves == 4, "the wave sums are added as four terms");
+    __shared__ T red[kWaves][64];
+    const int li = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = blockIdx.y * 64 + lane;           // entry (player, hand) of 2 * Hp
     const int64_t n = leaves[li];
     const DNode nd = nodes[n];
-    const int32_t* ho = hoff + (int64_t)nd.sub * (Hp + 1);
-    T* v = cfv + n * 2 * Hp;
-    for (int q = threadIdx.x; q < 2 * Hp; q += blockDim.x) {
+    const T* pp = part + (int64_t)li * n_groups * 2 * Hp + q;
+    T acc = T(0);
+    if (q < 2 * Hp) {
+        int g = wv;
+        for (; g + 7 * kWaves < n_groups; g += 8 * kWaves) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = pp[(int64_t)(g + u * kWaves) * 2 * Hp];
+#pragma unroll
+            for (int u = 0; u < 8; u++) acc += v[u];
+        }
+        for (; g < n_groups; g += kWaves) acc += pp[(int64_t)g * 2 * Hp];
+    }
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && q < 2 * Hp) {
+        const T tot = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
         const int h = q < Hp ? q : q - Hp;
-        T acc = T(0);
-        for (int g = 0; g < n_groups; g++) acc += part[((int64_t)li * n_groups + g) * 2 * Hp + q];
-        v[q] = h < H ? (T)(pot_over_k[li] / (double)(ho[h + 1] - ho[h])) * acc : T(0);
+        const int32_t* ho = hoff + (int64_t)nd.sub * (Hp + 1);
+        cfv[n * 2 * Hp + q] = h < H ? (T)(pot_over_k[li] / (double)(ho[h + 1] - ho[h])) * tot : T(0);
     }
 }
 
@@ -2847,8 +2901,8 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         const int64_t rows = L.n_net * L.n_next, Mp = (rows + 63) / 64 * 64;
         const int ldx = (int)net->P.pdims[0], ldy = (int)net->P.pdims[net->P.L];
         const float* Y = reinterpret_cast<const float*>(net->ws + net->P.off_y);
-        // about 1024 workgroups for the rows
-        const int fpg = (int)std::max<int64_t>(1, (rows + 1023) / 1024);
+        // 16 flops per workgroup of the input kernel (4 per wave)
+        const int fpg = 16;
         const int n_grp = (int)((L.n_next + fpg - 1) / fpg);
         if (tm) tm->before(4);
         hipLaunchKernelGGL((k_flop_leaf_input<T>), dim3((unsigned)L.n_net, (unsigned)n_grp), dim3(kBlock), 0, stream,
@@ -2864,7 +2918,8 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
                            s->at<int8_t>(L.off_flops), s->at<int32_t>(L.off_orbit), s->at<int32_t>(L.off_hoff),
                            s->at<int16_t>(L.off_hlist), Hp, (int)L.H_leaf, Y, ldy, s->at<T>(L.off_rc),
                            s->at<T>(L.off_agg), s->leaf_zero_sum ? 1 : 0, s->at<T>(L.off_fpart));
-        hipLaunchKernelGGL((k_flop_leaf_values<T>), dim3((unsigned)L.n_net), dim3(kBlock), 0, stream,
+        hipLaunchKernelGGL((k_flop_leaf_values<T>), dim3((unsigned)L.n_net, (unsigned)((2 * Hp + 63) / 64)), dim3(kBlock),
+                           0, stream,
                            s->at<int32_t>(L.off_net), s->at<double>(L.off_potk), nodes, s->at<int32_t>(L.off_hoff),
                            (int)L.n_fgrp, Hp, (int)L.H_leaf, s->at<T>(L.off_fpart), cfv);
         if (tm) tm->after();
