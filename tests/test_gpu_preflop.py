@@ -107,3 +107,52 @@ def test_preflop_strategies_repeat_over_each_class():
         m = cls == c
         assert np.ptp(st[:, m], axis=1).max() == 0.0
         assert np.ptp(v[:, m], axis=1).max() == 0.0
+
+
+@pytest.mark.parametrize("alternating", [0, 1])
+def test_preflop_batch_members_are_their_own_solves(alternating):
+    """Preflop roots batch like other depth-limited subgames: every member's
+    (leaf, canonical flop) rows go through one set of GEMMs, and on fixed
+    tiles each member comes out bitwise as its own solve (simultaneous and
+    alternating updates); a batch mixing a preflop root with a board is
+    refused."""
+    cases = [I.preflop_config(s, sizes=(100,), max_raises=1 + s % 2) for s in (4, 5, 6)]
+    trees = [P.Tree(**sp) for sp, _ in cases]
+    ranges = np.stack([r for _, r in cases])
+    cfg = P.SolverConfig(dtype="f64", alternating=alternating)
+    b = P.Batch(trees, ranges, cfg)
+    n_leaves, n_next = b.leaf_rows()
+    assert n_next == 1755 and n_leaves == sum(t.n_leaf for t in trees)
+    rng = np.random.default_rng(21)
+    params = None
+
+    def make_net(rows):
+        nonlocal params
+        net = P.LeafNet(P.LEAF_D_IN, 64, 2, P.LEAF_D_OUT, max_batch=rows)
+        if params is None:
+            params = rand_params(rng, net.layer_shapes(), scale=2.0)
+        net.set_params(params)
+        net.tiles = [0] * len(params)
+        return net
+
+    netb = make_net(n_leaves * n_next)
+    b.attach_leafnet(netb)
+    say(f"case: preflop batch of 3, {n_leaves} leaves x {n_next} flops, alternating={alternating}")
+    T = 4
+    b.iterate(T)
+    for g in range(3):
+        s = P.Solver(trees[g], ranges[g], cfg)
+        nl, nn = s.leaf_rows()
+        net = make_net(nl * nn)
+        s.attach_leafnet(net)
+        s.iterate(T)
+        np.testing.assert_array_equal(b.root_cfv_of(g, "current"), s.root_cfv("current"))
+        np.testing.assert_array_equal(b.strategy_of(g, 0, "avg"), s.strategy(0, "avg"))
+        s.close()
+        net.close()
+    eb = b.exploitability_all()[0]
+    assert np.all(np.isfinite(eb))
+    flop_spec, flop_r = I.flop_config(0)
+    with pytest.raises(P.PcfrError) as e:
+        P.Batch([trees[0], P.Tree(**flop_spec)], np.stack([ranges[0], flop_r]))
+    assert e.value.code == P.E_UNSUPPORTED
