@@ -66,6 +66,9 @@ MEASURED_TRAFFIC = {
     # k_backward<float,0,*> + k_backward_fused over one iteration of the
     # seed-0 turn subgame (all backward launches)
     "turn_backward_iteration": 2442259200,
+    # k_backward<float,0,*> + k_backward_fused over the last (tuned) iteration
+    # of the seed-0 256-subgame forest
+    "batch_backward_iteration": 4030041920,
 }
 CLASSES = ["bookkeeping", "forward", "terminal", "backward", "leaves", "leaf_gemm_hidden", "leaf_gemm_out"]
 
@@ -85,6 +88,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip training a leaf network and the exact flop solve")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="batch workload: skip timing the subgames one at a time")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="batch workload: skip timing the persistent cooperative launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-mb", type=int, default=0,
                     help="first run a plain elementwise kernel over this many MiB (reads it once, writes it "
@@ -368,11 +373,14 @@ def batch_sweep(args, seed, steps, warmup, individual=True):
     # the same forest with every iteration of the timed window in one
     # persistent cooperative launch (grid barriers between the phases);
     # identical iterates, so the same exploitability
-    pb = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=args.dtype))
-    pb.set_launch(True)
-    ms_persist = timed(pb, steps, warmup)
-    pb.close()
-    log(f"batch: graph {ms:.4f} ms/iter, persistent launch {ms_persist:.4f} ms/iter")
+    ms_persist = None
+    if not args.no_persistent:
+        pb = P.Batch(trees, np.stack([r for _, r in cases]), P.SolverConfig(dtype=args.dtype))
+        pb.set_launch(True)
+        ms_persist = timed(pb, steps, warmup)
+        pb.close()
+    log(f"batch: graph {ms:.4f} ms/iter, persistent launch {ms_persist} ms/iter")
+    traffic = MEASURED_TRAFFIC["batch_backward_iteration"] if seed == 0 and args.dtype == "f32" else None
     out = {
         "workload": f"256 river/turn subgames in one forest, seed {seed}",
         "subgames": len(trees), "river": n_river, "turn": len(trees) - n_river,
@@ -388,7 +396,11 @@ def batch_sweep(args, seed, steps, warmup, individual=True):
         "exploitability_mbb_per_hand_mean": float(np.mean(expl)) * 100.0,
         "roofline": {
             "kernel": "k_backward<float,0> over the forest", "bound": "hbm", "achieved": achieved,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_note": "HBM bytes per iteration over the backward launches of one tuned iteration (hardware "
+                            "counters)",
+            "counter_gbs": None if traffic is None else traffic / (pms[3] * 1e-3) / 1e9,
+            "counter_frac": None if traffic is None else traffic / (pms[3] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "avg_launch_us": 1e3 * pms[3] / max(pl[3], 1), "launches_per_iter": int(pl[3]),
             "alg_bytes_per_iter": alg_bytes,
         },
