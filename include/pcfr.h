@@ -483,8 +483,8 @@ int32_t pcfr_solver_attach_leafnet(pcfr_solver* s, pcfr_leafnet* net);
  * solved values do.  The paper does not say how leaf values are kept
  * consistent; this is a reading.  Re-captures the iteration graph. */
 int32_t pcfr_solver_set_leaf_zero_sum(pcfr_solver* s, int32_t on);
-/* Training samples for the leaf network from a solved batch (the survey of
- * the paper's depth-limited method: the network is trained on subgames the
+/* Training samples for the leaf network from a solved batch (the paper's
+ * depth-limited method, Sec. 3: the network is trained on subgames the
  * solver itself solves).  Row g of x (device fp32 [n][ldx], ldx >= 2705):
  * subgame g's root ranges normalised to sum 1 over the 1326 combos, its board
  * one-hot, its stack-to-pot ratio.  Row g of y and mask (device fp32

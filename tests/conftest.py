@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped, not failed, where no GPU is visible (this lets the
-    # CPU suite run everywhere); on a GPU machine they run and must pass.
+    # CPU suite run everywhere); on a machine with the GPU they run and must pass.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
