@@ -849,7 +849,13 @@ __device__ void term_fold(const DNode& nd, int64_t n, int Hp, const T* __restric
 // L = of compatible stronger ones; ties pay nothing.  The board's table
 // lists only hands alive on it, so no dealt-card masking is needed.  As for
 // folds, a hand none of whose compatible opponent hands has nonzero reach
-// (counted by the same inclusion-exclusion) gets exactly 0.
+// (counted by the same inclusion-exclusion) gets exactly 0; and W or L is
+// exactly 0 when no compatible weaker (stronger) hand has nonzero reach, so
+// a hand whose reaching opponents all tie with it is worth exactly 0 (the
+// differences of prefixes would leave rounding residues whose signs regret
+// matching then follows).  Those counts come from bitmasks of the nonzero
+// reaches, in sorted order and in card-list order, with per-word prefix
+// counts; they are taken only where W and L are both within rounding of 0.
 // Core of the showdown terminal: ra[i], rb[i] are the two players' reach of
 // hand tid + i * kBlock in hand order (read by the caller); v0 / v1 receive
 // the node's values.
@@ -866,6 +872,14 @@ __device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T 
     int16_t* clist = coff + kSdHeader;                                // [QN]
     int16_t* perm = clist + QN;                                       // [Hp]
     int32_t* cnz = reinterpret_cast<int32_t*>(perm + Hp);             // [2][52]: hands with reach per card
+    // nonzero-reach bitmasks: card-list order [2][NW], sorted order [2][NS],
+    // and their exclusive per-word prefix counts ([2][NW], [2][NS + 1]); the
+    // byte offset of lw is a multiple of 8 since Hp is a multiple of 64
+    const int NW = (QN + 63) >> 6, NS = Hp >> 6;
+    uint64_t* lw = reinterpret_cast<uint64_t*>(cnz + 104);
+    uint64_t* sw = lw + 2 * NW;
+    int32_t* lpre = reinterpret_cast<int32_t*>(sw + 2 * NS);
+    int32_t* spre = lpre + 2 * NW;
     const int16_t* glo = tb + Hp;
     const int16_t* ghi = tb + 2 * Hp;
     const int16_t* alo = tb + 3 * Hp;
@@ -908,10 +922,16 @@ __device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T 
         hh[i] = s < Hp ? perm[s] : 0;
         if (s < Hb) { a[i] = q0[hh[i]]; b[i] = q1[hh[i]]; }
     }
+    const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int s = tid + i * kBlock;
         if (s < Hb) { xs0[s] = a[i]; xs1[s] = b[i]; }
+        // the wave's 64 positions form one word of the sorted bitmasks
+        const uint64_t m0 = __ballot(s < Hb && a[i] != T(0));
+        const uint64_t m1 = __ballot(s < Hb && b[i] != T(0));
+        const int wd = (i * kBlock >> 6) + wv;
+        if (lane == 0 && wd < NS) { sw[wd] = m0; sw[NS + wd] = m1; }
     }
     __syncthreads();
     if (tid < 104) {
@@ -942,6 +962,37 @@ __device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T 
         q[hi] = acc;
         cnz[tid] = nz;
     }
+    if (wv >= 2) {
+        // meanwhile the last two waves build the card-list bitmasks, one
+        // 64-entry word per ballot (a list's total slot holds -1: no bit),
+        // ten words per step with their loads issued together
+        constexpr int kMaxNW = (2 * kMaxHp + kSdHeader + 63) / 64;
+        constexpr int kStep = 10;
+        const int nl = coff[52];
+#pragma unroll
+        for (int k0 = 0; k0 < (kMaxNW + 1) / 2; k0 += kStep) {
+            int ix[kStep];
+            T y0[kStep], y1[kStep];
+#pragma unroll
+            for (int u = 0; u < kStep; u++) {
+                const int j = ((wv - 2) + 2 * (k0 + u)) * 64 + lane;
+                ix[u] = j < nl ? clist[j] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kStep; u++) {
+                const int x = ix[u] < 0 ? 0 : ix[u];
+                y0[u] = xs0[x];
+                y1[u] = xs1[x];
+            }
+#pragma unroll
+            for (int u = 0; u < kStep; u++) {
+                const int wd = (wv - 2) + 2 * (k0 + u);
+                const uint64_t m0 = __ballot(ix[u] >= 0 && y0[u] != T(0));
+                const uint64_t m1 = __ballot(ix[u] >= 0 && y1[u] != T(0));
+                if (lane == 0 && wd < NW) { lw[wd] = m0; lw[NW + wd] = m1; }
+            }
+        }
+    }
     // exclusive scan of xs0 / xs1 over [0, Hb) in sorted order: each thread
     // owns a contiguous chunk, chunk sums are scanned across the workgroup
     constexpr int kMaxChunk = (kMaxHp + kBlock - 1) / kBlock;
@@ -963,6 +1014,25 @@ __device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T 
     T tot0, tot1;
     block_exscan2<T, true>(s0, s1, tot0, tot1, xch, &n0, &n1);   // synchronises: every chunk was read above
     const int nz0 = (int)n0, nz1 = (int)n1;
+    {
+        // exclusive per-word prefix counts of the four bitmasks, one wave each
+        // (the bitmasks are complete: the scan above synchronised)
+        static_assert(kWaves >= 4, "one wave per bitmask");
+        if (wv < 4) {
+            const int n = wv < 2 ? NW : NS;
+            const uint64_t* src = wv < 2 ? lw + wv * NW : sw + (wv - 2) * NS;
+            int32_t* dst = wv < 2 ? lpre + wv * NW : spre + (wv - 2) * (NS + 1);
+            const int c = lane < n ? __popcll(src[lane]) : 0;
+            int inc = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(inc, o);
+                if (lane >= o) inc += u;
+            }
+            if (lane < n) dst[lane] = inc - c;
+            if (wv >= 2 && lane == n - 1) dst[n] = inc;
+        }
+    }
     __syncthreads();                          // all reads of xs done before it is overwritten
 #pragma unroll
     for (int i = 0; i < kMaxChunk; i++) {
@@ -978,6 +1048,25 @@ __device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T 
     __syncthreads();
 
     const T pay = (T)nd.pay;
+    // hands with nonzero reach of player p among sorted positions [0, x) and
+    // among card-list positions [0, x)
+    auto cnt_sorted = [&](int p, int x) {
+        const int k = x >> 6, r = x & 63;
+        int c = spre[p * (NS + 1) + k];
+        if (r) c += __popcll(sw[p * NS + k] & ((1ull << r) - 1));
+        return c;
+    };
+    auto cnt_list = [&](int p, int x) {
+        const int k = x >> 6, r = x & 63;
+        int c = lpre[p * NW + k];
+        if (r) c += __popcll(lw[p * NW + k] & ((1ull << r) - 1));
+        return c;
+    };
+    // a bound on the rounding error of W and L (sums of at most Hb terms,
+    // each prefix at most the player's total reach, five prefixes and four
+    // differences): beyond it the exact value is certainly nonzero
+    constexpr T kEps = sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-07);
+    const T e0 = T(8 * (Hb + 1)) * kEps * tot0, e1 = T(8 * (Hb + 1)) * kEps * tot1;
 #pragma unroll
     for (int i = 0; i < kHandIt; i++) {
         const int s = tid + i * kBlock;
@@ -988,12 +1077,25 @@ __device__ void term_showdown_core(const DNode& nd, int Hp, T (&ra)[kHandIt], T 
         const int ae = coff[ca + 1] - 1, be = coff[cb + 1] - 1;
         const int gl = s_gl[i], gh = s_gh[i], al = s_al[i], ah = s_ah[i], bl = s_bl[i], bh = s_bh[i];
         // against player 1's reach (value of player 0)
-        const T w1 = xs1[gl] - q1[al] - q1[bl];
-        const T lo1 = (tot1 - xs1[gh]) - (q1[ae] - q1[ah]) - (q1[be] - q1[bh]);
-        const T w0 = xs0[gl] - q0[al] - q0[bl];
-        const T lo0 = (tot0 - xs0[gh]) - (q0[ae] - q0[ah]) - (q0[be] - q0[bh]);
+        T w1 = xs1[gl] - q1[al] - q1[bl];
+        T lo1 = (tot1 - xs1[gh]) - (q1[ae] - q1[ah]) - (q1[be] - q1[bh]);
+        T w0 = xs0[gl] - q0[al] - q0[bl];
+        T lo0 = (tot0 - xs0[gh]) - (q0[ae] - q0[ah]) - (q0[be] - q0[bh]);
         const bool any1 = nz1 - cnz[52 + ca] - cnz[52 + cb] + (b[i] != T(0)) > 0;
         const bool any0 = nz0 - cnz[ca] - cnz[cb] + (a[i] != T(0)) > 0;
+        const int la = coff[ca], lb = coff[cb];
+        if (any1 && fabs(w1) <= e1 && fabs(lo1) <= e1) {
+            if (cnt_sorted(1, gl) - (cnt_list(1, al) - cnt_list(1, la)) - (cnt_list(1, bl) - cnt_list(1, lb)) == 0)
+                w1 = T(0);
+            if ((nz1 - cnt_sorted(1, gh)) - (cnt_list(1, ae) - cnt_list(1, ah)) - (cnt_list(1, be) - cnt_list(1, bh)) == 0)
+                lo1 = T(0);
+        }
+        if (any0 && fabs(w0) <= e0 && fabs(lo0) <= e0) {
+            if (cnt_sorted(0, gl) - (cnt_list(0, al) - cnt_list(0, la)) - (cnt_list(0, bl) - cnt_list(0, lb)) == 0)
+                w0 = T(0);
+            if ((nz0 - cnt_sorted(0, gh)) - (cnt_list(0, ae) - cnt_list(0, ah)) - (cnt_list(0, be) - cnt_list(0, bh)) == 0)
+                lo0 = T(0);
+        }
         v0[h] = any1 ? pay * (w1 - lo1) : T(0);
         v1[h] = any0 ? pay * (w0 - lo0) : T(0);
     }
@@ -2683,8 +2785,10 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.off_tfterm = take(sizeof(int32_t) * std::max<size_t>(P.term.size(), 1));
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
+    const size_t sd_nw = (qn + 63) / 64, sd_ns = L.Hp / 64;   // nonzero-reach bitmask words
     const size_t sd_lds = L.esz * (2 * (L.Hp + 4) + 2 * qn + 2 * kBlock) + sizeof(int16_t) * (kSdHeader + qn + L.Hp) +
-                          sizeof(int32_t) * 104;
+                          sizeof(int32_t) * 104 + sizeof(uint64_t) * 2 * (sd_nw + sd_ns) +
+                          sizeof(int32_t) * 2 * (sd_nw + sd_ns + 1);
     const size_t fold_lds = L.esz * (2 * L.Hp + 208 + 2 * kBlock) + sizeof(int16_t) * 2 * L.Hp + sizeof(int32_t) * 208;
     L.lds_fold = fold_lds;
     L.lds_show = sd_lds;

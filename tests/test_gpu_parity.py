@@ -172,6 +172,56 @@ def test_river_single_hands_and_no_bets():
     compare(spec, r, 30, "f64")
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_showdown_against_only_ties_is_exactly_zero(dtype):
+    """A showdown hand whose compatible opponent hands with reach all tie with
+    it is worth exactly 0 (a sum of zero payoffs), while incompatible
+    opponent hands holding one of its cards carry random reach on both
+    sides of it in strength order: the prefix differences that remove them
+    must not leave a rounding residue.  Check-down river, one iteration;
+    every other hand's value against the oracle."""
+    rng = np.random.default_rng(11)
+    board = I.draw_board(rng, 5)
+    spec = dict(board=board, pot=20, stacks=(0, 0), sizes=[], allin=False, max_raises=0, depth_limit=0)
+    ot = O.Tree.holdem(**spec)
+    showdown = int(np.flatnonzero(ot.export()["type"] == O.T_SHOW)[0])
+    E = ot.equity_table(showdown)
+    cc = I.combo_cards()
+    ok = np.flatnonzero(~I.blocked_mask(board))
+    held = np.zeros((1326, 52), dtype=bool)
+    held[np.arange(1326)[:, None], cc] = True
+    n_cases = 0
+    for x in rng.permutation(ok):
+        compatible = ~held[ok][:, cc[x]].any(axis=1)
+        ties = ok[compatible & (E[x, ok] == 0) & (ok != x)]
+        if len(ties) == 0:
+            continue
+        blockers = ok[~compatible & (ok != x)]
+        r = np.zeros((2, 1326))
+        r[0, ties] = rng.uniform(0.1, 1.0, len(ties))
+        r[0, blockers] = rng.uniform(0.1, 1.0, len(blockers))
+        r[1, x] = 1.0
+        r[1, rng.choice(ok, 20, replace=False)] = rng.uniform(0.1, 1.0, 20)
+        say(f"case: showdown against ties only, {dtype}, board {board}, hand {x} ({len(ties)} ties, "
+            f"{len(blockers)} blocking hands with reach)")
+        os_ = O.Solver(ot, r)
+        os_.iterate(1)
+        gs = P.Solver(P.Tree(**spec), r, P.SolverConfig(dtype=dtype))
+        gs.iterate(1)
+        for which in ("current", "avg"):
+            vg = gs.root_cfv(which)
+            vo = os_.root_cfv(which)
+            assert vo[1, x] == 0.0
+            assert vg[1, x] == 0.0, (which, vg[1, x])
+            d = np.abs(vg - vo)[:, ok].max() / spec["pot"]
+            say(f"  {which}: value of the hand {vg[1, x]!r}, others max |d| = {d:.3e} pot")
+            assert d <= (1e-9 if dtype == "f64" else 1e-4)
+        n_cases += 1
+        if n_cases == 6:
+            break
+    assert n_cases == 6
+
+
 # ---------------------------------------------------------------- turn
 @pytest.mark.parametrize("seed,spr,support", [(1, 1, 64), (2, 2, 48)])
 def test_turn_sparse_support(seed, spr, support):

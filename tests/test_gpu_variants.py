@@ -96,33 +96,38 @@ def test_alternating_flop_network_leaves_runs_and_resumes():
 @pytest.mark.parametrize("variant", ["dcfr", "pcfr+"])
 @pytest.mark.parametrize("seed,support,spr", [(5, 40, 1.5), (7, 60, 1.0)])
 def test_alternating_turn_matches_oracle(variant, seed, support, spr):
-    """Alternating updates on turn trees (chance nodes).
+    """Alternating updates on turn trees (chance nodes), per iterate.
 
-    Per-iterate FP64 parity with the oracle after 1 and 3 iterations: 1e-9
-    pot on root values (last iterate and average strategies), exploitability
-    and both best responses.  Player 1's half-step meets the exact zeros of
-    player 0's new strategy at once, so many of player 1's hands face no
-    opponent hand with reach, or actions whose values tie exactly; both
-    implementations now value the first exactly 0 and treat regrets within
-    1e-10 of the actions' values as ties, which keeps the early iterates
-    equal to rounding.
+    FP64 parity with the oracle after 1, 3, 10 and 40 iterations: 1e-9 pot
+    on root values (last iterate and average strategies), exploitability
+    and both best responses; every average and current strategy entry of
+    the hands in the acting player's support at every decision node within
+    1e-9 through 10 iterations and 1e-7 at 40.  The strategies' bound widens
+    with T because regret matching near ties amplifies rounding: a change
+    of one ulp in the oracle's own input ranges moves its strategies by
+    1e-13 after 3 iterations and by up to 6e-10 after 40 (measured on these
+    four cases), and the GPU's sums, taken in another order, differ from
+    the oracle's by rounding in every operation (measured: 1e-11 after 3
+    iterations, 4e-11 after 10, 1.5e-8 after 40; root values 2e-12 pot).
 
-    After 40 iterations the iterates may have parted where a value that is
-    zero in exact arithmetic (a cancellation in the inclusion-exclusion sums,
-    a probability that is exactly zero on one side and a residue on the
-    other) decided a regret's sign; both runs are then valid CFR runs that
-    broke a tie differently.  There the check is what both must reach: the
-    exploitability within 1% of the oracle's and the root values under the
-    average strategies within 1e-3 pot (measured: 5e-5 to 1.2e-3 pot on the
-    last iterate, 1e-12 on one of the four cases)."""
+    Player 1's half-step meets the exact zeros of player 0's new strategy at
+    once: many of player 1's hands face opponents that all tie with them at
+    a showdown, or no opponent hand with reach, so their actions' values tie
+    exactly.  The oracle's sums over histories give exact zeros there; the
+    GPU's prefix differences must too (counts of nonzero-reach hands decide
+    when a win or loss sum is empty), or regret matching follows the signs
+    of rounding residues and the runs part."""
     spec, r = I.turn_config(seed, support=support, spr=spr)
     say(f"case: alternating {variant} turn {spec} support {support}")
     ot = O.Tree.holdem(**spec)
     os_ = O.Solver(ot, r, support_only=True, variant=variant, alternating=True)
-    gs = P.Solver(P.Tree(**spec), r, P.SolverConfig(dtype="f64", variant=variant, alternating=1))
+    gt = P.Tree(**spec)
+    gs = P.Solver(gt, r, P.SolverConfig(dtype="f64", variant=variant, alternating=1))
     pot = spec["pot"]
     mask = (r > 0) & ~I.blocked_mask(spec["board"])[None, :]
-    for T in (1, 3):
+    e = gt.export()
+    dec = [int(n) for n in np.flatnonzero(e["type"] == P.NODE_DECISION)]
+    for T in (1, 3, 10, 40):
         os_.iterate(T - os_.t)
         gs.iterate(T - gs.t)
         for which in ("current", "avg"):
@@ -131,15 +136,13 @@ def test_alternating_turn_matches_oracle(variant, seed, support, spr):
             assert d <= 1e-9
         eg, bg = gs.exploitability()
         eo, bo = os_.exploitability()
-        say(f"  T={T} exploitability gpu {eg:.9f} oracle {eo:.9f}")
+        say(f"  T={T} exploitability gpu {eg:.12f} oracle {eo:.12f}")
         assert abs(eg - eo) / pot <= 1e-9
         np.testing.assert_allclose(bg / pot, bo / pot, atol=1e-9)
-    os_.iterate(40 - os_.t)
-    gs.iterate(40 - gs.t)
-    dc = np.abs(gs.root_cfv("current") - os_.root_cfv("current"))[mask].max() / pot
-    da = np.abs(gs.root_cfv("avg") - os_.root_cfv("avg"))[mask].max() / pot
-    eg, _ = gs.exploitability()
-    eo, _ = os_.exploitability()
-    say(f"  T=40 root cfv (current) {dc:.3e}, (avg) {da:.3e} pot; exploitability gpu {eg:.9f} oracle {eo:.9f}")
-    assert da <= 1e-3
-    assert abs(eg - eo) <= 0.01 * eo
+        worst = 0.0
+        for n in dec:
+            own = mask[int(e["player"][n])]
+            for w in ("avg", "current"):
+                worst = max(worst, float(np.abs(gs.strategy(n, w) - os_.strategy(n, w))[:, own].max()))
+        say(f"  T={T} strategies (average and current) max |d| = {worst:.3e}")
+        assert worst <= (1e-9 if T <= 10 else 1e-7)
