@@ -1116,7 +1116,10 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
     term_showdown_core<T>(nd, Hp, ra, rb, tb, Hb, lds, v0, v0 + Hp);
 }
 
-template <typename T>
+// One workgroup per terminal node of one kind (KIND 0: folds, 1: showdowns):
+// a kernel per kind, so that the lighter fold path is not held to the
+// registers of the showdown path.
+template <typename T, int KIND>
 __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                      int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                                                      const uint16_t* __restrict__ hcards, const int32_t* __restrict__ coff,
@@ -1135,7 +1138,7 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
         return;
     }
     const uint16_t* hc = hcards + (int64_t)nd.sub * Hp;
-    if (nd.type == PCFR_NODE_FOLD)
+    if constexpr (KIND == 0)
         term_fold<T>(nd, n, Hp, reach, cfv, hc, coff + nd.sub * 53, chands + (int64_t)nd.sub * chand_stride, lds);
     else
         term_showdown<T>(nd, n, Hp, reach, cfv, hc, sd + (int64_t)nd.aux * sd_stride, sd_n[nd.aux], lds);
@@ -2965,11 +2968,16 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         const int64_t cnt = kind ? n_show : n_fold;
         if (!cnt) continue;
         if (tm) tm->before(2);
-        hipLaunchKernelGGL((k_terminal<T>), dim3((unsigned)cnt), dim3(kBlock), kind ? L.lds_show : L.lds_fold, side,
-                           nodes, tlist + (kind ? n_fold : 0), Hp, reach, cfv,
-                           s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff), s->at<int16_t>(L.off_chands),
-                           (int)L.chand_stride, s->at<int16_t>(L.off_sd), (int64_t)L.sd_stride,
-                           s->at<int32_t>(L.off_sdn), nzs);
+        if (kind)
+            hipLaunchKernelGGL((k_terminal<T, 1>), dim3((unsigned)cnt), dim3(kBlock), L.lds_show, side, nodes,
+                               tlist + n_fold, Hp, reach, cfv, s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff),
+                               s->at<int16_t>(L.off_chands), (int)L.chand_stride, s->at<int16_t>(L.off_sd),
+                               (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn), nzs);
+        else
+            hipLaunchKernelGGL((k_terminal<T, 0>), dim3((unsigned)cnt), dim3(kBlock), L.lds_fold, side, nodes, tlist,
+                               Hp, reach, cfv, s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff),
+                               s->at<int16_t>(L.off_chands), (int)L.chand_stride, s->at<int16_t>(L.off_sd),
+                               (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn), nzs);
         if (tm) tm->after();
     }
     // depth-limit leaves: exact equity for all-in leaves (and for every leaf
@@ -3376,12 +3384,14 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     if (L.lds_bytes > 160 * 1024) { set_error("hand count too large for the terminal kernel's LDS"); return PCFR_E_TOO_LARGE; }
     if (L.lds_bytes > 65536) {
         // gfx950 gives a workgroup up to 160 KB of LDS; dynamic sizes above 64 KB must be declared
-        hipError_t e = cfg->dtype == PCFR_F64
-                           ? hipFuncSetAttribute(reinterpret_cast<const void*>(&k_terminal<double>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes)
-                           : hipFuncSetAttribute(reinterpret_cast<const void*>(&k_terminal<float>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
-        if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+        const void* ks[2] = {cfg->dtype == PCFR_F64 ? reinterpret_cast<const void*>(&k_terminal<double, 0>)
+                                                    : reinterpret_cast<const void*>(&k_terminal<float, 0>),
+                             cfg->dtype == PCFR_F64 ? reinterpret_cast<const void*>(&k_terminal<double, 1>)
+                                                    : reinterpret_cast<const void*>(&k_terminal<float, 1>)};
+        for (const void* k : ks) {
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+            if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+        }
     }
     // ranges and the joint mass of compatible pairs: r0 . (total1 - per-card sums + r1)
     const ComboTable& cc = combos();
