@@ -222,6 +222,19 @@ def test_showdown_against_only_ties_is_exactly_zero(dtype):
     assert n_cases == 6
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_flop_to_showdown_sparse(dtype):
+    """A flop root played to showdown (31,124 nodes: 16,464 showdowns on river
+    boards, 248 chance nodes): the terminal kernels at the flop's hand count
+    (1,176 hands, the largest padded row), showdown tables of 1,081 live hands
+    and two chance levels.  Stacks of half the pot, one all-in per street."""
+    rng = np.random.default_rng(21)
+    board = I.draw_board(rng, 3)
+    r = np.stack([I.dirichlet_range(rng, board, 1.0, 40), I.dirichlet_range(rng, board, 1.0, 40)])
+    spec = dict(board=board, pot=20, stacks=(10, 10), sizes=[100], allin=True, max_raises=1, depth_limit=0)
+    compare(spec, r, 6, dtype, support_only=True, key="flop_showdown_sparse")
+
+
 # ---------------------------------------------------------------- turn
 @pytest.mark.parametrize("seed,spr,support", [(1, 1, 64), (2, 2, 48)])
 def test_turn_sparse_support(seed, spr, support):
