@@ -603,6 +603,12 @@ def learned_leaf_sweep(args, n_train=4096, gen_iters=200, train_steps=2000, iter
         done = k
         snaps[k] = ex.root_cfv("avg")
     e_ex, _ = ex.exploitability()
+    # one more iteration with per-launch timing: the sweep's kernel split and
+    # its algorithmic HBM fractions (R and S read and written once per
+    # action row and hand, as for the turn line)
+    esz = 8 if args.dtype == "f64" else 4
+    alg_ex = 4 * esz * tx.n_rows * tx.n_hands
+    pms_ex, _ = ex.profile(1)
     ex.close()
     del ex
     torch.cuda.empty_cache()
@@ -622,6 +628,10 @@ def learned_leaf_sweep(args, n_train=4096, gen_iters=200, train_steps=2000, iter
         "exact_nodes": tx.n_nodes, "exact_tree_build_s": build_s,
         "exact_ms_per_iter": ms_ex, "exact_iters_per_s": 1000.0 / ms_ex,
         "exact_exploitability_mbb_per_hand": e_ex * 100.0,
+        "exact_state_bytes_R_S": 2 * esz * tx.n_rows * tx.n_hands_padded,
+        "exact_kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms_ex)},
+        "exact_backward_alg_hbm_frac": alg_ex / (float(pms_ex[3]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "exact_iteration_alg_hbm_frac": alg_ex / (ms_ex * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "root_value_gap_mbb_per_hand": {"learned_leaves_vs_exact": g_dl, "checkdown_equity_leaves_vs_exact": g_stub},
         "exact_root_value_gap_by_iterations": curve,
         "exact_iterations_to_match": match,
@@ -630,6 +640,9 @@ def learned_leaf_sweep(args, n_train=4096, gen_iters=200, train_steps=2000, iter
     }
     log(f"learned leaf: {ms_dl:.4f} ms/iter, gap {g_dl:.1f} mbb/hand to exact ({ms_ex:.2f} ms/iter); exact needs "
         f"{match} iterations for that gap: {out['speedup_at_matched_quality']:.1f}x")
+    log(f"exact flop: {tx.n_nodes} nodes, {out['exact_state_bytes_R_S'] / 1e9:.1f} GB of R + S, backward "
+        f"{out['exact_backward_alg_hbm_frac']:.3f} and iteration {out['exact_iteration_alg_hbm_frac']:.3f} of HBM peak "
+        f"(algorithmic)")
     return out
 
 
