@@ -319,6 +319,24 @@ def test_checkpoint_resume_is_bitwise():
     assert a.save_state() == b.save_state()
 
 
+def test_zero_iterations_change_nothing_and_negative_counts_are_refused():
+    """iterate(0) is a no-op (iteration counter and state bitwise unchanged,
+    before and after the first iteration); a negative count is refused."""
+    spec, r = I.river_config(2, support=100)
+    say(f"case: zero and negative iteration counts, river {spec}")
+    s = P.Solver(P.Tree(**spec), r)
+    blob = s.save_state()
+    s.iterate(0)
+    assert s.t == 0 and s.save_state() == blob
+    s.iterate(3)
+    blob = s.save_state()
+    s.iterate(0)
+    assert s.t == 3 and s.save_state() == blob
+    with pytest.raises(P.PcfrError):
+        s.iterate(-1)
+    assert s.t == 3 and s.save_state() == blob
+
+
 def test_run_to_run_deterministic():
     spec, r = I.river_config(3)
     out = []

@@ -196,3 +196,20 @@ def test_batch_of_depth_limited_subgames_planned():
     rc, _ = _batch_workspace([flops[0], turn])
     assert rc == P.E_UNSUPPORTED
     assert "one size" in P.lib().pcfr_last_error().decode()
+
+
+def test_empty_batch_refused_before_any_device_call():
+    """A batch of no subgames has no plan: sizing and creation both return
+    PCFR_E_INVALID_ARG (checked before anything touches a device)."""
+    cfg = P.SolverConfig().to_c()
+    nb = ctypes.c_size_t(123)
+    arr = (ctypes.c_void_p * 1)(P.Tree(**SPECS[0])._h.value)
+    L = P.lib()
+    assert L.pcfr_batch_workspace_bytes(arr, 0, ctypes.byref(cfg), ctypes.byref(nb)) == 1
+    ranges = np.zeros(2 * 1326)
+    buf = ctypes.create_string_buffer(512)
+    ws = (ctypes.addressof(buf) + 255) // 256 * 256
+    out = ctypes.c_void_p()
+    rc = L.pcfr_batch_create(arr, 0, ctypes.byref(cfg), ranges.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(ws),
+                             ctypes.c_size_t(256), None, ctypes.byref(out))
+    assert rc == 1 and not out.value
