@@ -781,6 +781,45 @@ def preflop_sweep(args, steps, warmup):
     return out
 
 
+def flop_2000_rows(args, steps, warmup):
+    """A full iteration of a depth-limited flop with about 2,000 network rows:
+    three bet sizes (33, 66, 100% of the pot) and three raises give 43
+    network leaves x 49 turn cards = 2,107 rows (the headline's two sizes give
+    21 leaves, 1,029 rows, beside 14 all-in leaves valued by exact equity)."""
+    from paper_2605_19928_amd import inputs as I
+    from paper_2605_19928_amd import pcfr as P
+
+    spec, r = I.flop_config(args.seed, sizes=(33, 66, 100), max_raises=3)
+    tree = P.Tree(**spec)
+    s = P.Solver(tree, r, P.SolverConfig(dtype=args.dtype))
+    n_leaves, n_next = s.leaf_rows()
+    rows = n_leaves * n_next
+    net = P.LeafNet(P.LEAF_D_IN, 1536, 4, P.LEAF_D_OUT, max_batch=rows)
+    net.set_params(he_params(net.layer_shapes(), 7))
+    s.attach_leafnet(net)
+    before, after = s.autotune(3)
+    ms = timed(s, steps, warmup)
+    pms, pl = s.profile(args.profile_iters)
+    pms, pl = pms / args.profile_iters, pl // args.profile_iters
+    shapes = net.layer_shapes()
+    hidden_flops = 2.0 * rows * sum(o * i for o, i in shapes[:-1])
+    n_hidden = max(int(pl[5]), 1)
+    hidden_tflops = hidden_flops / (pms[5] * 1e-3) / 1e12
+    out = {
+        "workload": f"depth-limited flop, seed {args.seed}, bet sizes 33/66/100% + all-in, 3 raises",
+        "nodes": tree.n_nodes, "network_leaves": n_leaves, "allin_leaves": tree.n_allin, "network_rows": rows,
+        "ms_per_iter": ms, "iters_per_s": 1000.0 / ms, "autotune_ms_per_iter_before_after": [before, after],
+        "leaf_gemm_tiles": list(net.tiles), "kernel_ms_per_iter": {k: float(v) for k, v in zip(CLASSES, pms)},
+        "leaf_gemm_hidden_tflops": hidden_tflops, "leaf_gemm_hidden_frac": hidden_tflops / BF16_PEAK_TFLOPS,
+        "leaf_gemm_hidden_avg_launch_us": 1e3 * pms[5] / n_hidden,
+    }
+    s.close()
+    net.close()
+    log(f"flop with {rows} network rows: {ms:.4f} ms/iter, hidden GEMM {hidden_tflops:.0f} TFLOP/s "
+        f"({out['leaf_gemm_hidden_frac']:.3f} of peak)")
+    return out
+
+
 def gemm_shape_point(args, m=2048, reps=50):
     """The leaf network's forward at m rows (the second GEMM shape point),
     after the tile autotuner: us per forward and TFLOP/s."""
@@ -972,6 +1011,7 @@ def main():
         result["regret_based_pruning"] = rbp_sweep(args, tspec, tr, max(20, args.steps // 4), 5)
         result["turn_spr_sweep"] = spr_sweep(args, max(20, args.steps // 4), 5)
         result["leaf_gemm_m2048"] = gemm_shape_point(args)
+        result["flop_2000_rows"] = flop_2000_rows(args, max(20, args.steps // 4), 5)
         result["flop_batch"] = flop_batch_sweep(args, max(20, args.steps // 4), 5)
         result["preflop"] = preflop_sweep(args, max(20, args.steps // 4), 5)
         result["hbm_copy_ceiling_gbs"] = copy_ceiling_gbs()
