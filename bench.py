@@ -34,6 +34,11 @@ line): 8 and 32 depth-limited flops of the default abstraction, each with its
 own board and ranges, in one forest with one leaf network (1536 x 4), so
 every iteration sends all their (leaf, next card) rows through the same GEMMs.
 
+Training data (``--workload datagen`` only): random turn subgames of the leaf
+network's training recipe solved by the batched plain solver to 1000
+iterations each (a sample of ``--datagen-subgames``), with the rate and the
+time the recipe's 100k subgames would take.
+
 Prints one JSON line.  ``--gpus`` above 1 is refused: the solver runs on one
 GPU.
 """
@@ -79,7 +84,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="flop", choices=["flop", "turn", "batch", "flop-batch", "preflop"])
+    ap.add_argument("--workload", default="flop", choices=["flop", "turn", "batch", "flop-batch", "preflop", "datagen"])
+    ap.add_argument("--datagen-subgames", type=int, default=1024,
+                    help="--workload datagen: random turn subgames solved (a sample of the 100k of the recipe)")
+    ap.add_argument("--datagen-iters", type=int, default=1000, help="--workload datagen: solver iterations each")
     ap.add_argument("--batch-flops", type=int, default=32, help="flops per forest for --workload flop-batch")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--profile-iters", type=int, default=5)
@@ -882,6 +890,37 @@ def main():
             "config": {k: v for k, v in out.items() if k != "kernel_ms_per_iter"},
             "kernel_ms_per_iter": out["kernel_ms_per_iter"],
         }
+        print(json.dumps(result), flush=True)
+        return
+
+    if args.workload == "datagen":
+        # training data for the leaf network at the recipe's solve depth: random
+        # turn subgames solved by the batched plain solver, root targets sampled
+        from paper_2605_19928_amd import train as T
+
+        n, iters, batch = args.datagen_subgames, args.datagen_iters, 512
+        t0 = time.perf_counter()
+        X, Y, M, specs = T.generate(seed=args.seed + 1000, n=n, iters=iters, batch=batch, dtype=args.dtype, log=log)
+        import torch
+
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        nodes = [P.Tree(**s).n_nodes for s, _ in specs[:256]]
+        rate = n / wall
+        result = {
+            "metric": "leaf-network training data: turn subgames solved per second",
+            "value": rate, "unit": "subgames/s", "n_gpus": 1, "steps": iters, "warmup": 0,
+            "ms_per_step": 1e3 * wall / iters, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": args.dtype, "data": "synthetic",
+            "config": {"workload": f"{n} random turn subgames (Dirichlet(0.5-2) ranges, log-uniform pot and SPR "
+                                   f"0.1-8, 75% + all-in, 2 raises) x {iters} DCFR iterations, batches of {batch}",
+                       "subgames": n, "iterations": iters, "batch": batch,
+                       "nodes_per_subgame_median": float(np.median(nodes)),
+                       "wall_s": wall, "subgame_iterations_per_s": n * iters / wall,
+                       "extrapolated_s_for_100k_subgames": 1e5 / rate},
+        }
+        log(f"datagen: {n} subgames x {iters} iterations in {wall:.1f} s ({rate:.1f} subgames/s; "
+            f"100k would take {1e5 / rate / 60:.1f} min)")
         print(json.dumps(result), flush=True)
         return
 
