@@ -1118,9 +1118,10 @@ __device__ void term_showdown(const DNode& nd, int64_t n, int Hp, const T* __res
 
 // One workgroup per terminal node of one kind (KIND 0: folds, 1: showdowns):
 // a kernel per kind, so that the lighter fold path is not held to the
-// registers of the showdown path.
+// registers of the showdown path.  recs: the nodes' records in launch order
+// (each carries its id), so a workgroup's first load has a known address.
 template <typename T, int KIND>
-__global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ nodes, const int32_t* __restrict__ list,
+__global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ recs,
                                                      int Hp, const T* __restrict__ reach, T* __restrict__ cfv,
                                                      const uint16_t* __restrict__ hcards, const int32_t* __restrict__ coff,
                                                      const int16_t* __restrict__ chands, int chand_stride,
@@ -1129,8 +1130,8 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const DNode* __restrict__ n
                                                      const int32_t* __restrict__ nzs) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
-    const int64_t n = list[blockIdx.x];
-    const DNode nd = nodes[n];
+    const DNode nd = recs[blockIdx.x];
+    const int64_t n = nd.id;
     if (node_dead(nzs, nd)) {
         // unreachable (regret-based pruning): both value rows are zero
         T* v = cfv + n * 2 * Hp;
@@ -2243,7 +2244,7 @@ struct Plan {
     size_t off_nodes, off_fwd, off_dec, off_fwdoff, off_decoff, off_term, off_hc, off_coff, off_chands, off_sd, off_sdn, off_state,
         off_R, off_S, off_reach, off_cfv, off_root, off_stage, off_et, off_eq, off_eqpay, off_net, off_spr,
         off_potk, off_zs, off_agg, off_rc, off_next, off_c2h, off_h2c, off_roots, off_M, off_samp, off_eqpart,
-        off_eqgrp, off_nsub, off_b4, off_nzs, off_tfrec, off_tfrest, off_tfterm,
+        off_eqgrp, off_nsub, off_b4, off_nzs, off_tfrec, off_tfrest, off_tfterm, off_termrec, off_tftermrec,
         off_cmap, off_hmap, off_ncompat, off_flops, off_orbit, off_hoff, off_hlist, off_fpart, total;
     int64_t n_fgrp = 0;                   // preflop leaves: flop groups of the first pass
     size_t lds_bytes, lds_fold, lds_show;
@@ -2786,6 +2787,10 @@ static void make_plan(const Prepared& P, int64_t rows, int dtype, int variant, b
     L.off_tfrec = take(sizeof(DNode) * std::max<size_t>(P.dec.size(), 1));
     L.off_tfrest = take(sizeof(DNode) * std::max<size_t>(P.fwd.size(), 1));
     L.off_tfterm = take(sizeof(int32_t) * std::max<size_t>(P.term.size(), 1));
+    // terminal records in the terminal launches' order, and the same for the
+    // terminals left to those launches by terminal fusion
+    L.off_termrec = take(sizeof(DNode) * std::max<size_t>(P.term.size(), 1));
+    L.off_tftermrec = take(sizeof(DNode) * std::max<size_t>(P.term.size(), 1));
     L.total = o;
     const size_t qn = 2 * L.Hp + kSdHeader;
     const size_t sd_nw = (qn + 63) / 64, sd_ns = L.Hp / 64;   // nonzero-reach bitmask words
@@ -2957,6 +2962,7 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
     const int64_t n_fold = tfo ? s->tf.n_fold : (int64_t)P.folds.size();
     const int64_t n_show = tfo ? s->tf.n_show : (int64_t)P.shows.size();
     const int32_t* tlist = s->at<int32_t>(tfo ? L.off_tfterm : L.off_term);
+    const DNode* trec = s->at<DNode>(tfo ? L.off_tftermrec : L.off_termrec);
     if (P.preflop && n_fold) {
         // folds over the hand classes (a preflop tree has no showdown)
         if (tm) tm->before(2);
@@ -2969,12 +2975,12 @@ static int32_t enqueue_sweep(pcfr_solver* s, hipStream_t stream, LaunchTimer* tm
         if (!cnt) continue;
         if (tm) tm->before(2);
         if (kind)
-            hipLaunchKernelGGL((k_terminal<T, 1>), dim3((unsigned)cnt), dim3(kBlock), L.lds_show, side, nodes,
-                               tlist + n_fold, Hp, reach, cfv, s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff),
+            hipLaunchKernelGGL((k_terminal<T, 1>), dim3((unsigned)cnt), dim3(kBlock), L.lds_show, side,
+                               trec + n_fold, Hp, reach, cfv, s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff),
                                s->at<int16_t>(L.off_chands), (int)L.chand_stride, s->at<int16_t>(L.off_sd),
                                (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn), nzs);
         else
-            hipLaunchKernelGGL((k_terminal<T, 0>), dim3((unsigned)cnt), dim3(kBlock), L.lds_fold, side, nodes, tlist,
+            hipLaunchKernelGGL((k_terminal<T, 0>), dim3((unsigned)cnt), dim3(kBlock), L.lds_fold, side, trec,
                                Hp, reach, cfv, s->at<uint16_t>(L.off_hc), s->at<int32_t>(L.off_coff),
                                s->at<int16_t>(L.off_chands), (int)L.chand_stride, s->at<int16_t>(L.off_sd),
                                (int64_t)L.sd_stride, s->at<int32_t>(L.off_sdn), nzs);
@@ -3219,8 +3225,13 @@ static int32_t make_tf_plan(pcfr_solver* s) {
     if (!rest_rec.empty())
         HIPCHK(hipMemcpyAsync(s->ws + L.off_tfrest, rest_rec.data(), sizeof(DNode) * rest_rec.size(), hipMemcpyHostToDevice,
                               s->stream));
-    if (!term.empty())
+    std::vector<DNode> term_rec;
+    for (int32_t x : term) term_rec.push_back(P.nodes[x]);
+    if (!term.empty()) {
         HIPCHK(hipMemcpyAsync(s->ws + L.off_tfterm, term.data(), sizeof(int32_t) * term.size(), hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(s->ws + L.off_tftermrec, term_rec.data(), sizeof(DNode) * term_rec.size(),
+                              hipMemcpyHostToDevice, s->stream));
+    }
     HIPCHK(hipStreamSynchronize(s->stream));
     tf.on = true;
     return PCFR_OK;
@@ -3440,6 +3451,11 @@ static int32_t create_impl(const pcfr_tree* const* trees, int32_t n, const pcfr_
     if ((rc = up(L.off_fwdoff, P.fwd_off.data(), sizeof(int64_t) * P.fwd_off.size()))) return rc;
     if ((rc = up(L.off_decoff, P.dec_off.data(), sizeof(int64_t) * P.dec_off.size()))) return rc;
     if ((rc = up(L.off_term, P.term.data(), sizeof(int32_t) * P.term.size()))) return rc;
+    {
+        std::vector<DNode> tr;
+        for (int32_t x : P.term) tr.push_back(P.nodes[x]);
+        if ((rc = up(L.off_termrec, tr.data(), sizeof(DNode) * tr.size()))) return rc;
+    }
     if ((rc = up(L.off_hc, P.hcards.data(), sizeof(uint16_t) * P.hcards.size()))) return rc;
     if ((rc = up(L.off_coff, P.coff.data(), sizeof(int32_t) * P.coff.size()))) return rc;
     if ((rc = up(L.off_chands, P.chands.data(), sizeof(int16_t) * P.chands.size()))) return rc;
