@@ -335,11 +335,12 @@ int32_t pcfr_exploitability(pcfr_solver* s, double* chips_per_hand, double* br);
  * sums in the solver's dtype.  pcfr_state_bytes gives the buffer size; buf is
  * host memory.  The blob is the solver's own state, for pcfr_load_state on a
  * solver of the same trees and configuration, not a table of the paper's
- * quantities: the chance probability 1/K is applied once at each chance node,
- * so the regrets and average-strategy sums of rows below chance nodes hold
- * the paper's values times the product of the divisors K above them (regret
- * matching and every update rule are invariant under that per-row scale, so
- * the strategies are the paper's). */
+ * quantities: the chance probability 1/K is applied once at each chance node
+ * (to the values passed up), so the regrets of rows below chance nodes hold
+ * the paper's cumulative regrets times the product of the divisors K above
+ * them (regret matching and every update rule are invariant under that
+ * per-row scale, so the strategies are the paper's); the average-strategy
+ * sums, weighted by the player's own reach, are not scaled. */
 int32_t pcfr_state_bytes(pcfr_solver* s, size_t* bytes);
 int32_t pcfr_save_state(pcfr_solver* s, void* buf, size_t bytes);
 int32_t pcfr_load_state(pcfr_solver* s, const void* buf, size_t bytes);
